@@ -1,0 +1,217 @@
+"""Seeded synthetic inputs: clouds of unit vectors on the sphere S^{d-1}.
+
+This module is shared by the tests, the benchmark and the smoke check.  It
+holds no arithmetic of the test itself (no means, no reflection, no
+statistic): it only draws anisotropic Gaussian noise around a mean direction
+and projects each row onto the unit sphere, the normalisation the paper
+applies to every token embedding before testing (Sec. 3.1, Eq. 2).
+
+Every array is reproducible from integers alone:
+``numpy.random.default_rng(SeedSequence([config_id, pair, side]))``.
+
+Workloads (stand-ins for BERT-family token embeddings of corpus words, which
+are not available here; shapes follow the paper's d = 768 / 1024 encoders and
+its B = 5,000 ... 20,000 permutation budgets):
+
+* config 1 - one pair, d=64, n=50, m=60, diagonal noise lambda_i ~ 1/i
+  (trace 1), kappa = 3, independent mean directions, FP64.
+* config 2 - one pair, d=768, n=2000, m=1500, low-rank noise, kappa 2.0/2.4,
+  means 40 degrees apart, FP32.
+* config 3 - one pair, d=1024, n=3000, m=2000, low-rank noise, equal
+  kappa = 2.2 (null), FP32 input for the split-BF16 path.
+* config 4 - 512 pairs, d=768, n_p and m_p log-uniform on [20, 5000],
+  kappa ~ U[1.5, 3.0], half the pairs null, random mean directions.
+* config 5 - 4096 pairs, d=768, n and m log-uniform on [20, 2000].
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "rng_for", "unit_rows", "random_unit", "direction_at_angle", "lowrank_factor",
+    "cloud_diag", "cloud_lowrank", "Pair", "Batch", "config1", "config2", "config3",
+    "config4", "config5", "pack_batch", "log_uniform_int",
+]
+
+
+def rng_for(config_id: int, pair: int = 0, side: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(config_id), int(pair), int(side)]))
+
+
+def unit_rows(a: np.ndarray) -> np.ndarray:
+    """Project each row onto the unit sphere (computed in float64)."""
+    a = np.asarray(a, dtype=np.float64)
+    return a / np.linalg.norm(a, axis=-1, keepdims=True)
+
+
+def random_unit(rng: np.random.Generator, d: int) -> np.ndarray:
+    return unit_rows(rng.standard_normal(d))
+
+
+def direction_at_angle(rng: np.random.Generator, mu: np.ndarray, degrees: float) -> np.ndarray:
+    """A unit vector at the given angle from the unit vector ``mu``."""
+    w = rng.standard_normal(mu.shape[0])
+    w -= (w @ mu) * mu
+    w /= np.linalg.norm(w)
+    a = math.radians(degrees)
+    return math.cos(a) * mu + math.sin(a) * w
+
+
+def lowrank_factor(d: int, rank: int = 32, seed: int = 1, noise: float = 0.1):
+    """Fixed noise model Sigma = s^2 (L L^T + noise^2 I), scaled to unit trace.
+
+    Returns (L, noise, s).  A draw is w = s * (L z1 + noise * z2).
+    """
+    g = np.random.default_rng(np.random.SeedSequence([1000, int(d), int(rank), int(seed)]))
+    L = g.standard_normal((d, rank)) / math.sqrt(rank)
+    trace = float(np.sum(L * L)) + noise * noise * d
+    return L, noise, 1.0 / math.sqrt(trace)
+
+
+def cloud_diag(rng, n, d, kappa, mu, lam):
+    """x = normalize(kappa * mu + z), z ~ N(0, diag(lam))."""
+    z = rng.standard_normal((n, d)) * np.sqrt(lam)[None, :]
+    return unit_rows(kappa * mu[None, :] + z)
+
+
+def cloud_lowrank(rng, n, d, kappa, mu, factor):
+    """x = normalize(kappa * mu + s (L z1 + noise z2))."""
+    L, noise, s = factor
+    z1 = rng.standard_normal((n, L.shape[1]))
+    z2 = rng.standard_normal((n, d))
+    w = s * (z1 @ L.T + noise * z2)
+    return unit_rows(kappa * mu[None, :] + w)
+
+
+@dataclass
+class Pair:
+    X: np.ndarray            # (n, d) unit rows
+    Y: np.ndarray            # (m, d) unit rows
+    B: int                   # permutations
+    seed: int = 0            # permutation seed
+    pair_index: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.X.shape[0]
+
+    @property
+    def m(self):
+        return self.Y.shape[0]
+
+    @property
+    def d(self):
+        return self.X.shape[1]
+
+
+def config1() -> Pair:
+    d, n, m = 64, 50, 60
+    lam = 1.0 / np.arange(1, d + 1)
+    lam /= lam.sum()
+    mu_a = random_unit(rng_for(1, 0, 10), d)
+    mu_b = random_unit(rng_for(1, 0, 11), d)
+    X = cloud_diag(rng_for(1, 0, 0), n, d, 3.0, mu_a, lam)
+    Y = cloud_diag(rng_for(1, 0, 1), m, d, 3.0, mu_b, lam)
+    return Pair(X, Y, B=999, seed=0, meta=dict(config=1, dtype="f64"))
+
+
+def _lowrank_pair(cfg, pair, n, m, d, kappa_a, kappa_b, angle=None, factor=None):
+    factor = factor if factor is not None else lowrank_factor(d)
+    mu_a = random_unit(rng_for(cfg, pair, 10), d)
+    if angle is None:
+        mu_b = random_unit(rng_for(cfg, pair, 11), d)
+    else:
+        mu_b = direction_at_angle(rng_for(cfg, pair, 11), mu_a, angle)
+    X = cloud_lowrank(rng_for(cfg, pair, 0), n, d, kappa_a, mu_a, factor)
+    Y = cloud_lowrank(rng_for(cfg, pair, 1), m, d, kappa_b, mu_b, factor)
+    return X.astype(np.float32), Y.astype(np.float32)
+
+
+def config2(n=2000, m=1500, d=768, B=10000) -> Pair:
+    X, Y = _lowrank_pair(2, 0, n, m, d, 2.0, 2.4, angle=40.0)
+    return Pair(X, Y, B=B, seed=0, meta=dict(config=2, dtype="f32"))
+
+
+def config3(n=3000, m=2000, d=1024, B=20000) -> Pair:
+    X, Y = _lowrank_pair(3, 0, n, m, d, 2.2, 2.2, angle=40.0)
+    return Pair(X, Y, B=B, seed=0, meta=dict(config=3, dtype="f32"))
+
+
+def log_uniform_int(rng, lo, hi, size=None):
+    return np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi + 1), size=size))).astype(np.int64).clip(lo, hi)
+
+
+@dataclass
+class Batch:
+    Z: np.ndarray            # (sum_p n_p + m_p, d) float32: X_0, Y_0, X_1, Y_1, ...
+    row_offset: np.ndarray   # (P+1,) int64, row of X_p
+    n: np.ndarray            # (P,) int64
+    m: np.ndarray            # (P,) int64
+    B: np.ndarray            # (P,) int64
+    pair_index: np.ndarray = None  # (P,) uint32 Philox counter word per pair
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if self.pair_index is None:
+            self.pair_index = np.arange(self.n.shape[0], dtype=np.uint32)
+
+    @property
+    def npairs(self):
+        return int(self.n.shape[0])
+
+    @property
+    def d(self):
+        return int(self.Z.shape[1])
+
+    def pair(self, p) -> Pair:
+        o = int(self.row_offset[p])
+        n, m = int(self.n[p]), int(self.m[p])
+        return Pair(self.Z[o:o + n], self.Z[o + n:o + n + m], B=int(self.B[p]), seed=self.seed,
+                    pair_index=int(self.pair_index[p]))
+
+
+def pack_batch(pairs, d, seed=0, meta=None) -> Batch:
+    n = np.array([p.X.shape[0] for p in pairs], dtype=np.int64)
+    m = np.array([p.Y.shape[0] for p in pairs], dtype=np.int64)
+    B = np.array([p.B for p in pairs], dtype=np.int64)
+    off = np.zeros(len(pairs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(n + m)
+    Z = np.empty((int(off[-1]), d), dtype=np.float32)
+    for i, p in enumerate(pairs):
+        Z[off[i]:off[i] + n[i]] = p.X
+        Z[off[i] + n[i]:off[i + 1]] = p.Y
+    ids = np.array([p.pair_index for p in pairs], dtype=np.uint32)
+    return Batch(Z, off, n, m, B, pair_index=ids, seed=seed, meta=meta or {})
+
+
+def _batch_config(cfg, npairs, d, lo, hi, B, limit=None):
+    g = rng_for(cfg, 0, 99)
+    ns = log_uniform_int(g, lo, hi, npairs)
+    ms = log_uniform_int(g, lo, hi, npairs)
+    ka = g.uniform(1.5, 3.0, npairs)
+    kb = g.uniform(1.5, 3.0, npairs)
+    null = np.arange(npairs) % 2 == 0
+    kb = np.where(null, ka, kb)
+    factor = lowrank_factor(d)
+    idx = range(npairs) if limit is None else limit
+    pairs = []
+    for p in idx:
+        X, Y = _lowrank_pair(cfg, p, int(ns[p]), int(ms[p]), d, float(ka[p]), float(kb[p]),
+                             angle=None, factor=factor)
+        pairs.append(Pair(X, Y, B=B, seed=0, pair_index=p, meta=dict(null=bool(null[p]))))
+    return pairs, dict(kappa_a=ka, kappa_b=kb, null=null, n=ns, m=ms)
+
+
+def config4(npairs=512, d=768, B=2000, limit=None) -> Batch:
+    pairs, info = _batch_config(4, npairs, d, 20, 5000, B, limit)
+    return pack_batch(pairs, d, meta=dict(config=4, **info))
+
+
+def config5(npairs=4096, d=768, B=20000, limit=None) -> Batch:
+    pairs, info = _batch_config(5, npairs, d, 20, 2000, B, limit)
+    return pack_batch(pairs, d, meta=dict(config=5, **info))
