@@ -1,0 +1,179 @@
+/*
+ * hbt.h - C ABI of the Householder-aligned permutation test on AMD MI355X.
+ *
+ * The test compares the dispersion ("semantic breadth") of two clouds of
+ * l2-normalised vectors X (n x d) and Y (m x d) (paper Sec. 3.1, "Problem
+ * setting"; Algorithm 1 inputs).  It
+ *   1. computes the sample mean directions mu_x, mu_y in FP64 (Sec. 3.1,
+ *      "Householder mean-direction alignment"; Algorithm 1, Step 1);
+ *   2. reflects X with H = I - 2 v v^T / (v^T v), v = mu_x - mu_y, so that
+ *      H mu_x = mu_y, leaving Y unchanged (Eq. for u and H; eq:householder_fast);
+ *   3. computes T_obs = log v(X') - log v(Y) with v = 1 / g_d(r) and r the
+ *      mean resultant length (Sec. 3.1, "Dispersion proxy"; eq:tobs);
+ *   4. pools Z = [X'; Y], draws B random splits into sizes (n, m), and
+ *      counts splits with T_b >= T_obs (Sec. 3.1, "Permutation procedure";
+ *      Algorithm 1, Step 5; Algorithm 2 for the group sums as one product);
+ *   5. returns p = (1 + count) / (B + 1) (eq:pvalue).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers on the current HIP device unless
+ *     stated otherwise, row-major, owned by the caller.  The library never
+ *     allocates device memory: scratch space is the caller's workspace
+ *     (`ws`, `ws_bytes`), sized by the matching *_workspace_size call.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *     it and the call returns without synchronising; results are valid once
+ *     the stream reaches that point.
+ *   - Host-detectable errors return a non-zero hbt_status BEFORE anything is
+ *     enqueued.  Conditions found on the device (degenerate clouds, bad
+ *     explicit masks) are reported per pair in hbt_result.status.  HIP
+ *     failures return HBT_ERR_DEVICE.  hbt_last_error() gives a thread-local
+ *     message for the last non-OK return.  No C++ exception crosses the ABI.
+ *   - Inputs must have unit-norm rows (the paper normalises every embedding,
+ *     Sec. 3.1 Eq. 2).  They are not renormalised.
+ *
+ * Random splits.  Split b (a global index, perm_offset <= b < perm_offset+B)
+ * of pair `pair_index` under `seed` puts in group 1 the n items that come
+ * first in the order (P_i, S_i, i), where P_i is byte (i mod 4) of word
+ * (i mod 16)/4 of Philox4x32-10(counter (i/16, b, pair_index, 0), key seed)
+ * and S_i is word (i mod 4) of Philox4x32-10(counter (i/4, b, pair_index, 1),
+ * key seed); the key is (seed mod 2^32, seed >> 32).  Masks store bit
+ * (i mod 32) of word i/32 for item i, ceil(N/32) words per split.
+ */
+#ifndef HBT_H_
+#define HBT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HBT_ABI_VERSION 1
+#define HBT_MAX_N 65536     /* largest pooled size n + m */
+#define HBT_MAX_D 8192      /* largest dimension */
+
+typedef enum hbt_status {
+    HBT_OK = 0,
+    HBT_ERR_ARG = 1,          /* NULL pointer, bad enum, offset overflow */
+    HBT_ERR_SIZE = 2,         /* n < 2, m < 2, d < 1, B < 1, or above the limits */
+    HBT_ERR_DTYPE = 3,        /* unsupported input dtype / precision combination */
+    HBT_ERR_WORKSPACE = 4,    /* ws NULL or ws_bytes below the required size */
+    HBT_ERR_DEGENERATE = 5,   /* per pair: r_X or r_Y outside (0, 1); H = I used */
+    HBT_ERR_MASK = 6,         /* per pair: an explicit mask row does not hold n items */
+    HBT_ERR_DEVICE = 7,       /* a HIP call failed */
+    HBT_ERR_UNSUPPORTED = 8,  /* option not built */
+    HBT_ERR_INTERNAL = 9      /* per pair: split selection overflowed its bucket buffer */
+} hbt_status;
+
+typedef enum hbt_precision {
+    HBT_F64 = 0,      /* group sums on FP64 MFMA */
+    HBT_F32 = 1,      /* group sums on FP32 MFMA */
+    HBT_BF16X2 = 2    /* z = hi + lo split into two BF16 planes, FP32 accumulation */
+} hbt_precision;
+
+typedef enum hbt_dtype { HBT_IN_F32 = 0, HBT_IN_F64 = 1 } hbt_dtype;
+
+/* g_d of Sec. 3.1 ("Dispersion proxy"): the paper uses "the same estimator as
+ * in prior work" without writing it; BANERJEE is the vMF concentration
+ * estimate kappa = r (d - r^2) / (1 - r^2) (Banerjee et al., JMLR 2005). */
+typedef enum hbt_gd { HBT_GD_BANERJEE = 0, HBT_GD_IDENTITY = 1 } hbt_gd;
+
+/* GREATER: count T_b >= T_obs ("u broader than k", Sec. 3.1).
+ * TWO_SIDED: count |T_b| >= |T_obs| (Table 5 reports two-sided values). */
+typedef enum hbt_alternative { HBT_ALT_GREATER = 0, HBT_ALT_TWO_SIDED = 1 } hbt_alternative;
+
+/* Per-pair result, written to DEVICE memory (72 bytes). */
+typedef struct hbt_result {
+    double t_obs;        /* log v(X') - log v(Y), FP64 (eq:tobs) */
+    double r_x;          /* mean resultant length of X (= of X', H orthogonal) */
+    double r_y;          /* mean resultant length of Y */
+    double p;            /* (1 + count) / (B + 1) (eq:pvalue) */
+    double tau;          /* tie tolerance: T_b counts if T_b >= T_obs - tau */
+    int64_t count;       /* exceedances among the B splits */
+    int64_t B;           /* splits evaluated */
+    int64_t n_recheck;   /* splits re-evaluated in FP64 because T_b was near T_obs */
+    int32_t status;      /* hbt_status of this pair */
+    int32_t h_identity;  /* 1 when H = I (alignment off, or |v| <= 1e-12) */
+} hbt_result;
+
+/* Parameters of one test (96 bytes; host memory). */
+typedef struct hbt_perm_params {
+    int64_t n, m, d;        /* group sizes and dimension */
+    int64_t B;              /* number of random splits */
+    uint64_t seed;          /* Philox key */
+    uint64_t perm_offset;   /* global index of the first split (resume / sharding) */
+    uint32_t pair_index;    /* Philox counter word 2 */
+    int32_t precision;      /* hbt_precision */
+    int32_t input_dtype;    /* hbt_dtype of X and Y */
+    int32_t gd;             /* hbt_gd */
+    int32_t alternative;    /* hbt_alternative */
+    int32_t align;          /* 1 = Householder alignment (the paper), 0 = naive test */
+    int32_t stat_route;     /* 0 = norms of the group sums; 1 = point-to-centroid products */
+    int32_t flags;          /* bit 0 (HBT_FLAG_NO_RECHECK): skip the FP64 recheck */
+    int64_t block_perms;    /* splits per block (B0 of Algorithm 2); 0 = automatic.
+                               Results do not depend on it. */
+    const uint32_t* masks;  /* optional DEVICE B x ceil((n+m)/32) group-1 masks replacing
+                               the Philox splits; each row must hold exactly n items. */
+} hbt_perm_params;
+
+#define HBT_FLAG_NO_RECHECK 1
+
+int32_t hbt_abi_version(void);
+const char* hbt_status_string(int32_t status);
+const char* hbt_last_error(void);
+
+/* hbt_align: Steps 1-4 of Algorithm 1 (mean directions in FP64, Householder
+ * reflection of X onto Y's mean direction, T_obs).
+ *   X (n x d), Y (m x d): unit rows, dtype input_dtype.
+ *   X_out (n x d, same dtype): receives H x_i; may alias X.
+ *   v_out (d doubles, nullable): receives v = mu_x - mu_y.
+ *   result (device, one hbt_result): t_obs, r_x, r_y, tau, status, h_identity;
+ *   p, count, B and n_recheck are set to 0.
+ * Errors: HBT_ERR_ARG (NULL X/Y/X_out/result, bad enum), HBT_ERR_SIZE,
+ * HBT_ERR_WORKSPACE, HBT_ERR_DEVICE. */
+size_t hbt_align_workspace_size(int64_t n, int64_t m, int64_t d);
+hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* Y, int64_t m,
+                     int64_t d, int32_t align, int32_t gd, void* X_out, double* v_out,
+                     hbt_result* result, void* ws, size_t ws_bytes, void* stream);
+
+/* hbt_perm_test: the whole test for one pair (Algorithm 1; the group sums of
+ * all splits of a block are one product of the 0/1 split masks with Z, as in
+ * Algorithm 2 and eq:gemm).
+ *   X (n x d), Y (m x d): unit rows, dtype prm->input_dtype.
+ *   result: one device hbt_result.
+ *   T_out (nullable, device, B floats): T_b as computed by the chosen
+ *     precision (before any FP64 recheck).
+ *   mask_out (nullable, device, B x ceil((n+m)/32) words): the splits used.
+ * Errors: as hbt_align, plus HBT_ERR_DTYPE and HBT_ERR_UNSUPPORTED. */
+size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm);
+hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* prm,
+                         hbt_result* result, float* T_out, uint32_t* mask_out, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* hbt_perm_test_batched: many independent pairs in one sequence of launches.
+ *   Z_all (device, FP32 or FP64 per common->input_dtype): rows X_0, Y_0,
+ *     X_1, Y_1, ..., each d wide; pair p's X starts at row row_offset[p] and
+ *     its Y at row_offset[p] + n[p].
+ *   row_offset, n, m, B: HOST arrays of npairs int64 (row_offset may have
+ *     npairs + 1 entries; only the first npairs are read).
+ *   pair_index: HOST array of npairs Philox counter words, or NULL for
+ *     common->pair_index + p.
+ *   common: precision, input_dtype, gd, alternative, align, seed,
+ *     perm_offset, flags (n, m, d, B, masks and block_perms are ignored).
+ *   results: DEVICE array of npairs hbt_result.
+ * Errors: as hbt_perm_test; a pair with bad sizes fails the whole call. */
+size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, const int64_t* m,
+                                            const int64_t* B, int64_t d,
+                                            const hbt_perm_params* common);
+hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_t* row_offset,
+                                 const int64_t* n, const int64_t* m, const int64_t* B,
+                                 const uint32_t* pair_index, int64_t d,
+                                 const hbt_perm_params* common, hbt_result* results, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HBT_H_ */

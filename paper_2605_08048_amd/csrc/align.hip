@@ -1,0 +1,366 @@
+// Mean directions, Householder reflection and observed statistic on the GPU
+// (Sec. 3.1 "Householder mean-direction alignment", eq:householder_fast,
+// eq:tobs; Algorithm 1, Steps 1-4).  All reductions are FP64 and run in a
+// fixed order, so results do not depend on timing.
+#include <string.h>
+
+#include "hbt_launch.h"
+
+namespace hbt {
+
+// ---------------------------------------------------------------------------
+// small utilities: table upload through kernel arguments, zero fill
+// ---------------------------------------------------------------------------
+struct UploadChunk {
+    unsigned char b[3072];
+};
+
+__global__ void k_upload(unsigned char* dst, UploadChunk c, int bytes) {
+    for (int i = threadIdx.x; i < bytes; i += blockDim.x) dst[i] = c.b[i];
+}
+
+hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const unsigned char* p = (const unsigned char*)src;
+    unsigned char* q = (unsigned char*)dst;
+    while (bytes) {
+        const size_t k = bytes < sizeof(UploadChunk) ? bytes : sizeof(UploadChunk);
+        UploadChunk c;
+        memcpy(c.b, p, k);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, q, c, (int)k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        p += k;
+        q += k;
+        bytes -= k;
+    }
+    return hipSuccess;
+}
+
+__global__ void k_zero(uint64_t* dst, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0;
+}
+
+hipError_t zero(void* dst, size_t bytes, hipStream_t s) {
+    const int64_t words = (int64_t)(bytes / 8);
+    if (!words) return hipSuccess;
+    int64_t g = (words + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, s, (uint64_t*)dst, words);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// column sums: one work-group = 64 columns x one chunk of rows, 4 row phases
+// ---------------------------------------------------------------------------
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_colsum(const PairDesc* __restrict__ pairs,
+                                                const SumChunk* __restrict__ chunks, int d,
+                                                double* __restrict__ partial) {
+    const SumChunk ch = chunks[blockIdx.x];
+    const PairDesc pd = pairs[ch.pair];
+    const Tin* base = (const Tin*)(ch.side ? pd.Y : pd.X);
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + tx;
+    double s0 = 0.0, s1 = 0.0;
+    if (c < d) {
+        int r = ch.r0 + ty;
+        for (; r + 4 < ch.r1; r += 8) {
+            const double a = (double)base[(int64_t)r * d + c];
+            const double b = (double)base[(int64_t)(r + 4) * d + c];
+            s0 += a;
+            s1 += b;
+        }
+        if (r < ch.r1) s0 += (double)base[(int64_t)r * d + c];
+    }
+    __shared__ double red[4][64];
+    red[ty][tx] = s0 + s1;
+    __syncthreads();
+    if (ty == 0 && c < d)
+        partial[(int64_t)blockIdx.x * d + c] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, const SumChunk* chunks,
+                         int nchunks, int d, double* partial, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    dim3 grid(nchunks, (d + 63) / 64);
+    if (input_dtype == HBT_IN_F64)
+        hipLaunchKernelGGL(k_colsum<double>, grid, dim3(256), 0, s, pairs, chunks, d, partial);
+    else
+        hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, s, pairs, chunks, d, partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// finalize: one work-group per pair
+// ---------------------------------------------------------------------------
+// Deterministic block sum of per-thread values (256 threads).
+__device__ double block_sum(double x, double* red) {
+    const int t = threadIdx.x;
+    red[t] = x;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ pairs,
+                                                  const double* __restrict__ partial, int d,
+                                                  int d_pad, int align, int gd, double* sxy,
+                                                  PairState* st, double* v, double* t64,
+                                                  float* t32, PairCount* cnt, hbt_result* res) {
+    __shared__ double red[256];
+    const int p = blockIdx.x;
+    const PairDesc pd = pairs[p];
+    double* sx = sxy + (int64_t)p * 2 * d_pad;
+    double* sy = sx + d_pad;
+    double* vp = v + (int64_t)p * d_pad;
+    double* tp = t64 + (int64_t)p * d_pad;
+    float* tq = t32 + (int64_t)p * d_pad;
+    // Step 1: sums of X and Y, chunk partials added in chunk order
+    double ssx = 0.0, ssy = 0.0;
+    for (int c = threadIdx.x; c < d_pad; c += 256) {
+        double a = 0.0, b = 0.0;
+        if (c < d) {
+            for (int k = pd.cx0; k < pd.cx1; ++k) a += partial[(int64_t)k * d + c];
+            for (int k = pd.cx1; k < pd.cy1; ++k) b += partial[(int64_t)k * d + c];
+        }
+        sx[c] = a;
+        sy[c] = b;
+        ssx += a * a;
+        ssy += b * b;
+    }
+    ssx = block_sum(ssx, red);
+    ssy = block_sum(ssy, red);
+    const double nx = sqrt(ssx), ny = sqrt(ssy);
+    const double r_x = nx / (double)pd.n, r_y = ny / (double)pd.m;
+    // mean directions and v = mu_x - mu_y (Eq. for u, before normalisation)
+    double vv = 0.0;
+    for (int c = threadIdx.x; c < d_pad; c += 256) {
+        const double mx = nx > 0.0 ? sx[c] / nx : 0.0;
+        const double my = ny > 0.0 ? sy[c] / ny : 0.0;
+        const double vc = mx - my;
+        vp[c] = vc;
+        vv += vc * vc;
+    }
+    vv = block_sum(vv, red);
+    const int identity = (!align) || !(sqrt(vv) > 1e-12) || !(r_x > 0.0) || !(r_y > 0.0);
+    // t = H s_x + s_y: the pooled total of Z = [X'; Y]
+    double w = 0.0;
+    for (int c = threadIdx.x; c < d_pad; c += 256) w += vp[c] * sx[c];
+    w = block_sum(w, red);
+    const double coef = identity ? 0.0 : 2.0 * w / vv;
+    for (int c = threadIdx.x; c < d_pad; c += 256) {
+        const double tc = (sx[c] - coef * vp[c]) + sy[c];
+        tp[c] = tc;
+        tq[c] = (float)tc;
+    }
+    if (threadIdx.x == 0) {
+        const double dd = (double)d;
+        const double fx = log_g(r_x, dd, gd), fy = log_g(r_y, dd, gd);
+        const double scale = fabs(fx) + fabs(fy);
+        PairState q;
+        q.r_x = r_x;
+        q.r_y = r_y;
+        q.t_obs = fy - fx;  // log v(X') - log v(Y), v = 1/g_d(r)
+        q.tau = 1e-10 * (scale > 1.0 ? scale : 1.0);
+        q.vv = vv;
+        q.f_x = fx;
+        q.f_y = fy;
+        q._pad = 0.0;
+        q.identity = identity;
+        q.status = (r_x > 0.0 && r_x < 1.0 && r_y > 0.0 && r_y < 1.0) ? HBT_OK : HBT_ERR_DEGENERATE;
+        q._pad2[0] = q._pad2[1] = 0;
+        st[p] = q;
+        cnt[p].count = 0;
+        cnt[p].n_recheck = 0;
+        hbt_result r;
+        r.t_obs = q.t_obs;
+        r.r_x = r_x;
+        r.r_y = r_y;
+        r.p = 0.0;
+        r.tau = q.tau;
+        r.count = 0;
+        r.B = 0;
+        r.n_recheck = 0;
+        r.status = q.status;
+        r.h_identity = identity;
+        res[p] = r;
+    }
+}
+
+hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* partial, int d,
+                           int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
+                           double* t64, float* t32, PairCount* cnt, hbt_result* res,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(npairs), dim3(256), 0, s, pairs, partial, d, d_pad, align,
+                       gd, sxy, st, v, t64, t32, cnt, res);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reflection + storage: one work-group per octet of 8 pooled rows
+// ---------------------------------------------------------------------------
+// Z storage formats:
+//   HBT_F64    : double [Np][d_pad]
+//   HBT_F32    : float  [Np][d_pad]
+//   HBT_BF16X2 : two planes (hi, then lo at +zplane_elems) of bf16
+//                [Np/8][d_pad][8]: the 8 rows of an octet are contiguous per
+//                column, the operand layout of the bf16 MFMA.
+template <typename Tin, int PREC>
+__global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pairs, int npairs,
+                                                 const PairState* __restrict__ st,
+                                                 const double* __restrict__ v, int d, int d_pad,
+                                                 double* __restrict__ coef, void* zstore,
+                                                 int64_t zplane_elems) {
+    __shared__ double cf[8];
+    const int64_t oct = blockIdx.x;
+    const int p = upper_index(npairs, oct * 8, [&](int k) { return pairs[k].zrow0; });
+    const PairDesc pd = pairs[p];
+    const int identity = st[p].identity;
+    const double vv = st[p].vv;
+    const double* vp = v + (int64_t)p * d_pad;
+    const int i0 = (int)(oct * 8 - pd.zrow0);  // first pooled row of the octet
+    const int N = pd.n + pd.m;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // coefficients 2 (v . x_i) / (v . v) of the X rows (eq:householder_fast)
+    for (int r = wave; r < 8; r += 4) {
+        const int i = i0 + r;
+        double w = 0.0;
+        if (!identity && i < pd.n) {
+            const Tin* x = (const Tin*)pd.X + (int64_t)i * d;
+            for (int c = lane; c < d; c += 64) w += vp[c] * (double)x[c];
+            for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+        }
+        if (lane == 0) {
+            const double k = (!identity && i < pd.n) ? 2.0 * w / vv : 0.0;
+            cf[r] = k;
+            if (i < pd.n) coef[pd.coef0 + i] = k;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < d_pad; c += 256) {
+        double z[8];
+        const double vc = c < d ? vp[c] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = i0 + r;
+            double val = 0.0;
+            if (c < d) {
+                if (i < pd.n)
+                    val = (double)((const Tin*)pd.X)[(int64_t)i * d + c] - cf[r] * vc;
+                else if (i < N)
+                    val = (double)((const Tin*)pd.Y)[(int64_t)(i - pd.n) * d + c];
+            }
+            z[r] = val;
+        }
+        if (PREC == HBT_BF16X2) {
+            uint32_t hi[4], lo[4];
+#pragma unroll
+            for (int r = 0; r < 8; r += 2) {
+                const float a = (float)z[r], b = (float)z[r + 1];
+                const uint32_t ha = f32_to_bf16_bits(a), hb = f32_to_bf16_bits(b);
+                const uint32_t la = f32_to_bf16_bits(a - bf16_bits_to_f32(ha));
+                const uint32_t lb = f32_to_bf16_bits(b - bf16_bits_to_f32(hb));
+                hi[r / 2] = ha | (hb << 16);
+                lo[r / 2] = la | (lb << 16);
+            }
+            uint4* ph = (uint4*)zstore + oct * d_pad + c;
+            *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+            *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        } else if (PREC == HBT_F32) {
+            float* q = (float*)zstore + oct * 8 * d_pad + c;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) q[(int64_t)r * d_pad] = (float)z[r];
+        } else {
+            double* q = (double*)zstore + oct * 8 * d_pad + c;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) q[(int64_t)r * d_pad] = z[r];
+        }
+    }
+}
+
+template <typename Tin>
+static hipError_t launch_reflect_t(int precision, const PairDesc* pairs, int npairs,
+                                   int64_t total_octets, const PairState* st, const double* v,
+                                   int d, int d_pad, double* coef, void* z, int64_t ze,
+                                   hipStream_t s) {
+    dim3 g((unsigned)total_octets), b(256);
+    switch (precision) {
+        case HBT_F64:
+            hipLaunchKernelGGL((k_reflect<Tin, HBT_F64>), g, b, 0, s, pairs, npairs, st, v, d, d_pad,
+                               coef, z, ze);
+            break;
+        case HBT_F32:
+            hipLaunchKernelGGL((k_reflect<Tin, HBT_F32>), g, b, 0, s, pairs, npairs, st, v, d, d_pad,
+                               coef, z, ze);
+            break;
+        default:
+            hipLaunchKernelGGL((k_reflect<Tin, HBT_BF16X2>), g, b, 0, s, pairs, npairs, st, v, d,
+                               d_pad, coef, z, ze);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs, int npairs,
+                          int64_t total_octets, const PairState* st, const double* v, int d,
+                          int d_pad, double* coef, void* zstore, int64_t zplane_elems,
+                          hipStream_t s) {
+    if (total_octets <= 0) return hipSuccess;
+    if (input_dtype == HBT_IN_F64)
+        return launch_reflect_t<double>(precision, pairs, npairs, total_octets, st, v, d, d_pad,
+                                        coef, zstore, zplane_elems, s);
+    return launch_reflect_t<float>(precision, pairs, npairs, total_octets, st, v, d, d_pad, coef,
+                                   zstore, zplane_elems, s);
+}
+
+// ---------------------------------------------------------------------------
+// hbt_align's output: X' = H X in the input dtype, one wave per row
+// ---------------------------------------------------------------------------
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_reflect_out(const PairDesc* __restrict__ pair,
+                                                     const PairState* __restrict__ st,
+                                                     const double* __restrict__ v, int n, int d,
+                                                     Tin* X_out) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wave;
+    if (i >= n) return;
+    const Tin* x = (const Tin*)pair->X + (int64_t)i * d;
+    Tin* y = X_out + (int64_t)i * d;
+    const int identity = st->identity;
+    double w = 0.0;
+    if (!identity) {
+        for (int c = lane; c < d; c += 64) w += v[c] * (double)x[c];
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    }
+    const double k = identity ? 0.0 : 2.0 * w / st->vv;
+    // every lane has read its share of the row (inside the dot product) before
+    // any write, so X_out may alias X
+    for (int c = lane; c < d; c += 64) y[c] = (Tin)((double)x[c] - k * v[c]);
+}
+
+__global__ void k_copy_v(const double* v, int d, double* out) {
+    for (int c = threadIdx.x; c < d; c += blockDim.x) out[c] = v[c];
+}
+
+hipError_t launch_reflect_out(int input_dtype, const PairDesc* pair, const PairState* st,
+                              const double* v, int n, int d, void* X_out, double* v_out,
+                              hipStream_t s) {
+    dim3 g((n + 3) / 4), b(256);
+    if (input_dtype == HBT_IN_F64)
+        hipLaunchKernelGGL(k_reflect_out<double>, g, b, 0, s, pair, st, v, n, d, (double*)X_out);
+    else
+        hipLaunchKernelGGL(k_reflect_out<float>, g, b, 0, s, pair, st, v, n, d, (float*)X_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !v_out) return e;
+    hipLaunchKernelGGL(k_copy_v, dim3(1), dim3(256), 0, s, v, d, v_out);
+    return hipGetLastError();
+}
+
+}  // namespace hbt

@@ -1,0 +1,457 @@
+// Host side of the C ABI (include/hbt.h): argument checks, workspace carving,
+// plan tables and the launch sequence of a test.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "hbt_launch.h"
+
+namespace {
+
+using namespace hbt;
+
+thread_local std::string g_err;
+
+hbt_status fail(hbt_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+hbt_status fail(hbt_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(HBT_ERR_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                              \
+    } while (0)
+
+constexpr int kSumChunk = 128;       // rows per column-sum chunk
+constexpr int64_t kAutoBlock = 32768;  // splits per block when block_perms == 0
+
+int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
+
+// Relative error bound of the squared group-sum norms, per precision; a
+// split within the implied band of the threshold is re-evaluated in FP64.
+double precision_rel_err(int precision) {
+    switch (precision) {
+        case HBT_F64: return 1e-11;
+        case HBT_F32: return 3e-5;
+        default: return 1e-4;
+    }
+}
+
+size_t zstore_bytes(int precision, int64_t rows, int64_t d_pad) {
+    return (size_t)rows * d_pad * (precision == HBT_F64 ? 8 : 4);
+}
+
+// Bump allocator over the caller's workspace (256-byte aligned slices).
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (size_t)round_up((int64_t)off, 256);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// Everything a call needs in device memory, carved in one fixed order so that
+// the *_workspace_size functions and the calls agree.
+struct Workspace {
+    PairDesc* pairs;
+    BlockPair* bp;
+    SumChunk* chunks;
+    GemmTile* tiles;
+    int64_t* Btot;
+    double* partial_sum;
+    double* sxy;
+    PairState* st;
+    double* v;
+    double* t64;
+    float* t32;
+    PairCount* cnt;
+    double* coef;
+    void* zstore;
+    uint32_t* mask;
+    double* partial;
+    uint32_t* flags;
+    uint32_t* nflag;
+    size_t bytes;
+};
+
+struct Plan {
+    int npairs = 0;
+    int d = 0, d_pad = 0, nslot = 0;
+    int precision = HBT_F32;
+    int input_dtype = HBT_IN_F32;
+    int max_np = 0;
+    std::vector<PairDesc> pairs;
+    std::vector<BlockPair> bp;
+    std::vector<SumChunk> chunks;
+    std::vector<GemmTile> tiles;
+    std::vector<int64_t> Btot;
+    int64_t zrows = 0, ncoef = 0;
+    int64_t block_rows = 0;       // split rows of the largest block
+    int64_t block_mask_words = 0; // mask words of the largest block
+    bool need_store = true;       // group-sum path (false for hbt_align)
+};
+
+Workspace carve(const Plan& P, void* ws) {
+    Carve c(ws);
+    Workspace w;
+    const int np = std::max(P.npairs, 1);
+    w.pairs = c.take<PairDesc>(np);
+    w.bp = c.take<BlockPair>(np);
+    w.chunks = c.take<SumChunk>(std::max<size_t>(P.chunks.size(), 1));
+    w.tiles = c.take<GemmTile>(std::max<size_t>(P.tiles.size(), 1));
+    w.Btot = c.take<int64_t>(np);
+    w.partial_sum = c.take<double>(std::max<size_t>(P.chunks.size(), 1) * P.d);
+    w.sxy = c.take<double>((size_t)np * 2 * P.d_pad);
+    w.st = c.take<PairState>(np);
+    w.v = c.take<double>((size_t)np * P.d_pad);
+    w.t64 = c.take<double>((size_t)np * P.d_pad);
+    w.t32 = c.take<float>((size_t)np * P.d_pad);
+    w.cnt = c.take<PairCount>(np);
+    if (P.need_store) {
+        w.coef = c.take<double>(std::max<int64_t>(P.ncoef, 1));
+        const size_t zb = zstore_bytes(P.precision, P.zrows, P.d_pad);
+        w.zstore = c.take<char>(zb);
+        w.mask = c.take<uint32_t>(std::max<int64_t>(P.block_mask_words, 1));
+        w.partial = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.nslot * 2);
+        w.flags = c.take<uint32_t>(std::max<int64_t>(P.block_rows, 1));
+        w.nflag = c.take<uint32_t>(2);
+    } else {
+        w.coef = nullptr;
+        w.zstore = nullptr;
+        w.mask = nullptr;
+        w.partial = nullptr;
+        w.flags = nullptr;
+        w.nflag = nullptr;
+    }
+    w.bytes = c.off + 256;
+    return w;
+}
+
+void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint32_t pair_index) {
+    PairDesc pd;
+    memset(&pd, 0, sizeof pd);
+    pd.X = X;
+    pd.Y = Y;
+    pd.n = (int32_t)n;
+    pd.m = (int32_t)m;
+    pd.Np = (int32_t)round_up(n + m, kRowPad);
+    pd.Wp = pd.Np / 32;
+    pd.zrow0 = P.zrows;
+    pd.coef0 = P.ncoef;
+    pd.pair_index = pair_index;
+    pd.flip = m < n ? 1 : 0;
+    const int p = (int)P.pairs.size();
+    pd.cx0 = (int32_t)P.chunks.size();
+    for (int64_t r = 0; r < n; r += kSumChunk)
+        P.chunks.push_back(SumChunk{p, 0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + kSumChunk)});
+    pd.cx1 = (int32_t)P.chunks.size();
+    for (int64_t r = 0; r < m; r += kSumChunk)
+        P.chunks.push_back(SumChunk{p, 1, (int32_t)r, (int32_t)std::min<int64_t>(m, r + kSumChunk)});
+    pd.cy1 = (int32_t)P.chunks.size();
+    P.zrows += pd.Np;
+    P.ncoef += n;
+    P.max_np = std::max(P.max_np, (int)pd.Np);
+    P.pairs.push_back(pd);
+    P.npairs = (int)P.pairs.size();
+}
+
+hbt_status check_enums(const hbt_perm_params* prm) {
+    if (prm->precision < HBT_F64 || prm->precision > HBT_BF16X2)
+        return fail(HBT_ERR_ARG, "unknown precision %d", prm->precision);
+    if (prm->input_dtype != HBT_IN_F32 && prm->input_dtype != HBT_IN_F64)
+        return fail(HBT_ERR_DTYPE, "unknown input dtype %d", prm->input_dtype);
+    if (prm->gd != HBT_GD_BANERJEE && prm->gd != HBT_GD_IDENTITY)
+        return fail(HBT_ERR_ARG, "unknown g_d %d", prm->gd);
+    if (prm->alternative != HBT_ALT_GREATER && prm->alternative != HBT_ALT_TWO_SIDED)
+        return fail(HBT_ERR_ARG, "unknown alternative %d", prm->alternative);
+    if (prm->align != 0 && prm->align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
+    if (prm->stat_route != 0)
+        return fail(HBT_ERR_UNSUPPORTED, "stat_route %d is not available", prm->stat_route);
+    if (prm->flags & ~HBT_FLAG_NO_RECHECK) return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
+    return HBT_OK;
+}
+
+hbt_status check_sizes(int64_t n, int64_t m, int64_t d, int64_t B, uint64_t perm_offset) {
+    if (n < 2 || m < 2) return fail(HBT_ERR_SIZE, "n and m must be >= 2 (got %lld, %lld)", (long long)n, (long long)m);
+    if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld outside [1, %d]", (long long)d, HBT_MAX_D);
+    if (n + m > HBT_MAX_N) return fail(HBT_ERR_SIZE, "n + m = %lld above %d", (long long)(n + m), HBT_MAX_N);
+    if (B < 1) return fail(HBT_ERR_SIZE, "B must be >= 1");
+    if (perm_offset + (uint64_t)B > 0x100000000ull)
+        return fail(HBT_ERR_ARG, "perm_offset + B exceeds 2^32 split indices");
+    return HBT_OK;
+}
+
+void finish_plan(Plan& P, int64_t d, int precision, int input_dtype) {
+    P.d = (int)d;
+    P.d_pad = (int)round_up(d, kDPad);
+    P.nslot = P.d_pad / kDSlot;
+    P.precision = precision;
+    P.input_dtype = input_dtype;
+}
+
+// Single-pair plan with blocks of B0 splits.
+Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64_t* B0_out) {
+    Plan P;
+    add_pair(P, X, Y, prm->n, prm->m, prm->pair_index);
+    finish_plan(P, prm->d, prm->precision, prm->input_dtype);
+    int64_t B0 = prm->block_perms > 0 ? prm->block_perms : kAutoBlock;
+    B0 = std::min<int64_t>(B0, prm->B);
+    *B0_out = B0;
+    P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0});
+    for (int64_t b = 0; b < B0; b += kTileB) P.tiles.push_back(GemmTile{0, (int32_t)b});
+    P.Btot.push_back(prm->B);
+    P.block_rows = B0;
+    P.block_mask_words = B0 * P.pairs[0].Wp;
+    return P;
+}
+
+hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd, hbt_result* res,
+                            hipStream_t s) {
+    HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
+    HIP_TRY(upload(w.chunks, P.chunks.data(), P.chunks.size() * sizeof(SumChunk), s));
+    HIP_TRY(launch_colsum(P.input_dtype, w.pairs, w.chunks, (int)P.chunks.size(), P.d,
+                          w.partial_sum, s));
+    HIP_TRY(launch_finalize(w.pairs, P.npairs, w.partial_sum, P.d, P.d_pad, align, gd, w.sxy, w.st,
+                            w.v, w.t64, w.t32, w.cnt, res, s));
+    return HBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hbt_abi_version(void) { return HBT_ABI_VERSION; }
+
+const char* hbt_status_string(int32_t status) {
+    switch (status) {
+        case HBT_OK: return "ok";
+        case HBT_ERR_ARG: return "invalid argument";
+        case HBT_ERR_SIZE: return "invalid size";
+        case HBT_ERR_DTYPE: return "unsupported dtype";
+        case HBT_ERR_WORKSPACE: return "workspace too small";
+        case HBT_ERR_DEGENERATE: return "degenerate cloud (r outside (0,1))";
+        case HBT_ERR_MASK: return "explicit mask row does not hold n items";
+        case HBT_ERR_DEVICE: return "HIP error";
+        case HBT_ERR_UNSUPPORTED: return "unsupported option";
+        case HBT_ERR_INTERNAL: return "split selection bucket overflow";
+        default: return "unknown status";
+    }
+}
+
+const char* hbt_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+size_t hbt_align_workspace_size(int64_t n, int64_t m, int64_t d) {
+    if (n < 2 || m < 2 || d < 1 || d > HBT_MAX_D || n + m > HBT_MAX_N) return 0;
+    Plan P;
+    P.need_store = false;
+    add_pair(P, nullptr, nullptr, n, m, 0);
+    finish_plan(P, d, HBT_F64, HBT_IN_F32);
+    return carve(P, nullptr).bytes;
+}
+
+hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* Y, int64_t m,
+                     int64_t d, int32_t align, int32_t gd, void* X_out, double* v_out,
+                     hbt_result* result, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!X || !Y || !X_out || !result) return fail(HBT_ERR_ARG, "NULL X, Y, X_out or result");
+    if (input_dtype != HBT_IN_F32 && input_dtype != HBT_IN_F64)
+        return fail(HBT_ERR_DTYPE, "unknown input dtype %d", input_dtype);
+    if (gd != HBT_GD_BANERJEE && gd != HBT_GD_IDENTITY) return fail(HBT_ERR_ARG, "unknown g_d %d", gd);
+    if (align != 0 && align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
+    hbt_status st = check_sizes(n, m, d, 1, 0);
+    if (st) return st;
+    Plan P;
+    P.need_store = false;
+    add_pair(P, X, Y, n, m, 0);
+    finish_plan(P, d, HBT_F64, input_dtype);
+    const size_t need = carve(P, nullptr).bytes;
+    if (!ws || ws_bytes < need)
+        return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w = carve(P, ws);
+    st = enqueue_prologue(P, w, align, gd, result, s);
+    if (st) return st;
+    HIP_TRY(launch_reflect_out(input_dtype, w.pairs, w.st, w.v, (int)n, (int)d, X_out, v_out, s));
+    return HBT_OK;
+}
+
+// ---------------------------------------------------------------------------
+size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm) {
+    if (!prm || check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset) ||
+        prm->precision < HBT_F64 || prm->precision > HBT_BF16X2) {
+        return 0;
+    }
+    int64_t B0;
+    Plan P = plan_single(prm, nullptr, nullptr, &B0);
+    return carve(P, nullptr).bytes;
+}
+
+hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* prm,
+                         hbt_result* result, float* T_out, uint32_t* mask_out, void* ws,
+                         size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!prm) return fail(HBT_ERR_ARG, "NULL params");
+    if (!X || !Y || !result) return fail(HBT_ERR_ARG, "NULL X, Y or result");
+    hbt_status st = check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset);
+    if (st) return st;
+    if ((st = check_enums(prm))) return st;
+    if (prm->block_perms < 0) return fail(HBT_ERR_ARG, "block_perms must be >= 0");
+    int64_t B0;
+    Plan P = plan_single(prm, X, Y, &B0);
+    const size_t need = carve(P, nullptr).bytes;
+    if (!ws || ws_bytes < need)
+        return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (!prm->masks && split_lds_per_wave(P.max_np) > split_lds_limit())
+        return fail(HBT_ERR_SIZE, "n + m too large for the split kernel's LDS");
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w = carve(P, ws);
+    const PairDesc& pd = P.pairs[0];
+    const int N = (int)(prm->n + prm->m);
+    const int W = (N + 31) / 32;
+
+    st = enqueue_prologue(P, w, prm->align, prm->gd, result, s);
+    if (st) return st;
+    HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
+    HIP_TRY(upload(w.Btot, P.Btot.data(), sizeof(int64_t), s));
+    HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, 1, P.zrows / 8, w.st, w.v, P.d,
+                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s));
+    const double e_rel = precision_rel_err(P.precision);
+    const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
+    for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
+        const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
+        BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
+        HIP_TRY(upload(w.bp, &bq, sizeof bq, s));
+        HIP_TRY(zero(w.nflag, 8, s));
+        if (prm->masks)
+            HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.st, s));
+        else
+            HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.st, s));
+        const int ntiles = (int)((nb + kTileB - 1) / kTileB);
+        HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, P.d_pad, w.zstore,
+                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s));
+        HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st, w.partial, P.nslot, P.d, prm->gd,
+                            prm->alternative, e_rel, no_recheck, T_out ? T_out + b0 : nullptr,
+                            w.cnt, w.flags, w.nflag, s));
+        if (!no_recheck)
+            HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.coef, w.mask,
+                                   w.flags, w.nflag, nb, P.d, prm->gd, prm->alternative, w.cnt, s));
+        if (mask_out)
+            HIP_TRY(launch_export_masks(w.mask, nb, pd.Wp, W, mask_out + b0 * W, s));
+    }
+    HIP_TRY(launch_final(1, w.st, w.cnt, w.Btot, result, s));
+    return HBT_OK;
+}
+
+// ---------------------------------------------------------------------------
+static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64_t* row_offset,
+                         const int64_t* n, const int64_t* m, const int64_t* B,
+                         const uint32_t* pair_index, int64_t d, const hbt_perm_params* common) {
+    const size_t es = common->input_dtype == HBT_IN_F64 ? 8 : 4;
+    int64_t rows = 0, words = 0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        const char* X = Z_all ? (const char*)Z_all + (size_t)row_offset[p] * d * es : nullptr;
+        const char* Y = X ? X + (size_t)n[p] * d * es : nullptr;
+        add_pair(P, X, Y, n[p], m[p], pair_index ? pair_index[p] : common->pair_index + (uint32_t)p);
+        P.bp.push_back(BlockPair{rows, words, (uint32_t)common->perm_offset, (int32_t)B[p], 0});
+        P.Btot.push_back(B[p]);
+        rows += B[p];
+        words += B[p] * P.pairs.back().Wp;
+    }
+    finish_plan(P, d, common->precision, common->input_dtype);
+    // tiles, largest pooled size first (longest-processing-time order)
+    std::vector<int> order((size_t)npairs);
+    for (int64_t p = 0; p < npairs; ++p) order[(size_t)p] = (int)p;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
+    for (int p : order)
+        for (int64_t b = 0; b < B[p]; b += kTileB) P.tiles.push_back(GemmTile{p, (int32_t)b});
+    P.block_rows = rows;
+    P.block_mask_words = words;
+    return true;
+}
+
+size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, const int64_t* m,
+                                            const int64_t* B, int64_t d,
+                                            const hbt_perm_params* common) {
+    if (npairs < 1 || !n || !m || !B || !common) return 0;
+    if (common->precision < HBT_F64 || common->precision > HBT_BF16X2) return 0;
+    for (int64_t p = 0; p < npairs; ++p)
+        if (check_sizes(n[p], m[p], d, B[p], common->perm_offset)) return 0;
+    std::vector<int64_t> off((size_t)npairs + 1, 0);
+    Plan P;
+    plan_batched(P, npairs, nullptr, off.data(), n, m, B, nullptr, d, common);
+    return carve(P, nullptr).bytes;
+}
+
+hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_t* row_offset,
+                                 const int64_t* n, const int64_t* m, const int64_t* B,
+                                 const uint32_t* pair_index, int64_t d,
+                                 const hbt_perm_params* common, hbt_result* results, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!common || !Z_all || !row_offset || !n || !m || !B || !results)
+        return fail(HBT_ERR_ARG, "NULL argument");
+    if (npairs < 1 || npairs > (1 << 24)) return fail(HBT_ERR_SIZE, "npairs = %lld", (long long)npairs);
+    hbt_status st = check_enums(common);
+    if (st) return st;
+    int64_t total_rows = 0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        if ((st = check_sizes(n[p], m[p], d, B[p], common->perm_offset)))
+            return fail(st, "pair %lld: %s", (long long)p, g_err.c_str());
+        if (row_offset[p] < 0) return fail(HBT_ERR_ARG, "pair %lld: negative row offset", (long long)p);
+        total_rows += B[p];
+    }
+    if (total_rows >= (int64_t)1 << 32) return fail(HBT_ERR_SIZE, "too many splits in one call");
+    Plan P;
+    plan_batched(P, npairs, Z_all, row_offset, n, m, B, pair_index, d, common);
+    const size_t need = carve(P, nullptr).bytes;
+    if (!ws || ws_bytes < need)
+        return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (split_lds_per_wave(P.max_np) > split_lds_limit())
+        return fail(HBT_ERR_SIZE, "n + m too large for the split kernel's LDS");
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w = carve(P, ws);
+    const int np = P.npairs;
+    st = enqueue_prologue(P, w, common->align, common->gd, results, s);
+    if (st) return st;
+    HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
+    HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
+    HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
+    HIP_TRY(zero(w.nflag, 8, s));
+    HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, np, P.zrows / 8, w.st, w.v, P.d,
+                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s));
+    HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask,
+                               w.st, s));
+    HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), P.d_pad,
+                            w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s));
+    const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
+    HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
+                        common->alternative, precision_rel_err(P.precision), no_recheck, nullptr,
+                        w.cnt, w.flags, w.nflag, s));
+    if (!no_recheck)
+        HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.coef, w.mask, w.flags,
+                               w.nflag, P.block_rows, P.d, common->gd, common->alternative, w.cnt, s));
+    HIP_TRY(launch_final(np, w.st, w.cnt, w.Btot, results, s));
+    return HBT_OK;
+}
+
+}  // extern "C"

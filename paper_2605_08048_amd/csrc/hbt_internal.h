@@ -1,0 +1,173 @@
+// Internal plan structures and device helpers of the HIP path (gfx950).
+// Host and device code of the library include this header; it is not part of
+// the public ABI (include/hbt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hbt.h"
+
+namespace hbt {
+
+// Pooled rows of a pair are padded to a multiple of kRowPad in the Z
+// storage (zero rows), columns to a multiple of kDPad (zero columns).
+constexpr int kRowPad = 64;
+constexpr int kDPad = 64;
+// Each group-sum tile reduces its squared norms over kDSlot columns; the
+// statistic kernel adds the d_pad / kDSlot slots of a split row in FP64.
+constexpr int kDSlot = 64;
+// Split rows per group-sum tile (4 waves x 64 rows).
+constexpr int kTileB = 256;
+// Capacity of the boundary bucket of the split selection (items whose
+// primary key equals the selected byte; about N / 256 of them).
+constexpr int kCandCap = 512;
+
+// One pair of clouds (device table entry, 96 bytes).
+struct PairDesc {
+    const void* X;       // n rows of d values (input dtype)
+    const void* Y;       // m rows
+    int32_t n, m;
+    int32_t Np;          // n + m rounded up to kRowPad
+    int32_t Wp;          // mask words per split row in the workspace (Np / 32)
+    int64_t zrow0;       // first row of this pair in the Z storage
+    int64_t coef0;       // first of its n reflection coefficients
+    uint32_t pair_index; // Philox counter word 2
+    int32_t flip;        // 1 when m < n: group sums run on the group-2 mask
+    int32_t cx0, cx1;    // column-sum chunks of X: [cx0, cx1); of Y: [cx1, cy1)
+    int32_t cy1;
+    int32_t _pad0;
+    int64_t _pad1[3];
+};
+static_assert(sizeof(PairDesc) == 96, "PairDesc layout");
+
+// Splits of one pair inside the current block (device table entry).
+struct BlockPair {
+    int64_t mrow0;       // first split row of the pair in the block buffers
+    int64_t mword0;      // first mask word of that row (rows hold Wp words)
+    uint32_t perm_base;  // global index of that split
+    int32_t nb;          // splits of the pair in this block
+    int64_t _pad;
+};
+static_assert(sizeof(BlockPair) == 32, "BlockPair layout");
+
+#ifdef __HIPCC__
+// Mask words of split row `row` (a block row of pair bq).
+__device__ __forceinline__ const uint32_t* mask_row(const uint32_t* mask, const BlockPair& bq,
+                                                    int64_t row, int Wp) {
+    return mask + bq.mword0 + (row - bq.mrow0) * (int64_t)Wp;
+}
+#endif
+
+// A run of rows of one cloud for the column sums.
+struct SumChunk {
+    int32_t pair, side;  // side 0 = X, 1 = Y
+    int32_t r0, r1;
+};
+
+// A group-sum tile: kTileB split rows of one pair (all column slots).
+struct GemmTile {
+    int32_t pair;
+    int32_t b0;          // first split of the tile, relative to the pair's block rows
+};
+
+// FP64 per-pair state written by the finalize kernel.
+struct PairState {
+    double r_x, r_y, t_obs, tau, vv, f_x, f_y, _pad;
+    int32_t identity, status;
+    int32_t _pad2[2];
+};
+
+// Device-side counters of a pair (zeroed at the start of a call).
+struct PairCount {
+    unsigned long long count;
+    unsigned long long n_recheck;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+#ifdef __HIPCC__
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products, Weyl key schedule.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    }
+    return c;
+}
+
+// Memory fence + scheduling barrier among the lanes of one wave, for LDS
+// data written by one lane and read by another.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (l >= o) x += y;
+    }
+    return x;
+}
+
+// Round-to-nearest-even float -> bfloat16 bits.
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// log g_d(r) of Sec. 3.1 ("Dispersion proxy"), in FP64.
+__device__ __forceinline__ double log_g(double r, double d, int gd) {
+    if (gd == HBT_GD_IDENTITY) return log(r);
+    const double rr = r * r;
+    return log(r * (d - rr) / ((1.0 - r) * (1.0 + r)));
+}
+
+// |s * d/ds log g_d(sqrt(s))| for s = r^2: the factor by which a relative
+// error of s moves log g_d.
+__device__ __forceinline__ double log_g_sensitivity(double s, double d, int gd) {
+    if (gd == HBT_GD_IDENTITY) return 0.5;
+    return fabs(0.5 - s / (d - s) + s / (1.0 - s));
+}
+
+// Binary search: last index k in [0, count) with key(k) <= x, for an
+// ascending sequence of keys.
+template <typename F>
+__device__ __forceinline__ int upper_index(int count, int64_t x, F key) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (key(mid) <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+#endif  // __HIPCC__
+
+}  // namespace hbt

@@ -1,0 +1,79 @@
+// Host-side launchers of the HIP kernels (one translation unit per stage).
+// Every launcher enqueues on `s` and returns the HIP status of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hbt_internal.h"
+
+namespace hbt {
+
+// Copy `bytes` (<= 3072 per launch, split internally) of host data into
+// device memory through kernel arguments: stream-ordered, no host buffer
+// outlives the call, capturable in a graph.
+hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Zero `bytes` (a multiple of 8) of device memory with a fill kernel.
+hipError_t zero(void* dst, size_t bytes, hipStream_t s);
+
+// --- alignment (Algorithm 1, Steps 1-4) ---------------------------------
+// FP64 column sums of every chunk: partial[chunk][d].
+hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, const SumChunk* chunks,
+                         int nchunks, int d, double* partial, hipStream_t s);
+// Per pair: sums, r, mean directions, v, v.v, identity, T_obs, tau, the pooled
+// total t (FP64 and FP32), the hbt_result header.
+hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* partial, int d,
+                           int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
+                           double* t64, float* t32, PairCount* cnt, hbt_result* res,
+                           hipStream_t s);
+// Reflect X rows, write Z in the precision's storage format, the FP64
+// coefficients 2 (v.x_i) / (v.v) and zero padding.
+hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs, int npairs,
+                          int64_t total_octets, const PairState* st, const double* v, int d,
+                          int d_pad, double* coef, void* zstore, int64_t zplane_elems,
+                          hipStream_t s);
+// hbt_align's output: X' in the input dtype (may alias X).
+hipError_t launch_reflect_out(int input_dtype, const PairDesc* pair, const PairState* st,
+                              const double* v, int n, int d, void* X_out, double* v_out,
+                              hipStream_t s);
+
+// --- random splits ------------------------------------------------------
+// LDS bytes one split row needs for pairs of up to max_np pooled rows, and
+// the device's limit per work-group.
+size_t split_lds_per_wave(int max_np);
+size_t split_lds_limit();
+hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
+                              int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
+                              PairState* st, hipStream_t s);
+// Explicit masks: copy rows of ceil(N/32) words into the workspace layout and
+// check that each holds exactly n items.
+hipError_t launch_copy_masks(const uint32_t* user, int64_t user_row0, int64_t rows, int N, int n,
+                             int Wp, uint32_t* mask, PairState* st, hipStream_t s);
+// Copy workspace masks back to a caller buffer of ceil(N/32) words per row.
+hipError_t launch_export_masks(const uint32_t* mask, int64_t rows, int Wp, int W, uint32_t* out,
+                               hipStream_t s);
+
+// --- group sums (eq:gemm) -----------------------------------------------
+// partial[row][slot] = (|sigma_small|^2, |t - sigma_small|^2) over the slot's
+// kDSlot columns, sigma_small = mask_small . Z.
+hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
+                           const GemmTile* tiles, int ntiles, int d_pad, const void* zstore,
+                           int64_t zplane_elems, const uint32_t* mask, const float* t32,
+                           const double* t64, double* partial, hipStream_t s);
+
+// --- statistic, exceedances, recheck, p ---------------------------------
+hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
+                       const PairState* st, const double* partial, int nslot, int d, int gd,
+                       int alternative, double e_rel, int no_recheck, float* T_out,
+                       PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
+hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
+                          int npairs, const PairState* st, const double* v, const double* coef,
+                          const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
+                          int64_t max_flags, int d, int gd, int alternative, PairCount* cnt,
+                          hipStream_t s);
+hipError_t launch_final(int npairs, const PairState* st, const PairCount* cnt,
+                        const int64_t* Btot, hbt_result* res, hipStream_t s);
+
+}  // namespace hbt

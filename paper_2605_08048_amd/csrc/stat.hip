@@ -1,0 +1,196 @@
+// Permuted statistics, exceedance counts and the p-value (Algorithm 1,
+// Steps 5-6; Algorithm 2's r_1, r_2, T^(b) and streaming count; eq:pvalue).
+//
+// The scalar math per split (norms, g_d, T_b) is FP64.  A split whose T_b,
+// computed from FP32 / split-BF16 group sums, lies within the precision's
+// error bound of the decision threshold is not counted here: it goes to a
+// list and is re-evaluated from the input rows in FP64 (recheck), so the
+// final counts follow the FP64 statistic.
+#include "hbt_launch.h"
+
+namespace hbt {
+
+__global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs,
+                                              const BlockPair* __restrict__ bp, int npairs,
+                                              int64_t rows, const PairState* __restrict__ st,
+                                              const double* __restrict__ partial, int nslot, int d,
+                                              int gd, int alternative, double e_rel,
+                                              int no_recheck, float* T_out, PairCount* cnt,
+                                              uint32_t* flags, uint32_t* nflag) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool active = row < rows;
+    int p = 0;
+    bool exceed = false;
+    if (active) {
+        p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
+        const PairDesc pd = pairs[p];
+        const PairState q = st[p];
+        const double2* pr = (const double2*)partial + row * nslot;
+        double ss_small = 0.0, ss_large = 0.0;
+        for (int k = 0; k < nslot; ++k) {
+            const double2 v = pr[k];
+            ss_small += v.x;
+            ss_large += v.y;
+        }
+        // group 1 has n items, group 2 has m; the product ran on the smaller one
+        const double ss1 = pd.flip ? ss_large : ss_small;
+        const double ss2 = pd.flip ? ss_small : ss_large;
+        const double n = (double)pd.n, m = (double)pd.m, dd = (double)d;
+        const double r1 = sqrt(ss1) / n, r2 = sqrt(ss2) / m;
+        const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);  // log v(X^(b)) - log v(Y^(b))
+        if (T_out) T_out[row] = (float)T;
+        const bool two = alternative == HBT_ALT_TWO_SIDED;
+        const double val = two ? fabs(T) : T;
+        const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
+        const double fs = fabs(log_g(r1, dd, gd)) + fabs(log_g(r2, dd, gd));
+        const double eps = e_rel * (log_g_sensitivity(r1 * r1, dd, gd) +
+                                    log_g_sensitivity(r2 * r2, dd, gd)) + 1e-13 * fs;
+        const bool nan = T != T;
+        const bool border = !no_recheck && !nan && fabs(val - thr) <= eps;
+        if (border) {
+            const uint32_t k = atomicAdd(nflag, 1u);
+            flags[k] = (uint32_t)row;
+        } else {
+            exceed = nan || val >= thr;
+        }
+    }
+    // count: one atomic per wave when all its rows belong to one pair
+    const uint64_t ex = __ballot(exceed);
+    const int p0 = __shfl(p, 0, 64);
+    const uint64_t same = __ballot(!active || p == p0);
+    if (same == ~0ull) {
+        if (lane_id() == 0 && ex) atomicAdd(&cnt[p0].count, (unsigned long long)__popcll(ex));
+    } else if (exceed) {
+        atomicAdd(&cnt[p].count, 1ull);
+    }
+}
+
+hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
+                       const PairState* st, const double* partial, int nslot, int d, int gd,
+                       int alternative, double e_rel, int no_recheck, float* T_out,
+                       PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
+                       npairs, rows, st, partial, nslot, d, gd, alternative, e_rel, no_recheck,
+                       T_out, cnt, flags, nflag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 recheck: both group sums by direct summation over the pooled rows,
+// rows rebuilt from the input as x_i - coef_i v (X) or y_j (Y).
+// One work-group per flagged split; persistent over the flag list.
+// ---------------------------------------------------------------------------
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pairs,
+                                                 const BlockPair* __restrict__ bp, int npairs,
+                                                 const PairState* __restrict__ st,
+                                                 const double* __restrict__ v,
+                                                 const double* __restrict__ coef,
+                                                 const uint32_t* __restrict__ mask,
+                                                 const uint32_t* __restrict__ flags,
+                                                 const uint32_t* __restrict__ nflag, int d,
+                                                 int d_pad, int gd, int alternative,
+                                                 PairCount* cnt) {
+    __shared__ double red1[256], red2[256];
+    const uint32_t total = *nflag;
+    for (uint32_t f = blockIdx.x; f < total; f += gridDim.x) {
+        const int64_t row = flags[f];
+        const int p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
+        const PairDesc pd = pairs[p];
+        const PairState q = st[p];
+        const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
+        const double* vp = v + (int64_t)p * d_pad;
+        const double* cf = coef + pd.coef0;
+        const int N = pd.n + pd.m;
+        double ss1 = 0.0, ss2 = 0.0;
+        for (int c0 = 0; c0 < d; c0 += 1024) {
+            double a1[4] = {0, 0, 0, 0}, a2[4] = {0, 0, 0, 0};
+            for (int i = 0; i < N; ++i) {
+                const bool g1 = (mk[i >> 5] >> (i & 31)) & 1u;  // mask words are shared by the WG
+                const double k = i < pd.n ? cf[i] : 0.0;
+                const Tin* src = i < pd.n ? (const Tin*)pd.X + (int64_t)i * d
+                                          : (const Tin*)pd.Y + (int64_t)(i - pd.n) * d;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + u * 256 + threadIdx.x;
+                    if (c < d) {
+                        const double z = (double)src[c] - k * vp[c];
+                        if (g1) a1[u] += z;
+                        else a2[u] += z;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ss1 += a1[u] * a1[u];
+                ss2 += a2[u] * a2[u];
+            }
+        }
+        red1[threadIdx.x] = ss1;
+        red2[threadIdx.x] = ss2;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                red1[threadIdx.x] += red1[threadIdx.x + o];
+                red2[threadIdx.x] += red2[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double dd = (double)d;
+            const double r1 = sqrt(red1[0]) / (double)pd.n, r2 = sqrt(red2[0]) / (double)pd.m;
+            const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);
+            const bool two = alternative == HBT_ALT_TWO_SIDED;
+            const double val = two ? fabs(T) : T;
+            const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
+            if (T != T || val >= thr) atomicAdd(&cnt[p].count, 1ull);
+            atomicAdd(&cnt[p].n_recheck, 1ull);
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
+                          int npairs, const PairState* st, const double* v, const double* coef,
+                          const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
+                          int64_t max_flags, int d, int gd, int alternative, PairCount* cnt,
+                          hipStream_t s) {
+    if (max_flags <= 0) return hipSuccess;
+    const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
+    int64_t g = max_flags < 1024 ? max_flags : 1024;
+    if (input_dtype == HBT_IN_F64)
+        hipLaunchKernelGGL(k_recheck<double>, dim3((unsigned)g), dim3(256), 0, s, pairs, bp, npairs,
+                           st, v, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
+    else
+        hipLaunchKernelGGL(k_recheck<float>, dim3((unsigned)g), dim3(256), 0, s, pairs, bp, npairs,
+                           st, v, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// p = (1 + count) / (B + 1)  (eq:pvalue)
+// ---------------------------------------------------------------------------
+__global__ void k_final(int npairs, const PairState* __restrict__ st,
+                        const PairCount* __restrict__ cnt, const int64_t* __restrict__ Btot,
+                        hbt_result* res) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const PairState q = st[p];
+    hbt_result r = res[p];
+    r.count = (int64_t)cnt[p].count;
+    r.n_recheck = (int64_t)cnt[p].n_recheck;
+    r.B = Btot[p];
+    r.p = (1.0 + (double)r.count) / ((double)r.B + 1.0);
+    r.status = q.status;
+    res[p] = r;
+}
+
+hipError_t launch_final(int npairs, const PairState* st, const PairCount* cnt,
+                        const int64_t* Btot, hbt_result* res, hipStream_t s) {
+    hipLaunchKernelGGL(k_final, dim3((npairs + 255) / 256), dim3(256), 0, s, npairs, st, cnt, Btot,
+                       res);
+    return hipGetLastError();
+}
+
+}  // namespace hbt

@@ -1,0 +1,249 @@
+"""Python binding of ``libhbt.so`` (include/hbt.h): argument marshalling only.
+
+Every step of the test runs in the HIP kernels behind the C ABI; this module
+turns torch tensors into device pointers, sizes and allocates the workspace
+with torch (the library allocates nothing), passes torch's current stream,
+and copies the per-pair ``hbt_result`` back.  There is no fallback: without
+the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libhbt.so"
+
+OK, ERR_ARG, ERR_SIZE, ERR_DTYPE, ERR_WORKSPACE, ERR_DEGENERATE, ERR_MASK, ERR_DEVICE, \
+    ERR_UNSUPPORTED, ERR_INTERNAL = range(10)
+PRECISION = {"f64": 0, "f32": 1, "bf16x2": 2}
+DTYPE = {"f32": 0, "f64": 1}
+GD = {"banerjee": 0, "identity": 1}
+ALT = {"greater": 0, "two-sided": 1}
+FLAG_NO_RECHECK = 1
+MAX_N, MAX_D = 65536, 8192
+
+
+class HbtResult(C.Structure):
+    _fields_ = [("t_obs", C.c_double), ("r_x", C.c_double), ("r_y", C.c_double), ("p", C.c_double),
+                ("tau", C.c_double), ("count", C.c_int64), ("B", C.c_int64), ("n_recheck", C.c_int64),
+                ("status", C.c_int32), ("h_identity", C.c_int32)]
+
+
+class HbtPermParams(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("d", C.c_int64), ("B", C.c_int64),
+                ("seed", C.c_uint64), ("perm_offset", C.c_uint64), ("pair_index", C.c_uint32),
+                ("precision", C.c_int32), ("input_dtype", C.c_int32), ("gd", C.c_int32),
+                ("alternative", C.c_int32), ("align", C.c_int32), ("stat_route", C.c_int32),
+                ("flags", C.c_int32), ("block_perms", C.c_int64), ("masks", C.c_void_p)]
+
+
+assert C.sizeof(HbtResult) == 72 and C.sizeof(HbtPermParams) == 96
+
+RESULT_DTYPE = np.dtype([("t_obs", "f8"), ("r_x", "f8"), ("r_y", "f8"), ("p", "f8"), ("tau", "f8"),
+                         ("count", "i8"), ("B", "i8"), ("n_recheck", "i8"), ("status", "i4"),
+                         ("h_identity", "i4")])
+assert RESULT_DTYPE.itemsize == 72
+
+
+class HbtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hbt status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libhbt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2605_08048_amd.build`")
+        L = C.CDLL(str(LIB_PATH))
+        P, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+        L.hbt_abi_version.restype = i32
+        L.hbt_status_string.argtypes = [i32]
+        L.hbt_status_string.restype = C.c_char_p
+        L.hbt_last_error.restype = C.c_char_p
+        L.hbt_align_workspace_size.argtypes = [i64, i64, i64]
+        L.hbt_align_workspace_size.restype = sz
+        L.hbt_align.argtypes = [i32, P, i64, P, i64, i64, i32, i32, P, P, P, P, sz, P]
+        L.hbt_align.restype = i32
+        L.hbt_perm_test_workspace_size.argtypes = [C.POINTER(HbtPermParams)]
+        L.hbt_perm_test_workspace_size.restype = sz
+        L.hbt_perm_test.argtypes = [P, P, C.POINTER(HbtPermParams), P, P, P, P, sz, P]
+        L.hbt_perm_test.restype = i32
+        L.hbt_perm_test_batched_workspace_size.argtypes = [i64, P, P, P, i64, C.POINTER(HbtPermParams)]
+        L.hbt_perm_test_batched_workspace_size.restype = sz
+        L.hbt_perm_test_batched.argtypes = [i64, P, P, P, P, P, P, i64, C.POINTER(HbtPermParams), P, P,
+                                            sz, P]
+        L.hbt_perm_test_batched.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        L = lib()
+        raise HbtError(status, (L.hbt_last_error() or L.hbt_status_string(status)).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+_ws = {}
+
+
+def workspace(nbytes, device):
+    """A cached device byte buffer of at least ``nbytes`` (allocated by torch)."""
+    torch = _torch()
+    key = str(device)
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws[key] = buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    return buf
+
+
+def _dev_tensor(a, dtype, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def _input_dtype(X):
+    torch = _torch()
+    if X.dtype == torch.float64:
+        return DTYPE["f64"]
+    if X.dtype == torch.float32:
+        return DTYPE["f32"]
+    raise HbtError(ERR_DTYPE, f"inputs must be float32 or float64, got {X.dtype}")
+
+
+def results_to_numpy(res_tensor):
+    raw = res_tensor.cpu().numpy().tobytes()
+    return np.frombuffer(raw, dtype=RESULT_DTYPE).copy()
+
+
+def _result_dict(row):
+    return {k: (row[k].item()) for k in RESULT_DTYPE.names}
+
+
+def make_params(n, m, d, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", input_dtype=0,
+                gd="banerjee", alternative="greater", align=True, stat_route=0, recheck=True,
+                block_perms=0, masks_ptr=None):
+    return HbtPermParams(n=n, m=m, d=d, B=B, seed=seed, perm_offset=perm_offset, pair_index=pair_index,
+                         precision=PRECISION[precision], input_dtype=input_dtype, gd=GD[gd],
+                         alternative=ALT[alternative], align=1 if align else 0, stat_route=stat_route,
+                         flags=0 if recheck else FLAG_NO_RECHECK, block_perms=block_perms,
+                         masks=masks_ptr)
+
+
+def align(X, Y, *, align=True, gd="banerjee", out=None, stream=None):
+    """Householder alignment of X onto Y's mean direction (Algorithm 1, Steps 1-4)."""
+    torch = _torch()
+    n, d = X.shape
+    m = Y.shape[0]
+    dev = X.device
+    Y = Y.to(dtype=X.dtype).contiguous()
+    X = X.contiguous()
+    Xo = out if out is not None else torch.empty_like(X)
+    v = torch.empty(d, dtype=torch.float64, device=dev)
+    res = torch.zeros(72, dtype=torch.uint8, device=dev)
+    L = lib()
+    need = L.hbt_align_workspace_size(n, m, d)
+    ws = workspace(need, dev)
+    _check(L.hbt_align(_input_dtype(X), C.c_void_p(X.data_ptr()), n, C.c_void_p(Y.data_ptr()), m, d,
+                       1 if align else 0, GD[gd], C.c_void_p(Xo.data_ptr()), C.c_void_p(v.data_ptr()),
+                       C.c_void_p(res.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    r = _result_dict(results_to_numpy(res)[0])
+    r.update(X_out=Xo, v=v)
+    return r
+
+
+def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", gd="banerjee",
+              alternative="greater", align=True, recheck=True, block_perms=0, masks=None,
+              want_T=False, want_masks=False, stream=None, sync=True):
+    """The whole test for one pair.  Returns a dict of the hbt_result fields,
+    plus ``T`` (B floats) and ``masks`` (B x ceil(N/32) words) when asked."""
+    torch = _torch()
+    n, d = X.shape
+    m = Y.shape[0]
+    dev = X.device
+    X = X.contiguous()
+    Y = Y.to(dtype=X.dtype).contiguous()
+    W = (n + m + 31) // 32
+    mk = None
+    if masks is not None:
+        mk = _dev_tensor(np.asarray(masks, dtype=np.uint32).view(np.int32).reshape(B, W)
+                         if not isinstance(masks, torch.Tensor) else masks, torch.int32, dev)
+    prm = make_params(n, m, d, B, seed=seed, perm_offset=perm_offset, pair_index=pair_index,
+                      precision=precision, input_dtype=_input_dtype(X), gd=gd, alternative=alternative,
+                      align=align, recheck=recheck, block_perms=block_perms,
+                      masks_ptr=None if mk is None else mk.data_ptr())
+    L = lib()
+    need = L.hbt_perm_test_workspace_size(C.byref(prm))
+    if need == 0:
+        need = 256
+    ws = workspace(need, dev)
+    res = torch.zeros(72, dtype=torch.uint8, device=dev)
+    T = torch.empty(B, dtype=torch.float32, device=dev) if want_T else None
+    mo = torch.empty((B, W), dtype=torch.int32, device=dev) if want_masks else None
+    _check(L.hbt_perm_test(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), C.byref(prm),
+                           C.c_void_p(res.data_ptr()), None if T is None else C.c_void_p(T.data_ptr()),
+                           None if mo is None else C.c_void_p(mo.data_ptr()),
+                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    if not sync:
+        return dict(result=res, T=T, masks=mo)
+    r = _result_dict(results_to_numpy(res)[0])
+    if T is not None:
+        r["T"] = T.cpu().numpy()
+    if mo is not None:
+        r["masks"] = mo.cpu().numpy().view(np.uint32)
+    return r
+
+
+def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair_index=None,
+                      precision="bf16x2", gd="banerjee", alternative="greater", align=True, recheck=True,
+                      stream=None, sync=True, results=None):
+    """Many pairs in one call.  Z_all (device tensor) holds rows X_0, Y_0, X_1, ...;
+    row_offset/n/m/B are host integer arrays.  Returns a numpy structured array
+    of hbt_result (or, with sync=False, the device result tensor)."""
+    torch = _torch()
+    dev = Z_all.device
+    Z_all = Z_all.contiguous()
+    P = len(n)
+    off = np.ascontiguousarray(row_offset, dtype=np.int64)
+    nn = np.ascontiguousarray(n, dtype=np.int64)
+    mm = np.ascontiguousarray(m, dtype=np.int64)
+    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
+    ids = None if pair_index is None else np.ascontiguousarray(pair_index, dtype=np.uint32)
+    d = Z_all.shape[1]
+    prm = make_params(0, 0, d, 0, seed=seed, perm_offset=perm_offset, precision=precision,
+                      input_dtype=_input_dtype(Z_all), gd=gd, alternative=alternative, align=align,
+                      recheck=recheck)
+    L = lib()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    need = L.hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm))
+    ws = workspace(max(need, 256), dev)
+    res = results if results is not None else torch.zeros(72 * P, dtype=torch.uint8, device=dev)
+    _check(L.hbt_perm_test_batched(P, C.c_void_p(Z_all.data_ptr()), ptr(off), ptr(nn), ptr(mm), ptr(BB),
+                                   None if ids is None else ptr(ids), d, C.byref(prm),
+                                   C.c_void_p(res.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream(stream)))
+    if not sync:
+        return res
+    return results_to_numpy(res)

@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/hbt.h, and rejects bad arguments on the host before
+anything is enqueued (no compute call is made here)."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_2605_08048_amd import hbt
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "hbt.h"
+
+pytestmark = pytest.mark.skipif(not hbt.LIB_PATH.exists(), reason="libhbt.so not built")
+
+
+def declared_functions():
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    return sorted(set(re.findall(r"\b(hbt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_calls():
+    names = declared_functions()
+    for f in ["hbt_align", "hbt_perm_test", "hbt_perm_test_batched"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = hbt.lib()
+    missing = [f for f in declared_functions() if not hasattr(L, f)]
+    assert not missing, missing
+    assert L.hbt_abi_version() == 1
+
+
+def test_struct_sizes_match_header():
+    assert C.sizeof(hbt.HbtResult) == 72
+    assert C.sizeof(hbt.HbtPermParams) == 96
+    assert hbt.HbtPermParams.masks.offset == 88 and hbt.HbtPermParams.block_perms.offset == 80
+
+
+def test_status_strings():
+    L = hbt.lib()
+    for s in range(10):
+        assert L.hbt_status_string(s)
+    assert L.hbt_status_string(99) == b"unknown status"
+
+
+FAKE = C.c_void_p(0x1000)  # never dereferenced: every case below fails validation first
+
+
+def _call(prm, X=FAKE, Y=FAKE, res=FAKE, ws=FAKE, ws_bytes=1 << 40):
+    return hbt.lib().hbt_perm_test(X, Y, C.byref(prm), res, None, None, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("n,m,d,B,status", [
+    (1, 10, 8, 10, hbt.ERR_SIZE), (10, 1, 8, 10, hbt.ERR_SIZE), (10, 10, 0, 10, hbt.ERR_SIZE),
+    (10, 10, 8, 0, hbt.ERR_SIZE), (40000, 30000, 8, 10, hbt.ERR_SIZE), (10, 10, 9000, 10, hbt.ERR_SIZE),
+])
+def test_perm_test_rejects_bad_sizes(n, m, d, B, status):
+    assert _call(hbt.make_params(n, m, d, B)) == status
+    assert hbt.lib().hbt_last_error()
+
+
+def test_perm_test_rejects_null_pointers_and_enums():
+    prm = hbt.make_params(10, 12, 8, 10)
+    assert _call(prm, X=None) == hbt.ERR_ARG
+    assert _call(prm, res=None) == hbt.ERR_ARG
+    assert hbt.lib().hbt_perm_test(FAKE, FAKE, None, FAKE, None, None, FAKE, 1 << 40, None) == hbt.ERR_ARG
+    for field, bad, st in [("precision", 7, hbt.ERR_ARG), ("input_dtype", 5, hbt.ERR_DTYPE),
+                           ("gd", 3, hbt.ERR_ARG), ("alternative", 2, hbt.ERR_ARG),
+                           ("align", 2, hbt.ERR_ARG), ("flags", 8, hbt.ERR_ARG),
+                           ("stat_route", 5, hbt.ERR_UNSUPPORTED), ("block_perms", -1, hbt.ERR_ARG)]:
+        p = hbt.make_params(10, 12, 8, 10)
+        setattr(p, field, bad)
+        assert _call(p) == st, field
+
+
+def test_perm_offset_overflow():
+    prm = hbt.make_params(10, 12, 8, 100, perm_offset=2**32 - 50)
+    assert _call(prm) == hbt.ERR_ARG
+
+
+def test_workspace_size_and_too_small_workspace():
+    L = hbt.lib()
+    prm = hbt.make_params(2000, 1500, 768, 10000, precision="bf16x2")
+    need = L.hbt_perm_test_workspace_size(C.byref(prm))
+    # Z planes alone: 3520 rows x 768 x 4 bytes
+    assert need > 3520 * 768 * 4
+    assert _call(prm, ws_bytes=need - 1) == hbt.ERR_WORKSPACE
+    assert _call(prm, ws=None) == hbt.ERR_WORKSPACE
+    bad = hbt.make_params(1, 1500, 768, 10)
+    assert L.hbt_perm_test_workspace_size(C.byref(bad)) == 0
+    # more splits per block need more workspace; B0 = 1 needs the least
+    small = hbt.make_params(2000, 1500, 768, 10000, precision="bf16x2", block_perms=1)
+    assert L.hbt_perm_test_workspace_size(C.byref(small)) < need
+
+
+def test_align_validation():
+    L = hbt.lib()
+    assert L.hbt_align(0, None, 10, FAKE, 10, 8, 1, 0, FAKE, None, FAKE, FAKE, 1 << 30, None) == hbt.ERR_ARG
+    assert L.hbt_align(0, FAKE, 1, FAKE, 10, 8, 1, 0, FAKE, None, FAKE, FAKE, 1 << 30, None) == hbt.ERR_SIZE
+    assert L.hbt_align(3, FAKE, 10, FAKE, 10, 8, 1, 0, FAKE, None, FAKE, FAKE, 1 << 30, None) == hbt.ERR_DTYPE
+    need = L.hbt_align_workspace_size(10, 10, 8)
+    assert need > 0
+    assert L.hbt_align(0, FAKE, 10, FAKE, 10, 8, 1, 0, FAKE, None, FAKE, FAKE, need - 1, None) == hbt.ERR_WORKSPACE
+
+
+def test_batched_validation():
+    import numpy as np
+    L = hbt.lib()
+    P = 3
+    n = np.array([10, 20, 1], dtype=np.int64)
+    m = np.array([10, 20, 30], dtype=np.int64)
+    B = np.array([5, 5, 5], dtype=np.int64)
+    off = np.array([0, 20, 60, 91], dtype=np.int64)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    prm = hbt.make_params(0, 0, 8, 0, precision="bf16x2")
+    assert L.hbt_perm_test_batched_workspace_size(P, ptr(n), ptr(m), ptr(B), 8, C.byref(prm)) == 0
+    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                 FAKE, 1 << 40, None)
+    assert st == hbt.ERR_SIZE and b"pair 2" in L.hbt_last_error()
+    n[2] = 3
+    need = L.hbt_perm_test_batched_workspace_size(P, ptr(n), ptr(m), ptr(B), 8, C.byref(prm))
+    assert need > 0
+    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                 FAKE, need - 1, None)
+    assert st == hbt.ERR_WORKSPACE
+    st = L.hbt_perm_test_batched(0, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                 FAKE, need, None)
+    assert st == hbt.ERR_SIZE

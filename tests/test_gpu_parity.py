@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (per result, against FP64):
+  * random splits and their masks: bit-exact;
+  * Householder: r, T_obs in FP64 to 1e-12; aligned rows in the input dtype;
+  * permuted statistics T_b: |T_gpu - T_64| <= tol * (|f(r1)| + |f(r2)|) with
+    tol = 1e-10 (F64), 1e-5 (F32), 1e-4 (split BF16);
+  * exceedance counts: equal, except for splits with |T_64 - T_obs| <=
+    1e-6 |T_obs| (none of which occur in these cases, so counts are equal);
+  * p = (1 + count) / (B + 1) exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_08048_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from paper_2605_08048_amd import hbt  # noqa: E402
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4}
+
+
+def _dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def _logg(r, d):
+    return np.log(r * (d - r * r) / (1 - r * r))
+
+
+def _scale(X, Y, ora_at):
+    d = X.shape[1]
+    return np.abs(_logg(ora_at["r1"], d)) + np.abs(_logg(ora_at["r2"], d))
+
+
+def _tie_band(T64, tobs):
+    return int(np.sum(np.abs(T64 - tobs) <= 1e-6 * abs(tobs)))
+
+
+def _pair(n, m, d, kx=2.0, ky=2.4, angle=40.0, seed=0, f64=False):
+    g = np.random.default_rng([5, seed])
+    mu = synth.random_unit(g, d)
+    mv = synth.direction_at_angle(g, mu, angle)
+    X = synth.unit_rows(kx * mu + g.standard_normal((n, d)) / math.sqrt(d))
+    Y = synth.unit_rows(ky * mv + g.standard_normal((m, d)) / math.sqrt(d))
+    if not f64:
+        X, Y = X.astype(np.float32), Y.astype(np.float32)
+    return X, Y
+
+
+# --------------------------------------------------------------------- align
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_align_matches_oracle(f64):
+    print(f"align f64={f64}", flush=True)
+    X, Y = _pair(300, 257, 100, seed=1, f64=f64)
+    r = hbt.align(_dev(X), _dev(Y))
+    o = O.align(X, Y)
+    assert r["status"] == 0 and r["h_identity"] == 0
+    assert abs(r["r_x"] - o["r_x"]) < 1e-12 and abs(r["r_y"] - o["r_y"]) < 1e-12
+    assert abs(r["t_obs"] - o["t_obs"]) < 1e-12 * max(1, abs(o["t_obs"]))
+    assert np.abs(r["v"].cpu().numpy() - o["v"]).max() < 1e-13
+    Xp = r["X_out"].cpu().numpy().astype(np.float64)
+    ulp = 1e-15 if f64 else 2e-7
+    assert np.abs(Xp - o["Xp"]).max() <= ulp * 4
+    # H mu_x = mu_y and r(X') = r(X) on the GPU result
+    assert abs(np.linalg.norm(o["Xp"].mean(0)) - r["r_x"]) < 1e-12
+
+
+def test_align_in_place_and_identity():
+    X, Y = _pair(64, 70, 33, seed=2)
+    Xd = _dev(X)
+    o = O.align(X, Y)
+    r = hbt.align(Xd, _dev(Y), out=Xd)
+    assert np.abs(Xd.cpu().numpy() - o["Xp"]).max() < 1e-6
+    r0 = hbt.align(_dev(X), _dev(Y), align=False)
+    assert r0["h_identity"] == 1 and np.array_equal(r0["X_out"].cpu().numpy(), X)
+    same = hbt.align(_dev(X), _dev(X))
+    assert same["h_identity"] == 1 and same["t_obs"] == 0.0
+
+
+# --------------------------------------------------------------------- splits
+
+@pytest.mark.parametrize("n,m", [(4, 4), (2, 61), (50, 60), (777, 3), (1000, 1048), (2000, 1500), (5000, 4999)])
+def test_masks_bit_exact(n, m):
+    print(f"masks n={n} m={m}", flush=True)
+    N = n + m
+    d = 8
+    X, Y = _pair(n, m, d, seed=3)
+    B = 64
+    for seed, pair, off in [(0, 0, 0), (123456789012345, 77, 4000000000)]:
+        r = hbt.perm_test(_dev(X), _dev(Y), B, seed=seed, pair_index=pair, perm_offset=off,
+                          precision="f32", want_masks=True)
+        got = r["masks"]
+        assert got.shape == (B, (N + 31) // 32)
+        want = np.stack([O.split_mask(seed, pair, off + b, N, n) for b in range(B)])
+        assert np.array_equal(got, want)
+        assert r["status"] == 0
+
+
+# --------------------------------------------------------------------- full test, small shapes
+
+CASES = [
+    # n, m, d, B, precision, f64-input
+    (50, 60, 64, 999, "f64", True),     # the FP64 correctness configuration
+    (37, 150, 100, 700, "f64", False),
+    (37, 150, 100, 700, "f32", False),  # ragged d (pad to 128) and ragged N
+    (150, 37, 100, 700, "f32", False),  # n > m: the product runs on group 2
+    (37, 150, 100, 700, "bf16x2", False),
+    (150, 37, 100, 700, "bf16x2", False),
+    (300, 450, 768, 600, "bf16x2", False),
+    (300, 450, 768, 600, "f32", False),
+]
+
+
+@pytest.mark.parametrize("n,m,d,B,prec,f64", CASES)
+def test_perm_test_matches_oracle(n, m, d, B, prec, f64):
+    print(f"perm_test n={n} m={m} d={d} B={B} {prec} f64={f64}", flush=True)
+    X, Y = _pair(n, m, d, kx=2.0, ky=2.1, seed=n + m + d, f64=f64)
+    r = hbt.perm_test(_dev(X), _dev(Y), B, seed=7, precision=prec, want_T=True)
+    o = O.perm_test(X, Y, B, seed=7, want_T=True)
+    at = O.perm_stats_at(X, Y, np.arange(B), seed=7)
+    assert r["status"] == 0
+    assert abs(r["t_obs"] - o["t_obs"]) <= 1e-12 * max(1.0, abs(o["t_obs"]))
+    err = np.abs(r["T"].astype(np.float64) - o["T"]) / _scale(X, Y, at)
+    # T_out is rounded to float32 on output: allow its half-ulp on top of the bar
+    assert err.max() <= TOL[prec] + 1.2e-7, err.max()
+    band = _tie_band(o["T"], o["t_obs"])
+    assert abs(r["count"] - o["count"]) <= band
+    assert r["B"] == B and r["p"] == (1 + r["count"]) / (B + 1)
+
+
+def test_identical_groups_give_zero_and_count_all_ties():
+    X, _ = _pair(40, 40, 32, seed=9)
+    r = hbt.perm_test(_dev(X), _dev(X.copy()), 500, precision="f32")
+    o = O.perm_test(X, X.copy(), 500)
+    assert r["t_obs"] == 0.0 and r["h_identity"] == 1
+    assert r["count"] == o["count"]
+
+
+def test_exhaustive_70_splits_with_explicit_masks():
+    X, Y = _pair(4, 4, 16, kx=1.5, ky=2.5, angle=60.0, seed=11, f64=True)
+    from itertools import combinations
+    sel = np.zeros((70, 8), bool)
+    for k, c in enumerate(combinations(range(8), 4)):
+        sel[k, list(c)] = True
+    masks = O.bool_to_mask(sel)
+    ex = O.exhaustive(X, Y)
+    for prec in ["f64", "f32", "bf16x2"]:
+        r = hbt.perm_test(_dev(X), _dev(Y), 70, precision=prec, masks=masks)
+        assert r["status"] == 0
+        assert r["count"] == ex["count"]
+        assert r["count"] / 70 == ex["p"]
+
+
+def test_bad_explicit_mask_is_reported():
+    X, Y = _pair(10, 12, 8, seed=12)
+    masks = np.stack([O.split_mask(0, 0, b, 22, 10) for b in range(5)])
+    masks[2, 0] ^= 1
+    r = hbt.perm_test(_dev(X), _dev(Y), 5, masks=masks)
+    assert r["status"] == hbt.ERR_MASK
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2"])
+def test_block_size_offsets_and_repeat_do_not_change_results(prec):
+    X, Y = _pair(500, 700, 128, kx=2.0, ky=2.05, seed=13)
+    Xd, Yd = _dev(X), _dev(Y)
+    full = hbt.perm_test(Xd, Yd, 3000, seed=5, precision=prec, want_T=True)
+    again = hbt.perm_test(Xd, Yd, 3000, seed=5, precision=prec, want_T=True)
+    blocked = hbt.perm_test(Xd, Yd, 3000, seed=5, precision=prec, block_perms=700, want_T=True)
+    a = hbt.perm_test(Xd, Yd, 1234, seed=5, precision=prec)
+    b = hbt.perm_test(Xd, Yd, 3000 - 1234, seed=5, perm_offset=1234, precision=prec)
+    assert np.array_equal(full["T"], again["T"]) and np.array_equal(full["T"], blocked["T"])
+    assert full["count"] == again["count"] == blocked["count"] == a["count"] + b["count"]
+
+
+def test_two_sided_and_identity_gd():
+    X, Y = _pair(80, 90, 48, kx=1.5, ky=2.5, seed=14)
+    for alt in ["two-sided", "greater"]:
+        for gd in ["identity", "banerjee"]:
+            r = hbt.perm_test(_dev(X), _dev(Y), 400, seed=3, precision="f32", alternative=alt, gd=gd)
+            o = O.perm_test(X, Y, 400, seed=3, alternative=O.ALT_TWO_SIDED if alt != "greater" else 0,
+                            gd=O.GD_IDENTITY if gd == "identity" else 0, want_T=True)
+            assert r["count"] == o["count"], (alt, gd)
+
+
+def test_naive_alignment_flag():
+    X, Y = _pair(60, 70, 40, seed=15)
+    r = hbt.perm_test(_dev(X), _dev(Y), 300, precision="f32", align=False, want_T=True)
+    o = O.perm_test(X, Y, 300, align=0, want_T=True)
+    assert r["h_identity"] == 1 and r["count"] == o["count"]
+
+
+def test_no_recheck_flag_counts_raw_precision():
+    X, Y = _pair(300, 300, 128, kx=2.0, ky=2.0, seed=16)
+    r = hbt.perm_test(_dev(X), _dev(Y), 2000, precision="bf16x2", recheck=False, want_T=True)
+    assert r["n_recheck"] == 0
+    thr = r["t_obs"] - r["tau"]
+    # T_out is rounded to float32, so decisions right at the threshold may differ by a few
+    assert abs(r["count"] - int(np.sum(r["T"].astype(np.float64) >= thr))) <= 2
+
+
+# --------------------------------------------------------------------- batched
+
+def test_batched_matches_oracle_per_pair():
+    rng = np.random.default_rng(17)
+    pairs = []
+    for p in range(7):
+        n = int(rng.integers(2, 400))
+        m = int(rng.integers(2, 400))
+        X, Y = _pair(n, m, 96, kx=rng.uniform(1.5, 3), ky=rng.uniform(1.5, 3), seed=100 + p)
+        pairs.append(synth.Pair(X, Y, B=int(rng.integers(1, 700)), pair_index=p))
+    pairs[3] = synth.Pair(pairs[3].X, pairs[3].X.copy(), B=300, pair_index=3)  # identical groups
+    bt = synth.pack_batch(pairs, 96)
+    for prec in ["f32", "bf16x2", "f64"]:
+        res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=9, precision=prec)
+        for p, pr in enumerate(pairs):
+            o = O.perm_test(pr.X, pr.Y, pr.B, seed=9, pair=p, want_T=True)
+            assert res[p]["status"] == 0
+            assert abs(res[p]["t_obs"] - o["t_obs"]) <= 1e-12 * max(1, abs(o["t_obs"]))
+            assert abs(res[p]["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"]), (prec, p)
+            assert res[p]["B"] == pr.B
+
+
+# --------------------------------------------------------------------- full-size configurations
+
+def test_config1_fp64():
+    c = synth.config1()
+    r = hbt.perm_test(_dev(c.X), _dev(c.Y), c.B, seed=c.seed, precision="f64", want_T=True)
+    o = O.perm_test(c.X, c.Y, c.B, seed=c.seed, want_T=True)
+    at = O.perm_stats_at(c.X, c.Y, np.arange(c.B))
+    err = np.abs(r["T"] - o["T"]) / _scale(c.X, c.Y, at)
+    assert err.max() < 1e-7  # T_out is float32
+    assert r["count"] == o["count"] and r["p"] == o["p"]
+    assert abs(r["t_obs"] - o["t_obs"]) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2"])
+def test_config2_full_size(prec):
+    print(f"config2 {prec}", flush=True)
+    c = synth.config2()
+    Xd, Yd = _dev(c.X), _dev(c.Y)
+    r = hbt.perm_test(Xd, Yd, c.B, seed=c.seed, precision=prec, want_T=True)
+    sample = np.unique(np.concatenate([np.arange(0, c.B, 97), [c.B - 1]]))
+    at = O.perm_stats_at(c.X, c.Y, sample, want_masks=True)
+    m = hbt.perm_test(Xd, Yd, 1, seed=c.seed, perm_offset=int(sample[5]), precision=prec, want_masks=True)
+    assert np.array_equal(m["masks"][0], at["masks"][5])
+    err = np.abs(r["T"][sample] - at["T"]) / _scale(c.X, c.Y, at)
+    assert err.max() <= TOL[prec] + 1.2e-7, err.max()
+    o = O.perm_test(c.X, c.Y, c.B, seed=c.seed, want_T=True)
+    assert abs(r["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"])
+    assert abs(r["t_obs"] - o["t_obs"]) < 1e-12 * abs(o["t_obs"])
