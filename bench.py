@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the Householder-aligned permutation test on one MI355X.
+
+Metric: permuted statistics per second at d = 768.  One step is one call of
+the whole hot path (alignment, Philox splits, group-sum product, statistic,
+FP64 recheck, p-values) over the batched workload, inputs resident in HBM:
+512 pairs of synthetic clouds, d = 768, B = 2000 splits per pair, group
+sizes log-uniform on [20, 5000], split-BF16 group sums.  The same workload
+is also timed with plain FP32 group sums (the comparison in the metric).
+
+Prints one JSON line.  ``roofline`` is the group-sum kernel (the dominant
+kernel) timed with HIP events on the library's stream; ``cpu_baseline`` is
+the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 MFMA
+STAGES = ["align", "split", "groupsum", "stat", "recheck", "other"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ["groupsum.hip", "hbt_internal.h"]:
+        h.update((ROOT / "paper_2605_08048_amd" / "csrc" / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name, launches_per_step):
+    """HBM bytes per launch of the group-sum kernel from the committed
+    rocprofv3 counter summary, or None when it is missing or stale."""
+    f = ROOT / "profiles" / name
+    if not f.exists():
+        return None
+    try:
+        rec = json.loads(f.read_text())
+    except ValueError:
+        return None
+    if rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def stage_times(L, ctypes):
+    ms = (ctypes.c_double * 6)()
+    n = (ctypes.c_int64 * 6)()
+    st = L.hbt_stage_times(ms, n)
+    if st != 0:
+        raise RuntimeError(L.hbt_last_error().decode())
+    return list(ms), list(n)
+
+
+def cpu_baseline(batch, npairs_sample=32, splits=250):
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    threads = min(threads, 16)
+    t0 = time.perf_counter()
+    total = 0
+    for p in range(min(npairs_sample, batch.npairs)):
+        pr = batch.pair(p)
+        r = O.perm_test(pr.X, pr.Y, splits, seed=batch.seed, pair=pr.pair_index, nthreads=threads)
+        assert r["status"] in (0, O.ERR_DEGENERATE)
+        total += splits
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "permuted statistics/s", "cores": threads, "kind": "oracle",
+            "sample": f"pairs 0..{npairs_sample - 1} of the workload, first {splits} splits each "
+                      f"({total} statistics, {dt:.1f} s wall, FP64 C oracle, OpenMP over splits)"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the permutation test shards by split ranges, see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes
+    import torch
+    from paper_2605_08048_amd import hbt, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = time.perf_counter()
+    batch = synth.config4()
+    Z = torch.from_numpy(batch.Z).to(dev)
+    log(f"workload generated and resident in HBM ({time.perf_counter() - t:.1f} s, {Z.numel() * 4 / 1e9:.2f} GB)")
+    P = batch.npairs
+    N = (batch.n + batch.m).astype(np.int64)
+    d = batch.d
+    stats_per_step = int(batch.B.sum())
+    algo_flops = float(2 * d * np.sum(batch.B * N))       # 2 N d per permuted statistic
+    L = hbt.lib()
+
+    def run(prec, steps, warmup):
+        res = torch.zeros(72 * P, dtype=torch.uint8, device=dev)
+        for _ in range(warmup):
+            hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
+                                  precision=prec, sync=False, results=res)
+        torch.cuda.synchronize()
+        L.hbt_stage_timing(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
+                                  precision=prec, sync=False, results=res)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms, launches = stage_times(L, ctypes)
+        L.hbt_stage_timing(0)
+        out = hbt.results_to_numpy(res)
+        bad = int(np.sum(out["status"] != 0))
+        return (t1 - t0), ms, launches, out, bad
+
+    dt, ms, launches, out, bad = run("bf16x2", args.steps, args.warmup)
+    log(f"split-BF16: {dt / args.steps * 1e3:.2f} ms/step")
+    value = stats_per_step * args.steps / dt
+    g_ms = ms[2] / max(launches[2], 1)
+    achieved = algo_flops / (g_ms * 1e-3) / 1e12
+    traffic = load_traffic("groupsum_bf16x2_config4_traffic.json", 1)
+
+    fp = None
+    if args.fp32_steps > 0:
+        dt32, ms32, l32, out32, bad32 = run("f32", args.fp32_steps, 1)
+        log(f"FP32: {dt32 / args.fp32_steps * 1e3:.2f} ms/step")
+        v32 = stats_per_step * args.fp32_steps / dt32
+        g32 = ms32[2] / max(l32[2], 1)
+        agree = int(np.sum(out32["count"] == out["count"]))
+        fp = {"value": v32, "ms_per_step": dt32 / args.fp32_steps * 1e3,
+              "groupsum_ms": g32, "groupsum_tflops": algo_flops / (g32 * 1e-3) / 1e12,
+              "groupsum_frac_fp32_peak": algo_flops / (g32 * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+              "speedup_bf16x2_over_fp32": value / v32,
+              "pairs_with_equal_counts": f"{agree}/{P}"}
+
+    line = {
+        "metric": "permuted statistics/s at d=768 (batched split-BF16 MFMA; plain FP32 in fp32_plain)",
+        "value": value,
+        "unit": "permuted statistics/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "config4: 512 pairs, d=768, B=2000 splits/pair, n,m log-uniform [20,5000], "
+                               "split-BF16 group sums (hi+lo, FP32 accumulation), FP64 statistic + recheck",
+                   "pairs": P, "d": d, "splits_per_step": stats_per_step, "rows": int(N.sum())},
+        "roofline": {"bound": "mfma", "kernel": "k_groupsum_bf16x2", "achieved": achieved,
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
+                     "traffic": traffic,
+                     "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": g_ms,
+                     "executed_mfma_tflops": 2 * achieved},
+        "stages_ms_per_step": {k: ms[i] / args.steps for i, k in enumerate(STAGES)},
+        "pairs_bad_status": bad,
+        "fp32_plain": fp,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(batch)
+        log("cpu baseline done")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -110,14 +110,17 @@ typedef struct hbt_perm_params {
     int32_t alternative;    /* hbt_alternative */
     int32_t align;          /* 1 = Householder alignment (the paper), 0 = naive test */
     int32_t stat_route;     /* 0 = norms of the group sums; 1 = point-to-centroid products */
-    int32_t flags;          /* bit 0 (HBT_FLAG_NO_RECHECK): skip the FP64 recheck */
+    int32_t flags;          /* HBT_FLAG_* bits */
     int64_t block_perms;    /* splits per block (B0 of Algorithm 2); 0 = automatic.
                                Results do not depend on it. */
     const uint32_t* masks;  /* optional DEVICE B x ceil((n+m)/32) group-1 masks replacing
                                the Philox splits; each row must hold exactly n items. */
 } hbt_perm_params;
 
+/* flags: skip the FP64 recheck (counts then follow the chosen precision alone) */
 #define HBT_FLAG_NO_RECHECK 1
+/* flags: T_out of hbt_perm_test is a double array (B doubles) instead of floats */
+#define HBT_FLAG_T_OUT_F64 2
 
 int32_t hbt_abi_version(void);
 const char* hbt_status_string(int32_t status);
@@ -171,6 +174,25 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                  const uint32_t* pair_index, int64_t d,
                                  const hbt_perm_params* common, hbt_result* results, void* ws,
                                  size_t ws_bytes, void* stream);
+
+/* Stage timing, a profiling aid.  hbt_stage_timing(1) clears the record and
+ * makes every later call record a pair of HIP events around each of its
+ * stages on its stream; hbt_stage_timing(0) stops recording.
+ * hbt_stage_times() waits for the recorded events, writes the summed
+ * milliseconds (ms) and the number of timed launches (launches) of each stage
+ * (HBT_NUM_STAGES entries each, host memory) and clears the record.
+ * Errors: HBT_ERR_ARG (NULL outputs), HBT_ERR_DEVICE. */
+typedef enum hbt_stage {
+    HBT_STAGE_ALIGN = 0,     /* column sums, finalize, reflection + storage */
+    HBT_STAGE_SPLIT = 1,     /* Philox split masks */
+    HBT_STAGE_GROUPSUM = 2,  /* group-sum product (eq:gemm) with norm epilogue */
+    HBT_STAGE_STAT = 3,      /* permuted statistics and exceedance counts */
+    HBT_STAGE_RECHECK = 4,   /* FP64 re-evaluation near the threshold */
+    HBT_STAGE_OTHER = 5,     /* table uploads, zero fills, p-values */
+    HBT_NUM_STAGES = 6
+} hbt_stage;
+hbt_status hbt_stage_timing(int32_t enable);
+hbt_status hbt_stage_times(double* ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,18 +36,59 @@ hbt_status fail(hbt_status st, const char* fmt, ...) {
                         __FILE__, __LINE__);                                              \
     } while (0)
 
+// --- stage timing ------------------------------------------------------
+struct StageRecord {
+    int stage;
+    hipEvent_t start, stop;
+};
+std::mutex g_timing_mu;
+bool g_timing = false;
+std::vector<StageRecord> g_records;
+
+// Records a start event at construction and a stop event at destruction on
+// the stream, when timing is enabled.
+struct StageTimer {
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    int stage;
+    StageTimer(int st, hipStream_t str) : s(str), stage(st) {
+        std::lock_guard<std::mutex> g(g_timing_mu);
+        if (!g_timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+            hipEventRecord(a, s) != hipSuccess) {
+            a = b = nullptr;
+        }
+    }
+    ~StageTimer() {
+        if (!a) return;
+        if (hipEventRecord(b, s) != hipSuccess) return;
+        std::lock_guard<std::mutex> g(g_timing_mu);
+        g_records.push_back(StageRecord{stage, a, b});
+    }
+};
+
 constexpr int kSumChunk = 128;       // rows per column-sum chunk
 constexpr int64_t kAutoBlock = 32768;  // splits per block when block_perms == 0
 
 int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
 
-// Relative error bound of the squared group-sum norms, per precision; a
-// split within the implied band of the threshold is re-evaluated in FP64.
-double precision_rel_err(int precision) {
+// Recheck band.  A split is re-evaluated in FP64 when its T_b lies within
+//   (e_acc + e_store / sqrt(min(n, m) * d)) * (sens(r1^2) + sens(r2^2))
+// of the threshold, sens = |s d/ds log g_d(sqrt s)|: the relative error of
+// the squared group-sum norms times the sensitivity of log g_d.  e_acc covers
+// FP32 accumulation, e_store the BF16 hi+lo storage error, which averages
+// over the k items and d columns of the smaller group.  Measured worst cases
+// on MI355X (35 shapes, n and m from 2 to 5000, d = 64 ... 1024, r up to
+// 0.997): 2.5e-7 (F32), 1.6e-6 (split BF16, n = 2, d = 64); the constants
+// below are >= 9x those.
+struct Band {
+    double e_acc, e_store;
+};
+Band precision_band(int precision) {
     switch (precision) {
-        case HBT_F64: return 1e-11;
-        case HBT_F32: return 3e-5;
-        default: return 1e-4;
+        case HBT_F64: return Band{1e-12, 0.0};
+        case HBT_F32: return Band{4e-6, 0.0};
+        default: return Band{4e-6, 16.0 * 2.3 / 131072.0};
     }
 }
 
@@ -185,7 +227,8 @@ hbt_status check_enums(const hbt_perm_params* prm) {
     if (prm->align != 0 && prm->align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
     if (prm->stat_route != 0)
         return fail(HBT_ERR_UNSUPPORTED, "stat_route %d is not available", prm->stat_route);
-    if (prm->flags & ~HBT_FLAG_NO_RECHECK) return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
+    if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64))
+        return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
     return HBT_OK;
 }
 
@@ -216,7 +259,8 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     B0 = std::min<int64_t>(B0, prm->B);
     *B0_out = B0;
     P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0});
-    for (int64_t b = 0; b < B0; b += kTileB) P.tiles.push_back(GemmTile{0, (int32_t)b});
+    const int tb = groupsum_tile_splits(prm->precision);
+    for (int64_t b = 0; b < B0; b += tb) P.tiles.push_back(GemmTile{0, (int32_t)b});
     P.Btot.push_back(prm->B);
     P.block_rows = B0;
     P.block_mask_words = B0 * P.pairs[0].Wp;
@@ -225,8 +269,12 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
 
 hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd, hbt_result* res,
                             hipStream_t s) {
-    HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
-    HIP_TRY(upload(w.chunks, P.chunks.data(), P.chunks.size() * sizeof(SumChunk), s));
+    {
+        StageTimer t(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
+        HIP_TRY(upload(w.chunks, P.chunks.data(), P.chunks.size() * sizeof(SumChunk), s));
+    }
+    StageTimer t(HBT_STAGE_ALIGN, s);
     HIP_TRY(launch_colsum(P.input_dtype, w.pairs, w.chunks, (int)P.chunks.size(), P.d,
                           w.partial_sum, s));
     HIP_TRY(launch_finalize(w.pairs, P.npairs, w.partial_sum, P.d, P.d_pad, align, gd, w.sxy, w.st,
@@ -257,6 +305,48 @@ const char* hbt_status_string(int32_t status) {
 }
 
 const char* hbt_last_error(void) { return g_err.c_str(); }
+
+hbt_status hbt_stage_timing(int32_t enable) {
+    std::vector<StageRecord> old;
+    {
+        std::lock_guard<std::mutex> g(g_timing_mu);
+        g_timing = enable != 0;
+        old.swap(g_records);
+    }
+    for (auto& r : old) {
+        (void)hipEventSynchronize(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    return HBT_OK;
+}
+
+hbt_status hbt_stage_times(double* ms, int64_t* launches) {
+    g_err.clear();
+    if (!ms || !launches) return fail(HBT_ERR_ARG, "NULL output");
+    std::vector<StageRecord> recs;
+    {
+        std::lock_guard<std::mutex> g(g_timing_mu);
+        recs.swap(g_records);
+    }
+    for (int k = 0; k < HBT_NUM_STAGES; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    hbt_status st = HBT_OK;
+    for (auto& r : recs) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+        if (e != hipSuccess && st == HBT_OK)
+            st = fail(HBT_ERR_DEVICE, "stage timing: %s", hipGetErrorString(e));
+        ms[r.stage] += t;
+        launches[r.stage] += 1;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    return st;
+}
 
 // ---------------------------------------------------------------------------
 size_t hbt_align_workspace_size(int64_t n, int64_t m, int64_t d) {
@@ -330,34 +420,48 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 
     st = enqueue_prologue(P, w, prm->align, prm->gd, result, s);
     if (st) return st;
-    HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
-    HIP_TRY(upload(w.Btot, P.Btot.data(), sizeof(int64_t), s));
-    HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, 1, P.zrows / 8, w.st, w.v, P.d,
-                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s));
-    const double e_rel = precision_rel_err(P.precision);
+    {
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
+        HIP_TRY(upload(w.Btot, P.Btot.data(), sizeof(int64_t), s));
+    }
+    { StageTimer t_(HBT_STAGE_ALIGN, s); HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, 1, P.zrows / 8, w.st, w.v, P.d,
+                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s)); }
+    const Band band = precision_band(P.precision);
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
+    const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
     for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
         const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
         BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
-        HIP_TRY(upload(w.bp, &bq, sizeof bq, s));
-        HIP_TRY(zero(w.nflag, 8, s));
-        if (prm->masks)
-            HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.st, s));
-        else
-            HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.st, s));
-        const int ntiles = (int)((nb + kTileB - 1) / kTileB);
-        HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, P.d_pad, w.zstore,
-                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s));
-        HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st, w.partial, P.nslot, P.d, prm->gd,
-                            prm->alternative, e_rel, no_recheck, T_out ? T_out + b0 : nullptr,
-                            w.cnt, w.flags, w.nflag, s));
-        if (!no_recheck)
-            HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.coef, w.mask,
+        {
+            StageTimer t_(HBT_STAGE_OTHER, s);
+            HIP_TRY(upload(w.bp, &bq, sizeof bq, s));
+            HIP_TRY(zero(w.nflag, 8, s));
+        }
+        {
+            StageTimer t_(HBT_STAGE_SPLIT, s);
+            if (prm->masks)
+                HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.st, s));
+            else
+                HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.st, s));
+        }
+        const int tb = groupsum_tile_splits(P.precision);
+        const int ntiles = (int)((nb + tb - 1) / tb);
+        { StageTimer t_(HBT_STAGE_GROUPSUM, s); HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, P.d_pad, w.zstore,
+                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s)); }
+        { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st, w.partial, P.nslot, P.d, prm->gd,
+                            prm->alternative, band.e_acc, band.e_store, no_recheck,
+                            T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8,
+                            w.cnt, w.flags, w.nflag, s)); }
+        if (!no_recheck) {
+            StageTimer t_(HBT_STAGE_RECHECK, s);
+            HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.t64, w.coef, w.mask,
                                    w.flags, w.nflag, nb, P.d, prm->gd, prm->alternative, w.cnt, s));
+        }
         if (mask_out)
             HIP_TRY(launch_export_masks(w.mask, nb, pd.Wp, W, mask_out + b0 * W, s));
     }
-    HIP_TRY(launch_final(1, w.st, w.cnt, w.Btot, result, s));
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(1, w.st, w.cnt, w.Btot, result, s)); }
     return HBT_OK;
 }
 
@@ -382,8 +486,9 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
     for (int64_t p = 0; p < npairs; ++p) order[(size_t)p] = (int)p;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
+    const int tb = groupsum_tile_splits(common->precision);
     for (int p : order)
-        for (int64_t b = 0; b < B[p]; b += kTileB) P.tiles.push_back(GemmTile{p, (int32_t)b});
+        for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
     P.block_rows = rows;
     P.block_mask_words = words;
     return true;
@@ -433,24 +538,30 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     const int np = P.npairs;
     st = enqueue_prologue(P, w, common->align, common->gd, results, s);
     if (st) return st;
-    HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
-    HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
-    HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
-    HIP_TRY(zero(w.nflag, 8, s));
-    HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, np, P.zrows / 8, w.st, w.v, P.d,
-                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s));
-    HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask,
-                               w.st, s));
-    HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), P.d_pad,
-                            w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s));
+    {
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
+        HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
+        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
+        HIP_TRY(zero(w.nflag, 8, s));
+    }
+    { StageTimer t_(HBT_STAGE_ALIGN, s); HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, np, P.zrows / 8, w.st, w.v, P.d,
+                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s)); }
+    { StageTimer t_(HBT_STAGE_SPLIT, s); HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask,
+                               w.st, s)); }
+    { StageTimer t_(HBT_STAGE_GROUPSUM, s); HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), P.d_pad,
+                            w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s)); }
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
-    HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
-                        common->alternative, precision_rel_err(P.precision), no_recheck, nullptr,
-                        w.cnt, w.flags, w.nflag, s));
-    if (!no_recheck)
-        HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.coef, w.mask, w.flags,
+    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
+                        common->alternative, precision_band(P.precision).e_acc,
+                        precision_band(P.precision).e_store, no_recheck, nullptr,
+                        false, w.cnt, w.flags, w.nflag, s)); }
+    if (!no_recheck) {
+        StageTimer t_(HBT_STAGE_RECHECK, s);
+        HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
                                w.nflag, P.block_rows, P.d, common->gd, common->alternative, w.cnt, s));
-    HIP_TRY(launch_final(np, w.st, w.cnt, w.Btot, results, s));
+    }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.st, w.cnt, w.Btot, results, s)); }
     return HBT_OK;
 }
 

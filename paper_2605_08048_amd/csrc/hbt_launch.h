@@ -56,6 +56,8 @@ hipError_t launch_export_masks(const uint32_t* mask, int64_t rows, int Wp, int W
                                hipStream_t s);
 
 // --- group sums (eq:gemm) -----------------------------------------------
+// Splits per group-sum tile (the tile list steps b0 by this).
+int groupsum_tile_splits(int precision);
 // partial[row][slot] = (|sigma_small|^2, |t - sigma_small|^2) over the slot's
 // kDSlot columns, sigma_small = mask_small . Z.
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
@@ -66,10 +68,12 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
 // --- statistic, exceedances, recheck, p ---------------------------------
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int d, int gd,
-                       int alternative, double e_rel, int no_recheck, float* T_out,
+                       int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
+                       bool T_f64,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
 hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
-                          int npairs, const PairState* st, const double* v, const double* coef,
+                          int npairs, const PairState* st, const double* v, const double* t64,
+                          const double* coef,
                           const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
                           int64_t max_flags, int d, int gd, int alternative, PairCount* cnt,
                           hipStream_t s);

@@ -14,9 +14,10 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               const BlockPair* __restrict__ bp, int npairs,
                                               int64_t rows, const PairState* __restrict__ st,
                                               const double* __restrict__ partial, int nslot, int d,
-                                              int gd, int alternative, double e_rel,
-                                              int no_recheck, float* T_out, PairCount* cnt,
-                                              uint32_t* flags, uint32_t* nflag) {
+                                              int gd, int alternative, double e_acc,
+                                              double e_store, int no_recheck, void* T_out,
+                                              bool T_f64,
+                                              PairCount* cnt, uint32_t* flags, uint32_t* nflag) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = row < rows;
     int p = 0;
@@ -38,11 +39,15 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         const double n = (double)pd.n, m = (double)pd.m, dd = (double)d;
         const double r1 = sqrt(ss1) / n, r2 = sqrt(ss2) / m;
         const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);  // log v(X^(b)) - log v(Y^(b))
-        if (T_out) T_out[row] = (float)T;
+        if (T_out) {
+            if (T_f64) ((double*)T_out)[row] = T;
+            else ((float*)T_out)[row] = (float)T;
+        }
         const bool two = alternative == HBT_ALT_TWO_SIDED;
         const double val = two ? fabs(T) : T;
         const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
         const double fs = fabs(log_g(r1, dd, gd)) + fabs(log_g(r2, dd, gd));
+        const double e_rel = e_acc + e_store * rsqrt((n < m ? n : m) * dd);
         const double eps = e_rel * (log_g_sensitivity(r1 * r1, dd, gd) +
                                     log_g_sensitivity(r2 * r2, dd, gd)) + 1e-13 * fs;
         const bool nan = T != T;
@@ -67,31 +72,37 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
 
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int d, int gd,
-                       int alternative, double e_rel, int no_recheck, float* T_out,
-                       PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s) {
+                       int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
+                       bool T_f64, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
+                       hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
-                       npairs, rows, st, partial, nslot, d, gd, alternative, e_rel, no_recheck,
-                       T_out, cnt, flags, nflag);
+                       npairs, rows, st, partial, nslot, d, gd, alternative, e_acc, e_store,
+                       no_recheck,
+                       T_out, T_f64, cnt, flags, nflag);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// FP64 recheck: both group sums by direct summation over the pooled rows,
-// rows rebuilt from the input as x_i - coef_i v (X) or y_j (Y).
-// One work-group per flagged split; persistent over the flag list.
+// FP64 recheck of the flagged splits.  The smaller group's sum is gathered
+// from the input rows, each rebuilt in FP64 as the aligned row
+// x_i - coef_i v (X) or y_j (Y); the other group's sum is t - sigma_small
+// with the FP64 pooled total t.  One work-group per flagged split (persistent
+// over the flag list), 256 threads over the columns.
 // ---------------------------------------------------------------------------
 template <typename Tin>
 __global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pairs,
                                                  const BlockPair* __restrict__ bp, int npairs,
                                                  const PairState* __restrict__ st,
                                                  const double* __restrict__ v,
+                                                 const double* __restrict__ t64,
                                                  const double* __restrict__ coef,
                                                  const uint32_t* __restrict__ mask,
                                                  const uint32_t* __restrict__ flags,
                                                  const uint32_t* __restrict__ nflag, int d,
                                                  int d_pad, int gd, int alternative,
                                                  PairCount* cnt) {
+    constexpr int kCols = 4;  // columns per thread per pass (1024 per pass)
     __shared__ double red1[256], red2[256];
     const uint32_t total = *nflag;
     for (uint32_t f = blockIdx.x; f < total; f += gridDim.x) {
@@ -101,34 +112,50 @@ __global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pa
         const PairState q = st[p];
         const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
         const double* vp = v + (int64_t)p * d_pad;
+        const double* tp = t64 + (int64_t)p * d_pad;
         const double* cf = coef + pd.coef0;
         const int N = pd.n + pd.m;
-        double ss1 = 0.0, ss2 = 0.0;
-        for (int c0 = 0; c0 < d; c0 += 1024) {
-            double a1[4] = {0, 0, 0, 0}, a2[4] = {0, 0, 0, 0};
-            for (int i = 0; i < N; ++i) {
-                const bool g1 = (mk[i >> 5] >> (i & 31)) & 1u;  // mask words are shared by the WG
-                const double k = i < pd.n ? cf[i] : 0.0;
-                const Tin* src = i < pd.n ? (const Tin*)pd.X + (int64_t)i * d
-                                          : (const Tin*)pd.Y + (int64_t)(i - pd.n) * d;
+        const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+        const int W = (N + 31) >> 5;
+        double ss_small = 0.0, ss_large = 0.0;
+        for (int c0 = 0; c0 < d; c0 += 256 * kCols) {
+            double acc[kCols];
+            double vc[kCols];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int c = c0 + u * 256 + threadIdx.x;
-                    if (c < d) {
-                        const double z = (double)src[c] - k * vp[c];
-                        if (g1) a1[u] += z;
-                        else a2[u] += z;
+            for (int u = 0; u < kCols; ++u) {
+                acc[u] = 0.0;
+                const int c = c0 + u * 256 + threadIdx.x;
+                vc[u] = c < d ? vp[c] : 0.0;
+            }
+            for (int w = 0; w < W; ++w) {
+                uint32_t bits = mk[w] ^ flip;  // members of the smaller group
+                if (w == W - 1 && (N & 31)) bits &= (1u << (N & 31)) - 1u;
+                while (bits) {
+                    const int i = 32 * w + __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const bool isx = i < pd.n;
+                    const double k = isx ? cf[i] : 0.0;
+                    const Tin* src = isx ? (const Tin*)pd.X + (int64_t)i * d
+                                         : (const Tin*)pd.Y + (int64_t)(i - pd.n) * d;
+#pragma unroll
+                    for (int u = 0; u < kCols; ++u) {
+                        const int c = c0 + u * 256 + threadIdx.x;
+                        if (c < d) acc[u] += (double)src[c] - k * vc[u];
                     }
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                ss1 += a1[u] * a1[u];
-                ss2 += a2[u] * a2[u];
+            for (int u = 0; u < kCols; ++u) {
+                const int c = c0 + u * 256 + threadIdx.x;
+                if (c < d) {
+                    const double l = tp[c] - acc[u];
+                    ss_small += acc[u] * acc[u];
+                    ss_large += l * l;
+                }
             }
         }
-        red1[threadIdx.x] = ss1;
-        red2[threadIdx.x] = ss2;
+        red1[threadIdx.x] = ss_small;
+        red2[threadIdx.x] = ss_large;
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
             if (threadIdx.x < o) {
@@ -139,7 +166,9 @@ __global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pa
         }
         if (threadIdx.x == 0) {
             const double dd = (double)d;
-            const double r1 = sqrt(red1[0]) / (double)pd.n, r2 = sqrt(red2[0]) / (double)pd.m;
+            const double ss1 = pd.flip ? red2[0] : red1[0];
+            const double ss2 = pd.flip ? red1[0] : red2[0];
+            const double r1 = sqrt(ss1) / (double)pd.n, r2 = sqrt(ss2) / (double)pd.m;
             const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);
             const bool two = alternative == HBT_ALT_TWO_SIDED;
             const double val = two ? fabs(T) : T;
@@ -152,19 +181,19 @@ __global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pa
 }
 
 hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
-                          int npairs, const PairState* st, const double* v, const double* coef,
-                          const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
-                          int64_t max_flags, int d, int gd, int alternative, PairCount* cnt,
-                          hipStream_t s) {
+                          int npairs, const PairState* st, const double* v, const double* t64,
+                          const double* coef, const uint32_t* mask, const uint32_t* flags,
+                          const uint32_t* nflag, int64_t max_flags, int d, int gd, int alternative,
+                          PairCount* cnt, hipStream_t s) {
     if (max_flags <= 0) return hipSuccess;
     const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
-    int64_t g = max_flags < 1024 ? max_flags : 1024;
+    int64_t g = max_flags < 2048 ? max_flags : 2048;
     if (input_dtype == HBT_IN_F64)
         hipLaunchKernelGGL(k_recheck<double>, dim3((unsigned)g), dim3(256), 0, s, pairs, bp, npairs,
-                           st, v, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
+                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
     else
         hipLaunchKernelGGL(k_recheck<float>, dim3((unsigned)g), dim3(256), 0, s, pairs, bp, npairs,
-                           st, v, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
+                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ DTYPE = {"f32": 0, "f64": 1}
 GD = {"banerjee": 0, "identity": 1}
 ALT = {"greater": 0, "two-sided": 1}
 FLAG_NO_RECHECK = 1
+FLAG_T_OUT_F64 = 2
 MAX_N, MAX_D = 65536, 8192
 
 
@@ -81,6 +82,10 @@ def lib():
         L.hbt_perm_test_batched.argtypes = [i64, P, P, P, P, P, P, i64, C.POINTER(HbtPermParams), P, P,
                                             sz, P]
         L.hbt_perm_test_batched.restype = i32
+        L.hbt_stage_timing.argtypes = [i32]
+        L.hbt_stage_timing.restype = i32
+        L.hbt_stage_times.argtypes = [P, P]
+        L.hbt_stage_times.restype = i32
         _lib = L
     return _lib
 
@@ -178,7 +183,8 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
               alternative="greater", align=True, recheck=True, block_perms=0, masks=None,
               want_T=False, want_masks=False, stream=None, sync=True):
     """The whole test for one pair.  Returns a dict of the hbt_result fields,
-    plus ``T`` (B floats) and ``masks`` (B x ceil(N/32) words) when asked."""
+    plus ``T`` (B floats; doubles with want_T="f64") and ``masks``
+    (B x ceil(N/32) words) when asked."""
     torch = _torch()
     n, d = X.shape
     m = Y.shape[0]
@@ -194,13 +200,16 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
                       precision=precision, input_dtype=_input_dtype(X), gd=gd, alternative=alternative,
                       align=align, recheck=recheck, block_perms=block_perms,
                       masks_ptr=None if mk is None else mk.data_ptr())
+    t64 = want_T == "f64"
+    if t64:
+        prm.flags |= FLAG_T_OUT_F64
     L = lib()
     need = L.hbt_perm_test_workspace_size(C.byref(prm))
     if need == 0:
         need = 256
     ws = workspace(need, dev)
     res = torch.zeros(72, dtype=torch.uint8, device=dev)
-    T = torch.empty(B, dtype=torch.float32, device=dev) if want_T else None
+    T = torch.empty(B, dtype=torch.float64 if t64 else torch.float32, device=dev) if want_T else None
     mo = torch.empty((B, W), dtype=torch.int32, device=dev) if want_masks else None
     _check(L.hbt_perm_test(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), C.byref(prm),
                            C.c_void_p(res.data_ptr()), None if T is None else C.c_void_p(T.data_ptr()),

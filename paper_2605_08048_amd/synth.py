@@ -26,6 +26,8 @@ its B = 5,000 ... 20,000 permutation budgets):
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -78,11 +80,11 @@ def cloud_diag(rng, n, d, kappa, mu, lam):
 
 
 def cloud_lowrank(rng, n, d, kappa, mu, factor):
-    """x = normalize(kappa * mu + s (L z1 + noise z2))."""
+    """x = normalize(kappa * mu + s (L z1 + noise z2)); z1, z2 drawn in float32."""
     L, noise, s = factor
-    z1 = rng.standard_normal((n, L.shape[1]))
-    z2 = rng.standard_normal((n, d))
-    w = s * (z1 @ L.T + noise * z2)
+    z1 = rng.standard_normal((n, L.shape[1]), dtype=np.float32)
+    z2 = rng.standard_normal((n, d), dtype=np.float32)
+    w = (z1 @ L.T.astype(np.float32) + np.float32(noise) * z2).astype(np.float64) * s
     return unit_rows(kappa * mu[None, :] + w)
 
 
@@ -198,12 +200,16 @@ def _batch_config(cfg, npairs, d, lo, hi, B, limit=None):
     null = np.arange(npairs) % 2 == 0
     kb = np.where(null, ka, kb)
     factor = lowrank_factor(d)
-    idx = range(npairs) if limit is None else limit
-    pairs = []
-    for p in idx:
+    idx = list(range(npairs) if limit is None else limit)
+
+    def one(p):
         X, Y = _lowrank_pair(cfg, p, int(ns[p]), int(ms[p]), d, float(ka[p]), float(kb[p]),
                              angle=None, factor=factor)
-        pairs.append(Pair(X, Y, B=B, seed=0, pair_index=p, meta=dict(null=bool(null[p]))))
+        return Pair(X, Y, B=B, seed=0, pair_index=p, meta=dict(null=bool(null[p])))
+
+    # every pair has its own seeded generator, so the thread pool changes nothing
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        pairs = list(ex.map(one, idx))
     return pairs, dict(kappa_a=ka, kappa_b=kb, null=null, n=ns, m=ms)
 
 
