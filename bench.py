@@ -177,6 +177,7 @@ def main():
                      "executed_mfma_tflops": 2 * achieved},
         "stages_ms_per_step": {k: ms[i] / args.steps for i, k in enumerate(STAGES)},
         "pairs_bad_status": bad,
+        "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
     }
     if not args.no_cpu_baseline:

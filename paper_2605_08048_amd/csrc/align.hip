@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
                                                  const PairState* __restrict__ st,
                                                  const double* __restrict__ v, int d, int d_pad,
                                                  double* __restrict__ coef, void* zstore,
-                                                 int64_t zplane_elems) {
+                                                 int64_t zplane_elems, float* __restrict__ z32) {
     __shared__ double cf[8];
     const int64_t oct = blockIdx.x;
     const int p = upper_index(npairs, oct * 8, [&](int k) { return pairs[k].zrow0; });
@@ -259,6 +259,11 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
             }
             z[r] = val;
         }
+        if (z32) {  // row-major FP32 copy for the point-to-centroid route
+            float* q = z32 + oct * 8 * d_pad + c;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) q[(int64_t)r * d_pad] = (float)z[r];
+        }
         if (PREC == HBT_BF16X2) {
             uint32_t hi[4], lo[4];
 #pragma unroll
@@ -288,21 +293,21 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
 template <typename Tin>
 static hipError_t launch_reflect_t(int precision, const PairDesc* pairs, int npairs,
                                    int64_t total_octets, const PairState* st, const double* v,
-                                   int d, int d_pad, double* coef, void* z, int64_t ze,
+                                   int d, int d_pad, double* coef, void* z, int64_t ze, float* z32,
                                    hipStream_t s) {
     dim3 g((unsigned)total_octets), b(256);
     switch (precision) {
         case HBT_F64:
             hipLaunchKernelGGL((k_reflect<Tin, HBT_F64>), g, b, 0, s, pairs, npairs, st, v, d, d_pad,
-                               coef, z, ze);
+                               coef, z, ze, z32);
             break;
         case HBT_F32:
             hipLaunchKernelGGL((k_reflect<Tin, HBT_F32>), g, b, 0, s, pairs, npairs, st, v, d, d_pad,
-                               coef, z, ze);
+                               coef, z, ze, z32);
             break;
         default:
             hipLaunchKernelGGL((k_reflect<Tin, HBT_BF16X2>), g, b, 0, s, pairs, npairs, st, v, d,
-                               d_pad, coef, z, ze);
+                               d_pad, coef, z, ze, z32);
             break;
     }
     return hipGetLastError();
@@ -311,13 +316,13 @@ static hipError_t launch_reflect_t(int precision, const PairDesc* pairs, int npa
 hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs, int npairs,
                           int64_t total_octets, const PairState* st, const double* v, int d,
                           int d_pad, double* coef, void* zstore, int64_t zplane_elems,
-                          hipStream_t s) {
+                          float* z32, hipStream_t s) {
     if (total_octets <= 0) return hipSuccess;
     if (input_dtype == HBT_IN_F64)
         return launch_reflect_t<double>(precision, pairs, npairs, total_octets, st, v, d, d_pad,
-                                        coef, zstore, zplane_elems, s);
+                                        coef, zstore, zplane_elems, z32, s);
     return launch_reflect_t<float>(precision, pairs, npairs, total_octets, st, v, d, d_pad, coef,
-                                   zstore, zplane_elems, s);
+                                   zstore, zplane_elems, z32, s);
 }
 
 // ---------------------------------------------------------------------------

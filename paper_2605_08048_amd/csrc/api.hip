@@ -117,6 +117,7 @@ struct Workspace {
     BlockPair* bp;
     SumChunk* chunks;
     GemmTile* tiles;
+    GemmGroup* groups;
     int64_t* Btot;
     double* partial_sum;
     double* sxy;
@@ -131,6 +132,12 @@ struct Workspace {
     double* partial;
     uint32_t* flags;
     uint32_t* nflag;
+    // point-to-centroid route
+    float* sig;         // group sums of the smaller group, block rows x d_pad
+    float* z32;         // row-major FP32 Z when the main storage is not FP32
+    double* zt;         // z_i . t per pooled row
+    double* partial2;   // block rows x row tiles x 2
+    GemmTile* ctiles;   // its tile list (256 splits per tile)
     size_t bytes;
 };
 
@@ -144,11 +151,16 @@ struct Plan {
     std::vector<BlockPair> bp;
     std::vector<SumChunk> chunks;
     std::vector<GemmTile> tiles;
+    std::vector<GemmGroup> groups;
+    int64_t ntile_total = 0;      // tiles of the split-BF16 kernel over all groups
     std::vector<int64_t> Btot;
     int64_t zrows = 0, ncoef = 0;
     int64_t block_rows = 0;       // split rows of the largest block
     int64_t block_mask_words = 0; // mask words of the largest block
     bool need_store = true;       // group-sum path (false for hbt_align)
+    bool route2 = false;          // point-to-centroid statistic route
+    int ntile_i = 0;              // its row tiles (of 64) per split
+    std::vector<GemmTile> ctiles;
 };
 
 Workspace carve(const Plan& P, void* ws) {
@@ -159,6 +171,7 @@ Workspace carve(const Plan& P, void* ws) {
     w.bp = c.take<BlockPair>(np);
     w.chunks = c.take<SumChunk>(std::max<size_t>(P.chunks.size(), 1));
     w.tiles = c.take<GemmTile>(std::max<size_t>(P.tiles.size(), 1));
+    w.groups = c.take<GemmGroup>(std::max<size_t>(P.groups.size(), 1));
     w.Btot = c.take<int64_t>(np);
     w.partial_sum = c.take<double>(std::max<size_t>(P.chunks.size(), 1) * P.d);
     w.sxy = c.take<double>((size_t)np * 2 * P.d_pad);
@@ -175,7 +188,25 @@ Workspace carve(const Plan& P, void* ws) {
         w.partial = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.nslot * 2);
         w.flags = c.take<uint32_t>(std::max<int64_t>(P.block_rows, 1));
         w.nflag = c.take<uint32_t>(2);
+        if (P.route2) {
+            w.sig = c.take<float>((size_t)std::max<int64_t>(P.block_rows, 1) * P.d_pad);
+            w.z32 = P.precision == HBT_F32 ? nullptr : c.take<float>((size_t)P.zrows * P.d_pad);
+            w.zt = c.take<double>(std::max<int64_t>(P.zrows, 1));
+            w.partial2 = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.ntile_i * 2);
+            w.ctiles = c.take<GemmTile>(std::max<size_t>(P.ctiles.size(), 1));
+        } else {
+            w.sig = nullptr;
+            w.z32 = nullptr;
+            w.zt = nullptr;
+            w.partial2 = nullptr;
+            w.ctiles = nullptr;
+        }
     } else {
+        w.sig = nullptr;
+        w.z32 = nullptr;
+        w.zt = nullptr;
+        w.partial2 = nullptr;
+        w.ctiles = nullptr;
         w.coef = nullptr;
         w.zstore = nullptr;
         w.mask = nullptr;
@@ -225,8 +256,8 @@ hbt_status check_enums(const hbt_perm_params* prm) {
     if (prm->alternative != HBT_ALT_GREATER && prm->alternative != HBT_ALT_TWO_SIDED)
         return fail(HBT_ERR_ARG, "unknown alternative %d", prm->alternative);
     if (prm->align != 0 && prm->align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
-    if (prm->stat_route != 0)
-        return fail(HBT_ERR_UNSUPPORTED, "stat_route %d is not available", prm->stat_route);
+    if (prm->stat_route != 0 && prm->stat_route != 1)
+        return fail(HBT_ERR_ARG, "unknown stat_route %d", prm->stat_route);
     if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64))
         return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
     return HBT_OK;
@@ -261,6 +292,13 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0});
     const int tb = groupsum_tile_splits(prm->precision);
     for (int64_t b = 0; b < B0; b += tb) P.tiles.push_back(GemmTile{0, (int32_t)b});
+    P.groups.push_back(GemmGroup{0, (int32_t)((B0 + tb - 1) / tb), 0});
+    P.ntile_total = (int64_t)P.groups[0].nbt * P.nslot;
+    if (prm->stat_route == 1) {
+        P.route2 = true;
+        P.ntile_i = P.pairs[0].Np / 64;
+        for (int64_t b = 0; b < B0; b += kTileB) P.ctiles.push_back(GemmTile{0, (int32_t)b});
+    }
     P.Btot.push_back(prm->B);
     P.block_rows = B0;
     P.block_mask_words = B0 * P.pairs[0].Wp;
@@ -425,17 +463,28 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
         HIP_TRY(upload(w.Btot, P.Btot.data(), sizeof(int64_t), s));
     }
-    { StageTimer t_(HBT_STAGE_ALIGN, s); HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, 1, P.zrows / 8, w.st, w.v, P.d,
-                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s)); }
+    const float* z32 = P.precision == HBT_F32 ? (const float*)w.zstore : w.z32;
+    {
+        StageTimer t_(HBT_STAGE_ALIGN, s);
+        HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, 1, P.zrows / 8, w.st, w.v, P.d,
+                               P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, w.z32, s));
+        if (P.route2) {
+            HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(GemmTile), s));
+            HIP_TRY(launch_row_dot_t(w.pairs, 1, z32, w.t64, P.d_pad, P.zrows, w.zt, s));
+        }
+    }
     const Band band = precision_band(P.precision);
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
     const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
     for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
         const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
         BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
+        const int tb = groupsum_tile_splits(P.precision);
+        const GemmGroup grp{0, (int32_t)((nb + tb - 1) / tb), 0};
         {
             StageTimer t_(HBT_STAGE_OTHER, s);
             HIP_TRY(upload(w.bp, &bq, sizeof bq, s));
+            HIP_TRY(upload(w.groups, &grp, sizeof grp, s));
             HIP_TRY(zero(w.nflag, 8, s));
         }
         {
@@ -445,11 +494,19 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             else
                 HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.st, s));
         }
-        const int tb = groupsum_tile_splits(P.precision);
-        const int ntiles = (int)((nb + tb - 1) / tb);
-        { StageTimer t_(HBT_STAGE_GROUPSUM, s); HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, P.d_pad, w.zstore,
-                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s)); }
-        { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st, w.partial, P.nslot, P.d, prm->gd,
+        const int ntiles = grp.nbt;
+        {
+            StageTimer t_(HBT_STAGE_GROUPSUM, s);
+            HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, 1,
+                                    grp.nbt * P.nslot, P.d_pad, w.zstore, P.zrows * P.d_pad,
+                                    w.mask, w.t32, w.t64, w.partial, w.sig, s));
+            if (P.route2)
+                HIP_TRY(launch_centroid(w.pairs, w.bp, w.ctiles, (int)((nb + kTileB - 1) / kTileB),
+                                        P.ntile_i, P.d_pad, z32, w.sig, w.mask, w.zt, w.partial2,
+                                        s));
+        }
+        { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
+                            P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot, P.d, prm->gd,
                             prm->alternative, band.e_acc, band.e_store, no_recheck,
                             T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8,
                             w.cnt, w.flags, w.nflag, s)); }
@@ -487,8 +544,12 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
     const int tb = groupsum_tile_splits(common->precision);
-    for (int p : order)
+    for (int p : order) {
         for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
+        const int nbt = (int)((B[p] + tb - 1) / tb);
+        P.groups.push_back(GemmGroup{p, nbt, P.ntile_total});
+        P.ntile_total += (int64_t)nbt * P.nslot;
+    }
     P.block_rows = rows;
     P.block_mask_words = words;
     return true;
@@ -518,6 +579,8 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     if (npairs < 1 || npairs > (1 << 24)) return fail(HBT_ERR_SIZE, "npairs = %lld", (long long)npairs);
     hbt_status st = check_enums(common);
     if (st) return st;
+    if (common->stat_route != 0)
+        return fail(HBT_ERR_UNSUPPORTED, "the batched call computes the statistic by route 0 only");
     int64_t total_rows = 0;
     for (int64_t p = 0; p < npairs; ++p) {
         if ((st = check_sizes(n[p], m[p], d, B[p], common->perm_offset)))
@@ -541,16 +604,26 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     {
         StageTimer t_(HBT_STAGE_OTHER, s);
         HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
-        HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
+        if (P.precision == HBT_BF16X2)
+            HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
+        else
+            HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
         HIP_TRY(zero(w.nflag, 8, s));
     }
-    { StageTimer t_(HBT_STAGE_ALIGN, s); HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, np, P.zrows / 8, w.st, w.v, P.d,
-                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, s)); }
+    {
+        StageTimer t_(HBT_STAGE_ALIGN, s);
+        HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, np, P.zrows / 8, w.st, w.v, P.d,
+                               P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, nullptr, s));
+    }
     { StageTimer t_(HBT_STAGE_SPLIT, s); HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask,
                                w.st, s)); }
-    { StageTimer t_(HBT_STAGE_GROUPSUM, s); HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), P.d_pad,
-                            w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, s)); }
+    {
+        StageTimer t_(HBT_STAGE_GROUPSUM, s);
+        HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
+                                (int)P.groups.size(), (int)P.ntile_total, P.d_pad, w.zstore,
+                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, nullptr, s));
+    }
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
     { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
                         common->alternative, precision_band(P.precision).e_acc,

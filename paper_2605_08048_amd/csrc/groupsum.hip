@@ -45,75 +45,118 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast
 // B (16 x 32) lane l -> k 8(l/32)..+7, col l%32; D lane l -> col l%32,
 // rows 8(v/4) + 4(l/32) + v%4.
 //
-// Work-group tile: kDSlot (64) columns x kTileBF16 (512) splits; 4 waves,
-// wave w owns splits [128 w, 128 w + 128) as 4 blocks of 32 and all 64
-// columns as 2 blocks of 32 (accumulators: 2 x 4 x 16 floats per lane).
-// The pooled rows are consumed in chunks of 64 (8 octets): the chunk's
-// 64-column slice of both planes (16 KB) is staged in LDS once and read by
-// all four waves; the next chunk is loaded into registers while the current
-// one is multiplied (two LDS buffers).
+// Work-group tile: 64 columns x kTileBF16 (512) splits; 4 waves, wave w owns
+// splits [128 w, 128 w + 128) as 4 blocks of 32 and the 64 columns as 2
+// blocks of 32 (accumulators 2 x 4 x 16 floats per lane, in AGPRs).
+//  * Z streams through LDS in chunks of 128 pooled rows (16 octets; both
+//    planes of the 64-column slice = 32 KB) with direct global -> LDS loads,
+//    one chunk ahead, into two separate LDS objects.
+//  * Mask bytes become bf16 0/1 operands through a 16-entry nibble table in
+//    LDS (entry k = the four bf16 of nibble k): two conflict-free 8-byte
+//    reads per byte instead of bit arithmetic on the VALU.
+//  * Operands of K-step s+1 are read while the MFMAs of K-step s run.
+//  * Tiles are numbered so that the b-tiles of one (pair, column slice) go to
+//    one XCD (work-groups are dealt to the 8 XCDs round-robin), and the pair
+//    order is longest-first.
 // ---------------------------------------------------------------------------
 constexpr int kTileBF16 = 512;
-constexpr int kChunk = 64;                        // pooled rows per chunk
-constexpr int kChunkVec = 2 * (kChunk / 8) * kDSlot;  // uint4 per chunk (both planes)
+constexpr int kChunk = 128;                      // pooled rows per chunk
+constexpr int kOct = kChunk / 8;                 // octets per chunk
+constexpr int kChunkVec = 2 * kOct * kDSlot;     // uint4 per chunk (both planes)
+constexpr int kXcd = 8;                          // XCDs of an MI355X
+
+// Work-group g -> logical tile: within each block of 32 consecutive
+// work-groups, XCD x (= g mod 8) receives the 4 consecutive logical tiles
+// 4x .. 4x+3.  A permutation of [0, round_up(T, 32)).
+__device__ __forceinline__ int xcd_remap(int g) {
+    return 32 * (g / 32) + 4 * (g % kXcd) + (g / kXcd) % 4;
+}
+
+constexpr int kMaskVec = 4 * 128;                // uint4 per chunk: 4 waves x 128 split rows
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
-    const GemmTile* __restrict__ tiles, int nslot, int d_pad, const uint4* __restrict__ zhi,
-    const uint4* __restrict__ zlo, const uint32_t* __restrict__ mask,
-    const float* __restrict__ t32, double* __restrict__ partial) {
-    // two separate LDS objects ([plane][octet][column] each), so the compiler
-    // can see that a direct load into one never feeds a read of the other
+    const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
+    const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
+    const uint32_t* __restrict__ mask, const float* __restrict__ t32,
+    double* __restrict__ partial, float* __restrict__ sig) {
+    // separate LDS objects per buffer ([plane][octet][column] of Z; [wave][split]
+    // of mask words), so the compiler can see that a direct load into one
+    // buffer never feeds a read of the other
     __shared__ uint4 lds0[kChunkVec];
     __shared__ uint4 lds1[kChunkVec];
-    const GemmTile tile = tiles[blockIdx.x / nslot];
-    const int slot = blockIdx.x % nslot;
-    const PairDesc pd = pairs[tile.pair];
-    const BlockPair bq = bp[tile.pair];
+    __shared__ uint4 msk0[kMaskVec];
+    __shared__ uint4 msk1[kMaskVec];
+    __shared__ uint2 lut[16];
+    const int L = xcd_remap(blockIdx.x);
+    if (L >= ntile_total) return;
+    const int gi = upper_index(ngroups, L, [&](int k) { return groups[k].tile0; });
+    const GemmGroup grp = groups[gi];
+    const int local = L - (int)grp.tile0;
+    const int slot = local / grp.nbt;                       // 64-column slice
+    const int b0 = (local % grp.nbt) * kTileBF16;
+    const PairDesc pd = pairs[grp.pair];
+    const BlockPair bq = bp[grp.pair];
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    // wave index as a wave-uniform (scalar) value: the loader's row offsets
+    // then live in SGPRs and only the lane offset is per lane
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
     const int h = lane >> 5, c = lane & 31;
     const int d0 = slot * kDSlot;
     const int nchunk = pd.Np / kChunk;
 
-    // mask rows of this lane's four split blocks; rows past the pair's splits
-    // read its first row and are zeroed by keep[] (no branch around the load)
+    if (tid < 16) {
+        uint32_t w[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t two = (tid >> (2 * q)) & 3u;
+            w[q] = (two & 1u ? 0x3F80u : 0u) | (two & 2u ? 0x3F800000u : 0u);
+        }
+        lut[tid] = make_uint2(w[0], w[1]);
+    }
+
+    // splits of this lane's four blocks (rows past the pair's splits are
+    // loaded from its first row and zeroed by keep[] at use)
     int brow[4];
     uint32_t keep[4];
-    const uint2* mrow[4];
     const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        brow[j] = tile.b0 + wave * 128 + j * 32 + c;
-        const bool valid = brow[j] < bq.nb;
-        keep[j] = valid ? 0xffffffffu : 0u;
-        mrow[j] = (const uint2*)mask_row(mask, bq, bq.mrow0 + (valid ? brow[j] : 0), pd.Wp);
+        brow[j] = b0 + wave * 128 + j * 32 + c;
+        keep[j] = brow[j] < bq.nb ? 0xffffffffu : 0u;
+    }
+    // mask rows this lane moves into LDS: splits 128 w + l and 128 w + 64 + l
+    const uint4* mload[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int r = b0 + wave * 128 + 64 * k + lane;
+        mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
     }
 
-    // chunk loader: the chunk tile is 16 rows (plane x octet) of kDSlot uint4;
-    // wave w fills rows 4w .. 4w+3 with direct global -> LDS loads (lane l
-    // moves column l of a row, 1 KB per wave per load)
+    // chunk loader: 32 LDS rows of kDSlot uint4 (plane, octet); wave w fills
+    // rows 8w .. 8w+7, lane l moving column l (1 KB per wave per load); and
+    // the wave's 128 mask rows (2 loads)
     const int64_t oct0 = pd.zrow0 >> 3;
-    const uint4* gsrc[4];
+    const int64_t chunk_stride = (int64_t)kOct * d_pad;
+    // rows 8w .. 8w+7 of the chunk tile all lie in one plane (kOct = 16)
+    const uint4* zsrc = ((8 * wave) / kOct ? zlo : zhi) + (oct0 + (8 * wave) % kOct) * d_pad + d0;
+    auto issue = [&](int ch, uint4* dst, uint4* mdst) {
+        const uint4* base = zsrc + ch * chunk_stride;  // wave-uniform
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int r = 4 * wave + k;
-        const int plane = r / (kChunk / 8), oct = r % (kChunk / 8);
-        gsrc[k] = (plane ? zlo : zhi) + (oct0 + oct) * d_pad + d0 + lane;
-    }
-    const int64_t chunk_stride = (int64_t)(kChunk / 8) * d_pad;
-    auto issue = [&](int ch, uint4* dst) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 8; ++k) {
             __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void*)(gsrc[k] + ch * chunk_stride),
-                (__attribute__((address_space(3))) void*)(dst + (4 * wave + k) * kDSlot), 16, 0, 0);
+                (const __attribute__((address_space(1))) void*)(base + k * d_pad + lane),
+                (__attribute__((address_space(3))) void*)(dst + (8 * wave + k) * kDSlot), 16, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void*)(mload[k] + ch),
+                (__attribute__((address_space(3))) void*)(mdst + wave * 128 + 64 * k), 16, 0, 0);
     };
 
-    uint2 mw_next[4];
-    issue(0, lds0);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) mw_next[j] = mrow[j][0];
+    issue(0, lds0, msk0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -125,55 +168,69 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    // one chunk: stream chunk ch+1 into `nxt` while multiplying `cur`
-    auto step = [&](int ch, const uint4* cur, uint4* nxt) {
-        uint2 mw[4];
+    // one chunk: stream chunk ch+1 into (nxt, mnxt) while multiplying (cur, mcur)
+    auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
+        if (ch + 1 < nchunk) issue(ch + 1, nxt, mnxt);
+        // this chunk's mask words of the lane's 4 splits (16-byte rows: a
+        // conflict-free 128-bit read per split), group flip and validity applied once
+        uint4 mw[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            mw[j].x = (mw_next[j].x ^ flip) & keep[j];
-            mw[j].y = (mw_next[j].y ^ flip) & keep[j];
+            const uint4 x = mcur[wave * 128 + 32 * j + c];
+            mw[j] = make_uint4((x.x ^ flip) & keep[j], (x.y ^ flip) & keep[j],
+                               (x.z ^ flip) & keep[j], (x.w ^ flip) & keep[j]);
         }
-        if (ch + 1 < nchunk) {
-            issue(ch + 1, nxt);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) mw_next[j] = mrow[j][ch + 1];
-        }
-#pragma unroll
-        for (int s = 0; s < kChunk / 16; ++s) {  // K-steps of 16 pooled rows
-            const int o = 2 * s + h;             // octet of this lane's 8 rows
-            bf16x8 a_hi[2], a_lo[2], bm[4];
+        // operands of K-step s: Z fragments (2 planes x 2 column blocks) and
+        // the mask fragments of the 4 split blocks
+        auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[4]) {
+            const int o = 2 * s + h;
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a_hi[i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
-                a_lo[i] = as_bf16x8(cur[(kChunk / 8 + o) * kDSlot + 32 * i + c]);
+                a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
+                a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const uint32_t word = s < 2 ? mw[j].x : mw[j].y;
-                bm[j] = expand_bits_bf16((word >> (8 * (2 * (s & 1) + h))) & 0xffu);
+                const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
+                const uint32_t byte = (word >> (8 * (2 * (s & 1) + h))) & 0xffu;
+                const uint2 lo = lut[byte & 15u], hi = lut[byte >> 4];
+                bm[j] = as_bf16x8(make_uint4(lo.x, lo.y, hi.x, hi.y));
             }
+        };
+        bf16x8 a[2][2][2], bm[2][4];  // [buffer]...
+        fetch(0, a[0], bm[0]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+        for (int s = 0; s < kChunk / 16; ++s) {  // K-steps of 16 pooled rows
+            if (s + 1 < kChunk / 16) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi[i], bm[j], acc[i][j], 0, 0, 0);
+            for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo[i], bm[j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            a[s & 1][pl][i], bm[s & 1][j], acc[i][j], 0, 0, 0);
+            if (s + 1 < kChunk / 16) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);  // next K-step's LDS reads
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // 1 VALU
+                }
+            }
         }
-        // the next chunk's LDS writes and mask loads have landed; every wave is
-        // done reading `cur` before it is refilled
+        // the next chunk's LDS writes have landed; every wave is done reading
+        // (cur, mcur) before they are refilled
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     };
     for (int ch = 0; ch < nchunk; ch += 2) {
-        step(ch, lds0, lds1);
-        if (ch + 1 < nchunk) step(ch + 1, lds1, lds0);
+        step(ch, lds0, msk0, lds1, msk1);
+        if (ch + 1 < nchunk) step(ch + 1, lds1, msk1, lds0, msk0);
     }
-    // epilogue: squared norms of sigma_small and t - sigma_small over the 64 columns
-    const float* tp = t32 + (int64_t)tile.pair * d_pad + d0;
+
+    // epilogue: squared norms of sigma_small and t - sigma_small over the slice
+    const float* tp = t32 + (int64_t)grp.pair * d_pad + d0;
     float tv[2][16];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -196,6 +253,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if (h == 0 && keep[j]) {
             double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + slot;
             *out = make_double2((double)ss, (double)sl);
+        }
+        if (sig && keep[j]) {  // the group sums themselves, for the point-to-centroid route
+            float* sr = sig + (bq.mrow0 + brow[j]) * (int64_t)d_pad + d0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) sr[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)] = acc[i][j][v];
         }
     }
 }
@@ -232,7 +296,8 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
                                                      int nslot, int d_pad, const T* __restrict__ z,
                                                      const uint32_t* __restrict__ mask,
                                                      const T* __restrict__ tvec,
-                                                     double* __restrict__ partial) {
+                                                     double* __restrict__ partial,
+                                                     float* __restrict__ sig) {
     typedef typename MfmaFp<T>::acc_t acc_t;
     const GemmTile tile = tiles[blockIdx.x / nslot];
     const int slot = blockIdx.x % nslot;
@@ -299,31 +364,45 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
             double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + slot;
             *out = make_double2((double)ss, (double)sl);
         }
+        if (sig && valid[j]) {  // the group sums themselves, for the point-to-centroid route
+            float* sr = sig + (bq.mrow0 + brow[j]) * (int64_t)d_pad + d0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sr[16 * i + MfmaFp<T>::row(q, v)] = (float)acc[i][j][v];
+        }
     }
 }
 
 int groupsum_tile_splits(int precision) { return precision == HBT_BF16X2 ? kTileBF16 : kTileB; }
 
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
-                           const GemmTile* tiles, int ntiles, int d_pad, const void* zstore,
-                           int64_t zplane_elems, const uint32_t* mask, const float* t32,
-                           const double* t64, double* partial, hipStream_t s) {
-    if (ntiles <= 0) return hipSuccess;
+                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngroups,
+                           int ntile_total, int d_pad, const void* zstore, int64_t zplane_elems,
+                           const uint32_t* mask, const float* t32, const double* t64,
+                           double* partial, float* sig, hipStream_t s) {
     const int nslot = d_pad / kDSlot;
-    dim3 grid((unsigned)(ntiles * nslot)), block(256);
+    dim3 block(256);
     switch (precision) {
-        case HBT_BF16X2:
-            hipLaunchKernelGGL(k_groupsum_bf16x2, grid, block, 0, s, pairs, bp, tiles, nslot, d_pad,
-                               (const uint4*)zstore, (const uint4*)zstore + zplane_elems / 8, mask,
-                               t32, partial);
+        case HBT_BF16X2: {
+            if (ntile_total <= 0) return hipSuccess;
+            const int grid = (ntile_total + 31) / 32 * 32;
+            hipLaunchKernelGGL(k_groupsum_bf16x2, dim3((unsigned)grid), block, 0, s, pairs, bp,
+                               groups, ngroups, ntile_total, nslot, d_pad, (const uint4*)zstore,
+                               (const uint4*)zstore + zplane_elems / 8, mask, t32, partial, sig);
             break;
+        }
         case HBT_F32:
-            hipLaunchKernelGGL(k_groupsum_fp<float>, grid, block, 0, s, pairs, bp, tiles, nslot,
-                               d_pad, (const float*)zstore, mask, t32, partial);
+            if (ntiles <= 0) return hipSuccess;
+            hipLaunchKernelGGL(k_groupsum_fp<float>, dim3((unsigned)(ntiles * nslot)), block, 0, s,
+                               pairs, bp, tiles, nslot, d_pad, (const float*)zstore, mask, t32,
+                               partial, sig);
             break;
         default:
-            hipLaunchKernelGGL(k_groupsum_fp<double>, grid, block, 0, s, pairs, bp, tiles, nslot,
-                               d_pad, (const double*)zstore, mask, t64, partial);
+            if (ntiles <= 0) return hipSuccess;
+            hipLaunchKernelGGL(k_groupsum_fp<double>, dim3((unsigned)(ntiles * nslot)), block, 0, s,
+                               pairs, bp, tiles, nslot, d_pad, (const double*)zstore, mask, t64,
+                               partial, sig);
             break;
     }
     return hipGetLastError();

@@ -12,7 +12,7 @@ namespace hbt {
 
 // Pooled rows of a pair are padded to a multiple of kRowPad in the Z
 // storage (zero rows), columns to a multiple of kDPad (zero columns).
-constexpr int kRowPad = 64;
+constexpr int kRowPad = 128;
 constexpr int kDPad = 64;
 // Each group-sum tile reduces its squared norms over kDSlot columns; the
 // statistic kernel adds the d_pad / kDSlot slots of a split row in FP64.
@@ -65,10 +65,19 @@ struct SumChunk {
     int32_t r0, r1;
 };
 
-// A group-sum tile: kTileB split rows of one pair (all column slots).
+// A group-sum tile of the FP32 / FP64 kernels: kTileB split rows of one pair
+// (the grid covers all column slots).
 struct GemmTile {
     int32_t pair;
     int32_t b0;          // first split of the tile, relative to the pair's block rows
+};
+
+// The split-BF16 kernel's tiles of one pair: nbt split tiles x (d_pad / 64)
+// column slices, numbered from tile0 (slice-major, split tile fastest).
+struct GemmGroup {
+    int32_t pair;
+    int32_t nbt;
+    int64_t tile0;
 };
 
 // FP64 per-pair state written by the finalize kernel.

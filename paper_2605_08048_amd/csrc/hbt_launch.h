@@ -33,7 +33,7 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs, int npairs,
                           int64_t total_octets, const PairState* st, const double* v, int d,
                           int d_pad, double* coef, void* zstore, int64_t zplane_elems,
-                          hipStream_t s);
+                          float* z32, hipStream_t s);
 // hbt_align's output: X' in the input dtype (may alias X).
 hipError_t launch_reflect_out(int input_dtype, const PairDesc* pair, const PairState* st,
                               const double* v, int n, int d, void* X_out, double* v_out,
@@ -60,10 +60,24 @@ hipError_t launch_export_masks(const uint32_t* mask, int64_t rows, int Wp, int W
 int groupsum_tile_splits(int precision);
 // partial[row][slot] = (|sigma_small|^2, |t - sigma_small|^2) over the slot's
 // kDSlot columns, sigma_small = mask_small . Z.
+// FP32 / FP64 use the tile list; split BF16 uses the per-pair groups
+// (ntile_total tiles in all).
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
-                           const GemmTile* tiles, int ntiles, int d_pad, const void* zstore,
-                           int64_t zplane_elems, const uint32_t* mask, const float* t32,
-                           const double* t64, double* partial, hipStream_t s);
+                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngroups,
+                           int ntile_total, int d_pad, const void* zstore, int64_t zplane_elems,
+                           const uint32_t* mask, const float* t32, const double* t64,
+                           double* partial, float* sig, hipStream_t s);
+
+// --- point-to-centroid route (statistic route 2) -------------------------
+// z_i . t per pooled row; then Q = Z S^T with the masked column sums
+// partial[row][row tile] = (|sigma_small|^2 part, |t - sigma_small|^2 part).
+hipError_t launch_row_dot_t(const PairDesc* pairs, int npairs, const float* z32,
+                            const double* t64, int d_pad, int64_t total_rows, double* zt,
+                            hipStream_t s);
+hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const GemmTile* tiles,
+                           int ntiles, int ntile_i, int d_pad, const float* z32, const float* sig,
+                           const uint32_t* mask, const double* zt, double* partial,
+                           hipStream_t s);
 
 // --- statistic, exceedances, recheck, p ---------------------------------
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,

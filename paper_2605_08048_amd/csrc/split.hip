@@ -96,45 +96,75 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
     theta = __shfl(theta, src, 64);
     below = __shfl(below, src, 64);
     const uint32_t need = (uint32_t)n - below;
-    // 3. one pass over the keys: bits of P < theta, and the bucket P == theta
+    // 3. one pass over the keys: bits of P < theta, and the bucket P == theta.
+    //    Four independent byte reads per lane per iteration (items i0 + l + 64 t)
+    //    keep several LDS reads in flight; each ballot is one 64-item mask slice.
     uint32_t cnt = 0;
-    for (int i0 = 0; i0 < pd.Np; i0 += 64) {
-        const int i = i0 + lane;
-        const uint32_t P = keys[i];
-        const bool in = i < N;
-        const uint64_t lt = __ballot(in && P < theta);
-        const uint64_t eq = __ballot(in && P == theta);
-        if (lane == 0) {
-            mlds[i0 >> 5] = (uint32_t)lt;
-            mlds[(i0 >> 5) + 1] = (uint32_t)(lt >> 32);
+    for (int i0 = 0; i0 < pd.Np; i0 += 256) {
+        uint32_t P[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = i0 + 64 * t + lane;
+            P[t] = i < pd.Np ? (uint32_t)keys[i] : 0u;
         }
-        if (in && P == theta) {
-            const uint32_t pos = cnt + mbcnt64(eq);
-            if (pos < (uint32_t)kCandCap) cidx[pos] = (uint32_t)i;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ib = i0 + 64 * t;
+            if (ib >= pd.Np) break;
+            const int i = ib + lane;
+            const bool in = i < N;
+            const uint64_t lt = __ballot(in && P[t] < theta);
+            const uint64_t eq = __ballot(in && P[t] == theta);
+            if (lane == 0) {
+                mlds[ib >> 5] = (uint32_t)lt;
+                mlds[(ib >> 5) + 1] = (uint32_t)(lt >> 32);
+            }
+            if (in && P[t] == theta) {
+                const uint32_t pos = cnt + mbcnt64(eq);
+                if (pos < (uint32_t)kCandCap) cidx[pos] = (uint32_t)i;
+            }
+            cnt += (uint32_t)__popcll((unsigned long long)eq);
         }
-        cnt += (uint32_t)__popcll((unsigned long long)eq);
     }
     if (cnt > (uint32_t)kCandCap) {
         if (lane == 0) atomicExch(&st[p].status, (int)HBT_ERR_INTERNAL);
         cnt = kCandCap;
     }
     wave_sync();
-    // 4. secondary keys of the bucket items
-    for (uint32_t k = lane; k < cnt; k += 64) {
-        const uint32_t i = cidx[k];
-        const uint4 w = philox4x32_10(make_uint4(i >> 2, b, pd.pair_index, 1u), key0, key1);
-        ckey[k] = word_of(w, i & 3);
-    }
-    wave_sync();
-    // 5. the `need` bucket items first in (S, i) order join group 1
-    for (uint32_t k = lane; k < cnt; k += 64) {
-        const uint32_t sk = ckey[k], ik = cidx[k];
+    // 4. secondary keys of the bucket items; 5. the `need` bucket items first in
+    //    (S, i) order join group 1.  With at most 64 bucket items (the usual
+    //    case: about N / 256) each lane holds one and ranks it against the
+    //    others through lane broadcasts; larger buckets rank through LDS.
+    if (cnt <= 64) {
+        uint32_t sk = 0xffffffffu, ik = 0xffffffffu;
+        if ((uint32_t)lane < cnt) {
+            ik = cidx[lane];
+            const uint4 w = philox4x32_10(make_uint4(ik >> 2, b, pd.pair_index, 1u), key0, key1);
+            sk = word_of(w, ik & 3);
+        }
         uint32_t rank = 0;
         for (uint32_t q = 0; q < cnt; ++q) {
-            const uint32_t s2 = ckey[q], i2 = cidx[q];
+            const uint32_t s2 = __builtin_amdgcn_readlane(sk, q);
+            const uint32_t i2 = __builtin_amdgcn_readlane(ik, q);
             rank += (s2 < sk) || (s2 == sk && i2 < ik);
         }
-        if (rank < need) atomicOr(&mlds[ik >> 5], 1u << (ik & 31));
+        if ((uint32_t)lane < cnt && rank < need) atomicOr(&mlds[ik >> 5], 1u << (ik & 31));
+    } else {
+        for (uint32_t k = lane; k < cnt; k += 64) {
+            const uint32_t i = cidx[k];
+            const uint4 w = philox4x32_10(make_uint4(i >> 2, b, pd.pair_index, 1u), key0, key1);
+            ckey[k] = word_of(w, i & 3);
+        }
+        wave_sync();
+        for (uint32_t k = lane; k < cnt; k += 64) {
+            const uint32_t sk = ckey[k], ik = cidx[k];
+            uint32_t rank = 0;
+            for (uint32_t q = 0; q < cnt; ++q) {
+                const uint32_t s2 = ckey[q], i2 = cidx[q];
+                rank += (s2 < sk) || (s2 == sk && i2 < ik);
+            }
+            if (rank < need) atomicOr(&mlds[ik >> 5], 1u << (ik & 31));
+        }
     }
     wave_sync();
     uint32_t* out = const_cast<uint32_t*>(mask_row(mask, bp[p], row, pd.Wp));

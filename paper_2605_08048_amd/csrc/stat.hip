@@ -90,20 +90,24 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
 // with the FP64 pooled total t.  One work-group per flagged split (persistent
 // over the flag list), 256 threads over the columns.
 // ---------------------------------------------------------------------------
+constexpr int kRecheckWaves = 8;
+
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pairs,
-                                                 const BlockPair* __restrict__ bp, int npairs,
-                                                 const PairState* __restrict__ st,
-                                                 const double* __restrict__ v,
-                                                 const double* __restrict__ t64,
-                                                 const double* __restrict__ coef,
-                                                 const uint32_t* __restrict__ mask,
-                                                 const uint32_t* __restrict__ flags,
-                                                 const uint32_t* __restrict__ nflag, int d,
-                                                 int d_pad, int gd, int alternative,
-                                                 PairCount* cnt) {
-    constexpr int kCols = 4;  // columns per thread per pass (1024 per pass)
-    __shared__ double red1[256], red2[256];
+__global__ __launch_bounds__(64 * kRecheckWaves) void k_recheck(
+    const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
+    const PairState* __restrict__ st, const double* __restrict__ v,
+    const double* __restrict__ t64, const double* __restrict__ coef,
+    const uint32_t* __restrict__ mask, const uint32_t* __restrict__ flags,
+    const uint32_t* __restrict__ nflag, int d, int d_pad, int gd, int alternative,
+    PairCount* cnt) {
+    constexpr int kU = 12;                 // columns per lane per pass (768 per pass)
+    constexpr int kPass = 64 * kU;
+    constexpr int kRows = 4;               // rows in flight per wave
+    constexpr int kThreads = 64 * kRecheckWaves;
+    __shared__ double part[kRecheckWaves][kPass];  // per-wave partial group sums
+    __shared__ double red1[kThreads], red2[kThreads];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const uint32_t total = *nflag;
     for (uint32_t f = blockIdx.x; f < total; f += gridDim.x) {
         const int64_t row = flags[f];
@@ -117,47 +121,90 @@ __global__ __launch_bounds__(256) void k_recheck(const PairDesc* __restrict__ pa
         const int N = pd.n + pd.m;
         const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
         const int W = (N + 31) >> 5;
+        const Tin* X = (const Tin*)pd.X;
+        const Tin* Y = (const Tin*)pd.Y;
+        // members of the smaller group in mask word w
+        auto word_bits = [&](int w) -> uint32_t {
+            if (w >= W) return 0u;
+            uint32_t b = mk[w] ^ flip;
+            if (w == W - 1 && (N & 31)) b &= (1u << (N & 31)) - 1u;
+            return b;
+        };
         double ss_small = 0.0, ss_large = 0.0;
-        for (int c0 = 0; c0 < d; c0 += 256 * kCols) {
-            double acc[kCols];
-            double vc[kCols];
+        for (int c0 = 0; c0 < d; c0 += kPass) {
+            double acc[kU], vc[kU];
 #pragma unroll
-            for (int u = 0; u < kCols; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 acc[u] = 0.0;
-                const int c = c0 + u * 256 + threadIdx.x;
+                const int c = c0 + 64 * u + lane;
                 vc[u] = c < d ? vp[c] : 0.0;
             }
-            for (int w = 0; w < W; ++w) {
-                uint32_t bits = mk[w] ^ flip;  // members of the smaller group
-                if (w == W - 1 && (N & 31)) bits &= (1u << (N & 31)) - 1u;
-                while (bits) {
-                    const int i = 32 * w + __builtin_ctz(bits);
-                    bits &= bits - 1u;
-                    const bool isx = i < pd.n;
-                    const double k = isx ? cf[i] : 0.0;
-                    const Tin* src = isx ? (const Tin*)pd.X + (int64_t)i * d
-                                         : (const Tin*)pd.Y + (int64_t)(i - pd.n) * d;
+            // wave w walks mask words w, w + 8, ...; kRows rows at a time, all
+            // loads issued before the adds
+            int w = wave;
+            uint32_t bits = word_bits(w);
+            for (;;) {
+                int rows[kRows];
 #pragma unroll
-                    for (int u = 0; u < kCols; ++u) {
-                        const int c = c0 + u * 256 + threadIdx.x;
-                        if (c < d) acc[u] += (double)src[c] - k * vc[u];
+                for (int t = 0; t < kRows; ++t) {
+                    while (!bits && w < W) {
+                        w += kRecheckWaves;
+                        bits = word_bits(w);
+                    }
+                    if (bits) {
+                        rows[t] = 32 * w + __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                    } else {
+                        rows[t] = -1;
                     }
                 }
+                if (rows[0] < 0) break;
+                // loads of all kRows rows are issued before any add: columns are
+                // clamped to the row (no branch around a load), absent rows and
+                // clamped columns are weighted by 0
+                Tin z[kRows][kU];
+                double kc[kRows], wt[kRows];
+#pragma unroll
+                for (int t = 0; t < kRows; ++t) {
+                    const int i = rows[t] < 0 ? 0 : rows[t];
+                    const bool isx = i < pd.n;
+                    kc[t] = (rows[t] >= 0 && isx) ? cf[i] : 0.0;
+                    wt[t] = rows[t] >= 0 ? 1.0 : 0.0;
+                    const Tin* src = isx ? X + (int64_t)i * d : Y + (int64_t)(i - pd.n) * d;
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const int c = c0 + 64 * u + lane;
+                        z[t][u] = src[c < d ? c : d - 1];
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kRows; ++t)
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const double cm = (c0 + 64 * u + lane) < d ? wt[t] : 0.0;
+                        acc[u] += cm * ((double)z[t][u] - kc[t] * vc[u]);
+                    }
             }
 #pragma unroll
-            for (int u = 0; u < kCols; ++u) {
-                const int c = c0 + u * 256 + threadIdx.x;
+            for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = acc[u];
+            __syncthreads();
+            for (int cc = threadIdx.x; cc < kPass; cc += kThreads) {
+                const int c = c0 + cc;
                 if (c < d) {
-                    const double l = tp[c] - acc[u];
-                    ss_small += acc[u] * acc[u];
+                    double sm = 0.0;
+#pragma unroll
+                    for (int k = 0; k < kRecheckWaves; ++k) sm += part[k][cc];
+                    const double l = tp[c] - sm;
+                    ss_small += sm * sm;
                     ss_large += l * l;
                 }
             }
+            __syncthreads();
         }
         red1[threadIdx.x] = ss_small;
         red2[threadIdx.x] = ss_large;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
+        for (int o = kThreads / 2; o > 0; o >>= 1) {
             if (threadIdx.x < o) {
                 red1[threadIdx.x] += red1[threadIdx.x + o];
                 red2[threadIdx.x] += red2[threadIdx.x + o];
@@ -189,10 +236,10 @@ hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPai
     const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
     int64_t g = max_flags < 2048 ? max_flags : 2048;
     if (input_dtype == HBT_IN_F64)
-        hipLaunchKernelGGL(k_recheck<double>, dim3((unsigned)g), dim3(256), 0, s, pairs, bp, npairs,
+        hipLaunchKernelGGL(k_recheck<double>, dim3((unsigned)g), dim3(64 * kRecheckWaves), 0, s, pairs, bp, npairs,
                            st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
     else
-        hipLaunchKernelGGL(k_recheck<float>, dim3((unsigned)g), dim3(256), 0, s, pairs, bp, npairs,
+        hipLaunchKernelGGL(k_recheck<float>, dim3((unsigned)g), dim3(64 * kRecheckWaves), 0, s, pairs, bp, npairs,
                            st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
     return hipGetLastError();
 }

@@ -181,7 +181,7 @@ def align(X, Y, *, align=True, gd="banerjee", out=None, stream=None):
 
 def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", gd="banerjee",
               alternative="greater", align=True, recheck=True, block_perms=0, masks=None,
-              want_T=False, want_masks=False, stream=None, sync=True):
+              stat_route=0, want_T=False, want_masks=False, stream=None, sync=True):
     """The whole test for one pair.  Returns a dict of the hbt_result fields,
     plus ``T`` (B floats; doubles with want_T="f64") and ``masks``
     (B x ceil(N/32) words) when asked."""
@@ -198,7 +198,7 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
                          if not isinstance(masks, torch.Tensor) else masks, torch.int32, dev)
     prm = make_params(n, m, d, B, seed=seed, perm_offset=perm_offset, pair_index=pair_index,
                       precision=precision, input_dtype=_input_dtype(X), gd=gd, alternative=alternative,
-                      align=align, recheck=recheck, block_perms=block_perms,
+                      align=align, recheck=recheck, block_perms=block_perms, stat_route=stat_route,
                       masks_ptr=None if mk is None else mk.data_ptr())
     t64 = want_T == "f64"
     if t64:

@@ -70,7 +70,7 @@ def test_perm_test_rejects_null_pointers_and_enums():
     for field, bad, st in [("precision", 7, hbt.ERR_ARG), ("input_dtype", 5, hbt.ERR_DTYPE),
                            ("gd", 3, hbt.ERR_ARG), ("alternative", 2, hbt.ERR_ARG),
                            ("align", 2, hbt.ERR_ARG), ("flags", 8, hbt.ERR_ARG),
-                           ("stat_route", 5, hbt.ERR_UNSUPPORTED), ("block_perms", -1, hbt.ERR_ARG)]:
+                           ("stat_route", 5, hbt.ERR_ARG), ("block_perms", -1, hbt.ERR_ARG)]:
         p = hbt.make_params(10, 12, 8, 10)
         setattr(p, field, bad)
         assert _call(p) == st, field
@@ -129,3 +129,7 @@ def test_batched_validation():
     st = L.hbt_perm_test_batched(0, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                  FAKE, need, None)
     assert st == hbt.ERR_SIZE
+    prm.stat_route = 1  # the point-to-centroid route is single-pair only
+    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                 FAKE, need, None)
+    assert st == hbt.ERR_UNSUPPORTED

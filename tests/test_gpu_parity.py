@@ -207,6 +207,25 @@ def test_no_recheck_flag_counts_raw_precision():
     assert abs(r["count"] - int(np.sum(r["T"].astype(np.float64) >= thr))) <= 2
 
 
+# --------------------------------------------------------------------- point-to-centroid route
+
+@pytest.mark.parametrize("n,m,d,prec", [(37, 150, 100, "f32"), (150, 37, 100, "bf16x2"),
+                                        (300, 450, 768, "bf16x2"), (61, 70, 64, "f64")])
+def test_point_to_centroid_route_matches_oracle(n, m, d, prec):
+    print(f"route 2 n={n} m={m} d={d} {prec}", flush=True)
+    X, Y = _pair(n, m, d, kx=2.0, ky=2.1, seed=n + 3 * m + d)
+    B = 700
+    r1 = hbt.perm_test(_dev(X), _dev(Y), B, seed=7, precision=prec, want_T="f64")
+    r2 = hbt.perm_test(_dev(X), _dev(Y), B, seed=7, precision=prec, stat_route=1, want_T="f64")
+    o = O.perm_test(X, Y, B, seed=7, want_T=True)
+    at = O.perm_stats_at(X, Y, np.arange(B), seed=7)
+    sc = _scale(X, Y, at)
+    # route 2 reduces the same norms through FP32 products: the FP32 bar holds
+    assert (np.abs(r2["T"] - o["T"]) / sc).max() <= 1e-5
+    assert (np.abs(r2["T"] - r1["T"]) / sc).max() <= 2e-5
+    assert r2["count"] == r1["count"] == o["count"]
+
+
 # --------------------------------------------------------------------- batched
 
 def test_batched_matches_oracle_per_pair():
@@ -240,6 +259,15 @@ def test_config1_fp64():
     assert err.max() < 1e-7  # T_out is float32
     assert r["count"] == o["count"] and r["p"] == o["p"]
     assert abs(r["t_obs"] - o["t_obs"]) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2"])
+def test_config2_point_to_centroid_sampled(prec):
+    c = synth.config2()
+    r = hbt.perm_test(_dev(c.X), _dev(c.Y), 2000, seed=c.seed, precision=prec, stat_route=1, want_T="f64")
+    sample = np.arange(0, 2000, 37)
+    at = O.perm_stats_at(c.X, c.Y, sample)
+    assert (np.abs(r["T"][sample] - at["T"]) / _scale(c.X, c.Y, at)).max() <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x2"])
