@@ -54,6 +54,70 @@ def load_traffic(name, launches_per_step):
     return rec.get("hbm_bytes_per_launch")
 
 
+TRAFFIC_FILE = "groupsum_bf16x2_batch512_d768_traffic.json"
+COPY_BYTES = 1 << 30        # the calibration copy: 1 GiB read, 1 GiB written
+
+
+def counter_pass(args):
+    """One warm and one measured call of the batched split-BF16 path, then a
+    plain 1 GiB device copy whose byte counts calibrate the HBM counters.
+    Meant to run under ``rocprofv3 --pmc FETCH_SIZE`` (then WRITE_SIZE)."""
+    import torch
+    from paper_2605_08048_amd import hbt, synth
+    dev = torch.device("cuda:0")
+    batch = synth.batch_512_d768()
+    Z = torch.from_numpy(batch.Z).to(dev)
+    res = torch.zeros(hbt.RESULT_BYTES * batch.npairs, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
+                              precision="bf16x2", sync=False, results=res)
+    torch.cuda.synchronize()
+    log("batched split-BF16 calls done")
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("1 GiB calibration copy done")
+
+
+def write_traffic(fetch_csv, write_csv, command):
+    """HBM bytes per launch of k_groupsum_bf16x2 from two rocprofv3 counter
+    runs, each counter scaled by what it reads for the 1 GiB copy."""
+    import csv
+    from collections import defaultdict
+
+    def per_dispatch(path, counter):
+        acc = defaultdict(lambda: defaultdict(float))
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+    def pick(d, key):
+        hits = [v for k, v in d.items() if key in k]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel matching {key!r}, found {len(hits)}")
+        return hits[0]
+
+    f = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = per_dispatch(write_csv, "WRITE_SIZE")
+    f_copy, w_copy = pick(f, "copyBuffer"), pick(w, "copyBuffer")       # KiB per dispatch
+    f_gs, w_gs = pick(f, "k_groupsum_bf16x2"), pick(w, "k_groupsum_bf16x2")
+    sf, sw = COPY_BYTES / (f_copy * 1024), COPY_BYTES / (w_copy * 1024)
+    rec = {
+        "kernel": "k_groupsum_bf16x2", "workload": "batch_512_d768",
+        "kernel_hash": kernel_source_hash(),
+        "fetch_kib_per_dispatch": f_gs, "write_kib_per_dispatch": w_gs,
+        "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+        "fetch_scale": sf, "write_scale": sw,
+        "hbm_read_bytes_per_launch": f_gs * 1024 * sf, "hbm_write_bytes_per_launch": w_gs * 1024 * sw,
+        "hbm_bytes_per_launch": f_gs * 1024 * sf + w_gs * 1024 * sw,
+        "command": command,
+    }
+    (ROOT / "profiles" / TRAFFIC_FILE).write_text(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec))
+
+
 def stage_times(L, ctypes):
     ms = (ctypes.c_double * 6)()
     n = (ctypes.c_int64 * 6)()
@@ -91,11 +155,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="run the batched path twice and a 1 GiB copy, for rocprofv3 --pmc")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 counter CSVs into the committed traffic summary")
+    ap.add_argument("--traffic-command", default="", help="the commands that produced the CSVs")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, args.traffic_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the permutation test shards by split ranges, see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+
+    if args.counter_pass:
+        counter_pass(args)
+        return
 
     import ctypes
     import torch
@@ -104,7 +180,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t = time.perf_counter()
-    batch = synth.config4()
+    batch = synth.batch_512_d768()
     Z = torch.from_numpy(batch.Z).to(dev)
     log(f"workload generated and resident in HBM ({time.perf_counter() - t:.1f} s, {Z.numel() * 4 / 1e9:.2f} GB)")
     P = batch.npairs
@@ -115,7 +191,7 @@ def main():
     L = hbt.lib()
 
     def run(prec, steps, warmup):
-        res = torch.zeros(72 * P, dtype=torch.uint8, device=dev)
+        res = torch.zeros(hbt.RESULT_BYTES * P, dtype=torch.uint8, device=dev)
         for _ in range(warmup):
             hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
                                   precision=prec, sync=False, results=res)
@@ -139,7 +215,7 @@ def main():
     value = stats_per_step * args.steps / dt
     g_ms = ms[2] / max(launches[2], 1)
     achieved = algo_flops / (g_ms * 1e-3) / 1e12
-    traffic = load_traffic("groupsum_bf16x2_config4_traffic.json", 1)
+    traffic = load_traffic(TRAFFIC_FILE, 1)
 
     fp = None
     if args.fp32_steps > 0:
@@ -167,7 +243,7 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "config4: 512 pairs, d=768, B=2000 splits/pair, n,m log-uniform [20,5000], "
+        "config": {"workload": "batch_512_d768: 512 pairs, d=768, B=2000 splits/pair, n,m log-uniform [20,5000], "
                                "split-BF16 group sums (hi+lo, FP32 accumulation), FP64 statistic + recheck",
                    "pairs": P, "d": d, "splits_per_step": stats_per_step, "rows": int(N.sum())},
         "roofline": {"bound": "mfma", "kernel": "k_groupsum_bf16x2", "achieved": achieved,

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define HBT_ABI_VERSION 1
+#define HBT_ABI_VERSION 2
 #define HBT_MAX_N 65536     /* largest pooled size n + m */
 #define HBT_MAX_D 8192      /* largest dimension */
 
@@ -83,19 +83,25 @@ typedef enum hbt_gd { HBT_GD_BANERJEE = 0, HBT_GD_IDENTITY = 1 } hbt_gd;
  * TWO_SIDED: count |T_b| >= |T_obs| (Table 5 reports two-sided values). */
 typedef enum hbt_alternative { HBT_ALT_GREATER = 0, HBT_ALT_TWO_SIDED = 1 } hbt_alternative;
 
-/* Per-pair result, written to DEVICE memory (72 bytes). */
+/* Per-pair result, written to DEVICE memory (112 bytes). */
 typedef struct hbt_result {
     double t_obs;        /* log v(X') - log v(Y), FP64 (eq:tobs) */
     double r_x;          /* mean resultant length of X (= of X', H orthogonal) */
     double r_y;          /* mean resultant length of Y */
     double p;            /* (1 + count) / (B + 1) (eq:pvalue) */
     double tau;          /* tie tolerance: T_b counts if T_b >= T_obs - tau */
+    double mu_cos;       /* cosine of the angle between the unit mean directions,
+                            1 - |mu_x - mu_y|^2 / 2 (Sec. 3.1) */
+    double t_mean;       /* mean of the B permuted statistics T_b */
+    double t_sd;         /* their standard deviation (divisor B); both use the final
+                            T_b (FP64 for rechecked splits) and are NaN if any T_b is */
     int64_t count;       /* exceedances among the B splits */
     int64_t B;           /* splits evaluated */
     int64_t n_recheck;   /* splits re-evaluated in FP64 because T_b was near T_obs */
+    int64_t n, m;        /* group sizes of the pair */
     int32_t status;      /* hbt_status of this pair */
     int32_t h_identity;  /* 1 when H = I (alignment off, or |v| <= 1e-12) */
-} hbt_result;
+} hbt_result;            /* 112 bytes */
 
 /* Parameters of one test (96 bytes; host memory). */
 typedef struct hbt_perm_params {
@@ -131,8 +137,8 @@ const char* hbt_last_error(void);
  *   X (n x d), Y (m x d): unit rows, dtype input_dtype.
  *   X_out (n x d, same dtype): receives H x_i; may alias X.
  *   v_out (d doubles, nullable): receives v = mu_x - mu_y.
- *   result (device, one hbt_result): t_obs, r_x, r_y, tau, status, h_identity;
- *   p, count, B and n_recheck are set to 0.
+ *   result (device, one hbt_result): t_obs, r_x, r_y, tau, mu_cos, n, m,
+ *   status, h_identity; p, t_mean, t_sd, count, B and n_recheck are set to 0.
  * Errors: HBT_ERR_ARG (NULL X/Y/X_out/result, bad enum), HBT_ERR_SIZE,
  * HBT_ERR_WORKSPACE, HBT_ERR_DEVICE. */
 size_t hbt_align_workspace_size(int64_t n, int64_t m, int64_t d);
@@ -193,6 +199,73 @@ typedef enum hbt_stage {
 } hbt_stage;
 hbt_status hbt_stage_timing(int32_t enable);
 hbt_status hbt_stage_times(double* ms, int64_t* launches);
+
+/* ------------------------------------------------------------------------
+ * Learned permutation-budget allocator.  The paper gives every pair the same
+ * number of splits; here a small network estimates, from quantities of
+ * Algorithm 1 Steps 1-4, the mean and log standard deviation of a pair's
+ * permuted statistics T_b (Algorithm 1 Step 5), and the normal approximation
+ * p^ = 1 - Phi((T_obs - mean) / sd) sets how many splits the pair gets.  The
+ * permutation p-value of eq:pvalue stays the decision.
+ *
+ * Network: 12 -> 64 -> 64 -> 2, ReLU, FP32, parameters theta (HBT_MLP_PARAMS
+ * floats, device): shift[12], scale[12] (inputs enter as (x - shift) *
+ * scale; not trained), W1[64][12], b1[64], W2[64][64], b2[64], W3[2][64],
+ * b3[2], row-major.  Outputs per row: (mean, log sd).
+ * ------------------------------------------------------------------------ */
+#define HBT_MLP_FEATURES 12
+#define HBT_MLP_PARAMS 5146
+#define HBT_MLP_TRAINABLE_OFFSET 24   /* theta[24:] is trained */
+
+/* features (device, npairs x 12 floats) of each pair from its results (device,
+ * from hbt_perm_test or hbt_perm_test_batched; any B >= 1): log n, log m,
+ * r_X, r_Y, the pooled MRL after alignment (n r_X + m r_Y) / (n + m) (the
+ * appendix's alignment optimum), mu_cos, log g_d(r_X), log g_d(r_Y), T_obs,
+ * n / (n + m), log(1 - r_X^2), log(1 - r_Y^2); computed in FP64.
+ * Errors: HBT_ERR_ARG (NULL pointer, bad gd), HBT_ERR_SIZE (npairs < 1, d
+ * outside [1, HBT_MAX_D]), HBT_ERR_DEVICE. */
+hbt_status hbt_budget_features(int64_t npairs, const hbt_result* results, int64_t d, int32_t gd,
+                               float* features, void* stream);
+
+/* theta[0:24] = per-feature mean and 1 / standard deviation over `rows`
+ * feature rows (FP64 reductions; a constant feature gets scale 1).
+ * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (rows < 1), HBT_ERR_DEVICE. */
+hbt_status hbt_feature_norm(int64_t rows, const float* features, float* theta, void* stream);
+
+/* out (device, rows x 2 floats) = network(features).
+ * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (rows < 1), HBT_ERR_DEVICE. */
+hbt_status hbt_mlp_forward(int64_t rows, const float* features, const float* theta, float* out,
+                           void* stream);
+
+/* grad (device, HBT_MLP_PARAMS floats; entries below the trainable offset are
+ * left untouched) = gradient of L = (1/rows) sum_r (1/2) |out_r - target_r|^2
+ * with targets (device, rows x 2); loss (device double, nullable) = L.  The
+ * sum over rows runs in a fixed order in FP64, so results are reproducible.
+ * Errors: HBT_ERR_ARG, HBT_ERR_SIZE, HBT_ERR_WORKSPACE, HBT_ERR_DEVICE. */
+size_t hbt_mlp_grad_workspace_size(int64_t rows);
+hbt_status hbt_mlp_grad(int64_t rows, const float* features, const float* targets,
+                        const float* theta, float* grad, double* loss, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* One Adam step (Kingma & Ba 2015, Algorithm 1, bias-corrected; step >= 1)
+ * on theta[24:], with first and second moments adam_m, adam_v (device,
+ * HBT_MLP_PARAMS floats each, zero before step 1).
+ * Errors: HBT_ERR_ARG (NULL pointer, step < 1, lr <= 0, betas outside
+ * [0, 1)), HBT_ERR_DEVICE. */
+hbt_status hbt_mlp_adam(float* theta, const float* grad, float* adam_m, float* adam_v, int64_t step,
+                        float lr, float beta1, float beta2, float eps, void* stream);
+
+/* budgets (device, npairs int64) from the network outputs (device, npairs x 2)
+ * and the pairs' T_obs (results): with p^ as above, pairs with p^ in the
+ * fallback band [p_lo, p_hi] get b_max; the others get
+ * ceil(zq^2 p^ (1 - p^) / (p^ - e)^2), e the nearer band edge, clamped to
+ * [b_min, b_max] (the splits that put zq standard errors of the estimated p
+ * between p^ and the band).  p_lo = p_hi = alpha gives the plain rule.
+ * Errors: HBT_ERR_ARG (NULL pointer, 0 > p_lo > p_hi > 1, zq <= 0),
+ * HBT_ERR_SIZE (npairs < 1, b_min < 1, b_max < b_min), HBT_ERR_DEVICE. */
+hbt_status hbt_budgets(int64_t npairs, const float* mlp_out, const hbt_result* results,
+                       double p_lo, double p_hi, int64_t b_min, int64_t b_max, double zq,
+                       int64_t* budgets, void* stream);
 
 #ifdef __cplusplus
 }

@@ -92,6 +92,77 @@ hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, const SumChunk*
     return hipGetLastError();
 }
 
+// FP32 rows with d a multiple of 4 and 16-byte aligned rows: one
+// work-group = one chunk of rows x all columns; wave w sums rows w, w+4, ...
+// of the chunk with 16-byte loads (lane l: columns 4(l + 64 j) .. +3), the
+// four waves' sums are added in a fixed order through LDS.
+template <int J>
+__global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pairs,
+                                                 const SumChunk* __restrict__ chunks, int d,
+                                                 double* __restrict__ partial) {
+    __shared__ double red[3][256 * J];
+    const SumChunk ch = chunks[blockIdx.x];
+    const PairDesc pd = pairs[ch.pair];
+    const float* base = (const float*)(ch.side ? pd.Y : pd.X);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double acc[J][4];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[j][e] = 0.0;
+    for (int r = ch.r0 + wave; r < ch.r1; r += 4) {
+        const float4* row = (const float4*)(base + (int64_t)r * d);
+        float4 x[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int q = lane + 64 * j;
+            x[j] = 4 * q < d ? row[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            acc[j][0] += (double)x[j].x;
+            acc[j][1] += (double)x[j].y;
+            acc[j][2] += (double)x[j].z;
+            acc[j][3] += (double)x[j].w;
+        }
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[wave - 1][4 * (lane + 64 * j) + e] = acc[j][e];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = 4 * (lane + 64 * j) + e;
+                if (c < d)
+                    partial[(int64_t)blockIdx.x * d + c] =
+                        (acc[j][e] + red[0][c]) + (red[1][c] + red[2][c]);
+            }
+}
+
+bool vector_rows_ok(int input_dtype, int d, int d_pad) {
+    return input_dtype == HBT_IN_F32 && d % 4 == 0 && d_pad <= 1024;
+}
+
+hipError_t launch_colsum_vec(const PairDesc* pairs, const SumChunk* chunks, int nchunks, int d,
+                             int d_pad, double* partial, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    const int J = (d_pad + 255) / 256;
+    const dim3 g(nchunks), b(256);
+    switch (J) {
+        case 1: hipLaunchKernelGGL(k_colsum4<1>, g, b, 0, s, pairs, chunks, d, partial); break;
+        case 2: hipLaunchKernelGGL(k_colsum4<2>, g, b, 0, s, pairs, chunks, d, partial); break;
+        case 3: hipLaunchKernelGGL(k_colsum4<3>, g, b, 0, s, pairs, chunks, d, partial); break;
+        case 4: hipLaunchKernelGGL(k_colsum4<4>, g, b, 0, s, pairs, chunks, d, partial); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // finalize: one work-group per pair
 // ---------------------------------------------------------------------------
@@ -179,15 +250,22 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
         st[p] = q;
         cnt[p].count = 0;
         cnt[p].n_recheck = 0;
+        cnt[p].sum_dt = 0.0;
+        cnt[p].sum_dt2 = 0.0;
         hbt_result r;
         r.t_obs = q.t_obs;
         r.r_x = r_x;
         r.r_y = r_y;
         r.p = 0.0;
         r.tau = q.tau;
+        r.mu_cos = 1.0 - 0.5 * vv;  // |mu_x - mu_y|^2 = 2 - 2 cos
+        r.t_mean = 0.0;
+        r.t_sd = 0.0;
         r.count = 0;
         r.B = 0;
         r.n_recheck = 0;
+        r.n = pd.n;
+        r.m = pd.m;
         r.status = q.status;
         r.h_identity = identity;
         res[p] = r;
@@ -323,6 +401,154 @@ hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs,
                                         coef, zstore, zplane_elems, z32, s);
     return launch_reflect_t<float>(precision, pairs, npairs, total_octets, st, v, d, d_pad, coef,
                                    zstore, zplane_elems, z32, s);
+}
+
+// The same reflection and storage for FP32 rows with d a multiple of 4 and
+// 16-byte aligned rows: one wave per octet, the octet's 8 rows held in
+// registers (lane l: columns 4(l + 64 j) .. +3, j < J), loaded once with
+// 16-byte loads; the coefficients are FP64 wave reductions and every lane
+// then writes its 4 consecutive columns of the octet.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+template <int PREC, int J>
+__global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ pairs, int npairs,
+                                                  int64_t total_octets,
+                                                  const PairState* __restrict__ st,
+                                                  const double* __restrict__ v, int d, int d_pad,
+                                                  double* __restrict__ coef, void* zstore,
+                                                  int64_t zplane_elems, float* __restrict__ z32) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t oct = (int64_t)blockIdx.x * 4 + wave;
+    if (oct >= total_octets) return;
+    const int p = upper_index(npairs, oct * 8, [&](int k) { return pairs[k].zrow0; });
+    const PairDesc pd = pairs[p];
+    const int identity = st[p].identity;
+    const double vv = st[p].vv;
+    const double* vp = v + (int64_t)p * d_pad;
+    const int i0 = (int)(oct * 8 - pd.zrow0);
+    const int N = pd.n + pd.m;
+    float4 x[8][J];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = i0 + r;  // wave-uniform
+        const float* row = i < pd.n ? (const float*)pd.X + (int64_t)i * d
+                                    : (const float*)pd.Y + (int64_t)(i - pd.n) * d;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int c = 4 * (lane + 64 * j);
+            x[r][j] = (i < N && c < d) ? *(const float4*)(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    double vc[J][4];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 4 * (lane + 64 * j) + e;
+            vc[j][e] = c < d ? vp[c] : 0.0;
+        }
+    // coefficients 2 (v . x_i) / (v . v) of the X rows (eq:householder_fast)
+    double k[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = i0 + r;
+        k[r] = 0.0;
+        if (!identity && i < pd.n) {  // wave-uniform
+            double w = 0.0;
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                w += vc[j][0] * (double)x[r][j].x + vc[j][1] * (double)x[r][j].y +
+                     vc[j][2] * (double)x[r][j].z + vc[j][3] * (double)x[r][j].w;
+            k[r] = 2.0 * wave_sum_f64(w) / vv;
+        }
+    }
+    if (lane < 8) {
+        double kr = k[0];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) kr = lane == r ? k[r] : kr;
+        if (i0 + lane < pd.n) coef[pd.coef0 + i0 + lane] = kr;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int c0 = 4 * (lane + 64 * j);
+        if (c0 >= d_pad) continue;
+        double z[4][8];  // [column][row]
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            z[0][r] = (double)x[r][j].x - k[r] * vc[j][0];
+            z[1][r] = (double)x[r][j].y - k[r] * vc[j][1];
+            z[2][r] = (double)x[r][j].z - k[r] * vc[j][2];
+            z[3][r] = (double)x[r][j].w - k[r] * vc[j][3];
+        }
+        if (z32) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                *(float4*)(z32 + (oct * 8 + r) * d_pad + c0) =
+                    make_float4((float)z[0][r], (float)z[1][r], (float)z[2][r], (float)z[3][r]);
+        }
+        if (PREC == HBT_BF16X2) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t hi[4], lo[4];
+#pragma unroll
+                for (int r = 0; r < 8; r += 2) {
+                    const float a = (float)z[e][r], b = (float)z[e][r + 1];
+                    const uint32_t ha = f32_to_bf16_bits(a), hb = f32_to_bf16_bits(b);
+                    const uint32_t la = f32_to_bf16_bits(a - bf16_bits_to_f32(ha));
+                    const uint32_t lb = f32_to_bf16_bits(b - bf16_bits_to_f32(hb));
+                    hi[r / 2] = ha | (hb << 16);
+                    lo[r / 2] = la | (lb << 16);
+                }
+                uint4* ph = (uint4*)zstore + oct * d_pad + c0 + e;
+                *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+                *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+            }
+        } else if (PREC == HBT_F32) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                *(float4*)((float*)zstore + (oct * 8 + r) * d_pad + c0) =
+                    make_float4((float)z[0][r], (float)z[1][r], (float)z[2][r], (float)z[3][r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                double2* q = (double2*)((double*)zstore + (oct * 8 + r) * d_pad + c0);
+                q[0] = make_double2(z[0][r], z[1][r]);
+                q[1] = make_double2(z[2][r], z[3][r]);
+            }
+        }
+    }
+}
+
+hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
+                              int64_t total_octets, const PairState* st, const double* v, int d,
+                              int d_pad, double* coef, void* zstore, int64_t zplane_elems,
+                              float* z32, hipStream_t s) {
+    if (total_octets <= 0) return hipSuccess;
+    const int J = (d_pad + 255) / 256;
+    const dim3 g((unsigned)((total_octets + 3) / 4)), b(256);
+#define HBT_R4(PR, JJ)                                                                         \
+    hipLaunchKernelGGL((k_reflect4<PR, JJ>), g, b, 0, s, pairs, npairs, total_octets, st, v, d, \
+                       d_pad, coef, zstore, zplane_elems, z32)
+#define HBT_R4J(PR)                            \
+    switch (J) {                               \
+        case 1: HBT_R4(PR, 1); break;          \
+        case 2: HBT_R4(PR, 2); break;          \
+        case 3: HBT_R4(PR, 3); break;          \
+        case 4: HBT_R4(PR, 4); break;          \
+        default: return hipErrorInvalidValue;  \
+    }
+    switch (precision) {
+        case HBT_F64: HBT_R4J(HBT_F64); break;
+        case HBT_F32: HBT_R4J(HBT_F32); break;
+        default: HBT_R4J(HBT_BF16X2); break;
+    }
+#undef HBT_R4J
+#undef HBT_R4
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

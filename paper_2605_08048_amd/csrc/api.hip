@@ -131,6 +131,7 @@ struct Workspace {
     uint32_t* mask;
     double* partial;
     uint32_t* flags;
+    double* tw;         // final T_b of the current block (moments)
     uint32_t* nflag;
     // point-to-centroid route
     float* sig;         // group sums of the smaller group, block rows x d_pad
@@ -159,6 +160,7 @@ struct Plan {
     int64_t block_mask_words = 0; // mask words of the largest block
     bool need_store = true;       // group-sum path (false for hbt_align)
     bool route2 = false;          // point-to-centroid statistic route
+    bool aligned16 = true;        // every X, Y starts on a 16-byte boundary
     int ntile_i = 0;              // its row tiles (of 64) per split
     std::vector<GemmTile> ctiles;
 };
@@ -187,6 +189,7 @@ Workspace carve(const Plan& P, void* ws) {
         w.mask = c.take<uint32_t>(std::max<int64_t>(P.block_mask_words, 1));
         w.partial = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.nslot * 2);
         w.flags = c.take<uint32_t>(std::max<int64_t>(P.block_rows, 1));
+        w.tw = c.take<double>(std::max<int64_t>(P.block_rows, 1));
         w.nflag = c.take<uint32_t>(2);
         if (P.route2) {
             w.sig = c.take<float>((size_t)std::max<int64_t>(P.block_rows, 1) * P.d_pad);
@@ -212,6 +215,7 @@ Workspace carve(const Plan& P, void* ws) {
         w.mask = nullptr;
         w.partial = nullptr;
         w.flags = nullptr;
+        w.tw = nullptr;
         w.nflag = nullptr;
     }
     w.bytes = c.off + 256;
@@ -219,6 +223,7 @@ Workspace carve(const Plan& P, void* ws) {
 }
 
 void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint32_t pair_index) {
+    P.aligned16 = P.aligned16 && ((uintptr_t)X % 16 == 0) && ((uintptr_t)Y % 16 == 0);
     PairDesc pd;
     memset(&pd, 0, sizeof pd);
     pd.X = X;
@@ -305,6 +310,18 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     return P;
 }
 
+// 16-byte row loads apply: FP32 rows, d a multiple of 4, aligned bases.
+bool vector_rows(const Plan& P) { return P.aligned16 && vector_rows_ok(P.input_dtype, P.d, P.d_pad); }
+
+// Householder reflection of every pair and the precision's Z storage.
+hipError_t reflect(const Plan& P, const Workspace& w, float* z32, hipStream_t s) {
+    if (vector_rows(P))
+        return launch_reflect_vec(P.precision, w.pairs, P.npairs, P.zrows / 8, w.st, w.v, P.d, P.d_pad,
+                                  w.coef, w.zstore, P.zrows * P.d_pad, z32, s);
+    return launch_reflect(P.input_dtype, P.precision, w.pairs, P.npairs, P.zrows / 8, w.st, w.v, P.d,
+                          P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, z32, s);
+}
+
 hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd, hbt_result* res,
                             hipStream_t s) {
     {
@@ -313,8 +330,11 @@ hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd
         HIP_TRY(upload(w.chunks, P.chunks.data(), P.chunks.size() * sizeof(SumChunk), s));
     }
     StageTimer t(HBT_STAGE_ALIGN, s);
-    HIP_TRY(launch_colsum(P.input_dtype, w.pairs, w.chunks, (int)P.chunks.size(), P.d,
-                          w.partial_sum, s));
+    if (vector_rows(P))
+        HIP_TRY(launch_colsum_vec(w.pairs, w.chunks, (int)P.chunks.size(), P.d, P.d_pad, w.partial_sum, s));
+    else
+        HIP_TRY(launch_colsum(P.input_dtype, w.pairs, w.chunks, (int)P.chunks.size(), P.d,
+                              w.partial_sum, s));
     HIP_TRY(launch_finalize(w.pairs, P.npairs, w.partial_sum, P.d, P.d_pad, align, gd, w.sxy, w.st,
                             w.v, w.t64, w.t32, w.cnt, res, s));
     return HBT_OK;
@@ -448,7 +468,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     const size_t need = carve(P, nullptr).bytes;
     if (!ws || ws_bytes < need)
         return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-    if (!prm->masks && split_lds_per_wave(P.max_np) > split_lds_limit())
+    if (!prm->masks && split_lds_per_block(P.max_np) > std::min<size_t>(split_lds_limit(), 65536))
         return fail(HBT_ERR_SIZE, "n + m too large for the split kernel's LDS");
     hipStream_t s = (hipStream_t)stream;
     Workspace w = carve(P, ws);
@@ -466,8 +486,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     const float* z32 = P.precision == HBT_F32 ? (const float*)w.zstore : w.z32;
     {
         StageTimer t_(HBT_STAGE_ALIGN, s);
-        HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, 1, P.zrows / 8, w.st, w.v, P.d,
-                               P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, w.z32, s));
+        HIP_TRY(reflect(P, w, w.z32, s));
         if (P.route2) {
             HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(GemmTile), s));
             HIP_TRY(launch_row_dot_t(w.pairs, 1, z32, w.t64, P.d_pad, P.zrows, w.zt, s));
@@ -508,13 +527,14 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
                             P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot, P.d, prm->gd,
                             prm->alternative, band.e_acc, band.e_store, no_recheck,
-                            T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8,
+                            T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8, w.tw,
                             w.cnt, w.flags, w.nflag, s)); }
         if (!no_recheck) {
             StageTimer t_(HBT_STAGE_RECHECK, s);
             HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.t64, w.coef, w.mask,
-                                   w.flags, w.nflag, nb, P.d, prm->gd, prm->alternative, w.cnt, s));
+                                   w.flags, w.nflag, nb, P.d, prm->gd, prm->alternative, w.cnt, w.tw, s));
         }
+        { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(1, w.bp, w.st, w.tw, w.cnt, s)); }
         if (mask_out)
             HIP_TRY(launch_export_masks(w.mask, nb, pd.Wp, W, mask_out + b0 * W, s));
     }
@@ -594,7 +614,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     const size_t need = carve(P, nullptr).bytes;
     if (!ws || ws_bytes < need)
         return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-    if (split_lds_per_wave(P.max_np) > split_lds_limit())
+    if (split_lds_per_block(P.max_np) > std::min<size_t>(split_lds_limit(), 65536))
         return fail(HBT_ERR_SIZE, "n + m too large for the split kernel's LDS");
     hipStream_t s = (hipStream_t)stream;
     Workspace w = carve(P, ws);
@@ -613,8 +633,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     }
     {
         StageTimer t_(HBT_STAGE_ALIGN, s);
-        HIP_TRY(launch_reflect(P.input_dtype, P.precision, w.pairs, np, P.zrows / 8, w.st, w.v, P.d,
-                               P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, nullptr, s));
+        HIP_TRY(reflect(P, w, nullptr, s));
     }
     { StageTimer t_(HBT_STAGE_SPLIT, s); HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask,
                                w.st, s)); }
@@ -628,13 +647,90 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
                         common->alternative, precision_band(P.precision).e_acc,
                         precision_band(P.precision).e_store, no_recheck, nullptr,
-                        false, w.cnt, w.flags, w.nflag, s)); }
+                        false, w.tw, w.cnt, w.flags, w.nflag, s)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
-                               w.nflag, P.block_rows, P.d, common->gd, common->alternative, w.cnt, s));
+                               w.nflag, P.block_rows, P.d, common->gd, common->alternative, w.cnt, w.tw, s));
     }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
     { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.st, w.cnt, w.Btot, results, s)); }
+    return HBT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// permutation-budget allocator
+// ---------------------------------------------------------------------------
+hbt_status hbt_budget_features(int64_t npairs, const hbt_result* results, int64_t d, int32_t gd,
+                               float* features, void* stream) {
+    g_err.clear();
+    if (!results || !features) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (gd != HBT_GD_BANERJEE && gd != HBT_GD_IDENTITY) return fail(HBT_ERR_ARG, "unknown g_d %d", gd);
+    if (npairs < 1) return fail(HBT_ERR_SIZE, "npairs = %lld", (long long)npairs);
+    if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
+    HIP_TRY(launch_features(npairs, results, (int)d, gd, features, (hipStream_t)stream));
+    return HBT_OK;
+}
+
+hbt_status hbt_feature_norm(int64_t rows, const float* features, float* theta, void* stream) {
+    g_err.clear();
+    if (!features || !theta) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (rows < 1) return fail(HBT_ERR_SIZE, "rows = %lld", (long long)rows);
+    HIP_TRY(launch_feature_norm(rows, features, theta, (hipStream_t)stream));
+    return HBT_OK;
+}
+
+hbt_status hbt_mlp_forward(int64_t rows, const float* features, const float* theta, float* out,
+                           void* stream) {
+    g_err.clear();
+    if (!features || !theta || !out) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (rows < 1 || rows > ((int64_t)1 << 31) - 256) return fail(HBT_ERR_SIZE, "rows = %lld", (long long)rows);
+    HIP_TRY(launch_mlp_forward(rows, features, theta, out, (hipStream_t)stream));
+    return HBT_OK;
+}
+
+size_t hbt_mlp_grad_workspace_size(int64_t rows) {
+    return rows < 1 ? 0 : mlp_train_ws_bytes(rows);
+}
+
+hbt_status hbt_mlp_grad(int64_t rows, const float* features, const float* targets,
+                        const float* theta, float* grad, double* loss, void* ws, size_t ws_bytes,
+                        void* stream) {
+    g_err.clear();
+    if (!features || !targets || !theta || !grad) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (rows < 1 || rows > ((int64_t)1 << 31) - 256) return fail(HBT_ERR_SIZE, "rows = %lld", (long long)rows);
+    if (!ws || ws_bytes < mlp_train_ws_bytes(rows))
+        return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, mlp_train_ws_bytes(rows));
+    HIP_TRY(launch_mlp_grad(rows, features, targets, theta, grad, loss, ws, (hipStream_t)stream));
+    return HBT_OK;
+}
+
+hbt_status hbt_mlp_adam(float* theta, const float* grad, float* adam_m, float* adam_v, int64_t step,
+                        float lr, float beta1, float beta2, float eps, void* stream) {
+    g_err.clear();
+    if (!theta || !grad || !adam_m || !adam_v) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps >= 0.0f))
+        return fail(HBT_ERR_ARG, "bad Adam settings (step %lld, lr %g, betas %g %g, eps %g)",
+                    (long long)step, lr, beta1, beta2, eps);
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
+    HIP_TRY(launch_adam(theta, grad, adam_m, adam_v, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream));
+    return HBT_OK;
+}
+
+hbt_status hbt_budgets(int64_t npairs, const float* mlp_out, const hbt_result* results,
+                       double p_lo, double p_hi, int64_t b_min, int64_t b_max, double zq,
+                       int64_t* budgets, void* stream) {
+    g_err.clear();
+    if (!mlp_out || !results || !budgets) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (!(p_lo >= 0.0 && p_lo <= p_hi && p_hi <= 1.0) || !(zq > 0.0))
+        return fail(HBT_ERR_ARG, "band [%g, %g], zq %g", p_lo, p_hi, zq);
+    if (npairs < 1 || b_min < 1 || b_max < b_min)
+        return fail(HBT_ERR_SIZE, "npairs %lld, budgets [%lld, %lld]", (long long)npairs,
+                    (long long)b_min, (long long)b_max);
+    HIP_TRY(launch_budgets(npairs, mlp_out, results, p_lo, p_hi, b_min, b_max, zq, budgets,
+                           (hipStream_t)stream));
     return HBT_OK;
 }
 

@@ -65,6 +65,33 @@ constexpr int kOct = kChunk / 8;                 // octets per chunk
 constexpr int kChunkVec = 2 * kOct * kDSlot;     // uint4 per chunk (both planes)
 constexpr int kXcd = 8;                          // XCDs of an MI355X
 
+// One 16-byte-per-lane direct load from global memory into LDS: lane l's
+// 16 bytes land at LDS address lds + 16 l (M0 holds the wave's base).  Issued
+// as inline asm so that the compiler inserts no waits of its own for these
+// LDS writes: the kernel waits for them explicitly (vmcnt) before a barrier.
+__device__ __forceinline__ void dma16(const void* src, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(src), "s"(lds)
+                 : "memory", "m0");
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// Work-group barrier without a memory fence.  __syncthreads() would also
+// drain every outstanding global load, including the direct-to-LDS loads of
+// the chunks still in flight; the explicit s_waitcnt before each barrier
+// orders exactly the loads that must have landed, and every LDS read of the
+// previous chunk has been consumed by an MFMA before the barrier.  The empty
+// asm statements keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Work-group g -> logical tile: within each block of 32 consecutive
 // work-groups, XCD x (= g mod 8) receives the 4 consecutive logical tiles
 // 4x .. 4x+3.  A permutation of [0, round_up(T, 32)).
@@ -73,6 +100,12 @@ __device__ __forceinline__ int xcd_remap(int g) {
 }
 
 constexpr int kMaskVec = 4 * 128;                // uint4 per chunk: 4 waves x 128 split rows
+// s_waitcnt operand: at most 10 vector-memory operations outstanding (one
+// chunk's direct-to-LDS loads of a wave: 8 of Z, 2 of masks), no wait on
+// export or LDS counters (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt
+// [6:4], lgkmcnt [11:8])
+constexpr int kChunkLoads = 10;
+constexpr int kWaitOneChunk = (kChunkLoads & 0xf) | ((kChunkLoads >> 4) << 14) | (0x7 << 4) | (0xf << 8);
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
@@ -85,8 +118,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // buffer never feeds a read of the other
     __shared__ uint4 lds0[kChunkVec];
     __shared__ uint4 lds1[kChunkVec];
+    __shared__ uint4 lds2[kChunkVec];
     __shared__ uint4 msk0[kMaskVec];
     __shared__ uint4 msk1[kMaskVec];
+    __shared__ uint4 msk2[kMaskVec];
     __shared__ uint2 lut[16];
     const int L = xcd_remap(blockIdx.x);
     if (L >= ntile_total) return;
@@ -143,22 +178,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const uint4* zsrc = ((8 * wave) / kOct ? zlo : zhi) + (oct0 + (8 * wave) % kOct) * d_pad + d0;
     auto issue = [&](int ch, uint4* dst, uint4* mdst) {
         const uint4* base = zsrc + ch * chunk_stride;  // wave-uniform
+        const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(dst + 8 * wave * kDSlot));
+        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(mdst + wave * 128));
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void*)(base + k * d_pad + lane),
-                (__attribute__((address_space(3))) void*)(dst + (8 * wave + k) * kDSlot), 16, 0, 0);
-        }
+        for (int k = 0; k < 8; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            __builtin_amdgcn_global_load_lds(
-                (const __attribute__((address_space(1))) void*)(mload[k] + ch),
-                (__attribute__((address_space(3))) void*)(mdst + wave * 128 + 64 * k), 16, 0, 0);
+        for (int k = 0; k < 2; ++k) dma16(mload[k] + ch, ml + 16 * 64 * k);
     };
 
+    // three buffers: chunks ch+1 and ch+2 are in flight while ch is multiplied.
+    // A load is issued in every step (past the end, the last chunk again into
+    // the free buffer, never read), so one constant wait fits every step.
+    const int last = nchunk - 1;
     issue(0, lds0, msk0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    issue(last < 1 ? last : 1, lds1, msk1);
+    __builtin_amdgcn_s_waitcnt(kWaitOneChunk);  // chunk 0 landed, chunk 1 may not have
+    __syncthreads();  // also publishes the nibble table
 
     f32x16 acc[2][4];
 #pragma unroll
@@ -169,8 +204,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
     // one chunk: stream chunk ch+1 into (nxt, mnxt) while multiplying (cur, mcur)
+    // multiply chunk ch from (cur, mcur) while chunk ch+2 streams into
+    // (nxt, mnxt), the buffer every wave finished reading in the previous step
     auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
-        if (ch + 1 < nchunk) issue(ch + 1, nxt, mnxt);
+        issue(ch + 2 < last ? ch + 2 : last, nxt, mnxt);
         // this chunk's mask words of the lane's 4 splits (16-byte rows: a
         // conflict-free 128-bit read per split), group flip and validity applied once
         uint4 mw[4];
@@ -219,15 +256,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 }
             }
         }
-        // the next chunk's LDS writes have landed; every wave is done reading
-        // (cur, mcur) before they are refilled
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        // chunk ch+1 has landed (this wave's loads, then every wave's through
+        // the barrier), chunk ch+2 may still be in flight; every wave is done
+        // reading (cur, mcur) before the next step refills them
+        __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+        lds_barrier();
     };
-    for (int ch = 0; ch < nchunk; ch += 2) {
-        step(ch, lds0, msk0, lds1, msk1);
+    for (int ch = 0; ch < nchunk; ch += 3) {
+        step(ch, lds0, msk0, lds2, msk2);
         if (ch + 1 < nchunk) step(ch + 1, lds1, msk1, lds0, msk0);
+        if (ch + 2 < nchunk) step(ch + 2, lds2, msk2, lds1, msk1);
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the loads past the end
 
     // epilogue: squared norms of sigma_small and t - sigma_small over the slice
     const float* tp = t32 + (int64_t)grp.pair * d_pad + d0;

@@ -91,6 +91,7 @@ struct PairState {
 struct PairCount {
     unsigned long long count;
     unsigned long long n_recheck;
+    double sum_dt, sum_dt2;  // sums of T_b - T_obs and of its square, block by block
 };
 
 // ---------------------------------------------------------------------------
@@ -129,15 +130,18 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active): a
+// Kogge-Stone scan inside each row of 16 lanes by DPP row shifts, then the
+// row totals carried across rows by row broadcasts of lanes 15 and 31.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (l >= o) x += y;
-    }
-    return x;
+    int v = (int)x;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
+    return (uint32_t)v;
 }
 
 // Round-to-nearest-even float -> bfloat16 bits.

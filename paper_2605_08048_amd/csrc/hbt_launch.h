@@ -30,6 +30,15 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
                            hipStream_t s);
 // Reflect X rows, write Z in the precision's storage format, the FP64
 // coefficients 2 (v.x_i) / (v.v) and zero padding.
+// 16-byte-load variants for FP32 rows with d % 4 == 0 and d_pad <= 1024 (the
+// caller also checks that every X, Y is 16-byte aligned).
+bool vector_rows_ok(int input_dtype, int d, int d_pad);
+hipError_t launch_colsum_vec(const PairDesc* pairs, const SumChunk* chunks, int nchunks, int d,
+                             int d_pad, double* partial, hipStream_t s);
+hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
+                              int64_t total_octets, const PairState* st, const double* v, int d,
+                              int d_pad, double* coef, void* zstore, int64_t zplane_elems,
+                              float* z32, hipStream_t s);
 hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs, int npairs,
                           int64_t total_octets, const PairState* st, const double* v, int d,
                           int d_pad, double* coef, void* zstore, int64_t zplane_elems,
@@ -40,9 +49,9 @@ hipError_t launch_reflect_out(int input_dtype, const PairDesc* pair, const PairS
                               hipStream_t s);
 
 // --- random splits ------------------------------------------------------
-// LDS bytes one split row needs for pairs of up to max_np pooled rows, and
-// the device's limit per work-group.
-size_t split_lds_per_wave(int max_np);
+// LDS bytes a work-group of the split kernel (four split rows) needs for
+// pairs of up to max_np pooled rows, and the device's limit per work-group.
+size_t split_lds_per_block(int max_np);
 size_t split_lds_limit();
 hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
@@ -83,14 +92,33 @@ hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const Gem
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int d, int gd,
                        int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
-                       bool T_f64,
+                       bool T_f64, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
 hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
                           int npairs, const PairState* st, const double* v, const double* t64,
                           const double* coef,
                           const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
                           int64_t max_flags, int d, int gd, int alternative, PairCount* cnt,
+                          double* Tw, hipStream_t s);
+// Sums of T_b - T_obs and its square per pair over the current block (Tw
+// holds the block's final T_b, recheck applied).
+hipError_t launch_moments(int npairs, const BlockPair* bp, const PairState* st, const double* Tw,
+                          PairCount* cnt, hipStream_t s);
+// --- permutation-budget allocator ---------------------------------------
+size_t mlp_train_ws_bytes(int64_t rows);
+hipError_t launch_features(int64_t npairs, const hbt_result* res, int d, int gd, float* feat,
+                           hipStream_t s);
+hipError_t launch_feature_norm(int64_t rows, const float* feat, float* theta, hipStream_t s);
+hipError_t launch_mlp_forward(int64_t rows, const float* feat, const float* theta, float* out,
+                              hipStream_t s);
+hipError_t launch_mlp_grad(int64_t rows, const float* feat, const float* target, const float* theta,
+                           float* grad, double* loss, void* ws, hipStream_t s);
+hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_budgets(int64_t npairs, const float* out, const hbt_result* res, double lo,
+                          double hi, int64_t bmin, int64_t bmax, double zq, int64_t* budget,
                           hipStream_t s);
+
 hipError_t launch_final(int npairs, const PairState* st, const PairCount* cnt,
                         const int64_t* Btot, hbt_result* res, hipStream_t s);
 

@@ -20,65 +20,115 @@ __device__ __forceinline__ uint32_t word_of(uint4 w, int k) {
     return k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
 }
 
-// Per-wave LDS carve-up (bytes), for pairs with up to max_np pooled rows.
+// Per-wave LDS carve-up (bytes), for pairs with up to max_np pooled rows:
+// the 256-bin histogram, the bucket items (index, secondary key) and the
+// split's mask row.
+// (The 256-bin histograms live in a static array, one per wave, so that a
+// bin's LDS address is the key times 4 plus a constant.)
 struct SplitLds {
-    int keys, hist, mlds, cidx, ckey, total;
+    int cidx, ckey, mlds, total;
     __host__ __device__ SplitLds(int max_np) {
-        keys = 0;
-        hist = max_np;
-        mlds = hist + 1024;
-        cidx = mlds + max_np / 8;
+        cidx = 0;
         ckey = cidx + 4 * kCandCap;
-        total = ckey + 4 * kCandCap;
+        mlds = ckey + 4 * kCandCap;
+        total = mlds + max_np / 8;
     }
 };
+constexpr int kSplitWaves = 4;          // waves (split rows) per work-group
+constexpr int kSplitStaticLds = kSplitWaves * 1024;
 
+// hist[key] += 1 for the 16 keys of a block; W, the wave, is a constant so the
+// wave's histogram offset folds into the LDS instruction.
+template <int W>
+__device__ __forceinline__ void count_block(uint32_t (*hist)[256], uint4 w) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) atomicAdd(&hist[W][(word_of(w, j >> 2) >> (8 * (j & 3))) & 0xffu], 1u);
+}
+
+// Philox block c of split b: the primary keys of items 16c .. 16c+15 as 16
+// little-endian bytes.  Items at or past N get the key 0xFF; they are removed
+// from the histogram's top bin afterwards and never enter group 1.
+__device__ __forceinline__ uint4 primary_block(int c, int N, uint32_t b, uint32_t pair,
+                                               uint32_t k0, uint32_t k1) {
+    uint4 w = philox4x32_10(make_uint4((uint32_t)c, b, pair, 0u), k0, k1);
+    const int lim = N - 16 * c;
+    if (lim < 16) {
+        auto fill = [&](uint32_t x, int base) {
+            const int v = lim - base;
+            return v >= 4 ? x : v <= 0 ? 0xffffffffu : x | (0xffffffffu << (8 * v));
+        };
+        w = make_uint4(fill(w.x, 0), fill(w.y, 4), fill(w.z, 8), fill(w.w, 12));
+    }
+    return w;
+}
+
+// One wave per split row.  R > 0: each lane keeps its (at most R) Philox
+// blocks in registers between the histogram and the classification pass
+// (pairs with N <= 1024 R); R == 0: the blocks are generated again.
+template <int R>
 __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict__ pairs,
                                                      const BlockPair* __restrict__ bp, int npairs,
                                                      int64_t rows, int max_np, uint32_t key0,
                                                      uint32_t key1, uint32_t* __restrict__ mask,
                                                      PairState* st) {
+    __shared__ uint32_t hist_all[kSplitWaves][256];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const SplitLds L(max_np);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * kSplitWaves + wave;
     if (row >= rows) return;
     unsigned char* base = smem + wave * L.total;
-    unsigned char* keys = base + L.keys;
-    uint32_t* hist = (uint32_t*)(base + L.hist);
-    uint32_t* mlds = (uint32_t*)(base + L.mlds);
+    uint32_t* hist = hist_all[wave];
     uint32_t* cidx = (uint32_t*)(base + L.cidx);
     uint32_t* ckey = (uint32_t*)(base + L.ckey);
+    uint32_t* mlds = (uint32_t*)(base + L.mlds);
 
     const int p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
     const PairDesc pd = pairs[p];
     const uint32_t b = bp[p].perm_base + (uint32_t)(row - bp[p].mrow0);
     const int N = pd.n + pd.m, n = pd.n;
+    const int nc = (N + 15) >> 4;       // Philox blocks holding items
+    const int nw = pd.Np >> 4;          // blocks covering the padded mask row
+    const int niter = (nw + 63) >> 6;   // wave-uniform
 
-    for (int j = lane; j < 256; j += 64) hist[j] = 0;
+    ((uint4*)hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
     wave_sync();
-    // 1. primary keys: 16 per Philox block; histogram of their values
-    const int nc = (N + 15) >> 4;
-    for (int c = lane; c < nc; c += 64) {
-        const uint4 w = philox4x32_10(make_uint4((uint32_t)c, b, pd.pair_index, 0u), key0, key1);
-        ((uint4*)keys)[c] = w;
-        const int lim = N - 16 * c;
+    // 1. primary keys and their histogram
+    constexpr int RK = R > 0 ? R : 1;
+    uint4 key[RK];
+    auto gen_count = [&](int k) {
+        const int c = 64 * k + lane;
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (c < nc) {
+            w = primary_block(c, N, b, pd.pair_index, key0, key1);
+            switch (wave) {  // wave-uniform
+                case 0: count_block<0>(hist_all, w); break;
+                case 1: count_block<1>(hist_all, w); break;
+                case 2: count_block<2>(hist_all, w); break;
+                default: count_block<3>(hist_all, w); break;
+            }
+        }
+        return w;
+    };
+    if constexpr (R > 0) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (j < lim) atomicAdd(&hist[(word_of(w, j >> 2) >> (8 * (j & 3))) & 0xffu], 1u);
+        for (int k = 0; k < R; ++k) key[k] = k < niter ? gen_count(k) : make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int k = 0; k < niter; ++k) (void)gen_count(k);
     }
     wave_sync();
-    // 2. theta = the byte value holding rank n-1 (0-based); below = #{P < theta}
+    // 2. theta = the byte value holding rank n-1 (0-based); below = #{P < theta};
+    //    the padding keys are taken out of bin 255 first
     uint32_t h[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) h[j] = hist[4 * lane + j];
+    if (lane == 63) h[3] -= (uint32_t)(16 * nc - N);
     const uint32_t sum = h[0] + h[1] + h[2] + h[3];
     const uint32_t incl = wave_incl_scan(sum);
     const uint32_t excl = incl - sum;
     const bool owner = excl < (uint32_t)n && (uint32_t)n <= incl;
-    uint32_t theta = 0, below = 0;
+    uint32_t theta = 0, below = 0, bucket = 0;
     if (owner) {
-        // the first bin (from the left) where the running count reaches n
         uint32_t acc = excl;
         bool found = false;
 #pragma unroll
@@ -86,6 +136,7 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
             if (!found && acc + h[j] >= (uint32_t)n) {
                 theta = 4 * lane + j;
                 below = acc;
+                bucket = h[j];
                 found = true;
             }
             acc += h[j];
@@ -93,44 +144,67 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
     }
     const uint64_t own = __ballot(owner);
     const int src = __ffsll((unsigned long long)own) - 1;
-    theta = __shfl(theta, src, 64);
-    below = __shfl(below, src, 64);
+    theta = __builtin_amdgcn_readlane(theta, src);
+    below = __builtin_amdgcn_readlane(below, src);
+    bucket = __builtin_amdgcn_readlane(bucket, src);
     const uint32_t need = (uint32_t)n - below;
-    // 3. one pass over the keys: bits of P < theta, and the bucket P == theta.
-    //    Four independent byte reads per lane per iteration (items i0 + l + 64 t)
-    //    keep several LDS reads in flight; each ballot is one 64-item mask slice.
-    uint32_t cnt = 0;
-    for (int i0 = 0; i0 < pd.Np; i0 += 256) {
-        uint32_t P[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int i = i0 + 64 * t + lane;
-            P[t] = i < pd.Np ? (uint32_t)keys[i] : 0u;
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int ib = i0 + 64 * t;
-            if (ib >= pd.Np) break;
-            const int i = ib + lane;
-            const bool in = i < N;
-            const uint64_t lt = __ballot(in && P[t] < theta);
-            const uint64_t eq = __ballot(in && P[t] == theta);
-            if (lane == 0) {
-                mlds[ib >> 5] = (uint32_t)lt;
-                mlds[(ib >> 5) + 1] = (uint32_t)(lt >> 32);
-            }
-            if (in && P[t] == theta) {
-                const uint32_t pos = cnt + mbcnt64(eq);
-                if (pos < (uint32_t)kCandCap) cidx[pos] = (uint32_t)i;
-            }
-            cnt += (uint32_t)__popcll((unsigned long long)eq);
-        }
-    }
-    if (cnt > (uint32_t)kCandCap) {
+    if (bucket > (uint32_t)kCandCap) {  // not seen in practice (expected size N / 256)
         if (lane == 0) atomicExch(&st[p].status, (int)HBT_ERR_INTERNAL);
-        cnt = kCandCap;
+        uint32_t* out = const_cast<uint32_t*>(mask_row(mask, bp[p], row, pd.Wp));
+        for (int w = lane; w < pd.Wp; w += 64) out[w] = 0u;  // an empty group: nothing to gather
+        return;
+    }
+    // 3. classification: each lane builds the 16 bits "P < theta" of its
+    //    block, two neighbouring lanes form one 32-bit mask word; blocks that
+    //    hold a byte equal to theta (a few per split) list those items
+    const uint32_t theta4 = theta * 0x01010101u;
+    uint32_t cbase = 0;  // bucket items listed so far (wave-uniform)
+    auto classify = [&](int k, uint4 w) {
+        const int c = 64 * k + lane;
+        uint32_t lt = 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            lt |= (uint32_t)(((word_of(w, j >> 2) >> (8 * (j & 3))) & 0xffu) < theta) << j;
+        // bit 7 of each byte equal to theta (exact), gathered into one word:
+        // bit 8 b + q marks item 4 q + b of the block
+        uint32_t eq = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = word_of(w, q) ^ theta4;
+            const uint32_t z = ~(((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u;
+            eq |= z >> (7 - q);
+        }
+        if (c >= nc) {
+            lt = 0u;
+            eq = 0u;
+        } else if (16 * c + 16 > N) {  // tail block: drop the padding items (keys 0xFF)
+            for (int j = N - 16 * c; j < 16; ++j) eq &= ~(1u << (8 * (j & 3) + (j >> 2)));
+        }
+        const uint32_t ne = (uint32_t)__popc(eq);
+        const uint32_t incl = wave_incl_scan(ne);
+        uint32_t pos = cbase + incl - ne;
+        cbase += __builtin_amdgcn_readlane(incl, 63);
+        while (eq) {
+            const int t = __ffs(eq) - 1;
+            cidx[pos++] = (uint32_t)(16 * c + 4 * (t & 7) + (t >> 3));
+            eq &= eq - 1u;
+        }
+        // lane ^ 1's bits (quad_perm [1,0,3,2])
+        const uint32_t nb = (uint32_t)__builtin_amdgcn_mov_dpp((int)lt, 0xB1, 0xF, 0xF, false);
+        if (!(lane & 1) && c < nw) mlds[c >> 1] = lt | (nb << 16);
+    };
+    if constexpr (R > 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (k < niter) classify(k, key[k]);  // wave-uniform
+    } else {
+        for (int k = 0; k < niter; ++k) {
+            const int c = 64 * k + lane;
+            classify(k, c < nc ? primary_block(c, N, b, pd.pair_index, key0, key1) : make_uint4(0u, 0u, 0u, 0u));
+        }
     }
     wave_sync();
+    const uint32_t cnt = bucket;
     // 4. secondary keys of the bucket items; 5. the `need` bucket items first in
     //    (S, i) order join group 1.  With at most 64 bucket items (the usual
     //    case: about N / 256) each lane holds one and ranks it against the
@@ -184,22 +258,29 @@ size_t split_lds_limit() {
     return lim;
 }
 
-size_t split_lds_per_wave(int max_np) { return (size_t)SplitLds(max_np).total; }
+size_t split_lds_per_block(int max_np) { return (size_t)kSplitWaves * SplitLds(max_np).total + kSplitStaticLds; }
 
 hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
                               PairState* st, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     const SplitLds L(max_np);
-    // at most 64 KB of LDS per work-group
-    const size_t cap = split_lds_limit() < 65536 ? split_lds_limit() : 65536;
-    int waves = (int)(cap / (size_t)L.total);
-    if (waves > 4) waves = 4;
-    if (waves < 1) return hipErrorInvalidValue;
-    const size_t lds = (size_t)waves * L.total;
-    hipLaunchKernelGGL(k_split_masks, dim3((unsigned)((rows + waves - 1) / waves)), dim3(64 * waves),
-                       lds, s, pairs,
-                       bp, npairs, rows, max_np, (uint32_t)seed, (uint32_t)(seed >> 32), mask, st);
+    // four split rows per work-group; at most 64 KB of LDS per work-group
+    const size_t lds = (size_t)kSplitWaves * L.total;
+    if (lds + kSplitStaticLds > 65536 || lds + kSplitStaticLds > split_lds_limit()) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((rows + kSplitWaves - 1) / kSplitWaves)), block(64 * kSplitWaves);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    // registers for the keys of the largest pair: R blocks of 16 per lane
+    const int r = (max_np + 1023) / 1024;
+#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, pairs, bp, npairs, rows, max_np, k0, k1, mask, st)
+    if (r <= 1) HBT_SPLIT(1);
+    else if (r <= 2) HBT_SPLIT(2);
+    else if (r <= 4) HBT_SPLIT(4);
+    else if (r <= 8) HBT_SPLIT(8);
+    else if (r <= 12) HBT_SPLIT(12);
+    else if (r <= 16) HBT_SPLIT(16);
+    else HBT_SPLIT(0);
+#undef HBT_SPLIT
     return hipGetLastError();
 }
 

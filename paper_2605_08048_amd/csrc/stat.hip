@@ -16,7 +16,7 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               const double* __restrict__ partial, int nslot, int d,
                                               int gd, int alternative, double e_acc,
                                               double e_store, int no_recheck, void* T_out,
-                                              bool T_f64,
+                                              bool T_f64, double* __restrict__ Tw,
                                               PairCount* cnt, uint32_t* flags, uint32_t* nflag) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = row < rows;
@@ -43,6 +43,7 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
             if (T_f64) ((double*)T_out)[row] = T;
             else ((float*)T_out)[row] = (float)T;
         }
+        Tw[row] = T;
         const bool two = alternative == HBT_ALT_TWO_SIDED;
         const double val = two ? fabs(T) : T;
         const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
@@ -73,13 +74,13 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int d, int gd,
                        int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
-                       bool T_f64, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
+                       bool T_f64, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
                        hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
                        npairs, rows, st, partial, nslot, d, gd, alternative, e_acc, e_store,
                        no_recheck,
-                       T_out, T_f64, cnt, flags, nflag);
+                       T_out, T_f64, Tw, cnt, flags, nflag);
     return hipGetLastError();
 }
 
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(64 * kRecheckWaves) void k_recheck(
     const double* __restrict__ t64, const double* __restrict__ coef,
     const uint32_t* __restrict__ mask, const uint32_t* __restrict__ flags,
     const uint32_t* __restrict__ nflag, int d, int d_pad, int gd, int alternative,
-    PairCount* cnt) {
+    PairCount* cnt, double* __restrict__ Tw) {
     constexpr int kU = 12;                 // columns per lane per pass (768 per pass)
     constexpr int kPass = 64 * kU;
     constexpr int kRows = 4;               // rows in flight per wave
@@ -222,6 +223,7 @@ __global__ __launch_bounds__(64 * kRecheckWaves) void k_recheck(
             const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
             if (T != T || val >= thr) atomicAdd(&cnt[p].count, 1ull);
             atomicAdd(&cnt[p].n_recheck, 1ull);
+            Tw[row] = T;
         }
         __syncthreads();
     }
@@ -231,16 +233,55 @@ hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPai
                           int npairs, const PairState* st, const double* v, const double* t64,
                           const double* coef, const uint32_t* mask, const uint32_t* flags,
                           const uint32_t* nflag, int64_t max_flags, int d, int gd, int alternative,
-                          PairCount* cnt, hipStream_t s) {
+                          PairCount* cnt, double* Tw, hipStream_t s) {
     if (max_flags <= 0) return hipSuccess;
     const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
     int64_t g = max_flags < 2048 ? max_flags : 2048;
     if (input_dtype == HBT_IN_F64)
         hipLaunchKernelGGL(k_recheck<double>, dim3((unsigned)g), dim3(64 * kRecheckWaves), 0, s, pairs, bp, npairs,
-                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
+                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt, Tw);
     else
         hipLaunchKernelGGL(k_recheck<float>, dim3((unsigned)g), dim3(64 * kRecheckWaves), 0, s, pairs, bp, npairs,
-                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt);
+                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt, Tw);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// null moments: sums of T_b - T_obs and (T_b - T_obs)^2 over a block's splits,
+// one work-group per pair, in a fixed order; blocks add in stream order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_moments(const BlockPair* __restrict__ bp,
+                                                 const PairState* __restrict__ st,
+                                                 const double* __restrict__ Tw, PairCount* cnt) {
+    __shared__ double r1[256], r2[256];
+    const int p = blockIdx.x;
+    const BlockPair q = bp[p];
+    const double c = st[p].t_obs;
+    double a = 0.0, b = 0.0;
+    for (int64_t k = threadIdx.x; k < q.nb; k += 256) {
+        const double x = Tw[q.mrow0 + k] - c;
+        a += x;
+        b += x * x;
+    }
+    r1[threadIdx.x] = a;
+    r2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+            r2[threadIdx.x] += r2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[p].sum_dt += r1[0];
+        cnt[p].sum_dt2 += r2[0];
+    }
+}
+
+hipError_t launch_moments(int npairs, const BlockPair* bp, const PairState* st, const double* Tw,
+                          PairCount* cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments, dim3(npairs), dim3(256), 0, s, bp, st, Tw, cnt);
     return hipGetLastError();
 }
 
@@ -258,6 +299,10 @@ __global__ void k_final(int npairs, const PairState* __restrict__ st,
     r.n_recheck = (int64_t)cnt[p].n_recheck;
     r.B = Btot[p];
     r.p = (1.0 + (double)r.count) / ((double)r.B + 1.0);
+    const double mean = cnt[p].sum_dt / (double)r.B;
+    const double var = cnt[p].sum_dt2 / (double)r.B - mean * mean;
+    r.t_mean = q.t_obs + mean;
+    r.t_sd = var != var ? var : sqrt(var > 0.0 ? var : 0.0);
     r.status = q.status;
     res[p] = r;
 }

@@ -9,11 +9,13 @@ the built library every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from pathlib import Path
 
 import numpy as np
 
-LIB_PATH = Path(__file__).resolve().parent / "libhbt.so"
+# HBT_LIBRARY names another build of the same library (for A/B timing)
+LIB_PATH = Path(os.environ.get("HBT_LIBRARY") or Path(__file__).resolve().parent / "libhbt.so")
 
 OK, ERR_ARG, ERR_SIZE, ERR_DTYPE, ERR_WORKSPACE, ERR_DEGENERATE, ERR_MASK, ERR_DEVICE, \
     ERR_UNSUPPORTED, ERR_INTERNAL = range(10)
@@ -28,8 +30,9 @@ MAX_N, MAX_D = 65536, 8192
 
 class HbtResult(C.Structure):
     _fields_ = [("t_obs", C.c_double), ("r_x", C.c_double), ("r_y", C.c_double), ("p", C.c_double),
-                ("tau", C.c_double), ("count", C.c_int64), ("B", C.c_int64), ("n_recheck", C.c_int64),
-                ("status", C.c_int32), ("h_identity", C.c_int32)]
+                ("tau", C.c_double), ("mu_cos", C.c_double), ("t_mean", C.c_double), ("t_sd", C.c_double),
+                ("count", C.c_int64), ("B", C.c_int64), ("n_recheck", C.c_int64), ("n", C.c_int64),
+                ("m", C.c_int64), ("status", C.c_int32), ("h_identity", C.c_int32)]
 
 
 class HbtPermParams(C.Structure):
@@ -40,12 +43,14 @@ class HbtPermParams(C.Structure):
                 ("flags", C.c_int32), ("block_perms", C.c_int64), ("masks", C.c_void_p)]
 
 
-assert C.sizeof(HbtResult) == 72 and C.sizeof(HbtPermParams) == 96
+RESULT_BYTES = 112
+assert C.sizeof(HbtResult) == RESULT_BYTES and C.sizeof(HbtPermParams) == 96
 
 RESULT_DTYPE = np.dtype([("t_obs", "f8"), ("r_x", "f8"), ("r_y", "f8"), ("p", "f8"), ("tau", "f8"),
-                         ("count", "i8"), ("B", "i8"), ("n_recheck", "i8"), ("status", "i4"),
-                         ("h_identity", "i4")])
-assert RESULT_DTYPE.itemsize == 72
+                         ("mu_cos", "f8"), ("t_mean", "f8"), ("t_sd", "f8"),
+                         ("count", "i8"), ("B", "i8"), ("n_recheck", "i8"), ("n", "i8"), ("m", "i8"),
+                         ("status", "i4"), ("h_identity", "i4")])
+assert RESULT_DTYPE.itemsize == RESULT_BYTES
 
 
 class HbtError(RuntimeError):
@@ -167,7 +172,7 @@ def align(X, Y, *, align=True, gd="banerjee", out=None, stream=None):
     X = X.contiguous()
     Xo = out if out is not None else torch.empty_like(X)
     v = torch.empty(d, dtype=torch.float64, device=dev)
-    res = torch.zeros(72, dtype=torch.uint8, device=dev)
+    res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=dev)
     L = lib()
     need = L.hbt_align_workspace_size(n, m, d)
     ws = workspace(need, dev)
@@ -208,7 +213,7 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     if need == 0:
         need = 256
     ws = workspace(need, dev)
-    res = torch.zeros(72, dtype=torch.uint8, device=dev)
+    res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=dev)
     T = torch.empty(B, dtype=torch.float64 if t64 else torch.float32, device=dev) if want_T else None
     mo = torch.empty((B, W), dtype=torch.int32, device=dev) if want_masks else None
     _check(L.hbt_perm_test(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), C.byref(prm),
@@ -225,12 +230,25 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     return r
 
 
+def batched_workspace_size(row_offset, n, m, B, d, *, precision="bf16x2", input_dtype="f32"):
+    """Workspace bytes of one ``perm_test_batched`` call of these shapes."""
+    P = len(n)
+    nn = np.ascontiguousarray(n, dtype=np.int64)
+    mm = np.ascontiguousarray(m, dtype=np.int64)
+    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
+    prm = make_params(0, 0, d, 0, precision=precision, input_dtype={"f32": 0, "f64": 1}[input_dtype])
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    return int(lib().hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm)))
+
+
 def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair_index=None,
                       precision="bf16x2", gd="banerjee", alternative="greater", align=True, recheck=True,
-                      stream=None, sync=True, results=None):
+                      stream=None, sync=True, results=None, workspace=None):
     """Many pairs in one call.  Z_all (device tensor) holds rows X_0, Y_0, X_1, ...;
     row_offset/n/m/B are host integer arrays.  Returns a numpy structured array
-    of hbt_result (or, with sync=False, the device result tensor)."""
+    of hbt_result (or, with sync=False, the device result tensor).  A caller
+    that captures the call into a graph passes its own ``workspace`` (a uint8
+    device tensor that outlives the graph) instead of the shared cached one."""
     torch = _torch()
     dev = Z_all.device
     Z_all = Z_all.contiguous()
@@ -247,8 +265,13 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
     L = lib()
     ptr = lambda a: a.ctypes.data_as(C.c_void_p)
     need = L.hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm))
-    ws = workspace(max(need, 256), dev)
-    res = results if results is not None else torch.zeros(72 * P, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        ws = globals()["workspace"](max(need, 256), dev)
+    else:
+        ws = workspace
+        if ws.numel() < need:
+            raise ValueError(f"workspace of {ws.numel()} bytes, the call needs {need}")
+    res = results if results is not None else torch.zeros(RESULT_BYTES * P, dtype=torch.uint8, device=dev)
     _check(L.hbt_perm_test_batched(P, C.c_void_p(Z_all.data_ptr()), ptr(off), ptr(nn), ptr(mm), ptr(BB),
                                    None if ids is None else ptr(ids), d, C.byref(prm),
                                    C.c_void_p(res.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),

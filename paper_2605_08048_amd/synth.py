@@ -7,21 +7,22 @@ and projects each row onto the unit sphere, the normalisation the paper
 applies to every token embedding before testing (Sec. 3.1, Eq. 2).
 
 Every array is reproducible from integers alone:
-``numpy.random.default_rng(SeedSequence([config_id, pair, side]))``.
+``numpy.random.default_rng(SeedSequence([stream, pair, side]))``, with one
+stream number per workload.
 
 Workloads (stand-ins for BERT-family token embeddings of corpus words, which
 are not available here; shapes follow the paper's d = 768 / 1024 encoders and
 its B = 5,000 ... 20,000 permutation budgets):
 
-* config 1 - one pair, d=64, n=50, m=60, diagonal noise lambda_i ~ 1/i
+* small_pair_f64 (stream 1) - one pair, d=64, n=50, m=60, diagonal noise lambda_i ~ 1/i
   (trace 1), kappa = 3, independent mean directions, FP64.
-* config 2 - one pair, d=768, n=2000, m=1500, low-rank noise, kappa 2.0/2.4,
+* pair_d768 (stream 2) - one pair, d=768, n=2000, m=1500, low-rank noise, kappa 2.0/2.4,
   means 40 degrees apart, FP32.
-* config 3 - one pair, d=1024, n=3000, m=2000, low-rank noise, equal
+* null_pair_d1024 (stream 3) - one pair, d=1024, n=3000, m=2000, low-rank noise, equal
   kappa = 2.2 (null), FP32 input for the split-BF16 path.
-* config 4 - 512 pairs, d=768, n_p and m_p log-uniform on [20, 5000],
+* batch_512_d768 (stream 4) - 512 pairs, d=768, n_p and m_p log-uniform on [20, 5000],
   kappa ~ U[1.5, 3.0], half the pairs null, random mean directions.
-* config 5 - 4096 pairs, d=768, n and m log-uniform on [20, 2000].
+* budget_batch_4096 (stream 5) - 4096 pairs, d=768, n and m log-uniform on [20, 2000].
 """
 from __future__ import annotations
 
@@ -34,13 +35,13 @@ import numpy as np
 
 __all__ = [
     "rng_for", "unit_rows", "random_unit", "direction_at_angle", "lowrank_factor",
-    "cloud_diag", "cloud_lowrank", "Pair", "Batch", "config1", "config2", "config3",
-    "config4", "config5", "pack_batch", "log_uniform_int",
+    "cloud_diag", "cloud_lowrank", "Pair", "Batch", "small_pair_f64", "pair_d768", "null_pair_d1024",
+    "batch_512_d768", "budget_batch_4096", "pack_batch", "log_uniform_int",
 ]
 
 
-def rng_for(config_id: int, pair: int = 0, side: int = 0) -> np.random.Generator:
-    return np.random.default_rng(np.random.SeedSequence([int(config_id), int(pair), int(side)]))
+def rng_for(stream: int, pair: int = 0, side: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(stream), int(pair), int(side)]))
 
 
 def unit_rows(a: np.ndarray) -> np.ndarray:
@@ -110,7 +111,7 @@ class Pair:
         return self.X.shape[1]
 
 
-def config1() -> Pair:
+def small_pair_f64() -> Pair:
     d, n, m = 64, 50, 60
     lam = 1.0 / np.arange(1, d + 1)
     lam /= lam.sum()
@@ -118,29 +119,29 @@ def config1() -> Pair:
     mu_b = random_unit(rng_for(1, 0, 11), d)
     X = cloud_diag(rng_for(1, 0, 0), n, d, 3.0, mu_a, lam)
     Y = cloud_diag(rng_for(1, 0, 1), m, d, 3.0, mu_b, lam)
-    return Pair(X, Y, B=999, seed=0, meta=dict(config=1, dtype="f64"))
+    return Pair(X, Y, B=999, seed=0, meta=dict(workload="small_pair_f64", dtype="f64"))
 
 
-def _lowrank_pair(cfg, pair, n, m, d, kappa_a, kappa_b, angle=None, factor=None):
+def _lowrank_pair(stream, pair, n, m, d, kappa_a, kappa_b, angle=None, factor=None):
     factor = factor if factor is not None else lowrank_factor(d)
-    mu_a = random_unit(rng_for(cfg, pair, 10), d)
+    mu_a = random_unit(rng_for(stream, pair, 10), d)
     if angle is None:
-        mu_b = random_unit(rng_for(cfg, pair, 11), d)
+        mu_b = random_unit(rng_for(stream, pair, 11), d)
     else:
-        mu_b = direction_at_angle(rng_for(cfg, pair, 11), mu_a, angle)
-    X = cloud_lowrank(rng_for(cfg, pair, 0), n, d, kappa_a, mu_a, factor)
-    Y = cloud_lowrank(rng_for(cfg, pair, 1), m, d, kappa_b, mu_b, factor)
+        mu_b = direction_at_angle(rng_for(stream, pair, 11), mu_a, angle)
+    X = cloud_lowrank(rng_for(stream, pair, 0), n, d, kappa_a, mu_a, factor)
+    Y = cloud_lowrank(rng_for(stream, pair, 1), m, d, kappa_b, mu_b, factor)
     return X.astype(np.float32), Y.astype(np.float32)
 
 
-def config2(n=2000, m=1500, d=768, B=10000) -> Pair:
+def pair_d768(n=2000, m=1500, d=768, B=10000) -> Pair:
     X, Y = _lowrank_pair(2, 0, n, m, d, 2.0, 2.4, angle=40.0)
-    return Pair(X, Y, B=B, seed=0, meta=dict(config=2, dtype="f32"))
+    return Pair(X, Y, B=B, seed=0, meta=dict(workload="pair_d768", dtype="f32"))
 
 
-def config3(n=3000, m=2000, d=1024, B=20000) -> Pair:
+def null_pair_d1024(n=3000, m=2000, d=1024, B=20000) -> Pair:
     X, Y = _lowrank_pair(3, 0, n, m, d, 2.2, 2.2, angle=40.0)
-    return Pair(X, Y, B=B, seed=0, meta=dict(config=3, dtype="f32"))
+    return Pair(X, Y, B=B, seed=0, meta=dict(workload="null_pair_d1024", dtype="f32"))
 
 
 def log_uniform_int(rng, lo, hi, size=None):
@@ -191,8 +192,8 @@ def pack_batch(pairs, d, seed=0, meta=None) -> Batch:
     return Batch(Z, off, n, m, B, pair_index=ids, seed=seed, meta=meta or {})
 
 
-def _batch_config(cfg, npairs, d, lo, hi, B, limit=None):
-    g = rng_for(cfg, 0, 99)
+def _batch_workload(stream, npairs, d, lo, hi, B, limit=None):
+    g = rng_for(stream, 0, 99)
     ns = log_uniform_int(g, lo, hi, npairs)
     ms = log_uniform_int(g, lo, hi, npairs)
     ka = g.uniform(1.5, 3.0, npairs)
@@ -203,7 +204,7 @@ def _batch_config(cfg, npairs, d, lo, hi, B, limit=None):
     idx = list(range(npairs) if limit is None else limit)
 
     def one(p):
-        X, Y = _lowrank_pair(cfg, p, int(ns[p]), int(ms[p]), d, float(ka[p]), float(kb[p]),
+        X, Y = _lowrank_pair(stream, p, int(ns[p]), int(ms[p]), d, float(ka[p]), float(kb[p]),
                              angle=None, factor=factor)
         return Pair(X, Y, B=B, seed=0, pair_index=p, meta=dict(null=bool(null[p])))
 
@@ -213,11 +214,11 @@ def _batch_config(cfg, npairs, d, lo, hi, B, limit=None):
     return pairs, dict(kappa_a=ka, kappa_b=kb, null=null, n=ns, m=ms)
 
 
-def config4(npairs=512, d=768, B=2000, limit=None) -> Batch:
-    pairs, info = _batch_config(4, npairs, d, 20, 5000, B, limit)
-    return pack_batch(pairs, d, meta=dict(config=4, **info))
+def batch_512_d768(npairs=512, d=768, B=2000, limit=None) -> Batch:
+    pairs, info = _batch_workload(4, npairs, d, 20, 5000, B, limit)
+    return pack_batch(pairs, d, meta=dict(workload="batch_512_d768", **info))
 
 
-def config5(npairs=4096, d=768, B=20000, limit=None) -> Batch:
-    pairs, info = _batch_config(5, npairs, d, 20, 2000, B, limit)
-    return pack_batch(pairs, d, meta=dict(config=5, **info))
+def budget_batch_4096(npairs=4096, d=768, B=20000, limit=None) -> Batch:
+    pairs, info = _batch_workload(5, npairs, d, 20, 2000, B, limit)
+    return pack_batch(pairs, d, meta=dict(workload="budget_batch_4096", **info))

@@ -30,11 +30,11 @@ def test_library_exports_every_declared_symbol():
     L = hbt.lib()
     missing = [f for f in declared_functions() if not hasattr(L, f)]
     assert not missing, missing
-    assert L.hbt_abi_version() == 1
+    assert L.hbt_abi_version() == 2
 
 
 def test_struct_sizes_match_header():
-    assert C.sizeof(hbt.HbtResult) == 72
+    assert C.sizeof(hbt.HbtResult) == 112
     assert C.sizeof(hbt.HbtPermParams) == 96
     assert hbt.HbtPermParams.masks.offset == 88 and hbt.HbtPermParams.block_perms.offset == 80
 
