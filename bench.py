@@ -86,11 +86,21 @@ def write_traffic(fetch_csv, write_csv, command):
     import csv
     from collections import defaultdict
 
+    def rows(path):
+        """(kernel, counter, value, dispatch) from rocprofv3's CSV or SQLite output."""
+        if str(path).endswith(".db"):
+            import sqlite3
+            q = "select kernel_name, counter_name, value, dispatch_id from counters_collection"
+            yield from sqlite3.connect(path).execute(q)
+        else:
+            for r in csv.DictReader(open(path)):
+                yield r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]), r["Dispatch_Id"]
+
     def per_dispatch(path, counter):
         acc = defaultdict(lambda: defaultdict(float))
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] == counter:
-                acc[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        for kern, name, val, disp in rows(path):
+            if name == counter:
+                acc[kern][disp] += float(val)
         return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
     def pick(d, key):
@@ -157,8 +167,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run the batched path twice and a 1 GiB copy, for rocprofv3 --pmc")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn two rocprofv3 counter CSVs into the committed traffic summary")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH", "WRITE"),
+                    help="turn two rocprofv3 counter outputs (CSV or SQLite) into the committed traffic summary")
     ap.add_argument("--traffic-command", default="", help="the commands that produced the CSVs")
     args = ap.parse_args()
     if args.write_traffic:
