@@ -56,9 +56,9 @@ hipError_t zero(void* dst, size_t bytes, hipStream_t s) {
 // ---------------------------------------------------------------------------
 template <typename Tin>
 __global__ __launch_bounds__(256) void k_colsum(const PairDesc* __restrict__ pairs,
-                                                const SumChunk* __restrict__ chunks, int d,
+                                                int npairs, int d,
                                                 double* __restrict__ partial) {
-    const SumChunk ch = chunks[blockIdx.x];
+    const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
     const PairDesc pd = pairs[ch.pair];
     const Tin* base = (const Tin*)(ch.side ? pd.Y : pd.X);
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -81,14 +81,14 @@ __global__ __launch_bounds__(256) void k_colsum(const PairDesc* __restrict__ pai
         partial[(int64_t)blockIdx.x * d + c] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
-hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, const SumChunk* chunks,
+hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, int npairs,
                          int nchunks, int d, double* partial, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     dim3 grid(nchunks, (d + 63) / 64);
     if (input_dtype == HBT_IN_F64)
-        hipLaunchKernelGGL(k_colsum<double>, grid, dim3(256), 0, s, pairs, chunks, d, partial);
+        hipLaunchKernelGGL(k_colsum<double>, grid, dim3(256), 0, s, pairs, npairs, d, partial);
     else
-        hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, s, pairs, chunks, d, partial);
+        hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, s, pairs, npairs, d, partial);
     return hipGetLastError();
 }
 
@@ -98,10 +98,10 @@ hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, const SumChunk*
 // four waves' sums are added in a fixed order through LDS.
 template <int J>
 __global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pairs,
-                                                 const SumChunk* __restrict__ chunks, int d,
+                                                 int npairs, int d,
                                                  double* __restrict__ partial) {
     __shared__ double red[3][256 * J];
-    const SumChunk ch = chunks[blockIdx.x];
+    const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
     const PairDesc pd = pairs[ch.pair];
     const float* base = (const float*)(ch.side ? pd.Y : pd.X);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -148,16 +148,16 @@ bool vector_rows_ok(int input_dtype, int d, int d_pad) {
     return input_dtype == HBT_IN_F32 && d % 4 == 0 && d_pad <= 1024;
 }
 
-hipError_t launch_colsum_vec(const PairDesc* pairs, const SumChunk* chunks, int nchunks, int d,
+hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int d,
                              int d_pad, double* partial, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     const int J = (d_pad + 255) / 256;
     const dim3 g(nchunks), b(256);
     switch (J) {
-        case 1: hipLaunchKernelGGL(k_colsum4<1>, g, b, 0, s, pairs, chunks, d, partial); break;
-        case 2: hipLaunchKernelGGL(k_colsum4<2>, g, b, 0, s, pairs, chunks, d, partial); break;
-        case 3: hipLaunchKernelGGL(k_colsum4<3>, g, b, 0, s, pairs, chunks, d, partial); break;
-        case 4: hipLaunchKernelGGL(k_colsum4<4>, g, b, 0, s, pairs, chunks, d, partial); break;
+        case 1: hipLaunchKernelGGL(k_colsum4<1>, g, b, 0, s, pairs, npairs, d, partial); break;
+        case 2: hipLaunchKernelGGL(k_colsum4<2>, g, b, 0, s, pairs, npairs, d, partial); break;
+        case 3: hipLaunchKernelGGL(k_colsum4<3>, g, b, 0, s, pairs, npairs, d, partial); break;
+        case 4: hipLaunchKernelGGL(k_colsum4<4>, g, b, 0, s, pairs, npairs, d, partial); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -347,11 +347,9 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
 #pragma unroll
             for (int r = 0; r < 8; r += 2) {
                 const float a = (float)z[r], b = (float)z[r + 1];
-                const uint32_t ha = f32_to_bf16_bits(a), hb = f32_to_bf16_bits(b);
-                const uint32_t la = f32_to_bf16_bits(a - bf16_bits_to_f32(ha));
-                const uint32_t lb = f32_to_bf16_bits(b - bf16_bits_to_f32(hb));
-                hi[r / 2] = ha | (hb << 16);
-                lo[r / 2] = la | (lb << 16);
+                const uint2 hl = split_bf16x2(a, b);
+                hi[r / 2] = hl.x;
+                lo[r / 2] = hl.y;
             }
             uint4* ph = (uint4*)zstore + oct * d_pad + c;
             *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
@@ -466,6 +464,12 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
             k[r] = 2.0 * wave_sum_f64(w) / vv;
         }
     }
+    // the update below converts the rows to FP64 again instead of keeping the
+    // dot product's FP64 copies alive (twice the registers)
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int j = 0; j < J; ++j) asm volatile("" : "+v"(x[r][j].x), "+v"(x[r][j].y), "+v"(x[r][j].z), "+v"(x[r][j].w));
     if (lane < 8) {
         double kr = k[0];
 #pragma unroll
@@ -476,19 +480,38 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     for (int j = 0; j < J; ++j) {
         const int c0 = 4 * (lane + 64 * j);
         if (c0 >= d_pad) continue;
-        double z[4][8];  // [column][row]
+        if (PREC == HBT_F64) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                double2* q = (double2*)((double*)zstore + (oct * 8 + r) * d_pad + c0);
+                const double z0 = (double)x[r][j].x - k[r] * vc[j][0], z1 = (double)x[r][j].y - k[r] * vc[j][1];
+                const double z2 = (double)x[r][j].z - k[r] * vc[j][2], z3 = (double)x[r][j].w - k[r] * vc[j][3];
+                q[0] = make_double2(z0, z1);
+                q[1] = make_double2(z2, z3);
+                if (z32)
+                    *(float4*)(z32 + (oct * 8 + r) * d_pad + c0) =
+                        make_float4((float)z0, (float)z1, (float)z2, (float)z3);
+            }
+            continue;
+        }
+        // FP64 update, rounded to FP32 at once (the storage is FP32 or BF16 hi+lo)
+        float zf[4][8];  // [column][row]
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            z[0][r] = (double)x[r][j].x - k[r] * vc[j][0];
-            z[1][r] = (double)x[r][j].y - k[r] * vc[j][1];
-            z[2][r] = (double)x[r][j].z - k[r] * vc[j][2];
-            z[3][r] = (double)x[r][j].w - k[r] * vc[j][3];
+            zf[0][r] = (float)((double)x[r][j].x - k[r] * vc[j][0]);
+            zf[1][r] = (float)((double)x[r][j].y - k[r] * vc[j][1]);
+            zf[2][r] = (float)((double)x[r][j].z - k[r] * vc[j][2]);
+            zf[3][r] = (float)((double)x[r][j].w - k[r] * vc[j][3]);
         }
-        if (z32) {
+        if (PREC == HBT_F32 || z32) {
+            float* dst = PREC == HBT_F32 ? (float*)zstore : z32;
 #pragma unroll
             for (int r = 0; r < 8; ++r)
-                *(float4*)(z32 + (oct * 8 + r) * d_pad + c0) =
-                    make_float4((float)z[0][r], (float)z[1][r], (float)z[2][r], (float)z[3][r]);
+                *(float4*)(dst + (oct * 8 + r) * d_pad + c0) = make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
+            if (PREC == HBT_F32 && z32)
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    *(float4*)(z32 + (oct * 8 + r) * d_pad + c0) = make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
         }
         if (PREC == HBT_BF16X2) {
 #pragma unroll
@@ -496,28 +519,13 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
                 uint32_t hi[4], lo[4];
 #pragma unroll
                 for (int r = 0; r < 8; r += 2) {
-                    const float a = (float)z[e][r], b = (float)z[e][r + 1];
-                    const uint32_t ha = f32_to_bf16_bits(a), hb = f32_to_bf16_bits(b);
-                    const uint32_t la = f32_to_bf16_bits(a - bf16_bits_to_f32(ha));
-                    const uint32_t lb = f32_to_bf16_bits(b - bf16_bits_to_f32(hb));
-                    hi[r / 2] = ha | (hb << 16);
-                    lo[r / 2] = la | (lb << 16);
+                    const uint2 hl = split_bf16x2(zf[e][r], zf[e][r + 1]);
+                    hi[r / 2] = hl.x;
+                    lo[r / 2] = hl.y;
                 }
                 uint4* ph = (uint4*)zstore + oct * d_pad + c0 + e;
                 *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
                 *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-            }
-        } else if (PREC == HBT_F32) {
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-                *(float4*)((float*)zstore + (oct * 8 + r) * d_pad + c0) =
-                    make_float4((float)z[0][r], (float)z[1][r], (float)z[2][r], (float)z[3][r]);
-        } else {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                double2* q = (double2*)((double*)zstore + (oct * 8 + r) * d_pad + c0);
-                q[0] = make_double2(z[0][r], z[1][r]);
-                q[1] = make_double2(z[2][r], z[3][r]);
             }
         }
     }

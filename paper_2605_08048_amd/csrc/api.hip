@@ -67,7 +67,6 @@ struct StageTimer {
     }
 };
 
-constexpr int kSumChunk = 128;       // rows per column-sum chunk
 constexpr int64_t kAutoBlock = 32768;  // splits per block when block_perms == 0
 
 int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
@@ -115,7 +114,6 @@ struct Carve {
 struct Workspace {
     PairDesc* pairs;
     BlockPair* bp;
-    SumChunk* chunks;
     GemmTile* tiles;
     GemmGroup* groups;
     int64_t* Btot;
@@ -171,7 +169,6 @@ Workspace carve(const Plan& P, void* ws) {
     const int np = std::max(P.npairs, 1);
     w.pairs = c.take<PairDesc>(np);
     w.bp = c.take<BlockPair>(np);
-    w.chunks = c.take<SumChunk>(std::max<size_t>(P.chunks.size(), 1));
     w.tiles = c.take<GemmTile>(std::max<size_t>(P.tiles.size(), 1));
     w.groups = c.take<GemmGroup>(std::max<size_t>(P.groups.size(), 1));
     w.Btot = c.take<int64_t>(np);
@@ -327,13 +324,12 @@ hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd
     {
         StageTimer t(HBT_STAGE_OTHER, s);
         HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
-        HIP_TRY(upload(w.chunks, P.chunks.data(), P.chunks.size() * sizeof(SumChunk), s));
     }
     StageTimer t(HBT_STAGE_ALIGN, s);
     if (vector_rows(P))
-        HIP_TRY(launch_colsum_vec(w.pairs, w.chunks, (int)P.chunks.size(), P.d, P.d_pad, w.partial_sum, s));
+        HIP_TRY(launch_colsum_vec(w.pairs, P.npairs, (int)P.chunks.size(), P.d, P.d_pad, w.partial_sum, s));
     else
-        HIP_TRY(launch_colsum(P.input_dtype, w.pairs, w.chunks, (int)P.chunks.size(), P.d,
+        HIP_TRY(launch_colsum(P.input_dtype, w.pairs, P.npairs, (int)P.chunks.size(), P.d,
                               w.partial_sum, s));
     HIP_TRY(launch_finalize(w.pairs, P.npairs, w.partial_sum, P.d, P.d_pad, align, gd, w.sxy, w.st,
                             w.v, w.t64, w.t32, w.cnt, res, s));

@@ -64,6 +64,7 @@ struct SumChunk {
     int32_t pair, side;  // side 0 = X, 1 = Y
     int32_t r0, r1;
 };
+constexpr int kSumChunk = 128;  // rows per column-sum chunk
 
 // A group-sum tile of the FP32 / FP64 kernels: kTileB split rows of one pair
 // (the grid covers all column slots).
@@ -144,15 +145,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return (uint32_t)v;
 }
 
-// Round-to-nearest-even float -> bfloat16 bits.
-__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+// Split of two floats into BF16 hi + lo parts: hi = bf16(a), lo =
+// bf16(a - hi), both round-to-nearest-even (the gfx950 packed conversion
+// v_cvt_pk_bf16_f32); returns the packed hi pair and lo pair (element a in
+// the low 16 bits).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 split_bf16x2(float a, float b) {
+    const f32x2_t f = {a, b};
+    const bf16x2_t hi = __builtin_convertvector(f, bf16x2_t);
+    const bf16x2_t lo = __builtin_convertvector(f - __builtin_convertvector(hi, f32x2_t), bf16x2_t);
+    return make_uint2(__builtin_bit_cast(uint32_t, hi), __builtin_bit_cast(uint32_t, lo));
 }
-
-__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
 // log g_d(r) of Sec. 3.1 ("Dispersion proxy"), in FP64.
 __device__ __forceinline__ double log_g(double r, double d, int gd) {
@@ -179,6 +183,20 @@ __device__ __forceinline__ int upper_index(int count, int64_t x, F key) {
         else hi = mid - 1;
     }
     return lo;
+}
+
+// Column-sum chunk c: chunks are numbered pair by pair, the X chunks of a
+// pair ([cx0, cx1)) before its Y chunks ([cx1, cy1)), kSumChunk rows each.
+__device__ __forceinline__ SumChunk chunk_of(const PairDesc* pairs, int npairs, int c) {
+    const int p = upper_index(npairs, c, [&](int k) { return pairs[k].cx0; });
+    const int cx0 = pairs[p].cx0, cx1 = pairs[p].cx1;
+    SumChunk ch;
+    ch.pair = p;
+    ch.side = c < cx1 ? 0 : 1;
+    const int rows = ch.side ? pairs[p].m : pairs[p].n;
+    ch.r0 = (c - (ch.side ? cx1 : cx0)) * kSumChunk;
+    ch.r1 = ch.r0 + kSumChunk < rows ? ch.r0 + kSumChunk : rows;
+    return ch;
 }
 
 #endif  // __HIPCC__

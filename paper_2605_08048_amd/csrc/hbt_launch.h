@@ -20,7 +20,7 @@ hipError_t zero(void* dst, size_t bytes, hipStream_t s);
 
 // --- alignment (Algorithm 1, Steps 1-4) ---------------------------------
 // FP64 column sums of every chunk: partial[chunk][d].
-hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, const SumChunk* chunks,
+hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, int npairs,
                          int nchunks, int d, double* partial, hipStream_t s);
 // Per pair: sums, r, mean directions, v, v.v, identity, T_obs, tau, the pooled
 // total t (FP64 and FP32), the hbt_result header.
@@ -33,7 +33,7 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 // 16-byte-load variants for FP32 rows with d % 4 == 0 and d_pad <= 1024 (the
 // caller also checks that every X, Y is 16-byte aligned).
 bool vector_rows_ok(int input_dtype, int d, int d_pad);
-hipError_t launch_colsum_vec(const PairDesc* pairs, const SumChunk* chunks, int nchunks, int d,
+hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int d,
                              int d_pad, double* partial, hipStream_t s);
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
                               int64_t total_octets, const PairState* st, const double* v, int d,
