@@ -227,6 +227,11 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
 hbt_status hbt_budget_features(int64_t npairs, const hbt_result* results, int64_t d, int32_t gd,
                                float* features, void* stream);
 
+/* targets (device, npairs x 2 floats) = (t_mean, log t_sd) of each result:
+ * the network's training targets, from runs with many splits.
+ * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (npairs < 1), HBT_ERR_DEVICE. */
+hbt_status hbt_null_targets(int64_t npairs, const hbt_result* results, float* targets, void* stream);
+
 /* theta[0:24] = per-feature mean and 1 / standard deviation over `rows`
  * feature rows (FP64 reductions; a constant feature gets scale 1).
  * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (rows < 1), HBT_ERR_DEVICE. */

@@ -19,8 +19,9 @@ Pieces:
 * ``mlp_*``      a 12 -> 64 -> 64 -> 2 ReLU network with a fixed input
   standardisation, its squared-error loss, and backpropagation;
 * ``adam_step``  Adam (Kingma & Ba 2015, Algorithm 1, bias-corrected);
-* ``budgets``    B = clamp(ceil(zq^2 p(1-p) / (p - alpha)^2), Bmin, Bmax) with
-  p = 1 - Phi((T_obs - mu) / sigma).
+* ``budgets``    B = clamp(ceil(zq^2 p(1-p) / (p - e)^2), Bmin, Bmax) with
+  p = 1 - Phi((T_obs - mu) / sigma) and e the nearer edge of the fallback
+  band [lo, hi] (Bmax inside the band; lo = hi = alpha is the plain rule).
 """
 from __future__ import annotations
 
@@ -133,15 +134,19 @@ def normal_sf(z):
     return 0.5 * math.erfc(z / math.sqrt(2.0))
 
 
-def budgets(out, t_obs, alpha=0.05, bmin=200, bmax=20000, zq=2.3263478740408408):
+def budgets(out, t_obs, lo=0.05, hi=None, bmin=200, bmax=20000, zq=2.3263478740408408):
     """Permutations per pair from the network outputs (mu, log sigma)."""
+    hi = lo if hi is None else hi
     B = np.empty(out.shape[0], dtype=np.int64)
     for i in range(out.shape[0]):
         mu, ls = float(out[i, 0]), float(out[i, 1])
         p = normal_sf((float(t_obs[i]) - mu) / math.exp(ls))
-        gap = (p - alpha) ** 2
-        need = zq * zq * p * (1.0 - p) / gap if gap > 0 else math.inf
-        B[i] = bmax if not math.isfinite(need) or need >= bmax else max(bmin, int(math.ceil(need)))
+        if lo <= p <= hi:
+            B[i] = bmax
+            continue
+        e = lo if p < lo else hi
+        need = zq * zq * p * (1.0 - p) / (p - e) ** 2
+        B[i] = bmax if need >= bmax else max(bmin, int(math.ceil(need)))
     return B
 
 

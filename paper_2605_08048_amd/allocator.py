@@ -1,0 +1,126 @@
+"""Learned permutation-budget allocator: control flow over the C ABI.
+
+The permutation test of the paper spends the same number of random splits
+on every pair.  Here a small network (12 -> 64 -> 64 -> 2, FP32; the
+kernels are in ``csrc/budget.hip``) estimates each pair's permutation null
+distribution of T from the quantities of the alignment stage, and that
+estimate decides how many splits the pair gets:
+
+1. every pair is tested with ``b_min`` splits (this also yields the
+   alignment quantities the network reads);
+2. the network's (mean, log sd) and the pair's T_obs give a normal
+   approximation p^; the pair gets B_p splits, enough to put ``zq`` standard
+   errors between p^ and the fallback band [p_lo, p_hi] (b_max inside it);
+   the extra B_p - b_min splits continue the same counter-based stream
+   (``perm_offset = b_min``), so the counts simply add;
+3. pairs whose permutation p lands in [p_lo, p_hi] are tested again with the
+   full ``b_max`` splits from split 0 (the full-budget result itself).
+
+The decision is always the exact permutation p-value of eq:pvalue.  This
+module only marshals arguments and moves host-side arrays (budgets, the
+pair subsets of the later stages) between ABI calls; every computation runs
+in the library's kernels.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hbt
+
+ZQ_99 = 2.3263478740408408   # standard normal 0.99 quantile
+
+
+def init_theta(rng: np.random.Generator) -> np.ndarray:
+    """He-uniform weights (bound sqrt(6 / fan_in)), zero biases, identity
+    standardisation; the draws for W1, W2, W3 come from ``rng`` in that order."""
+    th = np.zeros(hbt.MLP_PARAMS, dtype=np.float64)
+    F, H = hbt.MLP_FEATURES, 64
+    th[F:2 * F] = 1.0
+    o = 2 * F
+    for rows, cols in ((H, F), (H, H), (2, H)):
+        lim = math.sqrt(6.0 / cols)
+        th[o:o + rows * cols] = rng.uniform(-lim, lim, rows * cols)
+        o += rows * cols + rows
+    return th
+
+
+@dataclass
+class Allocator:
+    theta: "object"                       # float32 device tensor, MLP_PARAMS
+    m: "object" = None
+    v: "object" = None
+    step: int = 0
+    history: list = field(default_factory=list)
+
+    @classmethod
+    def create(cls, device, seed=0, theta=None):
+        import torch
+        th = init_theta(np.random.default_rng(seed)) if theta is None else np.asarray(theta)
+        t = torch.tensor(th, dtype=torch.float32, device=device)
+        return cls(t, torch.zeros_like(t), torch.zeros_like(t))
+
+    def fit(self, features, targets, steps=500, lr=3e-3, normalise=True):
+        """Full-batch Adam on the mean half squared error; returns the losses."""
+        if normalise and self.step == 0:
+            hbt.feature_norm(features, self.theta)
+        grad = None
+        loss = None
+        losses = []
+        for _ in range(steps):
+            grad, loss = hbt.mlp_grad(features, targets, self.theta, grad, loss)
+            self.step += 1
+            hbt.mlp_adam(self.theta, grad, self.m, self.v, self.step, lr)
+            losses.append(loss)
+        out = [float(x.item()) for x in losses[:: max(1, steps // 50)]] + [float(losses[-1].item())]
+        self.history += out
+        return out
+
+    def predict(self, features):
+        return hbt.mlp_forward(features, self.theta)
+
+
+def adaptive_perm_test(Z_all, row_offset, n, m, allocator=None, *, d=None, seed=0, precision="bf16x2",
+                       gd="banerjee", p_lo=0.02, p_hi=0.10, b_min=200, b_max=20000, zq=ZQ_99):
+    """The three-stage test above; ``allocator=None`` skips stage 2 (every
+    pair keeps b_min unless stage 3 applies).  Returns per-pair numpy arrays
+    and the number of splits each stage evaluated."""
+    import torch
+    P = len(n)
+    d = Z_all.shape[1] if d is None else d
+    off = np.asarray(row_offset[:P], dtype=np.int64)
+    nn, mm = np.asarray(n, dtype=np.int64), np.asarray(m, dtype=np.int64)
+    ids = np.arange(P, dtype=np.uint32)
+    kw = dict(seed=seed, precision=precision, gd=gd)
+    # stage 1
+    r1 = hbt.perm_test_batched(Z_all, off, nn, mm, np.full(P, b_min), pair_index=ids, sync=False, **kw)
+    res = hbt.results_to_numpy(r1)
+    count = res["count"].astype(np.int64)
+    B = np.full(P, b_min, dtype=np.int64)
+    splits = {"stage1": int(P * b_min), "stage2": 0, "stage3": 0}
+    # stage 2
+    if allocator is not None:
+        feat = hbt.budget_features(r1, d, gd)
+        out = allocator.predict(feat)
+        Bp = hbt.budgets(out, r1, p_lo, p_hi, b_min, b_max, zq).cpu().numpy()
+        more = np.nonzero(Bp > b_min)[0]
+        if more.size:
+            r2 = hbt.perm_test_batched(Z_all, off[more], nn[more], mm[more], Bp[more] - b_min,
+                                       pair_index=ids[more], perm_offset=b_min, **kw)
+            count[more] += r2["count"]
+            B[more] = Bp[more]
+            splits["stage2"] = int(np.sum(Bp[more] - b_min))
+    p = (1.0 + count) / (B + 1.0)
+    # stage 3
+    redo = np.nonzero((p >= p_lo) & (p <= p_hi) & (B < b_max))[0]
+    if redo.size:
+        r3 = hbt.perm_test_batched(Z_all, off[redo], nn[redo], mm[redo], np.full(redo.size, b_max),
+                                   pair_index=ids[redo], **kw)
+        count[redo] = r3["count"]
+        B[redo] = b_max
+        p[redo] = r3["p"]
+        splits["stage3"] = int(redo.size * b_max)
+    splits["total"] = splits["stage1"] + splits["stage2"] + splits["stage3"]
+    return dict(p=p, count=count, B=B, t_obs=res["t_obs"], splits=splits, reran=redo)

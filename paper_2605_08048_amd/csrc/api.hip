@@ -668,6 +668,14 @@ hbt_status hbt_budget_features(int64_t npairs, const hbt_result* results, int64_
     return HBT_OK;
 }
 
+hbt_status hbt_null_targets(int64_t npairs, const hbt_result* results, float* targets, void* stream) {
+    g_err.clear();
+    if (!results || !targets) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (npairs < 1) return fail(HBT_ERR_SIZE, "npairs = %lld", (long long)npairs);
+    HIP_TRY(launch_null_targets(npairs, results, targets, (hipStream_t)stream));
+    return HBT_OK;
+}
+
 hbt_status hbt_feature_norm(int64_t rows, const float* features, float* theta, void* stream) {
     g_err.clear();
     if (!features || !theta) return fail(HBT_ERR_ARG, "NULL pointer");

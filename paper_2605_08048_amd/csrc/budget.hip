@@ -48,6 +48,21 @@ __global__ void k_features(int64_t npairs, const hbt_result* __restrict__ res, d
     for (int k = 0; k < kF; ++k) feat[p * kF + k] = (float)f[k];
 }
 
+// training targets of a pair: (mean, log sd) of its permuted statistics
+__global__ void k_null_targets(int64_t npairs, const hbt_result* __restrict__ res,
+                               float* __restrict__ target) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    target[p * kO] = (float)res[p].t_mean;
+    target[p * kO + 1] = (float)log(res[p].t_sd);
+}
+
+hipError_t launch_null_targets(int64_t npairs, const hbt_result* res, float* target, hipStream_t s) {
+    hipLaunchKernelGGL(k_null_targets, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, npairs,
+                       res, target);
+    return hipGetLastError();
+}
+
 // shift = mean, scale = 1 / sd (population) of each feature over the rows;
 // one work-group per feature, fixed-order FP64 reductions.  A constant
 // feature gets scale 1.

@@ -108,6 +108,7 @@ hipError_t launch_moments(int npairs, const BlockPair* bp, const PairState* st, 
 size_t mlp_train_ws_bytes(int64_t rows);
 hipError_t launch_features(int64_t npairs, const hbt_result* res, int d, int gd, float* feat,
                            hipStream_t s);
+hipError_t launch_null_targets(int64_t npairs, const hbt_result* res, float* target, hipStream_t s);
 hipError_t launch_feature_norm(int64_t rows, const float* feat, float* theta, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t rows, const float* feat, const float* theta, float* out,
                               hipStream_t s);

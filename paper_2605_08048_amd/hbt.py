@@ -91,6 +91,19 @@ def lib():
         L.hbt_stage_timing.restype = i32
         L.hbt_stage_times.argtypes = [P, P]
         L.hbt_stage_times.restype = i32
+        dbl, flt = C.c_double, C.c_float
+        L.hbt_budget_features.argtypes = [i64, P, i64, i32, P, P]
+        L.hbt_feature_norm.argtypes = [i64, P, P, P]
+        L.hbt_null_targets.argtypes = [i64, P, P, P]
+        L.hbt_mlp_forward.argtypes = [i64, P, P, P, P]
+        L.hbt_mlp_grad_workspace_size.argtypes = [i64]
+        L.hbt_mlp_grad_workspace_size.restype = sz
+        L.hbt_mlp_grad.argtypes = [i64, P, P, P, P, P, P, sz, P]
+        L.hbt_mlp_adam.argtypes = [P, P, P, P, i64, flt, flt, flt, flt, P]
+        L.hbt_budgets.argtypes = [i64, P, P, dbl, dbl, i64, i64, dbl, P, P]
+        for f in ["hbt_budget_features", "hbt_null_targets", "hbt_feature_norm", "hbt_mlp_forward", "hbt_mlp_grad",
+                  "hbt_mlp_adam", "hbt_budgets"]:
+            getattr(L, f).restype = i32
         _lib = L
     return _lib
 
@@ -279,3 +292,75 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
     if not sync:
         return res
     return results_to_numpy(res)
+
+
+# ------------------------------------------------------------------ allocator kernels
+
+MLP_FEATURES, MLP_PARAMS, MLP_TRAINABLE_OFFSET = 12, 5146, 24
+GD = {"banerjee": 0, "identity": 1}
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def budget_features(results, d, gd="banerjee", stream=None):
+    """(npairs, 12) float32 device tensor of allocator inputs from a device
+    tensor of hbt_result records (as returned with sync=False)."""
+    torch = _torch()
+    P = results.numel() // RESULT_BYTES
+    out = torch.empty((P, MLP_FEATURES), dtype=torch.float32, device=results.device)
+    _check(lib().hbt_budget_features(P, _ptr(results), d, GD[gd], _ptr(out), _stream(stream)))
+    return out
+
+
+def null_targets(results, stream=None):
+    """(npairs, 2) float32 device tensor (t_mean, log t_sd) of hbt_result records."""
+    torch = _torch()
+    P = results.numel() // RESULT_BYTES
+    out = torch.empty((P, 2), dtype=torch.float32, device=results.device)
+    _check(lib().hbt_null_targets(P, _ptr(results), _ptr(out), _stream(stream)))
+    return out
+
+
+def feature_norm(features, theta, stream=None):
+    """Write the per-feature standardisation (mean, 1/sd) into theta[0:24]."""
+    _check(lib().hbt_feature_norm(features.shape[0], _ptr(features), _ptr(theta), _stream(stream)))
+
+
+def mlp_forward(features, theta, stream=None):
+    torch = _torch()
+    out = torch.empty((features.shape[0], 2), dtype=torch.float32, device=features.device)
+    _check(lib().hbt_mlp_forward(features.shape[0], _ptr(features), _ptr(theta), _ptr(out), _stream(stream)))
+    return out
+
+
+def mlp_grad(features, targets, theta, grad=None, loss=None, stream=None):
+    """(grad, loss): float32 gradient of the mean half squared error and the
+    FP64 loss, both device tensors."""
+    torch = _torch()
+    R = features.shape[0]
+    dev = features.device
+    grad = grad if grad is not None else torch.zeros(MLP_PARAMS, dtype=torch.float32, device=dev)
+    loss = loss if loss is not None else torch.zeros(1, dtype=torch.float64, device=dev)
+    L = lib()
+    ws = workspace(L.hbt_mlp_grad_workspace_size(R), dev)
+    _check(L.hbt_mlp_grad(R, _ptr(features), _ptr(targets), _ptr(theta), _ptr(grad), _ptr(loss), _ptr(ws),
+                          ws.numel(), _stream(stream)))
+    return grad, loss
+
+
+def mlp_adam(theta, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().hbt_mlp_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                              _stream(stream)))
+
+
+def budgets(mlp_out, results, p_lo, p_hi, b_min, b_max, zq=2.3263478740408408, stream=None):
+    """int64 device tensor of permutation budgets per pair."""
+    torch = _torch()
+    P = mlp_out.shape[0]
+    out = torch.empty(P, dtype=torch.int64, device=mlp_out.device)
+    _check(lib().hbt_budgets(P, _ptr(mlp_out), _ptr(results), p_lo, p_hi, b_min, b_max, zq, _ptr(out),
+                             _stream(stream)))
+    return out
+

@@ -119,6 +119,21 @@ def test_budget_rule():
     assert all(b[i] <= b[i + 1] for i in range(len(b) - 1))
 
 
+def test_budget_band():
+    """With a band [lo, hi]: inside -> the full budget; outside, the distance
+    to the nearer edge replaces p - alpha."""
+    zq = stats.norm.ppf(0.99)
+    one = lambda p, lo, hi: Bu.budgets(np.array([[0.0, 0.0]]), np.array([stats.norm.isf(p)]), lo, hi)[0]
+    for p in [0.02, 0.05, 0.0999]:
+        assert one(p, 0.02, 0.10) == 20000
+    p = 0.15
+    assert one(p, 0.02, 0.10) == max(200, math.ceil(zq * zq * p * (1 - p) / (p - 0.10) ** 2))
+    p = 0.012
+    assert one(p, 0.02, 0.10) == max(200, math.ceil(zq * zq * p * (1 - p) / (p - 0.02) ** 2))
+    # the point band is the plain rule
+    assert one(0.03, 0.05, 0.05) == Bu.budgets(np.array([[0.0, 0.0]]), np.array([stats.norm.isf(0.03)]), 0.05)[0]
+
+
 def test_features_against_aligned_clouds():
     """r(Z) and the angle term against the aligned rows themselves."""
     c = synth.small_pair_f64()
