@@ -64,17 +64,16 @@ class Allocator:
 
     def fit(self, features, targets, steps=500, lr=3e-3, normalise=True):
         """Full-batch Adam on the mean half squared error; returns the losses."""
+        import torch
         if normalise and self.step == 0:
             hbt.feature_norm(features, self.theta)
         grad = None
-        loss = None
-        losses = []
-        for _ in range(steps):
-            grad, loss = hbt.mlp_grad(features, targets, self.theta, grad, loss)
+        hist = torch.empty(steps, dtype=torch.float64, device=self.theta.device)
+        for i in range(steps):  # step i writes its loss (before its update) into hist[i]
+            grad, _ = hbt.mlp_grad(features, targets, self.theta, grad, hist[i:i + 1])
             self.step += 1
             hbt.mlp_adam(self.theta, grad, self.m, self.v, self.step, lr)
-            losses.append(loss)
-        out = [float(x.item()) for x in losses[:: max(1, steps // 50)]] + [float(losses[-1].item())]
+        out = hist.cpu().numpy().tolist()
         self.history += out
         return out
 
@@ -87,7 +86,6 @@ def adaptive_perm_test(Z_all, row_offset, n, m, allocator=None, *, d=None, seed=
     """The three-stage test above; ``allocator=None`` skips stage 2 (every
     pair keeps b_min unless stage 3 applies).  Returns per-pair numpy arrays
     and the number of splits each stage evaluated."""
-    import torch
     P = len(n)
     d = Z_all.shape[1] if d is None else d
     off = np.asarray(row_offset[:P], dtype=np.int64)
