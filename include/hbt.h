@@ -210,12 +210,14 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
  *
  * Network: 12 -> 64 -> 64 -> 2, ReLU, FP32, parameters theta (HBT_MLP_PARAMS
  * floats, device): shift[12], scale[12] (inputs enter as (x - shift) *
- * scale; not trained), W1[64][12], b1[64], W2[64][64], b2[64], W3[2][64],
- * b3[2], row-major.  Outputs per row: (mean, log sd).
+ * scale), oshift[2], oscale[2] (outputs leave as oshift + oscale * y~), these
+ * 28 not trained; then W1[64][12], b1[64], W2[64][64], b2[64], W3[2][64],
+ * b3[2], row-major, y~ = W3 relu(W2 relu(W1 x~ + b1) + b2) + b3.  Outputs per
+ * row: (mean, log sd).
  * ------------------------------------------------------------------------ */
 #define HBT_MLP_FEATURES 12
-#define HBT_MLP_PARAMS 5146
-#define HBT_MLP_TRAINABLE_OFFSET 24   /* theta[24:] is trained */
+#define HBT_MLP_PARAMS 5150
+#define HBT_MLP_TRAINABLE_OFFSET 28   /* theta[28:] is trained */
 
 /* features (device, npairs x 12 floats) of each pair from its results (device,
  * from hbt_perm_test or hbt_perm_test_batched; any B >= 1): log n, log m,
@@ -237,14 +239,19 @@ hbt_status hbt_null_targets(int64_t npairs, const hbt_result* results, float* ta
  * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (rows < 1), HBT_ERR_DEVICE. */
 hbt_status hbt_feature_norm(int64_t rows, const float* features, float* theta, void* stream);
 
+/* theta[24:28] = per-output mean and standard deviation of `rows` targets
+ * (rows x 2 floats), so the network fits standardised targets.
+ * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (rows < 1), HBT_ERR_DEVICE. */
+hbt_status hbt_target_norm(int64_t rows, const float* targets, float* theta, void* stream);
+
 /* out (device, rows x 2 floats) = network(features).
  * Errors: HBT_ERR_ARG, HBT_ERR_SIZE (rows < 1), HBT_ERR_DEVICE. */
 hbt_status hbt_mlp_forward(int64_t rows, const float* features, const float* theta, float* out,
                            void* stream);
 
 /* grad (device, HBT_MLP_PARAMS floats; entries below the trainable offset are
- * left untouched) = gradient of L = (1/rows) sum_r (1/2) |out_r - target_r|^2
- * with targets (device, rows x 2); loss (device double, nullable) = L.  The
+ * left untouched) = gradient of L = (1/rows) sum_r (1/2) |(out_r - target_r) /
+ * oscale|^2 with targets (device, rows x 2); loss (device double, nullable) = L.  The
  * sum over rows runs in a fixed order in FP64, so results are reproducible.
  * Errors: HBT_ERR_ARG, HBT_ERR_SIZE, HBT_ERR_WORKSPACE, HBT_ERR_DEVICE. */
 size_t hbt_mlp_grad_workspace_size(int64_t rows);
@@ -253,7 +260,7 @@ hbt_status hbt_mlp_grad(int64_t rows, const float* features, const float* target
                         void* stream);
 
 /* One Adam step (Kingma & Ba 2015, Algorithm 1, bias-corrected; step >= 1)
- * on theta[24:], with first and second moments adam_m, adam_v (device,
+ * on theta[28:], with first and second moments adam_m, adam_v (device,
  * HBT_MLP_PARAMS floats each, zero before step 1).
  * Errors: HBT_ERR_ARG (NULL pointer, step < 1, lr <= 0, betas outside
  * [0, 1)), HBT_ERR_DEVICE. */

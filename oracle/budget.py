@@ -16,8 +16,9 @@ Pieces:
 * ``features``   12 numbers per pair (Sec. 3.1 quantities: group sizes, mean
   resultant lengths, the pooled MRL after alignment, the angle between the
   mean directions, log g_d, the observed statistic);
-* ``mlp_*``      a 12 -> 64 -> 64 -> 2 ReLU network with a fixed input
-  standardisation, its squared-error loss, and backpropagation;
+* ``mlp_*``      a 12 -> 64 -> 64 -> 2 ReLU network with fixed input and
+  output standardisations, its squared-error loss (on standardised
+  targets), and backpropagation;
 * ``adam_step``  Adam (Kingma & Ba 2015, Algorithm 1, bias-corrected);
 * ``budgets``    B = clamp(ceil(zq^2 p(1-p) / (p - e)^2), Bmin, Bmax) with
   p = 1 - Phi((T_obs - mu) / sigma) and e the nearer edge of the fallback
@@ -32,12 +33,12 @@ import numpy as np
 from . import oracle as O
 
 NF, H1, H2, NO = 12, 64, 64, 2
-NORM = 2 * NF                         # shift and scale of the inputs (not trained)
-SHAPES = [("shift", (NF,)), ("scale", (NF,)),
+NORM = 2 * NF + 2 * NO                # input shift/scale, output shift/scale (not trained)
+SHAPES = [("shift", (NF,)), ("scale", (NF,)), ("oshift", (NO,)), ("oscale", (NO,)),
           ("W1", (H1, NF)), ("b1", (H1,)),
           ("W2", (H2, H1)), ("b2", (H2,)),
           ("W3", (NO, H2)), ("b3", (NO,))]
-NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)   # 5146
+NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)   # 5150
 
 
 def unpack(theta):
@@ -51,11 +52,12 @@ def unpack(theta):
 
 
 def init_params(rng, shift=None, scale=None):
-    """He-uniform weights, zero biases; shift/scale default to 0/1."""
+    """He-uniform weights, zero biases; shifts default to 0, scales to 1."""
     theta = np.zeros(NPARAM)
     P = unpack(theta)
     P["shift"][:] = 0.0 if shift is None else shift
     P["scale"][:] = 1.0 if scale is None else scale
+    P["oscale"][:] = 1.0
     for w, fan in (("W1", NF), ("W2", H1), ("W3", H2)):
         lim = math.sqrt(6.0 / fan)
         P[w][:] = rng.uniform(-lim, lim, P[w].shape)
@@ -81,30 +83,33 @@ def features(n, m, d, r_x, r_y, vv, t_obs, gd=O.GD_BANERJEE):
 # ------------------------------------------------------------------ network
 
 def mlp_forward(theta, X):
-    """X (rows x 12) -> (out (rows x 2), cache)."""
+    """X (rows x 12) -> (out (rows x 2), cache); out = oshift + oscale * y~,
+    y~ the last layer's value."""
     P = unpack(theta)
     Xs = (X - P["shift"]) * P["scale"]
     A1 = Xs @ P["W1"].T + P["b1"]
     Z1 = np.maximum(A1, 0.0)
     A2 = Z1 @ P["W2"].T + P["b2"]
     Z2 = np.maximum(A2, 0.0)
-    out = Z2 @ P["W3"].T + P["b3"]
-    return out, (Xs, A1, Z1, A2, Z2)
+    Yt = Z2 @ P["W3"].T + P["b3"]
+    return P["oshift"] + P["oscale"] * Yt, (Xs, A1, Z1, A2, Z2)
 
 
-def mlp_loss(out, target):
-    """Mean over rows of half the squared error summed over the 2 outputs."""
-    return 0.5 * float(np.sum((out - target) ** 2)) / out.shape[0]
+def mlp_loss(theta, out, target):
+    """Mean over rows of half the squared error of the standardised outputs,
+    (out - target) / oscale, summed over the 2 outputs."""
+    e = (out - target) / unpack(theta)["oscale"]
+    return 0.5 * float(np.sum(e ** 2)) / out.shape[0]
 
 
 def mlp_backward(theta, cache, out, target):
-    """Gradient of mlp_loss with respect to theta (zero for shift/scale)."""
+    """Gradient of mlp_loss with respect to theta (zero for the standardisations)."""
     P = unpack(theta)
     Xs, A1, Z1, A2, Z2 = cache
     R = out.shape[0]
     g = np.zeros_like(theta)
     G = unpack(g)
-    dO = (out - target) / R
+    dO = (out - target) / P["oscale"] / R   # d loss / d y~
     G["W3"][:] = dO.T @ Z2
     G["b3"][:] = dO.sum(0)
     dA2 = (dO @ P["W3"]) * (A2 > 0)

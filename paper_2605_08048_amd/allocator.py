@@ -35,11 +35,12 @@ ZQ_99 = 2.3263478740408408   # standard normal 0.99 quantile
 
 def init_theta(rng: np.random.Generator) -> np.ndarray:
     """He-uniform weights (bound sqrt(6 / fan_in)), zero biases, identity
-    standardisation; the draws for W1, W2, W3 come from ``rng`` in that order."""
+    standardisations; the draws for W1, W2, W3 come from ``rng`` in that order."""
     th = np.zeros(hbt.MLP_PARAMS, dtype=np.float64)
     F, H = hbt.MLP_FEATURES, 64
     th[F:2 * F] = 1.0
-    o = 2 * F
+    th[2 * F + 2:2 * F + 4] = 1.0
+    o = hbt.MLP_TRAINABLE_OFFSET
     for rows, cols in ((H, F), (H, H), (2, H)):
         lim = math.sqrt(6.0 / cols)
         th[o:o + rows * cols] = rng.uniform(-lim, lim, rows * cols)
@@ -63,10 +64,12 @@ class Allocator:
         return cls(t, torch.zeros_like(t), torch.zeros_like(t))
 
     def fit(self, features, targets, steps=500, lr=3e-3, normalise=True):
-        """Full-batch Adam on the mean half squared error; returns the losses."""
+        """Full-batch Adam on the mean half squared error of the standardised
+        targets; returns the loss of every step."""
         import torch
         if normalise and self.step == 0:
             hbt.feature_norm(features, self.theta)
+            hbt.target_norm(targets, self.theta)
         grad = None
         hist = torch.empty(steps, dtype=torch.float64, device=self.theta.device)
         for i in range(steps):  # step i writes its loss (before its update) into hist[i]

@@ -684,6 +684,14 @@ hbt_status hbt_feature_norm(int64_t rows, const float* features, float* theta, v
     return HBT_OK;
 }
 
+hbt_status hbt_target_norm(int64_t rows, const float* targets, float* theta, void* stream) {
+    g_err.clear();
+    if (!targets || !theta) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (rows < 1) return fail(HBT_ERR_SIZE, "rows = %lld", (long long)rows);
+    HIP_TRY(launch_target_norm(rows, targets, theta, (hipStream_t)stream));
+    return HBT_OK;
+}
+
 hbt_status hbt_mlp_forward(int64_t rows, const float* features, const float* theta, float* out,
                            void* stream) {
     g_err.clear();

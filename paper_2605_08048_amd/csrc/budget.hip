@@ -10,15 +10,17 @@
 //
 // Parameter vector theta (float), row-major blocks in this order:
 //   shift[12], scale[12]      input standardisation x~ = (x - shift) * scale
+//   oshift[2], oscale[2]      output standardisation out = oshift + oscale * y~
 //   W1[64][12], b1[64]        hidden layer 1 (ReLU)
 //   W2[64][64], b2[64]        hidden layer 2 (ReLU)
-//   W3[2][64],  b3[2]         output: (mean, log sd)
+//   W3[2][64],  b3[2]         y~ (standardised (mean, log sd))
 #include "hbt_launch.h"
 
 namespace hbt {
 
 constexpr int kF = HBT_MLP_FEATURES, kH = 64, kO = 2;
-constexpr int oShift = 0, oScale = kF, oW1 = 2 * kF, oB1 = oW1 + kH * kF, oW2 = oB1 + kH,
+constexpr int oShift = 0, oScale = kF, oOShift = 2 * kF, oOScale = oOShift + kO, oW1 = oOScale + kO,
+              oB1 = oW1 + kH * kF, oW2 = oB1 + kH,
               oB2 = oW2 + kH * kH, oW3 = oB2 + kH, oB3 = oW3 + kO * kH, kP = oB3 + kO;
 static_assert(kP == HBT_MLP_PARAMS, "parameter layout");
 static_assert(oW1 == HBT_MLP_TRAINABLE_OFFSET, "trainable offset");
@@ -63,11 +65,12 @@ hipError_t launch_null_targets(int64_t npairs, const hbt_result* res, float* tar
     return hipGetLastError();
 }
 
-// shift = mean, scale = 1 / sd (population) of each feature over the rows;
-// one work-group per feature, fixed-order FP64 reductions.  A constant
-// feature gets scale 1.
-__global__ __launch_bounds__(256) void k_feature_norm(int64_t rows, const float* __restrict__ feat,
-                                                      float* __restrict__ theta) {
+// Column statistics of a rows x cols matrix: shift[k] = mean, scale[k] =
+// 1 / sd (invert) or sd (population sd); one work-group per column,
+// fixed-order FP64 reductions.  A constant column gets scale 1.
+__global__ __launch_bounds__(256) void k_col_norm(int64_t rows, int cols, const float* __restrict__ feat,
+                                                  float* __restrict__ shift, float* __restrict__ scale,
+                                                  int invert) {
     __shared__ double red[256];
     const int k = blockIdx.x;
     auto block_sum = [&](double x) {
@@ -82,17 +85,17 @@ __global__ __launch_bounds__(256) void k_feature_norm(int64_t rows, const float*
         return s;
     };
     double s = 0.0;
-    for (int64_t r = threadIdx.x; r < rows; r += 256) s += (double)feat[r * kF + k];
+    for (int64_t r = threadIdx.x; r < rows; r += 256) s += (double)feat[r * cols + k];
     const double mean = block_sum(s) / (double)rows;
     double q = 0.0;
     for (int64_t r = threadIdx.x; r < rows; r += 256) {
-        const double x = (double)feat[r * kF + k] - mean;
+        const double x = (double)feat[r * cols + k] - mean;
         q += x * x;
     }
     const double sd = sqrt(block_sum(q) / (double)rows);
     if (threadIdx.x == 0) {
-        theta[oShift + k] = (float)mean;
-        theta[oScale + k] = sd > 0.0 ? (float)(1.0 / sd) : 1.0f;
+        shift[k] = (float)mean;
+        scale[k] = sd > 0.0 ? (float)(invert ? 1.0 / sd : sd) : 1.0f;
     }
 }
 
@@ -140,11 +143,12 @@ __global__ __launch_bounds__(256) void k_mlp_forward(int64_t rows, const float* 
         o0 = fmaf(th[oW3 + j], z, o0);
         o1 = fmaf(th[oW3 + kH + j], z, o1);
     }
-    out[r * kO + 0] = o0;
-    out[r * kO + 1] = o1;
+    out[r * kO + 0] = fmaf(th[oOScale], o0, th[oOShift]);
+    out[r * kO + 1] = fmaf(th[oOScale + 1], o1, th[oOShift + 1]);
 }
 
-// Per-row pass of the gradient of L = (1/R) sum_r (1/2) |out_r - target_r|^2:
+// Per-row pass of the gradient of L = (1/R) sum_r (1/2) |(out_r - target_r) / oscale|^2
+// (the squared error of y~ against standardised targets):
 // forward, then the error signals at the pre-activations of the three layers
 // (dout, d2, d1).  Writes what the per-parameter reduction needs: x~, z1, z2,
 // d1, d2, dout, and the row's loss.
@@ -171,7 +175,9 @@ __global__ __launch_bounds__(256) void k_mlp_rows(int64_t rows, const float* __r
         o1 = fmaf(th[oW3 + kH + j], z, o1);
     }
     const float inv = 1.0f / (float)rows;
-    const float e0 = o0 - target[r * kO], e1 = o1 - target[r * kO + 1];
+    // error of y~ against the standardised target (t - oshift) / oscale
+    const float e0 = o0 - (target[r * kO] - th[oOShift]) / th[oOScale];
+    const float e1 = o1 - (target[r * kO + 1] - th[oOShift + 1]) / th[oOScale + 1];
     const float g0 = e0 * inv, g1 = e1 * inv;
     // d2_j = relu'(a2_j) (W3^T dout)_j, and d1 = relu'(a1) o (W2^T d2), the
     // latter accumulated unit by unit of layer 2
@@ -313,7 +319,14 @@ hipError_t launch_features(int64_t npairs, const hbt_result* res, int d, int gd,
 }
 
 hipError_t launch_feature_norm(int64_t rows, const float* feat, float* theta, hipStream_t s) {
-    hipLaunchKernelGGL(k_feature_norm, dim3(kF), dim3(256), 0, s, rows, feat, theta);
+    hipLaunchKernelGGL(k_col_norm, dim3(kF), dim3(256), 0, s, rows, kF, feat, theta + oShift,
+                       theta + oScale, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_target_norm(int64_t rows, const float* target, float* theta, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_norm, dim3(kO), dim3(256), 0, s, rows, kO, target, theta + oOShift,
+                       theta + oOScale, 0);
     return hipGetLastError();
 }
 

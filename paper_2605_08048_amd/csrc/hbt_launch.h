@@ -110,6 +110,7 @@ hipError_t launch_features(int64_t npairs, const hbt_result* res, int d, int gd,
                            hipStream_t s);
 hipError_t launch_null_targets(int64_t npairs, const hbt_result* res, float* target, hipStream_t s);
 hipError_t launch_feature_norm(int64_t rows, const float* feat, float* theta, hipStream_t s);
+hipError_t launch_target_norm(int64_t rows, const float* target, float* theta, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t rows, const float* feat, const float* theta, float* out,
                               hipStream_t s);
 hipError_t launch_mlp_grad(int64_t rows, const float* feat, const float* target, const float* theta,

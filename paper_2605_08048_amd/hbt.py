@@ -94,6 +94,7 @@ def lib():
         dbl, flt = C.c_double, C.c_float
         L.hbt_budget_features.argtypes = [i64, P, i64, i32, P, P]
         L.hbt_feature_norm.argtypes = [i64, P, P, P]
+        L.hbt_target_norm.argtypes = [i64, P, P, P]
         L.hbt_null_targets.argtypes = [i64, P, P, P]
         L.hbt_mlp_forward.argtypes = [i64, P, P, P, P]
         L.hbt_mlp_grad_workspace_size.argtypes = [i64]
@@ -101,7 +102,7 @@ def lib():
         L.hbt_mlp_grad.argtypes = [i64, P, P, P, P, P, P, sz, P]
         L.hbt_mlp_adam.argtypes = [P, P, P, P, i64, flt, flt, flt, flt, P]
         L.hbt_budgets.argtypes = [i64, P, P, dbl, dbl, i64, i64, dbl, P, P]
-        for f in ["hbt_budget_features", "hbt_null_targets", "hbt_feature_norm", "hbt_mlp_forward", "hbt_mlp_grad",
+        for f in ["hbt_budget_features", "hbt_null_targets", "hbt_feature_norm", "hbt_target_norm", "hbt_mlp_forward", "hbt_mlp_grad",
                   "hbt_mlp_adam", "hbt_budgets"]:
             getattr(L, f).restype = i32
         _lib = L
@@ -296,7 +297,7 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
 
 # ------------------------------------------------------------------ allocator kernels
 
-MLP_FEATURES, MLP_PARAMS, MLP_TRAINABLE_OFFSET = 12, 5146, 24
+MLP_FEATURES, MLP_PARAMS, MLP_TRAINABLE_OFFSET = 12, 5150, 28
 GD = {"banerjee": 0, "identity": 1}
 
 
@@ -326,6 +327,11 @@ def null_targets(results, stream=None):
 def feature_norm(features, theta, stream=None):
     """Write the per-feature standardisation (mean, 1/sd) into theta[0:24]."""
     _check(lib().hbt_feature_norm(features.shape[0], _ptr(features), _ptr(theta), _stream(stream)))
+
+
+def target_norm(targets, theta, stream=None):
+    """Write the output standardisation (mean, sd of the targets) into theta[24:28]."""
+    _check(lib().hbt_target_norm(targets.shape[0], _ptr(targets), _ptr(theta), _stream(stream)))
 
 
 def mlp_forward(features, theta, stream=None):

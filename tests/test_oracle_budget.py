@@ -20,16 +20,18 @@ def _net(seed):
     P["b1"][:] = g.normal(0, 0.3, Bu.H1)   # non-zero biases so every term is exercised
     P["b2"][:] = g.normal(0, 0.3, Bu.H2)
     P["b3"][:] = g.normal(0, 0.3, Bu.NO)
+    P["oshift"][:] = g.normal(0, 1, Bu.NO)
+    P["oscale"][:] = g.uniform(0.2, 3.0, Bu.NO)
     X = g.normal(0, 1, (7, Bu.NF))
     T = g.normal(0, 1, (7, Bu.NO))
     return th, X, T
 
 
 def test_layout():
-    assert Bu.NPARAM == 12 + 12 + 64 * 12 + 64 + 64 * 64 + 64 + 2 * 64 + 2
+    assert Bu.NPARAM == 12 + 12 + 2 + 2 + 64 * 12 + 64 + 64 * 64 + 64 + 2 * 64 + 2
     th = np.arange(Bu.NPARAM, dtype=np.float64)
     P = Bu.unpack(th)
-    assert P["W1"][1, 0] == 24 + 12 and P["b3"][-1] == Bu.NPARAM - 1
+    assert P["W1"][1, 0] == 28 + 12 and P["b3"][-1] == Bu.NPARAM - 1 and P["oscale"][0] == 26
 
 
 def test_hand_network():
@@ -39,6 +41,7 @@ def test_hand_network():
     P = Bu.unpack(th)
     P["shift"][:] = 1.0
     P["scale"][:] = 2.0
+    P["oscale"][:] = 1.0
     P["W1"][0, 0], P["W1"][1, 0] = 1.0, -1.0
     P["W2"][0, 0], P["W2"][0, 1] = 1.0, 1.0
     P["b2"][1] = -3.0                     # a unit that stays off
@@ -53,6 +56,11 @@ def test_hand_network():
     u = np.maximum(np.maximum([4.0, -3.0, 0.0], 0) - 3.0, 0)
     assert np.allclose(out[:, 0], 2 * h + 0.5, rtol=0, atol=1e-15)
     assert np.allclose(out[:, 1], 5 * u - 1.0, rtol=0, atol=1e-15)
+    # the output standardisation maps y~ to oshift + oscale y~
+    P["oshift"][:] = [1.0, -2.0]
+    P["oscale"][:] = [3.0, 0.5]
+    out2, _ = Bu.mlp_forward(th, X)
+    assert np.allclose(out2, [1.0, -2.0] + np.array([3.0, 0.5]) * out, rtol=0, atol=1e-14)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -69,7 +77,7 @@ def test_backward_matches_central_differences(seed):
         tp, tm = th.copy(), th.copy()
         tp[k] += h
         tm[k] -= h
-        num = (Bu.mlp_loss(Bu.mlp_forward(tp, X)[0], T) - Bu.mlp_loss(Bu.mlp_forward(tm, X)[0], T)) / (2 * h)
+        num = (Bu.mlp_loss(tp, Bu.mlp_forward(tp, X)[0], T) - Bu.mlp_loss(tm, Bu.mlp_forward(tm, X)[0], T)) / (2 * h)
         assert abs(num - g[k]) <= 1e-7 * max(1.0, abs(num)), (k, num, g[k])
 
 
@@ -162,9 +170,9 @@ def test_training_reduces_loss():
     T = np.stack([np.sin(X[:, 0]) + 0.5 * X[:, 1], 0.3 * X[:, 2] ** 2], 1)
     th = Bu.init_params(g)
     m, v = np.zeros(Bu.NPARAM), np.zeros(Bu.NPARAM)
-    l0 = Bu.mlp_loss(Bu.mlp_forward(th, X)[0], T)
+    l0 = Bu.mlp_loss(th, Bu.mlp_forward(th, X)[0], T)
     for t in range(1, 301):
         out, cache = Bu.mlp_forward(th, X)
         Bu.adam_step(th, Bu.mlp_backward(th, cache, out, T), m, v, t, lr=3e-3)
-    l1 = Bu.mlp_loss(Bu.mlp_forward(th, X)[0], T)
+    l1 = Bu.mlp_loss(th, Bu.mlp_forward(th, X)[0], T)
     assert l1 < 0.05 * l0
