@@ -69,12 +69,17 @@ constexpr int kXcd = 8;                          // XCDs of an MI355X
 // 16 bytes land at LDS address lds + 16 l (M0 holds the wave's base).  Issued
 // as inline asm so that the compiler inserts no waits of its own for these
 // LDS writes: the kernel waits for them explicitly (vmcnt) before a barrier.
+// M0 is declared clobbered; no code generated for this kernel reads M0
+// otherwise, so nothing of the compiler's lives there across the statement.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
 __device__ __forceinline__ void dma16(const void* src, uint32_t lds) {
     asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
                  :
                  : "v"(src), "s"(lds)
                  : "memory", "m0");
 }
+#pragma clang diagnostic pop
 
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
