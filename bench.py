@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the (untimed) tile-width tuning of the split-BF16 product")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run the batched path twice and a 1 GiB copy, for rocprofv3 --pmc")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH", "WRITE"),
@@ -199,6 +201,13 @@ def main():
     stats_per_step = int(batch.B.sum())
     algo_flops = float(2 * d * np.sum(batch.B * N))       # 2 N d per permuted statistic
     L = hbt.lib()
+    tuning = None
+    if not args.no_tune:
+        costs = hbt.tune_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed)
+        widths = hbt.tile_widths(batch.B, d)
+        tuning = {"cost_per_split_row_ms": {"512": costs[0], "256": costs[1]},
+                  "pairs_at_256": int(np.sum(widths == 256))}
+        log(f"tile widths tuned: {tuning}")
 
     def run(prec, steps, warmup):
         res = torch.zeros(hbt.RESULT_BYTES * P, dtype=torch.uint8, device=dev)
@@ -265,6 +274,7 @@ def main():
         "pairs_bad_status": bad,
         "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
+        "tile_tuning": tuning,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch)

@@ -200,6 +200,33 @@ typedef enum hbt_stage {
 hbt_status hbt_stage_timing(int32_t enable);
 hbt_status hbt_stage_times(double* ms, int64_t* launches);
 
+/* Tile widths of the split-BF16 product (the batching of Sec. 3.2's practical
+ * notes over many pairs).  A work-group of the product covers 64 columns of Z
+ * and 512 or 256 splits of one pair.  Every call picks, per pair (per block
+ * for hbt_perm_test), the width w minimising cost_w * round_up(B, w), with
+ * per-split costs for the pair's dimension (padded to 64) from a table in the
+ * library; until tuned, cost_512 = 1 and cost_256 = 1.15.  Results do not
+ * depend on the width.
+ *   hbt_tune_batched: runs hbt_perm_test_batched on its arguments once with
+ *     every pair at width 512 and once at 256, times the product with HIP
+ *     events and stores cost_w = time / sum_p round_up(B_p, w) *
+ *     round_up(n_p + m_p, 128) for this d.  It synchronises the stream, clears
+ *     the stage-timing record, and leaves the second run's results in
+ *     `results`.  Split BF16 only (HBT_ERR_ARG otherwise).
+ *   hbt_tune_get / hbt_tune_set: the table entry for d (costs[0] for width
+ *     512, costs[1] for 256; tuned = 1 once set), e.g. to keep a cache across
+ *     processes.
+ *   hbt_tile_widths: the widths (host, npairs entries) a call with these
+ *     per-pair B would use at dimension d.
+ * Errors: HBT_ERR_ARG, HBT_ERR_SIZE, and those of hbt_perm_test_batched. */
+hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* row_offset,
+                            const int64_t* n, const int64_t* m, const int64_t* B,
+                            const uint32_t* pair_index, int64_t d, const hbt_perm_params* common,
+                            hbt_result* results, void* ws, size_t ws_bytes, void* stream);
+hbt_status hbt_tune_get(int64_t d, double* costs, int32_t* tuned);
+hbt_status hbt_tune_set(int64_t d, const double* costs);
+hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t* widths);
+
 /* ------------------------------------------------------------------------
  * Learned permutation-budget allocator.  The paper gives every pair the same
  * number of splits; here a small network estimates, from quantities of

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -150,8 +151,10 @@ struct Plan {
     std::vector<BlockPair> bp;
     std::vector<SumChunk> chunks;
     std::vector<GemmTile> tiles;
-    std::vector<GemmGroup> groups;
+    std::vector<GemmGroup> groups; // split BF16: the 512-wide groups, then the 256-wide ones
     int64_t ntile_total = 0;      // tiles of the split-BF16 kernel over all groups
+    int ng512 = 0, ng256 = 0;     // groups of each tile width
+    int64_t nt512 = 0, nt256 = 0; // their tiles (tile0 counts from 0 in each segment)
     std::vector<int64_t> Btot;
     int64_t zrows = 0, ncoef = 0;
     int64_t block_rows = 0;       // split rows of the largest block
@@ -283,6 +286,52 @@ void finish_plan(Plan& P, int64_t d, int precision, int input_dtype) {
     P.input_dtype = input_dtype;
 }
 
+// ---------------------------------------------------------------------------
+// Tile width of the split-BF16 product: per pair (or per block of one pair),
+// the width w in {512, 256} minimising cost_w * round_up(B, w); per-split
+// costs come from a table keyed by d_pad (hbt_tune_batched fills it).
+// ---------------------------------------------------------------------------
+struct TileCost {
+    double c[2];   // [0]: 512-split tiles, [1]: 256-split tiles
+    bool tuned;
+};
+std::mutex g_tune_mu;
+std::map<int, TileCost> g_tune;
+thread_local int g_force_width = 0;  // 0: choose; 512 or 256: every pair (tuning runs)
+
+TileCost tile_cost(int d_pad) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(d_pad);
+    return it != g_tune.end() ? it->second : TileCost{{1.0, 1.15}, false};
+}
+
+int choose_width(int64_t B, const TileCost& tc) {
+    if (g_force_width) return g_force_width;
+    const double t512 = tc.c[0] * (double)round_up(B, 512), t256 = tc.c[1] * (double)round_up(B, 256);
+    return t256 < t512 ? 256 : 512;
+}
+
+// Groups of split-BF16 tiles, pairs in the given order, segmented by width.
+void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B) {
+    const TileCost tc = tile_cost(P.d_pad);
+    std::vector<GemmGroup> g2;
+    for (int p : order) {
+        const int w = choose_width(B[p], tc);
+        const int nbt = (int)((B[p] + w - 1) / w);
+        if (w == 512) {
+            P.groups.push_back(GemmGroup{p, nbt, P.nt512});
+            P.nt512 += (int64_t)nbt * P.nslot;
+        } else {
+            g2.push_back(GemmGroup{p, nbt, P.nt256});
+            P.nt256 += (int64_t)nbt * P.nslot;
+        }
+    }
+    P.ng512 = (int)P.groups.size();
+    P.ng256 = (int)g2.size();
+    P.groups.insert(P.groups.end(), g2.begin(), g2.end());
+    P.ntile_total = P.nt512 + P.nt256;
+}
+
 // Single-pair plan with blocks of B0 splits.
 Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64_t* B0_out) {
     Plan P;
@@ -294,7 +343,7 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0});
     const int tb = groupsum_tile_splits(prm->precision);
     for (int64_t b = 0; b < B0; b += tb) P.tiles.push_back(GemmTile{0, (int32_t)b});
-    P.groups.push_back(GemmGroup{0, (int32_t)((B0 + tb - 1) / tb), 0});
+    P.groups.push_back(GemmGroup{0, (int32_t)((B0 + 255) / 256), 0});  // room for the narrower width
     P.ntile_total = (int64_t)P.groups[0].nbt * P.nslot;
     if (prm->stat_route == 1) {
         P.route2 = true;
@@ -494,8 +543,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
         const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
         BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
-        const int tb = groupsum_tile_splits(P.precision);
-        const GemmGroup grp{0, (int32_t)((nb + tb - 1) / tb), 0};
+        const int wdt = choose_width(nb, tile_cost(P.d_pad));
+        const GemmGroup grp{0, (int32_t)((nb + wdt - 1) / wdt), 0};
         {
             StageTimer t_(HBT_STAGE_OTHER, s);
             HIP_TRY(upload(w.bp, &bq, sizeof bq, s));
@@ -509,12 +558,14 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             else
                 HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.st, s));
         }
-        const int ntiles = grp.nbt;
+        const int ntiles = (int)((nb + groupsum_tile_splits(P.precision) - 1) / groupsum_tile_splits(P.precision));
         {
             StageTimer t_(HBT_STAGE_GROUPSUM, s);
-            HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, 1,
-                                    grp.nbt * P.nslot, P.d_pad, w.zstore, P.zrows * P.d_pad,
-                                    w.mask, w.t32, w.t64, w.partial, w.sig, s));
+            const int nt = grp.nbt * P.nslot;
+            HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == 512,
+                                    wdt == 512 ? nt : 0, wdt == 256, wdt == 256 ? nt : 0, P.d_pad,
+                                    w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
+                                    w.sig, s));
             if (P.route2)
                 HIP_TRY(launch_centroid(w.pairs, w.bp, w.ctiles, (int)((nb + kTileB - 1) / kTileB),
                                         P.ntile_i, P.d_pad, z32, w.sig, w.mask, w.zt, w.partial2,
@@ -560,12 +611,9 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
     const int tb = groupsum_tile_splits(common->precision);
-    for (int p : order) {
+    for (int p : order)
         for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
-        const int nbt = (int)((B[p] + tb - 1) / tb);
-        P.groups.push_back(GemmGroup{p, nbt, P.ntile_total});
-        P.ntile_total += (int64_t)nbt * P.nslot;
-    }
+    add_groups(P, order, B);
     P.block_rows = rows;
     P.block_mask_words = words;
     return true;
@@ -636,7 +684,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     {
         StageTimer t_(HBT_STAGE_GROUPSUM, s);
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
-                                (int)P.groups.size(), (int)P.ntile_total, P.d_pad, w.zstore,
+                                P.ng512, (int)P.nt512, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
                                 P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, nullptr, s));
     }
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
@@ -744,6 +792,76 @@ hbt_status hbt_budgets(int64_t npairs, const float* mlp_out, const hbt_result* r
     HIP_TRY(launch_budgets(npairs, mlp_out, results, p_lo, p_hi, b_min, b_max, zq, budgets,
                            (hipStream_t)stream));
     return HBT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile widths of the split-BF16 product
+// ---------------------------------------------------------------------------
+hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t* widths) {
+    g_err.clear();
+    if (!B || !widths) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (npairs < 1 || d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "npairs %lld, d %lld", (long long)npairs, (long long)d);
+    const TileCost tc = tile_cost((int)round_up(d, kDPad));
+    for (int64_t p = 0; p < npairs; ++p) {
+        if (B[p] < 1) return fail(HBT_ERR_SIZE, "B[%lld] = %lld", (long long)p, (long long)B[p]);
+        widths[p] = choose_width(B[p], tc);
+    }
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_get(int64_t d, double* costs, int32_t* tuned) {
+    g_err.clear();
+    if (!costs) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
+    const TileCost tc = tile_cost((int)round_up(d, kDPad));
+    costs[0] = tc.c[0];
+    costs[1] = tc.c[1];
+    if (tuned) *tuned = tc.tuned ? 1 : 0;
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_set(int64_t d, const double* costs) {
+    g_err.clear();
+    if (!costs) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
+    if (!(costs[0] > 0.0) || !(costs[1] > 0.0)) return fail(HBT_ERR_ARG, "costs must be positive");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[(int)round_up(d, kDPad)] = TileCost{{costs[0], costs[1]}, true};
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* row_offset,
+                            const int64_t* n, const int64_t* m, const int64_t* B,
+                            const uint32_t* pair_index, int64_t d, const hbt_perm_params* common,
+                            hbt_result* results, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!common || !B || !n || !m) return fail(HBT_ERR_ARG, "NULL argument");
+    if (common->precision != HBT_BF16X2)
+        return fail(HBT_ERR_ARG, "tile widths are tuned for the split-BF16 product only");
+    if (npairs < 1 || d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "npairs %lld, d %lld", (long long)npairs, (long long)d);
+    const int widths[2] = {512, 256};
+    double cost[2];
+    for (int k = 0; k < 2; ++k) {
+        // per-split work of this width: padded splits times pooled rows
+        double units = 0.0;
+        for (int64_t p = 0; p < npairs; ++p)
+            units += (double)round_up(B[p], widths[k]) * (double)round_up(n[p] + m[p], kRowPad);
+        hbt_status st = hbt_stage_timing(1);
+        if (st) return st;
+        g_force_width = widths[k];
+        st = hbt_perm_test_batched(npairs, Z_all, row_offset, n, m, B, pair_index, d, common, results,
+                                   ws, ws_bytes, stream);
+        g_force_width = 0;
+        double ms[HBT_NUM_STAGES];
+        int64_t launches[HBT_NUM_STAGES];
+        const hbt_status st2 = hbt_stage_times(ms, launches);
+        hbt_stage_timing(0);
+        if (st) return st;
+        if (st2) return st2;
+        if (!(ms[HBT_STAGE_GROUPSUM] > 0.0)) return fail(HBT_ERR_DEVICE, "no timing of the product");
+        cost[k] = ms[HBT_STAGE_GROUPSUM] / units;
+    }
+    return hbt_tune_set(d, cost);
 }
 
 }  // extern "C"

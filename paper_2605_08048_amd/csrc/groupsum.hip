@@ -104,23 +104,27 @@ __device__ __forceinline__ int xcd_remap(int g) {
     return 32 * (g / 32) + 4 * (g % kXcd) + (g / kXcd) % 4;
 }
 
-constexpr int kMaskVec = 4 * 128;                // uint4 per chunk: 4 waves x 128 split rows
-// s_waitcnt operand: at most 10 vector-memory operations outstanding (one
-// chunk's direct-to-LDS loads of a wave: 8 of Z, 2 of masks), no wait on
-// export or LDS counters (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt
-// [6:4], lgkmcnt [11:8])
-constexpr int kChunkLoads = 10;
-constexpr int kWaitOneChunk = (kChunkLoads & 0xf) | ((kChunkLoads >> 4) << 14) | (0x7 << 4) | (0xf << 8);
+// s_waitcnt operand: at most `loads` vector-memory operations outstanding (one
+// chunk's direct-to-LDS loads of a wave), no wait on export or LDS counters
+// (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8])
+constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14) | (0x7 << 4) | (0xf << 8); }
 
+// JB split blocks of 32 per wave: a work-group covers 128 JB splits (JB = 4:
+// 512, JB = 2: 256; the tile width the plan picks per pair).
+template <int JB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
     double* __restrict__ partial, float* __restrict__ sig) {
+    constexpr int kWS = 32 * JB;            // splits per wave
+    constexpr int kTile = 4 * kWS;          // splits per work-group
+    constexpr int kMaskVec = kTile;         // uint4 per chunk: one 128-row word group per split
+    constexpr int kMaskLoads = kWS / 64;    // mask loads per wave per chunk
+    constexpr int kWaitOneChunk = wait_vmcnt(8 + kMaskLoads);
     // separate LDS objects per buffer ([plane][octet][column] of Z; [wave][split]
-    // of mask words), so the compiler can see that a direct load into one
-    // buffer never feeds a read of the other
+    // of mask words)
     __shared__ uint4 lds0[kChunkVec];
     __shared__ uint4 lds1[kChunkVec];
     __shared__ uint4 lds2[kChunkVec];
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const GemmGroup grp = groups[gi];
     const int local = L - (int)grp.tile0;
     const int slot = local / grp.nbt;                       // 64-column slice
-    const int b0 = (local % grp.nbt) * kTileBF16;
+    const int b0 = (local % grp.nbt) * kTile;
     const PairDesc pd = pairs[grp.pair];
     const BlockPair bq = bp[grp.pair];
     const int tid = threadIdx.x;
@@ -156,27 +160,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         lut[tid] = make_uint2(w[0], w[1]);
     }
 
-    // splits of this lane's four blocks (rows past the pair's splits are
+    // splits of this lane's JB blocks (rows past the pair's splits are
     // loaded from its first row and zeroed by keep[] at use)
-    int brow[4];
-    uint32_t keep[4];
+    int brow[JB];
+    uint32_t keep[JB];
     const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        brow[j] = b0 + wave * 128 + j * 32 + c;
+    for (int j = 0; j < JB; ++j) {
+        brow[j] = b0 + wave * kWS + j * 32 + c;
         keep[j] = brow[j] < bq.nb ? 0xffffffffu : 0u;
     }
-    // mask rows this lane moves into LDS: splits 128 w + l and 128 w + 64 + l
-    const uint4* mload[2];
+    // mask rows this lane moves into LDS: splits kWS w + 64 k + l
+    const uint4* mload[kMaskLoads];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int r = b0 + wave * 128 + 64 * k + lane;
+    for (int k = 0; k < kMaskLoads; ++k) {
+        const int r = b0 + wave * kWS + 64 * k + lane;
         mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
     }
 
     // chunk loader: 32 LDS rows of kDSlot uint4 (plane, octet); wave w fills
     // rows 8w .. 8w+7, lane l moving column l (1 KB per wave per load); and
-    // the wave's 128 mask rows (2 loads)
+    // the wave's kWS mask rows
     const int64_t oct0 = pd.zrow0 >> 3;
     const int64_t chunk_stride = (int64_t)kOct * d_pad;
     // rows 8w .. 8w+7 of the chunk tile all lie in one plane (kOct = 16)
@@ -184,11 +188,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     auto issue = [&](int ch, uint4* dst, uint4* mdst) {
         const uint4* base = zsrc + ch * chunk_stride;  // wave-uniform
         const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(dst + 8 * wave * kDSlot));
-        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(mdst + wave * 128));
+        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(mdst + wave * kWS));
 #pragma unroll
         for (int k = 0; k < 8; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) dma16(mload[k] + ch, ml + 16 * 64 * k);
+        for (int k = 0; k < kMaskLoads; ++k) dma16(mload[k] + ch, ml + 16 * 64 * k);
     };
 
     // three buffers: chunks ch+1 and ch+2 are in flight while ch is multiplied.
@@ -200,11 +204,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __builtin_amdgcn_s_waitcnt(kWaitOneChunk);  // chunk 0 landed, chunk 1 may not have
     __syncthreads();  // also publishes the nibble table
 
-    f32x16 acc[2][4];
+    f32x16 acc[2][JB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < JB; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
@@ -213,18 +217,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // (nxt, mnxt), the buffer every wave finished reading in the previous step
     auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
         issue(ch + 2 < last ? ch + 2 : last, nxt, mnxt);
-        // this chunk's mask words of the lane's 4 splits (16-byte rows: a
+        // this chunk's mask words of the lane's JB splits (16-byte rows: a
         // conflict-free 128-bit read per split), group flip and validity applied once
-        uint4 mw[4];
+        uint4 mw[JB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint4 x = mcur[wave * 128 + 32 * j + c];
+        for (int j = 0; j < JB; ++j) {
+            const uint4 x = mcur[wave * kWS + 32 * j + c];
             mw[j] = make_uint4((x.x ^ flip) & keep[j], (x.y ^ flip) & keep[j],
                                (x.z ^ flip) & keep[j], (x.w ^ flip) & keep[j]);
         }
         // operands of K-step s: Z fragments (2 planes x 2 column blocks) and
-        // the mask fragments of the 4 split blocks
-        auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[4]) {
+        // the mask fragments of the JB split blocks
+        auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[JB]) {
             const int o = 2 * s + h;
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
@@ -232,14 +236,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < JB; ++j) {
                 const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
                 const uint32_t byte = (word >> (8 * (2 * (s & 1) + h))) & 0xffu;
                 const uint2 lo = lut[byte & 15u], hi = lut[byte >> 4];
                 bm[j] = as_bf16x8(make_uint4(lo.x, lo.y, hi.x, hi.y));
             }
         };
-        bf16x8 a[2][2][2], bm[2][4];  // [buffer]...
+        bf16x8 a[2][2][2], bm[2][JB];  // [buffer]...
         fetch(0, a[0], bm[0]);
 #pragma unroll
         for (int s = 0; s < kChunk / 16; ++s) {  // K-steps of 16 pooled rows
@@ -249,13 +253,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < JB; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             a[s & 1][pl][i], bm[s & 1][j], acc[i][j], 0, 0, 0);
             if (s + 1 < kChunk / 16) {
-                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);  // next K-step's LDS reads
+                __builtin_amdgcn_sched_group_barrier(0x100, 4 * JB, 0);  // next K-step's LDS reads
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
+                for (int k = 0; k < 4 * JB; ++k) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
                     __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // 1 VALU
                 }
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
         for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JB; ++j) {
         float ss = 0.0f, sl = 0.0f;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -422,19 +426,24 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
 int groupsum_tile_splits(int precision) { return precision == HBT_BF16X2 ? kTileBF16 : kTileB; }
 
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
-                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngroups,
-                           int ntile_total, int d_pad, const void* zstore, int64_t zplane_elems,
-                           const uint32_t* mask, const float* t32, const double* t64,
-                           double* partial, float* sig, hipStream_t s) {
+                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ng512,
+                           int nt512, int ng256, int nt256, int d_pad, const void* zstore,
+                           int64_t zplane_elems, const uint32_t* mask, const float* t32,
+                           const double* t64, double* partial, float* sig, hipStream_t s) {
     const int nslot = d_pad / kDSlot;
     dim3 block(256);
     switch (precision) {
         case HBT_BF16X2: {
-            if (ntile_total <= 0) return hipSuccess;
-            const int grid = (ntile_total + 31) / 32 * 32;
-            hipLaunchKernelGGL(k_groupsum_bf16x2, dim3((unsigned)grid), block, 0, s, pairs, bp,
-                               groups, ngroups, ntile_total, nslot, d_pad, (const uint4*)zstore,
-                               (const uint4*)zstore + zplane_elems / 8, mask, t32, partial, sig);
+            const uint4* zhi = (const uint4*)zstore;
+            const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
+            if (nt512 > 0)
+                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3((unsigned)((nt512 + 31) / 32 * 32)), block, 0,
+                                   s, pairs, bp, groups, ng512, nt512, nslot, d_pad, zhi, zlo, mask,
+                                   t32, partial, sig);
+            if (nt256 > 0)
+                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3((unsigned)((nt256 + 31) / 32 * 32)), block, 0,
+                                   s, pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, zhi, zlo,
+                                   mask, t32, partial, sig);
             break;
         }
         case HBT_F32:

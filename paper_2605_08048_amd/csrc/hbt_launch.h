@@ -72,10 +72,10 @@ int groupsum_tile_splits(int precision);
 // FP32 / FP64 use the tile list; split BF16 uses the per-pair groups
 // (ntile_total tiles in all).
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
-                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngroups,
-                           int ntile_total, int d_pad, const void* zstore, int64_t zplane_elems,
-                           const uint32_t* mask, const float* t32, const double* t64,
-                           double* partial, float* sig, hipStream_t s);
+                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ng512,
+                           int nt512, int ng256, int nt256, int d_pad, const void* zstore,
+                           int64_t zplane_elems, const uint32_t* mask, const float* t32,
+                           const double* t64, double* partial, float* sig, hipStream_t s);
 
 // --- point-to-centroid route (statistic route 2) -------------------------
 // z_i . t per pooled row; then Q = Z S^T with the masked column sums

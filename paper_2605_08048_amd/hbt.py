@@ -92,6 +92,12 @@ def lib():
         L.hbt_stage_times.argtypes = [P, P]
         L.hbt_stage_times.restype = i32
         dbl, flt = C.c_double, C.c_float
+        L.hbt_tune_batched.argtypes = [i64, P, P, P, P, P, P, i64, C.POINTER(HbtPermParams), P, P, sz, P]
+        L.hbt_tune_get.argtypes = [i64, P, P]
+        L.hbt_tune_set.argtypes = [i64, P]
+        L.hbt_tile_widths.argtypes = [i64, P, i64, P]
+        for f in ["hbt_tune_batched", "hbt_tune_get", "hbt_tune_set", "hbt_tile_widths"]:
+            getattr(L, f).restype = i32
         L.hbt_budget_features.argtypes = [i64, P, i64, i32, P, P]
         L.hbt_feature_norm.argtypes = [i64, P, P, P]
         L.hbt_target_norm.argtypes = [i64, P, P, P]
@@ -369,4 +375,67 @@ def budgets(mlp_out, results, p_lo, p_hi, b_min, b_max, zq=2.3263478740408408, s
     _check(lib().hbt_budgets(P, _ptr(mlp_out), _ptr(results), p_lo, p_hi, b_min, b_max, zq, _ptr(out),
                              _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------ tile-width tuning
+
+def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="banerjee", workspace=None):
+    """Time both tile widths of the split-BF16 product on this batch and store
+    their per-split costs for its dimension; returns (cost_512, cost_256)."""
+    torch = _torch()
+    dev = Z_all.device
+    Z_all = Z_all.contiguous()
+    P = len(n)
+    off = np.ascontiguousarray(row_offset, dtype=np.int64)
+    nn = np.ascontiguousarray(n, dtype=np.int64)
+    mm = np.ascontiguousarray(m, dtype=np.int64)
+    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
+    ids = None if pair_index is None else np.ascontiguousarray(pair_index, dtype=np.uint32)
+    d = Z_all.shape[1]
+    prm = make_params(0, 0, d, 0, seed=seed, precision="bf16x2", input_dtype=_input_dtype(Z_all), gd=gd)
+    L = lib()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    need = L.hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm))
+    ws = workspace if workspace is not None else globals()["workspace"](max(need, 256), dev)
+    res = torch.zeros(RESULT_BYTES * P, dtype=torch.uint8, device=dev)
+    _check(L.hbt_tune_batched(P, C.c_void_p(Z_all.data_ptr()), ptr(off), ptr(nn), ptr(mm), ptr(BB),
+                              None if ids is None else ptr(ids), d, C.byref(prm), C.c_void_p(res.data_ptr()),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream(None)))
+    return tune_get(d)[0]
+
+
+def tune_get(d):
+    """((cost_512, cost_256), tuned) for dimension d."""
+    c = (C.c_double * 2)()
+    t = C.c_int32()
+    _check(lib().hbt_tune_get(d, c, C.byref(t)))
+    return (c[0], c[1]), bool(t.value)
+
+
+def tune_set(d, costs):
+    c = (C.c_double * 2)(*[float(x) for x in costs])
+    _check(lib().hbt_tune_set(d, c))
+
+
+def tile_widths(B, d):
+    BB = np.ascontiguousarray(np.asarray(B, dtype=np.int64).ravel())
+    out = np.zeros(BB.size, dtype=np.int32)
+    _check(lib().hbt_tile_widths(BB.size, BB.ctypes.data_as(C.c_void_p), d, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def save_tuning(path, dims):
+    """Write the tuned costs of the given dimensions to a JSON file."""
+    import json
+    rec = {str(int(d)): list(tune_get(int(d))[0]) for d in dims if tune_get(int(d))[1]}
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
+def load_tuning(path):
+    """Load costs written by save_tuning into the library's table."""
+    import json
+    with open(path) as f:
+        for d, c in json.load(f).items():
+            tune_set(int(d), c)
 

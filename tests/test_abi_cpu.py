@@ -133,3 +133,27 @@ def test_batched_validation():
     st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                  FAKE, need, None)
     assert st == hbt.ERR_UNSUPPORTED
+
+
+def test_tile_width_rule_and_tuning_table(tmp_path):
+    """Per pair, the width w in {512, 256} minimising cost_w * round_up(B, w)."""
+    import numpy as np
+    d = 4160  # a dimension no other test tunes
+    (c512, c256), tuned = hbt.tune_get(d)
+    assert (c512, c256) == (1.0, 1.15) and not tuned
+    B = np.array([1, 200, 250, 256, 257, 300, 512, 700, 2000, 20000])
+    want = [256 if c256 * -(-b // 256) * 256 < c512 * -(-b // 512) * 512 else 512 for b in B]
+    assert list(hbt.tile_widths(B, d)) == want
+    assert list(hbt.tile_widths([200, 2000], d)) == [256, 512]
+    hbt.tune_set(d, [1.0, 5.0])
+    assert list(hbt.tile_widths(B, d)) == [512] * len(B)
+    assert hbt.tune_get(d) == ((1.0, 5.0), True)
+    # the JSON cache round-trips through the library's table
+    f = tmp_path / "tune.json"
+    hbt.save_tuning(f, [d])
+    hbt.tune_set(d, [2.0, 1.0])
+    hbt.load_tuning(f)
+    assert hbt.tune_get(d) == ((1.0, 5.0), True)
+    L = hbt.lib()
+    assert L.hbt_tune_set(d, (C.c_double * 2)(1.0, -1.0)) == hbt.ERR_ARG
+    assert L.hbt_tile_widths(1, (C.c_int64 * 1)(0), d, (C.c_int32 * 1)()) == hbt.ERR_SIZE

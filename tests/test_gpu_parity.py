@@ -337,3 +337,46 @@ def test_batched_call_replays_from_a_hip_graph():
         other = hbt.perm_test_batched(*args, seed=b.seed + 1, precision="bf16x2", workspace=ws)
         assert np.all(other["status"] == 0)
 
+
+# --------------------------------------------------------------------- tile widths
+
+def _results_equal(a, b):
+    for f in ["t_obs", "r_x", "r_y", "p", "t_mean", "t_sd", "count", "B", "n_recheck", "status"]:
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_tile_widths_do_not_change_results():
+    """The product runs per pair with 512- or 256-split tiles; each split's
+    sums come from the same instructions in the same order, so results are
+    bit-identical whichever width the table picks."""
+    rng = np.random.default_rng(23)
+    pairs = []
+    for p in range(6):
+        n, m = int(rng.integers(2, 500)), int(rng.integers(2, 500))
+        X, Y = _pair(n, m, 160, kx=rng.uniform(1.5, 3), ky=rng.uniform(1.5, 3), seed=300 + p)
+        pairs.append(synth.Pair(X, Y, B=int(rng.integers(1, 1300)), pair_index=p))
+    bt = synth.pack_batch(pairs, 160)
+    runs = []
+    for costs in [(1.0, 1e9), (1e9, 1.0)]:
+        hbt.tune_set(160, costs)
+        assert set(hbt.tile_widths(bt.B, 160)) == ({512} if costs[0] < costs[1] else {256})
+        runs.append(hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=4,
+                                          precision="bf16x2"))
+        X, Y = pairs[0].X, pairs[0].Y
+        runs.append(hbt.perm_test(_dev(X), _dev(Y), 1100, seed=4, precision="bf16x2", want_T="f64"))
+    hbt.tune_set(160, (1.0, 1.15))
+    _results_equal(runs[0], runs[2])
+    assert np.array_equal(runs[1]["T"], runs[3]["T"])
+    for k in ["t_obs", "count", "p", "t_mean", "t_sd"]:
+        assert runs[1][k] == runs[3][k]
+
+
+def test_tuning_measures_both_widths():
+    b = synth.batch_512_d768(limit=range(24))
+    costs = hbt.tune_batched(_dev(b.Z), b.row_offset, b.n, b.m, np.full(24, 300))
+    (c512, c256), tuned = hbt.tune_get(768)
+    assert tuned and c512 > 0 and c256 > 0 and (c512, c256) == costs
+    print(f"tuned per-split costs at d=768: 512-wide {c512:.3e}, 256-wide {c256:.3e} ms", flush=True)
+    w = hbt.tile_widths([300, 2000], 768)
+    assert w[1] == (512 if c512 * 2048 <= c256 * 2048 else 256)
+
