@@ -256,14 +256,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     for (int j = 0; j < JB; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             a[s & 1][pl][i], bm[s & 1][j], acc[i][j], 0, 0, 0);
-            if (s + 1 < kChunk / 16) {
-                __builtin_amdgcn_sched_group_barrier(0x100, 4 * JB, 0);  // next K-step's LDS reads
-#pragma unroll
-                for (int k = 0; k < 4 * JB; ++k) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);  // 1 VALU
-                }
-            }
         }
         // chunk ch+1 has landed (this wave's loads, then every wave's through
         // the barrier), chunk ch+2 may still be in flight; every wave is done
