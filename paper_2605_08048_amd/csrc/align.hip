@@ -288,8 +288,12 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 //   HBT_F64    : double [Np][d_pad]
 //   HBT_F32    : float  [Np][d_pad]
 //   HBT_BF16X2 : two planes (hi, then lo at +zplane_elems) of bf16
-//                [Np/8][d_pad][8]: the 8 rows of an octet are contiguous per
-//                column, the operand layout of the bf16 MFMA.
+//                [Np/8][d_pad][8]: the 8 values of a storage octet are
+//                contiguous per column, the operand layout of the bf16 MFMA;
+//                storage octet 4 g + o4 holds rows 32 g + bf16_plane_row(o4, k)
+//                of the pair, scaled by bf16_plane_scale(o4, k) (k = 0..7).
+// A work-group (or wave) handles the 8 rows of one storage octet for every
+// format; the row-major formats simply write each row in its place.
 template <typename Tin, int PREC>
 __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pairs, int npairs,
                                                  const PairState* __restrict__ st,
@@ -303,12 +307,13 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
     const int identity = st[p].identity;
     const double vv = st[p].vv;
     const double* vp = v + (int64_t)p * d_pad;
-    const int i0 = (int)(oct * 8 - pd.zrow0);  // first pooled row of the octet
+    const int lo8 = (int)(oct - pd.zrow0 / 8);  // storage octet within the pair
+    const int g0 = 32 * (lo8 >> 2), o4 = lo8 & 3;
     const int N = pd.n + pd.m;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // coefficients 2 (v . x_i) / (v . v) of the X rows (eq:householder_fast)
     for (int r = wave; r < 8; r += 4) {
-        const int i = i0 + r;
+        const int i = g0 + bf16_plane_row(o4, r);
         double w = 0.0;
         if (!identity && i < pd.n) {
             const Tin* x = (const Tin*)pd.X + (int64_t)i * d;
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
         const double vc = c < d ? vp[c] : 0.0;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int i = i0 + r;
+            const int i = g0 + bf16_plane_row(o4, r);
             double val = 0.0;
             if (c < d) {
                 if (i < pd.n)
@@ -338,15 +343,16 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
             z[r] = val;
         }
         if (z32) {  // row-major FP32 copy for the point-to-centroid route
-            float* q = z32 + oct * 8 * d_pad + c;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) q[(int64_t)r * d_pad] = (float)z[r];
+            for (int r = 0; r < 8; ++r)
+                z32[(pd.zrow0 + g0 + bf16_plane_row(o4, r)) * (int64_t)d_pad + c] = (float)z[r];
         }
         if (PREC == HBT_BF16X2) {
             uint32_t hi[4], lo[4];
 #pragma unroll
             for (int r = 0; r < 8; r += 2) {
-                const float a = (float)z[r], b = (float)z[r + 1];
+                const float a = (float)z[r] * bf16_plane_scale(o4, r);
+                const float b = (float)z[r + 1] * bf16_plane_scale(o4, r + 1);
                 const uint2 hl = split_bf16x2(a, b);
                 hi[r / 2] = hl.x;
                 lo[r / 2] = hl.y;
@@ -355,13 +361,13 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
             *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
             *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
         } else if (PREC == HBT_F32) {
-            float* q = (float*)zstore + oct * 8 * d_pad + c;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) q[(int64_t)r * d_pad] = (float)z[r];
+            for (int r = 0; r < 8; ++r)
+                ((float*)zstore)[(pd.zrow0 + g0 + bf16_plane_row(o4, r)) * (int64_t)d_pad + c] = (float)z[r];
         } else {
-            double* q = (double*)zstore + oct * 8 * d_pad + c;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) q[(int64_t)r * d_pad] = z[r];
+            for (int r = 0; r < 8; ++r)
+                ((double*)zstore)[(pd.zrow0 + g0 + bf16_plane_row(o4, r)) * (int64_t)d_pad + c] = z[r];
         }
     }
 }
@@ -427,12 +433,13 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     const int identity = st[p].identity;
     const double vv = st[p].vv;
     const double* vp = v + (int64_t)p * d_pad;
-    const int i0 = (int)(oct * 8 - pd.zrow0);
+    const int lo8 = (int)(oct - pd.zrow0 / 8);  // storage octet within the pair
+    const int g0 = 32 * (lo8 >> 2), o4 = lo8 & 3;
     const int N = pd.n + pd.m;
     float4 x[8][J];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = i0 + r;  // wave-uniform
+        const int i = g0 + bf16_plane_row(o4, r);  // wave-uniform
         const float* row = i < pd.n ? (const float*)pd.X + (int64_t)i * d
                                     : (const float*)pd.Y + (int64_t)(i - pd.n) * d;
 #pragma unroll
@@ -453,7 +460,7 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     double k[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = i0 + r;
+        const int i = g0 + bf16_plane_row(o4, r);
         k[r] = 0.0;
         if (!identity && i < pd.n) {  // wave-uniform
             double w = 0.0;
@@ -474,7 +481,8 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
         double kr = k[0];
 #pragma unroll
         for (int r = 1; r < 8; ++r) kr = lane == r ? k[r] : kr;
-        if (i0 + lane < pd.n) coef[pd.coef0 + i0 + lane] = kr;
+        const int i = g0 + bf16_plane_row(o4, lane);
+        if (i < pd.n) coef[pd.coef0 + i] = kr;
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -483,13 +491,14 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
         if (PREC == HBT_F64) {
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                double2* q = (double2*)((double*)zstore + (oct * 8 + r) * d_pad + c0);
+                const int64_t zr = pd.zrow0 + g0 + bf16_plane_row(o4, r);
+                double2* q = (double2*)((double*)zstore + zr * d_pad + c0);
                 const double z0 = (double)x[r][j].x - k[r] * vc[j][0], z1 = (double)x[r][j].y - k[r] * vc[j][1];
                 const double z2 = (double)x[r][j].z - k[r] * vc[j][2], z3 = (double)x[r][j].w - k[r] * vc[j][3];
                 q[0] = make_double2(z0, z1);
                 q[1] = make_double2(z2, z3);
                 if (z32)
-                    *(float4*)(z32 + (oct * 8 + r) * d_pad + c0) =
+                    *(float4*)(z32 + zr * d_pad + c0) =
                         make_float4((float)z0, (float)z1, (float)z2, (float)z3);
             }
             continue;
@@ -507,11 +516,13 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
             float* dst = PREC == HBT_F32 ? (float*)zstore : z32;
 #pragma unroll
             for (int r = 0; r < 8; ++r)
-                *(float4*)(dst + (oct * 8 + r) * d_pad + c0) = make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
+                *(float4*)(dst + (pd.zrow0 + g0 + bf16_plane_row(o4, r)) * d_pad + c0) =
+                    make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
             if (PREC == HBT_F32 && z32)
 #pragma unroll
                 for (int r = 0; r < 8; ++r)
-                    *(float4*)(z32 + (oct * 8 + r) * d_pad + c0) = make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
+                    *(float4*)(z32 + (pd.zrow0 + g0 + bf16_plane_row(o4, r)) * d_pad + c0) =
+                        make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
         }
         if (PREC == HBT_BF16X2) {
 #pragma unroll
@@ -519,7 +530,8 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
                 uint32_t hi[4], lo[4];
 #pragma unroll
                 for (int r = 0; r < 8; r += 2) {
-                    const uint2 hl = split_bf16x2(zf[e][r], zf[e][r + 1]);
+                    const uint2 hl = split_bf16x2(zf[e][r] * bf16_plane_scale(o4, r),
+                                                  zf[e][r + 1] * bf16_plane_scale(o4, r + 1));
                     hi[r / 2] = hl.x;
                     lo[r / 2] = hl.y;
                 }

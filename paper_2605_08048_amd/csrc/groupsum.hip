@@ -24,19 +24,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// 8 mask bits -> 8 bf16 values 0.0 / 1.0 (bf16 1.0 = 0x3F80).
-__device__ __forceinline__ bf16x8 expand_bits_bf16(uint32_t byte) {
-    uint32_t w[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t two = (byte >> (2 * j)) & 3u;          // tokens 2j, 2j+1
-        const uint32_t spread = (two | (two << 15)) & 0x10001u; // bit0 -> bit0, bit1 -> bit16
-        w[j] = spread * 0x3F80u;
-    }
-    uint4 u = make_uint4(w[0], w[1], w[2], w[3]);
-    return __builtin_bit_cast(bf16x8, u);
-}
-
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
 
 // ---------------------------------------------------------------------------
@@ -51,9 +38,10 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast
 //  * Z streams through LDS in chunks of 128 pooled rows (16 octets; both
 //    planes of the 64-column slice = 32 KB) with direct global -> LDS loads,
 //    one chunk ahead, into two separate LDS objects.
-//  * Mask bytes become bf16 0/1 operands through a 16-entry nibble table in
-//    LDS (entry k = the four bf16 of nibble k): two conflict-free 8-byte
-//    reads per byte instead of bit arithmetic on the VALU.
+//  * Mask words become bf16 operands with one AND per register: a set bit
+//    lands in the exponent field (a power of two, not 1), and the stored
+//    planes hold each row divided by the power its bit meets, in the row
+//    order that makes this work (bf16_plane_row); no table, no LDS traffic.
 //  * Operands of K-step s+1 are read while the MFMAs of K-step s run.
 //  * Tiles are numbered so that the b-tiles of one (pair, column slice) go to
 //    one XCD (work-groups are dealt to the 8 XCDs round-robin), and the pair
@@ -131,7 +119,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __shared__ uint4 msk0[kMaskVec];
     __shared__ uint4 msk1[kMaskVec];
     __shared__ uint4 msk2[kMaskVec];
-    __shared__ uint2 lut[16];
     const int L = xcd_remap(blockIdx.x);
     if (L >= ntile_total) return;
     const int gi = upper_index(ngroups, L, [&](int k) { return groups[k].tile0; });
@@ -149,16 +136,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int h = lane >> 5, c = lane & 31;
     const int d0 = slot * kDSlot;
     const int nchunk = pd.Np / kChunk;
-
-    if (tid < 16) {
-        uint32_t w[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const uint32_t two = (tid >> (2 * q)) & 3u;
-            w[q] = (two & 1u ? 0x3F80u : 0u) | (two & 2u ? 0x3F800000u : 0u);
-        }
-        lut[tid] = make_uint2(w[0], w[1]);
-    }
+    const uint32_t rot = 8u * h;  // the upper lane half reads its rows 8 bits further on
 
     // splits of this lane's JB blocks (rows past the pair's splits are
     // loaded from its first row and zeroed by keep[] at use)
@@ -202,7 +180,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     issue(0, lds0, msk0);
     issue(last < 1 ? last : 1, lds1, msk1);
     __builtin_amdgcn_s_waitcnt(kWaitOneChunk);  // chunk 0 landed, chunk 1 may not have
-    __syncthreads();  // also publishes the nibble table
+    __syncthreads();
 
     f32x16 acc[2][JB];
 #pragma unroll
@@ -218,13 +196,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
         issue(ch + 2 < last ? ch + 2 : last, nxt, mnxt);
         // this chunk's mask words of the lane's JB splits (16-byte rows: a
-        // conflict-free 128-bit read per split), group flip and validity applied once
+        // conflict-free 128-bit read per split), group flip, validity and the
+        // lane half's rotation applied once
         uint4 mw[JB];
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
             const uint4 x = mcur[wave * kWS + 32 * j + c];
-            mw[j] = make_uint4((x.x ^ flip) & keep[j], (x.y ^ flip) & keep[j],
-                               (x.z ^ flip) & keep[j], (x.w ^ flip) & keep[j]);
+            auto prep = [&](uint32_t u) {
+                const uint32_t y = (u ^ flip) & keep[j];
+                return __builtin_amdgcn_alignbit(y, y, rot);
+            };
+            mw[j] = make_uint4(prep(x.x), prep(x.y), prep(x.z), prep(x.w));
         }
         // operands of K-step s: Z fragments (2 planes x 2 column blocks) and
         // the mask fragments of the JB split blocks
@@ -235,12 +217,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
                 a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
             }
+            // register e of the operand keeps exponent bit e of both bf16
+            // halves (the row order and scaling of the stored planes)
+            const uint32_t kBit = 0x00800080u << (4 * (s & 1));
 #pragma unroll
             for (int j = 0; j < JB; ++j) {
                 const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
-                const uint32_t byte = (word >> (8 * (2 * (s & 1) + h))) & 0xffu;
-                const uint2 lo = lut[byte & 15u], hi = lut[byte >> 4];
-                bm[j] = as_bf16x8(make_uint4(lo.x, lo.y, hi.x, hi.y));
+                bm[j] = as_bf16x8(make_uint4(word & kBit, word & (kBit << 1), word & (kBit << 2), word & (kBit << 3)));
             }
         };
         bf16x8 a[2][2][2], bm[2][JB];  // [buffer]...

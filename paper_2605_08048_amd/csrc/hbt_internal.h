@@ -158,6 +158,31 @@ __device__ __forceinline__ uint2 split_bf16x2(float a, float b) {
     return make_uint2(__builtin_bit_cast(uint32_t, hi), __builtin_bit_cast(uint32_t, lo));
 }
 
+// Split-BF16 row order and scaling.  The group-sum kernel turns a 32-bit
+// mask word (32 pooled rows) into its bf16 operand with one AND per register:
+// register e (0..7) of a lane is w & (0x00800080 << e), w the word rotated
+// right by 8 in the upper half of the wave.  A set bit thus becomes a bf16
+// whose only set bit is exponent bit e, the power of two 2^(2^e - 127)
+// instead of 1, and the rows that meet exponent bit e are stored divided by
+// it, so every product is the row value itself (scaling by a power of two is
+// exact, and |z| <= 1 keeps z * 2^126 finite).  Storage octet o4 = 2 s + h
+// (0..3) of a 32-row group, position k (0..7), holds group row
+// bf16_plane_row(o4, k), multiplied by bf16_plane_scale(o4, k).
+__host__ __device__ constexpr int bf16_plane_row(int o4, int k) {
+    return ((k & 1 ? 23 : 7) + 4 * (o4 >> 1) + (k >> 1) + 8 * (o4 & 1)) & 31;
+}
+constexpr bool bf16_plane_rows_ok() {  // a permutation of the 32 rows
+    uint32_t seen = 0;
+    for (int o = 0; o < 4; ++o)
+        for (int k = 0; k < 8; ++k) seen |= 1u << bf16_plane_row(o, k);
+    return seen == 0xffffffffu;
+}
+static_assert(bf16_plane_rows_ok(), "split-BF16 row order must be a permutation");
+__device__ __forceinline__ float bf16_plane_scale(int o4, int k) {
+    const int e = 4 * (o4 >> 1) + (k >> 1);
+    return __uint_as_float((uint32_t)(254 - (1 << e)) << 23);  // 2^(127 - 2^e)
+}
+
 // log g_d(r) of Sec. 3.1 ("Dispersion proxy"), in FP64.
 __device__ __forceinline__ double log_g(double r, double d, int gd) {
     if (gd == HBT_GD_IDENTITY) return log(r);
