@@ -29,6 +29,7 @@ sys.path.insert(0, str(ROOT))
 
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 MFMA
+INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 MFMA
 STAGES = ["align", "split", "groupsum", "stat", "recheck", "other"]
 
 
@@ -70,9 +71,9 @@ def counter_pass(args):
     res = torch.zeros(hbt.RESULT_BYTES * batch.npairs, dtype=torch.uint8, device=dev)
     for _ in range(2):
         hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
-                              precision="bf16x2", sync=False, results=res)
+                              precision=args.counter_precision, sync=False, results=res)
     torch.cuda.synchronize()
-    log("batched split-BF16 calls done")
+    log(f"batched {args.counter_precision} calls done")
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -164,9 +165,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) tile-width tuning of the split-BF16 product")
+    ap.add_argument("--counter-precision", default="bf16x2", help="precision of the --counter-pass calls")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run the batched path twice and a 1 GiB copy, for rocprofv3 --pmc")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH", "WRITE"),
@@ -249,6 +252,19 @@ def main():
               "speedup_bf16x2_over_fp32": value / v32,
               "pairs_with_equal_counts": f"{agree}/{P}"}
 
+    i8 = None
+    if args.i8_steps > 0:
+        dt8, ms8, l8, out8, bad8 = run("i8x3", args.i8_steps, 1)
+        log(f"int8 digit planes: {dt8 / args.i8_steps * 1e3:.2f} ms/step")
+        g8 = ms8[2] / max(l8[2], 1)
+        i8 = {"value": stats_per_step * args.i8_steps / dt8, "ms_per_step": dt8 / args.i8_steps * 1e3,
+              "groupsum_ms": g8, "groupsum_tops": algo_flops / (g8 * 1e-3) / 1e12,
+              "groupsum_frac_int8_peak": algo_flops / (g8 * 1e-3) / 1e12 / INT8_PEAK_TOPS,
+              "stages_ms_per_step": {k: ms8[i] / args.i8_steps for i, k in enumerate(STAGES)},
+              "rechecked_splits_per_step": int(out8["n_recheck"].sum()),
+              "pairs_bad_status": bad8,
+              "pairs_with_counts_equal_to_bf16x2": f"{int(np.sum(out8['count'] == out['count']))}/{P}"}
+
     line = {
         "metric": "permuted statistics/s at d=768 (batched split-BF16 MFMA; plain FP32 in fp32_plain)",
         "value": value,
@@ -274,6 +290,7 @@ def main():
         "pairs_bad_status": bad,
         "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
+        "int8_planes": i8,
         "tile_tuning": tuning,
     }
     if not args.no_cpu_baseline:

@@ -69,7 +69,11 @@ typedef enum hbt_status {
 typedef enum hbt_precision {
     HBT_F64 = 0,      /* group sums on FP64 MFMA */
     HBT_F32 = 1,      /* group sums on FP32 MFMA */
-    HBT_BF16X2 = 2    /* z = hi + lo split into two BF16 planes, FP32 accumulation */
+    HBT_BF16X2 = 2,   /* z = hi + lo split into two BF16 planes, FP32 accumulation */
+    HBT_I8X3 = 3      /* z rounded to 21-bit fixed point (z * 2^20), three balanced
+                         int8 digit planes on the int8 MFMA: exact integer group
+                         sums, FP64 epilogue; the 8-bit-operand variant of the
+                         group-sum product (route 0 only) */
 } hbt_precision;
 
 typedef enum hbt_dtype { HBT_IN_F32 = 0, HBT_IN_F64 = 1 } hbt_dtype;

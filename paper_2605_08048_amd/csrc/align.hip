@@ -292,6 +292,10 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 //                contiguous per column, the operand layout of the bf16 MFMA;
 //                storage octet 4 g + o4 holds rows 32 g + bf16_plane_row(o4, k)
 //                of the pair, scaled by bf16_plane_scale(o4, k) (k = 0..7).
+//   HBT_I8X3   : three planes (q0, q1, q2 at +zplane_elems bytes each) of
+//                int8 digits [Np/16][d_pad][16]; storage octet 4 g + o4
+//                fills bytes 8 (o4 & 1) .. +7 of unit 2 g + o4 / 2 with rows
+//                32 g + i8_plane_row(o4, k).
 // A work-group (or wave) handles the 8 rows of one storage octet for every
 // format; the row-major formats simply write each row in its place.
 template <typename Tin, int PREC>
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // coefficients 2 (v . x_i) / (v . v) of the X rows (eq:householder_fast)
     for (int r = wave; r < 8; r += 4) {
-        const int i = g0 + bf16_plane_row(o4, r);
+        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r));
         double w = 0.0;
         if (!identity && i < pd.n) {
             const Tin* x = (const Tin*)pd.X + (int64_t)i * d;
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
         const double vc = c < d ? vp[c] : 0.0;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int i = g0 + bf16_plane_row(o4, r);
+            const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r));
             double val = 0.0;
             if (c < d) {
                 if (i < pd.n)
@@ -347,7 +351,20 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
             for (int r = 0; r < 8; ++r)
                 z32[(pd.zrow0 + g0 + bf16_plane_row(o4, r)) * (int64_t)d_pad + c] = (float)z[r];
         }
-        if (PREC == HBT_BF16X2) {
+        if (PREC == HBT_I8X3) {
+            uint32_t w[3][2] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                uint32_t q[3];
+                i8_digits(z[r], q[0], q[1], q[2]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) w[k][r >> 2] |= q[k] << (8 * (r & 3));
+            }
+            uint2* dst = (uint2*)((char*)zstore + ((oct >> 1) * d_pad + c) * 16 + 8 * (oct & 1));
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                *(uint2*)((char*)dst + k * zplane_elems) = make_uint2(w[k][0], w[k][1]);
+        } else if (PREC == HBT_BF16X2) {
             uint32_t hi[4], lo[4];
 #pragma unroll
             for (int r = 0; r < 8; r += 2) {
@@ -386,6 +403,10 @@ static hipError_t launch_reflect_t(int precision, const PairDesc* pairs, int npa
         case HBT_F32:
             hipLaunchKernelGGL((k_reflect<Tin, HBT_F32>), g, b, 0, s, pairs, npairs, st, v, d, d_pad,
                                coef, z, ze, z32);
+            break;
+        case HBT_I8X3:
+            hipLaunchKernelGGL((k_reflect<Tin, HBT_I8X3>), g, b, 0, s, pairs, npairs, st, v, d,
+                               d_pad, coef, z, ze, z32);
             break;
         default:
             hipLaunchKernelGGL((k_reflect<Tin, HBT_BF16X2>), g, b, 0, s, pairs, npairs, st, v, d,
@@ -439,7 +460,7 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     float4 x[8][J];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = g0 + bf16_plane_row(o4, r);  // wave-uniform
+        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r));  // wave-uniform
         const float* row = i < pd.n ? (const float*)pd.X + (int64_t)i * d
                                     : (const float*)pd.Y + (int64_t)(i - pd.n) * d;
 #pragma unroll
@@ -460,7 +481,7 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     double k[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = g0 + bf16_plane_row(o4, r);
+        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r));
         k[r] = 0.0;
         if (!identity && i < pd.n) {  // wave-uniform
             double w = 0.0;
@@ -481,7 +502,7 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
         double kr = k[0];
 #pragma unroll
         for (int r = 1; r < 8; ++r) kr = lane == r ? k[r] : kr;
-        const int i = g0 + bf16_plane_row(o4, lane);
+        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, lane) : bf16_plane_row(o4, lane));
         if (i < pd.n) coef[pd.coef0 + i] = kr;
     }
 #pragma unroll
@@ -500,6 +521,24 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
                 if (z32)
                     *(float4*)(z32 + zr * d_pad + c0) =
                         make_float4((float)z0, (float)z1, (float)z2, (float)z3);
+            }
+            continue;
+        }
+        if (PREC == HBT_I8X3) {  // digits of the FP64 update
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t w[3][2] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const float xe = e == 0 ? x[r][j].x : e == 1 ? x[r][j].y : e == 2 ? x[r][j].z : x[r][j].w;
+                    uint32_t q[3];
+                    i8_digits((double)xe - k[r] * vc[j][e], q[0], q[1], q[2]);
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) w[t][r >> 2] |= q[t] << (8 * (r & 3));
+                }
+                char* dst = (char*)zstore + ((oct >> 1) * d_pad + c0 + e) * 16 + 8 * (oct & 1);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) *(uint2*)(dst + t * zplane_elems) = make_uint2(w[t][0], w[t][1]);
             }
             continue;
         }
@@ -564,6 +603,7 @@ hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
     switch (precision) {
         case HBT_F64: HBT_R4J(HBT_F64); break;
         case HBT_F32: HBT_R4J(HBT_F32); break;
+        case HBT_I8X3: HBT_R4J(HBT_I8X3); break;
         default: HBT_R4J(HBT_BF16X2); break;
     }
 #undef HBT_R4J

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -80,20 +81,25 @@ int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
 // over the k items and d columns of the smaller group.  Measured worst cases
 // on MI355X (35 shapes, n and m from 2 to 5000, d = 64 ... 1024, r up to
 // 0.997): 2.5e-7 (F32), 1.6e-6 (split BF16, n = 2, d = 64); the constants
-// below are >= 9x those.
+// below are >= 9x those.  The int8 planes hold z to an absolute 2^-21
+// (split BF16: relative 2^-17, i.e. about 2^-17 / sqrt(d) absolute for unit
+// rows), so their storage term is the BF16 one times 2^-4 sqrt(d); their sums
+// are exact and the epilogue is FP64.
 struct Band {
     double e_acc, e_store;
 };
-Band precision_band(int precision) {
+Band precision_band(int precision, int d) {
     switch (precision) {
         case HBT_F64: return Band{1e-12, 0.0};
         case HBT_F32: return Band{4e-6, 0.0};
+        case HBT_I8X3: return Band{1e-10, 16.0 * 2.3 / 2097152.0 * std::sqrt((double)d)};
         default: return Band{4e-6, 16.0 * 2.3 / 131072.0};
     }
 }
 
 size_t zstore_bytes(int precision, int64_t rows, int64_t d_pad) {
-    return (size_t)rows * d_pad * (precision == HBT_F64 ? 8 : 4);
+    const int bytes = precision == HBT_F64 ? 8 : precision == HBT_I8X3 ? 3 : 4;
+    return (size_t)rows * d_pad * bytes;
 }
 
 // Bump allocator over the caller's workspace (256-byte aligned slices).
@@ -252,7 +258,7 @@ void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint3
 }
 
 hbt_status check_enums(const hbt_perm_params* prm) {
-    if (prm->precision < HBT_F64 || prm->precision > HBT_BF16X2)
+    if (prm->precision < HBT_F64 || prm->precision > HBT_I8X3)
         return fail(HBT_ERR_ARG, "unknown precision %d", prm->precision);
     if (prm->input_dtype != HBT_IN_F32 && prm->input_dtype != HBT_IN_F64)
         return fail(HBT_ERR_DTYPE, "unknown input dtype %d", prm->input_dtype);
@@ -263,6 +269,8 @@ hbt_status check_enums(const hbt_perm_params* prm) {
     if (prm->align != 0 && prm->align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
     if (prm->stat_route != 0 && prm->stat_route != 1)
         return fail(HBT_ERR_ARG, "unknown stat_route %d", prm->stat_route);
+    if (prm->stat_route == 1 && prm->precision == HBT_I8X3)
+        return fail(HBT_ERR_UNSUPPORTED, "the int8 planes compute the statistic by route 0 only");
     if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64))
         return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
     return HBT_OK;
@@ -316,7 +324,7 @@ void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B) {
     const TileCost tc = tile_cost(P.d_pad);
     std::vector<GemmGroup> g2;
     for (int p : order) {
-        const int w = choose_width(B[p], tc);
+        const int w = P.precision == HBT_I8X3 ? kTileI8 : choose_width(B[p], tc);
         const int nbt = (int)((B[p] + w - 1) / w);
         if (w == 512) {
             P.groups.push_back(GemmGroup{p, nbt, P.nt512});
@@ -490,7 +498,7 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
 // ---------------------------------------------------------------------------
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm) {
     if (!prm || check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset) ||
-        prm->precision < HBT_F64 || prm->precision > HBT_BF16X2) {
+        prm->precision < HBT_F64 || prm->precision > HBT_I8X3) {
         return 0;
     }
     int64_t B0;
@@ -537,13 +545,13 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             HIP_TRY(launch_row_dot_t(w.pairs, 1, z32, w.t64, P.d_pad, P.zrows, w.zt, s));
         }
     }
-    const Band band = precision_band(P.precision);
+    const Band band = precision_band(P.precision, P.d);
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
     const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
     for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
         const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
         BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
-        const int wdt = choose_width(nb, tile_cost(P.d_pad));
+        const int wdt = P.precision == HBT_I8X3 ? kTileI8 : choose_width(nb, tile_cost(P.d_pad));
         const GemmGroup grp{0, (int32_t)((nb + wdt - 1) / wdt), 0};
         {
             StageTimer t_(HBT_STAGE_OTHER, s);
@@ -623,7 +631,7 @@ size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, co
                                             const int64_t* B, int64_t d,
                                             const hbt_perm_params* common) {
     if (npairs < 1 || !n || !m || !B || !common) return 0;
-    if (common->precision < HBT_F64 || common->precision > HBT_BF16X2) return 0;
+    if (common->precision < HBT_F64 || common->precision > HBT_I8X3) return 0;
     for (int64_t p = 0; p < npairs; ++p)
         if (check_sizes(n[p], m[p], d, B[p], common->perm_offset)) return 0;
     std::vector<int64_t> off((size_t)npairs + 1, 0);
@@ -668,7 +676,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     {
         StageTimer t_(HBT_STAGE_OTHER, s);
         HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
-        if (P.precision == HBT_BF16X2)
+        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
             HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
         else
             HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
@@ -689,8 +697,8 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     }
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
     { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
-                        common->alternative, precision_band(P.precision).e_acc,
-                        precision_band(P.precision).e_store, no_recheck, nullptr,
+                        common->alternative, precision_band(P.precision, P.d).e_acc,
+                        precision_band(P.precision, P.d).e_store, no_recheck, nullptr,
                         false, w.tw, w.cnt, w.flags, w.nflag, s)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);

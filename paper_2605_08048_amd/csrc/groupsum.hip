@@ -289,6 +289,194 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 // ---------------------------------------------------------------------------
+// int8 digit planes: z 2^20 = q0 2^14 + q1 2^7 + q2, stored as the planes
+// (q0, -q1, q2).  Two exact int32 sums per output on v_mfma_i32_32x32x32_i8:
+//   S_hi = Q0^T M,   S_lo = (-Q1)^T (-128 M) + Q2^T M = 128 Q1^T M + Q2^T M
+// (the mask byte -128 is 0x80), so sigma = (S_hi 2^14 + S_lo) 2^-20 in FP64.
+// A (32 x 32) lane l -> row l%32, k 16(l/32)..+15; B (32 x 32) lane l ->
+// k 16(l/32)..+15, col l%32; D lane l -> col l%32, rows 8(v/4) + 4(l/32) + v%4.
+//
+// Work-group tile: 64 columns x kTileI8 (512) splits; wave w owns splits
+// [128 w, 128 w + 128) as 4 blocks of 32 and the 64 columns as 2 blocks of
+// 32 (accumulators 2 sums x 2 x 4 x 16 int32 per lane, all of the AGPRs).
+// A K-step is 32 pooled rows, one mask word: operand register s of lane
+// half h is (word >> (s + 4 h)) & 0x01010101 (the planes' row order makes
+// those the lane's rows), and that shifted left by 7 for the middle plane.
+// Z streams through LDS in chunks of 128 rows (three planes of the 64
+// columns = 24 KB, mask words 8 KB), as in the split-BF16 kernel.  Splits
+// past the block's end take the mask of its first split and are not written.
+// ---------------------------------------------------------------------------
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+constexpr int kHex = kChunk / 16;                  // 16-row units per chunk
+constexpr int kChunkVecI8 = 3 * kHex * kDSlot;     // uint4 per chunk (three planes)
+// |S_lo| <= 64 N (2^7 + 1) and |S_hi| <= 64 N must stay int32 for every pooled size
+static_assert(64LL * HBT_MAX_N * 129 < (1LL << 31), "int8 digit sums overflow int32");
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_i8x3(
+    const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
+    const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
+    const uint4* __restrict__ zq, int64_t plane_vec, const uint32_t* __restrict__ mask,
+    const double* __restrict__ t64, double* __restrict__ partial) {
+    constexpr int JB = 4, kWS = 32 * JB;        // splits per wave
+    constexpr int kRowsPerWave = 3 * kHex / 4;  // LDS rows of Z each wave loads (6)
+    constexpr int kMaskLoads = kWS / 64;        // mask loads per wave per chunk
+    constexpr int kWaitOneChunk = wait_vmcnt(kRowsPerWave + kMaskLoads);
+    static_assert(kTileI8 == 4 * kWS, "tile width");
+    __shared__ uint4 lds0[kChunkVecI8];
+    __shared__ uint4 lds1[kChunkVecI8];
+    __shared__ uint4 lds2[kChunkVecI8];
+    __shared__ uint4 msk0[kTileI8];
+    __shared__ uint4 msk1[kTileI8];
+    __shared__ uint4 msk2[kTileI8];
+    const int L = xcd_remap(blockIdx.x);
+    if (L >= ntile_total) return;
+    const int gi = upper_index(ngroups, L, [&](int k) { return groups[k].tile0; });
+    const GemmGroup grp = groups[gi];
+    const int local = L - (int)grp.tile0;
+    const int slot = local / grp.nbt;
+    const int b0 = (local % grp.nbt) * kTileI8;
+    const PairDesc pd = pairs[grp.pair];
+    const BlockPair bq = bp[grp.pair];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int h = lane >> 5, c = lane & 31;
+    const int d0 = slot * kDSlot;
+    const int nchunk = pd.Np / kChunk;
+    const uint32_t rsh = 4u * h;
+    const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+    int brow[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) brow[j] = b0 + wave * kWS + j * 32 + c;
+    // mask rows this lane moves into LDS: splits kWS w + 64 k + l of the tile
+    const uint4* mload[kMaskLoads];
+#pragma unroll
+    for (int k = 0; k < kMaskLoads; ++k) {
+        const int r = b0 + kWS * wave + 64 * k + lane;
+        mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
+    }
+
+    // chunk loader: LDS rows (plane, unit) 6 w .. 6 w + 5, lane l moving column l
+    const int64_t hex0 = pd.zrow0 >> 4;
+    auto issue = [&](int ch, uint4* dst, uint4* mdst) {
+#pragma unroll
+        for (int k = 0; k < kRowsPerWave; ++k) {
+            const int r = kRowsPerWave * wave + k;  // wave-uniform
+            const uint4* src = zq + (r / kHex) * plane_vec + (hex0 + (int64_t)kHex * ch + r % kHex) * d_pad + d0;
+            dma16(src + lane, __builtin_amdgcn_readfirstlane(lds_addr(dst + r * kDSlot)));
+        }
+        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(mdst + kWS * wave));
+#pragma unroll
+        for (int k = 0; k < kMaskLoads; ++k) dma16(mload[k] + ch, ml + 16 * 64 * k);
+    };
+    const int last = nchunk - 1;
+    issue(0, lds0, msk0);
+    issue(last < 1 ? last : 1, lds1, msk1);
+    __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+    __syncthreads();
+
+    i32x16 acc[2][2][JB];  // [S_hi, S_lo][column block][split block]
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < JB; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[q][i][j][v] = 0;
+
+    auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
+        issue(ch + 2 < last ? ch + 2 : last, nxt, mnxt);
+        // the chunk's mask words of the lane's splits: group flip, lane-half shift
+        uint4 mw[JB];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            const uint4 x = mcur[kWS * wave + 32 * j + c];
+            mw[j] = make_uint4((x.x ^ flip) >> rsh, (x.y ^ flip) >> rsh, (x.z ^ flip) >> rsh, (x.w ^ flip) >> rsh);
+        }
+        auto fetch = [&](int s, i32x4 (&a)[3][2], i32x4 (&bm)[JB]) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const uint4 u = cur[(q * kHex + 2 * s + h) * kDSlot + 32 * i + c];
+                    a[q][i] = i32x4{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+                }
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const uint32_t w = s == 0 ? mw[j].x : s == 1 ? mw[j].y : s == 2 ? mw[j].z : mw[j].w;
+                bm[j] = i32x4{(int)(w & 0x01010101u), (int)((w >> 1) & 0x01010101u),
+                              (int)((w >> 2) & 0x01010101u), (int)((w >> 3) & 0x01010101u)};
+            }
+        };
+        i32x4 a[2][3][2], bm[2][JB];
+        fetch(0, a[0], bm[0]);
+#pragma unroll
+        for (int s = 0; s < kChunk / 32; ++s) {  // K-steps of 32 pooled rows
+            if (s + 1 < kChunk / 32) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
+            const int b = s & 1;
+            // middle plane first, then the high plane, then the low plane into
+            // the same sum as the middle one: 16 MFMAs between dependent ones
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < JB; ++j) {
+                    const i32x4 m128 = bm[b][j] << 7;  // bytes 0x80 = -128 where the mask is set
+                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[b][1][i], m128, acc[1][i][j], 0, 0, 0);
+                }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < JB; ++j)
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[b][0][i], bm[b][j], acc[0][i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < JB; ++j)
+                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[b][2][i], bm[b][j], acc[1][i][j], 0, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+        lds_barrier();
+    };
+    for (int ch = 0; ch < nchunk; ch += 3) {
+        step(ch, lds0, msk0, lds2, msk2);
+        if (ch + 1 < nchunk) step(ch + 1, lds1, msk1, lds0, msk0);
+        if (ch + 2 < nchunk) step(ch + 2, lds2, msk2, lds1, msk1);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the loads past the end
+
+    // epilogue: sigma_small in FP64, squared norms of sigma_small and
+    // t - sigma_small over the slot's 64 columns
+    const double* tp = t64 + (int64_t)grp.pair * d_pad + d0;
+    double tv[2][16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        double ss = 0.0, sl = 0.0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const double sv = __builtin_fma((double)acc[0][i][j][v], 16384.0, (double)acc[1][i][j][v]) *
+                                  (1.0 / 1048576.0);
+                const double lv = tv[i][v] - sv;
+                ss += sv * sv;
+                sl += lv * lv;
+            }
+        ss += __shfl_xor(ss, 32, 64);
+        sl += __shfl_xor(sl, 32, 64);
+        if (h == 0 && brow[j] < bq.nb) {
+            double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + slot;
+            *out = make_double2(ss, sl);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP32 / FP64: v_mfma_{f32_16x16x4f32, f64_16x16x4f64}
 // A (16 x 4) lane l -> row l%16, k l/16; B (4 x 16) lane l -> k l/16, col l%16;
 // D lane l -> col l%16, register v -> row 4(l/16) + v (f32) or 4v + l/16 (f64).
@@ -421,6 +609,12 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                                    mask, t32, partial, sig);
             break;
         }
+        case HBT_I8X3:
+            if (nt512 > 0)
+                hipLaunchKernelGGL(k_groupsum_i8x3, dim3((unsigned)((nt512 + 31) / 32 * 32)), block, 0, s,
+                                   pairs, bp, groups, ng512, nt512, nslot, d_pad, (const uint4*)zstore,
+                                   zplane_elems / 16, mask, t64, partial);
+            break;
         case HBT_F32:
             if (ntiles <= 0) return hipSuccess;
             hipLaunchKernelGGL(k_groupsum_fp<float>, dim3((unsigned)(ntiles * nslot)), block, 0, s,

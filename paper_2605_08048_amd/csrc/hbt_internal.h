@@ -17,6 +17,8 @@ constexpr int kDPad = 64;
 // Each group-sum tile reduces its squared norms over kDSlot columns; the
 // statistic kernel adds the d_pad / kDSlot slots of a split row in FP64.
 constexpr int kDSlot = 64;
+// Splits per work-group of the int8 digit-plane kernel (one tile width).
+constexpr int kTileI8 = 512;
 // Split rows per group-sum tile (4 waves x 64 rows).
 constexpr int kTileB = 256;
 // Capacity of the boundary bucket of the split selection (items whose
@@ -181,6 +183,39 @@ static_assert(bf16_plane_rows_ok(), "split-BF16 row order must be a permutation"
 __device__ __forceinline__ float bf16_plane_scale(int o4, int k) {
     const int e = 4 * (o4 >> 1) + (k >> 1);
     return __uint_as_float((uint32_t)(254 - (1 << e)) << 23);  // 2^(127 - 2^e)
+}
+
+// Int8 digit planes.  z is rounded to Q = round(z 2^20) and written as three
+// balanced base-128 digits, Q = q0 2^14 + q1 2^7 + q2 (q1, q2 in [-64, 63],
+// |q0| <= 64 for |z| <= 1), stored as the int8 planes q0, -q1, q2 (the
+// group-sum kernel multiplies the middle plane by the mask byte -128, which
+// folds 2^7 q1 into the sum of q2 exactly).  Storage unit: 16 rows of one column
+// (16 bytes, the int8 MFMA operand of one lane); unit h (0, 1) of a 32-row
+// group, byte p = 4 s + b, holds group row s + 4 h + 8 b, so that the group-sum
+// kernel makes operand register s of lane half h as (w >> (s + 4 h)) &
+// 0x01010101 from the group's mask word w.  A wave of the reflection writes
+// half a unit: storage octet o4 (0..3) of a group = unit o4 / 2, bytes
+// 8 (o4 & 1) .. +7, position k (0..7) holding group row i8_plane_row(o4, k).
+__host__ __device__ constexpr int i8_plane_row(int o4, int k) {
+    return 2 * (o4 & 1) + (k >> 2) + 4 * (o4 >> 1) + 8 * (k & 3);
+}
+constexpr bool i8_plane_rows_ok() {
+    uint32_t seen = 0;
+    for (int o = 0; o < 4; ++o)
+        for (int k = 0; k < 8; ++k) seen |= 1u << i8_plane_row(o, k);
+    return seen == 0xffffffffu;
+}
+static_assert(i8_plane_rows_ok(), "int8 row order must be a permutation");
+// the three plane bytes of z: q0, -q1, q2
+__device__ __forceinline__ void i8_digits(double z, uint32_t& q0, uint32_t& q1, uint32_t& q2) {
+    const int Q = __double2int_rn(z * 1048576.0);
+    const int d2 = ((Q + 64) & 127) - 64;
+    const int Q1 = (Q - d2) >> 7;  // exact: Q - d2 is a multiple of 128
+    const int d1 = ((Q1 + 64) & 127) - 64;
+    const int d0 = (Q1 - d1) >> 7;
+    q0 = (uint32_t)d0 & 0xffu;
+    q1 = (uint32_t)(-d1) & 0xffu;  // stored negated
+    q2 = (uint32_t)d2 & 0xffu;
 }
 
 // log g_d(r) of Sec. 3.1 ("Dispersion proxy"), in FP64.

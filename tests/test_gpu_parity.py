@@ -4,7 +4,7 @@ Bars (per result, against FP64):
   * random splits and their masks: bit-exact;
   * Householder: r, T_obs in FP64 to 1e-12; aligned rows in the input dtype;
   * permuted statistics T_b: |T_gpu - T_64| <= tol * (|f(r1)| + |f(r2)|) with
-    tol = 1e-10 (F64), 1e-5 (F32), 1e-4 (split BF16);
+    tol = 1e-10 (F64), 1e-5 (F32), 1e-4 (split BF16, int8 digit planes);
   * exceedance counts: equal, except for splits with |T_64 - T_obs| <=
     1e-6 |T_obs| (none of which occur in these cases, so counts are equal);
   * p = (1 + count) / (B + 1) exactly.
@@ -24,7 +24,7 @@ pytestmark = [pytest.mark.gpu,
 from paper_2605_08048_amd import hbt  # noqa: E402
 
 DEV = "cuda:0"
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4}
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "i8x3": 1e-4}
 
 
 def _dev(a, dtype=None):
@@ -122,6 +122,12 @@ CASES = [
     (300, 450, 768, 600, "f32", False),
     (40, 70, 37, 300, "f32", False),    # d % 4 != 0: the scalar-load alignment kernels
     (70, 40, 37, 300, "bf16x2", False),
+    (50, 60, 64, 999, "i8x3", True),    # int8 digit planes: FP64 input, exact integer sums
+    (37, 150, 100, 700, "i8x3", False),
+    (150, 37, 100, 700, "i8x3", False),
+    (300, 450, 768, 600, "i8x3", False),
+    (70, 40, 37, 300, "i8x3", False),
+    (2, 5000, 1024, 300, "i8x3", False),  # the smallest group, widest supported d in one slot set
 ]
 
 
@@ -169,7 +175,7 @@ def test_exhaustive_70_splits_with_explicit_masks():
         sel[k, list(c)] = True
     masks = O.bool_to_mask(sel)
     ex = O.exhaustive(X, Y)
-    for prec in ["f64", "f32", "bf16x2"]:
+    for prec in ["f64", "f32", "bf16x2", "i8x3"]:
         r = hbt.perm_test(_dev(X), _dev(Y), 70, precision=prec, masks=masks)
         assert r["status"] == 0
         assert r["count"] == ex["count"]
@@ -184,7 +190,7 @@ def test_bad_explicit_mask_is_reported():
     assert r["status"] == hbt.ERR_MASK
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x2"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
 def test_block_size_offsets_and_repeat_do_not_change_results(prec):
     X, Y = _pair(500, 700, 128, kx=2.0, ky=2.05, seed=13)
     Xd, Yd = _dev(X), _dev(Y)
@@ -223,6 +229,39 @@ def test_no_recheck_flag_counts_raw_precision():
     assert abs(r["count"] - int(np.sum(r["T"].astype(np.float64) >= thr))) <= 2
 
 
+def test_i8x3_equals_exact_sums_of_rounded_rows():
+    """The int8 digit planes hold round(z 2^20) exactly and their products with
+    the masks are summed in integers, so without the FP64 recheck each T_b is
+    the statistic of the rounded rows' sum over the smaller group, and of t
+    minus that sum for the larger one, up to FP64 rounding."""
+    for n, m, d in [(90, 200, 256), (203, 61, 100)]:
+        B = 150
+        X, Y = _pair(n, m, d, seed=31 + n)
+        r = hbt.perm_test(_dev(X), _dev(Y), B, seed=4, precision="i8x3", recheck=False, want_T="f64")
+        a = O.align(X, Y)
+        Z = np.vstack([a["Xp"], Y.astype(np.float64)])
+        Zq = np.rint(Z * 2.0 ** 20) / 2.0 ** 20
+        t = Z.sum(0)
+        N = n + m
+        T = np.empty(B)
+        for b in range(B):
+            g1 = O.mask_to_bool(O.split_mask(4, 0, b, N, n), N)
+            if n <= m:
+                s1 = Zq[g1].sum(0)
+                s2 = t - s1
+            else:
+                s2 = Zq[~g1].sum(0)
+                s1 = t - s2
+            T[b] = O.log_g(np.linalg.norm(s2) / m, d) - O.log_g(np.linalg.norm(s1) / n, d)
+        assert np.abs(r["T"] - T).max() <= 1e-9, (n, m, np.abs(r["T"] - T).max())
+
+
+def test_i8x3_rejects_point_to_centroid_route():
+    X, Y = _pair(20, 30, 16, seed=32)
+    with pytest.raises(RuntimeError, match="route 0 only"):
+        hbt.perm_test(_dev(X), _dev(Y), 10, precision="i8x3", stat_route=1)
+
+
 # --------------------------------------------------------------------- point-to-centroid route
 
 @pytest.mark.parametrize("n,m,d,prec", [(37, 150, 100, "f32"), (150, 37, 100, "bf16x2"),
@@ -254,7 +293,7 @@ def test_batched_matches_oracle_per_pair():
         pairs.append(synth.Pair(X, Y, B=int(rng.integers(1, 700)), pair_index=p))
     pairs[3] = synth.Pair(pairs[3].X, pairs[3].X.copy(), B=300, pair_index=3)  # identical groups
     bt = synth.pack_batch(pairs, 96)
-    for prec in ["f32", "bf16x2", "f64"]:
+    for prec in ["f32", "bf16x2", "f64", "i8x3"]:
         res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=9, precision=prec)
         for p, pr in enumerate(pairs):
             o = O.perm_test(pr.X, pr.Y, pr.B, seed=9, pair=p, want_T=True)
@@ -289,7 +328,7 @@ def test_pair_d768_point_to_centroid_sampled(prec):
     assert (np.abs(r["T"][sample] - at["T"]) / _scale(c.X, c.Y, at)).max() <= 1e-5
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x2"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
 def test_pair_d768_full_size(prec):
     print(f"pair_d768 {prec}", flush=True)
     c = synth.pair_d768()
