@@ -429,10 +429,12 @@ hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs,
 }
 
 // The same reflection and storage for FP32 rows with d a multiple of 4 and
-// 16-byte aligned rows: one wave per octet, the octet's 8 rows held in
-// registers (lane l: columns 4(l + 64 j) .. +3, j < J), loaded once with
-// 16-byte loads; the coefficients are FP64 wave reductions and every lane
-// then writes its 4 consecutive columns of the octet.
+// 16-byte aligned rows (the condition shared with the vector column sums):
+// one wave per octet, the octet's 8 rows held in registers (lane l: columns
+// 256 j + 64 e + l, j < J, e < 4, each load instruction reading 256
+// contiguous bytes of a row); the coefficients are FP64 wave reductions, and
+// every store instruction then writes one contiguous run of columns (1 KB per
+// plane for split BF16).
 __device__ __forceinline__ double wave_sum_f64(double x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -457,38 +459,36 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     const int lo8 = (int)(oct - pd.zrow0 / 8);  // storage octet within the pair
     const int g0 = 32 * (lo8 >> 2), o4 = lo8 & 3;
     const int N = pd.n + pd.m;
-    float4 x[8][J];
+    auto row_of = [&](int r) { return g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r)); };
+    auto col = [&](int j, int e) { return 256 * j + 64 * e + lane; };
+    float x[8][J][4];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r));  // wave-uniform
+        const int i = row_of(r);  // wave-uniform
         const float* row = i < pd.n ? (const float*)pd.X + (int64_t)i * d
                                     : (const float*)pd.Y + (int64_t)(i - pd.n) * d;
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int c = 4 * (lane + 64 * j);
-            x[r][j] = (i < N && c < d) ? *(const float4*)(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[r][j][e] = (i < N && col(j, e) < d) ? row[col(j, e)] : 0.f;
     }
     double vc[J][4];
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = 4 * (lane + 64 * j) + e;
-            vc[j][e] = c < d ? vp[c] : 0.0;
-        }
+        for (int e = 0; e < 4; ++e) vc[j][e] = col(j, e) < d ? vp[col(j, e)] : 0.0;
     // coefficients 2 (v . x_i) / (v . v) of the X rows (eq:householder_fast)
     double k[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r));
+        const int i = row_of(r);
         k[r] = 0.0;
         if (!identity && i < pd.n) {  // wave-uniform
             double w = 0.0;
 #pragma unroll
             for (int j = 0; j < J; ++j)
-                w += vc[j][0] * (double)x[r][j].x + vc[j][1] * (double)x[r][j].y +
-                     vc[j][2] * (double)x[r][j].z + vc[j][3] * (double)x[r][j].w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w += vc[j][e] * (double)x[r][j][e];
             k[r] = 2.0 * wave_sum_f64(w) / vv;
         }
     }
@@ -497,89 +497,70 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
 #pragma unroll
     for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int j = 0; j < J; ++j) asm volatile("" : "+v"(x[r][j].x), "+v"(x[r][j].y), "+v"(x[r][j].z), "+v"(x[r][j].w));
+        for (int j = 0; j < J; ++j)
+            asm volatile("" : "+v"(x[r][j][0]), "+v"(x[r][j][1]), "+v"(x[r][j][2]), "+v"(x[r][j][3]));
     if (lane < 8) {
         double kr = k[0];
 #pragma unroll
         for (int r = 1; r < 8; ++r) kr = lane == r ? k[r] : kr;
-        const int i = g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, lane) : bf16_plane_row(o4, lane));
+        const int i = row_of(lane);
         if (i < pd.n) coef[pd.coef0 + i] = kr;
     }
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int c0 = 4 * (lane + 64 * j);
-        if (c0 >= d_pad) continue;
-        if (PREC == HBT_F64) {
+    for (int j = 0; j < J; ++j)
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int64_t zr = pd.zrow0 + g0 + bf16_plane_row(o4, r);
-                double2* q = (double2*)((double*)zstore + zr * d_pad + c0);
-                const double z0 = (double)x[r][j].x - k[r] * vc[j][0], z1 = (double)x[r][j].y - k[r] * vc[j][1];
-                const double z2 = (double)x[r][j].z - k[r] * vc[j][2], z3 = (double)x[r][j].w - k[r] * vc[j][3];
-                q[0] = make_double2(z0, z1);
-                q[1] = make_double2(z2, z3);
-                if (z32)
-                    *(float4*)(z32 + zr * d_pad + c0) =
-                        make_float4((float)z0, (float)z1, (float)z2, (float)z3);
+        for (int e = 0; e < 4; ++e) {
+            const int c = col(j, e);
+            if (256 * j + 64 * e >= d_pad) continue;  // wave-uniform: d_pad is a multiple of 64
+            if (PREC == HBT_F64) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int64_t zr = pd.zrow0 + row_of(r);
+                    const double z = (double)x[r][j][e] - k[r] * vc[j][e];
+                    ((double*)zstore)[zr * d_pad + c] = z;
+                    if (z32) z32[zr * d_pad + c] = (float)z;
+                }
+                continue;
             }
-            continue;
-        }
-        if (PREC == HBT_I8X3) {  // digits of the FP64 update
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            if (PREC == HBT_I8X3) {  // digits of the FP64 update
                 uint32_t w[3][2] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
-                    const float xe = e == 0 ? x[r][j].x : e == 1 ? x[r][j].y : e == 2 ? x[r][j].z : x[r][j].w;
                     uint32_t q[3];
-                    i8_digits((double)xe - k[r] * vc[j][e], q[0], q[1], q[2]);
+                    i8_digits((double)x[r][j][e] - k[r] * vc[j][e], q[0], q[1], q[2]);
 #pragma unroll
                     for (int t = 0; t < 3; ++t) w[t][r >> 2] |= q[t] << (8 * (r & 3));
                 }
-                char* dst = (char*)zstore + ((oct >> 1) * d_pad + c0 + e) * 16 + 8 * (oct & 1);
+                char* dst = (char*)zstore + ((oct >> 1) * d_pad + c) * 16 + 8 * (oct & 1);
 #pragma unroll
                 for (int t = 0; t < 3; ++t) *(uint2*)(dst + t * zplane_elems) = make_uint2(w[t][0], w[t][1]);
+                continue;
             }
-            continue;
-        }
-        // FP64 update, rounded to FP32 at once (the storage is FP32 or BF16 hi+lo)
-        float zf[4][8];  // [column][row]
+            // FP64 update, rounded to FP32 at once (the storage is FP32 or BF16 hi+lo)
+            float zf[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            zf[0][r] = (float)((double)x[r][j].x - k[r] * vc[j][0]);
-            zf[1][r] = (float)((double)x[r][j].y - k[r] * vc[j][1]);
-            zf[2][r] = (float)((double)x[r][j].z - k[r] * vc[j][2]);
-            zf[3][r] = (float)((double)x[r][j].w - k[r] * vc[j][3]);
-        }
-        if (PREC == HBT_F32 || z32) {
-            float* dst = PREC == HBT_F32 ? (float*)zstore : z32;
+            for (int r = 0; r < 8; ++r) zf[r] = (float)((double)x[r][j][e] - k[r] * vc[j][e]);
+            if (PREC == HBT_F32 || z32) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
-                *(float4*)(dst + (pd.zrow0 + g0 + bf16_plane_row(o4, r)) * d_pad + c0) =
-                    make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
-            if (PREC == HBT_F32 && z32)
-#pragma unroll
-                for (int r = 0; r < 8; ++r)
-                    *(float4*)(z32 + (pd.zrow0 + g0 + bf16_plane_row(o4, r)) * d_pad + c0) =
-                        make_float4(zf[0][r], zf[1][r], zf[2][r], zf[3][r]);
-        }
-        if (PREC == HBT_BF16X2) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
+                for (int r = 0; r < 8; ++r) {
+                    const int64_t zr = pd.zrow0 + row_of(r);
+                    if (PREC == HBT_F32) ((float*)zstore)[zr * d_pad + c] = zf[r];
+                    if (z32) z32[zr * d_pad + c] = zf[r];
+                }
+            }
+            if (PREC == HBT_BF16X2) {
                 uint32_t hi[4], lo[4];
 #pragma unroll
                 for (int r = 0; r < 8; r += 2) {
-                    const uint2 hl = split_bf16x2(zf[e][r] * bf16_plane_scale(o4, r),
-                                                  zf[e][r + 1] * bf16_plane_scale(o4, r + 1));
+                    const uint2 hl = split_bf16x2(zf[r] * bf16_plane_scale(o4, r), zf[r + 1] * bf16_plane_scale(o4, r + 1));
                     hi[r / 2] = hl.x;
                     lo[r / 2] = hl.y;
                 }
-                uint4* ph = (uint4*)zstore + oct * d_pad + c0 + e;
+                uint4* ph = (uint4*)zstore + oct * d_pad + c;
                 *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
                 *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
             }
         }
-    }
 }
 
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
