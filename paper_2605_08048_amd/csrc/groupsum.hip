@@ -15,6 +15,8 @@
 //
 // Work-group = 4 waves; tile = kDSlot columns x (512 splits for split BF16,
 // 256 for FP32 / FP64).
+#include <atomic>
+
 #include "hbt_launch.h"
 
 namespace hbt {
@@ -99,6 +101,15 @@ constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14
 
 // JB split blocks of 32 per wave: a work-group covers 128 JB splits (JB = 4:
 // 512, JB = 2: 256; the tile width the plan picks per pair).
+//
+// Persistent launch: work-group b walks the tiles b, b + G, b + 2G, ...
+// (G = gridDim.x, a few work-groups per CU; tiles are numbered longest pair
+// first), and the chunk loader runs two chunks ahead of the multiplication
+// across tile boundaries, so the first chunks of the next tile stream in
+// during the last steps and the epilogue of the current one.  Chunk g of a
+// work-group's sequence goes to LDS buffer g mod 3; the step that multiplies
+// chunk g issues chunk g + 2 into the buffer every wave finished reading in
+// the previous step.
 template <int JB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
@@ -106,186 +117,188 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
     double* __restrict__ partial, float* __restrict__ sig) {
-    constexpr int kWS = 32 * JB;            // splits per wave
-    constexpr int kTile = 4 * kWS;          // splits per work-group
-    constexpr int kMaskVec = kTile;         // uint4 per chunk: one 128-row word group per split
-    constexpr int kMaskLoads = kWS / 64;    // mask loads per wave per chunk
+    constexpr int kWS = 32 * JB;
+    constexpr int kTile = 4 * kWS;
+    constexpr int kMaskVec = kTile;
+    constexpr int kMaskLoads = kWS / 64;
     constexpr int kWaitOneChunk = wait_vmcnt(8 + kMaskLoads);
-    // separate LDS objects per buffer ([plane][octet][column] of Z; [wave][split]
-    // of mask words)
-    __shared__ uint4 lds0[kChunkVec];
-    __shared__ uint4 lds1[kChunkVec];
-    __shared__ uint4 lds2[kChunkVec];
-    __shared__ uint4 msk0[kMaskVec];
-    __shared__ uint4 msk1[kMaskVec];
-    __shared__ uint4 msk2[kMaskVec];
-    const int L = xcd_remap(blockIdx.x);
-    if (L >= ntile_total) return;
-    const int gi = upper_index(ngroups, L, [&](int k) { return groups[k].tile0; });
-    const GemmGroup grp = groups[gi];
-    const int local = L - (int)grp.tile0;
-    const int slot = local / grp.nbt;                       // 64-column slice
-    const int b0 = (local % grp.nbt) * kTile;
-    const PairDesc pd = pairs[grp.pair];
-    const BlockPair bq = bp[grp.pair];
+    __shared__ uint4 zbuf[3][kChunkVec];
+    __shared__ uint4 mbuf[3][kMaskVec];
     const int tid = threadIdx.x;
-    // wave index as a wave-uniform (scalar) value: the loader's row offsets
-    // then live in SGPRs and only the lane offset is per lane
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int h = lane >> 5, c = lane & 31;
-    const int d0 = slot * kDSlot;
-    const int nchunk = pd.Np / kChunk;
-    const uint32_t rot = 8u * h;  // the upper lane half reads its rows 8 bits further on
+    const uint32_t rot = 8u * h;
+    const int nlogical = (ntile_total + 31) / 32 * 32;
+    auto next_valid = [&](int it) {  // the padding of the last 32 logical tiles is skipped
+        while (it < nlogical && xcd_remap(it) >= ntile_total) it += gridDim.x;
+        return it;
+    };
+    struct Tile {
+        int pair, slot, b0;
+    };
+    auto tile_of = [&](int it) {
+        const int L = xcd_remap(it);
+        const GemmGroup grp = groups[upper_index(ngroups, L, [&](int k) { return groups[k].tile0; })];
+        const int local = L - (int)grp.tile0;
+        return Tile{grp.pair, local / grp.nbt, (local % grp.nbt) * kTile};
+    };
 
-    // splits of this lane's JB blocks (rows past the pair's splits are
-    // loaded from its first row and zeroed by keep[] at use)
-    int brow[JB];
-    uint32_t keep[JB];
-    const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+    // loader cursor: tile l_it, chunk l_ch
+    int l_it = next_valid(blockIdx.x);
+    if (l_it >= nlogical) return;  // work-group-uniform
+    int l_ch = 0, l_nchunk = 0;
+    const uint4* l_zsrc = nullptr;
+    const uint4* l_mload[kMaskLoads];
+    auto l_setup = [&]() {
+        const Tile t = tile_of(l_it);
+        const PairDesc pd = pairs[t.pair];
+        const BlockPair bq = bp[t.pair];
+        l_nchunk = pd.Np / kChunk;
+        const int64_t oct0 = pd.zrow0 >> 3;
+        l_zsrc = ((8 * wave) / kOct ? zlo : zhi) + (oct0 + (8 * wave) % kOct) * d_pad + t.slot * kDSlot;
 #pragma unroll
-    for (int j = 0; j < JB; ++j) {
-        brow[j] = b0 + wave * kWS + j * 32 + c;
-        keep[j] = brow[j] < bq.nb ? 0xffffffffu : 0u;
-    }
-    // mask rows this lane moves into LDS: splits kWS w + 64 k + l
-    const uint4* mload[kMaskLoads];
-#pragma unroll
-    for (int k = 0; k < kMaskLoads; ++k) {
-        const int r = b0 + wave * kWS + 64 * k + lane;
-        mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
-    }
-
-    // chunk loader: 32 LDS rows of kDSlot uint4 (plane, octet); wave w fills
-    // rows 8w .. 8w+7, lane l moving column l (1 KB per wave per load); and
-    // the wave's kWS mask rows
-    const int64_t oct0 = pd.zrow0 >> 3;
+        for (int k = 0; k < kMaskLoads; ++k) {
+            const int r = t.b0 + wave * kWS + 64 * k + lane;
+            l_mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
+        }
+    };
+    l_setup();
     const int64_t chunk_stride = (int64_t)kOct * d_pad;
-    // rows 8w .. 8w+7 of the chunk tile all lie in one plane (kOct = 16)
-    const uint4* zsrc = ((8 * wave) / kOct ? zlo : zhi) + (oct0 + (8 * wave) % kOct) * d_pad + d0;
-    auto issue = [&](int ch, uint4* dst, uint4* mdst) {
-        const uint4* base = zsrc + ch * chunk_stride;  // wave-uniform
-        const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(dst + 8 * wave * kDSlot));
-        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(mdst + wave * kWS));
+    // one chunk at the cursor into buffer b, then advance the cursor (past the
+    // work-group's last chunk it stays there: a harmless reload into a free buffer)
+    auto issue_next = [&](int b) {
+        const uint4* base = l_zsrc + l_ch * chunk_stride;
+        const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(&zbuf[b][8 * wave * kDSlot]));
+        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(&mbuf[b][wave * kWS]));
 #pragma unroll
         for (int k = 0; k < 8; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
 #pragma unroll
-        for (int k = 0; k < kMaskLoads; ++k) dma16(mload[k] + ch, ml + 16 * 64 * k);
+        for (int k = 0; k < kMaskLoads; ++k) dma16(l_mload[k] + l_ch, ml + 16 * 64 * k);
+        if (l_ch + 1 < l_nchunk) {
+            ++l_ch;
+        } else {
+            const int nit = next_valid(l_it + gridDim.x);
+            if (nit < nlogical) {
+                l_it = nit;
+                l_ch = 0;
+                l_setup();
+            }
+        }
     };
 
-    // three buffers: chunks ch+1 and ch+2 are in flight while ch is multiplied.
-    // A load is issued in every step (past the end, the last chunk again into
-    // the free buffer, never read), so one constant wait fits every step.
-    const int last = nchunk - 1;
-    issue(0, lds0, msk0);
-    issue(last < 1 ? last : 1, lds1, msk1);
-    __builtin_amdgcn_s_waitcnt(kWaitOneChunk);  // chunk 0 landed, chunk 1 may not have
+    int g = 0;  // global step: buffer g % 3
+    issue_next(0);
+    issue_next(1);
+    __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
     __syncthreads();
 
-    f32x16 acc[2][JB];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < JB; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-
-    // one chunk: stream chunk ch+1 into (nxt, mnxt) while multiplying (cur, mcur)
-    // multiply chunk ch from (cur, mcur) while chunk ch+2 streams into
-    // (nxt, mnxt), the buffer every wave finished reading in the previous step
-    auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
-        issue(ch + 2 < last ? ch + 2 : last, nxt, mnxt);
-        // this chunk's mask words of the lane's JB splits (16-byte rows: a
-        // conflict-free 128-bit read per split), group flip, validity and the
-        // lane half's rotation applied once
-        uint4 mw[JB];
+    for (int c_it = next_valid(blockIdx.x); c_it < nlogical; c_it = next_valid(c_it + gridDim.x)) {
+        const Tile t = tile_of(c_it);
+        const PairDesc pd = pairs[t.pair];
+        const BlockPair bq = bp[t.pair];
+        const int nchunk = pd.Np / kChunk;
+        const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+        const int d0 = t.slot * kDSlot;
+        int brow[JB];
+        uint32_t keep[JB];
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
-            const uint4 x = mcur[wave * kWS + 32 * j + c];
-            auto prep = [&](uint32_t u) {
-                const uint32_t y = (u ^ flip) & keep[j];
-                return __builtin_amdgcn_alignbit(y, y, rot);
-            };
-            mw[j] = make_uint4(prep(x.x), prep(x.y), prep(x.z), prep(x.w));
+            brow[j] = t.b0 + wave * kWS + j * 32 + c;
+            keep[j] = brow[j] < bq.nb ? 0xffffffffu : 0u;
         }
-        // operands of K-step s: Z fragments (2 planes x 2 column blocks) and
-        // the mask fragments of the JB split blocks
-        auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[JB]) {
-            const int o = 2 * s + h;
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
-                a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
-            }
-            // register e of the operand keeps exponent bit e of both bf16
-            // halves (the row order and scaling of the stored planes)
-            const uint32_t kBit = 0x00800080u << (4 * (s & 1));
-#pragma unroll
-            for (int j = 0; j < JB; ++j) {
-                const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
-                bm[j] = as_bf16x8(make_uint4(word & kBit, word & (kBit << 1), word & (kBit << 2), word & (kBit << 3)));
-            }
-        };
-        bf16x8 a[2][2][2], bm[2][JB];  // [buffer]...
-        fetch(0, a[0], bm[0]);
-#pragma unroll
-        for (int s = 0; s < kChunk / 16; ++s) {  // K-steps of 16 pooled rows
-            if (s + 1 < kChunk / 16) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
-#pragma unroll
-            for (int pl = 0; pl < 2; ++pl)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < JB; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            a[s & 1][pl][i], bm[s & 1][j], acc[i][j], 0, 0, 0);
-        }
-        // chunk ch+1 has landed (this wave's loads, then every wave's through
-        // the barrier), chunk ch+2 may still be in flight; every wave is done
-        // reading (cur, mcur) before the next step refills them
-        __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
-        lds_barrier();
-    };
-    for (int ch = 0; ch < nchunk; ch += 3) {
-        step(ch, lds0, msk0, lds2, msk2);
-        if (ch + 1 < nchunk) step(ch + 1, lds1, msk1, lds0, msk0);
-        if (ch + 2 < nchunk) step(ch + 2, lds2, msk2, lds1, msk1);
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // the loads past the end
-
-    // epilogue: squared norms of sigma_small and t - sigma_small over the slice
-    const float* tp = t32 + (int64_t)grp.pair * d_pad + d0;
-    float tv[2][16];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
-#pragma unroll
-    for (int j = 0; j < JB; ++j) {
-        float ss = 0.0f, sl = 0.0f;
+        f32x16 acc[2][JB];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const float sv = acc[i][j][v];
-                const float lv = tv[i][v] - sv;
-                ss += sv * sv;
-                sl += lv * lv;
+            for (int j = 0; j < JB; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+        for (int ch = 0; ch < nchunk; ++ch, ++g) {
+            const int b = g % 3;
+            issue_next(b == 0 ? 2 : b - 1);  // buffer (g + 2) mod 3, read in step g - 1
+            const uint4* cur = zbuf[b];
+            const uint4* mcur = mbuf[b];
+            uint4 mw[JB];
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const uint4 x = mcur[wave * kWS + 32 * j + c];
+                auto prep = [&](uint32_t u) {
+                    const uint32_t y = (u ^ flip) & keep[j];
+                    return __builtin_amdgcn_alignbit(y, y, rot);
+                };
+                mw[j] = make_uint4(prep(x.x), prep(x.y), prep(x.z), prep(x.w));
             }
-        ss += __shfl_xor(ss, 32, 64);
-        sl += __shfl_xor(sl, 32, 64);
-        if (h == 0 && keep[j]) {
-            double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + slot;
-            *out = make_double2((double)ss, (double)sl);
+            auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[JB]) {
+                const int o = 2 * s + h;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
+                    a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
+                }
+                const uint32_t kBit = 0x00800080u << (4 * (s & 1));
+#pragma unroll
+                for (int j = 0; j < JB; ++j) {
+                    const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
+                    bm[j] = as_bf16x8(make_uint4(word & kBit, word & (kBit << 1), word & (kBit << 2), word & (kBit << 3)));
+                }
+            };
+            bf16x8 a[2][2][2], bm[2][JB];
+            fetch(0, a[0], bm[0]);
+#pragma unroll
+            for (int s = 0; s < kChunk / 16; ++s) {
+                if (s + 1 < kChunk / 16) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
+#pragma unroll
+                for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < JB; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s & 1][pl][i], bm[s & 1][j],
+                                                                                acc[i][j], 0, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+            lds_barrier();
         }
-        if (sig && keep[j]) {  // the group sums themselves, for the point-to-centroid route
-            float* sr = sig + (bq.mrow0 + brow[j]) * (int64_t)d_pad + d0;
+
+        const float* tp = t32 + (int64_t)t.pair * d_pad + d0;
+        float tv[2][16];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            float ss = 0.0f, sl = 0.0f;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) sr[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)] = acc[i][j][v];
+                for (int v = 0; v < 16; ++v) {
+                    const float sv = acc[i][j][v];
+                    const float lv = tv[i][v] - sv;
+                    ss += sv * sv;
+                    sl += lv * lv;
+                }
+            ss += __shfl_xor(ss, 32, 64);
+            sl += __shfl_xor(sl, 32, 64);
+            if (h == 0 && keep[j]) {
+                double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + t.slot;
+                *out = make_double2((double)ss, (double)sl);
+            }
+            if (sig && keep[j]) {
+                float* sr = sig + (bq.mrow0 + brow[j]) * (int64_t)d_pad + d0;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) sr[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)] = acc[i][j][v];
+            }
         }
+        // loads and stores may complete out of order: drain the stores (and
+        // the chunks in flight) so that the next steps' counts see loads only
+        __builtin_amdgcn_s_waitcnt(0);
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the reloads past the end
 }
 
 // ---------------------------------------------------------------------------
@@ -303,8 +316,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // half h is (word >> (s + 4 h)) & 0x01010101 (the planes' row order makes
 // those the lane's rows), and that shifted left by 7 for the middle plane.
 // Z streams through LDS in chunks of 128 rows (three planes of the 64
-// columns = 24 KB, mask words 8 KB), as in the split-BF16 kernel.  Splits
-// past the block's end take the mask of its first split and are not written.
+// columns = 24 KB, mask words 8 KB) with the persistent launch and cross-tile
+// prefetch of the split-BF16 kernel.  Splits past the block's end take the
+// mask of its first split and are not written.
 // ---------------------------------------------------------------------------
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
@@ -323,157 +337,188 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     constexpr int kMaskLoads = kWS / 64;        // mask loads per wave per chunk
     constexpr int kWaitOneChunk = wait_vmcnt(kRowsPerWave + kMaskLoads);
     static_assert(kTileI8 == 4 * kWS, "tile width");
-    __shared__ uint4 lds0[kChunkVecI8];
-    __shared__ uint4 lds1[kChunkVecI8];
-    __shared__ uint4 lds2[kChunkVecI8];
-    __shared__ uint4 msk0[kTileI8];
-    __shared__ uint4 msk1[kTileI8];
-    __shared__ uint4 msk2[kTileI8];
-    const int L = xcd_remap(blockIdx.x);
-    if (L >= ntile_total) return;
-    const int gi = upper_index(ngroups, L, [&](int k) { return groups[k].tile0; });
-    const GemmGroup grp = groups[gi];
-    const int local = L - (int)grp.tile0;
-    const int slot = local / grp.nbt;
-    const int b0 = (local % grp.nbt) * kTileI8;
-    const PairDesc pd = pairs[grp.pair];
-    const BlockPair bq = bp[grp.pair];
+    __shared__ uint4 zbuf[3][kChunkVecI8];
+    __shared__ uint4 mbuf[3][kTileI8];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int h = lane >> 5, c = lane & 31;
-    const int d0 = slot * kDSlot;
-    const int nchunk = pd.Np / kChunk;
     const uint32_t rsh = 4u * h;
-    const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
-    int brow[JB];
-#pragma unroll
-    for (int j = 0; j < JB; ++j) brow[j] = b0 + wave * kWS + j * 32 + c;
-    // mask rows this lane moves into LDS: splits kWS w + 64 k + l of the tile
-    const uint4* mload[kMaskLoads];
-#pragma unroll
-    for (int k = 0; k < kMaskLoads; ++k) {
-        const int r = b0 + kWS * wave + 64 * k + lane;
-        mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
-    }
+    const int nlogical = (ntile_total + 31) / 32 * 32;
+    auto next_valid = [&](int it) {
+        while (it < nlogical && xcd_remap(it) >= ntile_total) it += gridDim.x;
+        return it;
+    };
+    struct Tile {
+        int pair, slot, b0;
+    };
+    auto tile_of = [&](int it) {
+        const int L = xcd_remap(it);
+        const GemmGroup grp = groups[upper_index(ngroups, L, [&](int k) { return groups[k].tile0; })];
+        const int local = L - (int)grp.tile0;
+        return Tile{grp.pair, local / grp.nbt, (local % grp.nbt) * kTileI8};
+    };
 
-    // chunk loader: LDS rows (plane, unit) 6 w .. 6 w + 5, lane l moving column l
-    const int64_t hex0 = pd.zrow0 >> 4;
-    auto issue = [&](int ch, uint4* dst, uint4* mdst) {
+    // loader cursor (two chunks ahead of the multiplication, across tiles)
+    int l_it = next_valid(blockIdx.x);
+    if (l_it >= nlogical) return;  // work-group-uniform
+    int l_ch = 0, l_nchunk = 0;
+    int64_t l_unit0 = 0;  // first 16-row unit of the pair's column slice
+    int l_d0 = 0;
+    const uint4* l_mload[kMaskLoads];
+    auto l_setup = [&]() {
+        const Tile t = tile_of(l_it);
+        const PairDesc pd = pairs[t.pair];
+        const BlockPair bq = bp[t.pair];
+        l_nchunk = pd.Np / kChunk;
+        l_unit0 = pd.zrow0 >> 4;
+        l_d0 = t.slot * kDSlot;
+#pragma unroll
+        for (int k = 0; k < kMaskLoads; ++k) {
+            const int r = t.b0 + kWS * wave + 64 * k + lane;
+            l_mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
+        }
+    };
+    l_setup();
+    // chunk at the cursor: LDS rows (plane, unit) 6 w .. 6 w + 5, lane l moving
+    // column l; then the wave's mask words; then advance the cursor (it stays
+    // on the work-group's last chunk at the end: harmless reloads)
+    auto issue_next = [&](int b) {
 #pragma unroll
         for (int k = 0; k < kRowsPerWave; ++k) {
             const int r = kRowsPerWave * wave + k;  // wave-uniform
-            const uint4* src = zq + (r / kHex) * plane_vec + (hex0 + (int64_t)kHex * ch + r % kHex) * d_pad + d0;
-            dma16(src + lane, __builtin_amdgcn_readfirstlane(lds_addr(dst + r * kDSlot)));
+            const uint4* src = zq + (r / kHex) * plane_vec + (l_unit0 + (int64_t)kHex * l_ch + r % kHex) * d_pad + l_d0;
+            dma16(src + lane, __builtin_amdgcn_readfirstlane(lds_addr(&zbuf[b][r * kDSlot])));
         }
-        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(mdst + kWS * wave));
+        const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(&mbuf[b][kWS * wave]));
 #pragma unroll
-        for (int k = 0; k < kMaskLoads; ++k) dma16(mload[k] + ch, ml + 16 * 64 * k);
+        for (int k = 0; k < kMaskLoads; ++k) dma16(l_mload[k] + l_ch, ml + 16 * 64 * k);
+        if (l_ch + 1 < l_nchunk) {
+            ++l_ch;
+        } else {
+            const int nit = next_valid(l_it + gridDim.x);
+            if (nit < nlogical) {
+                l_it = nit;
+                l_ch = 0;
+                l_setup();
+            }
+        }
     };
-    const int last = nchunk - 1;
-    issue(0, lds0, msk0);
-    issue(last < 1 ? last : 1, lds1, msk1);
+
+    int g = 0;  // global step: buffer g % 3
+    issue_next(0);
+    issue_next(1);
     __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
     __syncthreads();
 
-    i32x16 acc[2][2][JB];  // [S_hi, S_lo][column block][split block]
+    for (int c_it = next_valid(blockIdx.x); c_it < nlogical; c_it = next_valid(c_it + gridDim.x)) {
+        const Tile t = tile_of(c_it);
+        const PairDesc pd = pairs[t.pair];
+        const BlockPair bq = bp[t.pair];
+        const int nchunk = pd.Np / kChunk;
+        const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+        const int d0 = t.slot * kDSlot;
+        i32x16 acc[2][2][JB];  // [S_hi, S_lo][column block][split block]
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < JB; ++j)
+                for (int j = 0; j < JB; ++j)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) acc[q][i][j][v] = 0;
+                    for (int v = 0; v < 16; ++v) acc[q][i][j][v] = 0;
 
-    auto step = [&](int ch, const uint4* cur, const uint4* mcur, uint4* nxt, uint4* mnxt) {
-        issue(ch + 2 < last ? ch + 2 : last, nxt, mnxt);
-        // the chunk's mask words of the lane's splits: group flip, lane-half shift
-        uint4 mw[JB];
-#pragma unroll
-        for (int j = 0; j < JB; ++j) {
-            const uint4 x = mcur[kWS * wave + 32 * j + c];
-            mw[j] = make_uint4((x.x ^ flip) >> rsh, (x.y ^ flip) >> rsh, (x.z ^ flip) >> rsh, (x.w ^ flip) >> rsh);
-        }
-        auto fetch = [&](int s, i32x4 (&a)[3][2], i32x4 (&bm)[JB]) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const uint4 u = cur[(q * kHex + 2 * s + h) * kDSlot + 32 * i + c];
-                    a[q][i] = i32x4{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-                }
+        for (int ch = 0; ch < nchunk; ++ch, ++g) {
+            const int b = g % 3;
+            issue_next(b == 0 ? 2 : b - 1);  // buffer (g + 2) mod 3, read in step g - 1
+            const uint4* cur = zbuf[b];
+            const uint4* mcur = mbuf[b];
+            // the chunk's mask words of the lane's splits: group flip, lane-half shift
+            uint4 mw[JB];
 #pragma unroll
             for (int j = 0; j < JB; ++j) {
-                const uint32_t w = s == 0 ? mw[j].x : s == 1 ? mw[j].y : s == 2 ? mw[j].z : mw[j].w;
-                bm[j] = i32x4{(int)(w & 0x01010101u), (int)((w >> 1) & 0x01010101u),
-                              (int)((w >> 2) & 0x01010101u), (int)((w >> 3) & 0x01010101u)};
+                const uint4 x = mcur[kWS * wave + 32 * j + c];
+                mw[j] = make_uint4((x.x ^ flip) >> rsh, (x.y ^ flip) >> rsh, (x.z ^ flip) >> rsh, (x.w ^ flip) >> rsh);
             }
-        };
-        i32x4 a[2][3][2], bm[2][JB];
-        fetch(0, a[0], bm[0]);
+            auto fetch = [&](int s, i32x4 (&a)[3][2], i32x4 (&bm)[JB]) {
 #pragma unroll
-        for (int s = 0; s < kChunk / 32; ++s) {  // K-steps of 32 pooled rows
-            if (s + 1 < kChunk / 32) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
-            const int b = s & 1;
-            // middle plane first, then the high plane, then the low plane into
-            // the same sum as the middle one: 16 MFMAs between dependent ones
+                for (int q = 0; q < 3; ++q)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < 2; ++i) {
+                        const uint4 u = cur[(q * kHex + 2 * s + h) * kDSlot + 32 * i + c];
+                        a[q][i] = i32x4{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+                    }
 #pragma unroll
                 for (int j = 0; j < JB; ++j) {
-                    const i32x4 m128 = bm[b][j] << 7;  // bytes 0x80 = -128 where the mask is set
-                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[b][1][i], m128, acc[1][i][j], 0, 0, 0);
+                    const uint32_t w = s == 0 ? mw[j].x : s == 1 ? mw[j].y : s == 2 ? mw[j].z : mw[j].w;
+                    bm[j] = i32x4{(int)(w & 0x01010101u), (int)((w >> 1) & 0x01010101u),
+                                  (int)((w >> 2) & 0x01010101u), (int)((w >> 3) & 0x01010101u)};
                 }
+            };
+            i32x4 a[2][3][2], bm[2][JB];
+            fetch(0, a[0], bm[0]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int s = 0; s < kChunk / 32; ++s) {  // K-steps of 32 pooled rows
+                if (s + 1 < kChunk / 32) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
+                const int bb = s & 1;
+                // middle plane first, then the high plane, then the low plane into
+                // the same sum as the middle one: 16 MFMAs between dependent ones
 #pragma unroll
-                for (int j = 0; j < JB; ++j)
-                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[b][0][i], bm[b][j], acc[0][i][j], 0, 0, 0);
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < JB; ++j) {
+                        const i32x4 m128 = bm[bb][j] << 7;  // bytes 0x80 = -128 where the mask is set
+                        acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[bb][1][i], m128, acc[1][i][j], 0, 0, 0);
+                    }
 #pragma unroll
-                for (int j = 0; j < JB; ++j)
-                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[b][2][i], bm[b][j], acc[1][i][j], 0, 0, 0);
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < JB; ++j)
+                        acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[bb][0][i], bm[bb][j], acc[0][i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < JB; ++j)
+                        acc[1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[bb][2][i], bm[bb][j], acc[1][i][j], 0, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+            lds_barrier();
         }
-        __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
-        lds_barrier();
-    };
-    for (int ch = 0; ch < nchunk; ch += 3) {
-        step(ch, lds0, msk0, lds2, msk2);
-        if (ch + 1 < nchunk) step(ch + 1, lds1, msk1, lds0, msk0);
-        if (ch + 2 < nchunk) step(ch + 2, lds2, msk2, lds1, msk1);
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // the loads past the end
 
-    // epilogue: sigma_small in FP64, squared norms of sigma_small and
-    // t - sigma_small over the slot's 64 columns
-    const double* tp = t64 + (int64_t)grp.pair * d_pad + d0;
-    double tv[2][16];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
-#pragma unroll
-    for (int j = 0; j < JB; ++j) {
-        double ss = 0.0, sl = 0.0;
+        // epilogue: sigma_small in FP64, squared norms of sigma_small and
+        // t - sigma_small over the slot's 64 columns
+        const double* tp = t64 + (int64_t)t.pair * d_pad + d0;
+        double tv[2][16];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const double sv = __builtin_fma((double)acc[0][i][j][v], 16384.0, (double)acc[1][i][j][v]) *
-                                  (1.0 / 1048576.0);
-                const double lv = tv[i][v] - sv;
-                ss += sv * sv;
-                sl += lv * lv;
+            for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            const int brow = t.b0 + wave * kWS + j * 32 + c;
+            double ss = 0.0, sl = 0.0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const double sv = __builtin_fma((double)acc[0][i][j][v], 16384.0, (double)acc[1][i][j][v]) *
+                                      (1.0 / 1048576.0);
+                    const double lv = tv[i][v] - sv;
+                    ss += sv * sv;
+                    sl += lv * lv;
+                }
+            ss += __shfl_xor(ss, 32, 64);
+            sl += __shfl_xor(sl, 32, 64);
+            if (h == 0 && brow < bq.nb) {
+                double2* out = (double2*)partial + (bq.mrow0 + brow) * nslot + t.slot;
+                *out = make_double2(ss, sl);
             }
-        ss += __shfl_xor(ss, 32, 64);
-        sl += __shfl_xor(sl, 32, 64);
-        if (h == 0 && brow[j] < bq.nb) {
-            double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + slot;
-            *out = make_double2(ss, sl);
         }
+        // loads and stores may complete out of order: drain the stores (and
+        // the chunks in flight) so that the next steps' counts see loads only
+        __builtin_amdgcn_s_waitcnt(0);
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the reloads past the end
 }
 
 // ---------------------------------------------------------------------------
@@ -586,6 +631,24 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
     }
 }
 
+// Work-groups of a persistent launch over `tiles` tiles: 4 per CU (measured
+// on MI355X: 1 per CU leaves the tail unbalanced, one per tile loses the
+// cross-tile prefetch), a multiple of 32 so that the XCD numbering holds.
+static std::atomic<int> g_cus[64];
+static unsigned persistent_grid(int64_t tiles) {
+    int dev = 0;
+    int cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        cus = g_cus[dev].load(std::memory_order_relaxed);
+        if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            g_cus[dev].store(cus, std::memory_order_relaxed);
+    }
+    if (cus <= 0) cus = 256;
+    const int64_t want = (int64_t)(cus * 4 + 31) / 32 * 32;
+    const int64_t all = (tiles + 31) / 32 * 32;
+    return (unsigned)(all < want ? all : want);
+}
+
 int groupsum_tile_splits(int precision) { return precision == HBT_BF16X2 ? kTileBF16 : kTileB; }
 
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
@@ -600,18 +663,18 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             const uint4* zhi = (const uint4*)zstore;
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
             if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3((unsigned)((nt512 + 31) / 32 * 32)), block, 0,
+                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512)), block, 0,
                                    s, pairs, bp, groups, ng512, nt512, nslot, d_pad, zhi, zlo, mask,
                                    t32, partial, sig);
             if (nt256 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3((unsigned)((nt256 + 31) / 32 * 32)), block, 0,
+                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256)), block, 0,
                                    s, pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, zhi, zlo,
                                    mask, t32, partial, sig);
             break;
         }
         case HBT_I8X3:
             if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_i8x3, dim3((unsigned)((nt512 + 31) / 32 * 32)), block, 0, s,
+                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt512)), block, 0, s,
                                    pairs, bp, groups, ng512, nt512, nslot, d_pad, (const uint4*)zstore,
                                    zplane_elems / 16, mask, t64, partial);
             break;
