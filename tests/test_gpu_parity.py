@@ -256,6 +256,42 @@ def test_i8x3_equals_exact_sums_of_rounded_rows():
         assert np.abs(r["T"] - T).max() <= 1e-9, (n, m, np.abs(r["T"] - T).max())
 
 
+# the recheck band of the statistic kernel, restated: a split is re-evaluated in
+# FP64 when |T_b - threshold| <= e_rel (sens(r1^2) + sens(r2^2)) + 1e-13 (|f(r1)| + |f(r2)|)
+# with e_rel = e_acc + e_store / sqrt(min(n, m) d)
+BAND = {"f32": (4e-6, lambda d: 0.0),
+        "bf16x2": (4e-6, lambda d: 16 * 2.3 / 131072),
+        "i8x3": (1e-10, lambda d: 16 * 2.3 / 2097152 * math.sqrt(d))}
+
+
+def _band_eps(prec, n, m, d, r1, r2):
+    e_acc, e_store = BAND[prec]
+    e_rel = e_acc + e_store(d) / math.sqrt(min(n, m) * d)
+    sens = lambda s: np.abs(0.5 - s / (d - s) + s / (1 - s))
+    fs = np.abs(_logg(r1, d)) + np.abs(_logg(r2, d))
+    return e_rel * (sens(r1 * r1) + sens(r2 * r2)) + 1e-13 * fs
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
+def test_raw_errors_stay_inside_the_recheck_band(prec):
+    """Without the recheck, every T_b of the reduced precision must lie within
+    the band around the FP64 value, or the recheck could miss a decision.  The
+    shapes are the hard cases: a group of 2, concentrated clouds (r near 1),
+    d from 16 to 1024.  The margin asked for is 2x."""
+    worst = 0.0
+    for n, m, d, kx, ky in [(2, 300, 64, 8.0, 8.0), (2, 61, 1024, 30.0, 30.0), (3, 500, 16, 4.0, 6.0),
+                            (400, 350, 768, 2.0, 2.2), (1000, 2, 256, 12.0, 12.0), (37, 41, 1024, 40.0, 45.0)]:
+        B = 300
+        X, Y = _pair(n, m, d, kx=kx, ky=ky, seed=n * 7 + d)
+        r = hbt.perm_test(_dev(X), _dev(Y), B, seed=11, precision=prec, recheck=False, want_T="f64")
+        at = O.perm_stats_at(X, Y, np.arange(B), seed=11)
+        eps = _band_eps(prec, n, m, d, at["r1"], at["r2"])
+        ratio = np.abs(r["T"] - at["T"]) / eps
+        worst = max(worst, float(ratio.max()))
+        assert ratio.max() <= 0.5, (prec, n, m, d, float(ratio.max()))
+    print(f"{prec}: worst |T - T64| / band = {worst:.3g}")
+
+
 def test_i8x3_rejects_point_to_centroid_route():
     X, Y = _pair(20, 30, 16, seed=32)
     with pytest.raises(RuntimeError, match="route 0 only"):
