@@ -138,7 +138,7 @@ def stage_times(L, ctypes):
     return list(ms), list(n)
 
 
-def cpu_baseline(batch, npairs_sample=128, splits=2000):
+def cpu_baseline(batch, npairs_sample=176, splits=2000):
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     threads = min(threads, 16)
