@@ -138,6 +138,7 @@ struct Workspace {
     uint32_t* flags;
     double* tw;         // final T_b of the current block (moments)
     uint32_t* nflag;
+    int32_t* sstat;     // per pair: problems of the split stage (merged into the result status)
     // point-to-centroid route
     float* sig;         // group sums of the smaller group, block rows x d_pad
     float* z32;         // row-major FP32 Z when the main storage is not FP32
@@ -197,6 +198,7 @@ Workspace carve(const Plan& P, void* ws) {
         w.flags = c.take<uint32_t>(std::max<int64_t>(P.block_rows, 1));
         w.tw = c.take<double>(std::max<int64_t>(P.block_rows, 1));
         w.nflag = c.take<uint32_t>(2);
+        w.sstat = c.take<int32_t>((size_t)(np + 1) / 2 * 2);
         if (P.route2) {
             w.sig = c.take<float>((size_t)std::max<int64_t>(P.block_rows, 1) * P.d_pad);
             w.z32 = P.precision == HBT_F32 ? nullptr : c.take<float>((size_t)P.zrows * P.d_pad);
@@ -223,6 +225,7 @@ Workspace carve(const Plan& P, void* ws) {
         w.flags = nullptr;
         w.tw = nullptr;
         w.nflag = nullptr;
+        w.sstat = nullptr;
     }
     w.bytes = c.off + 256;
     return w;
@@ -377,8 +380,8 @@ hipError_t reflect(const Plan& P, const Workspace& w, float* z32, hipStream_t s)
 }
 
 hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd, hbt_result* res,
-                            hipStream_t s) {
-    {
+                            hipStream_t s, bool upload_pairs = true) {
+    if (upload_pairs) {
         StageTimer t(HBT_STAGE_OTHER, s);
         HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
     }
@@ -392,6 +395,48 @@ hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd
                             w.v, w.t64, w.t32, w.cnt, res, s));
     return HBT_OK;
 }
+
+// A second stream per device for work that runs beside the caller's stream
+// within one call (default priority, created on first use and kept), and the
+// events that fork it from the caller's stream and join it back.  Both are
+// stream-ordered, so a captured call records them as graph edges.
+std::mutex g_side_mu;
+hipStream_t g_side[64];
+
+hipError_t side_stream(hipStream_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_side_mu);
+    if (!g_side[dev] && (e = hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking)) != hipSuccess)
+        return e;
+    *out = g_side[dev];
+    return hipSuccess;
+}
+
+struct Fork {
+    hipStream_t main, side = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit Fork(hipStream_t s) : main(s) {}
+    ~Fork() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    hipError_t begin() {
+        hipError_t e;
+        if ((e = side_stream(&side)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&b, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventRecord(a, main)) != hipSuccess) return e;
+        return hipStreamWaitEvent(side, a, 0);
+    }
+    hipError_t join() {
+        hipError_t e;
+        if ((e = hipEventRecord(b, side)) != hipSuccess) return e;
+        return hipStreamWaitEvent(main, b, 0);
+    }
+};
 
 }  // namespace
 
@@ -548,6 +593,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     const Band band = precision_band(P.precision, P.d);
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
     const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
+    HIP_TRY(zero(w.sstat, 8, s));
     for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
         const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
         BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
@@ -562,9 +608,9 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         {
             StageTimer t_(HBT_STAGE_SPLIT, s);
             if (prm->masks)
-                HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.st, s));
+                HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, s));
             else
-                HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.st, s));
+                HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat, s));
         }
         const int ntiles = (int)((nb + groupsum_tile_splits(P.precision) - 1) / groupsum_tile_splits(P.precision));
         {
@@ -593,7 +639,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         if (mask_out)
             HIP_TRY(launch_export_masks(w.mask, nb, pd.Wp, W, mask_out + b0 * W, s));
     }
-    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(1, w.st, w.cnt, w.Btot, result, s)); }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(1, w.st, w.sstat, w.cnt, w.Btot, result, s)); }
     return HBT_OK;
 }
 
@@ -671,10 +717,9 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     hipStream_t s = (hipStream_t)stream;
     Workspace w = carve(P, ws);
     const int np = P.npairs;
-    st = enqueue_prologue(P, w, common->align, common->gd, results, s);
-    if (st) return st;
     {
         StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
         HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
         if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
             HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
@@ -682,13 +727,25 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
             HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
         HIP_TRY(zero(w.nflag, 8, s));
+        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, s));
     }
+    // The splits depend only on the seeds and the group sizes, not on the
+    // alignment: they are drawn on a second stream beside it (integer VALU
+    // work beside HBM-bound work) and joined before the group sums.
+    Fork fork(s);
+    HIP_TRY(fork.begin());
+    {
+        StageTimer t_(HBT_STAGE_SPLIT, fork.side);
+        HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
+                                   fork.side));
+    }
+    st = enqueue_prologue(P, w, common->align, common->gd, results, s, false);
+    if (st) return st;
     {
         StageTimer t_(HBT_STAGE_ALIGN, s);
         HIP_TRY(reflect(P, w, nullptr, s));
     }
-    { StageTimer t_(HBT_STAGE_SPLIT, s); HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask,
-                               w.st, s)); }
+    HIP_TRY(fork.join());
     {
         StageTimer t_(HBT_STAGE_GROUPSUM, s);
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
@@ -706,7 +763,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                w.nflag, P.block_rows, P.d, common->gd, common->alternative, w.cnt, w.tw, s));
     }
     { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
-    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.st, w.cnt, w.Btot, results, s)); }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.st, w.sstat, w.cnt, w.Btot, results, s)); }
     return HBT_OK;
 }
 

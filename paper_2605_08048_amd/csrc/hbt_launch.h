@@ -53,13 +53,16 @@ hipError_t launch_reflect_out(int input_dtype, const PairDesc* pair, const PairS
 // pairs of up to max_np pooled rows, and the device's limit per work-group.
 size_t split_lds_per_block(int max_np);
 size_t split_lds_limit();
+// Per-pair problems found while drawing or copying splits go to sstat (one
+// int32 per pair, zeroed by the caller), apart from the pair state that the
+// alignment writes, so that the split stage may run beside the alignment.
 hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
-                              PairState* st, hipStream_t s);
+                              int32_t* sstat, hipStream_t s);
 // Explicit masks: copy rows of ceil(N/32) words into the workspace layout and
 // check that each holds exactly n items.
 hipError_t launch_copy_masks(const uint32_t* user, int64_t user_row0, int64_t rows, int N, int n,
-                             int Wp, uint32_t* mask, PairState* st, hipStream_t s);
+                             int Wp, uint32_t* mask, int32_t* sstat, hipStream_t s);
 // Copy workspace masks back to a caller buffer of ceil(N/32) words per row.
 hipError_t launch_export_masks(const uint32_t* mask, int64_t rows, int Wp, int W, uint32_t* out,
                                hipStream_t s);
@@ -121,7 +124,7 @@ hipError_t launch_budgets(int64_t npairs, const float* out, const hbt_result* re
                           double hi, int64_t bmin, int64_t bmax, double zq, int64_t* budget,
                           hipStream_t s);
 
-hipError_t launch_final(int npairs, const PairState* st, const PairCount* cnt,
+hipError_t launch_final(int npairs, const PairState* st, const int32_t* sstat, const PairCount* cnt,
                         const int64_t* Btot, hbt_result* res, hipStream_t s);
 
 }  // namespace hbt

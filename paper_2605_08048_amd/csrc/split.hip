@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
                                                      const BlockPair* __restrict__ bp, int npairs,
                                                      int64_t rows, int max_np, uint32_t key0,
                                                      uint32_t key1, uint32_t* __restrict__ mask,
-                                                     PairState* st) {
+                                                     int32_t* sstat) {
     __shared__ uint32_t hist_all[kSplitWaves][256];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const SplitLds L(max_np);
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
     bucket = __builtin_amdgcn_readlane(bucket, src);
     const uint32_t need = (uint32_t)n - below;
     if (bucket > (uint32_t)kCandCap) {  // not seen in practice (expected size N / 256)
-        if (lane == 0) atomicExch(&st[p].status, (int)HBT_ERR_INTERNAL);
+        if (lane == 0) atomicExch(&sstat[p], (int)HBT_ERR_INTERNAL);
         uint32_t* out = const_cast<uint32_t*>(mask_row(mask, bp[p], row, pd.Wp));
         for (int w = lane; w < pd.Wp; w += 64) out[w] = 0u;  // an empty group: nothing to gather
         return;
@@ -262,7 +262,7 @@ size_t split_lds_per_block(int max_np) { return (size_t)kSplitWaves * SplitLds(m
 
 hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
-                              PairState* st, hipStream_t s) {
+                              int32_t* sstat, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     const SplitLds L(max_np);
     // four split rows per work-group; at most 64 KB of LDS per work-group
@@ -272,7 +272,7 @@ hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int np
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     // registers for the keys of the largest pair: R blocks of 16 per lane
     const int r = (max_np + 1023) / 1024;
-#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, pairs, bp, npairs, rows, max_np, k0, k1, mask, st)
+#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, pairs, bp, npairs, rows, max_np, k0, k1, mask, sstat)
     if (r <= 1) HBT_SPLIT(1);
     else if (r <= 2) HBT_SPLIT(2);
     else if (r <= 4) HBT_SPLIT(4);
@@ -289,7 +289,7 @@ hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int np
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_copy_masks(const uint32_t* __restrict__ user,
                                                     int64_t rows, int N, int n, int Wp,
-                                                    uint32_t* __restrict__ mask, PairState* st) {
+                                                    uint32_t* __restrict__ mask, int32_t* sstat) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + wave;
     if (row >= rows) return;
@@ -306,15 +306,15 @@ __global__ __launch_bounds__(256) void k_copy_masks(const uint32_t* __restrict__
     }
     for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
     const bool anybad = __ballot(bad) != 0;
-    if (lane == 0 && (pc != n || anybad)) atomicExch(&st->status, (int)HBT_ERR_MASK);
+    if (lane == 0 && (pc != n || anybad)) atomicExch(sstat, (int)HBT_ERR_MASK);
 }
 
 hipError_t launch_copy_masks(const uint32_t* user, int64_t user_row0, int64_t rows, int N, int n,
-                             int Wp, uint32_t* mask, PairState* st, hipStream_t s) {
+                             int Wp, uint32_t* mask, int32_t* sstat, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     const int W = (N + 31) >> 5;
     hipLaunchKernelGGL(k_copy_masks, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s,
-                       user + user_row0 * W, rows, N, n, Wp, mask, st);
+                       user + user_row0 * W, rows, N, n, Wp, mask, sstat);
     return hipGetLastError();
 }
 
