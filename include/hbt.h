@@ -211,12 +211,14 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
  * per-split costs for the pair's dimension (padded to 64) from a table in the
  * library; until tuned, cost_512 = 1 and cost_256 = 1.15.  Results do not
  * depend on the width.
- *   hbt_tune_batched: runs hbt_perm_test_batched on its arguments once with
- *     every pair at width 512 and once at 256, times the product with HIP
- *     events and stores cost_w = time / sum_p round_up(B_p, w) *
- *     round_up(n_p + m_p, 128) for this d.  It synchronises the stream, clears
- *     the stage-timing record, and leaves the second run's results in
- *     `results`.  Split BF16 only (HBT_ERR_ARG otherwise).
+ *   hbt_tune_batched: runs hbt_perm_test_batched on its arguments four
+ *     times, every pair at width 512, 256, 512, 256, times the product with
+ *     HIP events and stores, per width, the smaller of its two
+ *     cost_w = time / sum_p round_up(B_p, w) * round_up(n_p + m_p, 128) for
+ *     this d (the first call also pays first-touch and clock ramp-up).  It
+ *     synchronises the stream, clears the stage-timing record, and leaves the
+ *     last run's results in `results`.  Split BF16 only (HBT_ERR_ARG
+ *     otherwise).
  *   hbt_tune_get / hbt_tune_set: the table entry for d (costs[0] for width
  *     512, costs[1] for 256; tuned = 1 once set), e.g. to keep a cache across
  *     processes.

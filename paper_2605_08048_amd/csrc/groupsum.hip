@@ -36,10 +36,10 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast
 //
 // Work-group tile: 64 columns x kTileBF16 (512) splits; 4 waves, wave w owns
 // splits [128 w, 128 w + 128) as 4 blocks of 32 and the 64 columns as 2
-// blocks of 32 (accumulators 2 x 4 x 16 floats per lane, in AGPRs).
+// blocks of 32 (accumulators 2 x 4 x 16 floats per lane).
 //  * Z streams through LDS in chunks of 128 pooled rows (16 octets; both
 //    planes of the 64-column slice = 32 KB) with direct global -> LDS loads,
-//    one chunk ahead, into two separate LDS objects.
+//    one chunk ahead, into two buffers.
 //  * Mask words become bf16 operands with one AND per register: a set bit
 //    lands in the exponent field (a power of two, not 1), and the stored
 //    planes hold each row divided by the power its bit meets, in the row
@@ -103,15 +103,18 @@ constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14
 // 512, JB = 2: 256; the tile width the plan picks per pair).
 //
 // Persistent launch: work-group b walks the tiles b, b + G, b + 2G, ...
-// (G = gridDim.x, a few work-groups per CU; tiles are numbered longest pair
-// first), and the chunk loader runs two chunks ahead of the multiplication
-// across tile boundaries, so the first chunks of the next tile stream in
-// during the last steps and the epilogue of the current one.  Chunk g of a
-// work-group's sequence goes to LDS buffer g mod 3; the step that multiplies
-// chunk g issues chunk g + 2 into the buffer every wave finished reading in
-// the previous step.
+// (G = gridDim.x; tiles are numbered longest pair first), and the chunk
+// loader runs one chunk ahead of the multiplication across tile boundaries,
+// so the first chunk of the next tile streams in during the last step and
+// the epilogue of the current one.  Chunk g of a work-group's sequence goes to
+// LDS buffer g mod 2; the step that multiplies chunk g issues chunk g + 1 into
+// the other buffer, which every wave finished reading in the previous step.
+// Two buffers (80 KB at 512 splits) and at most 256 registers per lane let two
+// work-groups share a CU (2 waves per SIMD): one's barriers, waits and
+// epilogue overlap the other's MFMAs (measured 4.7 -> 4.5 ms on 512 pairs
+// against one work-group per CU with three buffers).
 template <int JB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_bf16x2(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
@@ -121,9 +124,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     constexpr int kTile = 4 * kWS;
     constexpr int kMaskVec = kTile;
     constexpr int kMaskLoads = kWS / 64;
-    constexpr int kWaitOneChunk = wait_vmcnt(8 + kMaskLoads);
-    __shared__ uint4 zbuf[3][kChunkVec];
-    __shared__ uint4 mbuf[3][kMaskVec];
+    __shared__ uint4 zbuf[2][kChunkVec];
+    __shared__ uint4 mbuf[2][kMaskVec];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         return Tile{grp.pair, local / grp.nbt, (local % grp.nbt) * kTile};
     };
 
-    // loader cursor: tile l_it, chunk l_ch
+    // loader cursor: tile l_it, chunk l_ch (one chunk ahead of the multiplication)
     int l_it = next_valid(blockIdx.x);
     if (l_it >= nlogical) return;  // work-group-uniform
     int l_ch = 0, l_nchunk = 0;
@@ -187,10 +189,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
     };
 
-    int g = 0;  // global step: buffer g % 3
+    int g = 0;  // global step: buffer g % 2
     issue_next(0);
-    issue_next(1);
-    __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     for (int c_it = next_valid(blockIdx.x); c_it < nlogical; c_it = next_valid(c_it + gridDim.x)) {
@@ -216,8 +217,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
         for (int ch = 0; ch < nchunk; ++ch, ++g) {
-            const int b = g % 3;
-            issue_next(b == 0 ? 2 : b - 1);  // buffer (g + 2) mod 3, read in step g - 1
+            const int b = g & 1;
+            issue_next(b ^ 1);  // chunk g + 1 into the buffer read in step g - 1
             const uint4* cur = zbuf[b];
             const uint4* mcur = mbuf[b];
             uint4 mw[JB];
@@ -258,7 +259,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s & 1][pl][i], bm[s & 1][j],
                                                                                 acc[i][j], 0, 0, 0);
             }
-            __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
+            // chunk g + 1 has landed (this wave's loads, then every wave's
+            // through the barrier); every wave is done reading buffer b
+            __builtin_amdgcn_s_waitcnt(0);
             lds_barrier();
         }
 
@@ -631,11 +634,13 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
     }
 }
 
-// Work-groups of a persistent launch over `tiles` tiles: 4 per CU (measured
-// on MI355X: 1 per CU leaves the tail unbalanced, one per tile loses the
-// cross-tile prefetch), a multiple of 32 so that the XCD numbering holds.
+// Work-groups of a persistent launch over `tiles` tiles: per_cu per CU
+// (measured on MI355X with one resident work-group per CU: 1 per CU leaves
+// the tail unbalanced, one per tile loses the cross-tile prefetch, 4 is
+// best; with two resident, 8), a multiple of 32 so that the XCD numbering
+// holds.
 static std::atomic<int> g_cus[64];
-static unsigned persistent_grid(int64_t tiles) {
+static unsigned persistent_grid(int64_t tiles, int per_cu) {
     int dev = 0;
     int cus = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
@@ -644,7 +649,7 @@ static unsigned persistent_grid(int64_t tiles) {
             g_cus[dev].store(cus, std::memory_order_relaxed);
     }
     if (cus <= 0) cus = 256;
-    const int64_t want = (int64_t)(cus * 4 + 31) / 32 * 32;
+    const int64_t want = (int64_t)(cus * per_cu + 31) / 32 * 32;
     const int64_t all = (tiles + 31) / 32 * 32;
     return (unsigned)(all < want ? all : want);
 }
@@ -663,18 +668,18 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             const uint4* zhi = (const uint4*)zstore;
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
             if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512)), block, 0,
+                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512, 8)), block, 0,
                                    s, pairs, bp, groups, ng512, nt512, nslot, d_pad, zhi, zlo, mask,
                                    t32, partial, sig);
             if (nt256 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256)), block, 0,
+                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256, 8)), block, 0,
                                    s, pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, zhi, zlo,
                                    mask, t32, partial, sig);
             break;
         }
         case HBT_I8X3:
             if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt512)), block, 0, s,
+                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt512, 4)), block, 0, s,
                                    pairs, bp, groups, ng512, nt512, nslot, d_pad, (const uint4*)zstore,
                                    zplane_elems / 16, mask, t64, partial);
             break;
