@@ -312,15 +312,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // A (32 x 32) lane l -> row l%32, k 16(l/32)..+15; B (32 x 32) lane l ->
 // k 16(l/32)..+15, col l%32; D lane l -> col l%32, rows 8(v/4) + 4(l/32) + v%4.
 //
-// Work-group tile: 64 columns x kTileI8 (512) splits; wave w owns splits
-// [128 w, 128 w + 128) as 4 blocks of 32 and the 64 columns as 2 blocks of
-// 32 (accumulators 2 sums x 2 x 4 x 16 int32 per lane, all of the AGPRs).
+// Work-group tile: 64 columns x kTileI8 (256) splits; wave w owns splits
+// [64 w, 64 w + 64) as 2 blocks of 32 and the 64 columns as 2 blocks of 32
+// (accumulators 2 sums x 2 x 2 x 16 int32 per lane), so that two
+// work-groups share a CU (226 registers per lane, 56 KB of LDS each), as in
+// the split-BF16 kernel (512-split tiles with one work-group per CU and
+// three buffers: 4.32 ms on 512 pairs, d = 768; this form: 3.91 ms).
 // A K-step is 32 pooled rows, one mask word: operand register s of lane
 // half h is (word >> (s + 4 h)) & 0x01010101 (the planes' row order makes
 // those the lane's rows), and that shifted left by 7 for the middle plane.
 // Z streams through LDS in chunks of 128 rows (three planes of the 64
-// columns = 24 KB, mask words 8 KB) with the persistent launch and cross-tile
-// prefetch of the split-BF16 kernel.  Splits past the block's end take the
+// columns = 24 KB, mask words 4 KB), two buffers, with the persistent launch
+// of the split-BF16 kernel.  Splits past the block's end take the
 // mask of its first split and are not written.
 // ---------------------------------------------------------------------------
 typedef int i32x4 __attribute__((ext_vector_type(4)));
@@ -330,18 +333,18 @@ constexpr int kChunkVecI8 = 3 * kHex * kDSlot;     // uint4 per chunk (three pla
 // |S_lo| <= 64 N (2^7 + 1) and |S_hi| <= 64 N must stay int32 for every pooled size
 static_assert(64LL * HBT_MAX_N * 129 < (1LL << 31), "int8 digit sums overflow int32");
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_groupsum_i8x3(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_i8x3(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zq, int64_t plane_vec, const uint32_t* __restrict__ mask,
     const double* __restrict__ t64, double* __restrict__ partial) {
-    constexpr int JB = 4, kWS = 32 * JB;        // splits per wave
+    constexpr int JB = 2, kWS = 32 * JB;        // splits per wave
     constexpr int kRowsPerWave = 3 * kHex / 4;  // LDS rows of Z each wave loads (6)
     constexpr int kMaskLoads = kWS / 64;        // mask loads per wave per chunk
-    constexpr int kWaitOneChunk = wait_vmcnt(kRowsPerWave + kMaskLoads);
+    constexpr int kWaitOneChunk = wait_vmcnt(0);  // the one chunk in flight
     static_assert(kTileI8 == 4 * kWS, "tile width");
-    __shared__ uint4 zbuf[3][kChunkVecI8];
-    __shared__ uint4 mbuf[3][kTileI8];
+    __shared__ uint4 zbuf[2][kChunkVecI8];
+    __shared__ uint4 mbuf[2][kTileI8];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         return Tile{grp.pair, local / grp.nbt, (local % grp.nbt) * kTileI8};
     };
 
-    // loader cursor (two chunks ahead of the multiplication, across tiles)
+    // loader cursor (one chunk ahead of the multiplication, across tiles)
     int l_it = next_valid(blockIdx.x);
     if (l_it >= nlogical) return;  // work-group-uniform
     int l_ch = 0, l_nchunk = 0;
@@ -408,9 +411,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
     };
 
-    int g = 0;  // global step: buffer g % 3
+    int g = 0;  // global step: buffer g % 2
     issue_next(0);
-    issue_next(1);
     __builtin_amdgcn_s_waitcnt(kWaitOneChunk);
     __syncthreads();
 
@@ -432,8 +434,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     for (int v = 0; v < 16; ++v) acc[q][i][j][v] = 0;
 
         for (int ch = 0; ch < nchunk; ++ch, ++g) {
-            const int b = g % 3;
-            issue_next(b == 0 ? 2 : b - 1);  // buffer (g + 2) mod 3, read in step g - 1
+            const int b = g & 1;
+            issue_next(b ^ 1);
             const uint4* cur = zbuf[b];
             const uint4* mcur = mbuf[b];
             // the chunk's mask words of the lane's splits: group flip, lane-half shift
@@ -634,11 +636,13 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
     }
 }
 
-// Work-groups of a persistent launch over `tiles` tiles: per_cu per CU
-// (measured on MI355X with one resident work-group per CU: 1 per CU leaves
-// the tail unbalanced, one per tile loses the cross-tile prefetch, 4 is
-// best; with two resident, 8), a multiple of 32 so that the XCD numbering
-// holds.
+// Work-groups of a persistent launch over `tiles` tiles: per_cu per CU, a
+// multiple of 32 so that the XCD numbering holds.  Measured on MI355X (512
+// pairs, d = 768): with one resident work-group per CU (int8 planes), 1 per
+// CU leaves the tail unbalanced and one per tile loses the cross-tile
+// prefetch, 4 is best; with two resident (split BF16), 2 / 4 / 8 / 16 / 32 /
+// 64 per CU give 4.80 / 4.70 / 4.62 / 4.60 / 4.52 / 4.50 ms and one per tile
+// 4.51 ms: the co-resident work-group already hides a tile's start.
 static std::atomic<int> g_cus[64];
 static unsigned persistent_grid(int64_t tiles, int per_cu) {
     int dev = 0;
@@ -668,19 +672,19 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             const uint4* zhi = (const uint4*)zstore;
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
             if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512, 8)), block, 0,
+                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512, 32)), block, 0,
                                    s, pairs, bp, groups, ng512, nt512, nslot, d_pad, zhi, zlo, mask,
                                    t32, partial, sig);
             if (nt256 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256, 8)), block, 0,
+                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256, 32)), block, 0,
                                    s, pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, zhi, zlo,
                                    mask, t32, partial, sig);
             break;
         }
         case HBT_I8X3:
-            if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt512, 4)), block, 0, s,
-                                   pairs, bp, groups, ng512, nt512, nslot, d_pad, (const uint4*)zstore,
+            if (nt256 > 0)
+                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, 32)), block, 0, s,
+                                   pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, (const uint4*)zstore,
                                    zplane_elems / 16, mask, t64, partial);
             break;
         case HBT_F32:
