@@ -610,7 +610,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             if (prm->masks)
                 HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, s));
             else
-                HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat, s));
+                HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat, 0, s));
         }
         const int ntiles = (int)((nb + groupsum_tile_splits(P.precision) - 1) / groupsum_tile_splits(P.precision));
         {
@@ -731,13 +731,16 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     }
     // The splits depend only on the seeds and the group sizes, not on the
     // alignment: they are drawn on a second stream beside it (integer VALU
-    // work beside HBM-bound work) and joined before the group sums.
+    // work beside HBM-bound work) and joined before the group sums.  At most
+    // 5 split work-groups per CU leave wave slots to the alignment kernels
+    // (measured on 512 pairs, d = 768: 8.27 ms per call uncapped, where the
+    // stages take turns; 7.5 ms at 4 or 5; 7.85 ms at 3).
     Fork fork(s);
     HIP_TRY(fork.begin());
     {
         StageTimer t_(HBT_STAGE_SPLIT, fork.side);
         HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
-                                   fork.side));
+                                   5, fork.side));
     }
     st = enqueue_prologue(P, w, common->align, common->gd, results, s, false);
     if (st) return st;

@@ -56,9 +56,12 @@ size_t split_lds_limit();
 // Per-pair problems found while drawing or copying splits go to sstat (one
 // int32 per pair, zeroed by the caller), apart from the pair state that the
 // alignment writes, so that the split stage may run beside the alignment.
+// wg_per_cu > 0 pads each work-group's LDS so that at most that many share a
+// CU: beside the alignment kernels, an uncapped split kernel takes every wave
+// slot and the two stages run one after the other.
 hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
-                              int32_t* sstat, hipStream_t s);
+                              int32_t* sstat, int wg_per_cu, hipStream_t s);
 // Explicit masks: copy rows of ceil(N/32) words into the workspace layout and
 // check that each holds exactly n items.
 hipError_t launch_copy_masks(const uint32_t* user, int64_t user_row0, int64_t rows, int N, int n,

@@ -12,6 +12,8 @@
 //
 // One wavefront per split row; waves of a work-group are independent and
 // synchronise only within themselves.
+#include <atomic>
+
 #include "hbt_launch.h"
 
 namespace hbt {
@@ -245,6 +247,20 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
     for (int w = lane; w < pd.Wp; w += 64) out[w] = mlds[w];
 }
 
+// LDS of one CU (160 KB on MI355X), from the device.
+static size_t lds_per_cu() {
+    static std::atomic<size_t> v{0};
+    size_t x = v.load(std::memory_order_relaxed);
+    if (!x) {
+        int dev = 0, a = 0;
+        x = (hipGetDevice(&dev) == hipSuccess &&
+             hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+             a > 0) ? (size_t)a : 163840;
+        v.store(x, std::memory_order_relaxed);
+    }
+    return x;
+}
+
 size_t split_lds_limit() {
     static size_t lim = 0;
     if (!lim) {
@@ -262,11 +278,15 @@ size_t split_lds_per_block(int max_np) { return (size_t)kSplitWaves * SplitLds(m
 
 hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
-                              int32_t* sstat, hipStream_t s) {
+                              int32_t* sstat, int wg_per_cu, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     const SplitLds L(max_np);
     // four split rows per work-group; at most 64 KB of LDS per work-group
-    const size_t lds = (size_t)kSplitWaves * L.total;
+    size_t lds = (size_t)kSplitWaves * L.total;
+    if (wg_per_cu > 0) {
+        const size_t share = lds_per_cu() / (size_t)wg_per_cu;
+        if (share > lds + kSplitStaticLds) lds = share - kSplitStaticLds;
+    }
     if (lds + kSplitStaticLds > 65536 || lds + kSplitStaticLds > split_lds_limit()) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((rows + kSplitWaves - 1) / kSplitWaves)), block(64 * kSplitWaves);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
