@@ -721,12 +721,6 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         StageTimer t_(HBT_STAGE_OTHER, s);
         HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
         HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
-        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
-            HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
-        else
-            HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
-        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
-        HIP_TRY(zero(w.nflag, 8, s));
         HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, s));
     }
     // The splits depend only on the seeds and the group sizes, not on the
@@ -747,6 +741,15 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     {
         StageTimer t_(HBT_STAGE_ALIGN, s);
         HIP_TRY(reflect(P, w, nullptr, s));
+    }
+    {  // tables only the later stages read, enqueued while the splits finish
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
+            HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
+        else
+            HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
+        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
+        HIP_TRY(zero(w.nflag, 8, s));
     }
     HIP_TRY(fork.join());
     {
