@@ -23,6 +23,10 @@ its B = 5,000 ... 20,000 permutation budgets):
 * batch_512_d768 (stream 4) - 512 pairs, d=768, n_p and m_p log-uniform on [20, 5000],
   kappa ~ U[1.5, 3.0], half the pairs null, random mean directions.
 * budget_batch_4096 (stream 5) - 4096 pairs, d=768, n and m log-uniform on [20, 2000].
+* rejection_batch (stream 6) - the shape of the paper's rejection-rate experiment:
+  500 pairs, d=768, B=5000; n log-uniform on [100, 1000] and m within 10% of n,
+  kappa_X ~ U[2, 4], mean directions U[20, 70] degrees apart; "null" keeps
+  kappa_Y = kappa_X, "alt" makes Y 2% more concentrated (X broader).
 """
 from __future__ import annotations
 
@@ -36,7 +40,7 @@ import numpy as np
 __all__ = [
     "rng_for", "unit_rows", "random_unit", "direction_at_angle", "lowrank_factor",
     "cloud_diag", "cloud_lowrank", "Pair", "Batch", "small_pair_f64", "pair_d768", "null_pair_d1024",
-    "batch_512_d768", "budget_batch_4096", "pack_batch", "log_uniform_int",
+    "batch_512_d768", "budget_batch_4096", "rejection_batch", "pack_batch", "log_uniform_int",
 ]
 
 
@@ -222,3 +226,41 @@ def batch_512_d768(npairs=512, d=768, B=2000, limit=None) -> Batch:
 def budget_batch_4096(npairs=4096, d=768, B=20000, limit=None) -> Batch:
     pairs, info = _batch_workload(5, npairs, d, 20, 2000, B, limit)
     return pack_batch(pairs, d, meta=dict(workload="budget_batch_4096", **info))
+
+
+REJECTION_EFFECT = 0.02
+
+
+def rejection_batch(population="null", npairs=500, d=768, B=5000, limit=None) -> Batch:
+    """Pairs shaped like the paper's rejection-rate experiment (Sec. 5 of the
+    appendix experiments: 500 word pairs, B = 5,000, alpha = 0.05, a null and an
+    alternative condition).
+
+    Words a few frequency ranks apart have similar token counts, so m is drawn
+    within 10% of n.  Both conditions give the two clouds different mean
+    directions (the confounder the alignment removes); "null" keeps the same
+    breadth, "alt" makes Y's cloud more concentrated by REJECTION_EFFECT in
+    kappa, so X is the broader one and the "greater" alternative holds.  The two
+    conditions share every draw except kappa_Y (common random numbers), so their
+    rates are compared on the same clouds and directions.
+    """
+    if population not in ("null", "alt"):
+        raise ValueError("population must be 'null' or 'alt'")
+    g = rng_for(6, 0, 99)
+    ns = log_uniform_int(g, 100, 1000, npairs)
+    ms = np.rint(ns * g.uniform(0.9, 1.1, npairs)).astype(np.int64)
+    ka = g.uniform(2.0, 4.0, npairs)
+    angle = g.uniform(20.0, 70.0, npairs)
+    kb = ka * (1.0 + (REJECTION_EFFECT if population == "alt" else 0.0))
+    factor = lowrank_factor(d)
+    idx = list(range(npairs) if limit is None else limit)
+
+    def one(p):
+        X, Y = _lowrank_pair(6, p, int(ns[p]), int(ms[p]), d, float(ka[p]), float(kb[p]),
+                             angle=float(angle[p]), factor=factor)
+        return Pair(X, Y, B=B, seed=0, pair_index=p)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        pairs = list(ex.map(one, idx))
+    return pack_batch(pairs, d, meta=dict(workload="rejection_batch", population=population,
+                                          kappa_a=ka, kappa_b=kb, angle=angle, n=ns, m=ms))

@@ -270,6 +270,27 @@ def test_type_one_error_near_alpha_for_same_breadth_null():
     assert abs(rate - 0.05) <= band, rate
 
 
+def test_naive_test_rejects_too_often_when_directions_differ():
+    """The failure mode the alignment removes (Sec. 1, Fig. 1): with equal
+    breadth and equal group sizes, pooling two clouds whose mean directions
+    differ lowers every permuted r, which narrows the naive null of T, so the
+    naive test rejects well above alpha; the aligned test on the same pairs
+    stays at alpha.  (With very unequal n and m the share of X rows in a
+    permuted group varies to first order and widens the naive null instead.)"""
+    R, d, B = 300, 32, 199
+    fac = synth.lowrank_factor(d)
+    rej = {0: 0, 1: 0}
+    for k in range(R):
+        g = np.random.default_rng([78, k])
+        n = int(g.integers(60, 160))
+        X, Y = synth._lowrank_pair(60, k, n, n, d, 3.0, 3.0, angle=60.0, factor=fac)
+        for a in (0, 1):
+            rej[a] += O.perm_test(X, Y, B=B, seed=k, align=a)["p"] <= 0.05
+    band = 3 * np.sqrt(0.05 * 0.95 / R)
+    assert abs(rej[1] / R - 0.05) <= band, rej
+    assert rej[0] / R > 0.05 + band, rej
+
+
 def test_power_when_x_is_broader():
     rej = 0
     for k in range(60):
