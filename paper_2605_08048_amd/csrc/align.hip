@@ -96,13 +96,37 @@ hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, int npairs,
 // work-group = one chunk of rows x all columns; wave w sums rows w, w+4, ...
 // of the chunk with 16-byte loads (lane l: columns 4(l + 64 j) .. +3), the
 // four waves' sums are added in a fixed order through LDS.
+// Row loads through a buffer resource: the hardware returns 0 for every
+// byte offset at or past the resource's size without touching memory, so a
+// row that does not exist (size 0) or a column at or past d reads zero with
+// no branch and no select, and the loads of several rows are all in flight
+// before the first wait.  Word 3 is the gfx9 raw-buffer format (32-bit data).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+
+// This lane's J x 4 columns 256 j + 64 e + lane of one FP32 row of d values
+// (all zero when the row is not valid).
 template <int J>
-__global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pairs,
-                                                 int npairs, int d,
-                                                 double* __restrict__ partial) {
-    __shared__ double red[3][256 * J];
-    const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
-    const PairDesc pd = pairs[ch.pair];
+__device__ __forceinline__ void load_cols(float (&x)[J][4], const float* row, int d, bool valid) {
+    const int lane = threadIdx.x & 63;
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, valid ? 4 * d : 0);
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            x[j][e] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * (256 * j + 64 * e + lane), 0, 0));
+}
+
+// (red: at least 3 rows of 256 J doubles)
+template <int J>
+__device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc& pd, int d,
+                                              double* __restrict__ partial_row,
+                                              double (*red)[256 * J]) {
     const float* base = (const float*)(ch.side ? pd.Y : pd.X);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double acc[J][4];
@@ -110,21 +134,32 @@ __global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pa
     for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[j][e] = 0.0;
-    for (int r = ch.r0 + wave; r < ch.r1; r += 4) {
-        const float4* row = (const float4*)(base + (int64_t)r * d);
-        float4 x[J];
+    // rows r, r + 4, r + 8, r + 12 per step, all loads issued first (rows past
+    // the chunk read zero, see load_cols); the additions keep the row order
+    for (int r = ch.r0 + wave; r < ch.r1; r += 16) {
+        float4 x[4][J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int q = lane + 64 * j;
-            x[j] = 4 * q < d ? row[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = 0; q < 4; ++q) {
+            const int rr = r + 4 * q;
+            const __amdgpu_buffer_rsrc_t rs =
+                row_rsrc(base + (int64_t)(rr < ch.r1 ? rr : r) * d, rr < ch.r1 ? 4 * d : 0);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (lane + 64 * j), 0, 0);
+                x[q][j] = make_float4(__uint_as_float(u.x), __uint_as_float(u.y),
+                                      __uint_as_float(u.z), __uint_as_float(u.w));
+            }
         }
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            acc[j][0] += (double)x[j].x;
-            acc[j][1] += (double)x[j].y;
-            acc[j][2] += (double)x[j].z;
-            acc[j][3] += (double)x[j].w;
-        }
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (r + 4 * q >= ch.r1) continue;  // wave-uniform: nothing added past the chunk
+                acc[j][0] += (double)x[q][j].x;
+                acc[j][1] += (double)x[q][j].y;
+                acc[j][2] += (double)x[q][j].z;
+                acc[j][3] += (double)x[q][j].w;
+            }
     }
     if (wave > 0)
 #pragma unroll
@@ -138,10 +173,17 @@ __global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pa
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int c = 4 * (lane + 64 * j) + e;
-                if (c < d)
-                    partial[(int64_t)blockIdx.x * d + c] =
-                        (acc[j][e] + red[0][c]) + (red[1][c] + red[2][c]);
+                if (c < d) partial_row[c] = (acc[j][e] + red[0][c]) + (red[1][c] + red[2][c]);
             }
+}
+
+template <int J>
+__global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pairs,
+                                                 int npairs, int d,
+                                                 double* __restrict__ partial) {
+    __shared__ double red[3][256 * J];
+    const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
+    colsum4_chunk<J>(ch, pairs[ch.pair], d, partial + (int64_t)blockIdx.x * d, red);
 }
 
 bool vector_rows_ok(int input_dtype, int d, int d_pad) {
@@ -441,6 +483,81 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
     return x;
 }
 
+// Stores one storage octet of a pair: this lane's J x 4 columns of the 8
+// rows row_of(0..7) (pair-relative pooled rows), z_r = x_r - k_r vc in FP64,
+// in the precision's format.  soct is the octet's index in the whole storage.
+template <int PREC, int J, typename RowOf>
+__device__ __forceinline__ void store_octet(const float (&x)[8][J][4], const double (&k)[8],
+                                            const double (&vc)[J][4], int64_t soct, int64_t zrow0,
+                                            RowOf row_of, int o4, int d_pad, void* zstore,
+                                            int64_t zplane_elems, float* __restrict__ z32) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 256 * j + 64 * e + lane;
+            if (256 * j + 64 * e >= d_pad) continue;  // wave-uniform: d_pad is a multiple of 64
+            if (PREC == HBT_F64) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int64_t zr = zrow0 + row_of(r);
+                    const double z = (double)x[r][j][e] - k[r] * vc[j][e];
+                    ((double*)zstore)[zr * d_pad + c] = z;
+                    if (z32) z32[zr * d_pad + c] = (float)z;
+                }
+                continue;
+            }
+            if (PREC == HBT_I8X3) {  // digits of the FP64 update
+                uint32_t w[3][2] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    uint32_t q[3];
+                    i8_digits((double)x[r][j][e] - k[r] * vc[j][e], q[0], q[1], q[2]);
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) w[t][r >> 2] |= q[t] << (8 * (r & 3));
+                }
+                char* dst = (char*)zstore + ((soct >> 1) * d_pad + c) * 16 + 8 * (soct & 1);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) *(uint2*)(dst + t * zplane_elems) = make_uint2(w[t][0], w[t][1]);
+                continue;
+            }
+            // FP64 update, rounded to FP32 at once (the storage is FP32 or BF16 hi+lo)
+            float zf[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) zf[r] = (float)((double)x[r][j][e] - k[r] * vc[j][e]);
+            if (PREC == HBT_F32 || z32) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int64_t zr = zrow0 + row_of(r);
+                    if (PREC == HBT_F32) ((float*)zstore)[zr * d_pad + c] = zf[r];
+                    if (z32) z32[zr * d_pad + c] = zf[r];
+                }
+            }
+            if (PREC == HBT_BF16X2) {
+                uint32_t hi[4], lo[4];
+#pragma unroll
+                for (int r = 0; r < 8; r += 2) {
+                    const uint2 hl = split_bf16x2(zf[r] * bf16_plane_scale(o4, r), zf[r + 1] * bf16_plane_scale(o4, r + 1));
+                    hi[r / 2] = hl.x;
+                    lo[r / 2] = hl.y;
+                }
+                uint4* ph = (uint4*)zstore + soct * d_pad + c;
+                *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+                *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+            }
+        }
+}
+
+template <int PREC>
+__device__ __forceinline__ int plane_row(int o4, int k) {
+    return PREC == HBT_I8X3 ? i8_plane_row(o4, k) : bf16_plane_row(o4, k);
+}
+
+// The reflection on the 16-byte path: one wave per storage octet of the
+// 32-row groups that hold X rows (x_octets(n) per pair, numbered from
+// PairDesc::xoct0); the groups that hold only Y rows or padding are stored by
+// k_colsum_store4.
 template <int PREC, int J>
 __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ pairs, int npairs,
                                                   int64_t total_octets,
@@ -451,32 +568,31 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oct = (int64_t)blockIdx.x * 4 + wave;
     if (oct >= total_octets) return;
-    const int p = upper_index(npairs, oct * 8, [&](int k) { return pairs[k].zrow0; });
+    const int p = upper_index(npairs, oct, [&](int k) { return pairs[k].xoct0; });
     const PairDesc pd = pairs[p];
     const int identity = st[p].identity;
     const double vv = st[p].vv;
     const double* vp = v + (int64_t)p * d_pad;
-    const int lo8 = (int)(oct - pd.zrow0 / 8);  // storage octet within the pair
+    const int lo8 = (int)(oct - pd.xoct0);  // storage octet within the pair
     const int g0 = 32 * (lo8 >> 2), o4 = lo8 & 3;
     const int N = pd.n + pd.m;
-    auto row_of = [&](int r) { return g0 + (PREC == HBT_I8X3 ? i8_plane_row(o4, r) : bf16_plane_row(o4, r)); };
+    auto row_of = [&](int r) { return g0 + plane_row<PREC>(o4, r); };
     auto col = [&](int j, int e) { return 256 * j + 64 * e + lane; };
     float x[8][J][4];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int i = row_of(r);  // wave-uniform
+        const int i = row_of(r);  // wave-uniform; a padding row reads Y's last row and keeps zeros
         const float* row = i < pd.n ? (const float*)pd.X + (int64_t)i * d
-                                    : (const float*)pd.Y + (int64_t)(i - pd.n) * d;
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) x[r][j][e] = (i < N && col(j, e) < d) ? row[col(j, e)] : 0.f;
+                                    : (const float*)pd.Y + (int64_t)((i < N ? i : N - 1) - pd.n) * d;
+        load_cols<J>(x[r], row, d, i < N);
     }
     double vc[J][4];
+    const __amdgpu_buffer_rsrc_t vrs = row_rsrc(vp, 8 * d);  // columns past d read 0
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vc[j][e] = col(j, e) < d ? vp[col(j, e)] : 0.0;
+        for (int e = 0; e < 4; ++e)
+            vc[j][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(vrs, 8 * col(j, e), 0, 0));
     // coefficients 2 (v . x_i) / (v . v) of the X rows (eq:householder_fast)
     double k[8];
 #pragma unroll
@@ -506,61 +622,8 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
         const int i = row_of(lane);
         if (i < pd.n) coef[pd.coef0 + i] = kr;
     }
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = col(j, e);
-            if (256 * j + 64 * e >= d_pad) continue;  // wave-uniform: d_pad is a multiple of 64
-            if (PREC == HBT_F64) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int64_t zr = pd.zrow0 + row_of(r);
-                    const double z = (double)x[r][j][e] - k[r] * vc[j][e];
-                    ((double*)zstore)[zr * d_pad + c] = z;
-                    if (z32) z32[zr * d_pad + c] = (float)z;
-                }
-                continue;
-            }
-            if (PREC == HBT_I8X3) {  // digits of the FP64 update
-                uint32_t w[3][2] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    uint32_t q[3];
-                    i8_digits((double)x[r][j][e] - k[r] * vc[j][e], q[0], q[1], q[2]);
-#pragma unroll
-                    for (int t = 0; t < 3; ++t) w[t][r >> 2] |= q[t] << (8 * (r & 3));
-                }
-                char* dst = (char*)zstore + ((oct >> 1) * d_pad + c) * 16 + 8 * (oct & 1);
-#pragma unroll
-                for (int t = 0; t < 3; ++t) *(uint2*)(dst + t * zplane_elems) = make_uint2(w[t][0], w[t][1]);
-                continue;
-            }
-            // FP64 update, rounded to FP32 at once (the storage is FP32 or BF16 hi+lo)
-            float zf[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) zf[r] = (float)((double)x[r][j][e] - k[r] * vc[j][e]);
-            if (PREC == HBT_F32 || z32) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int64_t zr = pd.zrow0 + row_of(r);
-                    if (PREC == HBT_F32) ((float*)zstore)[zr * d_pad + c] = zf[r];
-                    if (z32) z32[zr * d_pad + c] = zf[r];
-                }
-            }
-            if (PREC == HBT_BF16X2) {
-                uint32_t hi[4], lo[4];
-#pragma unroll
-                for (int r = 0; r < 8; r += 2) {
-                    const uint2 hl = split_bf16x2(zf[r] * bf16_plane_scale(o4, r), zf[r + 1] * bf16_plane_scale(o4, r + 1));
-                    hi[r / 2] = hl.x;
-                    lo[r / 2] = hl.y;
-                }
-                uint4* ph = (uint4*)zstore + oct * d_pad + c;
-                *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-                *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-            }
-        }
+    store_octet<PREC, J>(x, k, vc, pd.zrow0 / 8 + lo8, pd.zrow0, row_of, o4, d_pad, zstore,
+                         zplane_elems, z32);
 }
 
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
@@ -589,6 +652,101 @@ hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
     }
 #undef HBT_R4J
 #undef HBT_R4
+    return hipGetLastError();
+}
+
+// Column sums and, in the same pass, the Z storage of the Y rows (16-byte
+// path, group-sum calls).  X chunks are summed as in k_colsum4.  A Y chunk is
+// one 32-row group of the storage: wave w loads octet w (the 8 rows
+// plane_row(w, .) of the group), adds its Y rows to the sums and stores the
+// octet as it is (H leaves Y unchanged; rows past n + m are the zero
+// padding), except in the group that also holds X rows, which the reflection
+// stores.  Y's rows are then read once for both purposes.
+template <int PREC, int J>
+__global__ __launch_bounds__(256) void k_colsum_store4(const PairDesc* __restrict__ pairs,
+                                                       int npairs, int d, int d_pad,
+                                                       double* __restrict__ partial, void* zstore,
+                                                       int64_t zplane_elems,
+                                                       float* __restrict__ z32) {
+    __shared__ double red[4][256 * J];
+    const int c = blockIdx.x;
+    const SumChunk ch = chunk_of(pairs, npairs, c);
+    const PairDesc pd = pairs[ch.pair];
+    double* prow = partial + (int64_t)c * d;
+    if (!ch.side) {  // work-group-uniform
+        colsum4_chunk<J>(ch, pd, d, prow, red);
+        return;
+    }
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int n = pd.n, N = n + pd.m;
+    const int g0 = (n + ch.r0) & ~31;  // the chunk's group
+    auto row_of = [&](int r) { return g0 + plane_row<PREC>(wave, r); };
+    auto col = [&](int j, int e) { return 256 * j + 64 * e + lane; };
+    float x[8][J][4];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = row_of(r);
+        const bool y = i >= n && i < N;  // wave-uniform; other rows read Y's first row and keep zeros
+        load_cols<J>(x[r], (const float*)pd.Y + (int64_t)(y ? i - n : 0) * d, d, y);
+    }
+    // each wave's sums go to LDS at once, so they are not live across the stores
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) t += (double)x[r][j][e];
+            red[wave][col(j, e)] = t;
+        }
+    // the stores convert the rows to FP64 again instead of keeping the sums'
+    // FP64 copies alive (twice the registers)
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            asm volatile("" : "+v"(x[r][j][0]), "+v"(x[r][j][1]), "+v"(x[r][j][2]), "+v"(x[r][j][3]));
+    if (g0 >= n) {  // wave-uniform
+        double k0[8], v0[J][4];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) k0[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v0[j][e] = 0.0;
+        store_octet<PREC, J>(x, k0, v0, pd.zrow0 / 8 + g0 / 8 + wave, pd.zrow0, row_of, wave, d_pad,
+                             zstore, zplane_elems, z32);
+    }
+    __syncthreads();
+    for (int cc = threadIdx.x; cc < d; cc += 256)
+        prow[cc] = (red[0][cc] + red[1][cc]) + (red[2][cc] + red[3][cc]);
+}
+
+hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npairs, int nchunks,
+                                   int d, int d_pad, double* partial, void* zstore,
+                                   int64_t zplane_elems, float* z32, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    const int J = (d_pad + 255) / 256;
+    const dim3 g(nchunks), b(256);
+#define HBT_C4(PR, JJ)                                                                         \
+    hipLaunchKernelGGL((k_colsum_store4<PR, JJ>), g, b, 0, s, pairs, npairs, d, d_pad, partial, \
+                       zstore, zplane_elems, z32)
+#define HBT_C4J(PR)                            \
+    switch (J) {                               \
+        case 1: HBT_C4(PR, 1); break;          \
+        case 2: HBT_C4(PR, 2); break;          \
+        case 3: HBT_C4(PR, 3); break;          \
+        case 4: HBT_C4(PR, 4); break;          \
+        default: return hipErrorInvalidValue;  \
+    }
+    switch (precision) {
+        case HBT_F64: HBT_C4J(HBT_F64); break;
+        case HBT_F32: HBT_C4J(HBT_F32); break;
+        case HBT_I8X3: HBT_C4J(HBT_I8X3); break;
+        default: HBT_C4J(HBT_BF16X2); break;
+    }
+#undef HBT_C4J
+#undef HBT_C4
     return hipGetLastError();
 }
 

@@ -164,6 +164,7 @@ struct Plan {
     int64_t nt512 = 0, nt256 = 0; // their tiles (tile0 counts from 0 in each segment)
     std::vector<int64_t> Btot;
     int64_t zrows = 0, ncoef = 0;
+    int64_t xoct = 0;             // storage octets that hold X rows (all pairs)
     int64_t block_rows = 0;       // split rows of the largest block
     int64_t block_mask_words = 0; // mask words of the largest block
     bool need_store = true;       // group-sum path (false for hbt_align)
@@ -250,9 +251,12 @@ void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint3
     for (int64_t r = 0; r < n; r += kSumChunk)
         P.chunks.push_back(SumChunk{p, 0, (int32_t)r, (int32_t)std::min<int64_t>(n, r + kSumChunk)});
     pd.cx1 = (int32_t)P.chunks.size();
-    for (int64_t r = 0; r < m; r += kSumChunk)
-        P.chunks.push_back(SumChunk{p, 1, (int32_t)r, (int32_t)std::min<int64_t>(m, r + kSumChunk)});
+    for (int64_t j = n / kSumChunkY; kSumChunkY * j < pd.Np; ++j)  // groups from row n to Np
+        P.chunks.push_back(SumChunk{p, 1, (int32_t)(std::max<int64_t>(n, kSumChunkY * j) - n),
+                                    (int32_t)(std::min<int64_t>(n + m, kSumChunkY * (j + 1)) - n)});
     pd.cy1 = (int32_t)P.chunks.size();
+    pd.xoct0 = P.xoct;
+    P.xoct += x_octets(n);
     P.zrows += pd.Np;
     P.ncoef += n;
     P.max_np = std::max(P.max_np, (int)pd.Np);
@@ -370,10 +374,13 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
 // 16-byte row loads apply: FP32 rows, d a multiple of 4, aligned bases.
 bool vector_rows(const Plan& P) { return P.aligned16 && vector_rows_ok(P.input_dtype, P.d, P.d_pad); }
 
-// Householder reflection of every pair and the precision's Z storage.
+// Householder reflection of every pair and the precision's Z storage.  On the
+// 16-byte-load path the column-sum pass has already stored the 32-row groups
+// that hold only Y rows or padding, so the reflection covers the groups that
+// hold X rows.
 hipError_t reflect(const Plan& P, const Workspace& w, float* z32, hipStream_t s) {
     if (vector_rows(P))
-        return launch_reflect_vec(P.precision, w.pairs, P.npairs, P.zrows / 8, w.st, w.v, P.d, P.d_pad,
+        return launch_reflect_vec(P.precision, w.pairs, P.npairs, P.xoct, w.st, w.v, P.d, P.d_pad,
                                   w.coef, w.zstore, P.zrows * P.d_pad, z32, s);
     return launch_reflect(P.input_dtype, P.precision, w.pairs, P.npairs, P.zrows / 8, w.st, w.v, P.d,
                           P.d_pad, w.coef, w.zstore, P.zrows * P.d_pad, z32, s);
@@ -386,7 +393,10 @@ hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd
         HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
     }
     StageTimer t(HBT_STAGE_ALIGN, s);
-    if (vector_rows(P))
+    if (vector_rows(P) && P.need_store)
+        HIP_TRY(launch_colsum_store_vec(P.precision, w.pairs, P.npairs, (int)P.chunks.size(), P.d,
+                                        P.d_pad, w.partial_sum, w.zstore, P.zrows * P.d_pad, w.z32, s));
+    else if (vector_rows(P))
         HIP_TRY(launch_colsum_vec(w.pairs, P.npairs, (int)P.chunks.size(), P.d, P.d_pad, w.partial_sum, s));
     else
         HIP_TRY(launch_colsum(P.input_dtype, w.pairs, P.npairs, (int)P.chunks.size(), P.d,
@@ -726,15 +736,16 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     // The splits depend only on the seeds and the group sizes, not on the
     // alignment: they are drawn on a second stream beside it (integer VALU
     // work beside HBM-bound work) and joined before the group sums.  At most
-    // 5 split work-groups per CU leave wave slots to the alignment kernels
-    // (measured on 512 pairs, d = 768: 8.27 ms per call uncapped, where the
-    // stages take turns; 7.5 ms at 4 or 5; 7.85 ms at 3).
+    // 6 split work-groups per CU leave wave slots to the alignment kernels
+    // (measured on 512 pairs, d = 768, split BF16: 8.03 ms per call at 8 or
+    // uncapped, where the alignment then waits for wave slots; 7.25 ms at 6,
+    // the two stages 2.1 ms each; 7.56 ms at 5, 7.63 ms at 4).
     Fork fork(s);
     HIP_TRY(fork.begin());
     {
         StageTimer t_(HBT_STAGE_SPLIT, fork.side);
         HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
-                                   5, fork.side));
+                                   6, fork.side));
     }
     st = enqueue_prologue(P, w, common->align, common->gd, results, s, false);
     if (st) return st;

@@ -39,7 +39,9 @@ struct PairDesc {
     int32_t cx0, cx1;    // column-sum chunks of X: [cx0, cx1); of Y: [cx1, cy1)
     int32_t cy1;
     int32_t _pad0;
-    int64_t _pad1[3];
+    int64_t xoct0;       // first of its x_octets(n) octets in the numbering of the storage
+                         // octets that hold X rows (the reflection's work items)
+    int64_t _pad1[2];
 };
 static_assert(sizeof(PairDesc) == 96, "PairDesc layout");
 
@@ -66,7 +68,10 @@ struct SumChunk {
     int32_t pair, side;  // side 0 = X, 1 = Y
     int32_t r0, r1;
 };
-constexpr int kSumChunk = 128;  // rows per column-sum chunk
+constexpr int kSumChunk = 128;  // X rows per column-sum chunk
+constexpr int kSumChunkY = 32;  // pooled rows per Y chunk: one 32-row group of the Z storage
+// Storage octets of a pair that hold X rows: the 32-row groups that hold any.
+__host__ __device__ constexpr int64_t x_octets(int64_t n) { return 4 * ((n + 31) / 32); }
 
 // A group-sum tile of the FP32 / FP64 kernels: kTileB split rows of one pair
 // (the grid covers all column slots).
@@ -246,16 +251,26 @@ __device__ __forceinline__ int upper_index(int count, int64_t x, F key) {
 }
 
 // Column-sum chunk c: chunks are numbered pair by pair, the X chunks of a
-// pair ([cx0, cx1)) before its Y chunks ([cx1, cy1)), kSumChunk rows each.
+// pair ([cx0, cx1)) before its Y chunks ([cx1, cy1)).  X chunk k holds X rows
+// [kSumChunk k, kSumChunk (k + 1)) (clipped to n).  The Y chunks are the
+// 32-row groups of the Z storage from the one holding row n to the padded
+// end Np: Y chunk k holds pooled rows [max(n, 32 j), min(n + m, 32 (j + 1)))
+// (none for the groups of padding only), j = n / 32 + k.
 __device__ __forceinline__ SumChunk chunk_of(const PairDesc* pairs, int npairs, int c) {
     const int p = upper_index(npairs, c, [&](int k) { return pairs[k].cx0; });
     const int cx0 = pairs[p].cx0, cx1 = pairs[p].cx1;
+    const int n = pairs[p].n, N = n + pairs[p].m;
     SumChunk ch;
     ch.pair = p;
     ch.side = c < cx1 ? 0 : 1;
-    const int rows = ch.side ? pairs[p].m : pairs[p].n;
-    ch.r0 = (c - (ch.side ? cx1 : cx0)) * kSumChunk;
-    ch.r1 = ch.r0 + kSumChunk < rows ? ch.r0 + kSumChunk : rows;
+    if (!ch.side) {
+        ch.r0 = (c - cx0) * kSumChunk;
+        ch.r1 = ch.r0 + kSumChunk < n ? ch.r0 + kSumChunk : n;
+    } else {
+        const int j = n / kSumChunkY + (c - cx1);
+        ch.r0 = (kSumChunkY * j > n ? kSumChunkY * j : n) - n;
+        ch.r1 = (kSumChunkY * (j + 1) < N ? kSumChunkY * (j + 1) : N) - n;
+    }
     return ch;
 }
 

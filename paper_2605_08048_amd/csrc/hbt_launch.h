@@ -35,6 +35,12 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 bool vector_rows_ok(int input_dtype, int d, int d_pad);
 hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int d,
                              int d_pad, double* partial, hipStream_t s);
+// Column sums plus the storage of the 32-row groups that hold no X rows (the
+// 16-byte path of the group-sum calls); launch_reflect_vec then takes the
+// x_octets(n) octets of each pair (total_octets = their sum over pairs).
+hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npairs, int nchunks,
+                                   int d, int d_pad, double* partial, void* zstore,
+                                   int64_t zplane_elems, float* z32, hipStream_t s);
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
                               int64_t total_octets, const PairState* st, const double* v, int d,
                               int d_pad, double* coef, void* zstore, int64_t zplane_elems,

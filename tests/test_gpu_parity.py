@@ -342,6 +342,33 @@ def test_batched_matches_oracle_per_pair():
                 _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
 
 
+@pytest.mark.parametrize("d", [64, 200])
+def test_batched_storage_group_boundaries(d):
+    """The Z storage is written in 32-row groups: the column-sum pass stores the
+    groups that hold only Y rows or padding, the reflection the groups that hold
+    X rows (the one straddling row n included).  Sizes around every boundary
+    of that split (n at, just below and above multiples of 32 and 128, m below
+    one group, n + m one below / at / above a 128-row padding boundary), d with
+    and without zero columns, each pair against the oracle."""
+    sizes = [(2, 2), (32, 5), (31, 33), (33, 31), (64, 64), (96, 31), (127, 1 + 1), (128, 2),
+             (129, 127), (130, 126), (200, 55), (7, 250), (256, 256), (95, 161)]
+    print(f"storage group boundaries d={d}: {len(sizes)} pairs", flush=True)
+    pairs = []
+    for p, (n, m) in enumerate(sizes):
+        X, Y = _pair(n, m, d, kx=2.0, ky=2.6, angle=50.0, seed=300 + p)
+        pairs.append(synth.Pair(X, Y, B=257, pair_index=p))
+    bt = synth.pack_batch(pairs, d)
+    for prec in ["bf16x2", "i8x3", "f32"]:
+        res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=4, precision=prec)
+        for p, pr in enumerate(pairs):
+            o = O.perm_test(pr.X, pr.Y, pr.B, seed=4, pair=p, want_T=True)
+            assert res[p]["status"] == 0, (prec, p)
+            assert abs(res[p]["t_obs"] - o["t_obs"]) <= 1e-12 * max(1, abs(o["t_obs"]))
+            assert abs(res[p]["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"]), (prec, p, sizes[p])
+            at = O.perm_stats_at(pr.X, pr.Y, np.arange(pr.B), seed=4, pair=p)
+            _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
+
+
 # --------------------------------------------------------------------- full-size configurations
 
 def test_small_pair_f64():
