@@ -235,13 +235,27 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
     double* vp = v + (int64_t)p * d_pad;
     double* tp = t64 + (int64_t)p * d_pad;
     float* tq = t32 + (int64_t)p * d_pad;
-    // Step 1: sums of X and Y, chunk partials added in chunk order
+    // Step 1: sums of X and Y, chunk partials added in chunk order (eight
+    // loads in flight at a time; the additions keep that order)
+    auto chunk_sum = [&](int k0, int k1, int c) {
+        double acc = 0.0;
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = partial[(int64_t)(k + u) * d + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t[u];
+        }
+        for (; k < k1; ++k) acc += partial[(int64_t)k * d + c];
+        return acc;
+    };
     double ssx = 0.0, ssy = 0.0;
     for (int c = threadIdx.x; c < d_pad; c += 256) {
         double a = 0.0, b = 0.0;
         if (c < d) {
-            for (int k = pd.cx0; k < pd.cx1; ++k) a += partial[(int64_t)k * d + c];
-            for (int k = pd.cx1; k < pd.cy1; ++k) b += partial[(int64_t)k * d + c];
+            a = chunk_sum(pd.cx0, pd.cx1, c);
+            b = chunk_sum(pd.cx1, pd.cy1, c);
         }
         sx[c] = a;
         sy[c] = b;
