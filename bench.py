@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
+    ap.add_argument("--single-steps", type=int, default=5,
+                    help="timed calls per precision of the single-pair workloads (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) tile-width tuning of the split-BF16 product")
@@ -265,6 +267,34 @@ def main():
               "pairs_bad_status": bad8,
               "pairs_with_counts_equal_to_bf16x2": f"{int(np.sum(out8['count'] == out['count']))}/{P}"}
 
+    # single-pair workloads (the per-pair call), every precision on the same input
+    single = None
+    if args.single_steps > 0:
+        single = {}
+        for name, pair in (("pair_d768", synth.pair_d768()), ("null_pair_d1024", synth.null_pair_d1024())):
+            X = torch.from_numpy(pair.X).to(dev)
+            Y = torch.from_numpy(pair.Y).to(dev)
+            row = {"n": pair.n, "m": pair.m, "d": pair.d, "B": pair.B}
+            counts = {}
+            for prec in ("f32", "bf16x2", "i8x3"):
+                call = lambda: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, sync=False)
+                call()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.single_steps):
+                    r = call()
+                torch.cuda.synchronize()
+                dt1 = (time.perf_counter() - t0) / args.single_steps
+                res = hbt.results_to_numpy(r["result"])[0]
+                counts[prec] = int(res["count"])
+                row[prec] = {"ms_per_call": dt1 * 1e3, "value": pair.B / dt1, "count": int(res["count"]),
+                             "p": float(res["p"]), "n_recheck": int(res["n_recheck"]),
+                             "status": int(res["status"])}
+            row["speedup_bf16x2_over_f32"] = row["f32"]["ms_per_call"] / row["bf16x2"]["ms_per_call"]
+            row["counts_equal"] = len(set(counts.values())) == 1
+            single[name] = row
+            log(f"single pair {name}: " + ", ".join(f"{k} {row[k]['ms_per_call']:.3f} ms" for k in counts))
+
     line = {
         "metric": "permuted statistics/s at d=768 (batched split-BF16 MFMA; plain FP32 in fp32_plain)",
         "value": value,
@@ -291,6 +321,7 @@ def main():
         "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
         "int8_planes": i8,
+        "single_pair": single,
         "tile_tuning": tuning,
     }
     if not args.no_cpu_baseline:

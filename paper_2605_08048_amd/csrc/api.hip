@@ -137,6 +137,7 @@ struct Workspace {
     double* partial;
     uint32_t* flags;
     double* tw;         // final T_b of the current block (moments)
+    double* rseg;       // recheck segment sums (nullptr when no pair has more than one segment)
     uint32_t* nflag;
     int32_t* sstat;     // per pair: problems of the split stage (merged into the result status)
     // point-to-centroid route
@@ -198,6 +199,8 @@ Workspace carve(const Plan& P, void* ws) {
         w.partial = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.nslot * 2);
         w.flags = c.take<uint32_t>(std::max<int64_t>(P.block_rows, 1));
         w.tw = c.take<double>(std::max<int64_t>(P.block_rows, 1));
+        w.rseg = recheck_segments(P.max_np) > 1
+                     ? c.take<double>((size_t)kRecheckSegSlots * kRecheckSegRows * P.d_pad) : nullptr;
         w.nflag = c.take<uint32_t>(2);
         w.sstat = c.take<int32_t>((size_t)(np + 1) / 2 * 2);
         if (P.route2) {
@@ -225,6 +228,7 @@ Workspace carve(const Plan& P, void* ws) {
         w.partial = nullptr;
         w.flags = nullptr;
         w.tw = nullptr;
+        w.rseg = nullptr;
         w.nflag = nullptr;
         w.sstat = nullptr;
     }
@@ -643,7 +647,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         if (!no_recheck) {
             StageTimer t_(HBT_STAGE_RECHECK, s);
             HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.t64, w.coef, w.mask,
-                                   w.flags, w.nflag, nb, P.d, prm->gd, prm->alternative, w.cnt, w.tw, s));
+                                   w.flags, w.nflag, nb, P.max_np, w.rseg, P.d, prm->gd, prm->alternative,
+                                   w.cnt, w.tw, s));
         }
         { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(1, w.bp, w.st, w.tw, w.cnt, s)); }
         if (mask_out)
@@ -777,7 +782,8 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
-                               w.nflag, P.block_rows, P.d, common->gd, common->alternative, w.cnt, w.tw, s));
+                               w.nflag, P.block_rows, P.max_np, w.rseg, P.d, common->gd, common->alternative,
+                               w.cnt, w.tw, s));
     }
     { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
     { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.st, w.sstat, w.cnt, w.Btot, results, s)); }

@@ -106,12 +106,18 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
                        bool T_f64, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
+// FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
+// doubles of per-wave segment sums (nullptr: every flag done whole by one
+// work-group); the value of each flag's sums does not depend on it.
+constexpr int kRecheckSegSlots = 256;
+constexpr int kRecheckSegRows = 8;  // per-wave rows of a slot
+int recheck_segments(int max_np);
 hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
                           int npairs, const PairState* st, const double* v, const double* t64,
                           const double* coef,
                           const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
-                          int64_t max_flags, int d, int gd, int alternative, PairCount* cnt,
-                          double* Tw, hipStream_t s);
+                          int64_t max_flags, int max_np, double* rseg, int d, int gd,
+                          int alternative, PairCount* cnt, double* Tw, hipStream_t s);
 // Sums of T_b - T_obs and its square per pair over the current block (Tw
 // holds the block's final T_b, recheck applied).
 hipError_t launch_moments(int npairs, const BlockPair* bp, const PairState* st, const double* Tw,

@@ -88,161 +88,286 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
 // FP64 recheck of the flagged splits.  The smaller group's sum is gathered
 // from the input rows, each rebuilt in FP64 as the aligned row
 // x_i - coef_i v (X) or y_j (Y); the other group's sum is t - sigma_small
-// with the FP64 pooled total t.  One work-group per flagged split (persistent
-// over the flag list), 256 threads over the columns.
+// with the FP64 pooled total t.
+//
+// The gather over a split's mask words is cut into segments of kSegWords
+// words (512 pooled rows); wave w of a work-group walks words w, w + 8, ...
+// of a segment.  sigma_small is always formed in one order: per wave, its
+// segment sums added in segment order; then the 8 waves' totals added in
+// wave order.  The first f_seg flags of the list (when segments are enabled)
+// are split into one work item per segment, whose per-wave sums go to
+// workspace slots that k_recheck_finish adds in that order; this puts many
+// work-groups on a call with few flags.  Every other flag is done whole by
+// one work-group whose waves keep their running totals in registers.  The
+// value of a flag's sums therefore does not depend on how the work is
+// spread.  512 threads, columns in passes of 768.
 // ---------------------------------------------------------------------------
-constexpr int kRecheckWaves = 8;
+constexpr int kRecheckWaves = kRecheckSegRows;  // 8
+constexpr int kRecheckThreads = 64 * kRecheckWaves;
+constexpr int kRecheckPass = 768;        // columns per pass (12 per lane)
+constexpr int kSegWords = 16;
+
+struct FlagCtx {
+    int64_t row;
+    int p, N, W, G;
+    PairDesc pd;
+    PairState q;
+    const uint32_t* mk;
+};
+
+__device__ __forceinline__ FlagCtx flag_ctx(const PairDesc* pairs, const BlockPair* bp, int npairs,
+                                            const PairState* st, const uint32_t* mask,
+                                            const uint32_t* flags, uint32_t f) {
+    FlagCtx c;
+    c.row = flags[f];
+    c.p = upper_index(npairs, c.row, [&](int k) { return bp[k].mrow0; });
+    c.pd = pairs[c.p];
+    c.q = st[c.p];
+    c.mk = mask_row(mask, bp[c.p], c.row, c.pd.Wp);
+    c.N = c.pd.n + c.pd.m;
+    c.W = (c.N + 31) >> 5;
+    c.G = (c.W + kSegWords - 1) / kSegWords;
+    return c;
+}
+
+// The flag's statistic from the per-thread sums of squares (thread t holds
+// the columns c0 + t + 512 k of every pass, in that order), its decision and
+// its FP64 T_b.
+__device__ void recheck_finish_flag(const FlagCtx& c, double ss_small, double ss_large, int d,
+                                    int gd, int alternative, PairCount* cnt, double* Tw,
+                                    double* red1, double* red2) {
+    red1[threadIdx.x] = ss_small;
+    red2[threadIdx.x] = ss_large;
+    __syncthreads();
+    for (int o = kRecheckThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            red1[threadIdx.x] += red1[threadIdx.x + o];
+            red2[threadIdx.x] += red2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double dd = (double)d;
+        const double ss1 = c.pd.flip ? red2[0] : red1[0];
+        const double ss2 = c.pd.flip ? red1[0] : red2[0];
+        const double r1 = sqrt(ss1) / (double)c.pd.n, r2 = sqrt(ss2) / (double)c.pd.m;
+        const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);
+        const bool two = alternative == HBT_ALT_TWO_SIDED;
+        const double val = two ? fabs(T) : T;
+        const double thr = (two ? fabs(c.q.t_obs) : c.q.t_obs) - c.q.tau;
+        if (T != T || val >= thr) atomicAdd(&cnt[c.p].count, 1ull);
+        atomicAdd(&cnt[c.p].n_recheck, 1ull);
+        Tw[c.row] = T;
+    }
+    __syncthreads();
+}
 
 template <typename Tin>
-__global__ __launch_bounds__(64 * kRecheckWaves) void k_recheck(
+__global__ __launch_bounds__(kRecheckThreads) void k_recheck(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
     const PairState* __restrict__ st, const double* __restrict__ v,
     const double* __restrict__ t64, const double* __restrict__ coef,
     const uint32_t* __restrict__ mask, const uint32_t* __restrict__ flags,
     const uint32_t* __restrict__ nflag, int d, int d_pad, int gd, int alternative,
-    PairCount* cnt, double* __restrict__ Tw) {
-    constexpr int kU = 12;                 // columns per lane per pass (768 per pass)
-    constexpr int kPass = 64 * kU;
+    double* __restrict__ rseg, int f_seg, int g_max, PairCount* cnt, double* __restrict__ Tw) {
+    constexpr int kU = kRecheckPass / 64;  // columns per lane per pass
     constexpr int kRows = 4;               // rows in flight per wave
-    constexpr int kThreads = 64 * kRecheckWaves;
-    __shared__ double part[kRecheckWaves][kPass];  // per-wave partial group sums
-    __shared__ double red1[kThreads], red2[kThreads];
+    __shared__ double part[kRecheckWaves][kRecheckPass];  // per-wave partial group sums
+    __shared__ double red1[kRecheckThreads], red2[kRecheckThreads];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const uint32_t total = *nflag;
-    for (uint32_t f = blockIdx.x; f < total; f += gridDim.x) {
-        const int64_t row = flags[f];
-        const int p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
-        const PairDesc pd = pairs[p];
-        const PairState q = st[p];
-        const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
-        const double* vp = v + (int64_t)p * d_pad;
-        const double* tp = t64 + (int64_t)p * d_pad;
+    const int64_t nseg = total < (uint32_t)f_seg ? (int64_t)total : (int64_t)f_seg;
+    const int64_t nitems = nseg * g_max + ((int64_t)total - nseg);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const bool whole = it >= nseg * g_max;
+        const uint32_t f = whole ? (uint32_t)(nseg + (it - nseg * g_max)) : (uint32_t)(it / g_max);
+        const int sg = whole ? 0 : (int)(it % g_max);
+        const FlagCtx c = flag_ctx(pairs, bp, npairs, st, mask, flags, f);
+        if (!whole && sg >= c.G) continue;  // work-group-uniform
+        const int s0 = sg, s1 = whole ? c.G : sg + 1;
+        const PairDesc& pd = c.pd;
+        const double* vp = v + (int64_t)c.p * d_pad;
+        const double* tp = t64 + (int64_t)c.p * d_pad;
         const double* cf = coef + pd.coef0;
-        const int N = pd.n + pd.m;
         const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
-        const int W = (N + 31) >> 5;
         const Tin* X = (const Tin*)pd.X;
         const Tin* Y = (const Tin*)pd.Y;
+        const int W = c.W, N = c.N;
         // members of the smaller group in mask word w
-        auto word_bits = [&](int w) -> uint32_t {
-            if (w >= W) return 0u;
-            uint32_t b = mk[w] ^ flip;
-            if (w == W - 1 && (N & 31)) b &= (1u << (N & 31)) - 1u;
-            return b;
+        auto word_bits = [&](int w, int wend) -> uint32_t {
+            if (w >= wend) return 0u;
+            uint32_t bits = c.mk[w] ^ flip;
+            if (w == W - 1 && (N & 31)) bits &= (1u << (N & 31)) - 1u;
+            return bits;
         };
         double ss_small = 0.0, ss_large = 0.0;
-        for (int c0 = 0; c0 < d; c0 += kPass) {
-            double acc[kU], vc[kU];
+        for (int c0 = 0; c0 < d; c0 += kRecheckPass) {
+            double vc[kU], tot[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                acc[u] = 0.0;
-                const int c = c0 + 64 * u + lane;
-                vc[u] = c < d ? vp[c] : 0.0;
+                const int col = c0 + 64 * u + lane;
+                vc[u] = col < d ? vp[col] : 0.0;
+                tot[u] = 0.0;
             }
-            // wave w walks mask words w, w + 8, ...; kRows rows at a time, all
-            // loads issued before the adds
-            int w = wave;
-            uint32_t bits = word_bits(w);
-            for (;;) {
-                int rows[kRows];
+            for (int sgi = s0; sgi < s1; ++sgi) {
+                const int wend = min(W, (sgi + 1) * kSegWords);
+                double acc[kU];
 #pragma unroll
-                for (int t = 0; t < kRows; ++t) {
-                    while (!bits && w < W) {
-                        w += kRecheckWaves;
-                        bits = word_bits(w);
+                for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+                // kRows rows at a time, all loads issued before the adds
+                int w = sgi * kSegWords + wave;
+                uint32_t bits = word_bits(w, wend);
+                for (;;) {
+                    int rows[kRows];
+#pragma unroll
+                    for (int t = 0; t < kRows; ++t) {
+                        while (!bits && w < wend) {
+                            w += kRecheckWaves;
+                            bits = word_bits(w, wend);
+                        }
+                        if (bits) {
+                            rows[t] = 32 * w + __builtin_ctz(bits);
+                            bits &= bits - 1u;
+                        } else {
+                            rows[t] = -1;
+                        }
                     }
-                    if (bits) {
-                        rows[t] = 32 * w + __builtin_ctz(bits);
-                        bits &= bits - 1u;
-                    } else {
-                        rows[t] = -1;
+                    if (rows[0] < 0) break;
+                    // columns are clamped to the row (no branch around a load);
+                    // absent rows and clamped columns are weighted by 0
+                    Tin z[kRows][kU];
+                    double kc[kRows], wt[kRows];
+#pragma unroll
+                    for (int t = 0; t < kRows; ++t) {
+                        const int i = rows[t] < 0 ? 0 : rows[t];
+                        const bool isx = i < pd.n;
+                        kc[t] = (rows[t] >= 0 && isx) ? cf[i] : 0.0;
+                        wt[t] = rows[t] >= 0 ? 1.0 : 0.0;
+                        const Tin* src = isx ? X + (int64_t)i * d : Y + (int64_t)(i - pd.n) * d;
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int col = c0 + 64 * u + lane;
+                            z[t][u] = src[col < d ? col : d - 1];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < kRows; ++t)
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const double cm = (c0 + 64 * u + lane) < d ? wt[t] : 0.0;
+                            acc[u] += cm * ((double)z[t][u] - kc[t] * vc[u]);
+                        }
+                }
+                if (whole) {
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) tot[u] += acc[u];
+                } else {
+                    double* dst = rseg + (((int64_t)f * g_max + sgi) * kRecheckWaves + wave) * d_pad + c0;
+#pragma unroll
+                    for (int u = 0; u < kU; ++u)
+                        if (c0 + 64 * u + lane < d) dst[64 * u + lane] = acc[u];
+                }
+            }
+            if (whole) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = tot[u];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int cc = threadIdx.x + kRecheckThreads * k;
+                    if (cc < kRecheckPass && c0 + cc < d) {
+                        double sm = 0.0;
+#pragma unroll
+                        for (int q = 0; q < kRecheckWaves; ++q) sm += part[q][cc];
+                        const double l = tp[c0 + cc] - sm;
+                        ss_small += sm * sm;
+                        ss_large += l * l;
                     }
                 }
-                if (rows[0] < 0) break;
-                // loads of all kRows rows are issued before any add: columns are
-                // clamped to the row (no branch around a load), absent rows and
-                // clamped columns are weighted by 0
-                Tin z[kRows][kU];
-                double kc[kRows], wt[kRows];
-#pragma unroll
-                for (int t = 0; t < kRows; ++t) {
-                    const int i = rows[t] < 0 ? 0 : rows[t];
-                    const bool isx = i < pd.n;
-                    kc[t] = (rows[t] >= 0 && isx) ? cf[i] : 0.0;
-                    wt[t] = rows[t] >= 0 ? 1.0 : 0.0;
-                    const Tin* src = isx ? X + (int64_t)i * d : Y + (int64_t)(i - pd.n) * d;
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const int c = c0 + 64 * u + lane;
-                        z[t][u] = src[c < d ? c : d - 1];
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kRows; ++t)
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const double cm = (c0 + 64 * u + lane) < d ? wt[t] : 0.0;
-                        acc[u] += cm * ((double)z[t][u] - kc[t] * vc[u]);
-                    }
+                __syncthreads();
             }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = acc[u];
-            __syncthreads();
-            for (int cc = threadIdx.x; cc < kPass; cc += kThreads) {
-                const int c = c0 + cc;
-                if (c < d) {
-                    double sm = 0.0;
-#pragma unroll
-                    for (int k = 0; k < kRecheckWaves; ++k) sm += part[k][cc];
-                    const double l = tp[c] - sm;
-                    ss_small += sm * sm;
-                    ss_large += l * l;
-                }
-            }
-            __syncthreads();
         }
-        red1[threadIdx.x] = ss_small;
-        red2[threadIdx.x] = ss_large;
-        __syncthreads();
-        for (int o = kThreads / 2; o > 0; o >>= 1) {
-            if (threadIdx.x < o) {
-                red1[threadIdx.x] += red1[threadIdx.x + o];
-                red2[threadIdx.x] += red2[threadIdx.x + o];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const double dd = (double)d;
-            const double ss1 = pd.flip ? red2[0] : red1[0];
-            const double ss2 = pd.flip ? red1[0] : red2[0];
-            const double r1 = sqrt(ss1) / (double)pd.n, r2 = sqrt(ss2) / (double)pd.m;
-            const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);
-            const bool two = alternative == HBT_ALT_TWO_SIDED;
-            const double val = two ? fabs(T) : T;
-            const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
-            if (T != T || val >= thr) atomicAdd(&cnt[p].count, 1ull);
-            atomicAdd(&cnt[p].n_recheck, 1ull);
-            Tw[row] = T;
-        }
-        __syncthreads();
+        if (whole) recheck_finish_flag(c, ss_small, ss_large, d, gd, alternative, cnt, Tw, red1, red2);
     }
+}
+
+// The segmented flags: sigma_small from the per-wave segment sums in the
+// order above, then the same statistic and decision as a whole flag.
+__global__ __launch_bounds__(kRecheckThreads) void k_recheck_finish(
+    const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
+    const PairState* __restrict__ st, const double* __restrict__ t64,
+    const uint32_t* __restrict__ mask, const uint32_t* __restrict__ flags,
+    const uint32_t* __restrict__ nflag, int d, int d_pad, int gd, int alternative,
+    const double* __restrict__ rseg, int f_seg, int g_max, PairCount* cnt, double* __restrict__ Tw) {
+    __shared__ double red1[kRecheckThreads], red2[kRecheckThreads];
+    const uint32_t total = *nflag;
+    const uint32_t f = blockIdx.x;
+    if (f >= total || f >= (uint32_t)f_seg) return;
+    const FlagCtx c = flag_ctx(pairs, bp, npairs, st, mask, flags, f);
+    const double* tp = t64 + (int64_t)c.p * d_pad;
+    double ss_small = 0.0, ss_large = 0.0;
+    for (int c0 = 0; c0 < d; c0 += kRecheckPass)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int cc = threadIdx.x + kRecheckThreads * k;
+            if (cc < kRecheckPass && c0 + cc < d) {
+                // the 8 wave totals are independent chains: each segment's 8
+                // loads are issued together
+                double t[kRecheckWaves];
+#pragma unroll
+                for (int q = 0; q < kRecheckWaves; ++q) t[q] = 0.0;
+                const double* src = rseg + (int64_t)f * g_max * kRecheckWaves * d_pad + c0 + cc;
+                for (int sgi = 0; sgi < c.G; ++sgi) {
+                    double x[kRecheckWaves];
+#pragma unroll
+                    for (int q = 0; q < kRecheckWaves; ++q) x[q] = src[((int64_t)sgi * kRecheckWaves + q) * d_pad];
+#pragma unroll
+                    for (int q = 0; q < kRecheckWaves; ++q) t[q] += x[q];
+                }
+                double sm = 0.0;
+#pragma unroll
+                for (int q = 0; q < kRecheckWaves; ++q) sm += t[q];
+                const double l = tp[c0 + cc] - sm;
+                ss_small += sm * sm;
+                ss_large += l * l;
+            }
+        }
+    recheck_finish_flag(c, ss_small, ss_large, d, gd, alternative, cnt, Tw, red1, red2);
+}
+
+int recheck_segments(int max_np) { return ((max_np + 31) / 32 + kSegWords - 1) / kSegWords; }
+
+int recheck_seg_flags(int max_np) {
+    const int g = recheck_segments(max_np);
+    return g > 1 ? kRecheckSegSlots / g : 0;
 }
 
 hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
                           int npairs, const PairState* st, const double* v, const double* t64,
                           const double* coef, const uint32_t* mask, const uint32_t* flags,
-                          const uint32_t* nflag, int64_t max_flags, int d, int gd, int alternative,
-                          PairCount* cnt, double* Tw, hipStream_t s) {
+                          const uint32_t* nflag, int64_t max_flags, int max_np, double* rseg, int d,
+                          int gd, int alternative, PairCount* cnt, double* Tw, hipStream_t s) {
     if (max_flags <= 0) return hipSuccess;
     const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
-    int64_t g = max_flags < 2048 ? max_flags : 2048;
+    const int g_max = recheck_segments(max_np);
+    int f_seg = rseg ? recheck_seg_flags(max_np) : 0;
+    if (f_seg > max_flags) f_seg = (int)max_flags;
+    // enough work-groups for every segment of the segmented flags
+    const int64_t want = max_flags + (int64_t)f_seg * (g_max - 1);
+    const unsigned g = (unsigned)(want < 4096 ? want : 4096);
     if (input_dtype == HBT_IN_F64)
-        hipLaunchKernelGGL(k_recheck<double>, dim3((unsigned)g), dim3(64 * kRecheckWaves), 0, s, pairs, bp, npairs,
-                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt, Tw);
+        hipLaunchKernelGGL(k_recheck<double>, dim3(g), dim3(kRecheckThreads), 0, s, pairs, bp, npairs,
+                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, rseg, f_seg,
+                           g_max, cnt, Tw);
     else
-        hipLaunchKernelGGL(k_recheck<float>, dim3((unsigned)g), dim3(64 * kRecheckWaves), 0, s, pairs, bp, npairs,
-                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, cnt, Tw);
+        hipLaunchKernelGGL(k_recheck<float>, dim3(g), dim3(kRecheckThreads), 0, s, pairs, bp, npairs,
+                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, rseg, f_seg,
+                           g_max, cnt, Tw);
+    if (f_seg > 0)
+        hipLaunchKernelGGL(k_recheck_finish, dim3((unsigned)f_seg), dim3(kRecheckThreads), 0, s, pairs, bp,
+                           npairs, st, t64, mask, flags, nflag, d, d_pad, gd, alternative, rseg, f_seg,
+                           g_max, cnt, Tw);
     return hipGetLastError();
 }
 

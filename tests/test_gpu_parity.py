@@ -447,6 +447,28 @@ def _results_equal(a, b):
         assert np.array_equal(a[f], b[f]), f
 
 
+def test_recheck_value_does_not_depend_on_how_it_is_spread():
+    """A flagged split's FP64 group sum is the sum of 512-row segment sums in
+    segment order, whether one work-group walks every segment (flags past the
+    segmented quota of a call) or each segment is a work item of its own (the
+    first flags of a call).  In the batched call below more flags are raised
+    than the quota, so some are done whole there, while a single-pair call
+    segments all of its few flags: their results must agree bit for bit."""
+    b = synth.batch_512_d768(limit=range(96))
+    print(f"recheck spread: {b.npairs} pairs of the 512-pair workload", flush=True)
+    res = hbt.perm_test_batched(_dev(b.Z), b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
+    assert int(res["n_recheck"].sum()) > 1280 // (((int(max(b.n + b.m)) + 127) // 128 * 128 // 32 + 15) // 16)
+    checked = 0
+    for p in np.nonzero(res["n_recheck"] > 0)[0][:12]:
+        pr = b.pair(int(p))
+        one = hbt.perm_test(_dev(pr.X), _dev(pr.Y), pr.B, seed=b.seed, pair_index=pr.pair_index,
+                            precision="bf16x2")
+        for f in ["t_obs", "count", "p", "n_recheck", "t_mean", "t_sd"]:
+            assert one[f] == res[p][f], (int(p), f, one[f], res[p][f])
+        checked += 1
+    assert checked > 0
+
+
 def test_tile_widths_do_not_change_results():
     """The product runs per pair with 512- or 256-split tiles; each split's
     sums come from the same instructions in the same order, so results are
