@@ -588,7 +588,42 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     const int N = (int)(prm->n + prm->m);
     const int W = (N + 31) / 32;
 
-    st = enqueue_prologue(P, w, prm->align, prm->gd, result, s);
+    const Band band = precision_band(P.precision, P.d);
+    const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
+    const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
+    // the tables of split block b0 (nb splits) and its tile width
+    auto block_width = [&](int64_t nb) {
+        return P.precision == HBT_I8X3 ? kTileI8 : choose_width(nb, tile_cost(P.d_pad));
+    };
+    auto block_tables = [&](int64_t b0, int64_t nb) -> hipError_t {
+        const BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
+        const int wdt = block_width(nb);
+        const GemmGroup grp{0, (int32_t)((nb + wdt - 1) / wdt), 0};
+        hipError_t e;
+        if ((e = upload(w.bp, &bq, sizeof bq, s)) != hipSuccess) return e;
+        if ((e = upload(w.groups, &grp, sizeof grp, s)) != hipSuccess) return e;
+        return zero(w.nflag, 8, s);
+    };
+    auto block_splits = [&](int64_t b0, int64_t nb, hipStream_t q) -> hipError_t {
+        if (prm->masks) return launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, q);
+        return launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat, 6, q);
+    };
+    {
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
+        HIP_TRY(zero(w.sstat, 8, s));
+        HIP_TRY(block_tables(0, std::min<int64_t>(B0, prm->B)));
+    }
+    // The first block's splits depend only on the seed and the sizes: they are
+    // drawn on a second stream beside the alignment and joined before the
+    // group sums (as in the batched call); later blocks follow in order.
+    Fork fork(s);
+    HIP_TRY(fork.begin());
+    {
+        StageTimer t_(HBT_STAGE_SPLIT, fork.side);
+        HIP_TRY(block_splits(0, std::min<int64_t>(B0, prm->B), fork.side));
+    }
+    st = enqueue_prologue(P, w, prm->align, prm->gd, result, s, false);
     if (st) return st;
     {
         StageTimer t_(HBT_STAGE_OTHER, s);
@@ -604,27 +639,18 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             HIP_TRY(launch_row_dot_t(w.pairs, 1, z32, w.t64, P.d_pad, P.zrows, w.zt, s));
         }
     }
-    const Band band = precision_band(P.precision, P.d);
-    const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
-    const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
-    HIP_TRY(zero(w.sstat, 8, s));
+    HIP_TRY(fork.join());
     for (int64_t b0 = 0; b0 < prm->B; b0 += B0) {
         const int64_t nb = std::min<int64_t>(B0, prm->B - b0);
-        BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
-        const int wdt = P.precision == HBT_I8X3 ? kTileI8 : choose_width(nb, tile_cost(P.d_pad));
+        const int wdt = block_width(nb);
         const GemmGroup grp{0, (int32_t)((nb + wdt - 1) / wdt), 0};
-        {
-            StageTimer t_(HBT_STAGE_OTHER, s);
-            HIP_TRY(upload(w.bp, &bq, sizeof bq, s));
-            HIP_TRY(upload(w.groups, &grp, sizeof grp, s));
-            HIP_TRY(zero(w.nflag, 8, s));
-        }
-        {
+        if (b0 > 0) {
+            {
+                StageTimer t_(HBT_STAGE_OTHER, s);
+                HIP_TRY(block_tables(b0, nb));
+            }
             StageTimer t_(HBT_STAGE_SPLIT, s);
-            if (prm->masks)
-                HIP_TRY(launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, s));
-            else
-                HIP_TRY(launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat, 0, s));
+            HIP_TRY(block_splits(b0, nb, s));
         }
         const int ntiles = (int)((nb + groupsum_tile_splits(P.precision) - 1) / groupsum_tile_splits(P.precision));
         {
