@@ -606,7 +606,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     };
     auto block_splits = [&](int64_t b0, int64_t nb, hipStream_t q) -> hipError_t {
         if (prm->masks) return launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, q);
-        return launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat, 6, q);
+        return launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat,
+                                  kSplitWgPerCuBesideAlign, q);
     };
     {
         StageTimer t_(HBT_STAGE_OTHER, s);
@@ -767,7 +768,8 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     // The splits depend only on the seeds and the group sizes, not on the
     // alignment: they are drawn on a second stream beside it (integer VALU
     // work beside HBM-bound work) and joined before the group sums.  At most
-    // 6 split work-groups per CU leave wave slots to the alignment kernels
+    // 6 split work-groups per CU (kSplitWgPerCuBesideAlign) leave wave slots
+    // to the alignment kernels
     // (measured on 512 pairs, d = 768, split BF16: 8.03 ms per call at 8 or
     // uncapped, where the alignment then waits for wave slots; 7.25 ms at 6,
     // the two stages 2.1 ms each; 7.56 ms at 5, 7.63 ms at 4).
@@ -776,7 +778,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     {
         StageTimer t_(HBT_STAGE_SPLIT, fork.side);
         HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
-                                   6, fork.side));
+                                   kSplitWgPerCuBesideAlign, fork.side));
     }
     st = enqueue_prologue(P, w, common->align, common->gd, results, s, false);
     if (st) return st;
