@@ -171,7 +171,12 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
  *   row_offset, n, m, B: HOST arrays of npairs int64 (row_offset may have
  *     npairs + 1 entries; only the first npairs are read).
  *   pair_index: HOST array of npairs Philox counter words, or NULL for
- *     common->pair_index + p.
+ *     common->pair_index + p.  Pairs with equal n, m, B and pair index get
+ *     identical splits (the reuse of one block of random splits across pairs
+ *     of equal sizes, Sec. 3.2 practical notes): the call draws them once and
+ *     those pairs share the masks.  Distinct indices give independent splits.
+ *     hbt_perm_test_batched_workspace_size takes no indices and returns the
+ *     size for distinct ones, which also covers shared ones.
  *   common: precision, input_dtype, gd, alternative, align, seed,
  *     perm_offset, flags (n, m, d, B, masks and block_perms are ignored).
  *   results: DEVICE array of npairs hbt_result.

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hbt_launch.h"
@@ -359,7 +360,7 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     int64_t B0 = prm->block_perms > 0 ? prm->block_perms : kAutoBlock;
     B0 = std::min<int64_t>(B0, prm->B);
     *B0_out = B0;
-    P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0});
+    P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0, 0});
     const int tb = groupsum_tile_splits(prm->precision);
     for (int64_t b = 0; b < B0; b += tb) P.tiles.push_back(GemmTile{0, (int32_t)b});
     P.groups.push_back(GemmGroup{0, (int32_t)((B0 + 255) / 256), 0});  // room for the narrower width
@@ -681,7 +682,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         if (mask_out)
             HIP_TRY(launch_export_masks(w.mask, nb, pd.Wp, W, mask_out + b0 * W, s));
     }
-    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(1, w.st, w.sstat, w.cnt, w.Btot, result, s)); }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(1, w.bp, w.st, w.sstat, w.cnt, w.Btot, result, s)); }
     return HBT_OK;
 }
 
@@ -691,14 +692,27 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
                          const uint32_t* pair_index, int64_t d, const hbt_perm_params* common) {
     const size_t es = common->input_dtype == HBT_IN_F64 ? 8 : 4;
     int64_t rows = 0, words = 0;
+    // Pairs with equal n, m, B and pair index get identical splits (the
+    // counters and the key are the same): the first of them draws the masks
+    // and the others read its mask words.
+    std::map<std::tuple<int64_t, int64_t, int64_t, uint32_t>, int> first;
     for (int64_t p = 0; p < npairs; ++p) {
         const char* X = Z_all ? (const char*)Z_all + (size_t)row_offset[p] * d * es : nullptr;
         const char* Y = X ? X + (size_t)n[p] * d * es : nullptr;
-        add_pair(P, X, Y, n[p], m[p], pair_index ? pair_index[p] : common->pair_index + (uint32_t)p);
-        P.bp.push_back(BlockPair{rows, words, (uint32_t)common->perm_offset, (int32_t)B[p], 0});
+        const uint32_t idx = pair_index ? pair_index[p] : common->pair_index + (uint32_t)p;
+        add_pair(P, X, Y, n[p], m[p], idx);
+        const auto key = std::make_tuple(n[p], m[p], B[p], idx);
+        const auto hit = first.find(key);
+        if (hit == first.end()) {
+            first.emplace(key, (int)p);
+            P.bp.push_back(BlockPair{rows, words, (uint32_t)common->perm_offset, (int32_t)B[p], (int32_t)p, 0});
+            words += B[p] * P.pairs.back().Wp;
+        } else {
+            const BlockPair& o = P.bp[(size_t)hit->second];
+            P.bp.push_back(BlockPair{rows, o.mword0, (uint32_t)common->perm_offset, (int32_t)B[p], hit->second, 0});
+        }
         P.Btot.push_back(B[p]);
         rows += B[p];
-        words += B[p] * P.pairs.back().Wp;
     }
     finish_plan(P, d, common->precision, common->input_dtype);
     // tiles, largest pooled size first (longest-processing-time order)
@@ -814,7 +828,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                w.cnt, w.tw, s));
     }
     { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
-    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.st, w.sstat, w.cnt, w.Btot, results, s)); }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.bp, w.st, w.sstat, w.cnt, w.Btot, results, s)); }
     return HBT_OK;
 }
 

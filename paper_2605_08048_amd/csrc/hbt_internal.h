@@ -51,7 +51,10 @@ struct BlockPair {
     int64_t mword0;      // first mask word of that row (rows hold Wp words)
     uint32_t perm_base;  // global index of that split
     int32_t nb;          // splits of the pair in this block
-    int64_t _pad;
+    int32_t owner;       // the pair whose split rows draw these masks: itself, or
+                         // the first pair with the same n, m, B and pair index
+                         // (identical splits), whose mask words mword0 points at
+    int32_t _pad;
 };
 static_assert(sizeof(BlockPair) == 32, "BlockPair layout");
 

@@ -140,7 +140,9 @@ hipError_t launch_budgets(int64_t npairs, const float* out, const hbt_result* re
                           double hi, int64_t bmin, int64_t bmax, double zq, int64_t* budget,
                           hipStream_t s);
 
-hipError_t launch_final(int npairs, const PairState* st, const int32_t* sstat, const PairCount* cnt,
-                        const int64_t* Btot, hbt_result* res, hipStream_t s);
+// Per pair: count, B, p, null moments and status (the alignment's, else that
+// of the split rows that drew its masks).
+hipError_t launch_final(int npairs, const BlockPair* bp, const PairState* st, const int32_t* sstat,
+                        const PairCount* cnt, const int64_t* Btot, hbt_result* res, hipStream_t s);
 
 }  // namespace hbt

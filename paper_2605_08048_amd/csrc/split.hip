@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
     uint32_t* mlds = (uint32_t*)(base + L.mlds);
 
     const int p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
+    if (bp[p].owner != p) return;  // another pair's rows draw these masks (wave-uniform)
     const PairDesc pd = pairs[p];
     const uint32_t b = bp[p].perm_base + (uint32_t)(row - bp[p].mrow0);
     const int N = pd.n + pd.m, n = pd.n;

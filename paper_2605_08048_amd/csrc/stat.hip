@@ -413,7 +413,8 @@ hipError_t launch_moments(int npairs, const BlockPair* bp, const PairState* st, 
 // ---------------------------------------------------------------------------
 // p = (1 + count) / (B + 1)  (eq:pvalue)
 // ---------------------------------------------------------------------------
-__global__ void k_final(int npairs, const PairState* __restrict__ st, const int32_t* __restrict__ sstat,
+__global__ void k_final(int npairs, const BlockPair* __restrict__ bp, const PairState* __restrict__ st,
+                        const int32_t* __restrict__ sstat,
                         const PairCount* __restrict__ cnt, const int64_t* __restrict__ Btot,
                         hbt_result* res) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -428,14 +429,14 @@ __global__ void k_final(int npairs, const PairState* __restrict__ st, const int3
     const double var = cnt[p].sum_dt2 / (double)r.B - mean * mean;
     r.t_mean = q.t_obs + mean;
     r.t_sd = var != var ? var : sqrt(var > 0.0 ? var : 0.0);
-    r.status = q.status != HBT_OK ? q.status : sstat[p];  // the alignment's status first
+    r.status = q.status != HBT_OK ? q.status : sstat[bp[p].owner];  // the alignment's status first
     res[p] = r;
 }
 
-hipError_t launch_final(int npairs, const PairState* st, const int32_t* sstat, const PairCount* cnt,
-                        const int64_t* Btot, hbt_result* res, hipStream_t s) {
-    hipLaunchKernelGGL(k_final, dim3((npairs + 255) / 256), dim3(256), 0, s, npairs, st, sstat, cnt,
-                       Btot, res);
+hipError_t launch_final(int npairs, const BlockPair* bp, const PairState* st, const int32_t* sstat,
+                        const PairCount* cnt, const int64_t* Btot, hbt_result* res, hipStream_t s) {
+    hipLaunchKernelGGL(k_final, dim3((npairs + 255) / 256), dim3(256), 0, s, npairs, bp, st, sstat,
+                       cnt, Btot, res);
     return hipGetLastError();
 }
 

@@ -265,7 +265,9 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
                       precision="bf16x2", gd="banerjee", alternative="greater", align=True, recheck=True,
                       stream=None, sync=True, results=None, workspace=None):
     """Many pairs in one call.  Z_all (device tensor) holds rows X_0, Y_0, X_1, ...;
-    row_offset/n/m/B are host integer arrays.  Returns a numpy structured array
+    row_offset/n/m/B are host integer arrays.  ``pair_index`` (host, one Philox
+    counter word per pair; default 0, 1, 2, ...): pairs with equal n, m, B and
+    index get identical splits, drawn once.  Returns a numpy structured array
     of hbt_result (or, with sync=False, the device result tensor).  A caller
     that captures the call into a graph passes its own ``workspace`` (a uint8
     device tensor that outlives the graph) instead of the shared cached one."""

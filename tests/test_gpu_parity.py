@@ -447,6 +447,32 @@ def _results_equal(a, b):
         assert np.array_equal(a[f], b[f]), f
 
 
+def test_pairs_with_equal_sizes_and_index_share_their_splits():
+    """Pairs with equal n, m, B and pair index have the same splits by
+    definition (same counters, same key): the batched call draws them once and
+    the other pairs read the first one's masks.  Pairs 0, 2, 4 share them
+    (different data), pair 5 has the same index but swapped sizes and draws its
+    own; every pair must match the oracle run with its pair index."""
+    d = 96
+    sizes = [(120, 90), (120, 90), (120, 90), (60, 200), (120, 90), (90, 120)]
+    index = [7, 1, 7, 3, 7, 7]
+    pairs = []
+    for p, ((n, m), k) in enumerate(zip(sizes, index)):
+        X, Y = _pair(n, m, d, kx=2.0, ky=2.3, angle=30.0, seed=500 + p)
+        pairs.append(synth.Pair(X, Y, B=400, pair_index=k))
+    bt = synth.pack_batch(pairs, d)
+    for prec in ["bf16x2", "f32", "i8x3"]:
+        res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=11,
+                                    pair_index=bt.pair_index, precision=prec)
+        for p, pr in enumerate(pairs):
+            o = O.perm_test(pr.X, pr.Y, pr.B, seed=11, pair=pr.pair_index, want_T=True)
+            assert res[p]["status"] == 0, (prec, p)
+            assert abs(res[p]["t_obs"] - o["t_obs"]) <= 1e-12 * max(1, abs(o["t_obs"]))
+            assert abs(res[p]["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"]), (prec, p)
+            at = O.perm_stats_at(pr.X, pr.Y, np.arange(pr.B), seed=11, pair=pr.pair_index)
+            _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
+
+
 def test_recheck_value_does_not_depend_on_how_it_is_spread():
     """A flagged split's FP64 group sum is the sum of 512-row segment sums in
     segment order, whether one work-group walks every segment (flags past the
