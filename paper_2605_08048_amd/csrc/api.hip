@@ -661,14 +661,15 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == 512,
                                     wdt == 512 ? nt : 0, wdt == 256, wdt == 256 ? nt : 0, P.d_pad,
                                     w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
-                                    w.sig, s));
+                                    P.block_rows, w.sig, s));
             if (P.route2)
                 HIP_TRY(launch_centroid(w.pairs, w.bp, w.ctiles, (int)((nb + kTileB - 1) / kTileB),
                                         P.ntile_i, P.d_pad, z32, w.sig, w.mask, w.zt, w.partial2,
-                                        s));
+                                        P.block_rows, s));
         }
         { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
-                            P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot, P.d, prm->gd,
+                            P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot,
+                            P.block_rows, P.d, prm->gd,
                             prm->alternative, band.e_acc, band.e_store, no_recheck,
                             T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8, w.tw,
                             w.cnt, w.flags, w.nflag, s)); }
@@ -814,10 +815,12 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         StageTimer t_(HBT_STAGE_GROUPSUM, s);
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
                                 P.ng512, (int)P.nt512, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
-                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, nullptr, s));
+                                P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
+                                nullptr, s));
     }
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
-    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot, P.d, common->gd,
+    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot,
+                        P.block_rows, P.d, common->gd,
                         common->alternative, precision_band(P.precision, P.d).e_acc,
                         precision_band(P.precision, P.d).e_store, no_recheck, nullptr,
                         false, w.tw, w.cnt, w.flags, w.nflag, s)); }

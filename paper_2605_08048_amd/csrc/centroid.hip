@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ p
                                                   const float* __restrict__ sig,
                                                   const uint32_t* __restrict__ mask,
                                                   const double* __restrict__ zt,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial, int64_t prow) {
     const GemmTile tile = tiles[blockIdx.x / ntile_i];
     const int itile = blockIdx.x % ntile_i;
     const PairDesc pd = pairs[tile.pair];
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ p
         s1 += __shfl_xor(s1, 32, 64);
         s2 += __shfl_xor(s2, 32, 64);
         if (q == 0 && valid[j]) {
-            double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * (int64_t)ntile_i + itile;
+            double2* out = (double2*)partial + itile * prow + bq.mrow0 + brow[j];
             *out = make_double2(s1, s2);
         }
     }
@@ -131,10 +131,10 @@ __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ p
 hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const GemmTile* tiles,
                            int ntiles, int ntile_i, int d_pad, const float* z32, const float* sig,
                            const uint32_t* mask, const double* zt, double* partial,
-                           hipStream_t s) {
+                           int64_t prow, hipStream_t s) {
     if (ntiles <= 0 || ntile_i <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_centroid, dim3((unsigned)(ntiles * ntile_i)), dim3(256), 0, s, pairs, bp,
-                       tiles, ntile_i, d_pad, z32, sig, mask, zt, partial);
+                       tiles, ntile_i, d_pad, z32, sig, mask, zt, partial, prow);
     return hipGetLastError();
 }
 

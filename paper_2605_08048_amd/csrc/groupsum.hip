@@ -10,8 +10,9 @@
 // so that each lane of an MFMA result holds one split (column) and several
 // columns of d (rows): the per-split norm reduction is then mostly in-lane.
 //
-// Output per split row and per slot of kDSlot columns:
-//   partial[row][slot] = (sum_c sigma_small[c]^2, sum_c (t[c] - sigma_small[c])^2)
+// Output per split row and per slot of kDSlot columns, slot-major (prow rows
+// per slot, so a tile's stores and the statistic's loads are contiguous):
+//   partial[slot][row] = (sum_c sigma_small[c]^2, sum_c (t[c] - sigma_small[c])^2)
 //
 // Work-group = 4 waves; tile = kDSlot columns x (512 splits for split BF16,
 // 256 for FP32 / FP64).
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
-    double* __restrict__ partial, float* __restrict__ sig) {
+    double* __restrict__ partial, int64_t prow, float* __restrict__ sig) {
     constexpr int kWS = 32 * JB;
     constexpr int kTile = 4 * kWS;
     constexpr int kMaskVec = kTile;
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             ss += __shfl_xor(ss, 32, 64);
             sl += __shfl_xor(sl, 32, 64);
             if (h == 0 && keep[j]) {
-                double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + t.slot;
+                double2* out = (double2*)partial + t.slot * prow + bq.mrow0 + brow[j];
                 *out = make_double2((double)ss, (double)sl);
             }
             if (sig && keep[j]) {
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zq, int64_t plane_vec, const uint32_t* __restrict__ mask,
-    const double* __restrict__ t64, double* __restrict__ partial) {
+    const double* __restrict__ t64, double* __restrict__ partial, int64_t prow) {
     constexpr int JB = 2, kWS = 32 * JB;        // splits per wave
     constexpr int kRowsPerWave = 3 * kHex / 4;  // LDS rows of Z each wave loads (6)
     constexpr int kMaskLoads = kWS / 64;        // mask loads per wave per chunk
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             ss += __shfl_xor(ss, 32, 64);
             sl += __shfl_xor(sl, 32, 64);
             if (h == 0 && brow < bq.nb) {
-                double2* out = (double2*)partial + (bq.mrow0 + brow) * nslot + t.slot;
+                double2* out = (double2*)partial + t.slot * prow + bq.mrow0 + brow;
                 *out = make_double2(ss, sl);
             }
         }
@@ -558,7 +559,7 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
                                                      int nslot, int d_pad, const T* __restrict__ z,
                                                      const uint32_t* __restrict__ mask,
                                                      const T* __restrict__ tvec,
-                                                     double* __restrict__ partial,
+                                                     double* __restrict__ partial, int64_t prow,
                                                      float* __restrict__ sig) {
     typedef typename MfmaFp<T>::acc_t acc_t;
     const GemmTile tile = tiles[blockIdx.x / nslot];
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
         ss += __shfl_xor(ss, 32, 64);
         sl += __shfl_xor(sl, 32, 64);
         if (q == 0 && valid[j]) {
-            double2* out = (double2*)partial + (bq.mrow0 + brow[j]) * nslot + slot;
+            double2* out = (double2*)partial + slot * prow + bq.mrow0 + brow[j];
             *out = make_double2((double)ss, (double)sl);
         }
         if (sig && valid[j]) {  // the group sums themselves, for the point-to-centroid route
@@ -664,7 +665,7 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ng512,
                            int nt512, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
-                           const double* t64, double* partial, float* sig, hipStream_t s) {
+                           const double* t64, double* partial, int64_t prow, float* sig, hipStream_t s) {
     const int nslot = d_pad / kDSlot;
     dim3 block(256);
     switch (precision) {
@@ -674,30 +675,30 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             if (nt512 > 0)
                 hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512, 32)), block, 0,
                                    s, pairs, bp, groups, ng512, nt512, nslot, d_pad, zhi, zlo, mask,
-                                   t32, partial, sig);
+                                   t32, partial, prow, sig);
             if (nt256 > 0)
                 hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256, 32)), block, 0,
                                    s, pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                   mask, t32, partial, sig);
+                                   mask, t32, partial, prow, sig);
             break;
         }
         case HBT_I8X3:
             if (nt256 > 0)
                 hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, 32)), block, 0, s,
                                    pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, (const uint4*)zstore,
-                                   zplane_elems / 16, mask, t64, partial);
+                                   zplane_elems / 16, mask, t64, partial, prow);
             break;
         case HBT_F32:
             if (ntiles <= 0) return hipSuccess;
             hipLaunchKernelGGL(k_groupsum_fp<float>, dim3((unsigned)(ntiles * nslot)), block, 0, s,
                                pairs, bp, tiles, nslot, d_pad, (const float*)zstore, mask, t32,
-                               partial, sig);
+                               partial, prow, sig);
             break;
         default:
             if (ntiles <= 0) return hipSuccess;
             hipLaunchKernelGGL(k_groupsum_fp<double>, dim3((unsigned)(ntiles * nslot)), block, 0, s,
                                pairs, bp, tiles, nslot, d_pad, (const double*)zstore, mask, t64,
-                               partial, sig);
+                               partial, prow, sig);
             break;
     }
     return hipGetLastError();

@@ -80,30 +80,33 @@ hipError_t launch_export_masks(const uint32_t* mask, int64_t rows, int Wp, int W
 // --- group sums (eq:gemm) -----------------------------------------------
 // Splits per group-sum tile (the tile list steps b0 by this).
 int groupsum_tile_splits(int precision);
-// partial[row][slot] = (|sigma_small|^2, |t - sigma_small|^2) over the slot's
-// kDSlot columns, sigma_small = mask_small . Z.
+// partial[slot][row] = (|sigma_small|^2, |t - sigma_small|^2) over the slot's
+// kDSlot columns, sigma_small = mask_small . Z; slot-major with prow rows per
+// slot (the block's split rows).
 // FP32 / FP64 use the tile list; split BF16 uses the per-pair groups
 // (ntile_total tiles in all).
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
                            const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ng512,
                            int nt512, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
-                           const double* t64, double* partial, float* sig, hipStream_t s);
+                           const double* t64, double* partial, int64_t prow, float* sig,
+                           hipStream_t s);
 
 // --- point-to-centroid route (statistic route 2) -------------------------
 // z_i . t per pooled row; then Q = Z S^T with the masked column sums
-// partial[row][row tile] = (|sigma_small|^2 part, |t - sigma_small|^2 part).
+// partial[row tile][row] = (|sigma_small|^2 part, |t - sigma_small|^2 part),
+// prow rows per tile.
 hipError_t launch_row_dot_t(const PairDesc* pairs, int npairs, const float* z32,
                             const double* t64, int d_pad, int64_t total_rows, double* zt,
                             hipStream_t s);
 hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const GemmTile* tiles,
                            int ntiles, int ntile_i, int d_pad, const float* z32, const float* sig,
                            const uint32_t* mask, const double* zt, double* partial,
-                           hipStream_t s);
+                           int64_t prow, hipStream_t s);
 
 // --- statistic, exceedances, recheck, p ---------------------------------
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
-                       const PairState* st, const double* partial, int nslot, int d, int gd,
+                       const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
                        bool T_f64, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);

@@ -13,7 +13,8 @@ namespace hbt {
 __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs,
                                               const BlockPair* __restrict__ bp, int npairs,
                                               int64_t rows, const PairState* __restrict__ st,
-                                              const double* __restrict__ partial, int nslot, int d,
+                                              const double* __restrict__ partial, int nslot,
+                                              int64_t prow, int d,
                                               int gd, int alternative, double e_acc,
                                               double e_store, int no_recheck, void* T_out,
                                               bool T_f64, double* __restrict__ Tw,
@@ -26,10 +27,12 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
         const PairDesc pd = pairs[p];
         const PairState q = st[p];
-        const double2* pr = (const double2*)partial + row * nslot;
+        // partials are slot-major (slot k of all rows, then slot k + 1), so
+        // the lanes of a wave read consecutive rows
+        const double2* pr = (const double2*)partial + row;
         double ss_small = 0.0, ss_large = 0.0;
         for (int k = 0; k < nslot; ++k) {
-            const double2 v = pr[k];
+            const double2 v = pr[k * prow];
             ss_small += v.x;
             ss_large += v.y;
         }
@@ -72,13 +75,13 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
 }
 
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
-                       const PairState* st, const double* partial, int nslot, int d, int gd,
+                       const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
                        bool T_f64, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
                        hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
-                       npairs, rows, st, partial, nslot, d, gd, alternative, e_acc, e_store,
+                       npairs, rows, st, partial, nslot, prow, d, gd, alternative, e_acc, e_store,
                        no_recheck,
                        T_out, T_f64, Tw, cnt, flags, nflag);
     return hipGetLastError();
