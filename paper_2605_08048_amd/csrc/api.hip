@@ -352,6 +352,23 @@ void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B) {
     P.ntile_total = P.nt512 + P.nt256;
 }
 
+// The block-table entry of a pair's splits [perm_base, perm_base + nb).
+BlockPair block_pair(int64_t mrow0, int64_t mword0, uint64_t perm_base, int64_t nb, int owner,
+                     const PairDesc& pd) {
+    BlockPair b;
+    memset(&b, 0, sizeof b);
+    b.mrow0 = mrow0;
+    b.mword0 = mword0;
+    b.perm_base = (uint32_t)perm_base;
+    b.nb = (int32_t)nb;
+    b.owner = owner;
+    b.n = pd.n;
+    b.m = pd.m;
+    b.Wp = pd.Wp;
+    b.pair_index = pd.pair_index;
+    return b;
+}
+
 // Single-pair plan with blocks of B0 splits.
 Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64_t* B0_out) {
     Plan P;
@@ -360,7 +377,7 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     int64_t B0 = prm->block_perms > 0 ? prm->block_perms : kAutoBlock;
     B0 = std::min<int64_t>(B0, prm->B);
     *B0_out = B0;
-    P.bp.push_back(BlockPair{0, 0, (uint32_t)prm->perm_offset, (int32_t)B0, 0, 0});
+    P.bp.push_back(block_pair(0, 0, prm->perm_offset, B0, 0, P.pairs[0]));
     const int tb = groupsum_tile_splits(prm->precision);
     for (int64_t b = 0; b < B0; b += tb) P.tiles.push_back(GemmTile{0, (int32_t)b});
     P.groups.push_back(GemmGroup{0, (int32_t)((B0 + 255) / 256), 0});  // room for the narrower width
@@ -597,7 +614,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         return P.precision == HBT_I8X3 ? kTileI8 : choose_width(nb, tile_cost(P.d_pad));
     };
     auto block_tables = [&](int64_t b0, int64_t nb) -> hipError_t {
-        const BlockPair bq{0, 0, (uint32_t)(prm->perm_offset + (uint64_t)b0), (int32_t)nb, 0};
+        const BlockPair bq = block_pair(0, 0, prm->perm_offset + (uint64_t)b0, nb, 0, pd);
         const int wdt = block_width(nb);
         const GemmGroup grp{0, (int32_t)((nb + wdt - 1) / wdt), 0};
         hipError_t e;
@@ -607,7 +624,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     };
     auto block_splits = [&](int64_t b0, int64_t nb, hipStream_t q) -> hipError_t {
         if (prm->masks) return launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, q);
-        return launch_split_masks(w.pairs, w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat,
+        return launch_split_masks(w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat,
                                   kSplitWgPerCuBesideAlign, q);
     };
     {
@@ -706,11 +723,11 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
         const auto hit = first.find(key);
         if (hit == first.end()) {
             first.emplace(key, (int)p);
-            P.bp.push_back(BlockPair{rows, words, (uint32_t)common->perm_offset, (int32_t)B[p], (int32_t)p, 0});
+            P.bp.push_back(block_pair(rows, words, common->perm_offset, B[p], (int)p, P.pairs.back()));
             words += B[p] * P.pairs.back().Wp;
         } else {
             const BlockPair& o = P.bp[(size_t)hit->second];
-            P.bp.push_back(BlockPair{rows, o.mword0, (uint32_t)common->perm_offset, (int32_t)B[p], hit->second, 0});
+            P.bp.push_back(block_pair(rows, o.mword0, common->perm_offset, B[p], hit->second, P.pairs.back()));
         }
         P.Btot.push_back(B[p]);
         rows += B[p];
@@ -774,11 +791,9 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     hipStream_t s = (hipStream_t)stream;
     Workspace w = carve(P, ws);
     const int np = P.npairs;
-    {
+    {  // the split stage reads only this table: it goes first
         StageTimer t_(HBT_STAGE_OTHER, s);
-        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
         HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
-        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, s));
     }
     // The splits depend only on the seeds and the group sizes, not on the
     // alignment: they are drawn on a second stream beside it (integer VALU
@@ -792,8 +807,13 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     HIP_TRY(fork.begin());
     {
         StageTimer t_(HBT_STAGE_SPLIT, fork.side);
-        HIP_TRY(launch_split_masks(w.pairs, w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
+        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, fork.side));
+        HIP_TRY(launch_split_masks(w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
                                    kSplitWgPerCuBesideAlign, fork.side));
+    }
+    {  // the pair table, uploaded while the splits are drawn
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
     }
     st = enqueue_prologue(P, w, common->align, common->gd, results, s, false);
     if (st) return st;

@@ -54,9 +54,14 @@ struct BlockPair {
     int32_t owner;       // the pair whose split rows draw these masks: itself, or
                          // the first pair with the same n, m, B and pair index
                          // (identical splits), whose mask words mword0 points at
+    // copies of the pair's PairDesc fields that the split stage reads, so that
+    // it needs this table only
+    int32_t n, m;
+    int32_t Wp;          // mask words per split row (Np / 32)
+    uint32_t pair_index; // Philox counter word 2
     int32_t _pad;
 };
-static_assert(sizeof(BlockPair) == 32, "BlockPair layout");
+static_assert(sizeof(BlockPair) == 48, "BlockPair layout");
 
 #ifdef __HIPCC__
 // Mask words of split row `row` (a block row of pair bq).

@@ -66,7 +66,7 @@ size_t split_lds_limit();
 // CU: beside the alignment kernels, an uncapped split kernel takes every wave
 // slot and the two stages run one after the other.
 constexpr int kSplitWgPerCuBesideAlign = 6;
-hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
+hipError_t launch_split_masks(const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
                               int32_t* sstat, int wg_per_cu, hipStream_t s);
 // Explicit masks: copy rows of ceil(N/32) words into the workspace layout and

@@ -68,8 +68,7 @@ __device__ __forceinline__ uint4 primary_block(int c, int N, uint32_t b, uint32_
 // blocks in registers between the histogram and the classification pass
 // (pairs with N <= 1024 R); R == 0: the blocks are generated again.
 template <int R>
-__global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict__ pairs,
-                                                     const BlockPair* __restrict__ bp, int npairs,
+__global__ __launch_bounds__(256) void k_split_masks(const BlockPair* __restrict__ bp, int npairs,
                                                      int64_t rows, int max_np, uint32_t key0,
                                                      uint32_t key1, uint32_t* __restrict__ mask,
                                                      int32_t* sstat) {
@@ -86,12 +85,12 @@ __global__ __launch_bounds__(256) void k_split_masks(const PairDesc* __restrict_
     uint32_t* mlds = (uint32_t*)(base + L.mlds);
 
     const int p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
-    if (bp[p].owner != p) return;  // another pair's rows draw these masks (wave-uniform)
-    const PairDesc pd = pairs[p];
+    const BlockPair pd = bp[p];   // the pair's sizes, mask row width and index
+    if (pd.owner != p) return;    // another pair's rows draw these masks (wave-uniform)
     const uint32_t b = bp[p].perm_base + (uint32_t)(row - bp[p].mrow0);
     const int N = pd.n + pd.m, n = pd.n;
     const int nc = (N + 15) >> 4;       // Philox blocks holding items
-    const int nw = pd.Np >> 4;          // blocks covering the padded mask row
+    const int nw = pd.Wp * 2;           // blocks covering the padded mask row (Np / 16)
     const int niter = (nw + 63) >> 6;   // wave-uniform
 
     ((uint4*)hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
@@ -277,7 +276,7 @@ size_t split_lds_limit() {
 
 size_t split_lds_per_block(int max_np) { return (size_t)kSplitWaves * SplitLds(max_np).total + kSplitStaticLds; }
 
-hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int npairs,
+hipError_t launch_split_masks(const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
                               int32_t* sstat, int wg_per_cu, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
@@ -293,7 +292,7 @@ hipError_t launch_split_masks(const PairDesc* pairs, const BlockPair* bp, int np
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     // registers for the keys of the largest pair: R blocks of 16 per lane
     const int r = (max_np + 1023) / 1024;
-#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, pairs, bp, npairs, rows, max_np, k0, k1, mask, sstat)
+#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, bp, npairs, rows, max_np, k0, k1, mask, sstat)
     if (r <= 1) HBT_SPLIT(1);
     else if (r <= 2) HBT_SPLIT(2);
     else if (r <= 4) HBT_SPLIT(4);
