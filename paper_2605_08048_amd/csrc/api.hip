@@ -628,10 +628,26 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
                                   kSplitWgPerCuBesideAlign, q);
     };
     {
+        // The plan tables and block 0's tables sit next to each other at the
+        // start of the workspace (pairs, bp, tiles, groups, Btot): one image,
+        // one upload.  The recheck counter and the split status are adjacent
+        // too: one fill.
         StageTimer t_(HBT_STAGE_OTHER, s);
-        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
-        HIP_TRY(zero(w.sstat, 8, s));
-        HIP_TRY(block_tables(0, std::min<int64_t>(B0, prm->B)));
+        const int64_t nb0 = std::min<int64_t>(B0, prm->B);
+        const BlockPair bq = block_pair(0, 0, prm->perm_offset, nb0, 0, pd);
+        const int wdt = block_width(nb0);
+        const GemmGroup grp{0, (int32_t)((nb0 + wdt - 1) / wdt), 0};
+        std::vector<unsigned char> img((size_t)((const char*)(w.Btot + 1) - (const char*)w.pairs), 0);
+        auto put = [&](const void* dst, const void* src, size_t bytes) {
+            memcpy(img.data() + ((const char*)dst - (const char*)w.pairs), src, bytes);
+        };
+        put(w.pairs, P.pairs.data(), sizeof(PairDesc));
+        put(w.bp, &bq, sizeof bq);
+        put(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile));
+        put(w.groups, &grp, sizeof grp);
+        put(w.Btot, P.Btot.data(), sizeof(int64_t));
+        HIP_TRY(upload(w.pairs, img.data(), img.size(), s));
+        HIP_TRY(zero(w.nflag, (size_t)((const char*)(w.sstat + 2) - (const char*)w.nflag), s));
     }
     // The first block's splits depend only on the seed and the sizes: they are
     // drawn on a second stream beside the alignment and joined before the
@@ -644,11 +660,6 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     }
     st = enqueue_prologue(P, w, prm->align, prm->gd, result, s, false);
     if (st) return st;
-    {
-        StageTimer t_(HBT_STAGE_OTHER, s);
-        HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
-        HIP_TRY(upload(w.Btot, P.Btot.data(), sizeof(int64_t), s));
-    }
     const float* z32 = P.precision == HBT_F32 ? (const float*)w.zstore : w.z32;
     {
         StageTimer t_(HBT_STAGE_ALIGN, s);
