@@ -64,7 +64,9 @@ size_t split_lds_limit();
 // alignment writes, so that the split stage may run beside the alignment.
 // wg_per_cu > 0 pads each work-group's LDS so that at most that many share a
 // CU: beside the alignment kernels, an uncapped split kernel takes every wave
-// slot and the two stages run one after the other.
+// slot and the two stages run one after the other.  The split kernel reads
+// only the block table (bp): sizes, mask row width and pair index are copied
+// there, and rows of pairs that share another pair's splits are skipped.
 constexpr int kSplitWgPerCuBesideAlign = 6;
 hipError_t launch_split_masks(const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_split_masks(const BlockPair* __restrict
     uint32_t* mlds = (uint32_t*)(base + L.mlds);
 
     const int p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
-    const BlockPair pd = bp[p];   // the pair's sizes, mask row width and index
+    const BlockPair pd = bp[p];   // the pair's sizes, mask row width and index (not a PairDesc)
     if (pd.owner != p) return;    // another pair's rows draw these masks (wave-uniform)
     const uint32_t b = bp[p].perm_base + (uint32_t)(row - bp[p].mrow0);
     const int N = pd.n + pd.m, n = pd.n;
