@@ -222,7 +222,7 @@ def main():
     if not args.no_tune:
         costs = hbt.tune_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed)
         widths = hbt.tile_widths(batch.B, d)
-        tuning = {"cost_per_split_row_ms": {"512": costs[0], "256": costs[1]},
+        tuning = {"cost_per_split_row_ms": {"1024": costs[0], "256": costs[1]},
                   "pairs_at_256": int(np.sum(widths == 256))}
         log(f"tile widths tuned: {tuning}")
 

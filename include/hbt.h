@@ -211,13 +211,16 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
 
 /* Tile widths of the split-BF16 product (the batching of Sec. 3.2's practical
  * notes over many pairs).  A work-group of the product covers 64 columns of Z
- * and 512 or 256 splits of one pair.  Every call picks, per pair (per block
+ * and 1024 splits of one pair (eight waves) or 256 (four waves).  Every call
+ * picks, per pair (per block
  * for hbt_perm_test), the width w minimising cost_w * round_up(B, w), with
  * per-split costs for the pair's dimension (padded to 64) from a table in the
- * library; until tuned, cost_512 = 1 and cost_256 = 1.15.  Results do not
+ * library; until tuned, cost_1024 = 1 and cost_256 = 1.15.  A single-pair
+ * call takes the narrow width when its block's wide tiles would number fewer
+ * than two per compute unit (one pair alone must fill the GPU).  Results do not
  * depend on the width.
  *   hbt_tune_batched: runs hbt_perm_test_batched on its arguments four
- *     times, every pair at width 512, 256, 512, 256, times the product with
+ *     times, every pair at width 1024, 256, 1024, 256, times the product with
  *     HIP events and stores, per width, the smaller of its two
  *     cost_w = time / sum_p round_up(B_p, w) * round_up(n_p + m_p, 128) for
  *     this d (the first call also pays first-touch and clock ramp-up).  It
@@ -225,7 +228,7 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
  *     last run's results in `results`.  Split BF16 only (HBT_ERR_ARG
  *     otherwise).
  *   hbt_tune_get / hbt_tune_set: the table entry for d (costs[0] for width
- *     512, costs[1] for 256; tuned = 1 once set), e.g. to keep a cache across
+ *     1024, costs[1] for 256; tuned = 1 once set), e.g. to keep a cache across
  *     processes.
  *   hbt_tile_widths: the widths (host, npairs entries) a call with these
  *     per-pair B would use at dimension d.

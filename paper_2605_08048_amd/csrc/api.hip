@@ -160,10 +160,10 @@ struct Plan {
     std::vector<BlockPair> bp;
     std::vector<SumChunk> chunks;
     std::vector<GemmTile> tiles;
-    std::vector<GemmGroup> groups; // split BF16: the 512-wide groups, then the 256-wide ones
+    std::vector<GemmGroup> groups; // split BF16: the kTileWide groups, then the 256-wide ones
     int64_t ntile_total = 0;      // tiles of the split-BF16 kernel over all groups
-    int ng512 = 0, ng256 = 0;     // groups of each tile width
-    int64_t nt512 = 0, nt256 = 0; // their tiles (tile0 counts from 0 in each segment)
+    int ngw = 0, ng256 = 0;       // groups of each tile width
+    int64_t ntw = 0, nt256 = 0;   // their tiles (tile0 counts from 0 in each segment)
     std::vector<int64_t> Btot;
     int64_t zrows = 0, ncoef = 0;
     int64_t xoct = 0;             // storage octets that hold X rows (all pairs)
@@ -308,16 +308,16 @@ void finish_plan(Plan& P, int64_t d, int precision, int input_dtype) {
 
 // ---------------------------------------------------------------------------
 // Tile width of the split-BF16 product: per pair (or per block of one pair),
-// the width w in {512, 256} minimising cost_w * round_up(B, w); per-split
+// the width w in {kTileWide, 256} minimising cost_w * round_up(B, w); per-split
 // costs come from a table keyed by d_pad (hbt_tune_batched fills it).
 // ---------------------------------------------------------------------------
 struct TileCost {
-    double c[2];   // [0]: 512-split tiles, [1]: 256-split tiles
+    double c[2];   // [0]: kTileWide-split tiles, [1]: 256-split tiles
     bool tuned;
 };
 std::mutex g_tune_mu;
 std::map<int, TileCost> g_tune;
-thread_local int g_force_width = 0;  // 0: choose; 512 or 256: every pair (tuning runs)
+thread_local int g_force_width = 0;  // 0: choose; kTileWide or 256: every pair (tuning runs)
 
 TileCost tile_cost(int d_pad) {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -327,8 +327,8 @@ TileCost tile_cost(int d_pad) {
 
 int choose_width(int64_t B, const TileCost& tc) {
     if (g_force_width) return g_force_width;
-    const double t512 = tc.c[0] * (double)round_up(B, 512), t256 = tc.c[1] * (double)round_up(B, 256);
-    return t256 < t512 ? 256 : 512;
+    const double tw = tc.c[0] * (double)round_up(B, kTileWide), t256 = tc.c[1] * (double)round_up(B, 256);
+    return t256 < tw ? 256 : kTileWide;
 }
 
 // Groups of split-BF16 tiles, pairs in the given order, segmented by width.
@@ -338,18 +338,18 @@ void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B) {
     for (int p : order) {
         const int w = P.precision == HBT_I8X3 ? kTileI8 : choose_width(B[p], tc);
         const int nbt = (int)((B[p] + w - 1) / w);
-        if (w == 512) {
-            P.groups.push_back(GemmGroup{p, nbt, P.nt512});
-            P.nt512 += (int64_t)nbt * P.nslot;
+        if (w == kTileWide) {
+            P.groups.push_back(GemmGroup{p, nbt, P.ntw});
+            P.ntw += (int64_t)nbt * P.nslot;
         } else {
             g2.push_back(GemmGroup{p, nbt, P.nt256});
             P.nt256 += (int64_t)nbt * P.nslot;
         }
     }
-    P.ng512 = (int)P.groups.size();
+    P.ngw = (int)P.groups.size();
     P.ng256 = (int)g2.size();
     P.groups.insert(P.groups.end(), g2.begin(), g2.end());
-    P.ntile_total = P.nt512 + P.nt256;
+    P.ntile_total = P.ntw + P.nt256;
 }
 
 // The block-table entry of a pair's splits [perm_base, perm_base + nb).
@@ -610,8 +610,16 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
     const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
     // the tables of split block b0 (nb splits) and its tile width
+    // One pair alone fills the GPU only with enough tiles: the narrow width
+    // when the wide one would not give two tiles per CU (the width never
+    // changes a result).
     auto block_width = [&](int64_t nb) {
-        return P.precision == HBT_I8X3 ? kTileI8 : choose_width(nb, tile_cost(P.d_pad));
+        if (P.precision == HBT_I8X3) return kTileI8;
+        const int w = choose_width(nb, tile_cost(P.d_pad));
+        if (w == kTileWide && !g_force_width &&
+            (nb + kTileWide - 1) / kTileWide * P.nslot < 2 * (int64_t)device_cus())
+            return kTileNarrow;
+        return w;
     };
     auto block_tables = [&](int64_t b0, int64_t nb) -> hipError_t {
         const BlockPair bq = block_pair(0, 0, prm->perm_offset + (uint64_t)b0, nb, 0, pd);
@@ -686,8 +694,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         {
             StageTimer t_(HBT_STAGE_GROUPSUM, s);
             const int nt = grp.nbt * P.nslot;
-            HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == 512,
-                                    wdt == 512 ? nt : 0, wdt == 256, wdt == 256 ? nt : 0, P.d_pad,
+            HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == kTileWide,
+                                    wdt == kTileWide ? nt : 0, wdt == 256, wdt == 256 ? nt : 0, P.d_pad,
                                     w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
                                     P.block_rows, w.sig, s));
             if (P.route2)
@@ -845,7 +853,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     {
         StageTimer t_(HBT_STAGE_GROUPSUM, s);
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
-                                P.ng512, (int)P.nt512, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
+                                P.ngw, (int)P.ntw, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
                                 P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
                                 nullptr, s));
     }
@@ -1003,7 +1011,7 @@ hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* ro
     if (common->precision != HBT_BF16X2)
         return fail(HBT_ERR_ARG, "tile widths are tuned for the split-BF16 product only");
     if (npairs < 1 || d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "npairs %lld, d %lld", (long long)npairs, (long long)d);
-    const int widths[2] = {512, 256};
+    const int widths[2] = {kTileWide, 256};
     double cost[2] = {0.0, 0.0};
     // each width twice, interleaved, keeping the faster call: the first call
     // also pays first-touch and clock ramp-up

@@ -14,8 +14,8 @@
 // per slot, so a tile's stores and the statistic's loads are contiguous):
 //   partial[slot][row] = (sum_c sigma_small[c]^2, sum_c (t[c] - sigma_small[c])^2)
 //
-// Work-group = 4 waves; tile = kDSlot columns x (512 splits for split BF16,
-// 256 for FP32 / FP64).
+// Tile = kDSlot columns x (1024 splits for split BF16 with eight waves, or
+// 256 with four; 256 for FP32 / FP64 and the int8 digit planes).
 #include <atomic>
 
 #include "hbt_launch.h"
@@ -35,12 +35,14 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast
 // B (16 x 32) lane l -> k 8(l/32)..+7, col l%32; D lane l -> col l%32,
 // rows 8(v/4) + 4(l/32) + v%4.
 //
-// Work-group tile: 64 columns x kTileBF16 (512) splits; 4 waves, wave w owns
+// Work-group tile: 64 columns x 1024 splits (kTileWide); 8 waves, wave w owns
 // splits [128 w, 128 w + 128) as 4 blocks of 32 and the 64 columns as 2
-// blocks of 32 (accumulators 2 x 4 x 16 floats per lane).
+// blocks of 32 (accumulators 2 x 4 x 16 floats per lane).  The narrow width
+// (256 splits) has 4 waves of 64 splits.
 //  * Z streams through LDS in chunks of 128 pooled rows (16 octets; both
 //    planes of the 64-column slice = 32 KB) with direct global -> LDS loads,
-//    one chunk ahead, into two buffers.
+//    one chunk ahead, into two buffers; each chunk feeds all waves of the
+//    work-group, so the wide tile reads each Z slice once per 1024 splits.
 //  * Mask words become bf16 operands with one AND per register: a set bit
 //    lands in the exponent field (a power of two, not 1), and the stored
 //    planes hold each row divided by the power its bit meets, in the row
@@ -50,7 +52,6 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast
 //    one XCD (work-groups are dealt to the 8 XCDs round-robin), and the pair
 //    order is longest-first.
 // ---------------------------------------------------------------------------
-constexpr int kTileBF16 = 512;
 constexpr int kChunk = 128;                      // pooled rows per chunk
 constexpr int kOct = kChunk / 8;                 // octets per chunk
 constexpr int kChunkVec = 2 * kOct * kDSlot;     // uint4 per chunk (both planes)
@@ -100,8 +101,9 @@ __device__ __forceinline__ int xcd_remap(int g) {
 // (gfx9 encoding: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8])
 constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14) | (0x7 << 4) | (0xf << 8); }
 
-// JB split blocks of 32 per wave: a work-group covers 128 JB splits (JB = 4:
-// 512, JB = 2: 256; the tile width the plan picks per pair).
+// JB split blocks of 32 per wave, NW waves: a work-group covers 32 JB NW
+// splits (JB = 4, NW = 8: 1024; JB = 2, NW = 4: 256; the tile width the plan
+// picks per pair).  Each wave loads 32 / NW of the chunk's 32 octet rows.
 //
 // Persistent launch: work-group b walks the tiles b, b + G, b + 2G, ...
 // (G = gridDim.x; tiles are numbered longest pair first), and the chunk
@@ -110,21 +112,25 @@ constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14
 // the epilogue of the current one.  Chunk g of a work-group's sequence goes to
 // LDS buffer g mod 2; the step that multiplies chunk g issues chunk g + 1 into
 // the other buffer, which every wave finished reading in the previous step.
-// Two buffers (80 KB at 512 splits) and at most 256 registers per lane let two
-// work-groups share a CU (2 waves per SIMD): one's barriers, waits and
-// epilogue overlap the other's MFMAs (measured 4.7 -> 4.5 ms on 512 pairs
-// against one work-group per CU with three buffers).
-template <int JB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_bf16x2(
+// Two waves per SIMD (at most 256 registers per lane): the wide tile is one
+// work-group of 8 waves per CU (two buffers, 96 KB of LDS), the narrow one
+// two work-groups of 4 (72 KB each), so that a wave's barriers, waits and
+// epilogue overlap the other waves' MFMAs.  On 512 pairs, d = 768: 4 waves x
+// 512 splits with two work-groups per CU 4.18 ms (11.1 GB fetched), 8 waves x
+// 1024 splits 4.02 ms; one work-group per CU of 4 waves 4.7 ms.
+template <int JB, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
     double* __restrict__ partial, int64_t prow, float* __restrict__ sig) {
     constexpr int kWS = 32 * JB;
-    constexpr int kTile = 4 * kWS;
+    constexpr int kTile = NW * kWS;
     constexpr int kMaskVec = kTile;
     constexpr int kMaskLoads = kWS / 64;
+    constexpr int kRowsW = 2 * kOct / NW;  // octet rows of a chunk (both planes) each wave loads
+    static_assert(kRowsW * NW == 2 * kOct, "waves split a chunk evenly");
     __shared__ uint4 zbuf[2][kChunkVec];
     __shared__ uint4 mbuf[2][kMaskVec];
     const int tid = threadIdx.x;
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const BlockPair bq = bp[t.pair];
         l_nchunk = pd.Np / kChunk;
         const int64_t oct0 = pd.zrow0 >> 3;
-        l_zsrc = ((8 * wave) / kOct ? zlo : zhi) + (oct0 + (8 * wave) % kOct) * d_pad + t.slot * kDSlot;
+        l_zsrc = ((kRowsW * wave) / kOct ? zlo : zhi) + (oct0 + (kRowsW * wave) % kOct) * d_pad + t.slot * kDSlot;
 #pragma unroll
         for (int k = 0; k < kMaskLoads; ++k) {
             const int r = t.b0 + wave * kWS + 64 * k + lane;
@@ -172,10 +178,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // work-group's last chunk it stays there: a harmless reload into a free buffer)
     auto issue_next = [&](int b) {
         const uint4* base = l_zsrc + l_ch * chunk_stride;
-        const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(&zbuf[b][8 * wave * kDSlot]));
+        const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(&zbuf[b][kRowsW * wave * kDSlot]));
         const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(&mbuf[b][wave * kWS]));
 #pragma unroll
-        for (int k = 0; k < 8; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
+        for (int k = 0; k < kRowsW; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
 #pragma unroll
         for (int k = 0; k < kMaskLoads; ++k) dma16(l_mload[k] + l_ch, ml + 16 * 64 * k);
         if (l_ch + 1 < l_nchunk) {
@@ -643,9 +649,10 @@ __global__ __launch_bounds__(256) void k_groupsum_fp(const PairDesc* __restrict_
 // CU leaves the tail unbalanced and one per tile loses the cross-tile
 // prefetch, 4 is best; with two resident (split BF16), 2 / 4 / 8 / 16 / 32 /
 // 64 per CU give 4.80 / 4.70 / 4.62 / 4.60 / 4.52 / 4.50 ms and one per tile
-// 4.51 ms: the co-resident work-group already hides a tile's start.
+// 4.51 ms: the co-resident work-group already hides a tile's start.  The
+// eight-wave wide tile (one work-group per CU): 8 or 16 per CU, within noise.
 static std::atomic<int> g_cus[64];
-static unsigned persistent_grid(int64_t tiles, int per_cu) {
+int device_cus() {
     int dev = 0;
     int cus = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
@@ -653,17 +660,21 @@ static unsigned persistent_grid(int64_t tiles, int per_cu) {
         if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
             g_cus[dev].store(cus, std::memory_order_relaxed);
     }
-    if (cus <= 0) cus = 256;
+    return cus > 0 ? cus : 256;
+}
+
+static unsigned persistent_grid(int64_t tiles, int per_cu) {
+    const int cus = device_cus();
     const int64_t want = (int64_t)(cus * per_cu + 31) / 32 * 32;
     const int64_t all = (tiles + 31) / 32 * 32;
     return (unsigned)(all < want ? all : want);
 }
 
-int groupsum_tile_splits(int precision) { return precision == HBT_BF16X2 ? kTileBF16 : kTileB; }
+int groupsum_tile_splits(int precision) { return precision == HBT_BF16X2 ? kTileWide : kTileB; }
 
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
-                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ng512,
-                           int nt512, int ng256, int nt256, int d_pad, const void* zstore,
+                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngw,
+                           int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig, hipStream_t s) {
     const int nslot = d_pad / kDSlot;
@@ -672,20 +683,21 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
         case HBT_BF16X2: {
             const uint4* zhi = (const uint4*)zstore;
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
-            if (nt512 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<4>, dim3(persistent_grid(nt512, 32)), block, 0,
-                                   s, pairs, bp, groups, ng512, nt512, nslot, d_pad, zhi, zlo, mask,
+            static_assert(32 * 4 * 8 == kTileWide && 32 * 2 * 4 == kTileNarrow, "tile widths");
+            if (ntw > 0)
+                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8>), dim3(persistent_grid(ntw, 16)), dim3(512), 0,
+                                   s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
                                    t32, partial, prow, sig);
             if (nt256 > 0)
-                hipLaunchKernelGGL(k_groupsum_bf16x2<2>, dim3(persistent_grid(nt256, 32)), block, 0,
-                                   s, pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, zhi, zlo,
+                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4>), dim3(persistent_grid(nt256, 32)), block, 0,
+                                   s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
                                    mask, t32, partial, prow, sig);
             break;
         }
         case HBT_I8X3:
             if (nt256 > 0)
                 hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, 32)), block, 0, s,
-                                   pairs, bp, groups + ng512, ng256, nt256, nslot, d_pad, (const uint4*)zstore,
+                                   pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, (const uint4*)zstore,
                                    zplane_elems / 16, mask, t64, partial, prow);
             break;
         case HBT_F32:

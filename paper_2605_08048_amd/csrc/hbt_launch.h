@@ -85,11 +85,16 @@ int groupsum_tile_splits(int precision);
 // partial[slot][row] = (|sigma_small|^2, |t - sigma_small|^2) over the slot's
 // kDSlot columns, sigma_small = mask_small . Z; slot-major with prow rows per
 // slot (the block's split rows).
-// FP32 / FP64 use the tile list; split BF16 uses the per-pair groups
-// (ntile_total tiles in all).
+// FP32 / FP64 use the tile list; split BF16 uses the per-pair groups: ngw
+// groups of kTileWide-split tiles (ntw tiles), then ng256 of kTileNarrow.
+// Split-BF16 tile widths: kTileWide splits per work-group of eight waves, or
+// kTileNarrow per work-group of four.
+constexpr int kTileWide = 1024, kTileNarrow = 256;
+// Compute units of the current device (cached per device).
+int device_cus();
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
-                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ng512,
-                           int nt512, int ng256, int nt256, int d_pad, const void* zstore,
+                           const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngw,
+                           int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig,
                            hipStream_t s);

@@ -383,7 +383,7 @@ def budgets(mlp_out, results, p_lo, p_hi, b_min, b_max, zq=2.3263478740408408, s
 
 def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="banerjee", workspace=None):
     """Time both tile widths of the split-BF16 product on this batch and store
-    their per-split costs for its dimension; returns (cost_512, cost_256)."""
+    their per-split costs for its dimension; returns (cost_1024, cost_256)."""
     torch = _torch()
     dev = Z_all.device
     Z_all = Z_all.contiguous()
@@ -407,7 +407,7 @@ def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="ban
 
 
 def tune_get(d):
-    """((cost_512, cost_256), tuned) for dimension d."""
+    """((cost_1024, cost_256), tuned) for dimension d."""
     c = (C.c_double * 2)()
     t = C.c_int32()
     _check(lib().hbt_tune_get(d, c, C.byref(t)))

@@ -136,17 +136,17 @@ def test_batched_validation():
 
 
 def test_tile_width_rule_and_tuning_table(tmp_path):
-    """Per pair, the width w in {512, 256} minimising cost_w * round_up(B, w)."""
+    """Per pair, the width w in {1024, 256} minimising cost_w * round_up(B, w)."""
     import numpy as np
     d = 4160  # a dimension no other test tunes
-    (c512, c256), tuned = hbt.tune_get(d)
-    assert (c512, c256) == (1.0, 1.15) and not tuned
-    B = np.array([1, 200, 250, 256, 257, 300, 512, 700, 2000, 20000])
-    want = [256 if c256 * -(-b // 256) * 256 < c512 * -(-b // 512) * 512 else 512 for b in B]
+    (cw, c256), tuned = hbt.tune_get(d)
+    assert (cw, c256) == (1.0, 1.15) and not tuned
+    B = np.array([1, 200, 250, 256, 257, 300, 512, 700, 1000, 1025, 2000, 20000])
+    want = [256 if c256 * -(-b // 256) * 256 < cw * -(-b // 1024) * 1024 else 1024 for b in B]
     assert list(hbt.tile_widths(B, d)) == want
-    assert list(hbt.tile_widths([200, 2000], d)) == [256, 512]
+    assert list(hbt.tile_widths([200, 2000], d)) == [256, 1024]
     hbt.tune_set(d, [1.0, 5.0])
-    assert list(hbt.tile_widths(B, d)) == [512] * len(B)
+    assert list(hbt.tile_widths(B, d)) == [1024] * len(B)
     assert hbt.tune_get(d) == ((1.0, 5.0), True)
     # the JSON cache round-trips through the library's table
     f = tmp_path / "tune.json"

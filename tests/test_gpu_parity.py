@@ -498,7 +498,7 @@ def test_recheck_value_does_not_depend_on_how_it_is_spread():
 
 
 def test_tile_widths_do_not_change_results():
-    """The product runs per pair with 512- or 256-split tiles; each split's
+    """The product runs per pair with 1024- or 256-split tiles; each split's
     sums come from the same instructions in the same order, so results are
     bit-identical whichever width the table picks."""
     rng = np.random.default_rng(23)
@@ -511,7 +511,7 @@ def test_tile_widths_do_not_change_results():
     runs = []
     for costs in [(1.0, 1e9), (1e9, 1.0)]:
         hbt.tune_set(160, costs)
-        assert set(hbt.tile_widths(bt.B, 160)) == ({512} if costs[0] < costs[1] else {256})
+        assert set(hbt.tile_widths(bt.B, 160)) == ({1024} if costs[0] < costs[1] else {256})
         runs.append(hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=4,
                                           precision="bf16x2"))
         X, Y = pairs[0].X, pairs[0].Y
