@@ -694,8 +694,9 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         {
             StageTimer t_(HBT_STAGE_GROUPSUM, s);
             const int nt = grp.nbt * P.nslot;
+            // the wide segment, or the other one (the narrow split-BF16 width, int8 planes)
             HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == kTileWide,
-                                    wdt == kTileWide ? nt : 0, wdt == 256, wdt == 256 ? nt : 0, P.d_pad,
+                                    wdt == kTileWide ? nt : 0, wdt != kTileWide, wdt != kTileWide ? nt : 0, P.d_pad,
                                     w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
                                     P.block_rows, w.sig, s));
             if (P.route2)

@@ -319,12 +319,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 // A (32 x 32) lane l -> row l%32, k 16(l/32)..+15; B (32 x 32) lane l ->
 // k 16(l/32)..+15, col l%32; D lane l -> col l%32, rows 8(v/4) + 4(l/32) + v%4.
 //
-// Work-group tile: 64 columns x kTileI8 (256) splits; wave w owns splits
-// [64 w, 64 w + 64) as 2 blocks of 32 and the 64 columns as 2 blocks of 32
-// (accumulators 2 sums x 2 x 2 x 16 int32 per lane), so that two
-// work-groups share a CU (226 registers per lane, 56 KB of LDS each), as in
-// the split-BF16 kernel (512-split tiles with one work-group per CU and
-// three buffers: 4.32 ms on 512 pairs, d = 768; this form: 3.91 ms).
+// Work-group tile: 64 columns x kTileI8 (512) splits of eight waves; wave w
+// owns splits [64 w, 64 w + 64) as 2 blocks of 32 and the 64 columns as 2
+// blocks of 32 (accumulators 2 sums x 2 x 2 x 16 int32 per lane; 224
+// registers per lane, 2 waves per SIMD).  One work-group per CU (64 KB of
+// LDS) shares each Z chunk between all eight waves, as the wide split-BF16
+// tile does (on 512 pairs, d = 768: 3.77 ms with 256 splits of four waves
+// and two work-groups per CU, 3.6-3.7 ms this way).
 // A K-step is 32 pooled rows, one mask word: operand register s of lane
 // half h is (word >> (s + 4 h)) & 0x01010101 (the planes' row order makes
 // those the lane's rows), and that shifted left by 7 for the middle plane.
@@ -340,16 +341,16 @@ constexpr int kChunkVecI8 = 3 * kHex * kDSlot;     // uint4 per chunk (three pla
 // |S_lo| <= 64 N (2^7 + 1) and |S_hi| <= 64 N must stay int32 for every pooled size
 static_assert(64LL * HBT_MAX_N * 129 < (1LL << 31), "int8 digit sums overflow int32");
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_i8x3(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_i8x3(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zq, int64_t plane_vec, const uint32_t* __restrict__ mask,
     const double* __restrict__ t64, double* __restrict__ partial, int64_t prow) {
     constexpr int JB = 2, kWS = 32 * JB;        // splits per wave
-    constexpr int kRowsPerWave = 3 * kHex / 4;  // LDS rows of Z each wave loads (6)
+    constexpr int kRowsPerWave = 3 * kHex / 8;  // LDS rows of Z each wave loads (3)
     constexpr int kMaskLoads = kWS / 64;        // mask loads per wave per chunk
     constexpr int kWaitOneChunk = wait_vmcnt(0);  // the one chunk in flight
-    static_assert(kTileI8 == 4 * kWS, "tile width");
+    static_assert(kTileI8 == 8 * kWS && kRowsPerWave * 8 == 3 * kHex, "eight waves");
     __shared__ uint4 zbuf[2][kChunkVecI8];
     __shared__ uint4 mbuf[2][kTileI8];
     const int tid = threadIdx.x;
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
     };
     l_setup();
-    // chunk at the cursor: LDS rows (plane, unit) 6 w .. 6 w + 5, lane l moving
+    // chunk at the cursor: LDS rows (plane, unit) 3 w .. 3 w + 2, lane l moving
     // column l; then the wave's mask words; then advance the cursor (it stays
     // on the work-group's last chunk at the end: harmless reloads)
     auto issue_next = [&](int b) {
@@ -696,7 +697,7 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
         }
         case HBT_I8X3:
             if (nt256 > 0)
-                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, 32)), block, 0, s,
+                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, 16)), dim3(512), 0, s,
                                    pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, (const uint4*)zstore,
                                    zplane_elems / 16, mask, t64, partial, prow);
             break;

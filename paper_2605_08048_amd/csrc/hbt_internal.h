@@ -18,7 +18,7 @@ constexpr int kDPad = 64;
 // statistic kernel adds the d_pad / kDSlot slots of a split row in FP64.
 constexpr int kDSlot = 64;
 // Splits per work-group of the int8 digit-plane kernel (one tile width).
-constexpr int kTileI8 = 256;
+constexpr int kTileI8 = 512;
 // Split rows per group-sum tile (4 waves x 64 rows).
 constexpr int kTileB = 256;
 // Capacity of the boundary bucket of the split selection (items whose
