@@ -497,6 +497,31 @@ def test_recheck_value_does_not_depend_on_how_it_is_spread():
     assert checked > 0
 
 
+def test_single_pair_wide_and_narrow_tiles_agree():
+    """A single-pair call takes the wide tile only when it gives at least two
+    tiles per CU; this pair (d = 1024, 32768 splits: 32 x 16 wide tiles) does,
+    so the call runs the eight-wave kernel with wide costs and the narrow one
+    with narrow costs, and the results must agree bit for bit."""
+    d, B = 1024, 32768
+    X, Y = _pair(300, 420, d, kx=2.0, ky=2.1, seed=71)
+    Xd, Yd = _dev(X), _dev(Y)
+    saved, _ = hbt.tune_get(d)
+    try:
+        runs = []
+        for costs in [(1.0, 1e9), (1e9, 1.0)]:
+            hbt.tune_set(d, costs)
+            runs.append(hbt.perm_test(Xd, Yd, B, seed=3, precision="bf16x2", want_T="f64"))
+    finally:
+        hbt.tune_set(d, saved)
+    assert runs[0]["status"] == 0 and runs[1]["status"] == 0
+    assert np.array_equal(runs[0]["T"], runs[1]["T"])
+    for k in ["t_obs", "count", "p", "n_recheck", "t_mean", "t_sd"]:
+        assert runs[0][k] == runs[1][k], k
+    o = O.perm_test(X, Y, 200, seed=3, want_T=True)  # the first 200 splits against the oracle
+    err = np.abs(runs[0]["T"][:200] - o["T"]) / _scale(X, Y, O.perm_stats_at(X, Y, np.arange(200), seed=3))
+    assert err.max() <= TOL["bf16x2"], err.max()
+
+
 def test_tile_widths_do_not_change_results():
     """The product runs per pair with 1024- or 256-split tiles; each split's
     sums come from the same instructions in the same order, so results are
