@@ -112,7 +112,8 @@ typedef struct hbt_perm_params {
     int64_t n, m, d;        /* group sizes and dimension */
     int64_t B;              /* number of random splits */
     uint64_t seed;          /* Philox key */
-    uint64_t perm_offset;   /* global index of the first split (resume / sharding) */
+    uint64_t perm_offset;   /* global index of the first split (resume / sharding);
+                               perm_offset + B <= 2^32, else HBT_ERR_ARG */
     uint32_t pair_index;    /* Philox counter word 2 */
     int32_t precision;      /* hbt_precision */
     int32_t input_dtype;    /* hbt_dtype of X and Y */

@@ -293,7 +293,7 @@ hbt_status check_sizes(int64_t n, int64_t m, int64_t d, int64_t B, uint64_t perm
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld outside [1, %d]", (long long)d, HBT_MAX_D);
     if (n + m > HBT_MAX_N) return fail(HBT_ERR_SIZE, "n + m = %lld above %d", (long long)(n + m), HBT_MAX_N);
     if (B < 1) return fail(HBT_ERR_SIZE, "B must be >= 1");
-    if (perm_offset + (uint64_t)B > 0x100000000ull)
+    if (perm_offset > 0x100000000ull || (uint64_t)B > 0x100000000ull - perm_offset)
         return fail(HBT_ERR_ARG, "perm_offset + B exceeds 2^32 split indices");
     return HBT_OK;
 }

@@ -79,6 +79,11 @@ def test_perm_test_rejects_null_pointers_and_enums():
 def test_perm_offset_overflow():
     prm = hbt.make_params(10, 12, 8, 100, perm_offset=2**32 - 50)
     assert _call(prm) == hbt.ERR_ARG
+    # offsets whose sum with B wraps around 2^64 are rejected too
+    for off in (2**64 - 1, 2**64 - 50, 2**33):
+        assert _call(hbt.make_params(10, 12, 8, 100, perm_offset=off)) == hbt.ERR_ARG, off
+    # the last valid window ends exactly at 2^32 (it fails later, on the fake workspace pointer's size)
+    assert _call(hbt.make_params(10, 12, 8, 100, perm_offset=2**32 - 100), ws_bytes=0) == hbt.ERR_WORKSPACE
 
 
 def test_workspace_size_and_too_small_workspace():
