@@ -154,6 +154,24 @@ def _dev_tensor(a, dtype, device):
     return t.contiguous()
 
 
+def _on_device(name, t, device=None):
+    """Raise unless ``t`` is a tensor in GPU memory (on ``device`` if given):
+    the library dereferences every pointer it is handed on the GPU."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise HbtError(ERR_ARG, f"{name} must be a GPU tensor")
+    if device is not None and t.device != device:
+        raise HbtError(ERR_ARG, f"{name} is on {t.device}, the call runs on {device}")
+
+
+def _pair_operands(X, Y):
+    """Shape checks shared by the one-pair calls: X (n, d), Y (m, d), one device."""
+    if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+        raise HbtError(ERR_SIZE, f"X {tuple(X.shape)} and Y {tuple(Y.shape)} must be (n, d) and (m, d)")
+    _on_device("X", X)
+    _on_device("Y", Y, X.device)
+
+
 def _input_dtype(X):
     torch = _torch()
     if X.dtype == torch.float64:
@@ -185,11 +203,16 @@ def make_params(n, m, d, B, *, seed=0, perm_offset=0, pair_index=0, precision="f
 def align(X, Y, *, align=True, gd="banerjee", out=None, stream=None):
     """Householder alignment of X onto Y's mean direction (Algorithm 1, Steps 1-4)."""
     torch = _torch()
+    _pair_operands(X, Y)
     n, d = X.shape
     m = Y.shape[0]
     dev = X.device
     Y = Y.to(dtype=X.dtype).contiguous()
     X = X.contiguous()
+    if out is not None:
+        _on_device("out", out, dev)
+        if out.shape != X.shape or out.dtype != X.dtype or not out.is_contiguous():
+            raise HbtError(ERR_ARG, f"out must be a contiguous {X.dtype} tensor of shape {tuple(X.shape)}")
     Xo = out if out is not None else torch.empty_like(X)
     v = torch.empty(d, dtype=torch.float64, device=dev)
     res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=dev)
@@ -211,6 +234,7 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     plus ``T`` (B floats; doubles with want_T="f64") and ``masks``
     (B x ceil(N/32) words) when asked."""
     torch = _torch()
+    _pair_operands(X, Y)
     n, d = X.shape
     m = Y.shape[0]
     dev = X.device
@@ -221,6 +245,8 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     if masks is not None:
         mk = _dev_tensor(np.asarray(masks, dtype=np.uint32).view(np.int32).reshape(B, W)
                          if not isinstance(masks, torch.Tensor) else masks, torch.int32, dev)
+        if mk.numel() != B * W:
+            raise HbtError(ERR_SIZE, f"masks hold {mk.numel()} words, B x ceil((n+m)/32) = {B * W}")
     prm = make_params(n, m, d, B, seed=seed, perm_offset=perm_offset, pair_index=pair_index,
                       precision=precision, input_dtype=_input_dtype(X), gd=gd, alternative=alternative,
                       align=align, recheck=recheck, block_perms=block_perms, stat_route=stat_route,
@@ -261,6 +287,30 @@ def batched_workspace_size(row_offset, n, m, B, d, *, precision="bf16x2", input_
     return int(lib().hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm)))
 
 
+def _batch_tables(Z_all, row_offset, n, m, B, pair_index):
+    """Host tables of a batched call, checked: Z_all (rows, d) on the GPU, one
+    entry per pair (row_offset may carry more, e.g. a cumulative table, whose
+    first P count), and every pair's rows inside Z_all, whose length the
+    library cannot see."""
+    if Z_all.dim() != 2:
+        raise HbtError(ERR_SIZE, f"Z_all must be (rows, d), got {tuple(Z_all.shape)}")
+    P = len(n)
+    off = np.ascontiguousarray(np.asarray(row_offset, dtype=np.int64)[:P])
+    nn = np.ascontiguousarray(n, dtype=np.int64)
+    mm = np.ascontiguousarray(m, dtype=np.int64)
+    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
+    ids = None if pair_index is None else np.ascontiguousarray(pair_index, dtype=np.uint32)
+    if off.shape != (P,) or mm.shape != (P,) or (ids is not None and ids.shape != (P,)):
+        raise HbtError(ERR_SIZE, "row_offset, n, m and pair_index need one entry per pair")
+    outside = (off < 0) | (off + nn + mm > Z_all.shape[0])
+    if np.any(outside):
+        k = int(np.flatnonzero(outside)[0])
+        raise HbtError(ERR_SIZE, f"pair {k}: rows [{off[k]}, {off[k] + nn[k] + mm[k]}) "
+                                 f"outside Z_all's {Z_all.shape[0]} rows")
+    _on_device("Z_all", Z_all)
+    return P, off, nn, mm, BB, ids
+
+
 def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair_index=None,
                       precision="bf16x2", gd="banerjee", alternative="greater", align=True, recheck=True,
                       stream=None, sync=True, results=None, workspace=None):
@@ -273,13 +323,16 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
     device tensor that outlives the graph) instead of the shared cached one."""
     torch = _torch()
     dev = Z_all.device
+    P, off, nn, mm, BB, ids = _batch_tables(Z_all, row_offset, n, m, B, pair_index)
+    if results is not None:
+        _on_device("results", results, dev)
+        if results.dtype != torch.uint8 or results.numel() < RESULT_BYTES * P or not results.is_contiguous():
+            raise HbtError(ERR_SIZE, f"results must be a contiguous uint8 tensor of {RESULT_BYTES * P} bytes")
+    if workspace is not None:
+        _on_device("workspace", workspace, dev)
+        if workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+            raise HbtError(ERR_ARG, "workspace must be a contiguous uint8 tensor")
     Z_all = Z_all.contiguous()
-    P = len(n)
-    off = np.ascontiguousarray(row_offset, dtype=np.int64)
-    nn = np.ascontiguousarray(n, dtype=np.int64)
-    mm = np.ascontiguousarray(m, dtype=np.int64)
-    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
-    ids = None if pair_index is None else np.ascontiguousarray(pair_index, dtype=np.uint32)
     d = Z_all.shape[1]
     prm = make_params(0, 0, d, 0, seed=seed, perm_offset=perm_offset, precision=precision,
                       input_dtype=_input_dtype(Z_all), gd=gd, alternative=alternative, align=align,
@@ -386,13 +439,12 @@ def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="ban
     their per-split costs for its dimension; returns (cost_1024, cost_256)."""
     torch = _torch()
     dev = Z_all.device
+    P, off, nn, mm, BB, ids = _batch_tables(Z_all, row_offset, n, m, B, pair_index)
+    if workspace is not None:
+        _on_device("workspace", workspace, dev)
+        if workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+            raise HbtError(ERR_ARG, "workspace must be a contiguous uint8 tensor")
     Z_all = Z_all.contiguous()
-    P = len(n)
-    off = np.ascontiguousarray(row_offset, dtype=np.int64)
-    nn = np.ascontiguousarray(n, dtype=np.int64)
-    mm = np.ascontiguousarray(m, dtype=np.int64)
-    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
-    ids = None if pair_index is None else np.ascontiguousarray(pair_index, dtype=np.uint32)
     d = Z_all.shape[1]
     prm = make_params(0, 0, d, 0, seed=seed, precision="bf16x2", input_dtype=_input_dtype(Z_all), gd=gd)
     L = lib()

@@ -86,6 +86,35 @@ def test_perm_offset_overflow():
     assert _call(hbt.make_params(10, 12, 8, 100, perm_offset=2**32 - 100), ws_bytes=0) == hbt.ERR_WORKSPACE
 
 
+def test_bindings_check_operands_before_any_device_call():
+    """Shapes, lengths and row ranges the library cannot see are checked in the
+    binding, and host tensors are refused before a pointer reaches the library."""
+    torch = pytest.importorskip("torch")
+    Z = torch.zeros(10, 8)
+    with pytest.raises(hbt.HbtError, match="outside Z_all's 10 rows"):
+        hbt.perm_test_batched(Z, [0, 4], [2, 3], [2, 4], 10)
+    with pytest.raises(hbt.HbtError, match="outside Z_all's 10 rows"):
+        hbt.perm_test_batched(Z, [-1], [2], [2], 10)
+    with pytest.raises(hbt.HbtError, match="one entry per pair"):
+        hbt.perm_test_batched(Z, [0], [2, 2], [2, 2], 10)
+    with pytest.raises(hbt.HbtError, match="must be \\(rows, d\\)"):
+        hbt.perm_test_batched(torch.zeros(10), [0], [2], [2], 10)
+    with pytest.raises(hbt.HbtError, match="Z_all must be a GPU tensor"):
+        hbt.perm_test_batched(Z, [0, 4], [2, 3], [2, 3], 10)
+    # a cumulative offset table (P + 1 entries) is accepted; too few entries are not
+    with pytest.raises(hbt.HbtError, match="Z_all must be a GPU tensor"):
+        hbt.perm_test_batched(Z, [0, 4, 10], [2, 3], [2, 3], 10)
+    with pytest.raises(hbt.HbtError, match="one entry per pair"):
+        hbt.perm_test_batched(Z, [0], [2, 3], [2, 3], 10)
+    X, Y = torch.zeros(5, 8), torch.zeros(6, 8)
+    with pytest.raises(hbt.HbtError, match="must be \\(n, d\\) and \\(m, d\\)"):
+        hbt.perm_test(X, torch.zeros(6, 7), 10)
+    with pytest.raises(hbt.HbtError, match="X must be a GPU tensor"):
+        hbt.perm_test(X, Y, 10)
+    with pytest.raises(hbt.HbtError, match="X must be a GPU tensor"):
+        hbt.align(X, Y)
+
+
 def test_workspace_size_and_too_small_workspace():
     L = hbt.lib()
     prm = hbt.make_params(2000, 1500, 768, 10000, precision="bf16x2")
