@@ -168,7 +168,9 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 /* hbt_perm_test_batched: many independent pairs in one sequence of launches.
  *   Z_all (device, FP32 or FP64 per common->input_dtype): rows X_0, Y_0,
  *     X_1, Y_1, ..., each d wide; pair p's X starts at row row_offset[p] and
- *     its Y at row_offset[p] + n[p].
+ *     its Y at row_offset[p] + n[p].  The call cannot see Z_all's length:
+ *     the caller guarantees row_offset[p] + n[p] + m[p] <= its row count
+ *     (the Python binding checks it); a negative offset is HBT_ERR_ARG.
  *   row_offset, n, m, B: HOST arrays of npairs int64 (row_offset may have
  *     npairs + 1 entries; only the first npairs are read).
  *   pair_index: HOST array of npairs Philox counter words, or NULL for
