@@ -366,11 +366,32 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(name, t, dtype, *, cols=None, numel=None, device=None):
+    """Raise unless ``t`` is a contiguous GPU tensor of ``dtype`` with ``cols``
+    columns (2-D) or ``numel`` elements: the kernels index it by those sizes."""
+    _on_device(name, t, device)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise HbtError(ERR_ARG, f"{name} must be a contiguous {dtype} tensor, got {t.dtype}")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise HbtError(ERR_SIZE, f"{name} must be (rows, {cols}), got {tuple(t.shape)}")
+    if numel is not None and t.numel() != numel:
+        raise HbtError(ERR_SIZE, f"{name} must hold {numel} elements, got {t.numel()}")
+
+
+def _results_records(results, device=None):
+    """Number of hbt_result records in a uint8 device tensor (checked)."""
+    torch = _torch()
+    _need("results", results, torch.uint8, device=device)
+    if results.numel() % RESULT_BYTES:
+        raise HbtError(ERR_SIZE, f"results hold {results.numel()} bytes, not a multiple of {RESULT_BYTES}")
+    return results.numel() // RESULT_BYTES
+
+
 def budget_features(results, d, gd="banerjee", stream=None):
     """(npairs, 12) float32 device tensor of allocator inputs from a device
     tensor of hbt_result records (as returned with sync=False)."""
     torch = _torch()
-    P = results.numel() // RESULT_BYTES
+    P = _results_records(results)
     out = torch.empty((P, MLP_FEATURES), dtype=torch.float32, device=results.device)
     _check(lib().hbt_budget_features(P, _ptr(results), d, GD[gd], _ptr(out), _stream(stream)))
     return out
@@ -379,7 +400,7 @@ def budget_features(results, d, gd="banerjee", stream=None):
 def null_targets(results, stream=None):
     """(npairs, 2) float32 device tensor (t_mean, log t_sd) of hbt_result records."""
     torch = _torch()
-    P = results.numel() // RESULT_BYTES
+    P = _results_records(results)
     out = torch.empty((P, 2), dtype=torch.float32, device=results.device)
     _check(lib().hbt_null_targets(P, _ptr(results), _ptr(out), _stream(stream)))
     return out
@@ -387,16 +408,24 @@ def null_targets(results, stream=None):
 
 def feature_norm(features, theta, stream=None):
     """Write the per-feature standardisation (mean, 1/sd) into theta[0:24]."""
+    torch = _torch()
+    _need("features", features, torch.float32, cols=MLP_FEATURES)
+    _need("theta", theta, torch.float32, numel=MLP_PARAMS, device=features.device)
     _check(lib().hbt_feature_norm(features.shape[0], _ptr(features), _ptr(theta), _stream(stream)))
 
 
 def target_norm(targets, theta, stream=None):
     """Write the output standardisation (mean, sd of the targets) into theta[24:28]."""
+    torch = _torch()
+    _need("targets", targets, torch.float32, cols=2)
+    _need("theta", theta, torch.float32, numel=MLP_PARAMS, device=targets.device)
     _check(lib().hbt_target_norm(targets.shape[0], _ptr(targets), _ptr(theta), _stream(stream)))
 
 
 def mlp_forward(features, theta, stream=None):
     torch = _torch()
+    _need("features", features, torch.float32, cols=MLP_FEATURES)
+    _need("theta", theta, torch.float32, numel=MLP_PARAMS, device=features.device)
     out = torch.empty((features.shape[0], 2), dtype=torch.float32, device=features.device)
     _check(lib().hbt_mlp_forward(features.shape[0], _ptr(features), _ptr(theta), _ptr(out), _stream(stream)))
     return out
@@ -406,10 +435,17 @@ def mlp_grad(features, targets, theta, grad=None, loss=None, stream=None):
     """(grad, loss): float32 gradient of the mean half squared error and the
     FP64 loss, both device tensors."""
     torch = _torch()
+    _need("features", features, torch.float32, cols=MLP_FEATURES)
     R = features.shape[0]
     dev = features.device
+    _need("targets", targets, torch.float32, cols=2, device=dev)
+    if targets.shape[0] != R:
+        raise HbtError(ERR_SIZE, f"{R} feature rows but {targets.shape[0]} target rows")
+    _need("theta", theta, torch.float32, numel=MLP_PARAMS, device=dev)
     grad = grad if grad is not None else torch.zeros(MLP_PARAMS, dtype=torch.float32, device=dev)
     loss = loss if loss is not None else torch.zeros(1, dtype=torch.float64, device=dev)
+    _need("grad", grad, torch.float32, numel=MLP_PARAMS, device=dev)
+    _need("loss", loss, torch.float64, numel=1, device=dev)
     L = lib()
     ws = workspace(L.hbt_mlp_grad_workspace_size(R), dev)
     _check(L.hbt_mlp_grad(R, _ptr(features), _ptr(targets), _ptr(theta), _ptr(grad), _ptr(loss), _ptr(ws),
@@ -418,6 +454,9 @@ def mlp_grad(features, targets, theta, grad=None, loss=None, stream=None):
 
 
 def mlp_adam(theta, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    torch = _torch()
+    for name, t in (("theta", theta), ("grad", grad), ("m", m), ("v", v)):
+        _need(name, t, torch.float32, numel=MLP_PARAMS, device=theta.device)
     _check(lib().hbt_mlp_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
                               _stream(stream)))
 
@@ -425,7 +464,10 @@ def mlp_adam(theta, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
 def budgets(mlp_out, results, p_lo, p_hi, b_min, b_max, zq=2.3263478740408408, stream=None):
     """int64 device tensor of permutation budgets per pair."""
     torch = _torch()
+    _need("mlp_out", mlp_out, torch.float32, cols=2)
     P = mlp_out.shape[0]
+    if _results_records(results, mlp_out.device) < P:
+        raise HbtError(ERR_SIZE, f"{P} predictions but fewer hbt_result records")
     out = torch.empty(P, dtype=torch.int64, device=mlp_out.device)
     _check(lib().hbt_budgets(P, _ptr(mlp_out), _ptr(results), p_lo, p_hi, b_min, b_max, zq, _ptr(out),
                              _stream(stream)))

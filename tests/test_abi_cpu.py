@@ -115,6 +115,19 @@ def test_bindings_check_operands_before_any_device_call():
         hbt.align(X, Y)
 
 
+def test_allocator_bindings_refuse_host_tensors():
+    torch = pytest.importorskip("torch")
+    F, T = torch.zeros(4, hbt.MLP_FEATURES), torch.zeros(4, 2)
+    th = torch.zeros(hbt.MLP_PARAMS)
+    res = torch.zeros(4 * hbt.RESULT_BYTES, dtype=torch.uint8)
+    for call in (lambda: hbt.budget_features(res, 8), lambda: hbt.null_targets(res),
+                 lambda: hbt.feature_norm(F, th), lambda: hbt.target_norm(T, th),
+                 lambda: hbt.mlp_forward(F, th), lambda: hbt.mlp_grad(F, T, th),
+                 lambda: hbt.mlp_adam(th, th, th, th, 1), lambda: hbt.budgets(T, res, 0.01, 0.1, 10, 100)):
+        with pytest.raises(hbt.HbtError, match="must be a GPU tensor"):
+            call()
+
+
 def test_workspace_size_and_too_small_workspace():
     L = hbt.lib()
     prm = hbt.make_params(2000, 1500, 768, 10000, precision="bf16x2")
