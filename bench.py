@@ -195,7 +195,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the permutation test shards by split ranges, see DESIGN.md).", file=sys.stderr)
+              "(the permutation test would shard by split ranges: perm_offset, B).", file=sys.stderr)
         sys.exit(2)
 
     if args.counter_pass:

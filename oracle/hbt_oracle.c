@@ -21,7 +21,7 @@
  *   5. pool Z = X' u Y, B random splits into sizes (n, m), statistic per split;
  *   6. p = (1 + #{T_b >= T_obs}) / (B + 1)                           (eq:pvalue).
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent or ambiguous:
  *   - g_d is the Banerjee et al. (2005) vMF concentration estimate
  *     r (d - r^2) / (1 - r^2); g_d(r) = r is offered as the alternative.
  *   - H = I when |v| <= 1e-12 or when alignment is switched off.
