@@ -408,6 +408,33 @@ def test_pair_d768_full_size(prec):
     assert abs(r["t_obs"] - o["t_obs"]) < 1e-12 * abs(o["t_obs"])
 
 
+def test_batch_512_d768_full_size_sampled_pairs():
+    """The whole 512-pair batch (d = 768, B = 2000 per pair, 1.05M rows) in
+    one call per precision, with tile widths tuned on it first, as the
+    throughput measurement runs it; seven pairs from the smallest to the
+    largest are checked against the oracle."""
+    print("batch_512_d768 full size", flush=True)
+    b = synth.batch_512_d768()
+    Z = _dev(b.Z)
+    hbt.tune_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed)
+    res = {prec: hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
+           for prec in ["bf16x2", "i8x3"]}
+    del Z
+    order = np.argsort(b.n + b.m, kind="stable")
+    P = b.npairs
+    for p in (int(order[k]) for k in (0, 1, P // 4, P // 2, 3 * P // 4, P - 2, P - 1)):
+        pr = b.pair(p)
+        print(f"pair {p}: n={pr.X.shape[0]} m={pr.Y.shape[0]}", flush=True)
+        o = O.perm_test(pr.X, pr.Y, pr.B, seed=b.seed, pair=p, want_T=True)
+        at = O.perm_stats_at(pr.X, pr.Y, np.arange(pr.B), seed=b.seed, pair=p)
+        for prec, r in res.items():
+            assert np.all(r["status"] == 0), prec
+            assert abs(r[p]["t_obs"] - o["t_obs"]) <= 1e-12 * max(1.0, abs(o["t_obs"])), (prec, p)
+            assert abs(r[p]["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"]), (prec, p)
+            assert r[p]["B"] == pr.B and r[p]["p"] == (1 + r[p]["count"]) / (pr.B + 1)
+            _check_extras(r[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
+
+
 # --------------------------------------------------------------------- graph capture
 
 def test_batched_call_replays_from_a_hip_graph():
