@@ -128,6 +128,10 @@ CASES = [
     (300, 450, 768, 600, "i8x3", False),
     (70, 40, 37, 300, "i8x3", False),
     (2, 5000, 1024, 300, "i8x3", False),  # the smallest group, widest supported d in one slot set
+    (101, 157, 1030, 300, "bf16x2", False),  # d_pad 1088: past the 16-byte-load alignment kernels
+    (101, 157, 8192, 200, "f32", False),     # the largest d the library accepts
+    (101, 157, 8192, 200, "bf16x2", False),
+    (157, 101, 8192, 200, "i8x3", False),
 ]
 
 
@@ -342,7 +346,7 @@ def test_batched_matches_oracle_per_pair():
                 _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
 
 
-@pytest.mark.parametrize("d", [64, 200])
+@pytest.mark.parametrize("d", [64, 200, 1030, 8192])
 def test_batched_storage_group_boundaries(d):
     """The Z storage is written in 32-row groups: the column-sum pass stores the
     groups that hold only Y rows or padding, the reflection the groups that hold
@@ -578,9 +582,11 @@ def test_tile_widths_do_not_change_results():
 def test_tuning_measures_both_widths():
     b = synth.batch_512_d768(limit=range(24))
     costs = hbt.tune_batched(_dev(b.Z), b.row_offset, b.n, b.m, np.full(24, 300))
-    (c512, c256), tuned = hbt.tune_get(768)
-    assert tuned and c512 > 0 and c256 > 0 and (c512, c256) == costs
-    print(f"tuned per-split costs at d=768: 512-wide {c512:.3e}, 256-wide {c256:.3e} ms", flush=True)
-    w = hbt.tile_widths([300, 2000], 768)
-    assert w[1] == (512 if c512 * 2048 <= c256 * 2048 else 256)
+    (c1024, c256), tuned = hbt.tune_get(768)
+    assert tuned and c1024 > 0 and c256 > 0 and (c1024, c256) == costs
+    print(f"tuned per-split costs at d=768: 1024-wide {c1024:.3e}, 256-wide {c256:.3e} ms", flush=True)
+    Bs = [1, 256, 300, 1024, 2000, 5000]
+    up = lambda B, w: -(-B // w) * w
+    want = [256 if c256 * up(B, 256) < c1024 * up(B, 1024) else 1024 for B in Bs]
+    assert list(hbt.tile_widths(Bs, 768)) == want
 
