@@ -305,7 +305,8 @@ def test_i8x3_rejects_point_to_centroid_route():
 # --------------------------------------------------------------------- point-to-centroid route
 
 @pytest.mark.parametrize("n,m,d,prec", [(37, 150, 100, "f32"), (150, 37, 100, "bf16x2"),
-                                        (300, 450, 768, "bf16x2"), (61, 70, 64, "f64")])
+                                        (300, 450, 768, "bf16x2"), (61, 70, 64, "f64"),
+                                        (101, 157, 8192, "f32")])
 def test_point_to_centroid_route_matches_oracle(n, m, d, prec):
     print(f"route 2 n={n} m={m} d={d} {prec}", flush=True)
     X, Y = _pair(n, m, d, kx=2.0, ky=2.1, seed=n + 3 * m + d)
