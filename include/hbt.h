@@ -29,7 +29,10 @@
  *     failures return HBT_ERR_DEVICE.  hbt_last_error() gives a thread-local
  *     message for the last non-OK return.  No C++ exception crosses the ABI.
  *   - Inputs must have unit-norm rows (the paper normalises every embedding,
- *     Sec. 3.1 Eq. 2).  They are not renormalised.
+ *     Sec. 3.1 Eq. 2).  They are not renormalised: every call tests each row
+ *     as it sums the columns, and a pair with a row whose norm is off by more
+ *     than 1e-4 gets the per-pair status HBT_ERR_NOT_UNIT (a pair whose mean
+ *     resultant length is outside (0, 1) gets HBT_ERR_DEGENERATE first).
  *
  * Random splits.  Split b (a global index, perm_offset <= b < perm_offset+B)
  * of pair `pair_index` under `seed` puts in group 1 the n items that come
@@ -63,7 +66,10 @@ typedef enum hbt_status {
     HBT_ERR_MASK = 6,         /* per pair: an explicit mask row does not hold n items */
     HBT_ERR_DEVICE = 7,       /* a HIP call failed */
     HBT_ERR_UNSUPPORTED = 8,  /* option not built */
-    HBT_ERR_INTERNAL = 9      /* per pair: split selection overflowed its bucket buffer */
+    HBT_ERR_INTERNAL = 9,     /* per pair: split selection overflowed its bucket buffer */
+    HBT_ERR_NOT_UNIT = 10     /* per pair: some row of X or Y has | |x| - 1 | > 1e-4 (or is
+                                 NaN); the test assumes l2-normalised rows (Sec. 3.1, Eq. 2),
+                                 and the pair's other results are not meaningful */
 } hbt_status;
 
 typedef enum hbt_precision {
@@ -192,6 +198,20 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                  const uint32_t* pair_index, int64_t d,
                                  const hbt_perm_params* common, hbt_result* results, void* ws,
                                  size_t ws_bytes, void* stream);
+
+/* hbt_recheck_band: the half-width *eps (host double) of the band around the
+ * decision threshold inside which a split's T_b, computed by `precision` and
+ * `stat_route`, is re-evaluated in FP64 (the count follows the FP64 statistic
+ * of Algorithm 1 Step 5 that way), for a split whose groups of n and m items
+ * have mean resultant lengths r1 and r2 (Sec. 3.1, "Dispersion proxy").  The
+ * band bounds |T_b - T_b(FP64)|: the storage error of the rows, which may add
+ * up coherently over repeated rows, the accumulation error of the product,
+ * and for stat_route 1 the FP32 point-to-centroid products.  Host function,
+ * nothing is enqueued.
+ * Errors: HBT_ERR_ARG (NULL eps, bad enum), HBT_ERR_SIZE (n, m < 1, d outside
+ * [1, HBT_MAX_D]). */
+hbt_status hbt_recheck_band(int32_t precision, int32_t stat_route, int32_t gd, int64_t n, int64_t m,
+                            int64_t d, double r1, double r2, double* eps);
 
 /* Stage timing, a profiling aid.  hbt_stage_timing(1) clears the record and
  * makes every later call record a pair of HIP events around each of its

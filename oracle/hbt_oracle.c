@@ -46,6 +46,7 @@
 #define ORC_ERR_SIZE 2
 #define ORC_ERR_DEGENERATE 5
 #define ORC_ERR_MASK 6
+#define ORC_ERR_NOT_UNIT 10
 
 #define ORC_GD_BANERJEE 0
 #define ORC_GD_IDENTITY 1
@@ -178,7 +179,9 @@ double oracle_mrl(const double* A, int64_t n, int64_t d) {
  *   info[0] = r_X   info[1] = r_Y   info[2] = T_obs   info[3] = h_identity
  *   info[4] = v.v   info[5] = tau   info[6] = f(r_X)  info[7] = f(r_Y)
  * mu_x, mu_y, v are d-vectors; Xp (n x d) receives the aligned X.
- * Returns ORC_OK or ORC_ERR_DEGENERATE (r outside (0, 1); H = I is used then).
+ * Returns ORC_OK, ORC_ERR_DEGENERATE (r outside (0, 1); H = I is used then)
+ * or ORC_ERR_NOT_UNIT (a row of X or Y is not l2-normalised as Sec. 3.1, Eq. 2
+ * assumes: | |x| - 1 | > 1e-4, or NaN; the computation goes on).
  * ---------------------------------------------------------------------- */
 int oracle_align(const double* X, int64_t n, const double* Y, int64_t m, int64_t d,
                  int align, int gd, double* Xp, double* mu_x, double* mu_y, double* v,
@@ -198,6 +201,13 @@ int oracle_align(const double* X, int64_t n, const double* Y, int64_t m, int64_t
     rx = sqrt(rx);
     ry = sqrt(ry);
     if (!(rx > 0.0 && rx < 1.0 && ry > 0.0 && ry < 1.0)) status = ORC_ERR_DEGENERATE;
+    /* precondition of Eq. 2: unit rows, | |x| - 1 | <= 1e-4 */
+    for (int64_t i = 0; i < n + m && status == ORC_OK; ++i) {
+        const double* row = i < n ? X + i * d : Y + (i - n) * d;
+        double ss = 0.0;
+        for (int64_t c = 0; c < d; ++c) ss += row[c] * row[c];
+        if (!(fabs(sqrt(ss) - 1.0) <= 1e-4)) status = ORC_ERR_NOT_UNIT;
+    }
     /* mean directions mu = x_bar / |x_bar| */
     for (int64_t c = 0; c < d; ++c) {
         mu_x[c] = rx > 0.0 ? xbar[c] / rx : 0.0;

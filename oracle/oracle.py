@@ -20,7 +20,7 @@ LIB = HERE / "libhbt_oracle.so"
 
 GD_BANERJEE, GD_IDENTITY = 0, 1
 ALT_GREATER, ALT_TWO_SIDED = 0, 1
-OK, ERR_ARG, ERR_SIZE, ERR_DEGENERATE, ERR_MASK = 0, 1, 2, 5, 6
+OK, ERR_ARG, ERR_SIZE, ERR_DEGENERATE, ERR_MASK, ERR_NOT_UNIT = 0, 1, 2, 5, 6, 10
 
 
 def build(force: bool = False) -> Path:

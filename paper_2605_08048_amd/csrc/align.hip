@@ -51,17 +51,56 @@ hipError_t zero(void* dst, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Unit-row check of the inputs (Sec. 3.1, Eq. 2: every embedding is
+// l2-normalised before the test): a row fails when | |x| - 1 | > 1e-4,
+// i.e. |x|^2 outside [(1 - 1e-4)^2, (1 + 1e-4)^2]; NaN fails too.  The
+// column-sum pass reads every row once, so it tests them there and writes one
+// flag per chunk (1 = some row of the chunk failed); the finalize step turns
+// a pair's flags into the status HBT_ERR_NOT_UNIT.
+__device__ __forceinline__ bool not_unit(double ss) {
+    return !(ss >= 0.99980001 && ss <= 1.00020001);
+}
+
+// Sum of x over the 64 lanes of a wave, returned to every lane: an inclusive
+// scan by DPP row shifts and row broadcasts (lane 63 ends with the total),
+// then a read of lane 63.
+__device__ __forceinline__ float wave_total_f32(float x) {
+    float v = x;
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // ---------------------------------------------------------------------------
 // column sums: one work-group = 64 columns x one chunk of rows, 4 row phases
 // ---------------------------------------------------------------------------
 template <typename Tin>
 __global__ __launch_bounds__(256) void k_colsum(const PairDesc* __restrict__ pairs,
                                                 int npairs, int d,
-                                                double* __restrict__ partial) {
+                                                double* __restrict__ partial,
+                                                int32_t* __restrict__ chunk_bad) {
     const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
     const PairDesc pd = pairs[ch.pair];
     const Tin* base = (const Tin*)(ch.side ? pd.Y : pd.X);
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    if (blockIdx.y == 0) {  // the first column tile also tests whole rows (wave ty: rows ty, ty + 4, ...)
+        bool bad = false;
+        for (int r = ch.r0 + ty; r < ch.r1; r += 4) {
+            double ss = 0.0;
+            for (int cc = tx; cc < d; cc += 64) {
+                const double a = (double)base[(int64_t)r * d + cc];
+                ss += a * a;
+            }
+            for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+            bad |= not_unit(ss);
+        }
+        bad = __syncthreads_or(bad);
+        if (threadIdx.x == 0) chunk_bad[blockIdx.x] = bad ? 1 : 0;
+    }
     const int c = blockIdx.y * 64 + tx;
     double s0 = 0.0, s1 = 0.0;
     if (c < d) {
@@ -82,13 +121,13 @@ __global__ __launch_bounds__(256) void k_colsum(const PairDesc* __restrict__ pai
 }
 
 hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, int npairs,
-                         int nchunks, int d, double* partial, hipStream_t s) {
+                         int nchunks, int d, double* partial, int32_t* chunk_bad, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     dim3 grid(nchunks, (d + 63) / 64);
     if (input_dtype == HBT_IN_F64)
-        hipLaunchKernelGGL(k_colsum<double>, grid, dim3(256), 0, s, pairs, npairs, d, partial);
+        hipLaunchKernelGGL(k_colsum<double>, grid, dim3(256), 0, s, pairs, npairs, d, partial, chunk_bad);
     else
-        hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, s, pairs, npairs, d, partial);
+        hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, s, pairs, npairs, d, partial, chunk_bad);
     return hipGetLastError();
 }
 
@@ -126,7 +165,7 @@ __device__ __forceinline__ void load_cols(float (&x)[J][4], const float* row, in
 template <int J>
 __device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc& pd, int d,
                                               double* __restrict__ partial_row,
-                                              double (*red)[256 * J]) {
+                                              double (*red)[256 * J], int32_t* chunk_bad) {
     const float* base = (const float*)(ch.side ? pd.Y : pd.X);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double acc[J][4];
@@ -134,6 +173,7 @@ __device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc
     for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[j][e] = 0.0;
+    bool bad = false;
     // rows r, r + 4, r + 8, r + 12 per step, all loads issued first (rows past
     // the chunk read zero, see load_cols); the additions keep the row order
     for (int r = ch.r0 + wave; r < ch.r1; r += 16) {
@@ -151,22 +191,28 @@ __device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q) {
+            if (r + 4 * q >= ch.r1) continue;  // wave-uniform: nothing added past the chunk
+            float ss = 0.0f;
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                if (r + 4 * q >= ch.r1) continue;  // wave-uniform: nothing added past the chunk
                 acc[j][0] += (double)x[q][j].x;
                 acc[j][1] += (double)x[q][j].y;
                 acc[j][2] += (double)x[q][j].z;
                 acc[j][3] += (double)x[q][j].w;
+                ss += x[q][j].x * x[q][j].x + x[q][j].y * x[q][j].y + x[q][j].z * x[q][j].z +
+                      x[q][j].w * x[q][j].w;
             }
+            bad |= not_unit((double)wave_total_f32(ss));
+        }
     }
     if (wave > 0)
 #pragma unroll
         for (int j = 0; j < J; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) red[wave - 1][4 * (lane + 64 * j) + e] = acc[j][e];
-    __syncthreads();
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) chunk_bad[blockIdx.x] = bad ? 1 : 0;
     if (wave == 0)
 #pragma unroll
         for (int j = 0; j < J; ++j)
@@ -180,10 +226,11 @@ __device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc
 template <int J>
 __global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pairs,
                                                  int npairs, int d,
-                                                 double* __restrict__ partial) {
+                                                 double* __restrict__ partial,
+                                                 int32_t* __restrict__ chunk_bad) {
     __shared__ double red[3][256 * J];
     const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
-    colsum4_chunk<J>(ch, pairs[ch.pair], d, partial + (int64_t)blockIdx.x * d, red);
+    colsum4_chunk<J>(ch, pairs[ch.pair], d, partial + (int64_t)blockIdx.x * d, red, chunk_bad);
 }
 
 bool vector_rows_ok(int input_dtype, int d, int d_pad) {
@@ -191,15 +238,15 @@ bool vector_rows_ok(int input_dtype, int d, int d_pad) {
 }
 
 hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int d,
-                             int d_pad, double* partial, hipStream_t s) {
+                             int d_pad, double* partial, int32_t* chunk_bad, hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     const int J = (d_pad + 255) / 256;
     const dim3 g(nchunks), b(256);
     switch (J) {
-        case 1: hipLaunchKernelGGL(k_colsum4<1>, g, b, 0, s, pairs, npairs, d, partial); break;
-        case 2: hipLaunchKernelGGL(k_colsum4<2>, g, b, 0, s, pairs, npairs, d, partial); break;
-        case 3: hipLaunchKernelGGL(k_colsum4<3>, g, b, 0, s, pairs, npairs, d, partial); break;
-        case 4: hipLaunchKernelGGL(k_colsum4<4>, g, b, 0, s, pairs, npairs, d, partial); break;
+        case 1: hipLaunchKernelGGL(k_colsum4<1>, g, b, 0, s, pairs, npairs, d, partial, chunk_bad); break;
+        case 2: hipLaunchKernelGGL(k_colsum4<2>, g, b, 0, s, pairs, npairs, d, partial, chunk_bad); break;
+        case 3: hipLaunchKernelGGL(k_colsum4<3>, g, b, 0, s, pairs, npairs, d, partial, chunk_bad); break;
+        case 4: hipLaunchKernelGGL(k_colsum4<4>, g, b, 0, s, pairs, npairs, d, partial, chunk_bad); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -223,7 +270,8 @@ __device__ double block_sum(double x, double* red) {
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ pairs,
-                                                  const double* __restrict__ partial, int d,
+                                                  const double* __restrict__ partial,
+                                                  const int32_t* __restrict__ chunk_bad, int d,
                                                   int d_pad, int align, int gd, double* sxy,
                                                   PairState* st, double* v, double* t64,
                                                   float* t32, PairCount* cnt, hbt_result* res) {
@@ -250,6 +298,9 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
         for (; k < k1; ++k) acc += partial[(int64_t)k * d + c];
         return acc;
     };
+    int bad = 0;
+    for (int k = pd.cx0 + threadIdx.x; k < pd.cy1; k += 256) bad |= chunk_bad[k];
+    bad = __syncthreads_or(bad);
     double ssx = 0.0, ssy = 0.0;
     for (int c = threadIdx.x; c < d_pad; c += 256) {
         double a = 0.0, b = 0.0;
@@ -301,7 +352,9 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
         q.f_y = fy;
         q._pad = 0.0;
         q.identity = identity;
-        q.status = (r_x > 0.0 && r_x < 1.0 && r_y > 0.0 && r_y < 1.0) ? HBT_OK : HBT_ERR_DEGENERATE;
+        q.status = (r_x > 0.0 && r_x < 1.0 && r_y > 0.0 && r_y < 1.0)
+                       ? (bad ? HBT_ERR_NOT_UNIT : HBT_OK)
+                       : HBT_ERR_DEGENERATE;
         q._pad2[0] = q._pad2[1] = 0;
         st[p] = q;
         cnt[p].count = 0;
@@ -328,11 +381,12 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
     }
 }
 
-hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* partial, int d,
+hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* partial,
+                           const int32_t* chunk_bad, int d,
                            int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
                            double* t64, float* t32, PairCount* cnt, hbt_result* res,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(npairs), dim3(256), 0, s, pairs, partial, d, d_pad, align,
+    hipLaunchKernelGGL(k_finalize, dim3(npairs), dim3(256), 0, s, pairs, partial, chunk_bad, d, d_pad, align,
                        gd, sxy, st, v, t64, t32, cnt, res);
     return hipGetLastError();
 }
@@ -681,14 +735,15 @@ __global__ __launch_bounds__(256) void k_colsum_store4(const PairDesc* __restric
                                                        int npairs, int d, int d_pad,
                                                        double* __restrict__ partial, void* zstore,
                                                        int64_t zplane_elems,
-                                                       float* __restrict__ z32) {
+                                                       float* __restrict__ z32,
+                                                       int32_t* __restrict__ chunk_bad) {
     __shared__ double red[4][256 * J];
     const int c = blockIdx.x;
     const SumChunk ch = chunk_of(pairs, npairs, c);
     const PairDesc pd = pairs[ch.pair];
     double* prow = partial + (int64_t)c * d;
     if (!ch.side) {  // work-group-uniform
-        colsum4_chunk<J>(ch, pd, d, prow, red);
+        colsum4_chunk<J>(ch, pd, d, prow, red, chunk_bad);
         return;
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -713,6 +768,18 @@ __global__ __launch_bounds__(256) void k_colsum_store4(const PairDesc* __restric
             for (int r = 0; r < 8; ++r) t += (double)x[r][j][e];
             red[wave][col(j, e)] = t;
         }
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = row_of(r);
+        if (i < n || i >= N) continue;  // wave-uniform: only this group's Y rows
+        float ss = 0.0f;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ss += x[r][j][e] * x[r][j][e];
+        bad |= not_unit((double)wave_total_f32(ss));
+    }
     // the stores convert the rows to FP64 again instead of keeping the sums'
     // FP64 copies alive (twice the registers)
 #pragma unroll
@@ -731,20 +798,22 @@ __global__ __launch_bounds__(256) void k_colsum_store4(const PairDesc* __restric
         store_octet<PREC, J>(x, k0, v0, pd.zrow0 / 8 + g0 / 8 + wave, pd.zrow0, row_of, wave, d_pad,
                              zstore, zplane_elems, z32);
     }
-    __syncthreads();
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) chunk_bad[c] = bad ? 1 : 0;
     for (int cc = threadIdx.x; cc < d; cc += 256)
         prow[cc] = (red[0][cc] + red[1][cc]) + (red[2][cc] + red[3][cc]);
 }
 
 hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npairs, int nchunks,
                                    int d, int d_pad, double* partial, void* zstore,
-                                   int64_t zplane_elems, float* z32, hipStream_t s) {
+                                   int64_t zplane_elems, float* z32, int32_t* chunk_bad,
+                                   hipStream_t s) {
     if (nchunks <= 0) return hipSuccess;
     const int J = (d_pad + 255) / 256;
     const dim3 g(nchunks), b(256);
 #define HBT_C4(PR, JJ)                                                                         \
     hipLaunchKernelGGL((k_colsum_store4<PR, JJ>), g, b, 0, s, pairs, npairs, d, d_pad, partial, \
-                       zstore, zplane_elems, z32)
+                       zstore, zplane_elems, z32, chunk_bad)
 #define HBT_C4J(PR)                            \
     switch (J) {                               \
         case 1: HBT_C4(PR, 1); break;          \

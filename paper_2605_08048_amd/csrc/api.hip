@@ -74,28 +74,34 @@ constexpr int64_t kAutoBlock = 32768;  // splits per block when block_perms == 0
 
 int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
 
-// Recheck band.  A split is re-evaluated in FP64 when its T_b lies within
-//   (e_acc + e_store / sqrt(min(n, m) * d)) * (sens(r1^2) + sens(r2^2))
-// of the threshold, sens = |s d/ds log g_d(sqrt s)|: the relative error of
-// the squared group-sum norms times the sensitivity of log g_d.  e_acc covers
-// FP32 accumulation, e_store the BF16 hi+lo storage error, which averages
-// over the k items and d columns of the smaller group.  Measured worst cases
-// on MI355X (35 shapes, n and m from 2 to 5000, d = 64 ... 1024, r up to
-// 0.997): 2.5e-7 (F32), 1.6e-6 (split BF16, n = 2, d = 64); the constants
-// below are >= 9x those.  The int8 planes hold z to an absolute 2^-21
-// (split BF16: relative 2^-17, i.e. about 2^-17 / sqrt(d) absolute for unit
-// rows), so their storage term is the BF16 one times 2^-4 sqrt(d); their sums
-// are exact and the epilogue is FP64.
-struct Band {
-    double e_acc, e_store;
-};
-Band precision_band(int precision, int d) {
+// Recheck band of each precision (recheck_eps; terms in hbt_internal.h).
+// Storage bounds per coordinate of a unit row, scaled to the RMS coordinate
+// 1/sqrt(d) where the format is relative: FP32 2^-24, split BF16 2^-16 (hi
+// rounds to 8 significant bits, lo the remainder to 8 more), int8 digit
+// planes an absolute 2^-21 (z rounded to a multiple of 2^-20).  e_acc is the
+// measured FP32 accumulation error (worst 2.5e-7 for FP32, 1.6e-6 for split
+// BF16 over 35 shapes with n, m from 2 to 5000, d = 64 ... 1024, r up to
+// 0.997); the int8 sums are exact.  The safety factors keep the worst error
+// of an exact emulation of the stored rows (duplicated rows repeated up to
+// 1000 times, clouds with r from 0.02 to 1, a group of 2) below a quarter of
+// the band.  The point-to-centroid route works in FP32 whatever the first
+// product's precision (its rows are an FP32 copy, its centroids floats), so
+// its band is at least the FP32 one, plus the dot-product term.
+RecheckBand precision_band(int precision, int d, bool route2) {
+    const double rd = 1.0 / std::sqrt((double)d);
+    RecheckBand b;
     switch (precision) {
-        case HBT_F64: return Band{1e-12, 0.0};
-        case HBT_F32: return Band{4e-6, 0.0};
-        case HBT_I8X3: return Band{1e-10, 16.0 * 2.3 / 2097152.0 * std::sqrt((double)d)};
-        default: return Band{4e-6, 16.0 * 2.3 / 131072.0};
+        case HBT_F64: b = RecheckBand{1e-12, 0x1p-53 * rd, 4.0, 0.0}; break;
+        case HBT_F32: b = RecheckBand{4e-6, 0x1p-24 * rd, 4.0, 0.0}; break;
+        case HBT_I8X3: b = RecheckBand{1e-10, 0x1p-21, 12.0, 0.0}; break;
+        default: b = RecheckBand{4e-6, 0x1p-16 * rd, 4.0, 0.0}; break;
     }
+    if (route2) {
+        b.e_acc = std::max(b.e_acc, 4e-6);
+        b.e_row = std::max(b.e_row, 0x1p-24 * rd);
+        b.e_q = 8.0 * 0x1p-24;
+    }
+    return b;
 }
 
 size_t zstore_bytes(int precision, int64_t rows, int64_t d_pad) {
@@ -126,6 +132,7 @@ struct Workspace {
     GemmGroup* groups;
     int64_t* Btot;
     double* partial_sum;
+    int32_t* chunk_bad;  // per column-sum chunk: a row is not a unit vector
     double* sxy;
     PairState* st;
     double* v;
@@ -186,6 +193,7 @@ Workspace carve(const Plan& P, void* ws) {
     w.groups = c.take<GemmGroup>(std::max<size_t>(P.groups.size(), 1));
     w.Btot = c.take<int64_t>(np);
     w.partial_sum = c.take<double>(std::max<size_t>(P.chunks.size(), 1) * P.d);
+    w.chunk_bad = c.take<int32_t>(std::max<size_t>(P.chunks.size(), 1));
     w.sxy = c.take<double>((size_t)np * 2 * P.d_pad);
     w.st = c.take<PairState>(np);
     w.v = c.take<double>((size_t)np * P.d_pad);
@@ -417,13 +425,15 @@ hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd
     StageTimer t(HBT_STAGE_ALIGN, s);
     if (vector_rows(P) && P.need_store)
         HIP_TRY(launch_colsum_store_vec(P.precision, w.pairs, P.npairs, (int)P.chunks.size(), P.d,
-                                        P.d_pad, w.partial_sum, w.zstore, P.zrows * P.d_pad, w.z32, s));
+                                        P.d_pad, w.partial_sum, w.zstore, P.zrows * P.d_pad, w.z32,
+                                        w.chunk_bad, s));
     else if (vector_rows(P))
-        HIP_TRY(launch_colsum_vec(w.pairs, P.npairs, (int)P.chunks.size(), P.d, P.d_pad, w.partial_sum, s));
+        HIP_TRY(launch_colsum_vec(w.pairs, P.npairs, (int)P.chunks.size(), P.d, P.d_pad, w.partial_sum,
+                                  w.chunk_bad, s));
     else
         HIP_TRY(launch_colsum(P.input_dtype, w.pairs, P.npairs, (int)P.chunks.size(), P.d,
-                              w.partial_sum, s));
-    HIP_TRY(launch_finalize(w.pairs, P.npairs, w.partial_sum, P.d, P.d_pad, align, gd, w.sxy, w.st,
+                              w.partial_sum, w.chunk_bad, s));
+    HIP_TRY(launch_finalize(w.pairs, P.npairs, w.partial_sum, w.chunk_bad, P.d, P.d_pad, align, gd, w.sxy, w.st,
                             w.v, w.t64, w.t32, w.cnt, res, s));
     return HBT_OK;
 }
@@ -488,6 +498,7 @@ const char* hbt_status_string(int32_t status) {
         case HBT_ERR_DEVICE: return "HIP error";
         case HBT_ERR_UNSUPPORTED: return "unsupported option";
         case HBT_ERR_INTERNAL: return "split selection bucket overflow";
+        case HBT_ERR_NOT_UNIT: return "a row is not a unit vector (| |x| - 1 | > 1e-4)";
         default: return "unknown status";
     }
 }
@@ -606,7 +617,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     const int N = (int)(prm->n + prm->m);
     const int W = (N + 31) / 32;
 
-    const Band band = precision_band(P.precision, P.d);
+    const RecheckBand band = precision_band(P.precision, P.d, P.route2);
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
     const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
     // the tables of split block b0 (nb splits) and its tile width
@@ -707,7 +718,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
                             P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot,
                             P.block_rows, P.d, prm->gd,
-                            prm->alternative, band.e_acc, band.e_store, no_recheck,
+                            prm->alternative, band, no_recheck,
                             T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8, w.tw,
                             w.cnt, w.flags, w.nflag, s)); }
         if (!no_recheck) {
@@ -861,8 +872,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
     { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot,
                         P.block_rows, P.d, common->gd,
-                        common->alternative, precision_band(P.precision, P.d).e_acc,
-                        precision_band(P.precision, P.d).e_store, no_recheck, nullptr,
+                        common->alternative, precision_band(P.precision, P.d, false), no_recheck, nullptr,
                         false, w.tw, w.cnt, w.flags, w.nflag, s)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
@@ -979,6 +989,20 @@ hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t*
         if (B[p] < 1) return fail(HBT_ERR_SIZE, "B[%lld] = %lld", (long long)p, (long long)B[p]);
         widths[p] = choose_width(B[p], tc);
     }
+    return HBT_OK;
+}
+
+hbt_status hbt_recheck_band(int32_t precision, int32_t stat_route, int32_t gd, int64_t n, int64_t m,
+                            int64_t d, double r1, double r2, double* eps) {
+    g_err.clear();
+    if (!eps) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (precision < HBT_F64 || precision > HBT_I8X3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (stat_route != 0 && stat_route != 1) return fail(HBT_ERR_ARG, "unknown stat_route %d", stat_route);
+    if (gd != HBT_GD_BANERJEE && gd != HBT_GD_IDENTITY) return fail(HBT_ERR_ARG, "unknown g_d %d", gd);
+    if (n < 1 || m < 1 || d < 1 || d > HBT_MAX_D)
+        return fail(HBT_ERR_SIZE, "n %lld, m %lld, d %lld", (long long)n, (long long)m, (long long)d);
+    *eps = recheck_eps(precision_band(precision, (int)d, stat_route == 1), (double)n, (double)m,
+                       (double)d, r1, r2, gd);
     return HBT_OK;
 }
 

@@ -235,7 +235,7 @@ __device__ __forceinline__ void i8_digits(double z, uint32_t& q0, uint32_t& q1, 
 }
 
 // log g_d(r) of Sec. 3.1 ("Dispersion proxy"), in FP64.
-__device__ __forceinline__ double log_g(double r, double d, int gd) {
+__host__ __device__ inline double log_g(double r, double d, int gd) {
     if (gd == HBT_GD_IDENTITY) return log(r);
     const double rr = r * r;
     return log(r * (d - rr) / ((1.0 - r) * (1.0 + r)));
@@ -243,9 +243,51 @@ __device__ __forceinline__ double log_g(double r, double d, int gd) {
 
 // |s * d/ds log g_d(sqrt(s))| for s = r^2: the factor by which a relative
 // error of s moves log g_d.
-__device__ __forceinline__ double log_g_sensitivity(double s, double d, int gd) {
+__host__ __device__ inline double log_g_sensitivity(double s, double d, int gd) {
     if (gd == HBT_GD_IDENTITY) return 0.5;
     return fabs(0.5 - s / (d - s) + s / (1.0 - s));
+}
+
+// Recheck band: how far a reduced-precision T_b may lie from the FP64 value.
+// The product runs over the smaller group (k = min(n, m) items) and the
+// larger group's sum is t - sigma_small with an FP64 t, so both squared norms
+// carry the one error vector E of sigma_small:
+//   |sigma_g + E|^2 - |sigma_g|^2 = 2 sigma_g . E + |E|^2   (group g = 1, 2).
+// Per coordinate the stored rows are off by at most e_row (a unit row's RMS
+// coordinate scale times the storage format's bound).  Rows may repeat (the
+// same sentence twice gives the same vectors), so the k errors in E can add
+// coherently: |E| is not assumed to shrink as 1/sqrt(k).  Across the d
+// coordinates the rounding errors are taken as unrelated to the direction of
+// sigma_g, which gives, relative to |sigma_g|^2 = (n_g r_g)^2,
+//   rel_g = e_acc + a_g / r_g + a_g^2 d / r_g^2,   a_g = s_store e_row k / n_g,
+// with e_acc the accumulation error of the product (relative to the sums).
+// The point-to-centroid route adds the FP32 error of its K = d dot products
+// z_i . sigma: up to e_q sqrt(d) |sigma_small| each, summed over k (small
+// group) or the N - k others (large group).  A relative error rel of r^2
+// moves log g_d(r) by rel * sensitivity(r^2).
+struct RecheckBand {
+    double e_acc;    // relative accumulation error of the group sums
+    double e_row;    // per-coordinate storage error scale of a unit row
+    double s_store;  // safety factor on the storage term
+    double e_q;      // point-to-centroid dot-product error (0: route 0)
+};
+__host__ __device__ inline double recheck_eps(const RecheckBand& b, double n, double m, double d,
+                                              double r1, double r2, int gd) {
+    const double k = n < m ? n : m;
+    const double a1 = b.s_store * b.e_row * (k / n), a2 = b.s_store * b.e_row * (k / m);
+    double rel1 = b.e_acc + a1 / r1 + a1 * a1 * d / (r1 * r1);
+    double rel2 = b.e_acc + a2 / r2 + a2 * a2 * d / (r2 * r2);
+    if (b.e_q > 0.0) {
+        const bool small1 = n <= m;
+        const double rs = small1 ? r1 : r2, rl = small1 ? r2 : r1;
+        const double ql = b.e_q * sqrt(d) * (k / (n + m - k)) * rs / (rl * rl);
+        const double qs = b.e_q * sqrt(d) / rs;
+        rel1 += small1 ? qs : ql;
+        rel2 += small1 ? ql : qs;
+    }
+    const double fs = fabs(log_g(r1, d, gd)) + fabs(log_g(r2, d, gd));
+    return rel1 * log_g_sensitivity(r1 * r1, d, gd) + rel2 * log_g_sensitivity(r2 * r2, d, gd) +
+           1e-13 * fs;
 }
 
 // Binary search: last index k in [0, count) with key(k) <= x, for an

@@ -20,11 +20,14 @@ hipError_t zero(void* dst, size_t bytes, hipStream_t s);
 
 // --- alignment (Algorithm 1, Steps 1-4) ---------------------------------
 // FP64 column sums of every chunk: partial[chunk][d].
+// chunk_bad[chunk] = 1 when a row of the chunk is not a unit vector
+// (| |x| - 1 | > 1e-4 or NaN), else 0; every launcher below writes it.
 hipError_t launch_colsum(int input_dtype, const PairDesc* pairs, int npairs,
-                         int nchunks, int d, double* partial, hipStream_t s);
+                         int nchunks, int d, double* partial, int32_t* chunk_bad, hipStream_t s);
 // Per pair: sums, r, mean directions, v, v.v, identity, T_obs, tau, the pooled
 // total t (FP64 and FP32), the hbt_result header.
-hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* partial, int d,
+hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* partial,
+                           const int32_t* chunk_bad, int d,
                            int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
                            double* t64, float* t32, PairCount* cnt, hbt_result* res,
                            hipStream_t s);
@@ -34,13 +37,14 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 // caller also checks that every X, Y is 16-byte aligned).
 bool vector_rows_ok(int input_dtype, int d, int d_pad);
 hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int d,
-                             int d_pad, double* partial, hipStream_t s);
+                             int d_pad, double* partial, int32_t* chunk_bad, hipStream_t s);
 // Column sums plus the storage of the 32-row groups that hold no X rows (the
 // 16-byte path of the group-sum calls); launch_reflect_vec then takes the
 // x_octets(n) octets of each pair (total_octets = their sum over pairs).
 hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npairs, int nchunks,
                                    int d, int d_pad, double* partial, void* zstore,
-                                   int64_t zplane_elems, float* z32, hipStream_t s);
+                                   int64_t zplane_elems, float* z32, int32_t* chunk_bad,
+                                   hipStream_t s);
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
                               int64_t total_octets, const PairState* st, const double* v, int d,
                               int d_pad, double* coef, void* zstore, int64_t zplane_elems,
@@ -114,7 +118,7 @@ hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const Gem
 // --- statistic, exceedances, recheck, p ---------------------------------
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
-                       int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
+                       int alternative, const RecheckBand& band, int no_recheck, void* T_out,
                        bool T_f64, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad

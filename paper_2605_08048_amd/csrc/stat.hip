@@ -15,8 +15,8 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               int64_t rows, const PairState* __restrict__ st,
                                               const double* __restrict__ partial, int nslot,
                                               int64_t prow, int d,
-                                              int gd, int alternative, double e_acc,
-                                              double e_store, int no_recheck, void* T_out,
+                                              int gd, int alternative, RecheckBand band,
+                                              int no_recheck, void* T_out,
                                               bool T_f64, double* __restrict__ Tw,
                                               PairCount* cnt, uint32_t* flags, uint32_t* nflag) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -50,10 +50,7 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         const bool two = alternative == HBT_ALT_TWO_SIDED;
         const double val = two ? fabs(T) : T;
         const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
-        const double fs = fabs(log_g(r1, dd, gd)) + fabs(log_g(r2, dd, gd));
-        const double e_rel = e_acc + e_store * rsqrt((n < m ? n : m) * dd);
-        const double eps = e_rel * (log_g_sensitivity(r1 * r1, dd, gd) +
-                                    log_g_sensitivity(r2 * r2, dd, gd)) + 1e-13 * fs;
+        const double eps = recheck_eps(band, n, m, dd, r1, r2, gd);
         const bool nan = T != T;
         const bool border = !no_recheck && !nan && fabs(val - thr) <= eps;
         if (border) {
@@ -76,12 +73,12 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
 
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
-                       int alternative, double e_acc, double e_store, int no_recheck, void* T_out,
+                       int alternative, const RecheckBand& band, int no_recheck, void* T_out,
                        bool T_f64, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
                        hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
-                       npairs, rows, st, partial, nslot, prow, d, gd, alternative, e_acc, e_store,
+                       npairs, rows, st, partial, nslot, prow, d, gd, alternative, band,
                        no_recheck,
                        T_out, T_f64, Tw, cnt, flags, nflag);
     return hipGetLastError();

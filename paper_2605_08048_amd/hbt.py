@@ -18,7 +18,7 @@ import numpy as np
 LIB_PATH = Path(os.environ.get("HBT_LIBRARY") or Path(__file__).resolve().parent / "libhbt.so")
 
 OK, ERR_ARG, ERR_SIZE, ERR_DTYPE, ERR_WORKSPACE, ERR_DEGENERATE, ERR_MASK, ERR_DEVICE, \
-    ERR_UNSUPPORTED, ERR_INTERNAL = range(10)
+    ERR_UNSUPPORTED, ERR_INTERNAL, ERR_NOT_UNIT = range(11)
 PRECISION = {"f64": 0, "f32": 1, "bf16x2": 2, "i8x3": 3}
 DTYPE = {"f32": 0, "f64": 1}
 GD = {"banerjee": 0, "identity": 1}
@@ -96,7 +96,8 @@ def lib():
         L.hbt_tune_get.argtypes = [i64, P, P]
         L.hbt_tune_set.argtypes = [i64, P]
         L.hbt_tile_widths.argtypes = [i64, P, i64, P]
-        for f in ["hbt_tune_batched", "hbt_tune_get", "hbt_tune_set", "hbt_tile_widths"]:
+        L.hbt_recheck_band.argtypes = [i32, i32, i32, i64, i64, i64, dbl, dbl, P]
+        for f in ["hbt_tune_batched", "hbt_tune_get", "hbt_tune_set", "hbt_tile_widths", "hbt_recheck_band"]:
             getattr(L, f).restype = i32
         L.hbt_budget_features.argtypes = [i64, P, i64, i32, P, P]
         L.hbt_feature_norm.argtypes = [i64, P, P, P]
@@ -274,6 +275,21 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     if mo is not None:
         r["masks"] = mo.cpu().numpy().view(np.uint32)
     return r
+
+
+def recheck_band(precision, n, m, d, r1, r2, *, stat_route=0, gd="banerjee"):
+    """Half-width of the FP64 recheck band for splits with permuted mean
+    resultant lengths r1, r2 (arrays or scalars); a host call of the library."""
+    L = lib()
+    r1 = np.broadcast_to(np.asarray(r1, dtype=np.float64), np.broadcast(r1, r2).shape)
+    r2 = np.broadcast_to(np.asarray(r2, dtype=np.float64), r1.shape)
+    out = np.empty(r1.shape, dtype=np.float64)
+    e = C.c_double()
+    for idx in np.ndindex(r1.shape):
+        _check(L.hbt_recheck_band(PRECISION[precision], stat_route, GD[gd], n, m, d,
+                                  float(r1[idx]), float(r2[idx]), C.byref(e)))
+        out[idx] = e.value
+    return out if out.shape else float(out)
 
 
 def batched_workspace_size(row_offset, n, m, B, d, *, precision="bf16x2", input_dtype="f32"):

@@ -41,7 +41,7 @@ def test_struct_sizes_match_header():
 
 def test_status_strings():
     L = hbt.lib()
-    for s in range(10):
+    for s in range(11):
         assert L.hbt_status_string(s)
     assert L.hbt_status_string(99) == b"unknown status"
 

@@ -198,6 +198,28 @@ def test_exhaustive_70_splits_match_brute_force_and_scipy(seed):
     assert abs(res.pvalue - ex["p"]) < 1e-12
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_exhaustive_two_sided_p_matches_scipy_when_null_is_symmetric(seed):
+    """Two-sided rule (|T_b| >= |T_obs|; the paper reports two-sided values
+    without a definition).  With n = m every split's complement is also a
+    split and gives -T_b, so the exact null distribution is symmetric and the
+    rule must equal scipy's two-sided exact p (twice the smaller one-sided
+    p).  A dropped absolute value or a wrong sign of the threshold fails."""
+    X, Y = _pair(4, 4, 5, kx=1.5 + 0.5 * seed, ky=2.5, angle=60.0, seed=30 + seed)
+    ex = O.exhaustive(X, Y, alternative=O.ALT_TWO_SIDED)
+    a = O.align(X, Y)
+    Z = np.vstack([a["Xp"], Y])
+    d = 5
+    f = lambda r: np.log(r * (d - r * r) / (1 - r * r))
+    stat = lambda i, j: f(np.linalg.norm(Z[np.asarray(j, int)].mean(0))) - f(np.linalg.norm(Z[np.asarray(i, int)].mean(0)))
+    res = stats.permutation_test((np.arange(4), np.arange(4, 8)), stat, permutation_type="independent",
+                                 n_resamples=np.inf, alternative="two-sided", vectorized=False)
+    assert abs(res.pvalue - ex["p"]) < 1e-12, (res.pvalue, ex["p"])
+    # the swapped problem reflects with the same H and has T_obs -> -T_obs
+    sw = O.exhaustive(Y, X, alternative=O.ALT_TWO_SIDED)
+    assert sw["count"] == ex["count"]
+
+
 def test_monte_carlo_p_converges_to_exact_p():
     X, Y = _pair(5, 5, 6, kx=2.0, ky=2.5, angle=50.0, seed=21)
     ex = O.exhaustive(X, Y)
@@ -239,6 +261,23 @@ def test_two_sided_counts_both_tails():
     g = O.perm_test(X, Y, B=400, seed=1, want_T=True)
     t = O.perm_test(X, Y, B=400, seed=1, alternative=O.ALT_TWO_SIDED)
     assert t["count"] == int(np.sum(np.abs(g["T"]) >= abs(g["t_obs"]) - g["tau"]))
+
+
+def test_rows_that_are_not_unit_vectors_are_flagged():
+    """Eq. 2 normalises every embedding; a row off by more than 1e-4 in norm
+    (or NaN) is reported, one off by 5e-5 is not."""
+    X, Y = _pair(30, 20, 8, seed=26)
+    assert O.align(X, Y)["status"] == O.OK
+    for scale, status in [(1 + 2e-4, O.ERR_NOT_UNIT), (1 - 2e-4, O.ERR_NOT_UNIT), (1 + 5e-5, O.OK)]:
+        Xs = X.copy()
+        Xs[7] *= scale
+        assert O.align(Xs, Y)["status"] == status
+        Ys = Y.copy()
+        Ys[19] *= scale
+        assert O.perm_test(X, Ys, B=10)["status"] == status
+    Xn = X.copy()
+    Xn[0, 3] = np.nan
+    assert O.align(Xn, Y)["status"] in (O.ERR_NOT_UNIT, O.ERR_DEGENERATE)
 
 
 def test_degenerate_single_direction_is_flagged():
