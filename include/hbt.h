@@ -213,6 +213,24 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
 hbt_status hbt_recheck_band(int32_t precision, int32_t stat_route, int32_t gd, int64_t n, int64_t m,
                             int64_t d, double r1, double r2, double* eps);
 
+/* hbt_perm_test_static: hbt_perm_test for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as hbt_perm_test
+ * without ws / ws_bytes: the workspace is a static device array inside the
+ * library, HBT_STATIC_SCRATCH_BYTES per device (64 MiB; enough for one pair
+ * of n + m = 5000 at d = 1024 with B = 20,000), held by every device the
+ * library runs on until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); the first call on a
+ * device looks up that device's scratch address.  Calls on one device share
+ * the scratch: calls that overlap in time on one device (two streams, two
+ * host threads) race and must be serialised by the caller; each call
+ * initialises what it reads from the scratch.
+ * Errors: as hbt_perm_test; HBT_ERR_WORKSPACE when the test needs more than
+ * HBT_STATIC_SCRATCH_BYTES (hbt_perm_test_workspace_size tells). */
+#define HBT_STATIC_SCRATCH_BYTES (64u << 20)
+hbt_status hbt_perm_test_static(const void* X, const void* Y, const hbt_perm_params* prm,
+                                hbt_result* result, float* T_out, uint32_t* mask_out, void* stream);
+
 /* Stage timing, a profiling aid.  hbt_stage_timing(1) clears the record and
  * makes every later call record a pair of HIP events around each of its
  * stages on its stream; hbt_stage_timing(0) stops recording.

@@ -14,6 +14,13 @@
 
 #include "hbt_launch.h"
 
+// Device scratch of hbt_perm_test_static: the workspace of a single-pair test
+// for callers that cannot allocate.  Each device the library runs on holds its
+// own copy until the process ends.  Host code must never pass this name to a
+// kernel or a copy (in host code it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+__device__ __align__(256) unsigned char scratch[HBT_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace hbt;
@@ -1063,6 +1070,37 @@ hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* ro
         cost[k] = q < 2 ? c : std::min(cost[k], c);
     }
     return hbt_tune_set(d, cost);
+}
+
+// hbt_perm_test on the library's own scratch.  The scratch address of each
+// device is looked up once, with that device current, and kept.
+hbt_status hbt_perm_test_static(const void* X, const void* Y, const hbt_perm_params* prm,
+                                hbt_result* result, float* T_out, uint32_t* mask_out, void* stream) {
+    static std::mutex mu;
+    static void* ptr[64] = {};
+    g_err.clear();
+    if (!prm) return fail(HBT_ERR_ARG, "NULL params");
+    if (!X || !Y || !result) return fail(HBT_ERR_ARG, "NULL X, Y or result");
+    hbt_status st = check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset);
+    if (st) return st;
+    if ((st = check_enums(prm))) return st;
+    const size_t need = hbt_perm_test_workspace_size(prm);
+    if (need > (size_t)HBT_STATIC_SCRATCH_BYTES)
+        return fail(HBT_ERR_WORKSPACE,
+                    "this test needs %zu bytes of scratch; the static scratch holds %zu "
+                    "(use hbt_perm_test with a caller workspace)",
+                    need, (size_t)HBT_STATIC_SCRATCH_BYTES);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(HBT_ERR_DEVICE, "device %d out of range", dev);
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (!ptr[dev]) HIP_TRY(hipGetSymbolAddress(&ptr[dev], HIP_SYMBOL(scratch)));
+        ws = ptr[dev];
+    }
+    return hbt_perm_test(X, Y, prm, result, T_out, mask_out, ws, (size_t)HBT_STATIC_SCRATCH_BYTES,
+                         stream);
 }
 
 }  // extern "C"

@@ -97,6 +97,8 @@ def lib():
         L.hbt_tune_set.argtypes = [i64, P]
         L.hbt_tile_widths.argtypes = [i64, P, i64, P]
         L.hbt_recheck_band.argtypes = [i32, i32, i32, i64, i64, i64, dbl, dbl, P]
+        L.hbt_perm_test_static.argtypes = [P, P, C.POINTER(HbtPermParams), P, P, P, P]
+        L.hbt_perm_test_static.restype = i32
         for f in ["hbt_tune_batched", "hbt_tune_get", "hbt_tune_set", "hbt_tile_widths", "hbt_recheck_band"]:
             getattr(L, f).restype = i32
         L.hbt_budget_features.argtypes = [i64, P, i64, i32, P, P]
@@ -230,10 +232,13 @@ def align(X, Y, *, align=True, gd="banerjee", out=None, stream=None):
 
 def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", gd="banerjee",
               alternative="greater", align=True, recheck=True, block_perms=0, masks=None,
-              stat_route=0, want_T=False, want_masks=False, stream=None, sync=True):
+              stat_route=0, want_T=False, want_masks=False, stream=None, sync=True,
+              static_scratch=False):
     """The whole test for one pair.  Returns a dict of the hbt_result fields,
     plus ``T`` (B floats; doubles with want_T="f64") and ``masks``
-    (B x ceil(N/32) words) when asked."""
+    (B x ceil(N/32) words) when asked.  ``static_scratch``: call
+    hbt_perm_test_static, which uses the library's own device scratch
+    instead of a workspace allocated here."""
     torch = _torch()
     _pair_operands(X, Y)
     n, d = X.shape
@@ -256,17 +261,21 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     if t64:
         prm.flags |= FLAG_T_OUT_F64
     L = lib()
-    need = L.hbt_perm_test_workspace_size(C.byref(prm))
-    if need == 0:
-        need = 256
-    ws = workspace(need, dev)
     res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=dev)
     T = torch.empty(B, dtype=torch.float64 if t64 else torch.float32, device=dev) if want_T else None
     mo = torch.empty((B, W), dtype=torch.int32, device=dev) if want_masks else None
-    _check(L.hbt_perm_test(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), C.byref(prm),
-                           C.c_void_p(res.data_ptr()), None if T is None else C.c_void_p(T.data_ptr()),
-                           None if mo is None else C.c_void_p(mo.data_ptr()),
-                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    outs = (C.c_void_p(res.data_ptr()), None if T is None else C.c_void_p(T.data_ptr()),
+            None if mo is None else C.c_void_p(mo.data_ptr()))
+    if static_scratch:
+        _check(L.hbt_perm_test_static(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), C.byref(prm),
+                                      *outs, _stream(stream)))
+    else:
+        need = L.hbt_perm_test_workspace_size(C.byref(prm))
+        if need == 0:
+            need = 256
+        ws = workspace(need, dev)
+        _check(L.hbt_perm_test(C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), C.byref(prm), *outs,
+                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
     if not sync:
         return dict(result=res, T=T, masks=mo)
     r = _result_dict(results_to_numpy(res)[0])
