@@ -138,13 +138,35 @@ def stage_times(L, ctypes):
     return list(ms), list(n)
 
 
+def host_cpu():
+    """What the host offers this process: nproc, the CPUs it may run on, the
+    thread budget set for the job (OMP_NUM_THREADS) and the CPU model."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity, "omp_num_threads": omp or None,
+            "cpu_model": model}
+
+
 def cpu_baseline(batch, npairs_sample=176, splits=2000):
     from oracle import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    threads = min(threads, 16)
+    host = host_cpu()
+    # every core the job may use: the CPUs of its affinity mask, within the
+    # thread budget the host sets for one GPU's job (OMP_NUM_THREADS)
+    threads = host["affinity_cpus"] or 1
+    if host["omp_num_threads"]:
+        threads = min(threads, host["omp_num_threads"])
+    sample = sorted(set(np.linspace(0, batch.npairs - 1, npairs_sample).round().astype(int).tolist()))
     t0 = time.perf_counter()
     total = 0
-    for p in range(min(npairs_sample, batch.npairs)):
+    for p in sample:
         pr = batch.pair(p)
         r = O.perm_test(pr.X, pr.Y, splits, seed=batch.seed, pair=pr.pair_index, nthreads=threads)
         assert r["status"] in (0, O.ERR_DEGENERATE)
@@ -153,18 +175,59 @@ def cpu_baseline(batch, npairs_sample=176, splits=2000):
     # the same oracle on one thread, on every 16th pair of that sample
     t1 = time.perf_counter()
     total1 = 0
-    for p in range(0, min(npairs_sample, batch.npairs), 16):
+    for p in sample[::16]:
         pr = batch.pair(p)
         r = O.perm_test(pr.X, pr.Y, splits, seed=batch.seed, pair=pr.pair_index, nthreads=1)
         assert r["status"] in (0, O.ERR_DEGENERATE)
         total1 += splits
     dt1 = time.perf_counter() - t1
     return {"value": total / dt, "unit": "permuted statistics/s", "cores": threads, "kind": "oracle",
-            "sample": f"pairs 0..{npairs_sample - 1} of the workload, first {splits} splits each "
-                      f"({total} statistics, {dt:.1f} s wall, FP64 C oracle, OpenMP over splits)",
+            "host": host,
+            "sample": f"{len(sample)} pairs evenly spaced over the workload's 512 (sizes spread as in the "
+                      f"whole batch), first {splits} splits each ({total} statistics, {dt:.1f} s wall, "
+                      f"FP64 C oracle, OpenMP over splits on {threads} threads)",
             "single_thread": {"value": total1 / dt1, "cores": 1,
                               "sample": f"every 16th of those pairs, first {splits} splits each "
                                         f"({total1} statistics, {dt1:.1f} s wall)"}}
+
+
+# The paper's own runtime figure (Table 4), context only: another workload
+# (BCCWJ token embeddings from BERT-large, d = 1024, B = 20,000 per test),
+# other hardware.
+PAPER_CONTEXT = {
+    "paper_speedup_gpu_over_cpu": 23.0,
+    "paper_ms_per_permutation": {"cpu": 1.588, "gpu": 0.069},
+    "paper_workload": "Table 4: BCCWJ embeddings from BERT-large (d = 1024), B = 20,000 permutations per test",
+    "paper_hardware": "CPU model not named; GPU not named in the table, the compute-budget note names two NVIDIA H100s",
+    "note": "context only: not this workload, not this hardware",
+}
+
+
+def stage_errors(dev, pair, hbt, torch, sample_every=97):
+    """Error of each stage of the reduced precisions against the library's
+    FP64 path on the same splits: the squared group-sum norms the product
+    yields, the mean resultant lengths r1, r2 and T_b (before any recheck).
+    The FP64 path itself matches the FP64 CPU oracle to 1e-10 in the tests."""
+    X = torch.from_numpy(pair.X).to(dev)
+    Y = torch.from_numpy(pair.Y).to(dev)
+    runs = {prec: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, want_T="norms")["T"]
+            for prec in ("f64", "f32", "bf16x2", "i8x3")}
+    ref = runs.pop("f64")
+    idx = np.arange(0, pair.B, sample_every)
+    n, m, d = pair.n, pair.m, pair.d
+    rel = lambda a, b: float(np.max(np.abs(a - b) / np.abs(b)))
+    f = lambda r: np.log(r * (d - r * r) / (1 - r * r))
+    r1r, r2r = np.sqrt(ref[idx, 1]) / n, np.sqrt(ref[idx, 2]) / m
+    scale = np.abs(f(r1r)) + np.abs(f(r2r))
+    out = {"workload": f"{pair.meta.get('workload')}: n {n}, m {m}, d {d}, B {pair.B}; {len(idx)} sampled splits",
+           "reference": "the library's FP64 group sums (FP64 MFMA), same splits"}
+    for prec, T in runs.items():
+        r1, r2 = np.sqrt(T[idx, 1]) / n, np.sqrt(T[idx, 2]) / m
+        out[prec] = {"sq_norm_rel_max": max(rel(T[idx, 1], ref[idx, 1]), rel(T[idx, 2], ref[idx, 2])),
+                     "r_rel_max": max(rel(r1, r1r), rel(r2, r2r)),
+                     "T_abs_max": float(np.max(np.abs(T[idx, 0] - ref[idx, 0]))),
+                     "T_rel_to_scale_max": float(np.max(np.abs(T[idx, 0] - ref[idx, 0]) / scale))}
+    return out
 
 
 def log(msg):
@@ -180,6 +243,8 @@ def main():
     ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
     ap.add_argument("--single-steps", type=int, default=5,
                     help="timed calls per precision of the single-pair workloads (0 skips them)")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="timed replays of the split-BF16 call captured as a HIP graph (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the (untimed) tile-width tuning of the split-BF16 product")
@@ -252,6 +317,42 @@ def main():
     g_ms = ms[2] / max(launches[2], 1)
     achieved = algo_flops / (g_ms * 1e-3) / 1e12
     traffic = load_traffic(TRAFFIC_FILE, 1)
+    # the alignment stage (column sums, finalize, reflection + split-BF16
+    # storage): algorithmic bytes = every row read once by the column sums, the
+    # X rows read again by the reflection, and the two BF16 planes written
+    nx = int(batch.n.sum())
+    align_bytes = 4.0 * d * (N.sum() + nx) + 4.0 * d * N.sum()
+    align_ms = ms[0] / args.steps
+    align = {"ms_per_step": align_ms, "algorithmic_bytes": align_bytes,
+             "hbm_gbs": align_bytes / (align_ms * 1e-3) / 1e9,
+             "frac_hbm_peak": align_bytes / (align_ms * 1e-3) / 8.0e12}
+
+    graph = None
+    if args.graph_steps > 0:
+        # the same call captured once into a HIP graph and replayed
+        need = hbt.batched_workspace_size(batch.row_offset, batch.n, batch.m, batch.B, d, precision="bf16x2")
+        gws = torch.empty(need, dtype=torch.uint8, device=dev)
+        gres = torch.zeros(hbt.RESULT_BYTES * P, dtype=torch.uint8, device=dev)
+        call = lambda: hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
+                                             precision="bf16x2", sync=False, results=gres, workspace=gws)
+        call()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            call()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            g.replay()
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        gout = hbt.results_to_numpy(gres)
+        graph = {"ms_per_step": dtg / args.graph_steps * 1e3, "value": stats_per_step * args.graph_steps / dtg,
+                 "steps": args.graph_steps,
+                 "counts_equal_to_eager": bool(np.array_equal(gout["count"], out["count"]))}
+        log(f"graph replay: {graph['ms_per_step']:.2f} ms/step")
+        del g, gws
 
     fp = None
     if args.fp32_steps > 0:
@@ -307,6 +408,11 @@ def main():
             single[name] = row
             log(f"single pair {name}: " + ", ".join(f"{k} {row[k]['ms_per_call']:.3f} ms" for k in counts))
 
+    errors = None
+    if args.single_steps > 0:
+        errors = stage_errors(dev, synth.null_pair_d1024(), hbt, torch)
+        log("stage errors at null_pair_d1024 done")
+
     line = {
         "metric": "permuted statistics/s at d=768 (batched split-BF16 MFMA; plain FP32 in fp32_plain)",
         "value": value,
@@ -328,13 +434,19 @@ def main():
                      "traffic": traffic,
                      "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": g_ms,
                      "executed_mfma_tflops": 2 * achieved},
+        "whole_call": {"algorithmic_tflops": algo_flops / (dt / args.steps) / 1e12,
+                       "frac_bf16_peak": algo_flops / (dt / args.steps) / 1e12 / BF16_PEAK_TFLOPS},
         "stages_ms_per_step": {k: ms[i] / args.steps for i, k in enumerate(STAGES)},
+        "align_stage": align,
+        "graph_replay": graph,
         "pairs_bad_status": bad,
         "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
         "int8_planes": i8,
         "single_pair": single,
         "tile_tuning": tuning,
+        "stage_errors_null_pair_d1024": errors,
+        "context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch)

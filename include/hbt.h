@@ -138,6 +138,11 @@ typedef struct hbt_perm_params {
 #define HBT_FLAG_NO_RECHECK 1
 /* flags: T_out of hbt_perm_test is a double array (B doubles) instead of floats */
 #define HBT_FLAG_T_OUT_F64 2
+/* flags: T_out of hbt_perm_test holds 3 doubles per split: T_b and the squared
+ * norms |sigma_1|^2, |sigma_2|^2 of the two group sums it came from (the
+ * output of the group-sum product, before any FP64 recheck; a diagnostic of
+ * each stage's error) */
+#define HBT_FLAG_T_OUT_NORMS 4
 
 int32_t hbt_abi_version(void);
 const char* hbt_status_string(int32_t status);
@@ -162,8 +167,9 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
  * Algorithm 2 and eq:gemm).
  *   X (n x d), Y (m x d): unit rows, dtype prm->input_dtype.
  *   result: one device hbt_result.
- *   T_out (nullable, device, B floats): T_b as computed by the chosen
- *     precision (before any FP64 recheck).
+ *   T_out (nullable, device, B floats; B doubles with HBT_FLAG_T_OUT_F64;
+ *     B x 3 doubles (T_b, |sigma_1|^2, |sigma_2|^2) with HBT_FLAG_T_OUT_NORMS):
+ *     T_b as computed by the chosen precision (before any FP64 recheck).
  *   mask_out (nullable, device, B x ceil((n+m)/32) words): the splits used.
  * Errors: as hbt_align, plus HBT_ERR_DTYPE and HBT_ERR_UNSUPPORTED. */
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm);

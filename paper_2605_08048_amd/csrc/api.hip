@@ -298,7 +298,7 @@ hbt_status check_enums(const hbt_perm_params* prm) {
         return fail(HBT_ERR_ARG, "unknown stat_route %d", prm->stat_route);
     if (prm->stat_route == 1 && prm->precision == HBT_I8X3)
         return fail(HBT_ERR_UNSUPPORTED, "the int8 planes compute the statistic by route 0 only");
-    if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64))
+    if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64 | HBT_FLAG_T_OUT_NORMS))
         return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
     return HBT_OK;
 }
@@ -626,7 +626,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 
     const RecheckBand band = precision_band(P.precision, P.d, P.route2);
     const int no_recheck = prm->flags & HBT_FLAG_NO_RECHECK;
-    const int64_t t_size = (prm->flags & HBT_FLAG_T_OUT_F64) ? 8 : 4;
+    const int t_mode = (prm->flags & HBT_FLAG_T_OUT_NORMS) ? 2 : (prm->flags & HBT_FLAG_T_OUT_F64) ? 1 : 0;
+    const int64_t t_size = t_mode == 2 ? 24 : t_mode == 1 ? 8 : 4;
     // the tables of split block b0 (nb splits) and its tile width
     // One pair alone fills the GPU only with enough tiles: the narrow width
     // when the wide one would not give two tiles per CU (the width never
@@ -726,7 +727,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
                             P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot,
                             P.block_rows, P.d, prm->gd,
                             prm->alternative, band, no_recheck,
-                            T_out ? (char*)T_out + b0 * t_size : nullptr, t_size == 8, w.tw,
+                            T_out ? (char*)T_out + b0 * t_size : nullptr, t_mode, w.tw,
                             w.cnt, w.flags, w.nflag, s)); }
         if (!no_recheck) {
             StageTimer t_(HBT_STAGE_RECHECK, s);
@@ -880,7 +881,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot,
                         P.block_rows, P.d, common->gd,
                         common->alternative, precision_band(P.precision, P.d, false), no_recheck, nullptr,
-                        false, w.tw, w.cnt, w.flags, w.nflag, s)); }
+                        0, w.tw, w.cnt, w.flags, w.nflag, s)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,

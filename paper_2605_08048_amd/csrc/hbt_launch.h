@@ -119,7 +119,7 @@ hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const Gem
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, const RecheckBand& band, int no_recheck, void* T_out,
-                       bool T_f64, double* Tw,
+                       int T_mode, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
 // doubles of per-wave segment sums (nullptr: every flag done whole by one

@@ -17,7 +17,7 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               int64_t prow, int d,
                                               int gd, int alternative, RecheckBand band,
                                               int no_recheck, void* T_out,
-                                              bool T_f64, double* __restrict__ Tw,
+                                              int T_mode, double* __restrict__ Tw,
                                               PairCount* cnt, uint32_t* flags, uint32_t* nflag) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = row < rows;
@@ -43,8 +43,16 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         const double r1 = sqrt(ss1) / n, r2 = sqrt(ss2) / m;
         const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);  // log v(X^(b)) - log v(Y^(b))
         if (T_out) {
-            if (T_f64) ((double*)T_out)[row] = T;
-            else ((float*)T_out)[row] = (float)T;
+            if (T_mode == 2) {  // T_b and both squared group-sum norms
+                double* o = (double*)T_out + 3 * row;
+                o[0] = T;
+                o[1] = ss1;
+                o[2] = ss2;
+            } else if (T_mode == 1) {
+                ((double*)T_out)[row] = T;
+            } else {
+                ((float*)T_out)[row] = (float)T;
+            }
         }
         Tw[row] = T;
         const bool two = alternative == HBT_ALT_TWO_SIDED;
@@ -74,13 +82,13 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, const RecheckBand& band, int no_recheck, void* T_out,
-                       bool T_f64, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
+                       int T_mode, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
                        hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
                        npairs, rows, st, partial, nslot, prow, d, gd, alternative, band,
                        no_recheck,
-                       T_out, T_f64, Tw, cnt, flags, nflag);
+                       T_out, T_mode, Tw, cnt, flags, nflag);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ GD = {"banerjee": 0, "identity": 1}
 ALT = {"greater": 0, "two-sided": 1}
 FLAG_NO_RECHECK = 1
 FLAG_T_OUT_F64 = 2
+FLAG_T_OUT_NORMS = 4
 MAX_N, MAX_D = 65536, 8192
 
 
@@ -235,7 +236,8 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
               stat_route=0, want_T=False, want_masks=False, stream=None, sync=True,
               static_scratch=False):
     """The whole test for one pair.  Returns a dict of the hbt_result fields,
-    plus ``T`` (B floats; doubles with want_T="f64") and ``masks``
+    plus ``T`` (B floats; doubles with want_T="f64"; B x 3 doubles (T_b,
+    |sigma_1|^2, |sigma_2|^2) with want_T="norms") and ``masks``
     (B x ceil(N/32) words) when asked.  ``static_scratch``: call
     hbt_perm_test_static, which uses the library's own device scratch
     instead of a workspace allocated here."""
@@ -257,12 +259,15 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
                       precision=precision, input_dtype=_input_dtype(X), gd=gd, alternative=alternative,
                       align=align, recheck=recheck, block_perms=block_perms, stat_route=stat_route,
                       masks_ptr=None if mk is None else mk.data_ptr())
-    t64 = want_T == "f64"
-    if t64:
+    t64 = want_T in ("f64", "norms")
+    if want_T == "f64":
         prm.flags |= FLAG_T_OUT_F64
+    if want_T == "norms":
+        prm.flags |= FLAG_T_OUT_NORMS
     L = lib()
     res = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=dev)
-    T = torch.empty(B, dtype=torch.float64 if t64 else torch.float32, device=dev) if want_T else None
+    T = torch.empty((B, 3) if want_T == "norms" else B, dtype=torch.float64 if t64 else torch.float32,
+                    device=dev) if want_T else None
     mo = torch.empty((B, W), dtype=torch.int32, device=dev) if want_masks else None
     outs = (C.c_void_p(res.data_ptr()), None if T is None else C.c_void_p(T.data_ptr()),
             None if mo is None else C.c_void_p(mo.data_ptr()))

@@ -422,11 +422,40 @@ def test_pair_d768_full_size(prec):
     assert abs(r["t_obs"] - o["t_obs"]) < 1e-12 * abs(o["t_obs"])
 
 
+_NULL1024 = {}
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
+def test_null_pair_d1024_full_size(prec):
+    """The precision-path workload at its stated size (n 3000, m 2000, d 1024,
+    B 20,000, equal concentration): counts against the oracle's full run,
+    T_b on sampled splits against the oracle's FP64 values, masks bit-exact."""
+    print(f"null_pair_d1024 {prec}", flush=True)
+    c = synth.null_pair_d1024()
+    if not _NULL1024:
+        _NULL1024["o"] = O.perm_test(c.X, c.Y, c.B, seed=c.seed, want_T=True)
+        sample = np.unique(np.concatenate([np.arange(0, c.B, 101), [c.B - 1]]))
+        _NULL1024["sample"] = sample
+        _NULL1024["at"] = O.perm_stats_at(c.X, c.Y, sample, seed=c.seed, want_masks=True)
+    o, sample, at = _NULL1024["o"], _NULL1024["sample"], _NULL1024["at"]
+    Xd, Yd = _dev(c.X), _dev(c.Y)
+    r = hbt.perm_test(Xd, Yd, c.B, seed=c.seed, precision=prec, want_T="f64", want_masks=True)
+    assert r["status"] == 0
+    assert np.array_equal(r["masks"][sample], at["masks"])
+    err = np.abs(r["T"][sample] - at["T"]) / _scale(c.X, c.Y, at)
+    assert err.max() <= TOL[prec] + 1.2e-7, err.max()
+    assert abs(r["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"]), (r["count"], o["count"])
+    assert abs(r["t_obs"] - o["t_obs"]) < 1e-12 * max(1.0, abs(o["t_obs"]))
+    assert r["p"] == (1 + r["count"]) / (c.B + 1)
+    print(f"  count {r['count']} (oracle {o['count']}), rechecked {r['n_recheck']}, worst T err {err.max():.2e}")
+
+
 def test_batch_512_d768_full_size_sampled_pairs():
     """The whole 512-pair batch (d = 768, B = 2000 per pair, 1.05M rows) in
     one call per precision, with tile widths tuned on it first, as the
-    throughput measurement runs it; seven pairs from the smallest to the
-    largest are checked against the oracle."""
+    throughput measurement runs it; 32 pairs at evenly spaced ranks of the
+    pooled size, from the smallest to the largest, are checked against the
+    oracle (counts, T_obs, p, moments)."""
     print("batch_512_d768 full size", flush=True)
     b = synth.batch_512_d768()
     Z = _dev(b.Z)
@@ -436,11 +465,14 @@ def test_batch_512_d768_full_size_sampled_pairs():
     del Z
     order = np.argsort(b.n + b.m, kind="stable")
     P = b.npairs
-    for p in (int(order[k]) for k in (0, 1, P // 4, P // 2, 3 * P // 4, P - 2, P - 1)):
+    # 32 pairs at evenly spaced ranks of the pooled size, smallest and largest included
+    picks = sorted(set(np.linspace(0, P - 1, 32).round().astype(int).tolist()))
+    assert len(picks) == 32
+    for p in (int(order[k]) for k in picks):
         pr = b.pair(p)
         print(f"pair {p}: n={pr.X.shape[0]} m={pr.Y.shape[0]}", flush=True)
         o = O.perm_test(pr.X, pr.Y, pr.B, seed=b.seed, pair=p, want_T=True)
-        at = O.perm_stats_at(pr.X, pr.Y, np.arange(pr.B), seed=b.seed, pair=p)
+        at = O.perm_stats_at(pr.X, pr.Y, np.arange(0, pr.B, 10), seed=b.seed, pair=p)
         for prec, r in res.items():
             assert np.all(r["status"] == 0), prec
             assert abs(r[p]["t_obs"] - o["t_obs"]) <= 1e-12 * max(1.0, abs(o["t_obs"])), (prec, p)
