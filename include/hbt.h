@@ -205,6 +205,16 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                  const hbt_perm_params* common, hbt_result* results, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* hbt_pipeline_chunks: how many chunks of pairs the batched call pipelines
+ * (the product of one chunk runs while the next is aligned and split, on
+ * three streams joined by events; split BF16 and int8 planes with FP32 rows,
+ * d a multiple of 4 and at most 1024, 16-byte aligned rows; other calls run
+ * as one chunk).  chunks = 1 turns the pipeline off, 0 restores the default
+ * (4); *previous (nullable) receives the setting it replaces.  Process-wide,
+ * for later calls; results do not depend on it.
+ * Errors: HBT_ERR_ARG (chunks outside [0, 64]). */
+hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous);
+
 /* hbt_recheck_band: the half-width *eps (host double) of the band around the
  * decision threshold inside which a split's T_b, computed by `precision` and
  * `stat_route`, is re-evaluated in FP64 (the count follows the FP64 statistic

@@ -165,7 +165,7 @@ __device__ __forceinline__ void load_cols(float (&x)[J][4], const float* row, in
 template <int J>
 __device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc& pd, int d,
                                               double* __restrict__ partial_row,
-                                              double (*red)[256 * J], int32_t* chunk_bad) {
+                                              double (*red)[256 * J], int32_t* bad_out) {
     const float* base = (const float*)(ch.side ? pd.Y : pd.X);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double acc[J][4];
@@ -212,7 +212,7 @@ __device__ __forceinline__ void colsum4_chunk(const SumChunk& ch, const PairDesc
 #pragma unroll
             for (int e = 0; e < 4; ++e) red[wave - 1][4 * (lane + 64 * j) + e] = acc[j][e];
     bad = __syncthreads_or(bad);
-    if (threadIdx.x == 0) chunk_bad[blockIdx.x] = bad ? 1 : 0;
+    if (threadIdx.x == 0) *bad_out = bad ? 1 : 0;
     if (wave == 0)
 #pragma unroll
         for (int j = 0; j < J; ++j)
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_colsum4(const PairDesc* __restrict__ pa
                                                  int32_t* __restrict__ chunk_bad) {
     __shared__ double red[3][256 * J];
     const SumChunk ch = chunk_of(pairs, npairs, blockIdx.x);
-    colsum4_chunk<J>(ch, pairs[ch.pair], d, partial + (int64_t)blockIdx.x * d, red, chunk_bad);
+    colsum4_chunk<J>(ch, pairs[ch.pair], d, partial + (int64_t)blockIdx.x * d, red, chunk_bad + blockIdx.x);
 }
 
 bool vector_rows_ok(int input_dtype, int d, int d_pad) {
@@ -274,9 +274,10 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
                                                   const int32_t* __restrict__ chunk_bad, int d,
                                                   int d_pad, int align, int gd, double* sxy,
                                                   PairState* st, double* v, double* t64,
-                                                  float* t32, PairCount* cnt, hbt_result* res) {
+                                                  float* t32, PairCount* cnt, hbt_result* res,
+                                                  int p0) {
     __shared__ double red[256];
-    const int p = blockIdx.x;
+    const int p = blockIdx.x + p0;
     const PairDesc pd = pairs[p];
     double* sx = sxy + (int64_t)p * 2 * d_pad;
     double* sy = sx + d_pad;
@@ -385,9 +386,10 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
                            const int32_t* chunk_bad, int d,
                            int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
                            double* t64, float* t32, PairCount* cnt, hbt_result* res,
-                           hipStream_t s) {
+                           hipStream_t s, int p0) {
+    if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(npairs), dim3(256), 0, s, pairs, partial, chunk_bad, d, d_pad, align,
-                       gd, sxy, st, v, t64, t32, cnt, res);
+                       gd, sxy, st, v, t64, t32, cnt, res, p0);
     return hipGetLastError();
 }
 
@@ -632,9 +634,10 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
                                                   const PairState* __restrict__ st,
                                                   const double* __restrict__ v, int d, int d_pad,
                                                   double* __restrict__ coef, void* zstore,
-                                                  int64_t zplane_elems, float* __restrict__ z32) {
+                                                  int64_t zplane_elems, float* __restrict__ z32,
+                                                  int64_t oct0) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t oct = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t oct = (int64_t)blockIdx.x * 4 + wave + oct0;
     if (oct >= total_octets) return;
     const int p = upper_index(npairs, oct, [&](int k) { return pairs[k].xoct0; });
     const PairDesc pd = pairs[p];
@@ -697,13 +700,13 @@ __global__ __launch_bounds__(256) void k_reflect4(const PairDesc* __restrict__ p
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
                               int64_t total_octets, const PairState* st, const double* v, int d,
                               int d_pad, double* coef, void* zstore, int64_t zplane_elems,
-                              float* z32, hipStream_t s) {
-    if (total_octets <= 0) return hipSuccess;
+                              float* z32, hipStream_t s, int64_t oct0) {
+    if (total_octets <= oct0) return hipSuccess;
     const int J = (d_pad + 255) / 256;
-    const dim3 g((unsigned)((total_octets + 3) / 4)), b(256);
+    const dim3 g((unsigned)((total_octets - oct0 + 3) / 4)), b(256);
 #define HBT_R4(PR, JJ)                                                                         \
     hipLaunchKernelGGL((k_reflect4<PR, JJ>), g, b, 0, s, pairs, npairs, total_octets, st, v, d, \
-                       d_pad, coef, zstore, zplane_elems, z32)
+                       d_pad, coef, zstore, zplane_elems, z32, oct0)
 #define HBT_R4J(PR)                            \
     switch (J) {                               \
         case 1: HBT_R4(PR, 1); break;          \
@@ -736,14 +739,14 @@ __global__ __launch_bounds__(256) void k_colsum_store4(const PairDesc* __restric
                                                        double* __restrict__ partial, void* zstore,
                                                        int64_t zplane_elems,
                                                        float* __restrict__ z32,
-                                                       int32_t* __restrict__ chunk_bad) {
+                                                       int32_t* __restrict__ chunk_bad, int c0) {
     __shared__ double red[4][256 * J];
-    const int c = blockIdx.x;
+    const int c = blockIdx.x + c0;
     const SumChunk ch = chunk_of(pairs, npairs, c);
     const PairDesc pd = pairs[ch.pair];
     double* prow = partial + (int64_t)c * d;
     if (!ch.side) {  // work-group-uniform
-        colsum4_chunk<J>(ch, pd, d, prow, red, chunk_bad);
+        colsum4_chunk<J>(ch, pd, d, prow, red, chunk_bad + c);
         return;
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -807,13 +810,13 @@ __global__ __launch_bounds__(256) void k_colsum_store4(const PairDesc* __restric
 hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npairs, int nchunks,
                                    int d, int d_pad, double* partial, void* zstore,
                                    int64_t zplane_elems, float* z32, int32_t* chunk_bad,
-                                   hipStream_t s) {
+                                   hipStream_t s, int c0) {
     if (nchunks <= 0) return hipSuccess;
     const int J = (d_pad + 255) / 256;
     const dim3 g(nchunks), b(256);
 #define HBT_C4(PR, JJ)                                                                         \
     hipLaunchKernelGGL((k_colsum_store4<PR, JJ>), g, b, 0, s, pairs, npairs, d, d_pad, partial, \
-                       zstore, zplane_elems, z32, chunk_bad)
+                       zstore, zplane_elems, z32, chunk_bad, c0)
 #define HBT_C4J(PR)                            \
     switch (J) {                               \
         case 1: HBT_C4(PR, 1); break;          \

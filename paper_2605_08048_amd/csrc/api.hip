@@ -78,6 +78,7 @@ struct StageTimer {
 };
 
 constexpr int64_t kAutoBlock = 32768;  // splits per block when block_perms == 0
+constexpr int kPipelineChunks = 1;     // pipeline chunks of a batched call (1: no pipeline)
 
 int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
 
@@ -188,6 +189,13 @@ struct Plan {
     bool aligned16 = true;        // every X, Y starts on a 16-byte boundary
     int ntile_i = 0;              // its row tiles (of 64) per split
     std::vector<GemmTile> ctiles;
+    // Pipeline chunks of the batched call: pairs [pa, pb), their groups from
+    // g0 (the wide ones, then the narrow ones, tiles numbered from 0 in each)
+    struct Chunk {
+        int pa, pb, g0, ngw, ng256;
+        int64_t ntw, nt256;
+    };
+    std::vector<Chunk> cplan;
 };
 
 Workspace carve(const Plan& P, void* ws) {
@@ -347,24 +355,33 @@ int choose_width(int64_t B, const TileCost& tc) {
 }
 
 // Groups of split-BF16 tiles, pairs in the given order, segmented by width.
-void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B) {
+// The product's groups of the pairs [pa, pb) (in `order`, largest first), as
+// one pipeline chunk: its wide groups, then its narrow ones, tiles numbered
+// from 0 within each width.
+void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B, int pa, int pb) {
     const TileCost tc = tile_cost(P.d_pad);
+    Plan::Chunk c{pa, pb, (int)P.groups.size(), 0, 0, 0, 0};
     std::vector<GemmGroup> g2;
     for (int p : order) {
         const int w = P.precision == HBT_I8X3 ? kTileI8 : choose_width(B[p], tc);
         const int nbt = (int)((B[p] + w - 1) / w);
         if (w == kTileWide) {
-            P.groups.push_back(GemmGroup{p, nbt, P.ntw});
-            P.ntw += (int64_t)nbt * P.nslot;
+            P.groups.push_back(GemmGroup{p, nbt, c.ntw});
+            c.ntw += (int64_t)nbt * P.nslot;
         } else {
-            g2.push_back(GemmGroup{p, nbt, P.nt256});
-            P.nt256 += (int64_t)nbt * P.nslot;
+            g2.push_back(GemmGroup{p, nbt, c.nt256});
+            c.nt256 += (int64_t)nbt * P.nslot;
         }
     }
-    P.ngw = (int)P.groups.size();
-    P.ng256 = (int)g2.size();
+    c.ngw = (int)P.groups.size() - c.g0;
+    c.ng256 = (int)g2.size();
     P.groups.insert(P.groups.end(), g2.begin(), g2.end());
+    P.ngw += c.ngw;
+    P.ng256 += c.ng256;
+    P.ntw += c.ntw;
+    P.nt256 += c.nt256;
     P.ntile_total = P.ntw + P.nt256;
+    P.cplan.push_back(c);
 }
 
 // The block-table entry of a pair's splits [perm_base, perm_base + nb).
@@ -450,19 +467,36 @@ hbt_status enqueue_prologue(const Plan& P, const Workspace& w, int align, int gd
 // events that fork it from the caller's stream and join it back.  Both are
 // stream-ordered, so a captured call records them as graph edges.
 std::mutex g_side_mu;
-hipStream_t g_side[64];
+hipStream_t g_side[2][64];
 
-hipError_t side_stream(hipStream_t* out) {
+hipError_t side_stream(hipStream_t* out, int which = 0) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> g(g_side_mu);
-    if (!g_side[dev] && (e = hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking)) != hipSuccess)
-        return e;
-    *out = g_side[dev];
+    hipStream_t& q = g_side[which][dev];
+    if (!q && (e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess) return e;
+    *out = q;
     return hipSuccess;
 }
+
+// Events of one call (created and destroyed by the call; their records and
+// waits are stream-ordered, so a captured call records them as graph edges).
+struct Events {
+    std::vector<hipEvent_t> ev;
+    ~Events() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t record(hipStream_t s, hipEvent_t* out) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+        *out = e;
+        return hipEventRecord(e, s);
+    }
+};
 
 struct Fork {
     hipStream_t main, side = nullptr;
@@ -486,6 +520,103 @@ struct Fork {
         return hipStreamWaitEvent(main, b, 0);
     }
 };
+
+// The stages after the group sums: statistic and counts, recheck, null
+// moments, p-values.
+hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_params* common,
+                            hbt_result* results, hipStream_t s) {
+    const int np = P.npairs;
+    const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
+    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot,
+                        P.block_rows, P.d, common->gd,
+                        common->alternative, precision_band(P.precision, P.d, false), no_recheck, nullptr,
+                        0, w.tw, w.cnt, w.flags, w.nflag, s)); }
+    if (!no_recheck) {
+        StageTimer t_(HBT_STAGE_RECHECK, s);
+        HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
+                               w.nflag, P.block_rows, P.max_np, w.rseg, P.d, common->gd, common->alternative,
+                               w.cnt, w.tw, s));
+    }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
+    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.bp, w.st, w.sstat, w.cnt, w.Btot, results, s)); }
+    return HBT_OK;
+}
+
+// The batched call as a pipeline over chunks of pairs (Plan::cplan): the
+// caller's stream aligns chunk k (column sums, finalize, reflection and
+// storage), a second stream draws its splits, and a third runs its group-sum
+// product once both are done, so that the product of chunk k overlaps the
+// alignment and the splits of chunk k + 1.  Events order the streams (a
+// captured call records them as graph edges); the streams join before the
+// statistic.  Every stage computes what it does without the pipeline, so the
+// results do not depend on the chunking.
+hbt_status batched_pipelined(const Plan& P, const Workspace& w, const hbt_perm_params* common,
+                             hbt_result* results, hipStream_t s) {
+    const int np = P.npairs;
+    hipStream_t qs, qg;  // splits, group sums
+    HIP_TRY(side_stream(&qs, 0));
+    HIP_TRY(side_stream(&qg, 1));
+    Events ev;
+    hipEvent_t e0;
+    {
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
+    }
+    HIP_TRY(ev.record(s, &e0));
+    HIP_TRY(hipStreamWaitEvent(qs, e0, 0));
+    {
+        StageTimer t_(HBT_STAGE_SPLIT, qs);
+        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, qs));
+    }
+    {
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
+        HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
+        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
+        HIP_TRY(zero(w.nflag, 8, s));
+    }
+    HIP_TRY(ev.record(s, &e0));
+    HIP_TRY(hipStreamWaitEvent(qg, e0, 0));
+    for (const Plan::Chunk& c : P.cplan) {
+        const bool last = c.pb == np;
+        const int64_t r0 = P.bp[c.pa].mrow0, r1 = last ? P.block_rows : P.bp[c.pb].mrow0;
+        const int c0 = P.pairs[c.pa].cx0, c1 = P.pairs[c.pb - 1].cy1;
+        const int64_t o0 = P.pairs[c.pa].xoct0, o1 = last ? P.xoct : P.pairs[c.pb].xoct0;
+        hipEvent_t es, ea;
+        {
+            StageTimer t_(HBT_STAGE_SPLIT, qs);
+            HIP_TRY(launch_split_masks(w.bp, np, r1, P.max_np, common->seed, w.mask, w.sstat,
+                                       kSplitWgPerCuBesideAlign, qs, r0));
+        }
+        HIP_TRY(ev.record(qs, &es));
+        {
+            StageTimer t_(HBT_STAGE_ALIGN, s);
+            HIP_TRY(launch_colsum_store_vec(P.precision, w.pairs, np, c1 - c0, P.d, P.d_pad, w.partial_sum,
+                                            w.zstore, P.zrows * P.d_pad, w.z32, w.chunk_bad, s, c0));
+            HIP_TRY(launch_finalize(w.pairs, c.pb - c.pa, w.partial_sum, w.chunk_bad, P.d, P.d_pad,
+                                    common->align, common->gd, w.sxy, w.st, w.v, w.t64, w.t32, w.cnt,
+                                    results, s, c.pa));
+            HIP_TRY(launch_reflect_vec(P.precision, w.pairs, np, o1, w.st, w.v, P.d, P.d_pad, w.coef,
+                                       w.zstore, P.zrows * P.d_pad, nullptr, s, o0));
+        }
+        HIP_TRY(ev.record(s, &ea));
+        HIP_TRY(hipStreamWaitEvent(qg, es, 0));
+        HIP_TRY(hipStreamWaitEvent(qg, ea, 0));
+        {
+            StageTimer t_(HBT_STAGE_GROUPSUM, qg);
+            HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, 0, w.groups + c.g0, c.ngw,
+                                    (int)c.ntw, c.ng256, (int)c.nt256, P.d_pad, w.zstore,
+                                    P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
+                                    nullptr, qg));
+        }
+    }
+    hipEvent_t ej;
+    HIP_TRY(ev.record(qs, &ej));
+    HIP_TRY(hipStreamWaitEvent(s, ej, 0));
+    HIP_TRY(ev.record(qg, &ej));
+    HIP_TRY(hipStreamWaitEvent(s, ej, 0));
+    return batched_epilogue(P, w, common, results, s);
+}
 
 }  // namespace
 
@@ -744,6 +875,14 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 }
 
 // ---------------------------------------------------------------------------
+// Number of pipeline chunks of a batched call (1 = no pipeline).
+int g_pipeline_chunks = kPipelineChunks;
+int pipeline_chunks(const Plan& P, int64_t npairs) {
+    if (!(P.precision == HBT_BF16X2 || P.precision == HBT_I8X3) || !vector_rows(P) || !P.need_store)
+        return 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g_pipeline_chunks, npairs));
+}
+
 static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64_t* row_offset,
                          const int64_t* n, const int64_t* m, const int64_t* B,
                          const uint32_t* pair_index, int64_t d, const hbt_perm_params* common) {
@@ -773,14 +912,38 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
     }
     finish_plan(P, d, common->precision, common->input_dtype);
     // tiles, largest pooled size first (longest-processing-time order)
-    std::vector<int> order((size_t)npairs);
-    for (int64_t p = 0; p < npairs; ++p) order[(size_t)p] = (int)p;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
+    auto by_size = [&](int pa, int pb) {
+        std::vector<int> order;
+        for (int p = pa; p < pb; ++p) order.push_back(p);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
+        return order;
+    };
+    const std::vector<int> order = by_size(0, (int)npairs);
     const int tb = groupsum_tile_splits(common->precision);
     for (int p : order)
         for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
-    add_groups(P, order, B);
+    // Pipeline chunks: consecutive pair ranges of about equal product work
+    // (B N), so that the product of one chunk runs while the next chunk is
+    // aligned and split.  Only for the persistent product kernels on the
+    // 16-byte-load path; otherwise one chunk.
+    const int nchunk = pipeline_chunks(P, npairs);
+    if (nchunk <= 1) {
+        add_groups(P, order, B, 0, (int)npairs);
+    } else {
+        double total = 0.0;
+        for (int64_t p = 0; p < npairs; ++p) total += (double)B[p] * P.pairs[p].Np;
+        double acc = 0.0;
+        int pa = 0;
+        for (int64_t p = 0; p < npairs; ++p) {
+            acc += (double)B[p] * P.pairs[p].Np;
+            const int k = (int)P.cplan.size();
+            if (p + 1 == npairs || (acc >= total * (k + 1) / nchunk && k + 1 < nchunk)) {
+                add_groups(P, by_size(pa, (int)p + 1), B, pa, (int)p + 1);
+                pa = (int)p + 1;
+            }
+        }
+    }
     P.block_rows = rows;
     P.block_mask_words = words;
     return true;
@@ -830,27 +993,43 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     hipStream_t s = (hipStream_t)stream;
     Workspace w = carve(P, ws);
     const int np = P.npairs;
-    {  // the split stage reads only this table: it goes first
-        StageTimer t_(HBT_STAGE_OTHER, s);
-        HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), s));
-    }
-    // The splits depend only on the seeds and the group sizes, not on the
-    // alignment: they are drawn on a second stream beside it (integer VALU
-    // work beside HBM-bound work) and joined before the group sums.  At most
-    // 6 split work-groups per CU (kSplitWgPerCuBesideAlign) leave wave slots
-    // to the alignment kernels
-    // (measured on 512 pairs, d = 768, split BF16: 8.03 ms per call at 8 or
-    // uncapped, where the alignment then waits for wave slots; 7.25 ms at 6,
-    // the two stages 2.1 ms each; 7.56 ms at 5, 7.63 ms at 4).
-    Fork fork(s);
-    HIP_TRY(fork.begin());
+    if (P.cplan.size() > 1) return batched_pipelined(P, w, common, results, s);
+    // Three streams until the group sums: the caller's uploads the pair table
+    // and aligns; a second one uploads the block table (all the split stage
+    // reads) and draws the splits, which depend only on the seeds and the
+    // group sizes (integer VALU work beside HBM-bound work); a third uploads
+    // the tables only the later stages read.  The table uploads are chains of
+    // small kernels (a few microseconds each), so no chain waits for another.
+    // At most 6 split work-groups per CU (kSplitWgPerCuBesideAlign) leave
+    // wave slots to the alignment kernels (measured on 512 pairs, d = 768,
+    // split BF16: 8.03 ms per call at 8 or uncapped, where the alignment
+    // then waits for wave slots; 7.25 ms at 6, the two stages 2.1 ms each;
+    // 7.56 ms at 5, 7.63 ms at 4).
+    hipStream_t qs, qt;
+    HIP_TRY(side_stream(&qs, 0));
+    HIP_TRY(side_stream(&qt, 1));
+    Events ev;
+    hipEvent_t e0;
+    HIP_TRY(ev.record(s, &e0));
+    HIP_TRY(hipStreamWaitEvent(qs, e0, 0));
+    HIP_TRY(hipStreamWaitEvent(qt, e0, 0));
     {
-        StageTimer t_(HBT_STAGE_SPLIT, fork.side);
-        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, fork.side));
+        StageTimer t_(HBT_STAGE_SPLIT, qs);
+        HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), qs));
+        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, qs));
         HIP_TRY(launch_split_masks(w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
-                                   kSplitWgPerCuBesideAlign, fork.side));
+                                   kSplitWgPerCuBesideAlign, qs));
     }
-    {  // the pair table, uploaded while the splits are drawn
+    {
+        StageTimer t_(HBT_STAGE_OTHER, qt);
+        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
+            HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), qt));
+        else
+            HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), qt));
+        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), qt));
+        HIP_TRY(zero(w.nflag, 8, qt));
+    }
+    {
         StageTimer t_(HBT_STAGE_OTHER, s);
         HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
     }
@@ -860,16 +1039,10 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         StageTimer t_(HBT_STAGE_ALIGN, s);
         HIP_TRY(reflect(P, w, nullptr, s));
     }
-    {  // tables only the later stages read, enqueued while the splits finish
-        StageTimer t_(HBT_STAGE_OTHER, s);
-        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
-            HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
-        else
-            HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), s));
-        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
-        HIP_TRY(zero(w.nflag, 8, s));
-    }
-    HIP_TRY(fork.join());
+    HIP_TRY(ev.record(qs, &e0));
+    HIP_TRY(hipStreamWaitEvent(s, e0, 0));
+    HIP_TRY(ev.record(qt, &e0));
+    HIP_TRY(hipStreamWaitEvent(s, e0, 0));
     {
         StageTimer t_(HBT_STAGE_GROUPSUM, s);
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
@@ -877,21 +1050,9 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                 P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
                                 nullptr, s));
     }
-    const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
-    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot,
-                        P.block_rows, P.d, common->gd,
-                        common->alternative, precision_band(P.precision, P.d, false), no_recheck, nullptr,
-                        0, w.tw, w.cnt, w.flags, w.nflag, s)); }
-    if (!no_recheck) {
-        StageTimer t_(HBT_STAGE_RECHECK, s);
-        HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
-                               w.nflag, P.block_rows, P.max_np, w.rseg, P.d, common->gd, common->alternative,
-                               w.cnt, w.tw, s));
-    }
-    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
-    { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_final(np, w.bp, w.st, w.sstat, w.cnt, w.Btot, results, s)); }
-    return HBT_OK;
+    return batched_epilogue(P, w, common, results, s);
 }
+
 
 // ---------------------------------------------------------------------------
 // permutation-budget allocator
@@ -997,6 +1158,15 @@ hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t*
         if (B[p] < 1) return fail(HBT_ERR_SIZE, "B[%lld] = %lld", (long long)p, (long long)B[p]);
         widths[p] = choose_width(B[p], tc);
     }
+    return HBT_OK;
+}
+
+hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous) {
+    g_err.clear();
+    if (chunks < 0 || chunks > 64) return fail(HBT_ERR_ARG, "chunks = %d (0 ... 64)", chunks);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (previous) *previous = g_pipeline_chunks;
+    g_pipeline_chunks = chunks == 0 ? kPipelineChunks : chunks;
     return HBT_OK;
 }
 

@@ -30,7 +30,7 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
                            const int32_t* chunk_bad, int d,
                            int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
                            double* t64, float* t32, PairCount* cnt, hbt_result* res,
-                           hipStream_t s);
+                           hipStream_t s, int p0 = 0);  // pairs [p0, p0 + npairs)
 // Reflect X rows, write Z in the precision's storage format, the FP64
 // coefficients 2 (v.x_i) / (v.v) and zero padding.
 // 16-byte-load variants for FP32 rows with d % 4 == 0 and d_pad <= 1024 (the
@@ -44,11 +44,12 @@ hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int
 hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npairs, int nchunks,
                                    int d, int d_pad, double* partial, void* zstore,
                                    int64_t zplane_elems, float* z32, int32_t* chunk_bad,
-                                   hipStream_t s);
+                                   hipStream_t s, int c0 = 0);  // chunks [c0, c0 + nchunks)
 hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
                               int64_t total_octets, const PairState* st, const double* v, int d,
                               int d_pad, double* coef, void* zstore, int64_t zplane_elems,
-                              float* z32, hipStream_t s);
+                              float* z32, hipStream_t s,
+                              int64_t oct0 = 0  /* octets [oct0, total_octets) */);
 hipError_t launch_reflect(int input_dtype, int precision, const PairDesc* pairs, int npairs,
                           int64_t total_octets, const PairState* st, const double* v, int d,
                           int d_pad, double* coef, void* zstore, int64_t zplane_elems,
@@ -74,7 +75,8 @@ size_t split_lds_limit();
 constexpr int kSplitWgPerCuBesideAlign = 6;
 hipError_t launch_split_masks(const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
-                              int32_t* sstat, int wg_per_cu, hipStream_t s);
+                              int32_t* sstat, int wg_per_cu, hipStream_t s,
+                              int64_t row0 = 0  /* split rows [row0, rows) */);
 // Explicit masks: copy rows of ceil(N/32) words into the workspace layout and
 // check that each holds exactly n items.
 hipError_t launch_copy_masks(const uint32_t* user, int64_t user_row0, int64_t rows, int N, int n,

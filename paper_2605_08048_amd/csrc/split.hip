@@ -71,12 +71,12 @@ template <int R>
 __global__ __launch_bounds__(256) void k_split_masks(const BlockPair* __restrict__ bp, int npairs,
                                                      int64_t rows, int max_np, uint32_t key0,
                                                      uint32_t key1, uint32_t* __restrict__ mask,
-                                                     int32_t* sstat) {
+                                                     int32_t* sstat, int64_t row0) {
     __shared__ uint32_t hist_all[kSplitWaves][256];
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const SplitLds L(max_np);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * kSplitWaves + wave;
+    const int64_t row = (int64_t)blockIdx.x * kSplitWaves + wave + row0;
     if (row >= rows) return;
     unsigned char* base = smem + wave * L.total;
     uint32_t* hist = hist_all[wave];
@@ -278,8 +278,8 @@ size_t split_lds_per_block(int max_np) { return (size_t)kSplitWaves * SplitLds(m
 
 hipError_t launch_split_masks(const BlockPair* bp, int npairs,
                               int64_t rows, int max_np, uint64_t seed, uint32_t* mask,
-                              int32_t* sstat, int wg_per_cu, hipStream_t s) {
-    if (rows <= 0) return hipSuccess;
+                              int32_t* sstat, int wg_per_cu, hipStream_t s, int64_t row0) {
+    if (rows <= row0) return hipSuccess;
     const SplitLds L(max_np);
     // four split rows per work-group; at most 64 KB of LDS per work-group
     size_t lds = (size_t)kSplitWaves * L.total;
@@ -288,11 +288,11 @@ hipError_t launch_split_masks(const BlockPair* bp, int npairs,
         if (share > lds + kSplitStaticLds) lds = share - kSplitStaticLds;
     }
     if (lds + kSplitStaticLds > 65536 || lds + kSplitStaticLds > split_lds_limit()) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((rows + kSplitWaves - 1) / kSplitWaves)), block(64 * kSplitWaves);
+    const dim3 grid((unsigned)((rows - row0 + kSplitWaves - 1) / kSplitWaves)), block(64 * kSplitWaves);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     // registers for the keys of the largest pair: R blocks of 16 per lane
     const int r = (max_np + 1023) / 1024;
-#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, bp, npairs, rows, max_np, k0, k1, mask, sstat)
+#define HBT_SPLIT(RR) hipLaunchKernelGGL(k_split_masks<RR>, grid, block, lds, s, bp, npairs, rows, max_np, k0, k1, mask, sstat, row0)
     if (r <= 1) HBT_SPLIT(1);
     else if (r <= 2) HBT_SPLIT(2);
     else if (r <= 4) HBT_SPLIT(4);

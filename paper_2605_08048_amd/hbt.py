@@ -99,6 +99,8 @@ def lib():
         L.hbt_tile_widths.argtypes = [i64, P, i64, P]
         L.hbt_recheck_band.argtypes = [i32, i32, i32, i64, i64, i64, dbl, dbl, P]
         L.hbt_perm_test_static.argtypes = [P, P, C.POINTER(HbtPermParams), P, P, P, P]
+        L.hbt_pipeline_chunks.argtypes = [i32, P]
+        L.hbt_pipeline_chunks.restype = i32
         L.hbt_perm_test_static.restype = i32
         for f in ["hbt_tune_batched", "hbt_tune_get", "hbt_tune_set", "hbt_tile_widths", "hbt_recheck_band"]:
             getattr(L, f).restype = i32
@@ -289,6 +291,14 @@ def perm_test(X, Y, B, *, seed=0, perm_offset=0, pair_index=0, precision="f32", 
     if mo is not None:
         r["masks"] = mo.cpu().numpy().view(np.uint32)
     return r
+
+
+def pipeline_chunks(chunks):
+    """Set the number of pipeline chunks of later batched calls (0 = default);
+    returns the previous setting."""
+    prev = C.c_int32()
+    _check(lib().hbt_pipeline_chunks(int(chunks), C.byref(prev)))
+    return prev.value
 
 
 def recheck_band(precision, n, m, d, r1, r2, *, stat_route=0, gd="banerjee"):

@@ -513,6 +513,25 @@ def test_batched_call_replays_from_a_hip_graph():
         assert np.all(other["status"] == 0)
 
 
+@pytest.mark.parametrize("prec", ["bf16x2", "i8x3"])
+def test_pipeline_chunks_do_not_change_results(prec):
+    """The batched call pipelines chunks of pairs over three streams; every
+    chunking gives the same results, bit for bit, as one chunk."""
+    print(f"pipeline chunks {prec}: 60 pairs of the 512-pair workload", flush=True)
+    b = synth.batch_512_d768(limit=range(60))
+    Z = _dev(b.Z)
+    prev = hbt.pipeline_chunks(1)
+    try:
+        ref = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
+        for c in (2, 3, 4, 7, 60):
+            hbt.pipeline_chunks(c)
+            got = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
+            _results_equal(got, ref)
+    finally:
+        hbt.pipeline_chunks(prev)
+    assert np.all(ref["status"] == 0)
+
+
 # --------------------------------------------------------------------- tile widths
 
 def _results_equal(a, b):
