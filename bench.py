@@ -247,7 +247,7 @@ def main():
                     help="timed replays of the split-BF16 call captured as a HIP graph (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
-                    help="skip the (untimed) tile-width tuning of the split-BF16 product")
+                    help="skip the (untimed) autotuning of the launch parameters")
     ap.add_argument("--counter-precision", default="bf16x2", help="precision of the --counter-pass calls")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run the batched path twice and a 1 GiB copy, for rocprofv3 --pmc")
@@ -285,11 +285,14 @@ def main():
     L = hbt.lib()
     tuning = None
     if not args.no_tune:
-        costs = hbt.tune_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed)
-        widths = hbt.tile_widths(batch.B, d)
-        tuning = {"cost_per_split_row_ms": {"1024": costs[0], "256": costs[1]},
-                  "pairs_at_256": int(np.sum(widths == 256))}
-        log(f"tile widths tuned: {tuning}")
+        # the autotuner (untimed): tile widths, persistent grids, split
+        # work-groups per CU and pipeline chunks, per precision
+        tuning = {}
+        for prec in ("bf16x2", "i8x3"):
+            hbt.tune_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed, precision=prec)
+            tuning[prec] = hbt.tune_entry_get(prec, d)
+        tuning["pairs_at_256"] = int(np.sum(hbt.tile_widths(batch.B, d) == 256))
+        log(f"tuned: {tuning}")
 
     def run(prec, steps, warmup):
         res = torch.zeros(hbt.RESULT_BYTES * P, dtype=torch.uint8, device=dev)
@@ -444,7 +447,7 @@ def main():
         "fp32_plain": fp,
         "int8_planes": i8,
         "single_pair": single,
-        "tile_tuning": tuning,
+        "tuning": tuning,
         "stage_errors_null_pair_d1024": errors,
         "context": PAPER_CONTEXT,
     }

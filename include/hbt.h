@@ -209,9 +209,9 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
  * (the product of one chunk runs while the next is aligned and split, on
  * three streams joined by events; split BF16 and int8 planes with FP32 rows,
  * d a multiple of 4 and at most 1024, 16-byte aligned rows; other calls run
- * as one chunk).  chunks = 1 turns the pipeline off, 0 restores the default
- * (4); *previous (nullable) receives the setting it replaces.  Process-wide,
- * for later calls; results do not depend on it.
+ * as one chunk).  chunks = 1 turns the pipeline off, 0 returns to the tuned
+ * value (default 1); *previous (nullable) receives the setting it replaces.  Process-wide,
+ * for later calls, overriding the tuned value; results do not depend on it.
  * Errors: HBT_ERR_ARG (chunks outside [0, 64]). */
 hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous);
 
@@ -266,36 +266,63 @@ typedef enum hbt_stage {
 hbt_status hbt_stage_timing(int32_t enable);
 hbt_status hbt_stage_times(double* ms, int64_t* launches);
 
-/* Tile widths of the split-BF16 product (the batching of Sec. 3.2's practical
- * notes over many pairs).  A work-group of the product covers 64 columns of Z
- * and 1024 splits of one pair (eight waves) or 256 (four waves).  Every call
- * picks, per pair (per block
- * for hbt_perm_test), the width w minimising cost_w * round_up(B, w), with
- * per-split costs for the pair's dimension (padded to 64) from a table in the
- * library; until tuned, cost_1024 = 1 and cost_256 = 1.15.  A single-pair
- * call takes the narrow width when its block's wide tiles would number fewer
- * than two per compute unit (one pair alone must fill the GPU).  Results do not
- * depend on the width.
- *   hbt_tune_batched: runs hbt_perm_test_batched on its arguments four
- *     times, every pair at width 1024, 256, 1024, 256, times the product with
- *     HIP events and stores, per width, the smaller of its two
- *     cost_w = time / sum_p round_up(B_p, w) * round_up(n_p + m_p, 128) for
- *     this d (the first call also pays first-touch and clock ramp-up).  It
- *     synchronises the stream, clears the stage-timing record, and leaves the
- *     last run's results in `results`.  Split BF16 only (HBT_ERR_ARG
- *     otherwise).
- *   hbt_tune_get / hbt_tune_set: the table entry for d (costs[0] for width
- *     1024, costs[1] for 256; tuned = 1 once set), e.g. to keep a cache across
- *     processes.
- *   hbt_tile_widths: the widths (host, npairs entries) a call with these
- *     per-pair B would use at dimension d.
- * Errors: HBT_ERR_ARG, HBT_ERR_SIZE, and those of hbt_perm_test_batched. */
+/* Tuned launch parameters (the batching of Sec. 3.2's practical notes over
+ * many pairs), one entry per (precision, d padded to 64):
+ *   cost[2]     per-split costs of the two tile widths of the split-BF16
+ *               product: a work-group covers 64 columns of Z and 1024
+ *               splits of one pair (eight waves) or 256 (four waves).  Every
+ *               call picks, per pair (per block for hbt_perm_test), the
+ *               width w minimising cost_w * round_up(B, w); until tuned
+ *               cost_1024 = 1 and cost_256 = 1.15.  A single-pair call takes
+ *               the narrow width when its block's wide tiles would number
+ *               fewer than two per compute unit (one pair must fill the GPU).
+ *   grid_wide   work-groups per compute unit of the persistent 1024-split
+ *               launch (default 16);
+ *   grid_narrow the same for the 256-split split-BF16 launch (default 32) or
+ *               the int8-plane launch (default 16);
+ *   split_cap   split-stage work-groups per compute unit while it runs
+ *               beside the alignment (default 6);
+ *   chunks      pipeline chunks of the batched call (default 1; see
+ *               hbt_pipeline_chunks).
+ * No result depends on any of them.
+ *   hbt_tune_batched: measures them on the caller's workload (split BF16 or
+ *     int8 planes, common->precision) with HIP events, every candidate
+ *     twice keeping the faster: the widths (every pair forced to each;
+ *     cost_w = product time / sum_p round_up(B_p, w) round_up(n_p + m_p,
+ *     128)), then the grids of the launches the workload uses (wide 4, 8,
+ *     16, 32; narrow 8, 16, 32, 64; by product time), then split_cap (4, 5,
+ *     6, 8) and chunks (1, 2, 4) by whole-call time.  About 30 calls of
+ *     hbt_perm_test_batched on its arguments; it synchronises the stream,
+ *     clears the stage-timing record, installs the entry and leaves the
+ *     results of a last call with the chosen parameters in `results`.  When
+ *     the environment variable HBT_TUNE_CACHE names a file, the tuned
+ *     entries are written to it (JSON), and the library reads it on first
+ *     use in every process.
+ *   hbt_tune_entry_get / hbt_tune_entry_set: one entry (tuned = 1 once
+ *     measured, set or loaded).
+ *   hbt_tune_get / hbt_tune_set: only the split-BF16 costs of dimension d
+ *     (costs[0] for width 1024, costs[1] for 256).
+ *   hbt_tune_save / hbt_tune_load: every tuned entry to / from a JSON file
+ *     (the format HBT_TUNE_CACHE uses); a malformed file changes nothing.
+ *   hbt_tile_widths: the split-BF16 widths (host, npairs entries) a call
+ *     with these per-pair B would use at dimension d.
+ * Errors: HBT_ERR_ARG (bad pointer, precision, value or file), HBT_ERR_SIZE,
+ * and those of hbt_perm_test_batched. */
+typedef struct hbt_tune_entry {
+    double cost[2];
+    int32_t grid_wide, grid_narrow, split_cap, chunks;
+    int32_t tuned, _pad;
+} hbt_tune_entry;  /* 40 bytes */
 hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* row_offset,
                             const int64_t* n, const int64_t* m, const int64_t* B,
                             const uint32_t* pair_index, int64_t d, const hbt_perm_params* common,
                             hbt_result* results, void* ws, size_t ws_bytes, void* stream);
+hbt_status hbt_tune_entry_get(int32_t precision, int64_t d, hbt_tune_entry* entry);
+hbt_status hbt_tune_entry_set(int32_t precision, int64_t d, const hbt_tune_entry* entry);
 hbt_status hbt_tune_get(int64_t d, double* costs, int32_t* tuned);
 hbt_status hbt_tune_set(int64_t d, const double* costs);
+hbt_status hbt_tune_save(const char* path);
+hbt_status hbt_tune_load(const char* path);
 hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t* widths);
 
 /* ------------------------------------------------------------------------

@@ -78,7 +78,6 @@ struct StageTimer {
 };
 
 constexpr int64_t kAutoBlock = 32768;  // splits per block when block_perms == 0
-constexpr int kPipelineChunks = 1;     // pipeline chunks of a batched call (1: no pipeline)
 
 int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
 
@@ -165,6 +164,18 @@ struct Workspace {
     size_t bytes;
 };
 
+// Tuned launch parameters (see tile_cost).
+struct TileCost {
+    double c[2];      // [0]: kTileWide-split tiles, [1]: 256-split tiles
+    int grid_wide;    // persistent work-groups per CU, 1024-split launch
+    int grid_narrow;  // ... 256-split split-BF16 or int8 launch
+    int split_cap;    // split work-groups per CU beside the alignment
+    int chunks;       // pipeline chunks of the batched call
+    bool tuned;
+};
+TileCost default_tune(int precision) {
+    return TileCost{{1.0, 1.15}, 16, precision == HBT_I8X3 ? 16 : 32, kSplitWgPerCuBesideAlign, 1, false};
+}
 struct Plan {
     int npairs = 0;
     int d = 0, d_pad = 0, nslot = 0;
@@ -196,6 +207,7 @@ struct Plan {
         int64_t ntw, nt256;
     };
     std::vector<Chunk> cplan;
+    TileCost tune = default_tune(HBT_BF16X2);  // launch parameters of (precision, d_pad)
 };
 
 Workspace carve(const Plan& P, void* ws) {
@@ -321,31 +333,105 @@ hbt_status check_sizes(int64_t n, int64_t m, int64_t d, int64_t B, uint64_t perm
     return HBT_OK;
 }
 
+TileCost tile_cost(int d_pad, int precision);
+
 void finish_plan(Plan& P, int64_t d, int precision, int input_dtype) {
     P.d = (int)d;
     P.d_pad = (int)round_up(d, kDPad);
     P.nslot = P.d_pad / kDSlot;
     P.precision = precision;
     P.input_dtype = input_dtype;
+    P.tune = tile_cost(P.d_pad, precision);
 }
 
 // ---------------------------------------------------------------------------
-// Tile width of the split-BF16 product: per pair (or per block of one pair),
-// the width w in {kTileWide, 256} minimising cost_w * round_up(B, w); per-split
-// costs come from a table keyed by d_pad (hbt_tune_batched fills it).
+// Tuned launch parameters, per (precision, d_pad): the per-split costs of the
+// two tile widths of the split-BF16 product (per pair, or per block of one
+// pair, the width w in {kTileWide, 256} minimising cost_w * round_up(B, w)),
+// the persistent grids of the product launches, the split stage's
+// work-groups per CU beside the alignment and the pipeline chunks of the
+// batched call.  hbt_tune_batched measures them on the caller's workload;
+// HBT_TUNE_CACHE names a JSON file that is read on first use and written
+// after each tuning.
 // ---------------------------------------------------------------------------
-struct TileCost {
-    double c[2];   // [0]: kTileWide-split tiles, [1]: 256-split tiles
-    bool tuned;
-};
 std::mutex g_tune_mu;
-std::map<int, TileCost> g_tune;
+std::map<std::pair<int, int>, TileCost> g_tune;  // (precision, d_pad)
 thread_local int g_force_width = 0;  // 0: choose; kTileWide or 256: every pair (tuning runs)
+int tune_load_locked(const char* path);
+void tune_cache_once_locked() {
+    static bool done = false;
+    if (done) return;
+    done = true;
+    const char* path = getenv("HBT_TUNE_CACHE");
+    if (path && *path) (void)tune_load_locked(path);
+}
 
-TileCost tile_cost(int d_pad) {
+TileCost tile_cost(int d_pad, int precision) {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    auto it = g_tune.find(d_pad);
-    return it != g_tune.end() ? it->second : TileCost{{1.0, 1.15}, false};
+    tune_cache_once_locked();
+    auto it = g_tune.find({precision, d_pad});
+    return it != g_tune.end() ? it->second : default_tune(precision);
+}
+
+// JSON cache: {"hbt_tune_version": 1, "entries": [{"precision": p, "d_pad":
+// D, "cost": [c0, c1], "grid_wide": g, "grid_narrow": g, "split_cap": s,
+// "chunks": k}, ...]}, one entry per line.
+int tune_save_locked(const char* path) {
+    FILE* f = fopen(path, "w");
+    if (!f) return -1;
+    fprintf(f, "{\"hbt_tune_version\": 1, \"entries\": [");
+    bool first = true;
+    for (const auto& kv : g_tune) {
+        const TileCost& t = kv.second;
+        if (!t.tuned) continue;
+        fprintf(f, "%s\n {\"precision\": %d, \"d_pad\": %d, \"cost\": [%.17g, %.17g], \"grid_wide\": %d, "
+                   "\"grid_narrow\": %d, \"split_cap\": %d, \"chunks\": %d}",
+                first ? "" : ",", kv.first.first, kv.first.second, t.c[0], t.c[1], t.grid_wide, t.grid_narrow,
+                t.split_cap, t.chunks);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    return fclose(f) == 0 ? 0 : -1;
+}
+
+bool tune_valid(const TileCost& t) {
+    return t.c[0] > 0.0 && t.c[1] > 0.0 && t.grid_wide >= 1 && t.grid_wide <= 256 && t.grid_narrow >= 1 &&
+           t.grid_narrow <= 256 && t.split_cap >= 1 && t.split_cap <= 16 && t.chunks >= 1 && t.chunks <= 64;
+}
+
+// Reads the entries of a file written by tune_save_locked; returns the number
+// read, or -1 when the file cannot be read or holds a malformed entry (then
+// nothing is changed).
+int tune_load_locked(const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return -1;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+    fclose(f);
+    if (text.find("\"hbt_tune_version\": 1") == std::string::npos) return -1;
+    std::vector<std::pair<std::pair<int, int>, TileCost>> got;
+    size_t pos = text.find('[');
+    while (pos != std::string::npos && (pos = text.find('{', pos + 1)) != std::string::npos) {
+        const size_t end = text.find('}', pos);
+        if (end == std::string::npos) return -1;
+        const std::string e = text.substr(pos, end - pos + 1);
+        int prec, dp;
+        TileCost t{};
+        t.tuned = true;
+        if (sscanf(e.c_str(),
+                   "{\"precision\": %d, \"d_pad\": %d, \"cost\": [%lf, %lf], \"grid_wide\": %d, "
+                   "\"grid_narrow\": %d, \"split_cap\": %d, \"chunks\": %d}",
+                   &prec, &dp, &t.c[0], &t.c[1], &t.grid_wide, &t.grid_narrow, &t.split_cap, &t.chunks) != 8)
+            return -1;
+        if (prec < HBT_F64 || prec > HBT_I8X3 || dp < kDPad || dp > HBT_MAX_D || dp % kDPad || !tune_valid(t))
+            return -1;
+        got.push_back({{prec, dp}, t});
+        pos = end;
+    }
+    for (const auto& kv : got) g_tune[kv.first] = kv.second;
+    return (int)got.size();
 }
 
 int choose_width(int64_t B, const TileCost& tc) {
@@ -359,7 +445,7 @@ int choose_width(int64_t B, const TileCost& tc) {
 // one pipeline chunk: its wide groups, then its narrow ones, tiles numbered
 // from 0 within each width.
 void add_groups(Plan& P, const std::vector<int>& order, const int64_t* B, int pa, int pb) {
-    const TileCost tc = tile_cost(P.d_pad);
+    const TileCost& tc = P.tune;
     Plan::Chunk c{pa, pb, (int)P.groups.size(), 0, 0, 0, 0};
     std::vector<GemmGroup> g2;
     for (int p : order) {
@@ -586,7 +672,7 @@ hbt_status batched_pipelined(const Plan& P, const Workspace& w, const hbt_perm_p
         {
             StageTimer t_(HBT_STAGE_SPLIT, qs);
             HIP_TRY(launch_split_masks(w.bp, np, r1, P.max_np, common->seed, w.mask, w.sstat,
-                                       kSplitWgPerCuBesideAlign, qs, r0));
+                                       P.tune.split_cap, qs, r0));
         }
         HIP_TRY(ev.record(qs, &es));
         {
@@ -607,7 +693,7 @@ hbt_status batched_pipelined(const Plan& P, const Workspace& w, const hbt_perm_p
             HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, 0, w.groups + c.g0, c.ngw,
                                     (int)c.ntw, c.ng256, (int)c.nt256, P.d_pad, w.zstore,
                                     P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
-                                    nullptr, qg));
+                                    nullptr, qg, P.tune.grid_wide, P.tune.grid_narrow));
         }
     }
     hipEvent_t ej;
@@ -765,7 +851,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     // changes a result).
     auto block_width = [&](int64_t nb) {
         if (P.precision == HBT_I8X3) return kTileI8;
-        const int w = choose_width(nb, tile_cost(P.d_pad));
+        const int w = choose_width(nb, P.tune);
         if (w == kTileWide && !g_force_width &&
             (nb + kTileWide - 1) / kTileWide * P.nslot < 2 * (int64_t)device_cus())
             return kTileNarrow;
@@ -783,7 +869,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     auto block_splits = [&](int64_t b0, int64_t nb, hipStream_t q) -> hipError_t {
         if (prm->masks) return launch_copy_masks(prm->masks, b0, nb, N, (int)prm->n, pd.Wp, w.mask, w.sstat, q);
         return launch_split_masks(w.bp, 1, nb, P.max_np, prm->seed, w.mask, w.sstat,
-                                  kSplitWgPerCuBesideAlign, q);
+                                  P.tune.split_cap, q);
     };
     {
         // The plan tables and block 0's tables sit next to each other at the
@@ -848,7 +934,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
             HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == kTileWide,
                                     wdt == kTileWide ? nt : 0, wdt != kTileWide, wdt != kTileWide ? nt : 0, P.d_pad,
                                     w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
-                                    P.block_rows, w.sig, s));
+                                    P.block_rows, w.sig, s, P.tune.grid_wide, P.tune.grid_narrow));
             if (P.route2)
                 HIP_TRY(launch_centroid(w.pairs, w.bp, w.ctiles, (int)((nb + kTileB - 1) / kTileB),
                                         P.ntile_i, P.d_pad, z32, w.sig, w.mask, w.zt, w.partial2,
@@ -876,11 +962,12 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 
 // ---------------------------------------------------------------------------
 // Number of pipeline chunks of a batched call (1 = no pipeline).
-int g_pipeline_chunks = kPipelineChunks;
+int g_pipeline_chunks = 0;  // process-wide override (hbt_pipeline_chunks); 0: the tuned value
 int pipeline_chunks(const Plan& P, int64_t npairs) {
     if (!(P.precision == HBT_BF16X2 || P.precision == HBT_I8X3) || !vector_rows(P) || !P.need_store)
         return 1;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g_pipeline_chunks, npairs));
+    const int c = g_pipeline_chunks > 0 ? g_pipeline_chunks : P.tune.chunks;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(c, npairs));
 }
 
 static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64_t* row_offset,
@@ -1000,7 +1087,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     // group sizes (integer VALU work beside HBM-bound work); a third uploads
     // the tables only the later stages read.  The table uploads are chains of
     // small kernels (a few microseconds each), so no chain waits for another.
-    // At most 6 split work-groups per CU (kSplitWgPerCuBesideAlign) leave
+    // At most 6 split work-groups per CU (the default split_cap) leave
     // wave slots to the alignment kernels (measured on 512 pairs, d = 768,
     // split BF16: 8.03 ms per call at 8 or uncapped, where the alignment
     // then waits for wave slots; 7.25 ms at 6, the two stages 2.1 ms each;
@@ -1018,7 +1105,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), qs));
         HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, qs));
         HIP_TRY(launch_split_masks(w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
-                                   kSplitWgPerCuBesideAlign, qs));
+                                   P.tune.split_cap, qs));
     }
     {
         StageTimer t_(HBT_STAGE_OTHER, qt);
@@ -1048,7 +1135,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
                                 P.ngw, (int)P.ntw, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
                                 P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
-                                nullptr, s));
+                                nullptr, s, P.tune.grid_wide, P.tune.grid_narrow));
     }
     return batched_epilogue(P, w, common, results, s);
 }
@@ -1153,7 +1240,7 @@ hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t*
     g_err.clear();
     if (!B || !widths) return fail(HBT_ERR_ARG, "NULL pointer");
     if (npairs < 1 || d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "npairs %lld, d %lld", (long long)npairs, (long long)d);
-    const TileCost tc = tile_cost((int)round_up(d, kDPad));
+    const TileCost tc = tile_cost((int)round_up(d, kDPad), HBT_BF16X2);
     for (int64_t p = 0; p < npairs; ++p) {
         if (B[p] < 1) return fail(HBT_ERR_SIZE, "B[%lld] = %lld", (long long)p, (long long)B[p]);
         widths[p] = choose_width(B[p], tc);
@@ -1166,7 +1253,7 @@ hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous) {
     if (chunks < 0 || chunks > 64) return fail(HBT_ERR_ARG, "chunks = %d (0 ... 64)", chunks);
     std::lock_guard<std::mutex> g(g_tune_mu);
     if (previous) *previous = g_pipeline_chunks;
-    g_pipeline_chunks = chunks == 0 ? kPipelineChunks : chunks;
+    g_pipeline_chunks = chunks;
     return HBT_OK;
 }
 
@@ -1188,7 +1275,7 @@ hbt_status hbt_tune_get(int64_t d, double* costs, int32_t* tuned) {
     g_err.clear();
     if (!costs) return fail(HBT_ERR_ARG, "NULL pointer");
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
-    const TileCost tc = tile_cost((int)round_up(d, kDPad));
+    const TileCost tc = tile_cost((int)round_up(d, kDPad), HBT_BF16X2);
     costs[0] = tc.c[0];
     costs[1] = tc.c[1];
     if (tuned) *tuned = tc.tuned ? 1 : 0;
@@ -1201,7 +1288,63 @@ hbt_status hbt_tune_set(int64_t d, const double* costs) {
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
     if (!(costs[0] > 0.0) || !(costs[1] > 0.0)) return fail(HBT_ERR_ARG, "costs must be positive");
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[(int)round_up(d, kDPad)] = TileCost{{costs[0], costs[1]}, true};
+    tune_cache_once_locked();
+    const std::pair<int, int> key{HBT_BF16X2, (int)round_up(d, kDPad)};
+    auto it = g_tune.find(key);
+    TileCost t = it != g_tune.end() ? it->second : default_tune(HBT_BF16X2);
+    t.c[0] = costs[0];
+    t.c[1] = costs[1];
+    t.tuned = true;
+    g_tune[key] = t;
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_entry_get(int32_t precision, int64_t d, hbt_tune_entry* e) {
+    g_err.clear();
+    if (!e) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (precision < HBT_F64 || precision > HBT_I8X3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
+    const TileCost t = tile_cost((int)round_up(d, kDPad), precision);
+    memset(e, 0, sizeof *e);
+    e->cost[0] = t.c[0];
+    e->cost[1] = t.c[1];
+    e->grid_wide = t.grid_wide;
+    e->grid_narrow = t.grid_narrow;
+    e->split_cap = t.split_cap;
+    e->chunks = t.chunks;
+    e->tuned = t.tuned ? 1 : 0;
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_entry_set(int32_t precision, int64_t d, const hbt_tune_entry* e) {
+    g_err.clear();
+    if (!e) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (precision < HBT_F64 || precision > HBT_I8X3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
+    const TileCost t{{e->cost[0], e->cost[1]}, e->grid_wide, e->grid_narrow, e->split_cap, e->chunks, true};
+    if (!tune_valid(t))
+        return fail(HBT_ERR_ARG, "costs must be positive, grids in [1, 256], split_cap in [1, 16], chunks in [1, 64]");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache_once_locked();
+    g_tune[{precision, (int)round_up(d, kDPad)}] = t;
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_save(const char* path) {
+    g_err.clear();
+    if (!path) return fail(HBT_ERR_ARG, "NULL path");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache_once_locked();
+    if (tune_save_locked(path) != 0) return fail(HBT_ERR_ARG, "cannot write %s", path);
+    return HBT_OK;
+}
+
+hbt_status hbt_tune_load(const char* path) {
+    g_err.clear();
+    if (!path) return fail(HBT_ERR_ARG, "NULL path");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache_once_locked();
+    if (tune_load_locked(path) < 0) return fail(HBT_ERR_ARG, "cannot read %s or it is malformed", path);
     return HBT_OK;
 }
 
@@ -1211,36 +1354,140 @@ hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* ro
                             hbt_result* results, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     if (!common || !B || !n || !m) return fail(HBT_ERR_ARG, "NULL argument");
-    if (common->precision != HBT_BF16X2)
-        return fail(HBT_ERR_ARG, "tile widths are tuned for the split-BF16 product only");
+    const int prec = common->precision;
+    if (prec != HBT_BF16X2 && prec != HBT_I8X3)
+        return fail(HBT_ERR_ARG, "tuning covers the split-BF16 and int8-plane products only");
     if (npairs < 1 || d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "npairs %lld, d %lld", (long long)npairs, (long long)d);
-    const int widths[2] = {kTileWide, 256};
-    double cost[2] = {0.0, 0.0};
-    // each width twice, interleaved, keeping the faster call: the first call
-    // also pays first-touch and clock ramp-up
-    for (int q = 0; q < 4; ++q) {
-        const int k = q & 1;
-        // per-split work of this width: padded splits times pooled rows
-        double units = 0.0;
-        for (int64_t p = 0; p < npairs; ++p)
-            units += (double)round_up(B[p], widths[k]) * (double)round_up(n[p] + m[p], kRowPad);
+    const int d_pad = (int)round_up(d, kDPad);
+    hipStream_t s = (hipStream_t)stream;
+    TileCost best = tile_cost(d_pad, prec);
+    auto install = [&](const TileCost& t) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[{prec, d_pad}] = t;
+    };
+    auto call = [&]() {
+        return hbt_perm_test_batched(npairs, Z_all, row_offset, n, m, B, pair_index, d, common, results, ws,
+                                     ws_bytes, stream);
+    };
+    // one measured call: the product's time (stage events) and the whole call's
+    auto measure = [&](double* product_ms, double* call_ms) -> hbt_status {
         hbt_status st = hbt_stage_timing(1);
         if (st) return st;
-        g_force_width = widths[k];
-        st = hbt_perm_test_batched(npairs, Z_all, row_offset, n, m, B, pair_index, d, common, results,
-                                   ws, ws_bytes, stream);
-        g_force_width = 0;
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        HIP_TRY(hipEventRecord(a, s));
+        st = call();
+        HIP_TRY(hipEventRecord(b, s));
         double ms[HBT_NUM_STAGES];
         int64_t launches[HBT_NUM_STAGES];
         const hbt_status st2 = hbt_stage_times(ms, launches);
         hbt_stage_timing(0);
+        HIP_TRY(hipEventSynchronize(b));
+        float total = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&total, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
         if (st) return st;
         if (st2) return st2;
         if (!(ms[HBT_STAGE_GROUPSUM] > 0.0)) return fail(HBT_ERR_DEVICE, "no timing of the product");
-        const double c = ms[HBT_STAGE_GROUPSUM] / units;
-        cost[k] = q < 2 ? c : std::min(cost[k], c);
+        *product_ms = ms[HBT_STAGE_GROUPSUM];
+        *call_ms = total;
+        return HBT_OK;
+    };
+    // every candidate twice, keeping the faster call (the first call of a
+    // setting may pay first-touch or clock ramp-up)
+    auto best_of_two = [&](const TileCost& t, double* product_ms, double* call_ms) -> hbt_status {
+        install(t);
+        double p0, c0, p1, c1;
+        hbt_status st = measure(&p0, &c0);
+        if (!st) st = measure(&p1, &c1);
+        if (st) return st;
+        *product_ms = std::min(p0, p1);
+        *call_ms = std::min(c0, c1);
+        return HBT_OK;
+    };
+    const int saved_chunks = g_pipeline_chunks;
+    g_pipeline_chunks = 0;
+    hbt_status st = HBT_OK;
+    // 1. tile widths (split BF16): per-split costs of each width with every
+    // pair forced to it
+    if (prec == HBT_BF16X2) {
+        const int widths[2] = {kTileWide, 256};
+        for (int k = 0; k < 2 && !st; ++k) {
+            double units = 0.0;  // padded splits times pooled rows
+            for (int64_t p = 0; p < npairs; ++p)
+                units += (double)round_up(B[p], widths[k]) * (double)round_up(n[p] + m[p], kRowPad);
+            g_force_width = widths[k];
+            double pm, cm;
+            st = best_of_two(best, &pm, &cm);
+            g_force_width = 0;
+            if (!st) best.c[k] = pm / units;
+        }
     }
-    return hbt_tune_set(d, cost);
+    // 2. persistent grids of the product launches this workload uses
+    {
+        double pm, cm;
+        if (!st) st = best_of_two(best, &pm, &cm);
+        double best_ms = pm;
+        const int wide[] = {4, 8, 16, 32};
+        const int narrow[] = {8, 16, 32, 64};
+        bool any_wide = false, any_narrow = prec == HBT_I8X3;
+        for (int64_t p = 0; p < npairs && prec == HBT_BF16X2; ++p) {
+            const int w = choose_width(B[p], best);
+            any_wide |= w == kTileWide;
+            any_narrow |= w != kTileWide;
+        }
+        for (int g : wide) {
+            if (st || !any_wide) break;
+            TileCost t = best;
+            t.grid_wide = g;
+            st = best_of_two(t, &pm, &cm);
+            if (!st && pm < best_ms) { best_ms = pm; best = t; }
+        }
+        for (int g : narrow) {
+            if (st || !any_narrow) break;
+            TileCost t = best;
+            t.grid_narrow = g;
+            st = best_of_two(t, &pm, &cm);
+            if (!st && pm < best_ms) { best_ms = pm; best = t; }
+        }
+    }
+    // 3. split work-groups per CU beside the alignment, then 4. pipeline
+    // chunks: whole-call time
+    {
+        double pm, cm;
+        if (!st) st = best_of_two(best, &pm, &cm);
+        double best_call = cm;
+        for (int c : {4, 5, 6, 8}) {
+            if (st) break;
+            TileCost t = best;
+            t.split_cap = c;
+            st = best_of_two(t, &pm, &cm);
+            if (!st && cm < best_call) { best_call = cm; best = t; }
+        }
+        for (int k : {1, 2, 4}) {
+            if (st) break;
+            TileCost t = best;
+            t.chunks = k;
+            st = best_of_two(t, &pm, &cm);
+            if (!st && cm < best_call) { best_call = cm; best = t; }
+        }
+    }
+    g_pipeline_chunks = saved_chunks;
+    if (st) return st;
+    best.tuned = true;
+    install(best);
+    // a last call with the chosen parameters leaves its results in `results`
+    st = call();
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    const char* path = getenv("HBT_TUNE_CACHE");
+    if (path && *path) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        if (tune_save_locked(path) != 0) return fail(HBT_ERR_ARG, "cannot write the tuning cache %s", path);
+    }
+    return HBT_OK;
 }
 
 // hbt_perm_test on the library's own scratch.  The scratch address of each

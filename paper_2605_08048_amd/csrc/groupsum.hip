@@ -677,8 +677,11 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngw,
                            int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
-                           const double* t64, double* partial, int64_t prow, float* sig, hipStream_t s) {
+                           const double* t64, double* partial, int64_t prow, float* sig, hipStream_t s,
+                           int grid_wide, int grid_narrow) {
     const int nslot = d_pad / kDSlot;
+    if (grid_wide <= 0) grid_wide = 16;
+    if (grid_narrow <= 0) grid_narrow = precision == HBT_I8X3 ? 16 : 32;
     dim3 block(256);
     switch (precision) {
         case HBT_BF16X2: {
@@ -686,18 +689,18 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
             static_assert(32 * 4 * 8 == kTileWide && 32 * 2 * 4 == kTileNarrow, "tile widths");
             if (ntw > 0)
-                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8>), dim3(persistent_grid(ntw, 16)), dim3(512), 0,
+                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8>), dim3(persistent_grid(ntw, grid_wide)), dim3(512), 0,
                                    s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
                                    t32, partial, prow, sig);
             if (nt256 > 0)
-                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4>), dim3(persistent_grid(nt256, 32)), block, 0,
+                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4>), dim3(persistent_grid(nt256, grid_narrow)), block, 0,
                                    s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
                                    mask, t32, partial, prow, sig);
             break;
         }
         case HBT_I8X3:
             if (nt256 > 0)
-                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, 16)), dim3(512), 0, s,
+                hipLaunchKernelGGL(k_groupsum_i8x3, dim3(persistent_grid(nt256, grid_narrow)), dim3(512), 0, s,
                                    pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, (const uint4*)zstore,
                                    zplane_elems / 16, mask, t64, partial, prow);
             break;

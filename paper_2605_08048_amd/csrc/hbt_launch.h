@@ -103,7 +103,10 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig,
-                           hipStream_t s);
+                           hipStream_t s, int grid_wide = 16, int grid_narrow = 0);
+// grid_wide / grid_narrow: persistent work-groups per CU of the 1024-split
+// launch and of the 256-split (or int8) launch (0: 32 for the 256-split
+// split-BF16 kernel, 16 for int8).
 
 // --- point-to-centroid route (statistic route 2) -------------------------
 // z_i . t per pooled row; then Q = Z S^T with the masked column sums

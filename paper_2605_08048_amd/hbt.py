@@ -44,8 +44,14 @@ class HbtPermParams(C.Structure):
                 ("flags", C.c_int32), ("block_perms", C.c_int64), ("masks", C.c_void_p)]
 
 
+class HbtTuneEntry(C.Structure):
+    _fields_ = [("cost", C.c_double * 2), ("grid_wide", C.c_int32), ("grid_narrow", C.c_int32),
+                ("split_cap", C.c_int32), ("chunks", C.c_int32), ("tuned", C.c_int32), ("_pad", C.c_int32)]
+
+
+TUNE_FIELDS = ("cost", "grid_wide", "grid_narrow", "split_cap", "chunks", "tuned")
 RESULT_BYTES = 112
-assert C.sizeof(HbtResult) == RESULT_BYTES and C.sizeof(HbtPermParams) == 96
+assert C.sizeof(HbtResult) == RESULT_BYTES and C.sizeof(HbtPermParams) == 96 and C.sizeof(HbtTuneEntry) == 40
 
 RESULT_DTYPE = np.dtype([("t_obs", "f8"), ("r_x", "f8"), ("r_y", "f8"), ("p", "f8"), ("tau", "f8"),
                          ("mu_cos", "f8"), ("t_mean", "f8"), ("t_sd", "f8"),
@@ -96,6 +102,12 @@ def lib():
         L.hbt_tune_batched.argtypes = [i64, P, P, P, P, P, P, i64, C.POINTER(HbtPermParams), P, P, sz, P]
         L.hbt_tune_get.argtypes = [i64, P, P]
         L.hbt_tune_set.argtypes = [i64, P]
+        L.hbt_tune_entry_get.argtypes = [i32, i64, C.POINTER(HbtTuneEntry)]
+        L.hbt_tune_entry_set.argtypes = [i32, i64, C.POINTER(HbtTuneEntry)]
+        L.hbt_tune_save.argtypes = [C.c_char_p]
+        L.hbt_tune_load.argtypes = [C.c_char_p]
+        for f in ["hbt_tune_entry_get", "hbt_tune_entry_set", "hbt_tune_save", "hbt_tune_load"]:
+            getattr(L, f).restype = i32
         L.hbt_tile_widths.argtypes = [i64, P, i64, P]
         L.hbt_recheck_band.argtypes = [i32, i32, i32, i64, i64, i64, dbl, dbl, P]
         L.hbt_perm_test_static.argtypes = [P, P, C.POINTER(HbtPermParams), P, P, P, P]
@@ -516,9 +528,12 @@ def budgets(mlp_out, results, p_lo, p_hi, b_min, b_max, zq=2.3263478740408408, s
 
 # ------------------------------------------------------------------ tile-width tuning
 
-def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="banerjee", workspace=None):
-    """Time both tile widths of the split-BF16 product on this batch and store
-    their per-split costs for its dimension; returns (cost_1024, cost_256)."""
+def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="banerjee", workspace=None,
+                 precision="bf16x2"):
+    """Measure the launch parameters of this batch's precision and dimension
+    (tile widths, persistent grids, split work-groups per CU, pipeline
+    chunks) and install them; returns the split-BF16 costs (cost_1024,
+    cost_256) for d (see tune_entry_get for the rest)."""
     torch = _torch()
     dev = Z_all.device
     P, off, nn, mm, BB, ids = _batch_tables(Z_all, row_offset, n, m, B, pair_index)
@@ -528,7 +543,7 @@ def tune_batched(Z_all, row_offset, n, m, B, *, seed=0, pair_index=None, gd="ban
             raise HbtError(ERR_ARG, "workspace must be a contiguous uint8 tensor")
     Z_all = Z_all.contiguous()
     d = Z_all.shape[1]
-    prm = make_params(0, 0, d, 0, seed=seed, precision="bf16x2", input_dtype=_input_dtype(Z_all), gd=gd)
+    prm = make_params(0, 0, d, 0, seed=seed, precision=precision, input_dtype=_input_dtype(Z_all), gd=gd)
     L = lib()
     ptr = lambda a: a.ctypes.data_as(C.c_void_p)
     need = L.hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm))
@@ -560,18 +575,29 @@ def tile_widths(B, d):
     return out
 
 
-def save_tuning(path, dims):
-    """Write the tuned costs of the given dimensions to a JSON file."""
-    import json
-    rec = {str(int(d)): list(tune_get(int(d))[0]) for d in dims if tune_get(int(d))[1]}
-    with open(path, "w") as f:
-        json.dump(rec, f, indent=1)
+def tune_entry_get(precision, d):
+    """The tuned launch parameters of (precision, d) as a dict."""
+    e = HbtTuneEntry()
+    _check(lib().hbt_tune_entry_get(PRECISION[precision], d, C.byref(e)))
+    return {"cost": (e.cost[0], e.cost[1]), "grid_wide": e.grid_wide, "grid_narrow": e.grid_narrow,
+            "split_cap": e.split_cap, "chunks": e.chunks, "tuned": bool(e.tuned)}
+
+
+def tune_entry_set(precision, d, entry):
+    e = HbtTuneEntry()
+    e.cost[0], e.cost[1] = (float(x) for x in entry["cost"])
+    for k in ("grid_wide", "grid_narrow", "split_cap", "chunks"):
+        setattr(e, k, int(entry[k]))
+    _check(lib().hbt_tune_entry_set(PRECISION[precision], d, C.byref(e)))
+
+
+def save_tuning(path):
+    """Write every tuned entry to a JSON file (the library's format, also the
+    HBT_TUNE_CACHE file)."""
+    _check(lib().hbt_tune_save(os.fsencode(str(path))))
 
 
 def load_tuning(path):
-    """Load costs written by save_tuning into the library's table."""
-    import json
-    with open(path) as f:
-        for d, c in json.load(f).items():
-            tune_set(int(d), c)
+    """Load entries written by save_tuning into the library's table."""
+    _check(lib().hbt_tune_load(os.fsencode(str(path))))
 

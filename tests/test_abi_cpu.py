@@ -2,6 +2,7 @@
 declared in include/hbt.h, and rejects bad arguments on the host before
 anything is enqueued (no compute call is made here)."""
 import ctypes as C
+import os
 import re
 from pathlib import Path
 
@@ -195,12 +196,54 @@ def test_tile_width_rule_and_tuning_table(tmp_path):
     hbt.tune_set(d, [1.0, 5.0])
     assert list(hbt.tile_widths(B, d)) == [1024] * len(B)
     assert hbt.tune_get(d) == ((1.0, 5.0), True)
-    # the JSON cache round-trips through the library's table
+    # whole entries, per precision; the JSON cache round-trips through the
+    # library's table
+    e = hbt.tune_entry_get("bf16x2", d)
+    assert e["cost"] == (1.0, 5.0) and e["tuned"] and (e["grid_wide"], e["grid_narrow"]) == (16, 32)
+    assert (e["split_cap"], e["chunks"]) == (6, 1)
+    i8 = hbt.tune_entry_get("i8x3", d)
+    assert not i8["tuned"] and i8["grid_narrow"] == 16
+    hbt.tune_entry_set("i8x3", d, dict(cost=(1.0, 1.0), grid_wide=8, grid_narrow=24, split_cap=5, chunks=2))
     f = tmp_path / "tune.json"
-    hbt.save_tuning(f, [d])
+    hbt.save_tuning(f)
     hbt.tune_set(d, [2.0, 1.0])
+    hbt.tune_entry_set("i8x3", d, dict(cost=(3.0, 3.0), grid_wide=1, grid_narrow=1, split_cap=1, chunks=1))
     hbt.load_tuning(f)
     assert hbt.tune_get(d) == ((1.0, 5.0), True)
+    got = hbt.tune_entry_get("i8x3", d)
+    assert (got["grid_wide"], got["grid_narrow"], got["split_cap"], got["chunks"]) == (8, 24, 5, 2)
+    # a malformed file changes nothing
+    bad = tmp_path / "bad.json"
+    bad.write_text(f.read_text().replace('"chunks": 2', '"chunks": 99'))
+    with pytest.raises(hbt.HbtError):
+        hbt.load_tuning(bad)
+    assert hbt.tune_entry_get("i8x3", d)["chunks"] == 2
+    with pytest.raises(hbt.HbtError):
+        hbt.tune_entry_set("i8x3", d, dict(cost=(1.0, 1.0), grid_wide=0, grid_narrow=24, split_cap=5, chunks=2))
     L = hbt.lib()
     assert L.hbt_tune_set(d, (C.c_double * 2)(1.0, -1.0)) == hbt.ERR_ARG
     assert L.hbt_tile_widths(1, (C.c_int64 * 1)(0), d, (C.c_int32 * 1)()) == hbt.ERR_SIZE
+
+
+def test_tuning_cache_is_read_on_first_use(tmp_path):
+    """HBT_TUNE_CACHE names a JSON file the library reads on first use."""
+    import subprocess
+    import sys
+    import textwrap
+    f = tmp_path / "cache.json"
+    f.write_text('{"hbt_tune_version": 1, "entries": [\n'
+                 ' {"precision": 2, "d_pad": 320, "cost": [2.5, 1.5], "grid_wide": 8, "grid_narrow": 4, '
+                 '"split_cap": 5, "chunks": 3}\n]}\n')
+    code = textwrap.dedent(f"""
+        import sys
+        sys.path.insert(0, {str(ROOT)!r})
+        from paper_2605_08048_amd import hbt
+        e = hbt.tune_entry_get("bf16x2", 300)
+        assert e == {{"cost": (2.5, 1.5), "grid_wide": 8, "grid_narrow": 4, "split_cap": 5, "chunks": 3,
+                      "tuned": True}}, e
+        assert not hbt.tune_entry_get("bf16x2", 1000)["tuned"]
+        print("ok")
+    """)
+    env = dict(os.environ, HBT_TUNE_CACHE=str(f))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr

@@ -651,3 +651,30 @@ def test_tuning_measures_both_widths():
     want = [256 if c256 * up(B, 256) < c1024 * up(B, 1024) else 1024 for B in Bs]
     assert list(hbt.tile_widths(Bs, 768)) == want
 
+
+@pytest.mark.parametrize("prec", ["bf16x2", "i8x3"])
+def test_tuner_picks_launch_parameters_from_its_candidates(prec, tmp_path):
+    """The tuner measures grids, split work-groups per CU and pipeline chunks
+    and installs them; the tuned calls give the untuned results; the entry
+    round-trips through the JSON cache."""
+    print(f"tuner {prec}", flush=True)
+    b = synth.batch_512_d768(limit=range(40))
+    Z = _dev(b.Z)
+    d = 768
+    before = hbt.tune_entry_get(prec, d)
+    ref = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
+    try:
+        hbt.tune_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
+        e = hbt.tune_entry_get(prec, d)
+        print(f"  tuned: {e}", flush=True)
+        assert e["tuned"] and e["grid_wide"] in (4, 8, 16, 32) and e["grid_narrow"] in (8, 16, 32, 64)
+        assert e["split_cap"] in (4, 5, 6, 8) and e["chunks"] in (1, 2, 4)
+        _results_equal(hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec), ref)
+        f = tmp_path / "tune.json"
+        hbt.save_tuning(f)
+        hbt.tune_entry_set(prec, d, dict(before, cost=(1.0, 1.15)))
+        hbt.load_tuning(f)
+        assert hbt.tune_entry_get(prec, d) == e
+    finally:
+        hbt.tune_entry_set(prec, d, before)
+
