@@ -404,6 +404,22 @@ hbt_status hbt_budgets(int64_t npairs, const float* mlp_out, const hbt_result* r
                        double p_lo, double p_hi, int64_t b_min, int64_t b_max, double zq,
                        int64_t* budgets, void* stream);
 
+/* budgets (device, npairs int64) by expected cost, from the network outputs
+ * and the pairs' T_obs as in hbt_budgets: a pair whose p^ lies in the
+ * fallback band [p_lo, p_hi] gets b_max (it would be rerun with b_max
+ * splits anyway); any other pair gets the B among b_min, 2 b_min, 4 b_min,
+ * ... (below b_max) and b_max that minimises the expected number of splits
+ * B + b_max * P(its permutation p after B splits lands in the band), the
+ * p-value (1 + count) / (B + 1) taken as normal with mean (1 + B p^) / (B + 1)
+ * and standard deviation sqrt(B p^ (1 - p^)) / (B + 1) (ties: the smaller
+ * B).  A pair far from the band thus gets b_min, one near an edge as many
+ * splits as keep a rerun unlikely, unless a rerun is the cheaper risk.
+ * Errors: HBT_ERR_ARG (NULL pointer, 0 > p_lo > p_hi > 1), HBT_ERR_SIZE
+ * (npairs < 1, b_min < 1, b_max < b_min), HBT_ERR_DEVICE. */
+hbt_status hbt_budgets_min_cost(int64_t npairs, const float* mlp_out, const hbt_result* results,
+                                double p_lo, double p_hi, int64_t b_min, int64_t b_max,
+                                int64_t* budgets, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

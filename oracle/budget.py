@@ -22,7 +22,9 @@ Pieces:
 * ``adam_step``  Adam (Kingma & Ba 2015, Algorithm 1, bias-corrected);
 * ``budgets``    B = clamp(ceil(zq^2 p(1-p) / (p - e)^2), Bmin, Bmax) with
   p = 1 - Phi((T_obs - mu) / sigma) and e the nearer edge of the fallback
-  band [lo, hi] (Bmax inside the band; lo = hi = alpha is the plain rule).
+  band [lo, hi] (Bmax inside the band; lo = hi = alpha is the plain rule);
+* ``budgets_min_cost``  the B (Bmin doubling, or Bmax) with the least
+  expected splits B + Bmax * P(p lands in the band after B splits).
 """
 from __future__ import annotations
 
@@ -152,6 +154,42 @@ def budgets(out, t_obs, lo=0.05, hi=None, bmin=200, bmax=20000, zq=2.32634787404
         e = lo if p < lo else hi
         need = zq * zq * p * (1.0 - p) / (p - e) ** 2
         B[i] = bmax if need >= bmax else max(bmin, int(math.ceil(need)))
+    return B
+
+
+def land_prob(p, B, lo, hi):
+    """Probability that the permutation p-value (1 + count) / (B + 1) of a
+    pair with p-value p lands in [lo, hi], the count binomial(B, p) taken as
+    normal (mean B p, variance B p (1 - p))."""
+    mean = (1.0 + B * p) / (B + 1.0)
+    sd = math.sqrt(B * p * (1.0 - p)) / (B + 1.0)
+    if not sd > 0.0:
+        return 1.0 if lo <= mean <= hi else 0.0
+    return normal_sf((lo - mean) / sd) - normal_sf((hi - mean) / sd)
+
+
+def budgets_min_cost(out, t_obs, lo, hi, bmin, bmax):
+    """Permutations per pair minimising the expected splits: Bmax inside the
+    band; otherwise the B in {Bmin 2^k < Bmax} u {Bmax} with the least
+    B + Bmax * land_prob(p, B) (the smaller B on ties)."""
+    B = np.empty(out.shape[0], dtype=np.int64)
+    for i in range(out.shape[0]):
+        mu, ls = float(out[i, 0]), float(out[i, 1])
+        p = normal_sf((float(t_obs[i]) - mu) / math.exp(ls))
+        if lo <= p <= hi:
+            B[i] = bmax
+            continue
+        cands = []
+        c = bmin
+        while c < bmax:
+            cands.append(c)
+            c *= 2
+        best, bestB = float(bmax), bmax
+        for c in cands:
+            cost = c + bmax * land_prob(p, c, lo, hi)
+            if cost < best:
+                best, bestB = cost, c
+        B[i] = bestB
     return B
 
 

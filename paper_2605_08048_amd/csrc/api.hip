@@ -1233,6 +1233,20 @@ hbt_status hbt_budgets(int64_t npairs, const float* mlp_out, const hbt_result* r
     return HBT_OK;
 }
 
+hbt_status hbt_budgets_min_cost(int64_t npairs, const float* mlp_out, const hbt_result* results,
+                                double p_lo, double p_hi, int64_t b_min, int64_t b_max, int64_t* budgets,
+                                void* stream) {
+    g_err.clear();
+    if (!mlp_out || !results || !budgets) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (!(p_lo >= 0.0 && p_lo <= p_hi && p_hi <= 1.0)) return fail(HBT_ERR_ARG, "band [%g, %g]", p_lo, p_hi);
+    if (npairs < 1 || b_min < 1 || b_max < b_min)
+        return fail(HBT_ERR_SIZE, "npairs %lld, budgets [%lld, %lld]", (long long)npairs,
+                    (long long)b_min, (long long)b_max);
+    HIP_TRY(launch_budgets_cost(npairs, mlp_out, results, p_lo, p_hi, b_min, b_max, budgets,
+                                (hipStream_t)stream));
+    return HBT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // tile widths of the split-BF16 product
 // ---------------------------------------------------------------------------

@@ -285,6 +285,43 @@ __global__ void k_budgets(int64_t npairs, const float* __restrict__ out,
     budget[p] = B;
 }
 
+// Expected-cost rule: a pair whose p^ lies in the fallback band gets bmax
+// (it would be rerun there anyway); any other pair gets the B among bmin,
+// 2 bmin, 4 bmin, ... (below bmax) and bmax that minimises the expected
+// splits B + bmax * P(its p lands in [lo, hi] after B splits) (a landing
+// is rerun with bmax splits), the estimate (1 + count) / (B + 1) taken as
+// normal with mean (1 + B p^) / (B + 1) and sd sqrt(B p^ (1 - p^)) / (B + 1);
+// ties go to the smaller B.
+__device__ double land_prob(double ph, double B, double lo, double hi) {
+    const double mean = (1.0 + B * ph) / (B + 1.0);
+    const double sd = sqrt(B * ph * (1.0 - ph)) / (B + 1.0);
+    if (!(sd > 0.0)) return (mean >= lo && mean <= hi) ? 1.0 : 0.0;
+    const double k = 0.70710678118654752440 / sd;
+    // Phi((hi - mean) / sd) - Phi((lo - mean) / sd)
+    return 0.5 * erfc((lo - mean) * k) - 0.5 * erfc((hi - mean) * k);
+}
+
+__global__ void k_budgets_cost(int64_t npairs, const float* __restrict__ out,
+                               const hbt_result* __restrict__ res, double lo, double hi, int64_t bmin,
+                               int64_t bmax, int64_t* __restrict__ budget) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const double mu = (double)out[p * kO], sd = exp((double)out[p * kO + 1]);
+    const double ph = 0.5 * erfc((res[p].t_obs - mu) / sd * 0.70710678118654752440);
+    int64_t B = bmax;
+    if (ph < lo || ph > hi) {
+        double best = (double)bmax;
+        for (int64_t c = bmin; c < bmax; c *= 2) {
+            const double cost = (double)c + (double)bmax * land_prob(ph, (double)c, lo, hi);
+            if (cost < best) {
+                best = cost;
+                B = c;
+            }
+        }
+    }
+    budget[p] = B;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -362,6 +399,13 @@ hipError_t launch_budgets(int64_t npairs, const float* out, const hbt_result* re
                           hipStream_t s) {
     hipLaunchKernelGGL(k_budgets, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, npairs, out,
                        res, lo, hi, bmin, bmax, zq, budget);
+    return hipGetLastError();
+}
+
+hipError_t launch_budgets_cost(int64_t npairs, const float* out, const hbt_result* res, double lo,
+                               double hi, int64_t bmin, int64_t bmax, int64_t* budget, hipStream_t s) {
+    hipLaunchKernelGGL(k_budgets_cost, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, npairs,
+                       out, res, lo, hi, bmin, bmax, budget);
     return hipGetLastError();
 }
 

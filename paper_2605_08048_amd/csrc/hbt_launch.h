@@ -158,6 +158,8 @@ hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, floa
 hipError_t launch_budgets(int64_t npairs, const float* out, const hbt_result* res, double lo,
                           double hi, int64_t bmin, int64_t bmax, double zq, int64_t* budget,
                           hipStream_t s);
+hipError_t launch_budgets_cost(int64_t npairs, const float* out, const hbt_result* res, double lo,
+                               double hi, int64_t bmin, int64_t bmax, int64_t* budget, hipStream_t s);
 
 // Per pair: count, B, p, null moments and status (the alignment's, else that
 // of the split rows that drew its masks).

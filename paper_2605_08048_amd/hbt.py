@@ -126,6 +126,8 @@ def lib():
         L.hbt_mlp_grad.argtypes = [i64, P, P, P, P, P, P, sz, P]
         L.hbt_mlp_adam.argtypes = [P, P, P, P, i64, flt, flt, flt, flt, P]
         L.hbt_budgets.argtypes = [i64, P, P, dbl, dbl, i64, i64, dbl, P, P]
+        L.hbt_budgets_min_cost.argtypes = [i64, P, P, dbl, dbl, i64, i64, P, P]
+        L.hbt_budgets_min_cost.restype = i32
         for f in ["hbt_budget_features", "hbt_null_targets", "hbt_feature_norm", "hbt_target_norm", "hbt_mlp_forward", "hbt_mlp_grad",
                   "hbt_mlp_adam", "hbt_budgets"]:
             getattr(L, f).restype = i32
@@ -523,6 +525,19 @@ def budgets(mlp_out, results, p_lo, p_hi, b_min, b_max, zq=2.3263478740408408, s
     out = torch.empty(P, dtype=torch.int64, device=mlp_out.device)
     _check(lib().hbt_budgets(P, _ptr(mlp_out), _ptr(results), p_lo, p_hi, b_min, b_max, zq, _ptr(out),
                              _stream(stream)))
+    return out
+
+
+def budgets_min_cost(mlp_out, results, p_lo, p_hi, b_min, b_max, stream=None):
+    """int64 device tensor of permutation budgets per pair by expected cost."""
+    torch = _torch()
+    _need("mlp_out", mlp_out, torch.float32, cols=2)
+    P = mlp_out.shape[0]
+    if _results_records(results, mlp_out.device) < P:
+        raise HbtError(ERR_SIZE, f"{P} predictions but fewer hbt_result records")
+    out = torch.empty(P, dtype=torch.int64, device=mlp_out.device)
+    _check(lib().hbt_budgets_min_cost(P, _ptr(mlp_out), _ptr(results), p_lo, p_hi, b_min, b_max, _ptr(out),
+                                      _stream(stream)))
     return out
 
 

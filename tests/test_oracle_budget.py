@@ -142,6 +142,45 @@ def test_budget_band():
     assert one(0.03, 0.05, 0.05) == Bu.budgets(np.array([[0.0, 0.0]]), np.array([stats.norm.isf(0.03)]), 0.05)[0]
 
 
+def test_landing_probability_against_the_binomial():
+    """The normal approximation of where the permutation p-value (1 + c) /
+    (B + 1) lands, c ~ binomial(B, p): against scipy's exact binomial
+    probabilities at large B (mean shifted by the +1, sd divided by B + 1)."""
+    lo, hi = 0.02, 0.10
+    for p, B in [(0.06, 8000), (0.11, 4096), (0.015, 8192), (0.3, 2000), (0.09, 16384)]:
+        # c with lo <= (1 + c) / (B + 1) <= hi
+        c_lo = math.ceil(lo * (B + 1) - 1)
+        c_hi = math.floor(hi * (B + 1) - 1)
+        exact = stats.binom.cdf(c_hi, B, p) - stats.binom.cdf(c_lo - 1, B, p)
+        approx = Bu.land_prob(p, B, lo, hi)
+        assert abs(approx - exact) <= 0.02, (p, B, approx, exact)
+        # and the same normal probability through scipy's own normal
+        mean, sd = (1 + B * p) / (B + 1), math.sqrt(B * p * (1 - p)) / (B + 1)
+        assert abs(approx - (stats.norm.cdf((hi - mean) / sd) - stats.norm.cdf((lo - mean) / sd))) < 1e-12
+
+
+def test_min_cost_budget_rule():
+    """Inside the band: Bmax.  Far from it (p ~ 0 or p ~ 0.5): Bmin.  Just
+    outside an edge the rule weighs more splits against the risk of a rerun:
+    the budget it picks costs no more in expectation than Bmin or Bmax, and
+    gets large (but below Bmax) at a moderate distance from the edge."""
+    lo, hi, bmin, bmax = 0.02, 0.10, 64, 10000
+    one = lambda p: Bu.budgets_min_cost(np.array([[0.0, 0.0]]), np.array([stats.norm.isf(p)]), lo, hi, bmin,
+                                        bmax)[0]
+    assert one(0.05) == bmax and one(0.0201) == bmax and one(0.0999) == bmax
+    assert one(1e-9) == bmin and one(0.5) == bmin and one(0.9) == bmin
+    cost = lambda p, B: B + bmax * Bu.land_prob(p, B, lo, hi) if B < bmax else bmax
+    for p in [0.003, 0.012, 0.016, 0.105, 0.11, 0.12, 0.14, 0.2]:
+        B = one(p)
+        assert B == bmax or (B >= bmin and (B & (B - 1)) == 0 or B % bmin == 0)
+        assert cost(p, B) <= cost(p, bmin) + 1e-9 and cost(p, B) <= bmax
+    assert bmin < one(0.12) < bmax
+    # the cost of a budget at p = 0.12 in numbers: 1024 splits leave a 2%
+    # chance of landing in the band, 64 splits a 36% chance
+    assert abs(Bu.land_prob(0.12, 1024, lo, hi) - stats.norm.cdf((0.10 - (1 + 1024 * 0.12) / 1025)
+                                                               / (math.sqrt(1024 * 0.12 * 0.88) / 1025))) < 1e-3
+
+
 def test_features_against_aligned_clouds():
     """r(Z) and the angle term against the aligned rows themselves."""
     c = synth.small_pair_f64()
