@@ -30,7 +30,7 @@ sys.path.insert(0, str(ROOT))
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 MFMA
 INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 MFMA
-STAGES = ["align", "split", "groupsum", "stat", "recheck", "other"]
+STAGES = ["align", "split", "groupsum", "stat", "recheck", "other", "centroid"]
 
 
 def kernel_source_hash():
@@ -130,8 +130,8 @@ def write_traffic(fetch_csv, write_csv, command):
 
 
 def stage_times(L, ctypes):
-    ms = (ctypes.c_double * 6)()
-    n = (ctypes.c_int64 * 6)()
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int64 * len(STAGES))()
     st = L.hbt_stage_times(ms, n)
     if st != 0:
         raise RuntimeError(L.hbt_last_error().decode())
@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
     ap.add_argument("--single-steps", type=int, default=5,
                     help="timed calls per precision of the single-pair workloads (0 skips them)")
+    ap.add_argument("--route2-steps", type=int, default=2,
+                    help="timed steps of the point-to-centroid route (0 skips them)")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="timed replays of the split-BF16 call captured as a HIP graph (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -294,18 +296,18 @@ def main():
         tuning["pairs_at_256"] = int(np.sum(hbt.tile_widths(batch.B, d) == 256))
         log(f"tuned: {tuning}")
 
-    def run(prec, steps, warmup):
+    def run(prec, steps, warmup, stat_route=0):
         res = torch.zeros(hbt.RESULT_BYTES * P, dtype=torch.uint8, device=dev)
         for _ in range(warmup):
             hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
-                                  precision=prec, sync=False, results=res)
+                                  precision=prec, sync=False, results=res, stat_route=stat_route)
         torch.cuda.synchronize()
         L.hbt_stage_timing(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             hbt.perm_test_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed,
-                                  precision=prec, sync=False, results=res)
+                                  precision=prec, sync=False, results=res, stat_route=stat_route)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ms, launches = stage_times(L, ctypes)
@@ -411,6 +413,46 @@ def main():
             single[name] = row
             log(f"single pair {name}: " + ", ".join(f"{k} {row[k]['ms_per_call']:.3f} ms" for k in counts))
 
+    # the point-to-centroid route (statistic route 1 of the ABI): the same
+    # workloads with the norms reduced from Q = Z S^T
+    route2 = None
+    if args.route2_steps > 0:
+        route2 = {}
+        centroid_flops = lambda n, m, B: 2.0 * (n + m) * d * B  # Q = Z S^T, K = d
+        for prec in ("bf16x2", "f32"):
+            dt2, ms2, l2, out2, bad2 = run(prec, args.route2_steps, 1, stat_route=1)
+            c_ms = ms2[6] / args.route2_steps
+            route2[f"batch_512_{prec}"] = {
+                "ms_per_step": dt2 / args.route2_steps * 1e3, "value": stats_per_step * args.route2_steps / dt2,
+                "centroid_ms": c_ms, "centroid_tflops": algo_flops / (c_ms * 1e-3) / 1e12,
+                "pairs_with_counts_equal_to_route0": f"{int(np.sum(out2['count'] == out['count']))}/{P}"
+                if prec == "bf16x2" else None,
+                "pairs_bad_status": bad2}
+            log(f"route 2 batched {prec}: {route2[f'batch_512_{prec}']['ms_per_step']:.2f} ms/step, "
+                f"centroid {c_ms:.2f} ms")
+        pair = synth.pair_d768()
+        X = torch.from_numpy(pair.X).to(dev)
+        Y = torch.from_numpy(pair.Y).to(dev)
+        for prec in ("bf16x2", "f32"):
+            call = lambda: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, stat_route=1, sync=False)
+            call()
+            torch.cuda.synchronize()
+            L.hbt_stage_timing(1)
+            t0 = time.perf_counter()
+            for _ in range(args.route2_steps):
+                r = call()
+            torch.cuda.synchronize()
+            dt1 = (time.perf_counter() - t0) / args.route2_steps
+            ms1, _ = stage_times(L, ctypes)
+            L.hbt_stage_timing(0)
+            c_ms = ms1[6] / args.route2_steps
+            res = hbt.results_to_numpy(r["result"])[0]
+            route2[f"pair_d768_{prec}"] = {
+                "ms_per_call": dt1 * 1e3, "value": pair.B / dt1, "centroid_ms": c_ms,
+                "centroid_tflops": centroid_flops(pair.n, pair.m, pair.B) / (c_ms * 1e-3) / 1e12,
+                "count": int(res["count"]), "status": int(res["status"])}
+            log(f"route 2 pair_d768 {prec}: {dt1 * 1e3:.3f} ms/call, centroid {c_ms:.3f} ms")
+
     errors = None
     if args.single_steps > 0:
         errors = stage_errors(dev, synth.null_pair_d1024(), hbt, torch)
@@ -446,6 +488,7 @@ def main():
         "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
         "int8_planes": i8,
+        "point_to_centroid": route2,
         "single_pair": single,
         "tuning": tuning,
         "stage_errors_null_pair_d1024": errors,

@@ -261,7 +261,8 @@ typedef enum hbt_stage {
     HBT_STAGE_STAT = 3,      /* permuted statistics and exceedance counts */
     HBT_STAGE_RECHECK = 4,   /* FP64 re-evaluation near the threshold */
     HBT_STAGE_OTHER = 5,     /* table uploads, zero fills, p-values */
-    HBT_NUM_STAGES = 6
+    HBT_STAGE_CENTROID = 6,  /* point-to-centroid products (statistic route 1) */
+    HBT_NUM_STAGES = 7
 } hbt_stage;
 hbt_status hbt_stage_timing(int32_t enable);
 hbt_status hbt_stage_times(double* ms, int64_t* launches);

@@ -91,9 +91,9 @@ int64_t round_up(int64_t x, int64_t k) { return (x + k - 1) / k * k; }
 // 0.997); the int8 sums are exact.  The safety factors keep the worst error
 // of an exact emulation of the stored rows (duplicated rows repeated up to
 // 1000 times, clouds with r from 0.02 to 1, a group of 2) below a quarter of
-// the band.  The point-to-centroid route works in FP32 whatever the first
-// product's precision (its rows are an FP32 copy, its centroids floats), so
-// its band is at least the FP32 one, plus the dot-product term.
+// the band.  The point-to-centroid route reads an FP32 copy of the rows and
+// the centroids as floats, so its band is at least the FP32 one, plus the
+// dot-product term of its products (FP32, or split BF16 in three terms).
 RecheckBand precision_band(int precision, int d, bool route2) {
     const double rd = 1.0 / std::sqrt((double)d);
     RecheckBand b;
@@ -106,7 +106,10 @@ RecheckBand precision_band(int precision, int d, bool route2) {
     if (route2) {
         b.e_acc = std::max(b.e_acc, 4e-6);
         b.e_row = std::max(b.e_row, 0x1p-24 * rd);
-        b.e_q = 8.0 * 0x1p-24;
+        // FP32 products: accumulation over K = d; split BF16 (three terms):
+        // besides, each product z_c s_c is off by up to 2^-15 |z_c s_c| (the
+        // two splits' remainders and the dropped lo x lo term)
+        b.e_q = 8.0 * 0x1p-24 + (precision == HBT_BF16X2 ? 0x1p-15 * rd : 0.0);
     }
     return b;
 }
@@ -160,7 +163,7 @@ struct Workspace {
     float* z32;         // row-major FP32 Z when the main storage is not FP32
     double* zt;         // z_i . t per pooled row
     double* partial2;   // block rows x row tiles x 2
-    GemmTile* ctiles;   // its tile list (256 splits per tile)
+    CTile* ctiles;      // its tile list (64 rows x 256 splits per tile)
     size_t bytes;
 };
 
@@ -198,8 +201,8 @@ struct Plan {
     bool need_store = true;       // group-sum path (false for hbt_align)
     bool route2 = false;          // point-to-centroid statistic route
     bool aligned16 = true;        // every X, Y starts on a 16-byte boundary
-    int ntile_i = 0;              // its row tiles (of 64) per split
-    std::vector<GemmTile> ctiles;
+    int ntile_i = 0;              // its row tiles (of 64) per split, largest pair
+    std::vector<CTile> ctiles;    // b-tile major, then row tiles (per pair)
     // Pipeline chunks of the batched call: pairs [pa, pb), their groups from
     // g0 (the wide ones, then the narrow ones, tiles numbered from 0 in each)
     struct Chunk {
@@ -244,7 +247,7 @@ Workspace carve(const Plan& P, void* ws) {
             w.z32 = P.precision == HBT_F32 ? nullptr : c.take<float>((size_t)P.zrows * P.d_pad);
             w.zt = c.take<double>(std::max<int64_t>(P.zrows, 1));
             w.partial2 = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.ntile_i * 2);
-            w.ctiles = c.take<GemmTile>(std::max<size_t>(P.ctiles.size(), 1));
+            w.ctiles = c.take<CTile>(std::max<size_t>(P.ctiles.size(), 1));
         } else {
             w.sig = nullptr;
             w.z32 = nullptr;
@@ -487,6 +490,13 @@ BlockPair block_pair(int64_t mrow0, int64_t mword0, uint64_t perm_base, int64_t 
     return b;
 }
 
+// Point-to-centroid tiles of pair p's first nb block rows: every 256-split
+// tile times every 64-row tile of its padded rows.
+void add_ctiles(Plan& P, int p, int64_t nb) {
+    for (int64_t b = 0; b < nb; b += kTileB)
+        for (int i0 = 0; i0 < P.pairs[p].Np; i0 += 64) P.ctiles.push_back(CTile{p, (int32_t)b, i0, 0});
+}
+
 // Single-pair plan with blocks of B0 splits.
 Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64_t* B0_out) {
     Plan P;
@@ -503,7 +513,7 @@ Plan plan_single(const hbt_perm_params* prm, const void* X, const void* Y, int64
     if (prm->stat_route == 1) {
         P.route2 = true;
         P.ntile_i = P.pairs[0].Np / 64;
-        for (int64_t b = 0; b < B0; b += kTileB) P.ctiles.push_back(GemmTile{0, (int32_t)b});
+        add_ctiles(P, 0, B0);
     }
     P.Btot.push_back(prm->B);
     P.block_rows = B0;
@@ -613,9 +623,10 @@ hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_pa
                             hbt_result* results, hipStream_t s) {
     const int np = P.npairs;
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
-    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st, w.partial, P.nslot,
+    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st,
+                        P.route2 ? w.partial2 : w.partial, P.route2 ? 0 : P.nslot,
                         P.block_rows, P.d, common->gd,
-                        common->alternative, precision_band(P.precision, P.d, false), no_recheck, nullptr,
+                        common->alternative, precision_band(P.precision, P.d, P.route2), no_recheck, nullptr,
                         0, w.tw, w.cnt, w.flags, w.nflag, s)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
@@ -909,7 +920,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         StageTimer t_(HBT_STAGE_ALIGN, s);
         HIP_TRY(reflect(P, w, w.z32, s));
         if (P.route2) {
-            HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(GemmTile), s));
+            HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(CTile), s));
             HIP_TRY(launch_row_dot_t(w.pairs, 1, z32, w.t64, P.d_pad, P.zrows, w.zt, s));
         }
     }
@@ -935,13 +946,15 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
                                     wdt == kTileWide ? nt : 0, wdt != kTileWide, wdt != kTileWide ? nt : 0, P.d_pad,
                                     w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
                                     P.block_rows, w.sig, s, P.tune.grid_wide, P.tune.grid_narrow));
-            if (P.route2)
-                HIP_TRY(launch_centroid(w.pairs, w.bp, w.ctiles, (int)((nb + kTileB - 1) / kTileB),
-                                        P.ntile_i, P.d_pad, z32, w.sig, w.mask, w.zt, w.partial2,
-                                        P.block_rows, s));
+        }
+        if (P.route2) {
+            StageTimer t_(HBT_STAGE_CENTROID, s);
+            HIP_TRY(launch_centroid(P.precision == HBT_BF16X2, w.pairs, w.bp, w.ctiles,
+                                    (int)((nb + kTileB - 1) / kTileB) * P.ntile_i, P.d_pad, z32, w.sig,
+                                    w.mask, w.zt, w.partial2, P.block_rows, s));
         }
         { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
-                            P.route2 ? w.partial2 : w.partial, P.route2 ? P.ntile_i : P.nslot,
+                            P.route2 ? w.partial2 : w.partial, P.route2 ? 0 : P.nslot,
                             P.block_rows, P.d, prm->gd,
                             prm->alternative, band, no_recheck,
                             T_out ? (char*)T_out + b0 * t_size : nullptr, t_mode, w.tw,
@@ -964,7 +977,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 // Number of pipeline chunks of a batched call (1 = no pipeline).
 int g_pipeline_chunks = 0;  // process-wide override (hbt_pipeline_chunks); 0: the tuned value
 int pipeline_chunks(const Plan& P, int64_t npairs) {
-    if (!(P.precision == HBT_BF16X2 || P.precision == HBT_I8X3) || !vector_rows(P) || !P.need_store)
+    if (!(P.precision == HBT_BF16X2 || P.precision == HBT_I8X3) || !vector_rows(P) || !P.need_store ||
+        P.route2)
         return 1;
     const int c = g_pipeline_chunks > 0 ? g_pipeline_chunks : P.tune.chunks;
     return (int)std::max<int64_t>(1, std::min<int64_t>(c, npairs));
@@ -1031,6 +1045,11 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
             }
         }
     }
+    if (common->stat_route == 1) {
+        P.route2 = true;
+        P.ntile_i = P.max_np / 64;
+        for (int64_t p = 0; p < npairs; ++p) add_ctiles(P, (int)p, B[p]);
+    }
     P.block_rows = rows;
     P.block_mask_words = words;
     return true;
@@ -1060,8 +1079,6 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     if (npairs < 1 || npairs > (1 << 24)) return fail(HBT_ERR_SIZE, "npairs = %lld", (long long)npairs);
     hbt_status st = check_enums(common);
     if (st) return st;
-    if (common->stat_route != 0)
-        return fail(HBT_ERR_UNSUPPORTED, "the batched call computes the statistic by route 0 only");
     int64_t total_rows = 0;
     for (int64_t p = 0; p < npairs; ++p) {
         if ((st = check_sizes(n[p], m[p], d, B[p], common->perm_offset)))
@@ -1115,6 +1132,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
             HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), qt));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), qt));
         HIP_TRY(zero(w.nflag, 8, qt));
+        if (P.route2) HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(CTile), qt));
     }
     {
         StageTimer t_(HBT_STAGE_OTHER, s);
@@ -1124,7 +1142,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     if (st) return st;
     {
         StageTimer t_(HBT_STAGE_ALIGN, s);
-        HIP_TRY(reflect(P, w, nullptr, s));
+        HIP_TRY(reflect(P, w, P.route2 ? w.z32 : nullptr, s));
     }
     HIP_TRY(ev.record(qs, &e0));
     HIP_TRY(hipStreamWaitEvent(s, e0, 0));
@@ -1135,7 +1153,14 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
                                 P.ngw, (int)P.ntw, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
                                 P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
-                                nullptr, s, P.tune.grid_wide, P.tune.grid_narrow));
+                                P.route2 ? w.sig : nullptr, s, P.tune.grid_wide, P.tune.grid_narrow));
+    }
+    if (P.route2) {
+        StageTimer t_(HBT_STAGE_CENTROID, s);
+        const float* z32 = P.precision == HBT_F32 ? (const float*)w.zstore : w.z32;
+        HIP_TRY(launch_row_dot_t(w.pairs, np, z32, w.t64, P.d_pad, P.zrows, w.zt, s));
+        HIP_TRY(launch_centroid(P.precision == HBT_BF16X2, w.pairs, w.bp, w.ctiles, (int)P.ctiles.size(),
+                                P.d_pad, z32, w.sig, w.mask, w.zt, w.partial2, P.block_rows, s));
     }
     return batched_epilogue(P, w, common, results, s);
 }

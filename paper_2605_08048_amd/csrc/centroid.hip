@@ -10,8 +10,11 @@
 //   |sigma_small|^2 = sum_i M_bi Q_ib,
 //   |t - sigma_small|^2 = sum_{i not in the small group, i < N} (z_i . t - Q_ib).
 // This is a second, independent reduction of the same quantities (route 2 of
-// the statistic); it runs on FP32 MFMA (v_mfma_f32_16x16x4f32) for every
-// precision of the first product.
+// the statistic); it runs on FP32 MFMA (v_mfma_f32_16x16x4f32) when the first
+// product is FP32 or FP64, and on split-BF16 MFMA (three terms) when it is
+// split BF16.
+#include <type_traits>
+
 #include "hbt_launch.h"
 
 namespace hbt {
@@ -44,97 +47,191 @@ hipError_t launch_row_dot_t(const PairDesc* pairs, int npairs, const float* z32,
     return hipGetLastError();
 }
 
-// Work-group tile: 64 pooled rows x 256 splits (4 waves along the splits,
-// each 64 x 64 as 4 x 4 blocks of 16 x 16); K = d in steps of 4.
-// A (16 x 4) lane l -> row l%16, k l/16; B (4 x 16) lane l -> k l/16, col
-// l%16; D lane l -> col (split) l%16, rows (pooled) 4(l/16) + v.
-// Output: partial[split row][row tile] = (sum M Q, sum (1 - M)(z.t - Q)).
+// Work-group tile: 64 pooled rows x 256 splits of one pair (CTile), four
+// waves, wave w owning splits [64 w, 64 w + 64).  K = d runs in chunks of 32
+// columns staged through LDS: each thread loads its share of the next chunk
+// (Z: 64 rows x 32 columns, 2 coalesced 16-byte loads; S: 256 split rows x 32
+// columns, 8 loads) into registers while the current chunk is multiplied
+// from LDS, then stores it after a barrier.  Two products:
+//  * FP32 (v_mfma_f32_16x16x4f32): the wave tile is 4 x 4 blocks of 16 x 16;
+//    K is taken four at a time per lane (lane l holds k = 4(l/16) .. +3 of a
+//    16-wide step as one 16-byte LDS read), each of the four MFMAs of a step
+//    consuming one of them (A lane l -> row l%16, k slot l/16; B the same k
+//    slot, col l%16; D lane l -> col l%16, rows 4(l/16) + v).
+//  * split BF16, three terms (v_mfma_f32_32x32x16_bf16): z = zh + zl and
+//    s = sh + sl split in registers from the staged FP32 values (round to
+//    nearest even), Q += zh sh + zh sl + zl sh (the zl sl term, below
+//    2^-16 |z| |s|, is dropped); the wave tile is 2 x 2 blocks of 32 x 32
+//    (A lane l -> row l%32, k 8(l/32) .. +7; D lane l -> col l%32, rows
+//    8(v/4) + 4(l/32) + v%4).
+// Epilogue: per split, the masked sums of Q over the tile's rows,
+// partial[row tile][split row] = (sum_small Q, sum_{other, i < N} (z_i . t - Q)).
+constexpr int kCK = 32;       // K columns per staged chunk
+constexpr int kCStride = 36;  // LDS row stride in floats (chunk + 4 padding)
+
+typedef __bf16 bf16x8c __attribute__((ext_vector_type(8)));
+typedef float f32x16c __attribute__((ext_vector_type(16)));
+
+// hi = bf16(x), lo = bf16(x - hi) of 8 floats
+__device__ __forceinline__ void split8(const float4& u, const float4& v, bf16x8c& hi, bf16x8c& lo) {
+    const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)x[e];
+        hi[e] = h;
+        lo[e] = (__bf16)(x[e] - (float)h);
+    }
+}
+
+template <bool BF>
 __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ pairs,
                                                   const BlockPair* __restrict__ bp,
-                                                  const GemmTile* __restrict__ tiles,
-                                                  int ntile_i, int d_pad,
+                                                  const CTile* __restrict__ tiles, int d_pad,
                                                   const float* __restrict__ z32,
                                                   const float* __restrict__ sig,
                                                   const uint32_t* __restrict__ mask,
                                                   const double* __restrict__ zt,
                                                   double* __restrict__ partial, int64_t prow) {
-    const GemmTile tile = tiles[blockIdx.x / ntile_i];
-    const int itile = blockIdx.x % ntile_i;
+    __shared__ __attribute__((aligned(16))) float Zs[64][kCStride];
+    __shared__ __attribute__((aligned(16))) float Ss[kTileB][kCStride];
+    const CTile tile = tiles[blockIdx.x];
     const PairDesc pd = pairs[tile.pair];
     const BlockPair bq = bp[tile.pair];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int q = lane >> 4, c = lane & 15;
-    const int i0 = itile * 64;
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int i0 = tile.i0, b0 = tile.b0;
     const int N = pd.n + pd.m;
-    if (i0 >= pd.Np) return;  // row tiles past this pair's rows (pairs differ in size)
-    int brow[4];
-    bool valid[4];
+    // this thread's loads of a chunk
+    const float* zsrc = z32 + (pd.zrow0 + i0 + (t >> 2)) * (int64_t)d_pad + 8 * (t & 3);
+    const float* ssrc[8];
+    bool sval[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        brow[j] = tile.b0 + wave * 64 + 16 * j + c;
-        valid[j] = brow[j] < bq.nb;
+    for (int j = 0; j < 8; ++j) {
+        const int r = b0 + (t >> 3) + 32 * j;
+        sval[j] = r < bq.nb;
+        ssrc[j] = sig + (bq.mrow0 + (sval[j] ? r : 0)) * (int64_t)d_pad + 4 * (t & 7);
     }
-    const float* za = z32 + (pd.zrow0 + i0 + c) * (int64_t)d_pad + q;
-    const float* sb[4];
+    float4 zr[2], sr[8];
+    auto fetch = [&](int k0) {
+        zr[0] = *(const float4*)(zsrc + k0);
+        zr[1] = *(const float4*)(zsrc + k0 + 4);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        sb[j] = sig + (bq.mrow0 + (valid[j] ? brow[j] : 0)) * (int64_t)d_pad + q;
-    f32x4c acc[4][4];
+        for (int j = 0; j < 8; ++j)
+            sr[j] = sval[j] ? *(const float4*)(ssrc[j] + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto stage = [&]() {
+        *(float4*)&Zs[t >> 2][8 * (t & 3)] = zr[0];
+        *(float4*)&Zs[t >> 2][8 * (t & 3) + 4] = zr[1];
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii)
+        for (int j = 0; j < 8; ++j) *(float4*)&Ss[(t >> 3) + 32 * j][4 * (t & 7)] = sr[j];
+    };
+    constexpr int NA = BF ? 2 : 4;   // row blocks per wave
+    constexpr int NB = BF ? 2 : 4;   // split blocks per wave
+    constexpr int NV = BF ? 16 : 4;  // accumulator floats per block
+    using Acc = typename std::conditional<BF, f32x16c, f32x4c>::type;
+    Acc acc[NA][NB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[ii][j][v] = 0.0f;
-    for (int k = 0; k < d_pad; k += 4) {
-        float a[4], b[4];
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii) a[ii] = za[(int64_t)16 * ii * d_pad + k];
+            for (int v = 0; v < NV; ++v) acc[a][b][v] = 0.0f;
+    fetch(0);
+    for (int k0 = 0; k0 < d_pad; k0 += kCK) {
+        __syncthreads();  // the previous chunk has been read
+        stage();
+        __syncthreads();
+        if (k0 + kCK < d_pad) fetch(k0 + kCK);  // in flight during this chunk's products
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = valid[j] ? sb[j][k] : 0.0f;
+        for (int kk = 0; kk < kCK; kk += 16) {
+            if constexpr (BF) {
+                bf16x8c ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii)
+                for (int a = 0; a < 2; ++a) {
+                    const float* src = &Zs[32 * a + (lane & 31)][kk + 8 * (lane >> 5)];
+                    split8(*(const float4*)src, *(const float4*)(src + 4), ah[a], al[a]);
+                }
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[ii][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ii], b[j], acc[ii][j], 0, 0, 0);
+                for (int b = 0; b < 2; ++b) {
+                    const float* src = &Ss[64 * wave + 32 * b + (lane & 31)][kk + 8 * (lane >> 5)];
+                    split8(*(const float4*)src, *(const float4*)(src + 4), bh[b], bl[b]);
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    }
+            } else {
+                float4 av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = *(const float4*)&Zs[16 * a + (lane & 15)][kk + 4 * (lane >> 4)];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    bv[b] = *(const float4*)&Ss[64 * wave + 16 * b + (lane & 15)][kk + 4 * (lane >> 4)];
+                const float* af = (const float*)av;
+                const float* bf = (const float*)bv;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[4 * a + q], bf[4 * b + q], acc[a][b],
+                                                                             0, 0, 0);
+            }
+        }
     }
+    // epilogue: masked sums per split column
     const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
     const double* ztp = zt + pd.zrow0 + i0;
+    constexpr int CW = BF ? 32 : 16;  // columns per block
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t* mk = mask_row(mask, bq, bq.mrow0 + (valid[j] ? brow[j] : 0), pd.Wp);
-        const uint2 w = *(const uint2*)(mk + (i0 >> 5));  // rows i0 .. i0+63 of this split
+    for (int b = 0; b < NB; ++b) {
+        const int brow = b0 + 64 * wave + CW * b + (lane % CW);
+        const bool valid = brow < bq.nb;
+        const uint32_t* mk = mask_row(mask, bq, bq.mrow0 + (valid ? brow : 0), pd.Wp);
+        const uint2 w = *(const uint2*)(mk + (i0 >> 5));  // rows i0 .. i0 + 63 of this split
         double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < 4; ++ii)
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * ii + 4 * q + v;  // row within the tile
+            for (int v = 0; v < NV; ++v) {
+                const int r = BF ? 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)
+                                 : 16 * a + 4 * (lane >> 4) + v;  // row within the tile
                 const int i = i0 + r;
                 const uint32_t word = r < 32 ? w.x : w.y;
                 const bool small = (((word ^ flip) >> (r & 31)) & 1u) && i < N;
-                const double Q = (double)acc[ii][j][v];
+                const double Q = (double)acc[a][b][v];
                 if (small) s1 += Q;
                 else if (i < N) s2 += ztp[r] - Q;
             }
-        s1 += __shfl_xor(s1, 16, 64);
-        s2 += __shfl_xor(s2, 16, 64);
+        if (!BF) {
+            s1 += __shfl_xor(s1, 16, 64);
+            s2 += __shfl_xor(s2, 16, 64);
+        }
         s1 += __shfl_xor(s1, 32, 64);
         s2 += __shfl_xor(s2, 32, 64);
-        if (q == 0 && valid[j]) {
-            double2* out = (double2*)partial + itile * prow + bq.mrow0 + brow[j];
+        if (lane < CW && valid) {
+            double2* out = (double2*)partial + (int64_t)(i0 / 64) * prow + bq.mrow0 + brow;
             *out = make_double2(s1, s2);
         }
     }
 }
 
-hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const GemmTile* tiles,
-                           int ntiles, int ntile_i, int d_pad, const float* z32, const float* sig,
+hipError_t launch_centroid(bool bf16x3, const PairDesc* pairs, const BlockPair* bp, const CTile* tiles,
+                           int ntiles, int d_pad, const float* z32, const float* sig,
                            const uint32_t* mask, const double* zt, double* partial,
                            int64_t prow, hipStream_t s) {
-    if (ntiles <= 0 || ntile_i <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_centroid, dim3((unsigned)(ntiles * ntile_i)), dim3(256), 0, s, pairs, bp,
-                       tiles, ntile_i, d_pad, z32, sig, mask, zt, partial, prow);
+    if (ntiles <= 0) return hipSuccess;
+    if (bf16x3)
+        hipLaunchKernelGGL(k_centroid<true>, dim3((unsigned)ntiles), dim3(256), 0, s, pairs, bp, tiles, d_pad,
+                           z32, sig, mask, zt, partial, prow);
+    else
+        hipLaunchKernelGGL(k_centroid<false>, dim3((unsigned)ntiles), dim3(256), 0, s, pairs, bp, tiles, d_pad,
+                           z32, sig, mask, zt, partial, prow);
     return hipGetLastError();
 }
 

@@ -88,6 +88,15 @@ struct GemmTile {
     int32_t b0;          // first split of the tile, relative to the pair's block rows
 };
 
+// A point-to-centroid tile: 64 pooled rows [i0, i0 + 64) x kTileB split rows
+// [b0, b0 + kTileB) of one pair's block rows.
+struct CTile {
+    int32_t pair;
+    int32_t b0;
+    int32_t i0;
+    int32_t _pad;
+};
+
 // The split-BF16 kernel's tiles of one pair: nbt split tiles x (d_pad / 64)
 // column slices, numbered from tile0 (slice-major, split tile fastest).
 struct GemmGroup {
@@ -261,9 +270,10 @@ __host__ __device__ inline double log_g_sensitivity(double s, double d, int gd) 
 // sigma_g, which gives, relative to |sigma_g|^2 = (n_g r_g)^2,
 //   rel_g = e_acc + a_g / r_g + a_g^2 d / r_g^2,   a_g = s_store e_row k / n_g,
 // with e_acc the accumulation error of the product (relative to the sums).
-// The point-to-centroid route adds the FP32 error of its K = d dot products
-// z_i . sigma: up to e_q sqrt(d) |sigma_small| each, summed over k (small
-// group) or the N - k others (large group).  A relative error rel of r^2
+// The point-to-centroid route adds the error of its K = d dot products
+// z_i . sigma (FP32, or split BF16 in three terms): up to e_q sqrt(d)
+// |sigma_small| each, summed over k (small group) or the N - k others
+// (large group).  A relative error rel of r^2
 // moves log g_d(r) by rel * sensitivity(r^2).
 struct RecheckBand {
     double e_acc;    // relative accumulation error of the group sums

@@ -115,8 +115,8 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
 hipError_t launch_row_dot_t(const PairDesc* pairs, int npairs, const float* z32,
                             const double* t64, int d_pad, int64_t total_rows, double* zt,
                             hipStream_t s);
-hipError_t launch_centroid(const PairDesc* pairs, const BlockPair* bp, const GemmTile* tiles,
-                           int ntiles, int ntile_i, int d_pad, const float* z32, const float* sig,
+hipError_t launch_centroid(bool bf16x3, const PairDesc* pairs, const BlockPair* bp, const CTile* tiles,
+                           int ntiles, int d_pad, const float* z32, const float* sig,
                            const uint32_t* mask, const double* zt, double* partial,
                            int64_t prow, hipStream_t s);
 

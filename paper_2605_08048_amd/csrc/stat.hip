@@ -31,7 +31,8 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         // the lanes of a wave read consecutive rows
         const double2* pr = (const double2*)partial + row;
         double ss_small = 0.0, ss_large = 0.0;
-        for (int k = 0; k < nslot; ++k) {
+        const int ns = nslot > 0 ? nslot : pd.Np / 64;  // 0: the point-to-centroid row tiles of the pair
+        for (int k = 0; k < ns; ++k) {
             const double2 v = pr[k * prow];
             ss_small += v.x;
             ss_large += v.y;

@@ -330,13 +330,14 @@ def recheck_band(precision, n, m, d, r1, r2, *, stat_route=0, gd="banerjee"):
     return out if out.shape else float(out)
 
 
-def batched_workspace_size(row_offset, n, m, B, d, *, precision="bf16x2", input_dtype="f32"):
+def batched_workspace_size(row_offset, n, m, B, d, *, precision="bf16x2", input_dtype="f32", stat_route=0):
     """Workspace bytes of one ``perm_test_batched`` call of these shapes."""
     P = len(n)
     nn = np.ascontiguousarray(n, dtype=np.int64)
     mm = np.ascontiguousarray(m, dtype=np.int64)
     BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
-    prm = make_params(0, 0, d, 0, precision=precision, input_dtype={"f32": 0, "f64": 1}[input_dtype])
+    prm = make_params(0, 0, d, 0, precision=precision, input_dtype={"f32": 0, "f64": 1}[input_dtype],
+                      stat_route=stat_route)
     ptr = lambda a: a.ctypes.data_as(C.c_void_p)
     return int(lib().hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm)))
 
@@ -367,7 +368,7 @@ def _batch_tables(Z_all, row_offset, n, m, B, pair_index):
 
 def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair_index=None,
                       precision="bf16x2", gd="banerjee", alternative="greater", align=True, recheck=True,
-                      stream=None, sync=True, results=None, workspace=None):
+                      stream=None, sync=True, results=None, workspace=None, stat_route=0):
     """Many pairs in one call.  Z_all (device tensor) holds rows X_0, Y_0, X_1, ...;
     row_offset/n/m/B are host integer arrays.  ``pair_index`` (host, one Philox
     counter word per pair; default 0, 1, 2, ...): pairs with equal n, m, B and
@@ -390,7 +391,7 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
     d = Z_all.shape[1]
     prm = make_params(0, 0, d, 0, seed=seed, perm_offset=perm_offset, precision=precision,
                       input_dtype=_input_dtype(Z_all), gd=gd, alternative=alternative, align=align,
-                      recheck=recheck)
+                      recheck=recheck, stat_route=stat_route)
     L = lib()
     ptr = lambda a: a.ctypes.data_as(C.c_void_p)
     need = L.hbt_perm_test_batched_workspace_size(P, ptr(nn), ptr(mm), ptr(BB), d, C.byref(prm))

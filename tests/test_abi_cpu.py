@@ -177,9 +177,17 @@ def test_batched_validation():
     st = L.hbt_perm_test_batched(0, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                  FAKE, need, None)
     assert st == hbt.ERR_SIZE
-    prm.stat_route = 1  # the point-to-centroid route is single-pair only
+    # the point-to-centroid route needs more workspace (centroids, an FP32
+    # copy of the rows, its partial sums), and the int8 planes do not have it
+    prm.stat_route = 1
+    need2 = L.hbt_perm_test_batched_workspace_size(P, ptr(n), ptr(m), ptr(B), 8, C.byref(prm))
+    assert need2 > need
     st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                  FAKE, need, None)
+    assert st == hbt.ERR_WORKSPACE
+    prm.precision = hbt.PRECISION["i8x3"]
+    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                 FAKE, need2, None)
     assert st == hbt.ERR_UNSUPPORTED
 
 
