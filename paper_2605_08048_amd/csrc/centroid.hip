@@ -59,8 +59,8 @@ hipError_t launch_row_dot_t(const PairDesc* pairs, int npairs, const float* z32,
 //    consuming one of them (A lane l -> row l%16, k slot l/16; B the same k
 //    slot, col l%16; D lane l -> col l%16, rows 4(l/16) + v).
 //  * split BF16, three terms (v_mfma_f32_32x32x16_bf16): z = zh + zl and
-//    s = sh + sl split in registers from the staged FP32 values (round to
-//    nearest even), Q += zh sh + zh sl + zl sh (the zl sl term, below
+//    s = sh + sl split (round to nearest even) once, as the chunk is staged
+//    into LDS as bf16 planes, Q += zh sh + zh sl + zl sh (the zl sl term, below
 //    2^-16 |z| |s|, is dropped); the wave tile is 2 x 2 blocks of 32 x 32
 //    (A lane l -> row l%32, k 8(l/32) .. +7; D lane l -> col l%32, rows
 //    8(v/4) + 4(l/32) + v%4).
@@ -92,8 +92,13 @@ __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ p
                                                   const uint32_t* __restrict__ mask,
                                                   const double* __restrict__ zt,
                                                   double* __restrict__ partial, int64_t prow) {
-    __shared__ __attribute__((aligned(16))) float Zs[64][kCStride];
-    __shared__ __attribute__((aligned(16))) float Ss[kTileB][kCStride];
+    // FP32 mode: the chunk as floats; split-BF16 mode: its hi and lo parts as
+    // bf16, split once when staged
+    constexpr int kBStride = kCK + 8;  // bf16 row stride (80 bytes)
+    __shared__ __attribute__((aligned(16))) float Zs[BF ? 1 : 64][kCStride];
+    __shared__ __attribute__((aligned(16))) float Ss[BF ? 1 : kTileB][kCStride];
+    __shared__ __attribute__((aligned(16))) __bf16 Zb[BF ? 2 : 1][BF ? 64 : 1][kBStride];
+    __shared__ __attribute__((aligned(16))) __bf16 Sb[BF ? 2 : 1][BF ? kTileB : 1][kBStride];
     const CTile tile = tiles[blockIdx.x];
     const PairDesc pd = pairs[tile.pair];
     const BlockPair bq = bp[tile.pair];
@@ -120,10 +125,23 @@ __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ p
             sr[j] = sval[j] ? *(const float4*)(ssrc[j] + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
     };
     auto stage = [&]() {
-        *(float4*)&Zs[t >> 2][8 * (t & 3)] = zr[0];
-        *(float4*)&Zs[t >> 2][8 * (t & 3) + 4] = zr[1];
+        if constexpr (BF) {
+            bf16x8c h, l;
+            split8(zr[0], zr[1], h, l);
+            *(bf16x8c*)&Zb[0][t >> 2][8 * (t & 3)] = h;
+            *(bf16x8c*)&Zb[1][t >> 2][8 * (t & 3)] = l;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) *(float4*)&Ss[(t >> 3) + 32 * j][4 * (t & 7)] = sr[j];
+            for (int j = 0; j < 8; ++j) {
+                const uint2 hl0 = split_bf16x2(sr[j].x, sr[j].y), hl1 = split_bf16x2(sr[j].z, sr[j].w);
+                *(uint2*)&Sb[0][(t >> 3) + 32 * j][4 * (t & 7)] = make_uint2(hl0.x, hl1.x);
+                *(uint2*)&Sb[1][(t >> 3) + 32 * j][4 * (t & 7)] = make_uint2(hl0.y, hl1.y);
+            }
+        } else {
+            *(float4*)&Zs[t >> 2][8 * (t & 3)] = zr[0];
+            *(float4*)&Zs[t >> 2][8 * (t & 3) + 4] = zr[1];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) *(float4*)&Ss[(t >> 3) + 32 * j][4 * (t & 7)] = sr[j];
+        }
     };
     constexpr int NA = BF ? 2 : 4;   // row blocks per wave
     constexpr int NB = BF ? 2 : 4;   // split blocks per wave
@@ -148,13 +166,15 @@ __global__ __launch_bounds__(256) void k_centroid(const PairDesc* __restrict__ p
                 bf16x8c ah[2], al[2], bh[2], bl[2];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    const float* src = &Zs[32 * a + (lane & 31)][kk + 8 * (lane >> 5)];
-                    split8(*(const float4*)src, *(const float4*)(src + 4), ah[a], al[a]);
+                    const int r = 32 * a + (lane & 31), k = kk + 8 * (lane >> 5);
+                    ah[a] = *(const bf16x8c*)&Zb[0][r][k];
+                    al[a] = *(const bf16x8c*)&Zb[1][r][k];
                 }
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    const float* src = &Ss[64 * wave + 32 * b + (lane & 31)][kk + 8 * (lane >> 5)];
-                    split8(*(const float4*)src, *(const float4*)(src + 4), bh[b], bl[b]);
+                    const int r = 64 * wave + 32 * b + (lane & 31), k = kk + 8 * (lane >> 5);
+                    bh[b] = *(const bf16x8c*)&Sb[0][r][k];
+                    bl[b] = *(const bf16x8c*)&Sb[1][r][k];
                 }
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
