@@ -205,6 +205,43 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
                                  const hbt_perm_params* common, hbt_result* results, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* hbt_perm_test_clouds: many pairs over a set of clouds that pairs share
+ * (e.g. every pair of one word with others: the word's cloud is one of
+ * them), each cloud stored once.  The permutation test of Algorithm 1 for
+ * every pair, as hbt_perm_test_batched computes it, with the Householder
+ * reflection (eq:householder_fast) folded into the statistic instead of
+ * applied to the stored rows: the group-sum product runs on the unreflected
+ * rows of both clouds, and per split the reflected group sums follow as
+ *   sigma' = sigma - c v,  c = sum over the smaller group's X rows of
+ *   2 (v . x_i) / (v . v)  (FP64, from the split mask),
+ *   |sigma'|^2 = |sigma|^2 - 2 c (v . sigma) + c^2 (v . v),
+ *   |t - sigma'|^2 = |t - sigma|^2 + 2 c (v . t - v . sigma) + c^2 (v . v),
+ * whose error is 2 sigma' . E + |E|^2 for the product's error E, as without
+ * the fold, whatever v . v is.
+ *   Z_all (device, FP32): the clouds' rows; cloud c is cloud_rows[c] rows
+ *     from row cloud_offset[c] (host arrays of nclouds int64), every cloud
+ *     starting on a 16-byte boundary.  The caller guarantees the rows exist.
+ *   pair_x, pair_y (host, npairs int64): the clouds of pair p (X, Y); B, and
+ *     pair_index (nullable), as in hbt_perm_test_batched.
+ *   common: precision must be HBT_BF16X2, input_dtype HBT_IN_F32,
+ *     stat_route 0; gd, alternative, align, seed, perm_offset, flags apply.
+ *   d: a multiple of 4, at most 1024.
+ *   results: DEVICE array of npairs hbt_result.
+ * The splits, counts and p-values are those of the same pairs in
+ * hbt_perm_test_batched (counts follow the FP64 statistic through the same
+ * recheck band).
+ * Errors: HBT_ERR_ARG (NULL, cloud index out of range, negative offset),
+ * HBT_ERR_SIZE, HBT_ERR_UNSUPPORTED (other precisions, dtypes, routes, d or
+ * alignment), HBT_ERR_WORKSPACE, HBT_ERR_DEVICE. */
+size_t hbt_perm_test_clouds_workspace_size(int64_t nclouds, const int64_t* cloud_rows, int64_t npairs,
+                                           const int64_t* pair_x, const int64_t* pair_y, const int64_t* B,
+                                           int64_t d, const hbt_perm_params* common);
+hbt_status hbt_perm_test_clouds(int64_t nclouds, const void* Z_all, const int64_t* cloud_offset,
+                                const int64_t* cloud_rows, int64_t npairs, const int64_t* pair_x,
+                                const int64_t* pair_y, const int64_t* B, const uint32_t* pair_index, int64_t d,
+                                const hbt_perm_params* common, hbt_result* results, void* ws, size_t ws_bytes,
+                                void* stream);
+
 /* hbt_pipeline_chunks: how many chunks of pairs the batched call pipelines
  * (the product of one chunk runs while the next is aligned and split, on
  * three streams joined by events; split BF16 and int8 planes with FP32 rows,

@@ -253,6 +253,39 @@ hipError_t launch_colsum_vec(const PairDesc* pairs, int npairs, int nchunks, int
 }
 
 // ---------------------------------------------------------------------------
+// Householder coefficients 2 (v . x_i) / (v . v) of every X row, for pairs
+// whose rows are stored unreflected (eq:householder_fast folded into the
+// statistic): one wave per row, FP64 dot product of the FP32 row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fold_coef(const PairDesc* __restrict__ pairs, int npairs,
+                                                   const PairState* __restrict__ st,
+                                                   const double* __restrict__ v, int d, int d_pad,
+                                                   int64_t total, double* __restrict__ coef) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    if (r >= total) return;
+    const int p = upper_index(npairs, r, [&](int k) { return pairs[k].coef0; });
+    const PairDesc pd = pairs[p];
+    const int identity = st[p].identity;
+    double w = 0.0;
+    if (!identity) {  // wave-uniform
+        const float* x = (const float*)pd.X + (r - pd.coef0) * d;
+        const double* vp = v + (int64_t)p * d_pad;
+        for (int c = lane; c < d; c += 64) w += vp[c] * (double)x[c];
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    }
+    if (lane == 0) coef[r] = identity ? 0.0 : 2.0 * w / st[p].vv;
+}
+
+hipError_t launch_fold_coef(const PairDesc* pairs, int npairs, const PairState* st, const double* v, int d,
+                            int d_pad, int64_t total, double* coef, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_coef, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, pairs, npairs, st, v,
+                       d, d_pad, total, coef);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // finalize: one work-group per pair
 // ---------------------------------------------------------------------------
 // Deterministic block sum of per-thread values (256 threads).
@@ -275,7 +308,7 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
                                                   int d_pad, int align, int gd, double* sxy,
                                                   PairState* st, double* v, double* t64,
                                                   float* t32, PairCount* cnt, hbt_result* res,
-                                                  int p0) {
+                                                  int p0, float* __restrict__ v32) {
     __shared__ double red[256];
     const int p = blockIdx.x + p0;
     const PairDesc pd = pairs[p];
@@ -300,14 +333,15 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
         return acc;
     };
     int bad = 0;
-    for (int k = pd.cx0 + threadIdx.x; k < pd.cy1; k += 256) bad |= chunk_bad[k];
+    for (int k = pd.cx0 + threadIdx.x; k < pd.cx1; k += 256) bad |= chunk_bad[k];
+    for (int k = pd.cy0 + threadIdx.x; k < pd.cy1; k += 256) bad |= chunk_bad[k];
     bad = __syncthreads_or(bad);
     double ssx = 0.0, ssy = 0.0;
     for (int c = threadIdx.x; c < d_pad; c += 256) {
         double a = 0.0, b = 0.0;
         if (c < d) {
             a = chunk_sum(pd.cx0, pd.cx1, c);
-            b = chunk_sum(pd.cx1, pd.cy1, c);
+            b = chunk_sum(pd.cy0, pd.cy1, c);
         }
         sx[c] = a;
         sy[c] = b;
@@ -334,11 +368,15 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
     for (int c = threadIdx.x; c < d_pad; c += 256) w += vp[c] * sx[c];
     w = block_sum(w, red);
     const double coef = identity ? 0.0 : 2.0 * w / vv;
+    double vt = 0.0;
     for (int c = threadIdx.x; c < d_pad; c += 256) {
         const double tc = (sx[c] - coef * vp[c]) + sy[c];
         tp[c] = tc;
         tq[c] = (float)tc;
+        vt += vp[c] * tc;
+        if (v32) v32[(int64_t)p * d_pad + c] = (float)vp[c];
     }
+    vt = block_sum(vt, red);
     if (threadIdx.x == 0) {
         const double dd = (double)d;
         const double fx = log_g(r_x, dd, gd), fy = log_g(r_y, dd, gd);
@@ -351,7 +389,7 @@ __global__ __launch_bounds__(256) void k_finalize(const PairDesc* __restrict__ p
         q.vv = vv;
         q.f_x = fx;
         q.f_y = fy;
-        q._pad = 0.0;
+        q.vt = vt;
         q.identity = identity;
         q.status = (r_x > 0.0 && r_x < 1.0 && r_y > 0.0 && r_y < 1.0)
                        ? (bad ? HBT_ERR_NOT_UNIT : HBT_OK)
@@ -386,10 +424,10 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
                            const int32_t* chunk_bad, int d,
                            int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
                            double* t64, float* t32, PairCount* cnt, hbt_result* res,
-                           hipStream_t s, int p0) {
+                           hipStream_t s, int p0, float* v32) {
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(npairs), dim3(256), 0, s, pairs, partial, chunk_bad, d, d_pad, align,
-                       gd, sxy, st, v, t64, t32, cnt, res, p0);
+                       gd, sxy, st, v, t64, t32, cnt, res, p0, v32);
     return hipGetLastError();
 }
 

@@ -164,6 +164,10 @@ struct Workspace {
     double* zt;         // z_i . t per pooled row
     double* partial2;   // block rows x row tiles x 2
     CTile* ctiles;      // its tile list (64 rows x 256 splits per tile)
+    // pairs of shared clouds (rows stored unreflected, the Householder fold)
+    PairDesc* cdesc;    // one run of storage per cloud (the column-sum table)
+    float* v32;         // FP32 copy of each pair's v
+    double* pv;         // v . sigma per split row and slot (slot-major)
     size_t bytes;
 };
 
@@ -211,6 +215,8 @@ struct Plan {
     };
     std::vector<Chunk> cplan;
     TileCost tune = default_tune(HBT_BF16X2);  // launch parameters of (precision, d_pad)
+    bool fold = false;             // pairs of shared clouds, stored unreflected
+    std::vector<PairDesc> cdesc;   // their clouds
 };
 
 Workspace carve(const Plan& P, void* ws) {
@@ -271,6 +277,15 @@ Workspace carve(const Plan& P, void* ws) {
         w.nflag = nullptr;
         w.sstat = nullptr;
     }
+    if (P.fold) {
+        w.cdesc = c.take<PairDesc>(std::max<size_t>(P.cdesc.size(), 1));
+        w.v32 = c.take<float>((size_t)np * P.d_pad);
+        w.pv = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.nslot);
+    } else {
+        w.cdesc = nullptr;
+        w.v32 = nullptr;
+        w.pv = nullptr;
+    }
     w.bytes = c.off + 256;
     return w;
 }
@@ -298,6 +313,10 @@ void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint3
         P.chunks.push_back(SumChunk{p, 1, (int32_t)(std::max<int64_t>(n, kSumChunkY * j) - n),
                                     (int32_t)(std::min<int64_t>(n + m, kSumChunkY * (j + 1)) - n)});
     pd.cy1 = (int32_t)P.chunks.size();
+    pd.cy0 = pd.cx1;
+    pd.zrow_y = P.zrows;
+    pd.nxc = pd.Np / kRowPad;
+    pd.ygap = 0;
     pd.xoct0 = P.xoct;
     P.xoct += x_octets(n);
     P.zrows += pd.Np;
@@ -487,6 +506,7 @@ BlockPair block_pair(int64_t mrow0, int64_t mword0, uint64_t perm_base, int64_t 
     b.m = pd.m;
     b.Wp = pd.Wp;
     b.pair_index = pd.pair_index;
+    b.ygap = pd.ygap;
     return b;
 }
 
@@ -627,7 +647,7 @@ hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_pa
                         P.route2 ? w.partial2 : w.partial, P.route2 ? 0 : P.nslot,
                         P.block_rows, P.d, common->gd,
                         common->alternative, precision_band(P.precision, P.d, P.route2), no_recheck, nullptr,
-                        0, w.tw, w.cnt, w.flags, w.nflag, s)); }
+                        0, w.tw, w.cnt, w.flags, w.nflag, s, w.pv, w.mask, w.coef)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
@@ -974,6 +994,88 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
 }
 
 // ---------------------------------------------------------------------------
+// Pairs of shared clouds: every cloud is stored once, unreflected, in one run
+// padded to kRowPad rows (its 32-row groups stored by the column-sum pass as
+// they are summed); pair p pools cloud pair_x[p] (X) and cloud pair_y[p] (Y)
+// as two runs, X's padding between them in the mask order.
+static bool plan_clouds(Plan& P, int64_t nclouds, const void* Z_all, const int64_t* cloud_offset,
+                        const int64_t* cloud_rows, int64_t npairs, const int64_t* pair_x,
+                        const int64_t* pair_y, const int64_t* B, const uint32_t* pair_index, int64_t d,
+                        const hbt_perm_params* common) {
+    P.fold = true;
+    for (int64_t c = 0; c < nclouds; ++c) {
+        const char* base = Z_all ? (const char*)Z_all + (size_t)cloud_offset[c] * d * 4 : nullptr;
+        P.aligned16 = P.aligned16 && ((uintptr_t)base % 16 == 0);
+        PairDesc cd;
+        memset(&cd, 0, sizeof cd);
+        cd.X = base;
+        cd.Y = base;
+        cd.n = 0;
+        cd.m = (int32_t)cloud_rows[c];
+        cd.Np = (int32_t)round_up(cloud_rows[c], kRowPad);
+        cd.Wp = cd.Np / 32;
+        cd.zrow0 = P.zrows;
+        cd.zrow_y = P.zrows;
+        cd.nxc = cd.Np / kRowPad;
+        cd.cx0 = cd.cx1 = cd.cy0 = (int32_t)P.chunks.size();
+        for (int64_t j = 0; kSumChunkY * j < cd.Np; ++j)
+            P.chunks.push_back(SumChunk{(int32_t)c, 1, (int32_t)(kSumChunkY * j),
+                                        (int32_t)std::min<int64_t>(cd.m, kSumChunkY * (j + 1))});
+        cd.cy1 = (int32_t)P.chunks.size();
+        P.zrows += cd.Np;
+        P.cdesc.push_back(cd);
+    }
+    int64_t rows = 0, words = 0;
+    std::map<std::tuple<int64_t, int64_t, int64_t, uint32_t>, int> first;
+    for (int64_t p = 0; p < npairs; ++p) {
+        const PairDesc& cx = P.cdesc[(size_t)pair_x[p]];
+        const PairDesc& cy = P.cdesc[(size_t)pair_y[p]];
+        PairDesc pd;
+        memset(&pd, 0, sizeof pd);
+        pd.X = cx.X;
+        pd.Y = cy.X;
+        pd.n = cx.m;
+        pd.m = cy.m;
+        pd.Np = cx.Np + cy.Np;
+        pd.Wp = pd.Np / 32;
+        pd.zrow0 = cx.zrow0;
+        pd.zrow_y = cy.zrow0;
+        pd.nxc = cx.Np / kRowPad;
+        pd.ygap = cx.Np - cx.m;
+        pd.coef0 = P.ncoef;
+        pd.pair_index = pair_index ? pair_index[p] : common->pair_index + (uint32_t)p;
+        pd.flip = pd.m < pd.n ? 1 : 0;
+        pd.cx0 = cx.cx1;
+        pd.cx1 = cx.cy1;
+        pd.cy0 = cy.cx1;
+        pd.cy1 = cy.cy1;
+        P.ncoef += pd.n;
+        P.max_np = std::max(P.max_np, (int)pd.Np);
+        P.pairs.push_back(pd);
+        const auto key = std::make_tuple((int64_t)pd.n, (int64_t)pd.m, B[p], pd.pair_index);
+        const auto hit = first.find(key);
+        if (hit == first.end()) {
+            first.emplace(key, (int)p);
+            P.bp.push_back(block_pair(rows, words, common->perm_offset, B[p], (int)p, pd));
+            words += B[p] * pd.Wp;
+        } else {
+            const BlockPair& o = P.bp[(size_t)hit->second];
+            P.bp.push_back(block_pair(rows, o.mword0, common->perm_offset, B[p], hit->second, pd));
+        }
+        P.Btot.push_back(B[p]);
+        rows += B[p];
+    }
+    P.npairs = (int)npairs;
+    finish_plan(P, d, common->precision, common->input_dtype);
+    std::vector<int> order((size_t)npairs);
+    for (int64_t p = 0; p < npairs; ++p) order[(size_t)p] = (int)p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.pairs[a].Np > P.pairs[b].Np; });
+    add_groups(P, order, B, 0, (int)npairs);
+    P.block_rows = rows;
+    P.block_mask_words = words;
+    return true;
+}
+
 // Number of pipeline chunks of a batched call (1 = no pipeline).
 int g_pipeline_chunks = 0;  // process-wide override (hbt_pipeline_chunks); 0: the tuned value
 int pipeline_chunks(const Plan& P, int64_t npairs) {
@@ -1285,6 +1387,120 @@ hbt_status hbt_tile_widths(int64_t npairs, const int64_t* B, int64_t d, int32_t*
         widths[p] = choose_width(B[p], tc);
     }
     return HBT_OK;
+}
+
+// The checks of the shared-clouds call that need no device memory.
+static hbt_status check_clouds(int64_t nclouds, const int64_t* cloud_rows, int64_t npairs,
+                               const int64_t* pair_x, const int64_t* pair_y, const int64_t* B, int64_t d,
+                               const hbt_perm_params* common) {
+    if (!common || !cloud_rows || !pair_x || !pair_y || !B) return fail(HBT_ERR_ARG, "NULL argument");
+    if (nclouds < 1 || nclouds > (1 << 24) || npairs < 1 || npairs > (1 << 24))
+        return fail(HBT_ERR_SIZE, "nclouds %lld, npairs %lld", (long long)nclouds, (long long)npairs);
+    hbt_status st = check_enums(common);
+    if (st) return st;
+    if (common->precision != HBT_BF16X2 || common->input_dtype != HBT_IN_F32 || common->stat_route != 0)
+        return fail(HBT_ERR_UNSUPPORTED, "shared clouds: split BF16 from FP32 rows, statistic route 0");
+    if (d < 1 || d > 1024 || d % 4)
+        return fail(HBT_ERR_UNSUPPORTED, "shared clouds: d a multiple of 4 up to 1024 (got %lld)", (long long)d);
+    for (int64_t c = 0; c < nclouds; ++c)
+        if (cloud_rows[c] < 2 || cloud_rows[c] > HBT_MAX_N)
+            return fail(HBT_ERR_SIZE, "cloud %lld has %lld rows", (long long)c, (long long)cloud_rows[c]);
+    int64_t total = 0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        if (pair_x[p] < 0 || pair_x[p] >= nclouds || pair_y[p] < 0 || pair_y[p] >= nclouds)
+            return fail(HBT_ERR_ARG, "pair %lld: cloud index out of range", (long long)p);
+        const int64_t n = cloud_rows[pair_x[p]], m = cloud_rows[pair_y[p]];
+        if (round_up(n, kRowPad) + round_up(m, kRowPad) > HBT_MAX_N + kRowPad)
+            return fail(HBT_ERR_SIZE, "pair %lld: n + m too large", (long long)p);
+        if ((st = check_sizes(n, m, d, B[p], common->perm_offset)))
+            return fail(st, "pair %lld: %s", (long long)p, g_err.c_str());
+        total += B[p];
+    }
+    if (total >= (int64_t)1 << 32) return fail(HBT_ERR_SIZE, "too many splits in one call");
+    return HBT_OK;
+}
+
+size_t hbt_perm_test_clouds_workspace_size(int64_t nclouds, const int64_t* cloud_rows, int64_t npairs,
+                                           const int64_t* pair_x, const int64_t* pair_y, const int64_t* B,
+                                           int64_t d, const hbt_perm_params* common) {
+    if (check_clouds(nclouds, cloud_rows, npairs, pair_x, pair_y, B, d, common)) return 0;
+    std::vector<int64_t> off((size_t)nclouds, 0);
+    Plan P;
+    plan_clouds(P, nclouds, nullptr, off.data(), cloud_rows, npairs, pair_x, pair_y, B, nullptr, d, common);
+    return carve(P, nullptr).bytes;
+}
+
+hbt_status hbt_perm_test_clouds(int64_t nclouds, const void* Z_all, const int64_t* cloud_offset,
+                                const int64_t* cloud_rows, int64_t npairs, const int64_t* pair_x,
+                                const int64_t* pair_y, const int64_t* B, const uint32_t* pair_index, int64_t d,
+                                const hbt_perm_params* common, hbt_result* results, void* ws, size_t ws_bytes,
+                                void* stream) {
+    g_err.clear();
+    if (!Z_all || !cloud_offset || !results) return fail(HBT_ERR_ARG, "NULL argument");
+    hbt_status st = check_clouds(nclouds, cloud_rows, npairs, pair_x, pair_y, B, d, common);
+    if (st) return st;
+    for (int64_t c = 0; c < nclouds; ++c)
+        if (cloud_offset[c] < 0) return fail(HBT_ERR_ARG, "cloud %lld: negative row offset", (long long)c);
+    Plan P;
+    plan_clouds(P, nclouds, Z_all, cloud_offset, cloud_rows, npairs, pair_x, pair_y, B, pair_index, d, common);
+    if (!vector_rows(P)) return fail(HBT_ERR_UNSUPPORTED, "shared clouds: every cloud must start on 16 bytes");
+    const size_t need = carve(P, nullptr).bytes;
+    if (!ws || ws_bytes < need)
+        return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (split_lds_per_block(P.max_np) > std::min<size_t>(split_lds_limit(), 65536))
+        return fail(HBT_ERR_SIZE, "n + m too large for the split kernel's LDS");
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w = carve(P, ws);
+    const int np = P.npairs;
+    hipStream_t qs, qt;
+    HIP_TRY(side_stream(&qs, 0));
+    HIP_TRY(side_stream(&qt, 1));
+    Events ev;
+    hipEvent_t e0;
+    HIP_TRY(ev.record(s, &e0));
+    HIP_TRY(hipStreamWaitEvent(qs, e0, 0));
+    HIP_TRY(hipStreamWaitEvent(qt, e0, 0));
+    {
+        StageTimer t_(HBT_STAGE_SPLIT, qs);
+        HIP_TRY(upload(w.bp, P.bp.data(), P.bp.size() * sizeof(BlockPair), qs));
+        HIP_TRY(zero(w.sstat, (size_t)(np + 1) / 2 * 8, qs));
+        HIP_TRY(launch_split_masks(w.bp, np, P.block_rows, P.max_np, common->seed, w.mask, w.sstat,
+                                   P.tune.split_cap, qs));
+    }
+    {
+        StageTimer t_(HBT_STAGE_OTHER, qt);
+        HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), qt));
+        HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), qt));
+        HIP_TRY(zero(w.nflag, 8, qt));
+    }
+    {
+        StageTimer t_(HBT_STAGE_OTHER, s);
+        HIP_TRY(upload(w.cdesc, P.cdesc.data(), P.cdesc.size() * sizeof(PairDesc), s));
+        HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
+    }
+    {
+        // every cloud summed and stored once; per pair the directions, v, T_obs
+        // and the reflected total; then the pairs' coefficients 2 (v . x_i) / (v . v)
+        StageTimer t_(HBT_STAGE_ALIGN, s);
+        HIP_TRY(launch_colsum_store_vec(P.precision, w.cdesc, (int)P.cdesc.size(), (int)P.chunks.size(), P.d,
+                                        P.d_pad, w.partial_sum, w.zstore, P.zrows * P.d_pad, nullptr,
+                                        w.chunk_bad, s));
+        HIP_TRY(launch_finalize(w.pairs, np, w.partial_sum, w.chunk_bad, P.d, P.d_pad, common->align, common->gd,
+                                w.sxy, w.st, w.v, w.t64, w.t32, w.cnt, results, s, 0, w.v32));
+        HIP_TRY(launch_fold_coef(w.pairs, np, w.st, w.v, P.d, P.d_pad, P.ncoef, w.coef, s));
+    }
+    HIP_TRY(ev.record(qs, &e0));
+    HIP_TRY(hipStreamWaitEvent(s, e0, 0));
+    HIP_TRY(ev.record(qt, &e0));
+    HIP_TRY(hipStreamWaitEvent(s, e0, 0));
+    {
+        StageTimer t_(HBT_STAGE_GROUPSUM, s);
+        HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, 0, w.groups, P.ngw, (int)P.ntw, P.ng256,
+                                (int)P.nt256, P.d_pad, w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64,
+                                w.partial, P.block_rows, nullptr, s, P.tune.grid_wide, P.tune.grid_narrow,
+                                w.v32, w.pv));
+    }
+    return batched_epilogue(P, w, common, results, s);
 }
 
 hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous) {

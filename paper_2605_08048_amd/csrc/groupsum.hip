@@ -118,13 +118,18 @@ constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14
 // epilogue overlap the other waves' MFMAs.  On 512 pairs, d = 768: 4 waves x
 // 512 splits with two work-groups per CU 4.18 ms (11.1 GB fetched), 8 waves x
 // 1024 splits 4.02 ms; one work-group per CU of 4 waves 4.7 ms.
-template <int JB, int NW>
+//
+// FOLD (pairs of shared clouds, stored unreflected): the epilogue also sums
+// v . sigma per split and slot into pv (v the pair's FP32 Householder vector
+// v32), from which the statistic reflects the group sums (Householder fold).
+template <int JB, int NW, bool FOLD>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
-    double* __restrict__ partial, int64_t prow, float* __restrict__ sig) {
+    double* __restrict__ partial, int64_t prow, float* __restrict__ sig,
+    const float* __restrict__ v32, double* __restrict__ pv) {
     constexpr int kWS = 32 * JB;
     constexpr int kTile = NW * kWS;
     constexpr int kMaskVec = kTile;
@@ -156,16 +161,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // loader cursor: tile l_it, chunk l_ch (one chunk ahead of the multiplication)
     int l_it = next_valid(blockIdx.x);
     if (l_it >= nlogical) return;  // work-group-uniform
-    int l_ch = 0, l_nchunk = 0;
+    int l_ch = 0, l_nchunk = 0, l_nxc = 0;
     const uint4* l_zsrc = nullptr;
+    const uint4* l_zsrc_y = nullptr;
     const uint4* l_mload[kMaskLoads];
     auto l_setup = [&]() {
         const Tile t = tile_of(l_it);
         const PairDesc pd = pairs[t.pair];
         const BlockPair bq = bp[t.pair];
         l_nchunk = pd.Np / kChunk;
-        const int64_t oct0 = pd.zrow0 >> 3;
-        l_zsrc = ((kRowsW * wave) / kOct ? zlo : zhi) + (oct0 + (kRowsW * wave) % kOct) * d_pad + t.slot * kDSlot;
+        l_nxc = pd.nxc;
+        const uint4* plane = (kRowsW * wave) / kOct ? zlo : zhi;
+        const int64_t off = (kRowsW * wave) % kOct;
+        l_zsrc = plane + ((pd.zrow0 >> 3) + off) * d_pad + t.slot * kDSlot;
+        l_zsrc_y = plane + ((pd.zrow_y >> 3) + off) * d_pad + t.slot * kDSlot;
 #pragma unroll
         for (int k = 0; k < kMaskLoads; ++k) {
             const int r = t.b0 + wave * kWS + 64 * k + lane;
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // one chunk at the cursor into buffer b, then advance the cursor (past the
     // work-group's last chunk it stays there: a harmless reload into a free buffer)
     auto issue_next = [&](int b) {
-        const uint4* base = l_zsrc + l_ch * chunk_stride;
+        const uint4* base = l_ch < l_nxc ? l_zsrc + l_ch * chunk_stride : l_zsrc_y + (l_ch - l_nxc) * chunk_stride;
         const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(&zbuf[b][kRowsW * wave * kDSlot]));
         const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(&mbuf[b][wave * kWS]));
 #pragma unroll
@@ -278,9 +287,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
+        const float* vq = FOLD ? v32 + (int64_t)t.pair * d_pad + d0 : nullptr;
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
-            float ss = 0.0f, sl = 0.0f;
+            float ss = 0.0f, sl = 0.0f, sd = 0.0f;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -289,12 +299,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
                     const float lv = tv[i][v] - sv;
                     ss += sv * sv;
                     sl += lv * lv;
+                    if (FOLD) sd += vq[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)] * sv;
                 }
             ss += __shfl_xor(ss, 32, 64);
             sl += __shfl_xor(sl, 32, 64);
+            if (FOLD) sd += __shfl_xor(sd, 32, 64);
             if (h == 0 && keep[j]) {
                 double2* out = (double2*)partial + t.slot * prow + bq.mrow0 + brow[j];
                 *out = make_double2((double)ss, (double)sl);
+                if (FOLD) pv[t.slot * prow + bq.mrow0 + brow[j]] = (double)sd;
             }
             if (sig && keep[j]) {
                 float* sr = sig + (bq.mrow0 + brow[j]) * (int64_t)d_pad + d0;
@@ -678,7 +691,7 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig, hipStream_t s,
-                           int grid_wide, int grid_narrow) {
+                           int grid_wide, int grid_narrow, const float* v32, double* pv) {
     const int nslot = d_pad / kDSlot;
     if (grid_wide <= 0) grid_wide = 16;
     if (grid_narrow <= 0) grid_narrow = precision == HBT_I8X3 ? 16 : 32;
@@ -688,14 +701,26 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             const uint4* zhi = (const uint4*)zstore;
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
             static_assert(32 * 4 * 8 == kTileWide && 32 * 2 * 4 == kTileNarrow, "tile widths");
-            if (ntw > 0)
-                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8>), dim3(persistent_grid(ntw, grid_wide)), dim3(512), 0,
-                                   s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
-                                   t32, partial, prow, sig);
-            if (nt256 > 0)
-                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4>), dim3(persistent_grid(nt256, grid_narrow)), block, 0,
-                                   s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                   mask, t32, partial, prow, sig);
+            if (ntw > 0) {
+                if (pv)
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, true>), dim3(persistent_grid(ntw, grid_wide)),
+                                       dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
+                                       t32, partial, prow, sig, v32, pv);
+                else
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false>), dim3(persistent_grid(ntw, grid_wide)),
+                                       dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
+                                       t32, partial, prow, sig, nullptr, nullptr);
+            }
+            if (nt256 > 0) {
+                if (pv)
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, true>), dim3(persistent_grid(nt256, grid_narrow)),
+                                       block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
+                                       mask, t32, partial, prow, sig, v32, pv);
+                else
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false>), dim3(persistent_grid(nt256, grid_narrow)),
+                                       block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
+                                       mask, t32, partial, prow, sig, nullptr, nullptr);
+            }
             break;
         }
         case HBT_I8X3:

@@ -36,12 +36,18 @@ struct PairDesc {
     int64_t coef0;       // first of its n reflection coefficients
     uint32_t pair_index; // Philox counter word 2
     int32_t flip;        // 1 when m < n: group sums run on the group-2 mask
-    int32_t cx0, cx1;    // column-sum chunks of X: [cx0, cx1); of Y: [cx1, cy1)
+    int32_t cx0, cx1;    // column-sum chunks of X: [cx0, cx1); of Y: [cy0, cy1)
     int32_t cy1;
-    int32_t _pad0;
+    int32_t cy0;         // (= cx1 when X and Y are stored as one pooled run)
     int64_t xoct0;       // first of its x_octets(n) octets in the numbering of the storage
                          // octets that hold X rows (the reflection's work items)
-    int64_t _pad1[2];
+    // Two-run storage (pairs of shared clouds): the pooled rows [0, Np) are
+    // nxc 128-row chunks of X's storage from zrow0, then Y's storage from
+    // zrow_y; in the pooled (and mask) order Y's rows start at n + ygap, the
+    // ygap rows between being X's padding.  One run: nxc = Np / 128, ygap = 0.
+    int64_t zrow_y;
+    int32_t nxc;
+    int32_t ygap;
 };
 static_assert(sizeof(PairDesc) == 96, "PairDesc layout");
 
@@ -59,9 +65,23 @@ struct BlockPair {
     int32_t n, m;
     int32_t Wp;          // mask words per split row (Np / 32)
     uint32_t pair_index; // Philox counter word 2
-    int32_t _pad;
+    int32_t ygap;        // PairDesc::ygap: Y's items sit ygap positions further in the mask
 };
 static_assert(sizeof(BlockPair) == 48, "BlockPair layout");
+
+#ifdef __HIPCC__
+// The bits of mask word w that stand for items (not padding): positions
+// [0, n) (X) and [n + ygap, n + m + ygap) (Y).
+__device__ __forceinline__ uint32_t range_bits(int w, int lo, int hi) {
+    const int a = lo > 32 * w ? lo - 32 * w : 0, b = hi < 32 * w + 32 ? hi - 32 * w : 32;
+    if (a >= b) return 0u;
+    const uint32_t upto_b = b == 32 ? 0xffffffffu : (1u << b) - 1u;
+    return upto_b & ~((1u << a) - 1u);
+}
+__device__ __forceinline__ uint32_t item_bits(int w, int n, int m, int ygap) {
+    return range_bits(w, 0, n) | range_bits(w, n + ygap, n + m + ygap);
+}
+#endif
 
 #ifdef __HIPCC__
 // Mask words of split row `row` (a block row of pair bq).
@@ -107,7 +127,8 @@ struct GemmGroup {
 
 // FP64 per-pair state written by the finalize kernel.
 struct PairState {
-    double r_x, r_y, t_obs, tau, vv, f_x, f_y, _pad;
+    double r_x, r_y, t_obs, tau, vv, f_x, f_y;
+    double vt;           // v . t (t the pooled total of the aligned rows)
     int32_t identity, status;
     int32_t _pad2[2];
 };

@@ -30,7 +30,12 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
                            const int32_t* chunk_bad, int d,
                            int d_pad, int align, int gd, double* sxy, PairState* st, double* v,
                            double* t64, float* t32, PairCount* cnt, hbt_result* res,
-                           hipStream_t s, int p0 = 0);  // pairs [p0, p0 + npairs)
+                           hipStream_t s, int p0 = 0,  // pairs [p0, p0 + npairs)
+                           float* v32 = nullptr);      // FP32 copy of v (d_pad per pair), nullable
+// coef[coef0 + i] = 2 (v . x_i) / (v . v) (0 when H = I) for the X rows of
+// every pair (FP32 rows), total = sum of n.
+hipError_t launch_fold_coef(const PairDesc* pairs, int npairs, const PairState* st, const double* v, int d,
+                            int d_pad, int64_t total, double* coef, hipStream_t s);
 // Reflect X rows, write Z in the precision's storage format, the FP64
 // coefficients 2 (v.x_i) / (v.v) and zero padding.
 // 16-byte-load variants for FP32 rows with d % 4 == 0 and d_pad <= 1024 (the
@@ -103,10 +108,13 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig,
-                           hipStream_t s, int grid_wide = 16, int grid_narrow = 0);
+                           hipStream_t s, int grid_wide = 16, int grid_narrow = 0,
+                           const float* v32 = nullptr, double* pv = nullptr);
 // grid_wide / grid_narrow: persistent work-groups per CU of the 1024-split
 // launch and of the 256-split (or int8) launch (0: 32 for the 256-split
-// split-BF16 kernel, 16 for int8).
+// split-BF16 kernel, 16 for int8).  pv (split BF16 only, nullable): also
+// v . sigma per split and slot (v32 the pairs' FP32 Householder vectors),
+// for pairs whose rows are stored unreflected.
 
 // --- point-to-centroid route (statistic route 2) -------------------------
 // z_i . t per pooled row; then Q = Z S^T with the masked column sums
@@ -125,7 +133,8 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, const RecheckBand& band, int no_recheck, void* T_out,
                        int T_mode, double* Tw,
-                       PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s);
+                       PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s, const double* pv = nullptr,
+                       const uint32_t* mask = nullptr, const double* coef = nullptr);
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
 // doubles of per-wave segment sums (nullptr: every flag done whole by one
 // work-group); the value of each flag's sums does not depend on it.

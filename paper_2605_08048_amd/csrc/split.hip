@@ -244,7 +244,25 @@ __global__ __launch_bounds__(256) void k_split_masks(const BlockPair* __restrict
     }
     wave_sync();
     uint32_t* out = const_cast<uint32_t*>(mask_row(mask, bp[p], row, pd.Wp));
-    for (int w = lane; w < pd.Wp; w += 64) out[w] = mlds[w];
+    if (pd.ygap == 0) {
+        for (int w = lane; w < pd.Wp; w += 64) out[w] = mlds[w];
+    } else {
+        // two-run storage: X's items keep their positions, Y's move ygap
+        // positions on (X's padding in between); n + ygap is a multiple of 128
+        const int ys = n + pd.ygap;
+        for (int w = lane; w < pd.Wp; w += 64) {
+            uint32_t x;
+            if (32 * w < ys) {
+                x = mlds[w] & range_bits(w, 0, n);
+            } else {
+                const int p0 = 32 * w - pd.ygap, q = p0 >> 5, sh = p0 & 31;
+                const uint32_t a = mlds[q], b = q + 1 < pd.Wp ? mlds[q + 1] : 0u;
+                x = sh ? (a >> sh) | (b << (32 - sh)) : a;
+                x &= range_bits(w, ys, ys + pd.m);
+            }
+            out[w] = x;
+        }
+    }
 }
 
 // LDS of one CU (160 KB on MI355X), from the device.

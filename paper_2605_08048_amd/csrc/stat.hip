@@ -18,7 +18,10 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               int gd, int alternative, RecheckBand band,
                                               int no_recheck, void* T_out,
                                               int T_mode, double* __restrict__ Tw,
-                                              PairCount* cnt, uint32_t* flags, uint32_t* nflag) {
+                                              PairCount* cnt, uint32_t* flags, uint32_t* nflag,
+                                              const double* __restrict__ pv,
+                                              const uint32_t* __restrict__ mask,
+                                              const double* __restrict__ coef) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = row < rows;
     int p = 0;
@@ -36,6 +39,30 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
             const double2 v = pr[k * prow];
             ss_small += v.x;
             ss_large += v.y;
+        }
+        if (pv) {
+            // Householder fold: the product summed the unreflected rows, so
+            // sigma' = sigma - c v with c = sum over the smaller group's X rows
+            // of 2 (v . x_i) / (v . v) (FP64, from the mask bits), and
+            //   |sigma'|^2     = |sigma|^2 - 2 c (v . sigma) + c^2 (v . v),
+            //   |t - sigma'|^2 = |t - sigma|^2 + 2 c (v . t - v . sigma) + c^2 (v . v)
+            // (t the pooled total of the reflected rows).
+            double sv = 0.0;
+            for (int k = 0; k < ns; ++k) sv += pv[k * prow + row];
+            const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
+            const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+            const double* cf = coef + pd.coef0;
+            double c = 0.0;
+            for (int w = 0; 32 * w < pd.n; ++w) {
+                uint32_t bits = (mk[w] ^ flip) & range_bits(w, 0, pd.n);
+                while (bits) {
+                    c += cf[32 * w + __builtin_ctz(bits)];
+                    bits &= bits - 1u;
+                }
+            }
+            const double cvv = c * c * q.vv;
+            ss_small = ss_small - 2.0 * c * sv + cvv;
+            ss_large = ss_large + 2.0 * c * (q.vt - sv) + cvv;
         }
         // group 1 has n items, group 2 has m; the product ran on the smaller one
         const double ss1 = pd.flip ? ss_large : ss_small;
@@ -84,12 +111,12 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, const RecheckBand& band, int no_recheck, void* T_out,
                        int T_mode, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
-                       hipStream_t s) {
+                       hipStream_t s, const double* pv, const uint32_t* mask, const double* coef) {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
                        npairs, rows, st, partial, nslot, prow, d, gd, alternative, band,
                        no_recheck,
-                       T_out, T_mode, Tw, cnt, flags, nflag);
+                       T_out, T_mode, Tw, cnt, flags, nflag, pv, mask, coef);
     return hipGetLastError();
 }
 
@@ -134,7 +161,7 @@ __device__ __forceinline__ FlagCtx flag_ctx(const PairDesc* pairs, const BlockPa
     c.q = st[c.p];
     c.mk = mask_row(mask, bp[c.p], c.row, c.pd.Wp);
     c.N = c.pd.n + c.pd.m;
-    c.W = (c.N + 31) >> 5;
+    c.W = (c.N + c.pd.ygap + 31) >> 5;  // mask words that hold items (Y's start ygap further on)
     c.G = (c.W + kSegWords - 1) / kSegWords;
     return c;
 }
@@ -202,13 +229,11 @@ __global__ __launch_bounds__(kRecheckThreads) void k_recheck(
         const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
         const Tin* X = (const Tin*)pd.X;
         const Tin* Y = (const Tin*)pd.Y;
-        const int W = c.W, N = c.N;
+        const int W = c.W;
         // members of the smaller group in mask word w
         auto word_bits = [&](int w, int wend) -> uint32_t {
             if (w >= wend) return 0u;
-            uint32_t bits = c.mk[w] ^ flip;
-            if (w == W - 1 && (N & 31)) bits &= (1u << (N & 31)) - 1u;
-            return bits;
+            return (c.mk[w] ^ flip) & item_bits(w, pd.n, pd.m, pd.ygap);
         };
         double ss_small = 0.0, ss_large = 0.0;
         for (int c0 = 0; c0 < d; c0 += kRecheckPass) {
@@ -249,7 +274,8 @@ __global__ __launch_bounds__(kRecheckThreads) void k_recheck(
                     double kc[kRows], wt[kRows];
 #pragma unroll
                     for (int t = 0; t < kRows; ++t) {
-                        const int i = rows[t] < 0 ? 0 : rows[t];
+                        int i = rows[t] < 0 ? 0 : rows[t];
+                        if (i >= pd.n) i -= pd.ygap;  // Y's mask positions to pooled items
                         const bool isx = i < pd.n;
                         kc[t] = (rows[t] >= 0 && isx) ? cf[i] : 0.0;
                         wt[t] = rows[t] >= 0 ? 1.0 : 0.0;

@@ -111,6 +111,11 @@ def lib():
         L.hbt_tile_widths.argtypes = [i64, P, i64, P]
         L.hbt_recheck_band.argtypes = [i32, i32, i32, i64, i64, i64, dbl, dbl, P]
         L.hbt_perm_test_static.argtypes = [P, P, C.POINTER(HbtPermParams), P, P, P, P]
+        L.hbt_perm_test_clouds_workspace_size.argtypes = [i64, P, i64, P, P, P, i64, C.POINTER(HbtPermParams)]
+        L.hbt_perm_test_clouds_workspace_size.restype = sz
+        L.hbt_perm_test_clouds.argtypes = [i64, P, P, P, i64, P, P, P, P, i64, C.POINTER(HbtPermParams), P, P,
+                                           sz, P]
+        L.hbt_perm_test_clouds.restype = i32
         L.hbt_pipeline_chunks.argtypes = [i32, P]
         L.hbt_pipeline_chunks.restype = i32
         L.hbt_perm_test_static.restype = i32
@@ -406,6 +411,58 @@ def perm_test_batched(Z_all, row_offset, n, m, B, *, seed=0, perm_offset=0, pair
                                    None if ids is None else ptr(ids), d, C.byref(prm),
                                    C.c_void_p(res.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
                                    _stream(stream)))
+    if not sync:
+        return res
+    return results_to_numpy(res)
+
+
+def perm_test_clouds(Z_all, cloud_offset, cloud_rows, pair_x, pair_y, B, *, seed=0, perm_offset=0,
+                     pair_index=None, gd="banerjee", alternative="greater", align=True, recheck=True,
+                     stream=None, sync=True, results=None, workspace=None):
+    """Many pairs over shared clouds, each cloud stored once (split BF16, the
+    Householder reflection folded into the statistic).  Z_all (device FP32
+    tensor) holds the clouds' rows: cloud c is ``cloud_rows[c]`` rows from row
+    ``cloud_offset[c]``; pair p tests cloud ``pair_x[p]`` (X) against cloud
+    ``pair_y[p]`` (Y) with ``B[p]`` splits.  Returns a numpy structured array
+    of hbt_result (or, with sync=False, the device result tensor)."""
+    torch = _torch()
+    dev = Z_all.device
+    _on_device("Z_all", Z_all, dev)
+    if Z_all.dtype != torch.float32 or Z_all.dim() != 2:
+        raise HbtError(ERR_DTYPE, "Z_all must be a 2-D float32 tensor")
+    Z_all = Z_all.contiguous()
+    d = Z_all.shape[1]
+    off = np.ascontiguousarray(cloud_offset, dtype=np.int64).ravel()
+    rows = np.ascontiguousarray(cloud_rows, dtype=np.int64).ravel()
+    px = np.ascontiguousarray(pair_x, dtype=np.int64).ravel()
+    py = np.ascontiguousarray(pair_y, dtype=np.int64).ravel()
+    P = px.size
+    BB = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.int64), (P,)))
+    if off.size != rows.size or py.size != P:
+        raise HbtError(ERR_SIZE, "cloud_offset / cloud_rows and pair_x / pair_y must have equal lengths")
+    if np.any(off < 0) or np.any(off + rows > Z_all.shape[0]):
+        raise HbtError(ERR_SIZE, "a cloud's rows lie outside Z_all")
+    ids = None if pair_index is None else np.ascontiguousarray(pair_index, dtype=np.uint32).ravel()
+    if ids is not None and ids.size != P:
+        raise HbtError(ERR_SIZE, "pair_index needs one entry per pair")
+    prm = make_params(0, 0, d, 0, seed=seed, perm_offset=perm_offset, precision="bf16x2", input_dtype=0, gd=gd,
+                      alternative=alternative, align=align, recheck=recheck)
+    L = lib()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    need = L.hbt_perm_test_clouds_workspace_size(rows.size, ptr(rows), P, ptr(px), ptr(py), ptr(BB), d,
+                                                 C.byref(prm))
+    if need == 0:
+        need = 256
+    ws = workspace if workspace is not None else globals()["workspace"](need, dev)
+    if results is not None:
+        _on_device("results", results, dev)
+        if results.dtype != torch.uint8 or results.numel() < RESULT_BYTES * P or not results.is_contiguous():
+            raise HbtError(ERR_SIZE, f"results must be a contiguous uint8 tensor of {RESULT_BYTES * P} bytes")
+    res = results if results is not None else torch.zeros(RESULT_BYTES * P, dtype=torch.uint8, device=dev)
+    _check(L.hbt_perm_test_clouds(rows.size, C.c_void_p(Z_all.data_ptr()), ptr(off), ptr(rows), P, ptr(px),
+                                  ptr(py), ptr(BB), None if ids is None else ptr(ids), d, C.byref(prm),
+                                  C.c_void_p(res.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                  _stream(stream)))
     if not sync:
         return res
     return results_to_numpy(res)

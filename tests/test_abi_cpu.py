@@ -191,6 +191,32 @@ def test_batched_validation():
     assert st == hbt.ERR_UNSUPPORTED
 
 
+def test_clouds_validation():
+    """The shared-clouds call refuses what it does not cover before anything
+    is enqueued: other precisions, a cloud index out of range, odd d, a cloud
+    of fewer than 2 rows, a too-small workspace."""
+    L = hbt.lib()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    import numpy as np
+    FAKE = C.c_void_p(256)
+    rows = np.array([40, 70, 33], dtype=np.int64)
+    off = np.array([0, 40, 110], dtype=np.int64)
+    px, py = np.array([0, 1], dtype=np.int64), np.array([1, 2], dtype=np.int64)
+    B = np.array([100, 200], dtype=np.int64)
+    prm = hbt.make_params(0, 0, 64, 0, precision="bf16x2")
+    need = L.hbt_perm_test_clouds_workspace_size(3, ptr(rows), 2, ptr(px), ptr(py), ptr(B), 64, C.byref(prm))
+    assert need > 0
+    call = lambda prm, rows=rows, px=px, d=64, ws=need: L.hbt_perm_test_clouds(
+        3, FAKE, ptr(off), ptr(rows), 2, ptr(px), ptr(py), ptr(B), None, d, C.byref(prm), FAKE, FAKE, ws, None)
+    assert call(prm, ws=need - 1) == hbt.ERR_WORKSPACE
+    assert call(prm, px=np.array([0, 3], dtype=np.int64)) == hbt.ERR_ARG
+    assert call(prm, rows=np.array([40, 1, 33], dtype=np.int64)) == hbt.ERR_SIZE
+    assert call(prm, d=66) == hbt.ERR_UNSUPPORTED
+    for prec in ("f32", "i8x3"):
+        assert call(hbt.make_params(0, 0, 64, 0, precision=prec)) == hbt.ERR_UNSUPPORTED
+    assert call(hbt.make_params(0, 0, 64, 0, precision="bf16x2", stat_route=1)) == hbt.ERR_UNSUPPORTED
+
+
 def test_tile_width_rule_and_tuning_table(tmp_path):
     """Per pair, the width w in {1024, 256} minimising cost_w * round_up(B, w)."""
     import numpy as np
