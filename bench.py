@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
     ap.add_argument("--single-steps", type=int, default=5,
                     help="timed calls per precision of the single-pair workloads (0 skips them)")
+    ap.add_argument("--cloud-steps", type=int, default=5,
+                    help="timed calls of the shared-clouds workload and of its pairs stored apart (0 skips them)")
     ap.add_argument("--route2-steps", type=int, default=2,
                     help="timed steps of the point-to-centroid route (0 skips them)")
     ap.add_argument("--graph-steps", type=int, default=10,
@@ -453,6 +455,42 @@ def main():
                 "count": int(res["count"]), "status": int(res["status"])}
             log(f"route 2 pair_d768 {prec}: {dt1 * 1e3:.3f} ms/call, centroid {c_ms:.3f} ms")
 
+    # shared clouds: the same kind of batch with each word's cloud in many
+    # pairs, stored once (Householder fold), against the batched call on the
+    # same pairs stored pair by pair
+    clouds = None
+    if args.cloud_steps > 0:
+        wc = synth.word_clouds(d=d)
+        pb = wc.pairs_batch()
+        Zc = torch.from_numpy(wc.Z).to(dev)
+        Zp = torch.from_numpy(pb.Z).to(dev)
+        rc_res = torch.zeros(hbt.RESULT_BYTES * len(wc.B), dtype=torch.uint8, device=dev)
+        rb_res = torch.zeros_like(rc_res)
+        c_call = lambda: hbt.perm_test_clouds(Zc, wc.offset, wc.rows, wc.pair_x, wc.pair_y, wc.B, seed=wc.seed,
+                                              sync=False, results=rc_res)
+        b_call = lambda: hbt.perm_test_batched(Zp, pb.row_offset, pb.n, pb.m, pb.B, seed=pb.seed, sync=False,
+                                               results=rb_res)
+        timing = {}
+        for name, call in (("clouds", c_call), ("batched", b_call)):
+            call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.cloud_steps):
+                call()
+            torch.cuda.synchronize()
+            timing[name] = (time.perf_counter() - t0) / args.cloud_steps * 1e3
+        oc, ob = hbt.results_to_numpy(rc_res), hbt.results_to_numpy(rb_res)
+        nst = int(wc.B.sum())
+        clouds = {"workload": f"word_clouds: {len(wc.rows)} word clouds (n log-uniform [20, 5000]), "
+                              f"{len(wc.B)} pairs of distinct words, d={d}, B=2000",
+                  "ms_per_call_shared_clouds": timing["clouds"], "ms_per_call_pairs_stored_apart": timing["batched"],
+                  "value_shared_clouds": nst / (timing["clouds"] * 1e-3),
+                  "rows_stored_shared": int(wc.rows.sum()), "rows_stored_apart": int(pb.Z.shape[0]),
+                  "pairs_with_equal_counts": f"{int(np.sum(oc['count'] == ob['count']))}/{len(wc.B)}",
+                  "pairs_bad_status": int(np.sum(oc["status"] != 0))}
+        log(f"shared clouds: {timing['clouds']:.2f} ms/call vs {timing['batched']:.2f} ms stored apart")
+        del Zc, Zp
+
     errors = None
     if args.single_steps > 0:
         errors = stage_errors(dev, synth.null_pair_d1024(), hbt, torch)
@@ -489,6 +527,7 @@ def main():
         "fp32_plain": fp,
         "int8_planes": i8,
         "point_to_centroid": route2,
+        "shared_clouds": clouds,
         "single_pair": single,
         "tuning": tuning,
         "stage_errors_null_pair_d1024": errors,

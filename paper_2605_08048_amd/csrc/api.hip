@@ -237,7 +237,7 @@ Workspace carve(const Plan& P, void* ws) {
     w.t32 = c.take<float>((size_t)np * P.d_pad);
     w.cnt = c.take<PairCount>(np);
     if (P.need_store) {
-        w.coef = c.take<double>(std::max<int64_t>(P.ncoef, 1));
+        w.coef = c.take<double>(std::max<int64_t>(P.ncoef, 1) + 32);  // 32 spare: whole mask words read
         const size_t zb = zstore_bytes(P.precision, P.zrows, P.d_pad);
         w.zstore = c.take<char>(zb);
         w.mask = c.take<uint32_t>(std::max<int64_t>(P.block_mask_words, 1));

@@ -287,7 +287,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int v = 0; v < 16; ++v) tv[i][v] = tp[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
-        const float* vq = FOLD ? v32 + (int64_t)t.pair * d_pad + d0 : nullptr;
+        float vr[2][16];
+        if constexpr (FOLD) {
+            const float* vq = v32 + (int64_t)t.pair * d_pad + d0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) vr[i][v] = vq[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)];
+        }
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
             float ss = 0.0f, sl = 0.0f, sd = 0.0f;
@@ -299,7 +306,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
                     const float lv = tv[i][v] - sv;
                     ss += sv * sv;
                     sl += lv * lv;
-                    if (FOLD) sd += vq[32 * i + 8 * (v >> 2) + 4 * h + (v & 3)] * sv;
+                    if (FOLD) sd += vr[i][v] * sv;
                 }
             ss += __shfl_xor(ss, 32, 64);
             sl += __shfl_xor(sl, 32, 64);

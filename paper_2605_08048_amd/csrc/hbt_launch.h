@@ -135,6 +135,10 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        int T_mode, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s, const double* pv = nullptr,
                        const uint32_t* mask = nullptr, const double* coef = nullptr);
+// launch_stat with pv (v . sigma per slot), mask and coef non-null reflects
+// the group sums of pairs stored unreflected (the Householder fold): a first
+// kernel writes each split's fold coefficient c into Tw, which the statistic
+// kernel reads before it stores T_b there.
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
 // doubles of per-wave segment sums (nullptr: every flag done whole by one
 // work-group); the value of each flag's sums does not depend on it.

@@ -10,6 +10,85 @@
 
 namespace hbt {
 
+// Householder fold: c = sum over the smaller group's X rows of 2 (v . x_i) /
+// (v . v) per split row, into c_out[row] (FP64; four running sums, over the
+// indices i % 4 = 0, 1, 2, 3, added at the end).  A kernel of its own so that
+// the loop runs at a higher occupancy than the statistic's FP64 scalar math
+// allows.  In a wave of one pair (consecutive split rows, Wp words apart) the
+// X words of the 64 rows pass through LDS 16 at a time, read as 64-byte runs
+// of each row so that every fetched line is used whole; the 32 coefficients
+// of a word are wave-uniform (scalar loads) and a lane adds the ones its
+// bits select, the selection made with sign-extended one-bit masks rather
+// than branches.  A wave across a pair boundary takes each lane's own pair.
+constexpr int kFoldWords = 16;  // mask words per LDS pass
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+void k_fold_c(const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
+              int64_t rows, const uint32_t* __restrict__ mask, const double* __restrict__ coef,
+              double* __restrict__ c_out) {
+    // 64 rows x 16 words per wave; a row takes 20 words so that the lanes'
+    // 16-byte reads of their own rows fall on distinct banks
+    __shared__ uint4 stg[4][64][kFoldWords / 4 + 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 + 64 * wave;
+    const int64_t row = row0 + lane;
+    const bool active = row < rows;
+    if (row0 >= rows) return;  // the whole wave
+    int p = 0;
+    if (active) p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
+    const int p0 = __shfl(p, 0, 64);  // lane 0 is active
+    const bool one_pair = __ballot(!active || p == p0) == ~0ull;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (one_pair) {
+        const int pu = __builtin_amdgcn_readfirstlane(p0);
+        const int nu = pairs[pu].n, Wp = pairs[pu].Wp;
+        const int nw = (nu + 31) >> 5;  // X words of a row (nw <= Wp, Wp % 4 == 0)
+        const uint32_t flip = pairs[pu].flip ? 0xffffffffu : 0u;
+        const double* cf = coef + pairs[pu].coef0;
+        const uint32_t* mk0 = mask_row(mask, bp[pu], row0, Wp);  // 16-byte aligned rows
+        for (int w0 = 0; w0 < nw; w0 += kFoldWords) {
+#pragma unroll
+            for (int i = 0; i < kFoldWords; i += 4) {
+                const int idx = i * 16 + lane, r = idx >> 2, q = idx & 3, wq = w0 + 4 * q;
+                uint4 val = make_uint4(0u, 0u, 0u, 0u);
+                if (row0 + r < rows && wq < nw) val = *(const uint4*)(mk0 + (int64_t)r * Wp + wq);
+                stg[wave][r][q] = val;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int kend = min(kFoldWords, nw - w0);
+            for (int k = 0; k < kend; ++k) {
+                const int w = w0 + k;
+                const uint4 u = stg[wave][lane][k >> 2];
+                const uint32_t word = (k & 3) == 0 ? u.x : (k & 3) == 1 ? u.y : (k & 3) == 2 ? u.z : u.w;
+                const uint32_t bits = (word ^ flip) & range_bits(w, 0, nu);
+                const double* cw = cf + 32 * w;  // the array has 32 spare entries at its end
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe((int)bits, j, 1);
+                    const uint64_t cb = (uint64_t)__double_as_longlong(cw[j]);
+                    const uint64_t m = ((uint64_t)sel << 32) | sel;
+                    acc[j & 3] += __longlong_as_double((long long)(cb & m));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    } else if (active) {
+        const PairDesc pd = pairs[p];
+        const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
+        const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+        const double* cf = coef + pd.coef0;
+        for (int w = 0; 32 * w < pd.n; ++w) {
+            const uint32_t bits = (mk[w] ^ flip) & range_bits(w, 0, pd.n);
+#pragma unroll 4
+            for (int j = 0; j < 32; ++j) acc[j & 3] += (bits >> j) & 1u ? cf[32 * w + j] : 0.0;
+        }
+    }
+    if (active) c_out[row] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs,
                                               const BlockPair* __restrict__ bp, int npairs,
                                               int64_t rows, const PairState* __restrict__ st,
@@ -19,15 +98,16 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               int no_recheck, void* T_out,
                                               int T_mode, double* __restrict__ Tw,
                                               PairCount* cnt, uint32_t* flags, uint32_t* nflag,
-                                              const double* __restrict__ pv,
-                                              const uint32_t* __restrict__ mask,
-                                              const double* __restrict__ coef) {
+                                              const double* __restrict__ pv) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = row < rows;
     int p = 0;
     bool exceed = false;
+    if (active) p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
+    // a wave's first lane is active whenever any of its lanes is
+    const int p0 = __shfl(p, 0, 64);
+    const bool one_pair = __ballot(!active || p == p0) == ~0ull;
     if (active) {
-        p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
         const PairDesc pd = pairs[p];
         const PairState q = st[p];
         // partials are slot-major (slot k of all rows, then slot k + 1), so
@@ -43,23 +123,13 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         if (pv) {
             // Householder fold: the product summed the unreflected rows, so
             // sigma' = sigma - c v with c = sum over the smaller group's X rows
-            // of 2 (v . x_i) / (v . v) (FP64, from the mask bits), and
+            // of 2 (v . x_i) / (v . v) (k_fold_c), and
             //   |sigma'|^2     = |sigma|^2 - 2 c (v . sigma) + c^2 (v . v),
             //   |t - sigma'|^2 = |t - sigma|^2 + 2 c (v . t - v . sigma) + c^2 (v . v)
             // (t the pooled total of the reflected rows).
             double sv = 0.0;
             for (int k = 0; k < ns; ++k) sv += pv[k * prow + row];
-            const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
-            const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
-            const double* cf = coef + pd.coef0;
-            double c = 0.0;
-            for (int w = 0; 32 * w < pd.n; ++w) {
-                uint32_t bits = (mk[w] ^ flip) & range_bits(w, 0, pd.n);
-                while (bits) {
-                    c += cf[32 * w + __builtin_ctz(bits)];
-                    bits &= bits - 1u;
-                }
-            }
+            const double c = Tw[row];  // k_fold_c's
             const double cvv = c * c * q.vv;
             ss_small = ss_small - 2.0 * c * sv + cvv;
             ss_large = ss_large + 2.0 * c * (q.vt - sv) + cvv;
@@ -98,9 +168,7 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
     }
     // count: one atomic per wave when all its rows belong to one pair
     const uint64_t ex = __ballot(exceed);
-    const int p0 = __shfl(p, 0, 64);
-    const uint64_t same = __ballot(!active || p == p0);
-    if (same == ~0ull) {
+    if (one_pair) {
         if (lane_id() == 0 && ex) atomicAdd(&cnt[p0].count, (unsigned long long)__popcll(ex));
     } else if (exceed) {
         atomicAdd(&cnt[p].count, 1ull);
@@ -113,10 +181,13 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        int T_mode, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
                        hipStream_t s, const double* pv, const uint32_t* mask, const double* coef) {
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stat, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, pairs, bp,
-                       npairs, rows, st, partial, nslot, prow, d, gd, alternative, band,
-                       no_recheck,
-                       T_out, T_mode, Tw, cnt, flags, nflag, pv, mask, coef);
+    const dim3 grid((unsigned)((rows + 255) / 256));
+    if (pv) {
+        if (!mask || !coef) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_fold_c, grid, dim3(256), 0, s, pairs, bp, npairs, rows, mask, coef, Tw);
+    }
+    hipLaunchKernelGGL(k_stat, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial, nslot, prow, d,
+                       gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag, pv);
     return hipGetLastError();
 }
 

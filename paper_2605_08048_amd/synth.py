@@ -264,3 +264,47 @@ def rejection_batch(population="null", npairs=500, d=768, B=5000, limit=None) ->
         pairs = list(ex.map(one, idx))
     return pack_batch(pairs, d, meta=dict(workload="rejection_batch", population=population,
                                           kappa_a=ka, kappa_b=kb, angle=angle, n=ns, m=ms))
+
+
+@dataclass
+class Clouds:
+    Z: np.ndarray            # (sum of cloud rows, d) float32
+    offset: np.ndarray       # (C,) int64 first row of each cloud
+    rows: np.ndarray         # (C,) int64
+    pair_x: np.ndarray       # (P,) int64 cloud of X
+    pair_y: np.ndarray       # (P,) int64 cloud of Y
+    B: np.ndarray            # (P,) int64
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+    def pairs_batch(self) -> Batch:
+        """The same pairs packed one by one (rows X_0, Y_0, X_1, ...)."""
+        o, r = self.offset, self.rows
+        pairs = [Pair(self.Z[o[x]:o[x] + r[x]], self.Z[o[y]:o[y] + r[y]], B=int(b), pair_index=p)
+                 for p, (x, y, b) in enumerate(zip(self.pair_x, self.pair_y, self.B))]
+        return pack_batch(pairs, self.Z.shape[1], seed=self.seed)
+
+
+def word_clouds(nwords=64, npairs=512, d=768, lo=20, hi=5000, B=2000) -> Clouds:
+    """Words whose clouds take part in many pairs (each word in about
+    2 npairs / nwords of them): a cloud per word, n log-uniform on [lo, hi],
+    kappa ~ U[1.5, 3], a random mean direction; pairs of distinct words drawn
+    at random.  The shared-cloud form of the batched workload."""
+    g = rng_for(7, 0, 99)
+    ns = log_uniform_int(g, lo, hi, nwords)
+    kappa = g.uniform(1.5, 3.0, nwords)
+    px = g.integers(0, nwords, npairs)
+    py = (px + g.integers(1, nwords, npairs)) % nwords
+    factor = lowrank_factor(d)
+
+    def one(w):
+        rng = rng_for(7, w, 0)
+        return cloud_lowrank(rng, int(ns[w]), d, float(kappa[w]), random_unit(rng, d), factor).astype(np.float32)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        clouds = list(ex.map(one, range(nwords)))
+    off = np.zeros(nwords, dtype=np.int64)
+    off[1:] = np.cumsum(ns)[:-1]
+    return Clouds(np.concatenate(clouds), off, ns.astype(np.int64), px.astype(np.int64), py.astype(np.int64),
+                  np.full(npairs, B, dtype=np.int64),
+                  meta=dict(workload="word_clouds", nwords=nwords, npairs=npairs, d=d))
