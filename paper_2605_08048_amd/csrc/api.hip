@@ -168,6 +168,7 @@ struct Workspace {
     PairDesc* cdesc;    // one run of storage per cloud (the column-sum table)
     float* v32;         // FP32 copy of each pair's v
     double* pv;         // v . sigma per split row and slot (slot-major)
+    double* fpart;      // fold sums per segment of X items and split row (segment-major)
     size_t bytes;
 };
 
@@ -216,6 +217,7 @@ struct Plan {
     std::vector<Chunk> cplan;
     TileCost tune = default_tune(HBT_BF16X2);  // launch parameters of (precision, d_pad)
     bool fold = false;             // pairs of shared clouds, stored unreflected
+    int fold_segs = 0;             // the largest pair's fold_segments(n)
     std::vector<PairDesc> cdesc;   // their clouds
 };
 
@@ -281,10 +283,12 @@ Workspace carve(const Plan& P, void* ws) {
         w.cdesc = c.take<PairDesc>(std::max<size_t>(P.cdesc.size(), 1));
         w.v32 = c.take<float>((size_t)np * P.d_pad);
         w.pv = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * P.nslot);
+        w.fpart = c.take<double>((size_t)std::max<int64_t>(P.block_rows, 1) * std::max(P.fold_segs, 1));
     } else {
         w.cdesc = nullptr;
         w.v32 = nullptr;
         w.pv = nullptr;
+        w.fpart = nullptr;
     }
     w.bytes = c.off + 256;
     return w;
@@ -647,7 +651,7 @@ hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_pa
                         P.route2 ? w.partial2 : w.partial, P.route2 ? 0 : P.nslot,
                         P.block_rows, P.d, common->gd,
                         common->alternative, precision_band(P.precision, P.d, P.route2), no_recheck, nullptr,
-                        0, w.tw, w.cnt, w.flags, w.nflag, s, w.pv, w.mask, w.coef)); }
+                        0, w.tw, w.cnt, w.flags, w.nflag, s, w.pv, w.mask, w.coef, w.fpart, P.fold_segs)); }
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
@@ -1051,6 +1055,7 @@ static bool plan_clouds(Plan& P, int64_t nclouds, const void* Z_all, const int64
         pd.cy1 = cy.cy1;
         P.ncoef += pd.n;
         P.max_np = std::max(P.max_np, (int)pd.Np);
+        P.fold_segs = std::max(P.fold_segs, fold_segments(pd.n));
         P.pairs.push_back(pd);
         const auto key = std::make_tuple((int64_t)pd.n, (int64_t)pd.m, B[p], pd.pair_index);
         const auto hit = first.find(key);

@@ -129,16 +129,22 @@ hipError_t launch_centroid(bool bf16x3, const PairDesc* pairs, const BlockPair* 
                            int64_t prow, hipStream_t s);
 
 // --- statistic, exceedances, recheck, p ---------------------------------
+// Fold sums of shared clouds: mask words per segment of a split's X items
+// (each segment is summed by its own wave), and the segments of a pair.
+constexpr int kFoldSegWords = 16;
+__host__ __device__ inline int fold_segments(int n) { return ((n + 31) / 32 + kFoldSegWords - 1) / kFoldSegWords; }
 hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, const RecheckBand& band, int no_recheck, void* T_out,
                        int T_mode, double* Tw,
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s, const double* pv = nullptr,
-                       const uint32_t* mask = nullptr, const double* coef = nullptr);
-// launch_stat with pv (v . sigma per slot), mask and coef non-null reflects
-// the group sums of pairs stored unreflected (the Householder fold): a first
-// kernel writes each split's fold coefficient c into Tw, which the statistic
-// kernel reads before it stores T_b there.
+                       const uint32_t* mask = nullptr, const double* coef = nullptr,
+                       double* fpart = nullptr, int fold_segs = 0);
+// launch_stat with pv (v . sigma per slot), mask, coef and fpart non-null
+// reflects the group sums of pairs stored unreflected (the Householder fold):
+// a first kernel writes each split's fold sums per segment into fpart
+// (fold_segs x rows doubles, segment-major; fold_segs = the largest pair's
+// fold_segments(n)), which the statistic kernel adds in segment order.
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
 // doubles of per-wave segment sums (nullptr: every flag done whole by one
 // work-group); the value of each flag's sums does not depend on it.

@@ -11,24 +11,28 @@
 namespace hbt {
 
 // Householder fold: c = sum over the smaller group's X rows of 2 (v . x_i) /
-// (v . v) per split row, into c_out[row] (FP64; four running sums, over the
-// indices i % 4 = 0, 1, 2, 3, added at the end).  A kernel of its own so that
-// the loop runs at a higher occupancy than the statistic's FP64 scalar math
-// allows.  In a wave of one pair (consecutive split rows, Wp words apart) the
-// X words of the 64 rows pass through LDS 16 at a time, read as 64-byte runs
-// of each row so that every fetched line is used whole; the 32 coefficients
-// of a word are wave-uniform (scalar loads) and a lane adds the ones its
-// bits select, the selection made with sign-extended one-bit masks rather
-// than branches.  A wave across a pair boundary takes each lane's own pair.
-constexpr int kFoldWords = 16;  // mask words per LDS pass
+// (v . v) per split row, in segments of kFoldSegWords mask words (512 X
+// items): work-group (x, y) takes the 256 split rows of block x and segment y
+// of each row's pair, and writes the segment's sum (FP64; four running sums,
+// over the indices i % 4 = 0, 1, 2, 3, added at the end) to
+// fpart[y][row]; segments past a pair's fold_segments(n) are not written.
+// Large pairs thus spread over as many waves as they have segments.  In a
+// wave of one pair (consecutive split rows, Wp words apart) the segment's
+// words of the 64 rows pass through LDS, read as 64-byte runs of each row so
+// that every fetched line is used whole; the 32 coefficients of a word are
+// wave-uniform (scalar loads) and a lane adds the ones its bits select, the
+// selection made with sign-extended one-bit masks rather than branches.  A
+// wave across a pair boundary takes each lane's own pair.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 void k_fold_c(const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
               int64_t rows, const uint32_t* __restrict__ mask, const double* __restrict__ coef,
-              double* __restrict__ c_out) {
+              double* __restrict__ fpart) {
+    constexpr int kW = kFoldSegWords;
     // 64 rows x 16 words per wave; a row takes 20 words so that the lanes'
     // 16-byte reads of their own rows fall on distinct banks
-    __shared__ uint4 stg[4][64][kFoldWords / 4 + 1];
+    __shared__ uint4 stg[4][64][kW / 4 + 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int seg = blockIdx.y, w0 = kW * seg;
     const int64_t row0 = (int64_t)blockIdx.x * 256 + 64 * wave;
     const int64_t row = row0 + lane;
     const bool active = row < rows;
@@ -42,51 +46,49 @@ void k_fold_c(const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ 
         const int pu = __builtin_amdgcn_readfirstlane(p0);
         const int nu = pairs[pu].n, Wp = pairs[pu].Wp;
         const int nw = (nu + 31) >> 5;  // X words of a row (nw <= Wp, Wp % 4 == 0)
+        if (w0 >= nw) return;           // wave-uniform: no such segment
         const uint32_t flip = pairs[pu].flip ? 0xffffffffu : 0u;
         const double* cf = coef + pairs[pu].coef0;
         const uint32_t* mk0 = mask_row(mask, bp[pu], row0, Wp);  // 16-byte aligned rows
-        for (int w0 = 0; w0 < nw; w0 += kFoldWords) {
 #pragma unroll
-            for (int i = 0; i < kFoldWords; i += 4) {
-                const int idx = i * 16 + lane, r = idx >> 2, q = idx & 3, wq = w0 + 4 * q;
-                uint4 val = make_uint4(0u, 0u, 0u, 0u);
-                if (row0 + r < rows && wq < nw) val = *(const uint4*)(mk0 + (int64_t)r * Wp + wq);
-                stg[wave][r][q] = val;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int kend = min(kFoldWords, nw - w0);
-            for (int k = 0; k < kend; ++k) {
-                const int w = w0 + k;
-                const uint4 u = stg[wave][lane][k >> 2];
-                const uint32_t word = (k & 3) == 0 ? u.x : (k & 3) == 1 ? u.y : (k & 3) == 2 ? u.z : u.w;
-                const uint32_t bits = (word ^ flip) & range_bits(w, 0, nu);
-                const double* cw = cf + 32 * w;  // the array has 32 spare entries at its end
+        for (int i = 0; i < kW / 4; ++i) {
+            const int idx = 64 * i + lane, r = idx >> 2, q = idx & 3, wq = w0 + 4 * q;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (row0 + r < rows && wq < nw) val = *(const uint4*)(mk0 + (int64_t)r * Wp + wq);
+            stg[wave][r][q] = val;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int kend = min(kW, nw - w0);
+        for (int k = 0; k < kend; ++k) {
+            const int w = w0 + k;
+            const uint4 u = stg[wave][lane][k >> 2];
+            const uint32_t word = (k & 3) == 0 ? u.x : (k & 3) == 1 ? u.y : (k & 3) == 2 ? u.z : u.w;
+            const uint32_t bits = (word ^ flip) & range_bits(w, 0, nu);
+            const double* cw = cf + 32 * w;  // the array has 32 spare entries at its end
 #pragma unroll
-                for (int j = 0; j < 32; ++j) {
-                    const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe((int)bits, j, 1);
-                    const uint64_t cb = (uint64_t)__double_as_longlong(cw[j]);
-                    const uint64_t m = ((uint64_t)sel << 32) | sel;
-                    acc[j & 3] += __longlong_as_double((long long)(cb & m));
-                }
+            for (int j = 0; j < 32; ++j) {
+                const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe((int)bits, j, 1);
+                const uint64_t cb = (uint64_t)__double_as_longlong(cw[j]);
+                const uint64_t m = ((uint64_t)sel << 32) | sel;
+                acc[j & 3] += __longlong_as_double((long long)(cb & m));
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     } else if (active) {
         const PairDesc pd = pairs[p];
+        const int nw = (pd.n + 31) >> 5;
+        if (w0 >= nw) return;
         const uint32_t* mk = mask_row(mask, bp[p], row, pd.Wp);
         const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
         const double* cf = coef + pd.coef0;
-        for (int w = 0; 32 * w < pd.n; ++w) {
+        for (int w = w0; w < min(nw, w0 + kW); ++w) {
             const uint32_t bits = (mk[w] ^ flip) & range_bits(w, 0, pd.n);
 #pragma unroll 4
             for (int j = 0; j < 32; ++j) acc[j & 3] += (bits >> j) & 1u ? cf[32 * w + j] : 0.0;
         }
     }
-    if (active) c_out[row] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (active) fpart[(int64_t)seg * rows + row] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs,
@@ -98,7 +100,8 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               int no_recheck, void* T_out,
                                               int T_mode, double* __restrict__ Tw,
                                               PairCount* cnt, uint32_t* flags, uint32_t* nflag,
-                                              const double* __restrict__ pv) {
+                                              const double* __restrict__ pv,
+                                              const double* __restrict__ fpart) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool active = row < rows;
     int p = 0;
@@ -123,13 +126,14 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         if (pv) {
             // Householder fold: the product summed the unreflected rows, so
             // sigma' = sigma - c v with c = sum over the smaller group's X rows
-            // of 2 (v . x_i) / (v . v) (k_fold_c), and
+            // of 2 (v . x_i) / (v . v) (k_fold_c's segment sums), and
             //   |sigma'|^2     = |sigma|^2 - 2 c (v . sigma) + c^2 (v . v),
             //   |t - sigma'|^2 = |t - sigma|^2 + 2 c (v . t - v . sigma) + c^2 (v . v)
             // (t the pooled total of the reflected rows).
             double sv = 0.0;
             for (int k = 0; k < ns; ++k) sv += pv[k * prow + row];
-            const double c = Tw[row];  // k_fold_c's
+            double c = 0.0;  // k_fold_c's segments, in order
+            for (int k = 0; k < fold_segments(pd.n); ++k) c += fpart[k * rows + row];
             const double cvv = c * c * q.vv;
             ss_small = ss_small - 2.0 * c * sv + cvv;
             ss_large = ss_large + 2.0 * c * (q.vt - sv) + cvv;
@@ -179,15 +183,17 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                        int alternative, const RecheckBand& band, int no_recheck, void* T_out,
                        int T_mode, double* Tw, PairCount* cnt, uint32_t* flags, uint32_t* nflag,
-                       hipStream_t s, const double* pv, const uint32_t* mask, const double* coef) {
+                       hipStream_t s, const double* pv, const uint32_t* mask, const double* coef,
+                       double* fpart, int fold_segs) {
     if (rows <= 0) return hipSuccess;
     const dim3 grid((unsigned)((rows + 255) / 256));
     if (pv) {
-        if (!mask || !coef) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_fold_c, grid, dim3(256), 0, s, pairs, bp, npairs, rows, mask, coef, Tw);
+        if (!mask || !coef || !fpart || fold_segs < 1 || fold_segs > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_fold_c, dim3(grid.x, (unsigned)fold_segs), dim3(256), 0, s, pairs, bp, npairs,
+                           rows, mask, coef, fpart);
     }
     hipLaunchKernelGGL(k_stat, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial, nslot, prow, d,
-                       gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag, pv);
+                       gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag, pv, fpart);
     return hipGetLastError();
 }
 
