@@ -211,7 +211,7 @@ def stage_errors(dev, pair, hbt, torch, sample_every=97):
     X = torch.from_numpy(pair.X).to(dev)
     Y = torch.from_numpy(pair.Y).to(dev)
     runs = {prec: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, want_T="norms")["T"]
-            for prec in ("f64", "f32", "bf16x2", "i8x3")}
+            for prec in ("f64", "f32", "bf16x2", "i8x3", "bf16e4m3")}
     ref = runs.pop("f64")
     idx = np.arange(0, pair.B, sample_every)
     n, m, d = pair.n, pair.m, pair.d
@@ -241,6 +241,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
+    ap.add_argument("--f8-steps", type=int, default=3, help="timed steps of the BF16 hi + e4m3 lo variant")
     ap.add_argument("--single-steps", type=int, default=5,
                     help="timed calls per precision of the single-pair workloads (0 skips them)")
     ap.add_argument("--cloud-steps", type=int, default=5,
@@ -292,7 +293,7 @@ def main():
         # the autotuner (untimed): tile widths, persistent grids, split
         # work-groups per CU and pipeline chunks, per precision
         tuning = {}
-        for prec in ("bf16x2", "i8x3"):
+        for prec in ("bf16x2", "i8x3", "bf16e4m3"):
             hbt.tune_batched(Z, batch.row_offset, batch.n, batch.m, batch.B, seed=batch.seed, precision=prec)
             tuning[prec] = hbt.tune_entry_get(prec, d)
         tuning["pairs_at_256"] = int(np.sum(hbt.tile_widths(batch.B, d) == 256))
@@ -372,7 +373,10 @@ def main():
               "groupsum_ms": g32, "groupsum_tflops": algo_flops / (g32 * 1e-3) / 1e12,
               "groupsum_frac_fp32_peak": algo_flops / (g32 * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
               "speedup_bf16x2_over_fp32": value / v32,
-              "pairs_with_equal_counts": f"{agree}/{P}"}
+              "pairs_with_equal_counts": f"{agree}/{P}",
+              "kernel": "k_groupsum_fp<float>: v_mfma_f32_16x16x4f32, 64x64 wave tiles, operands loaded "
+                        "from global memory without LDS staging (a comparison path, not tuned like the "
+                        "split-BF16 kernel)"}
 
     i8 = None
     if args.i8_steps > 0:
@@ -387,6 +391,21 @@ def main():
               "pairs_bad_status": bad8,
               "pairs_with_counts_equal_to_bf16x2": f"{int(np.sum(out8['count'] == out['count']))}/{P}"}
 
+    f8 = None
+    if args.f8_steps > 0:
+        dtf, msf, lf, outf, badf = run("bf16e4m3", args.f8_steps, 1)
+        log(f"BF16 hi + e4m3 lo: {dtf / args.f8_steps * 1e3:.2f} ms/step")
+        gf = msf[2] / max(lf[2], 1)
+        f8 = {"value": stats_per_step * args.f8_steps / dtf, "ms_per_step": dtf / args.f8_steps * 1e3,
+              "groupsum_ms": gf, "groupsum_tflops": algo_flops / (gf * 1e-3) / 1e12,
+              "groupsum_frac_bf16_peak": algo_flops / (gf * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+              "stages_ms_per_step": {k: msf[i] / args.f8_steps for i, k in enumerate(STAGES)},
+              "rechecked_splits_per_step": int(outf["n_recheck"].sum()),
+              "pairs_bad_status": badf,
+              "pairs_with_counts_equal_to_bf16x2": f"{int(np.sum(outf['count'] == out['count']))}/{P}",
+              "kernel": "k_groupsum_bf16x2<4, 8, false, true>: bf16 MFMA on the hi plane, "
+                        "v_mfma_scale_f32_32x32x64_f8f6f4 on the e4m3 lo plane, one FP32 accumulator"}
+
     # single-pair workloads (the per-pair call), every precision on the same input
     single = None
     if args.single_steps > 0:
@@ -396,7 +415,7 @@ def main():
             Y = torch.from_numpy(pair.Y).to(dev)
             row = {"n": pair.n, "m": pair.m, "d": pair.d, "B": pair.B}
             counts = {}
-            for prec in ("f32", "bf16x2", "i8x3"):
+            for prec in ("f32", "bf16x2", "i8x3", "bf16e4m3"):
                 call = lambda: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, sync=False)
                 call()
                 torch.cuda.synchronize()
@@ -526,6 +545,7 @@ def main():
         "rechecked_splits_per_step": int(out["n_recheck"].sum()),
         "fp32_plain": fp,
         "int8_planes": i8,
+        "bf16_hi_e4m3_lo": f8,
         "point_to_centroid": route2,
         "shared_clouds": clouds,
         "single_pair": single,

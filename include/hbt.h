@@ -76,10 +76,14 @@ typedef enum hbt_precision {
     HBT_F64 = 0,      /* group sums on FP64 MFMA */
     HBT_F32 = 1,      /* group sums on FP32 MFMA */
     HBT_BF16X2 = 2,   /* z = hi + lo split into two BF16 planes, FP32 accumulation */
-    HBT_I8X3 = 3      /* z rounded to 21-bit fixed point (z * 2^20), three balanced
+    HBT_I8X3 = 3,     /* z rounded to 21-bit fixed point (z * 2^20), three balanced
                          int8 digit planes on the int8 MFMA: exact integer group
                          sums, FP64 epilogue; the 8-bit-operand variant of the
                          group-sum product (route 0 only) */
+    HBT_BF16_E4M3 = 4 /* the split-BF16 hi plane plus lo = z - hi as FP8 e4m3 (of
+                         lo * 2^17, round to nearest even): bf16 MFMA for hi, the
+                         E8M0-scaled fp8 MFMA for lo, one FP32 accumulator; the
+                         mask stays exact (route 0, split rows of FP32 or FP64) */
 } hbt_precision;
 
 typedef enum hbt_dtype { HBT_IN_F32 = 0, HBT_IN_F64 = 1 } hbt_dtype;

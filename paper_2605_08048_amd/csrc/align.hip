@@ -433,6 +433,20 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 
 // ---------------------------------------------------------------------------
 // reflection + storage: one work-group per octet of 8 pooled rows
+// Two values' e4m3 lo bytes: lo = z - hi (hi the stored, scaled bf16 of each,
+// times inv to undo the plane scale; exact in FP32), rounded to nearest even
+// as e4m3 of lo 2^kE4m3LoShift, at group rows ra, rb of the 32-row group whose
+// first lo unit (of this column) plo points at.
+__device__ __forceinline__ void store_e4m3_lo2(unsigned char* plo, int d_pad, int ra, int rb, float za,
+                                               float zb, uint32_t hi2, float inva, float invb) {
+    const float ha = __uint_as_float(hi2 << 16) * inva;
+    const float hb = __uint_as_float(hi2 & 0xffff0000u) * invb;
+    constexpr float up = (float)(1 << kE4m3LoShift);
+    const uint32_t q = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32((za - ha) * up, (zb - hb) * up, 0, false);
+    plo[(int64_t)f8_unit(ra) * d_pad * 16 + f8_byte(ra)] = (unsigned char)(q & 0xffu);
+    plo[(int64_t)f8_unit(rb) * d_pad * 16 + f8_byte(rb)] = (unsigned char)((q >> 8) & 0xffu);
+}
+
 // ---------------------------------------------------------------------------
 // Z storage formats:
 //   HBT_F64    : double [Np][d_pad]
@@ -442,6 +456,8 @@ hipError_t launch_finalize(const PairDesc* pairs, int npairs, const double* part
 //                contiguous per column, the operand layout of the bf16 MFMA;
 //                storage octet 4 g + o4 holds rows 32 g + bf16_plane_row(o4, k)
 //                of the pair, scaled by bf16_plane_scale(o4, k) (k = 0..7).
+//   HBT_BF16_E4M3: the HBT_BF16X2 hi plane, then at byte 2 zplane_elems the
+//                e4m3 lo plane [Np/16][d_pad][16] (f8_unit, f8_byte).
 //   HBT_I8X3   : three planes (q0, q1, q2 at +zplane_elems bytes each) of
 //                int8 digits [Np/16][d_pad][16]; storage octet 4 g + o4
 //                fills bytes 8 (o4 & 1) .. +7 of unit 2 g + o4 / 2 with rows
@@ -527,6 +543,17 @@ __global__ __launch_bounds__(256) void k_reflect(const PairDesc* __restrict__ pa
             uint4* ph = (uint4*)zstore + oct * d_pad + c;
             *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
             *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        } else if (PREC == HBT_BF16_E4M3) {
+            uint32_t hi[4];
+            unsigned char* plo = (unsigned char*)zstore + 2 * zplane_elems + (((oct >> 2) * 2) * d_pad + c) * 16;
+#pragma unroll
+            for (int r = 0; r < 8; r += 2) {
+                const float a = (float)z[r], b = (float)z[r + 1];
+                hi[r / 2] = split_bf16x2(a * bf16_plane_scale(o4, r), b * bf16_plane_scale(o4, r + 1)).x;
+                store_e4m3_lo2(plo, d_pad, bf16_plane_row(o4, r), bf16_plane_row(o4, r + 1), a, b, hi[r / 2],
+                               bf16_plane_inv_scale(o4, r), bf16_plane_inv_scale(o4, r + 1));
+            }
+            *((uint4*)zstore + oct * d_pad + c) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
         } else if (PREC == HBT_F32) {
 #pragma unroll
             for (int r = 0; r < 8; ++r)
@@ -556,6 +583,10 @@ static hipError_t launch_reflect_t(int precision, const PairDesc* pairs, int npa
             break;
         case HBT_I8X3:
             hipLaunchKernelGGL((k_reflect<Tin, HBT_I8X3>), g, b, 0, s, pairs, npairs, st, v, d,
+                               d_pad, coef, z, ze, z32);
+            break;
+        case HBT_BF16_E4M3:
+            hipLaunchKernelGGL((k_reflect<Tin, HBT_BF16_E4M3>), g, b, 0, s, pairs, npairs, st, v, d,
                                d_pad, coef, z, ze, z32);
             break;
         default:
@@ -653,6 +684,17 @@ __device__ __forceinline__ void store_octet(const float (&x)[8][J][4], const dou
                 uint4* ph = (uint4*)zstore + soct * d_pad + c;
                 *ph = make_uint4(hi[0], hi[1], hi[2], hi[3]);
                 *(ph + zplane_elems / 8) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+            }
+            if (PREC == HBT_BF16_E4M3) {
+                uint32_t hi[4];
+                unsigned char* plo = (unsigned char*)zstore + 2 * zplane_elems + (((soct >> 2) * 2) * d_pad + c) * 16;
+#pragma unroll
+                for (int r = 0; r < 8; r += 2) {
+                    hi[r / 2] = split_bf16x2(zf[r] * bf16_plane_scale(o4, r), zf[r + 1] * bf16_plane_scale(o4, r + 1)).x;
+                    store_e4m3_lo2(plo, d_pad, row_of(r) & 31, row_of(r + 1) & 31, zf[r], zf[r + 1], hi[r / 2],
+                                   bf16_plane_inv_scale(o4, r), bf16_plane_inv_scale(o4, r + 1));
+                }
+                *((uint4*)zstore + soct * d_pad + c) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
             }
         }
 }
@@ -757,6 +799,7 @@ hipError_t launch_reflect_vec(int precision, const PairDesc* pairs, int npairs,
         case HBT_F64: HBT_R4J(HBT_F64); break;
         case HBT_F32: HBT_R4J(HBT_F32); break;
         case HBT_I8X3: HBT_R4J(HBT_I8X3); break;
+        case HBT_BF16_E4M3: HBT_R4J(HBT_BF16_E4M3); break;
         default: HBT_R4J(HBT_BF16X2); break;
     }
 #undef HBT_R4J
@@ -867,6 +910,7 @@ hipError_t launch_colsum_store_vec(int precision, const PairDesc* pairs, int npa
         case HBT_F64: HBT_C4J(HBT_F64); break;
         case HBT_F32: HBT_C4J(HBT_F32); break;
         case HBT_I8X3: HBT_C4J(HBT_I8X3); break;
+        case HBT_BF16_E4M3: HBT_C4J(HBT_BF16_E4M3); break;
         default: HBT_C4J(HBT_BF16X2); break;
     }
 #undef HBT_C4J

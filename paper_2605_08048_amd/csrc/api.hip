@@ -101,6 +101,11 @@ RecheckBand precision_band(int precision, int d, bool route2) {
         case HBT_F64: b = RecheckBand{1e-12, 0x1p-53 * rd, 4.0, 0.0}; break;
         case HBT_F32: b = RecheckBand{4e-6, 0x1p-24 * rd, 4.0, 0.0}; break;
         case HBT_I8X3: b = RecheckBand{1e-10, 0x1p-21, 12.0, 0.0}; break;
+        // e4m3 keeps 4 significant bits: |lo - e4m3(lo)| <= 2^-4 |lo| <= 2^-12 |z|
+        // (lo the bf16 remainder, |lo| <= 2^-8 |z|); plus the fp8 MFMA's own
+        // rounding of its 64-term dot products (2^-13 of the lo terms, i.e.
+        // 2^-21 |z|) and the subnormal spacing of the scaled lo (2^-27 absolute)
+        case HBT_BF16_E4M3: b = RecheckBand{4e-6, (0x1p-12 + 0x1p-21) * rd + 0x1p-27, 4.0, 0.0}; break;
         default: b = RecheckBand{4e-6, 0x1p-16 * rd, 4.0, 0.0}; break;
     }
     if (route2) {
@@ -115,7 +120,7 @@ RecheckBand precision_band(int precision, int d, bool route2) {
 }
 
 size_t zstore_bytes(int precision, int64_t rows, int64_t d_pad) {
-    const int bytes = precision == HBT_F64 ? 8 : precision == HBT_I8X3 ? 3 : 4;
+    const int bytes = precision == HBT_F64 ? 8 : precision == HBT_I8X3 || precision == HBT_BF16_E4M3 ? 3 : 4;
     return (size_t)rows * d_pad * bytes;
 }
 
@@ -331,7 +336,7 @@ void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint3
 }
 
 hbt_status check_enums(const hbt_perm_params* prm) {
-    if (prm->precision < HBT_F64 || prm->precision > HBT_I8X3)
+    if (prm->precision < HBT_F64 || prm->precision > HBT_BF16_E4M3)
         return fail(HBT_ERR_ARG, "unknown precision %d", prm->precision);
     if (prm->input_dtype != HBT_IN_F32 && prm->input_dtype != HBT_IN_F64)
         return fail(HBT_ERR_DTYPE, "unknown input dtype %d", prm->input_dtype);
@@ -342,8 +347,8 @@ hbt_status check_enums(const hbt_perm_params* prm) {
     if (prm->align != 0 && prm->align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
     if (prm->stat_route != 0 && prm->stat_route != 1)
         return fail(HBT_ERR_ARG, "unknown stat_route %d", prm->stat_route);
-    if (prm->stat_route == 1 && prm->precision == HBT_I8X3)
-        return fail(HBT_ERR_UNSUPPORTED, "the int8 planes compute the statistic by route 0 only");
+    if (prm->stat_route == 1 && (prm->precision == HBT_I8X3 || prm->precision == HBT_BF16_E4M3))
+        return fail(HBT_ERR_UNSUPPORTED, "the int8 and BF16 + e4m3 planes compute the statistic by route 0 only");
     if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64 | HBT_FLAG_T_OUT_NORMS))
         return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
     return HBT_OK;
@@ -451,7 +456,7 @@ int tune_load_locked(const char* path) {
                    "\"grid_narrow\": %d, \"split_cap\": %d, \"chunks\": %d}",
                    &prec, &dp, &t.c[0], &t.c[1], &t.grid_wide, &t.grid_narrow, &t.split_cap, &t.chunks) != 8)
             return -1;
-        if (prec < HBT_F64 || prec > HBT_I8X3 || dp < kDPad || dp > HBT_MAX_D || dp % kDPad || !tune_valid(t))
+        if (prec < HBT_F64 || prec > HBT_BF16_E4M3 || dp < kDPad || dp > HBT_MAX_D || dp % kDPad || !tune_valid(t))
             return -1;
         got.push_back({{prec, dp}, t});
         pos = end;
@@ -845,7 +850,7 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
 // ---------------------------------------------------------------------------
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm) {
     if (!prm || check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset) ||
-        prm->precision < HBT_F64 || prm->precision > HBT_I8X3) {
+        prm->precision < HBT_F64 || prm->precision > HBT_BF16_E4M3) {
         return 0;
     }
     int64_t B0;
@@ -1084,8 +1089,8 @@ static bool plan_clouds(Plan& P, int64_t nclouds, const void* Z_all, const int64
 // Number of pipeline chunks of a batched call (1 = no pipeline).
 int g_pipeline_chunks = 0;  // process-wide override (hbt_pipeline_chunks); 0: the tuned value
 int pipeline_chunks(const Plan& P, int64_t npairs) {
-    if (!(P.precision == HBT_BF16X2 || P.precision == HBT_I8X3) || !vector_rows(P) || !P.need_store ||
-        P.route2)
+    if (!(P.precision == HBT_BF16X2 || P.precision == HBT_I8X3 || P.precision == HBT_BF16_E4M3) || !vector_rows(P) ||
+        !P.need_store || P.route2)
         return 1;
     const int c = g_pipeline_chunks > 0 ? g_pipeline_chunks : P.tune.chunks;
     return (int)std::max<int64_t>(1, std::min<int64_t>(c, npairs));
@@ -1166,7 +1171,7 @@ size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, co
                                             const int64_t* B, int64_t d,
                                             const hbt_perm_params* common) {
     if (npairs < 1 || !n || !m || !B || !common) return 0;
-    if (common->precision < HBT_F64 || common->precision > HBT_I8X3) return 0;
+    if (common->precision < HBT_F64 || common->precision > HBT_BF16_E4M3) return 0;
     for (int64_t p = 0; p < npairs; ++p)
         if (check_sizes(n[p], m[p], d, B[p], common->perm_offset)) return 0;
     std::vector<int64_t> off((size_t)npairs + 1, 0);
@@ -1233,7 +1238,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     }
     {
         StageTimer t_(HBT_STAGE_OTHER, qt);
-        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3)
+        if (P.precision == HBT_BF16X2 || P.precision == HBT_I8X3 || P.precision == HBT_BF16_E4M3)
             HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), qt));
         else
             HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), qt));
@@ -1521,7 +1526,7 @@ hbt_status hbt_recheck_band(int32_t precision, int32_t stat_route, int32_t gd, i
                             int64_t d, double r1, double r2, double* eps) {
     g_err.clear();
     if (!eps) return fail(HBT_ERR_ARG, "NULL pointer");
-    if (precision < HBT_F64 || precision > HBT_I8X3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (precision < HBT_F64 || precision > HBT_BF16_E4M3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
     if (stat_route != 0 && stat_route != 1) return fail(HBT_ERR_ARG, "unknown stat_route %d", stat_route);
     if (gd != HBT_GD_BANERJEE && gd != HBT_GD_IDENTITY) return fail(HBT_ERR_ARG, "unknown g_d %d", gd);
     if (n < 1 || m < 1 || d < 1 || d > HBT_MAX_D)
@@ -1562,7 +1567,7 @@ hbt_status hbt_tune_set(int64_t d, const double* costs) {
 hbt_status hbt_tune_entry_get(int32_t precision, int64_t d, hbt_tune_entry* e) {
     g_err.clear();
     if (!e) return fail(HBT_ERR_ARG, "NULL pointer");
-    if (precision < HBT_F64 || precision > HBT_I8X3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (precision < HBT_F64 || precision > HBT_BF16_E4M3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
     const TileCost t = tile_cost((int)round_up(d, kDPad), precision);
     memset(e, 0, sizeof *e);
@@ -1579,7 +1584,7 @@ hbt_status hbt_tune_entry_get(int32_t precision, int64_t d, hbt_tune_entry* e) {
 hbt_status hbt_tune_entry_set(int32_t precision, int64_t d, const hbt_tune_entry* e) {
     g_err.clear();
     if (!e) return fail(HBT_ERR_ARG, "NULL pointer");
-    if (precision < HBT_F64 || precision > HBT_I8X3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (precision < HBT_F64 || precision > HBT_BF16_E4M3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
     const TileCost t{{e->cost[0], e->cost[1]}, e->grid_wide, e->grid_narrow, e->split_cap, e->chunks, true};
     if (!tune_valid(t))
@@ -1615,8 +1620,8 @@ hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* ro
     g_err.clear();
     if (!common || !B || !n || !m) return fail(HBT_ERR_ARG, "NULL argument");
     const int prec = common->precision;
-    if (prec != HBT_BF16X2 && prec != HBT_I8X3)
-        return fail(HBT_ERR_ARG, "tuning covers the split-BF16 and int8-plane products only");
+    if (prec != HBT_BF16X2 && prec != HBT_I8X3 && prec != HBT_BF16_E4M3)
+        return fail(HBT_ERR_ARG, "tuning covers the split-BF16, BF16 + e4m3 and int8-plane products only");
     if (npairs < 1 || d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "npairs %lld, d %lld", (long long)npairs, (long long)d);
     const int d_pad = (int)round_up(d, kDPad);
     hipStream_t s = (hipStream_t)stream;
@@ -1670,9 +1675,10 @@ hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* ro
     const int saved_chunks = g_pipeline_chunks;
     g_pipeline_chunks = 0;
     hbt_status st = HBT_OK;
-    // 1. tile widths (split BF16): per-split costs of each width with every
-    // pair forced to it
-    if (prec == HBT_BF16X2) {
+    // 1. tile widths (split BF16, BF16 + e4m3): per-split costs of each width
+    // with every pair forced to it
+    const bool widths_tuned = prec == HBT_BF16X2 || prec == HBT_BF16_E4M3;
+    if (widths_tuned) {
         const int widths[2] = {kTileWide, 256};
         for (int k = 0; k < 2 && !st; ++k) {
             double units = 0.0;  // padded splits times pooled rows
@@ -1693,7 +1699,7 @@ hbt_status hbt_tune_batched(int64_t npairs, const void* Z_all, const int64_t* ro
         const int wide[] = {4, 8, 16, 32};
         const int narrow[] = {8, 16, 32, 64};
         bool any_wide = false, any_narrow = prec == HBT_I8X3;
-        for (int64_t p = 0; p < npairs && prec == HBT_BF16X2; ++p) {
+        for (int64_t p = 0; p < npairs && widths_tuned; ++p) {
             const int w = choose_width(B[p], best);
             any_wide |= w == kTileWide;
             any_narrow |= w != kTileWide;

@@ -26,6 +26,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
 
@@ -122,20 +123,37 @@ constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14
 // FOLD (pairs of shared clouds, stored unreflected): the epilogue also sums
 // v . sigma per split and slot into pv (v the pair's FP32 Householder vector
 // v32), from which the statistic reflects the group sums (Householder fold).
-template <int JB, int NW, bool FOLD>
+//
+// LO8 (BF16 hi + E4M3 lo): the lo plane is one e4m3 byte per value,
+// round(lo 2^17), in 16-row units (the int8 planes' layout: unit h of a
+// 32-row group, byte 4 s + b, holds group row s + 4 h + 8 b).  A chunk holds
+// the 16 hi octets and the 8 lo units; the hi product runs as above on one
+// plane, and the lo product on v_mfma_scale_f32_32x32x64_f8f6f4, one 64-row
+// K-step per two mask words: lane half h takes the 32 bytes of group 2 s + h
+// (its two units) as the A operand, and register v of the B operand is
+// (w >> v) & 0x01010101 for the group's mask word w, a byte 0x01 (e4m3
+// 2^-9) per member.  E8M0 scales 2^-17 (A) and 2^9 (B) make the product
+// sum_i m_i lo_i exactly as stored, into the same FP32 accumulators.  The
+// fp8 MFMA forms each 64-term dot product to about 2^-13 of the sum of the
+// terms' magnitudes (measured), far below the e4m3 rounding of lo itself.
+template <int JB, int NW, bool FOLD, bool LO8>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
     const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
     double* __restrict__ partial, int64_t prow, float* __restrict__ sig,
-    const float* __restrict__ v32, double* __restrict__ pv) {
+    const float* __restrict__ v32, double* __restrict__ pv, int scale_lo, int scale_mask) {
     constexpr int kWS = 32 * JB;
     constexpr int kTile = NW * kWS;
     constexpr int kMaskVec = kTile;
     constexpr int kMaskLoads = kWS / 64;
-    constexpr int kRowsW = 2 * kOct / NW;  // octet rows of a chunk (both planes) each wave loads
-    static_assert(kRowsW * NW == 2 * kOct, "waves split a chunk evenly");
+    // LDS rows (64 uint4 each) of a chunk: 16 octets of each bf16 plane, or
+    // 16 hi octets and 8 lo units; each wave loads an equal share
+    constexpr int kChunkRows = LO8 ? kOct + kOct / 2 : 2 * kOct;
+    constexpr int kRowsW = kChunkRows / NW;
+    static_assert(kRowsW * NW == kChunkRows, "waves split a chunk evenly");
+    static_assert(!(FOLD && LO8), "the fold runs on split BF16 only");
     __shared__ uint4 zbuf[2][kChunkVec];
     __shared__ uint4 mbuf[2][kMaskVec];
     const int tid = threadIdx.x;
@@ -164,6 +182,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     int l_ch = 0, l_nchunk = 0, l_nxc = 0;
     const uint4* l_zsrc = nullptr;
     const uint4* l_zsrc_y = nullptr;
+    const uint4* l_lo8 = nullptr;  // LO8: the pair's first lo unit in this column slice
     const uint4* l_mload[kMaskLoads];
     auto l_setup = [&]() {
         const Tile t = tile_of(l_it);
@@ -171,10 +190,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
         const BlockPair bq = bp[t.pair];
         l_nchunk = pd.Np / kChunk;
         l_nxc = pd.nxc;
-        const uint4* plane = (kRowsW * wave) / kOct ? zlo : zhi;
-        const int64_t off = (kRowsW * wave) % kOct;
-        l_zsrc = plane + ((pd.zrow0 >> 3) + off) * d_pad + t.slot * kDSlot;
-        l_zsrc_y = plane + ((pd.zrow_y >> 3) + off) * d_pad + t.slot * kDSlot;
+        if constexpr (LO8) {
+            l_zsrc = zhi + (pd.zrow0 >> 3) * d_pad + t.slot * kDSlot;
+            l_lo8 = zlo + (pd.zrow0 >> 4) * d_pad + t.slot * kDSlot;
+        } else {
+            const uint4* plane = (kRowsW * wave) / kOct ? zlo : zhi;
+            const int64_t off = (kRowsW * wave) % kOct;
+            l_zsrc = plane + ((pd.zrow0 >> 3) + off) * d_pad + t.slot * kDSlot;
+            l_zsrc_y = plane + ((pd.zrow_y >> 3) + off) * d_pad + t.slot * kDSlot;
+        }
 #pragma unroll
         for (int k = 0; k < kMaskLoads; ++k) {
             const int r = t.b0 + wave * kWS + 64 * k + lane;
@@ -186,11 +210,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // one chunk at the cursor into buffer b, then advance the cursor (past the
     // work-group's last chunk it stays there: a harmless reload into a free buffer)
     auto issue_next = [&](int b) {
-        const uint4* base = l_ch < l_nxc ? l_zsrc + l_ch * chunk_stride : l_zsrc_y + (l_ch - l_nxc) * chunk_stride;
         const uint32_t zl = __builtin_amdgcn_readfirstlane(lds_addr(&zbuf[b][kRowsW * wave * kDSlot]));
         const uint32_t ml = __builtin_amdgcn_readfirstlane(lds_addr(&mbuf[b][wave * kWS]));
+        if constexpr (LO8) {
 #pragma unroll
-        for (int k = 0; k < kRowsW; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
+            for (int k = 0; k < kRowsW; ++k) {
+                const int r = kRowsW * wave + k;  // wave-uniform
+                const uint4* src = r < kOct ? l_zsrc + ((int64_t)kOct * l_ch + r) * d_pad
+                                            : l_lo8 + ((int64_t)(kOct / 2) * l_ch + (r - kOct)) * d_pad;
+                dma16(src + lane, zl + 16 * kDSlot * k);
+            }
+        } else {
+            const uint4* base = l_ch < l_nxc ? l_zsrc + l_ch * chunk_stride : l_zsrc_y + (l_ch - l_nxc) * chunk_stride;
+#pragma unroll
+            for (int k = 0; k < kRowsW; ++k) dma16(base + k * d_pad + lane, zl + 16 * kDSlot * k);
+        }
 #pragma unroll
         for (int k = 0; k < kMaskLoads; ++k) dma16(l_mload[k] + l_ch, ml + 16 * 64 * k);
         if (l_ch + 1 < l_nchunk) {
@@ -252,7 +286,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
-                    a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
+                    if (!LO8) a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
                 }
                 const uint32_t kBit = 0x00800080u << (4 * (s & 1));
 #pragma unroll
@@ -267,13 +301,42 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
             for (int s = 0; s < kChunk / 16; ++s) {
                 if (s + 1 < kChunk / 16) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
 #pragma unroll
-                for (int pl = 0; pl < 2; ++pl)
+                for (int pl = 0; pl < (LO8 ? 1 : 2); ++pl)
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
 #pragma unroll
                         for (int j = 0; j < JB; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s & 1][pl][i], bm[s & 1][j],
                                                                                 acc[i][j], 0, 0, 0);
+            }
+            if constexpr (LO8) {
+                // the lo plane: two 64-row K-steps; group g = 2 s2 + h of the
+                // chunk is mask word g, and the words were rotated right by
+                // 8 h for the bf16 operands (rotate back)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int g = 2 * s2 + h;
+                    i32x8 a8[2];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const uint4 u0 = cur[(kOct + 2 * g) * kDSlot + 32 * i + c];
+                        const uint4 u1 = cur[(kOct + 2 * g + 1) * kDSlot + 32 * i + c];
+                        a8[i] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                                      (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+                    }
+#pragma unroll
+                    for (int j = 0; j < JB; ++j) {
+                        const uint32_t wr = s2 == 0 ? (h ? mw[j].y : mw[j].x) : (h ? mw[j].w : mw[j].z);
+                        const uint32_t w = __builtin_amdgcn_alignbit(wr, wr, 32u - rot);
+                        i32x8 b8;
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) b8[v] = (int)((w >> v) & 0x01010101u);
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+                            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                a8[i], b8, acc[i][j], 0, 0, 0, scale_lo, 0, scale_mask);
+                    }
+                }
             }
             // chunk g + 1 has landed (this wave's loads, then every wave's
             // through the barrier); every wave is done reading buffer b
@@ -691,7 +754,9 @@ static unsigned persistent_grid(int64_t tiles, int per_cu) {
     return (unsigned)(all < want ? all : want);
 }
 
-int groupsum_tile_splits(int precision) { return precision == HBT_BF16X2 ? kTileWide : kTileB; }
+int groupsum_tile_splits(int precision) {
+    return precision == HBT_BF16X2 || precision == HBT_BF16_E4M3 ? kTileWide : kTileB;
+}
 
 hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair* bp,
                            const GemmTile* tiles, int ntiles, const GemmGroup* groups, int ngw,
@@ -710,24 +775,40 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             static_assert(32 * 4 * 8 == kTileWide && 32 * 2 * 4 == kTileNarrow, "tile widths");
             if (ntw > 0) {
                 if (pv)
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, true>), dim3(persistent_grid(ntw, grid_wide)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, true, false>), dim3(persistent_grid(ntw, grid_wide)),
                                        dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
-                                       t32, partial, prow, sig, v32, pv);
+                                       t32, partial, prow, sig, v32, pv, 0, 0);
                 else
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false>), dim3(persistent_grid(ntw, grid_wide)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, false>), dim3(persistent_grid(ntw, grid_wide)),
                                        dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
-                                       t32, partial, prow, sig, nullptr, nullptr);
+                                       t32, partial, prow, sig, nullptr, nullptr, 0, 0);
             }
             if (nt256 > 0) {
                 if (pv)
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, true>), dim3(persistent_grid(nt256, grid_narrow)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, true, false>), dim3(persistent_grid(nt256, grid_narrow)),
                                        block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                       mask, t32, partial, prow, sig, v32, pv);
+                                       mask, t32, partial, prow, sig, v32, pv, 0, 0);
                 else
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false>), dim3(persistent_grid(nt256, grid_narrow)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, false>), dim3(persistent_grid(nt256, grid_narrow)),
                                        block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                       mask, t32, partial, prow, sig, nullptr, nullptr);
+                                       mask, t32, partial, prow, sig, nullptr, nullptr, 0, 0);
             }
+            break;
+        }
+        case HBT_BF16_E4M3: {
+            // hi plane: bf16 [rows/8][d_pad][8]; lo plane at byte 2 zplane_elems:
+            // e4m3 [rows/16][d_pad][16]
+            const uint4* zhi = (const uint4*)zstore;
+            const uint4* zlo = (const uint4*)((const char*)zstore + 2 * zplane_elems);
+            const int sa = 127 - kE4m3LoShift, sb = 127 + 9;  // E8M0: 2^-17 on lo, 2^9 on the 0x01 mask bytes
+            if (ntw > 0)
+                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, true>), dim3(persistent_grid(ntw, grid_wide)),
+                                   dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
+                                   t32, partial, prow, sig, nullptr, nullptr, sa, sb);
+            if (nt256 > 0)
+                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, true>), dim3(persistent_grid(nt256, grid_narrow)),
+                                   block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
+                                   mask, t32, partial, prow, sig, nullptr, nullptr, sa, sb);
             break;
         }
         case HBT_I8X3:

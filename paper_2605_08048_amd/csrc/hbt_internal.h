@@ -231,6 +231,20 @@ __device__ __forceinline__ float bf16_plane_scale(int o4, int k) {
     return __uint_as_float((uint32_t)(254 - (1 << e)) << 23);  // 2^(127 - 2^e)
 }
 
+__device__ __forceinline__ float bf16_plane_inv_scale(int o4, int k) {
+    const int e = 4 * (o4 >> 1) + (k >> 1);
+    return __uint_as_float((uint32_t)(1 << e) << 23);  // 2^(2^e - 127)
+}
+
+// BF16 hi + E4M3 lo: the hi plane is the split-BF16 hi plane; the lo plane
+// holds e4m3(lo 2^kE4m3LoShift), lo = z - hi exact in FP32 (|lo| <= 2^-9 |z|,
+// so a unit row's values stay below e4m3's largest finite 448), one byte per
+// value in 16-row units [rows/16][d_pad][16]: unit f8_unit(r) of a 32-row
+// group, byte f8_byte(r), holds group row r (the int8 planes' order).
+constexpr int kE4m3LoShift = 17;
+__host__ __device__ constexpr int f8_unit(int r) { return (r & 7) >> 2; }
+__host__ __device__ constexpr int f8_byte(int r) { return 4 * (r & 3) + (r >> 3); }
+
 // Int8 digit planes.  z is rounded to Q = round(z 2^20) and written as three
 // balanced base-128 digits, Q = q0 2^14 + q1 2^7 + q2 (q1, q2 in [-64, 63],
 // |q0| <= 64 for |z| <= 1), stored as the int8 planes q0, -q1, q2 (the

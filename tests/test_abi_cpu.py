@@ -185,10 +185,11 @@ def test_batched_validation():
     st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                  FAKE, need, None)
     assert st == hbt.ERR_WORKSPACE
-    prm.precision = hbt.PRECISION["i8x3"]
-    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
-                                 FAKE, need2, None)
-    assert st == hbt.ERR_UNSUPPORTED
+    for prec in ("i8x3", "bf16e4m3"):  # route 0 only
+        prm.precision = hbt.PRECISION[prec]
+        st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                     FAKE, need2, None)
+        assert st == hbt.ERR_UNSUPPORTED, prec
 
 
 def test_clouds_validation():
@@ -212,7 +213,7 @@ def test_clouds_validation():
     assert call(prm, px=np.array([0, 3], dtype=np.int64)) == hbt.ERR_ARG
     assert call(prm, rows=np.array([40, 1, 33], dtype=np.int64)) == hbt.ERR_SIZE
     assert call(prm, d=66) == hbt.ERR_UNSUPPORTED
-    for prec in ("f32", "i8x3"):
+    for prec in ("f32", "i8x3", "bf16e4m3"):
         assert call(hbt.make_params(0, 0, 64, 0, precision=prec)) == hbt.ERR_UNSUPPORTED
     assert call(hbt.make_params(0, 0, 64, 0, precision="bf16x2", stat_route=1)) == hbt.ERR_UNSUPPORTED
 

@@ -56,7 +56,7 @@ RAW_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec,route", [("f32", 0), ("bf16x2", 0), ("i8x3", 0),
+@pytest.mark.parametrize("prec,route", [("f32", 0), ("bf16x2", 0), ("i8x3", 0), ("bf16e4m3", 0),
                                         ("f32", 1), ("bf16x2", 1), ("f64", 1)])
 def test_raw_errors_stay_inside_the_recheck_band(prec, route):
     """Without the recheck, |T_b - T_b(FP64)| <= band / 2 for every split."""
@@ -83,7 +83,7 @@ REPEAT_CASES = [(1000, 1000, 768, 2.2, 10), (1000, 1000, 768, 2.2, 100), (1000, 
                 (1500, 900, 1024, 0.03, 300), (700, 2100, 768, 0.03, 1)]
 
 
-@pytest.mark.parametrize("prec", ["bf16x2", "i8x3"])
+@pytest.mark.parametrize("prec", ["bf16x2", "i8x3", "bf16e4m3"])
 def test_repeated_rows_counts_match_oracle(prec):
     """Clouds built from few distinct rows, and diffuse clouds: the counts of
     the single-pair call and of the batched call equal the oracle's."""

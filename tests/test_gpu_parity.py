@@ -24,7 +24,7 @@ pytestmark = [pytest.mark.gpu,
 from paper_2605_08048_amd import hbt  # noqa: E402
 
 DEV = "cuda:0"
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "i8x3": 1e-4}
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "i8x3": 1e-4, "bf16e4m3": 1e-4}
 
 
 def _dev(a, dtype=None):
@@ -177,6 +177,13 @@ CASES = [
     (101, 157, 8192, 200, "f32", False),     # the largest d the library accepts
     (101, 157, 8192, 200, "bf16x2", False),
     (157, 101, 8192, 200, "i8x3", False),
+    (50, 60, 64, 999, "bf16e4m3", True),      # BF16 hi + e4m3 lo: FP64 input (row-at-a-time alignment)
+    (37, 150, 100, 700, "bf16e4m3", False),
+    (150, 37, 100, 700, "bf16e4m3", False),
+    (300, 450, 768, 600, "bf16e4m3", False),
+    (70, 40, 37, 300, "bf16e4m3", False),
+    (101, 157, 1030, 300, "bf16e4m3", False),
+    (101, 157, 8192, 200, "bf16e4m3", False),
 ]
 
 
@@ -224,7 +231,7 @@ def test_exhaustive_70_splits_with_explicit_masks():
         sel[k, list(c)] = True
     masks = O.bool_to_mask(sel)
     ex = O.exhaustive(X, Y)
-    for prec in ["f64", "f32", "bf16x2", "i8x3"]:
+    for prec in ["f64", "f32", "bf16x2", "i8x3", "bf16e4m3"]:
         r = hbt.perm_test(_dev(X), _dev(Y), 70, precision=prec, masks=masks)
         assert r["status"] == 0
         assert r["count"] == ex["count"]
@@ -239,7 +246,7 @@ def test_bad_explicit_mask_is_reported():
     assert r["status"] == hbt.ERR_MASK
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3", "bf16e4m3"])
 def test_block_size_offsets_and_repeat_do_not_change_results(prec):
     X, Y = _pair(500, 700, 128, kx=2.0, ky=2.05, seed=13)
     Xd, Yd = _dev(X), _dev(Y)
@@ -374,7 +381,7 @@ def test_batched_matches_oracle_per_pair():
         pairs.append(synth.Pair(X, Y, B=int(rng.integers(1, 700)), pair_index=p))
     pairs[3] = synth.Pair(pairs[3].X, pairs[3].X.copy(), B=300, pair_index=3)  # identical groups
     bt = synth.pack_batch(pairs, 96)
-    for prec in ["f32", "bf16x2", "f64", "i8x3"]:
+    for prec in ["f32", "bf16x2", "f64", "i8x3", "bf16e4m3"]:
         res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=9, precision=prec)
         for p, pr in enumerate(pairs):
             o = O.perm_test(pr.X, pr.Y, pr.B, seed=9, pair=p, want_T=True)
@@ -403,7 +410,7 @@ def test_batched_storage_group_boundaries(d):
         X, Y = _pair(n, m, d, kx=2.0, ky=2.6, angle=50.0, seed=300 + p)
         pairs.append(synth.Pair(X, Y, B=257, pair_index=p))
     bt = synth.pack_batch(pairs, d)
-    for prec in ["bf16x2", "i8x3", "f32"]:
+    for prec in ["bf16x2", "i8x3", "f32", "bf16e4m3"]:
         res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=4, precision=prec)
         for p, pr in enumerate(pairs):
             o = O.perm_test(pr.X, pr.Y, pr.B, seed=4, pair=p, want_T=True)
@@ -436,7 +443,7 @@ def test_pair_d768_point_to_centroid_sampled(prec):
     assert (np.abs(r["T"][sample] - at["T"]) / _scale(c.X, c.Y, at)).max() <= (1e-5 if prec == "f32" else 1e-4)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3", "bf16e4m3"])
 def test_pair_d768_full_size(prec):
     print(f"pair_d768 {prec}", flush=True)
     c = synth.pair_d768()
@@ -456,7 +463,7 @@ def test_pair_d768_full_size(prec):
 _NULL1024 = {}
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x2", "i8x3", "bf16e4m3"])
 def test_null_pair_d1024_full_size(prec):
     """The precision-path workload at its stated size (n 3000, m 2000, d 1024,
     B 20,000, equal concentration): counts against the oracle's full run,
@@ -492,7 +499,7 @@ def test_batch_512_d768_full_size_sampled_pairs():
     Z = _dev(b.Z)
     hbt.tune_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed)
     res = {prec: hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
-           for prec in ["bf16x2", "i8x3"]}
+           for prec in ["bf16x2", "i8x3", "bf16e4m3"]}
     del Z
     order = np.argsort(b.n + b.m, kind="stable")
     P = b.npairs

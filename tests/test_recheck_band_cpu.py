@@ -5,7 +5,8 @@ library's band (hbt_recheck_band) of the threshold, so the band must cover
 |T_b - T_b(FP64)| for every split, or a split could be decided on the wrong
 side without a recheck.  Here the rows are stored as the kernels store them
 (FP32; split BF16 hi = bf16(z), lo = bf16(z - hi), both round-to-nearest-even
-from the FP32 row; int8 digits of round(z 2^20) from the FP64 row) and the
+from the FP32 row; BF16 + e4m3 the same hi and lo = e4m3(2^17 (z - hi)) 2^-17,
+nearest-even; int8 digits of round(z 2^20) from the FP64 row) and the
 group sums are formed exactly in FP64, which isolates the storage error
 (the accumulation error is the band's e_acc, checked on the GPU).
 
@@ -30,6 +31,16 @@ def _bf16(a):
     return r.astype(np.uint32).view(np.float32)
 
 
+def _e4m3(x):
+    """Nearest e4m3 value (OCP E4M3FN: 4 significant bits, smallest normal
+    2^-6, subnormal spacing 2^-9), ties to even; |x| <= 448 here."""
+    x = np.asarray(x, np.float64)
+    a = np.abs(x)
+    _, E = np.frexp(np.where(a > 0, a, 1.0))        # a = f 2^E, f in [0.5, 1)
+    q = np.where(a < 2.0 ** -6, 2.0 ** -9, np.ldexp(1.0, E - 4))  # spacing of a's binade
+    return np.sign(x) * np.rint(a / q) * q
+
+
 def _stored(Z, prec):
     if prec == "i8x3":
         return np.rint(Z * 2.0 ** 20) / 2.0 ** 20
@@ -37,8 +48,19 @@ def _stored(Z, prec):
     if prec == "f32":
         return zf.astype(np.float64)
     hi = _bf16(zf)
+    if prec == "bf16e4m3":
+        lo = (zf - hi).astype(np.float64)            # exact in FP32
+        return hi.astype(np.float64) + _e4m3(lo * 2.0 ** 17) / 2.0 ** 17
     lo = _bf16(zf - hi)
     return hi.astype(np.float64) + lo.astype(np.float64)
+
+
+def test_e4m3_rounding_definition():
+    """The emulation's e4m3 grid: exact values stay, ties go to the even
+    significand, subnormals step by 2^-9."""
+    v = np.array([1.0, 1.125, 1.0625, 1.1875, 448.0, 2.0 ** -6, 2.0 ** -9, 3 * 2.0 ** -10, 2.0 ** -10, 0.0, -1.0625])
+    want = np.array([1.0, 1.125, 1.0, 1.25, 448.0, 2.0 ** -6, 2.0 ** -9, 2 * 2.0 ** -9, 0.0, 0.0, -1.0])
+    assert np.array_equal(_e4m3(v), want)
 
 
 def _cloud(g, n, d, kappa, mu, rep):
@@ -78,7 +100,7 @@ def _worst_ratio(n, m, d, kx, ky, rep, B, seed=0):
 
     r1, r2, T64 = stat(Z)
     out = {}
-    for prec in ("f32", "bf16x2", "i8x3"):
+    for prec in ("f32", "bf16x2", "i8x3", "bf16e4m3"):
         T = stat(_stored(Z, prec))[2]
         eps = hbt.recheck_band(prec, n, m, d, r1, r2)
         out[prec] = float((np.abs(T - T64) / eps).max())
