@@ -523,7 +523,7 @@ BlockPair block_pair(int64_t mrow0, int64_t mword0, uint64_t perm_base, int64_t 
 // tile times every 64-row tile of its padded rows.
 void add_ctiles(Plan& P, int p, int64_t nb) {
     for (int64_t b = 0; b < nb; b += kTileB)
-        for (int i0 = 0; i0 < P.pairs[p].Np; i0 += 64) P.ctiles.push_back(CTile{p, (int32_t)b, i0, 0});
+        for (int i0 = 0; i0 < P.pairs[p].Np; i0 += kCTileRows) P.ctiles.push_back(CTile{p, (int32_t)b, i0, 0});
 }
 
 // Single-pair plan with blocks of B0 splits.
@@ -979,7 +979,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         if (P.route2) {
             StageTimer t_(HBT_STAGE_CENTROID, s);
             HIP_TRY(launch_centroid(P.precision == HBT_BF16X2, w.pairs, w.bp, w.ctiles,
-                                    (int)((nb + kTileB - 1) / kTileB) * P.ntile_i, P.d_pad, z32, w.sig,
+                                    (int)((nb + kTileB - 1) / kTileB) * (P.pairs[0].Np / kCTileRows), P.d_pad,
+                                    z32, w.sig,
                                     w.mask, w.zt, w.partial2, P.block_rows, s));
         }
         { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,

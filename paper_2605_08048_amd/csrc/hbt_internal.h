@@ -108,8 +108,10 @@ struct GemmTile {
     int32_t b0;          // first split of the tile, relative to the pair's block rows
 };
 
-// A point-to-centroid tile: 64 pooled rows [i0, i0 + 64) x kTileB split rows
-// [b0, b0 + kTileB) of one pair's block rows.
+// A point-to-centroid tile: kCTileRows pooled rows [i0, i0 + kCTileRows) x
+// kTileB split rows [b0, b0 + kTileB) of one pair's block rows.  Its partial
+// sums are written per 64 rows (pooled sizes are padded to 128).
+constexpr int kCTileRows = 128;
 struct CTile {
     int32_t pair;
     int32_t b0;
