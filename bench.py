@@ -212,6 +212,10 @@ def stage_errors(dev, pair, hbt, torch, sample_every=97):
     Y = torch.from_numpy(pair.Y).to(dev)
     runs = {prec: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, want_T="norms")["T"]
             for prec in ("f64", "f32", "bf16x2", "i8x3", "bf16e4m3")}
+    # the point-to-centroid route (X S^T, K = d): FP32 MFMA, and split BF16 in three terms
+    for prec in ("f32", "bf16x2"):
+        runs[f"{prec}_point_to_centroid"] = hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec,
+                                                          stat_route=1, want_T="norms")["T"]
     ref = runs.pop("f64")
     idx = np.arange(0, pair.B, sample_every)
     n, m, d = pair.n, pair.m, pair.d
