@@ -184,6 +184,8 @@ CASES = [
     (70, 40, 37, 300, "bf16e4m3", False),
     (101, 157, 1030, 300, "bf16e4m3", False),
     (101, 157, 8192, 200, "bf16e4m3", False),
+    (9000, 8000, 64, 100, "bf16e4m3", False),  # many 32-row groups and lo units per pair
+    (9000, 8000, 64, 100, "bf16x2", False),
 ]
 
 
