@@ -39,12 +39,56 @@ struct SplitLds {
 constexpr int kSplitWaves = 4;          // waves (split rows) per work-group
 constexpr int kSplitStaticLds = kSplitWaves * 1024;
 
-// hist[key] += 1 for the 16 keys of a block; W, the wave, is a constant so the
-// wave's histogram offset folds into the LDS instruction.
+// hist[W][key] += 1 for the 16 keys of a block.  The wave's histogram offset
+// W * 1024 goes into the LDS instruction's immediate offset, so that a key
+// costs one VALU operation (its byte times 4) besides the LDS add.  (Written
+// as inline asm: with plain atomics the compiler merges the four waves' code
+// paths and adds the offset in a register.  An add without return writes no
+// register, and one wave's LDS operations complete in issue order, so the
+// later reads of the histogram see every add.)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+template <int OFF>
+__device__ __forceinline__ void lds_inc(uint32_t addr, uint32_t one) {
+    asm volatile("ds_add_u32 %0, %1 offset:%2" : : "v"(addr), "v"(one), "i"(OFF) : "memory");
+}
+#pragma clang diagnostic pop
 template <int W>
 __device__ __forceinline__ void count_block(uint32_t (*hist)[256], uint4 w) {
+    const uint32_t base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)&hist[0][0];
+    const uint32_t one = 1u;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) atomicAdd(&hist[W][(word_of(w, j >> 2) >> (8 * (j & 3))) & 0xffu], 1u);
+    for (int j = 0; j < 16; ++j)
+        lds_inc<W * 1024>(base + (((word_of(w, j >> 2) >> (8 * (j & 3))) & 0xffu) << 2), one);
+}
+
+// Bit j of the result = [byte j % 4 of word j / 4 < theta] for the 16 keys of
+// a block (item j's primary key, below the bucket byte theta), with four
+// bytes compared at once: for each byte x and t = theta,
+//   x < t  <=>  (x7 = 0 and t7 = 1) or (x7 = t7 and (x & 127) < (t & 127)),
+// where (x & 127) + (128 - (t & 127)) has bit 7 set exactly when
+// (x & 127) >= (t & 127) (no carry leaves the byte); one three-input logic
+// operation combines the three conditions in bit 7.  The 16 flags are then
+// gathered: bit 8 b + q <- byte b of word q, packed to bit 4 b + q, and the
+// 4 x 4 bit matrix transposed (two delta swaps) to bit 4 q + b.
+__device__ __forceinline__ uint32_t below_theta(uint4 w, uint32_t theta4) {
+    const uint32_t k = 0x80808080u - (theta4 & 0x7f7f7f7fu);  // per byte 128 - (t & 127)
+    // truth table of (~x & t) | (~(x ^ t) & ~s) over the operands (x, t, s)
+    constexpr unsigned kTT = ((~0xF0u & 0xCCu) | (~(0xF0u ^ 0xCCu) & ~0xAAu)) & 0xffu;
+    auto lt7 = [&](uint32_t x) {
+        return __builtin_amdgcn_bitop3_b32(x, theta4, (x & 0x7f7f7f7fu) + k, (unsigned char)kTT);
+    };
+    uint32_t u = (lt7(w.x) >> 7) & 0x01010101u;
+    u |= (lt7(w.y) >> 6) & 0x02020202u;
+    u |= (lt7(w.z) >> 5) & 0x04040404u;
+    u |= (lt7(w.w) >> 4) & 0x08080808u;
+    uint32_t v = (u | (u >> 4)) & 0x00ff00ffu;
+    v = (v | (v >> 8)) & 0xffffu;
+    uint32_t t = (v ^ (v >> 3)) & 0x0A0Au;
+    v ^= t ^ (t << 3);
+    t = (v ^ (v >> 6)) & 0x00CCu;
+    v ^= t ^ (t << 6);
+    return v;
 }
 
 // Philox block c of split b: the primary keys of items 16c .. 16c+15 as 16
@@ -163,10 +207,7 @@ __global__ __launch_bounds__(256) void k_split_masks(const BlockPair* __restrict
     uint32_t cbase = 0;  // bucket items listed so far (wave-uniform)
     auto classify = [&](int k, uint4 w) {
         const int c = 64 * k + lane;
-        uint32_t lt = 0u;
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            lt |= (uint32_t)(((word_of(w, j >> 2) >> (8 * (j & 3))) & 0xffu) < theta) << j;
+        uint32_t lt = below_theta(w, theta4);
         // bit 7 of each byte equal to theta (exact), gathered into one word:
         // bit 8 b + q marks item 4 q + b of the block
         uint32_t eq = 0u;
@@ -218,11 +259,13 @@ __global__ __launch_bounds__(256) void k_split_masks(const BlockPair* __restrict
             const uint4 w = philox4x32_10(make_uint4(ik >> 2, b, pd.pair_index, 1u), key0, key1);
             sk = word_of(w, ik & 3);
         }
+        // (S, i) order as one 64-bit key
+        const uint64_t key = ((uint64_t)sk << 32) | ik;
         uint32_t rank = 0;
         for (uint32_t q = 0; q < cnt; ++q) {
-            const uint32_t s2 = __builtin_amdgcn_readlane(sk, q);
-            const uint32_t i2 = __builtin_amdgcn_readlane(ik, q);
-            rank += (s2 < sk) || (s2 == sk && i2 < ik);
+            const uint64_t k2 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(sk, q) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane(ik, q);
+            rank += k2 < key;
         }
         if ((uint32_t)lane < cnt && rank < need) atomicOr(&mlds[ik >> 5], 1u << (ik & 31));
     } else {
