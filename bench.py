@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--i8-steps", type=int, default=3, help="timed steps of the int8 digit-plane variant")
     ap.add_argument("--f8-steps", type=int, default=3, help="timed steps of the BF16 hi + e4m3 lo variant")
+    ap.add_argument("--lazy-steps", type=int, default=3,
+                    help="timed steps of the lazy split-BF16 precision (hi plane first, lo near the threshold)")
     ap.add_argument("--single-steps", type=int, default=5,
                     help="timed calls per precision of the single-pair workloads (0 skips them)")
     ap.add_argument("--cloud-steps", type=int, default=5,
@@ -407,8 +409,27 @@ def main():
               "rechecked_splits_per_step": int(outf["n_recheck"].sum()),
               "pairs_bad_status": badf,
               "pairs_with_counts_equal_to_bf16x2": f"{int(np.sum(outf['count'] == out['count']))}/{P}",
-              "kernel": "k_groupsum_bf16x2<4, 8, false, true>: bf16 MFMA on the hi plane, "
+              "kernel": "k_groupsum_bf16x2<4, 8, false, 1>: bf16 MFMA on the hi plane, "
                         "v_mfma_scale_f32_32x32x64_f8f6f4 on the e4m3 lo plane, one FP32 accumulator"}
+
+    lazy = None
+    if args.lazy_steps > 0:
+        dtl, msl, ll, outl, badl = run("bf16lazy", args.lazy_steps, 1)
+        log(f"lazy split BF16: {dtl / args.lazy_steps * 1e3:.2f} ms/step")
+        gl = msl[2] / args.lazy_steps  # both products of a call (hi plane, then the listed splits)
+        lazy = {"value": stats_per_step * args.lazy_steps / dtl, "ms_per_step": dtl / args.lazy_steps * 1e3,
+                "speedup_over_split_bf16": (stats_per_step * args.lazy_steps / dtl) / value,
+                "groupsum_ms_per_step": gl, "groupsum_tflops": algo_flops / (gl * 1e-3) / 1e12,
+                "groupsum_frac_bf16_peak": algo_flops / (gl * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                "stages_ms_per_step": {k: msl[i] / args.lazy_steps for i, k in enumerate(STAGES)},
+                "rechecked_splits_per_step": int(outl["n_recheck"].sum()),
+                "pairs_bad_status": badl,
+                "pairs_with_counts_equal_to_bf16x2": f"{int(np.sum(outl['count'] == out['count']))}/{P}",
+                "pairs_with_n_recheck_equal_to_bf16x2":
+                    f"{int(np.sum(outl['n_recheck'] == out['n_recheck']))}/{P}",
+                "kernels": "k_groupsum_bf16x2<4, 8, false, 2> (hi plane, every split), then "
+                           "k_groupsum_bf16x2<2, 4, false, 3> (both planes, the splits within the hi "
+                           "plane's error band of the threshold)"}
 
     # single-pair workloads (the per-pair call), every precision on the same input
     single = None
@@ -550,6 +571,7 @@ def main():
         "fp32_plain": fp,
         "int8_planes": i8,
         "bf16_hi_e4m3_lo": f8,
+        "lazy_split_bf16": lazy,
         "point_to_centroid": route2,
         "shared_clouds": clouds,
         "single_pair": single,

@@ -80,10 +80,22 @@ typedef enum hbt_precision {
                          int8 digit planes on the int8 MFMA: exact integer group
                          sums, FP64 epilogue; the 8-bit-operand variant of the
                          group-sum product (route 0 only) */
-    HBT_BF16_E4M3 = 4 /* the split-BF16 hi plane plus lo = z - hi as FP8 e4m3 (of
+    HBT_BF16_E4M3 = 4, /* the split-BF16 hi plane plus lo = z - hi as FP8 e4m3 (of
                          lo * 2^17, round to nearest even): bf16 MFMA for hi, the
                          E8M0-scaled fp8 MFMA for lo, one FP32 accumulator; the
                          mask stays exact (route 0, split rows of FP32 or FP64) */
+    HBT_BF16_LAZY = 5 /* the split-BF16 planes, with the lo plane multiplied only
+                         where it can change a decision: the group sums of every
+                         split from the hi plane alone (one BF16 product, the
+                         half-precision GEMM of Sec. 3.2, practical note 1);
+                         splits whose T_b lies within that product's error band
+                         of the threshold (every split of a pair with
+                         min(n, m) < 16) get the split-BF16 product of both
+                         planes, then the FP64 recheck as usual.  Counts and p
+                         are those of the FP64 statistic, as for the other
+                         precisions; T_b (and t_mean, t_sd) carry the hi plane's
+                         error outside the band.  hbt_perm_test_batched only
+                         (HBT_ERR_UNSUPPORTED elsewhere), route 0 */
 } hbt_precision;
 
 typedef enum hbt_dtype { HBT_IN_F32 = 0, HBT_IN_F64 = 1 } hbt_dtype;
@@ -260,7 +272,9 @@ hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous);
  * decision threshold inside which a split's T_b, computed by `precision` and
  * `stat_route`, is re-evaluated in FP64 (the count follows the FP64 statistic
  * of Algorithm 1 Step 5 that way), for a split whose groups of n and m items
- * have mean resultant lengths r1 and r2 (Sec. 3.1, "Dispersion proxy").  The
+ * have mean resultant lengths r1 and r2 (Sec. 3.1, "Dispersion proxy").  For
+ * HBT_BF16_LAZY it is the band of the first, hi-plane product, inside which a
+ * split goes to the split-BF16 product (whose band is HBT_BF16X2's).  The
  * band bounds |T_b - T_b(FP64)|: the storage error of the rows, which may add
  * up coherently over repeated rows, the accumulation error of the product,
  * and for stat_route 1 the FP32 point-to-centroid products.  Host function,

@@ -106,6 +106,11 @@ RecheckBand precision_band(int precision, int d, bool route2) {
         // rounding of its 64-term dot products (2^-13 of the lo terms, i.e.
         // 2^-21 |z|) and the subnormal spacing of the scaled lo (2^-27 absolute)
         case HBT_BF16_E4M3: b = RecheckBand{4e-6, (0x1p-12 + 0x1p-21) * rd + 0x1p-27, 4.0, 0.0}; break;
+        // the lazy precision's first pass: the bf16 hi plane alone keeps 8
+        // significant bits, |z - hi| <= 2^-8 |z| (the second pass has the
+        // split-BF16 band; pairs with a group under kLazyMinGroup skip the
+        // first pass's decisions)
+        case HBT_BF16_LAZY: b = RecheckBand{4e-6, 0x1p-8 * rd, 4.0, 0.0}; break;
         default: b = RecheckBand{4e-6, 0x1p-16 * rd, 4.0, 0.0}; break;
     }
     if (route2) {
@@ -174,6 +179,11 @@ struct Workspace {
     float* v32;         // FP32 copy of each pair's v
     double* pv;         // v . sigma per split row and slot (slot-major)
     double* fpart;      // fold sums per segment of X items and split row (segment-major)
+    // the lazy precision's refinement lists and their tile table
+    uint32_t* rlist;    // per pair, from its first block row: the split rows to refine
+    uint32_t* rcnt;     // per pair: their number
+    GemmGroup* rgroups; // tile table of the refinement product (one group per product group)
+    int64_t* rtiles;    // its tile count
     size_t bytes;
 };
 
@@ -221,6 +231,7 @@ struct Plan {
     };
     std::vector<Chunk> cplan;
     TileCost tune = default_tune(HBT_BF16X2);  // launch parameters of (precision, d_pad)
+    bool lazy = false;             // HBT_BF16_LAZY: split-BF16 storage (precision), hi-plane first pass
     bool fold = false;             // pairs of shared clouds, stored unreflected
     int fold_segs = 0;             // the largest pair's fold_segments(n)
     std::vector<PairDesc> cdesc;   // their clouds
@@ -295,6 +306,17 @@ Workspace carve(const Plan& P, void* ws) {
         w.pv = nullptr;
         w.fpart = nullptr;
     }
+    if (P.lazy) {
+        w.rlist = c.take<uint32_t>((size_t)std::max<int64_t>(P.block_rows, 1));
+        w.rcnt = c.take<uint32_t>((size_t)(np + 1) / 2 * 2);
+        w.rgroups = c.take<GemmGroup>(std::max<size_t>(P.groups.size(), 1));
+        w.rtiles = c.take<int64_t>(1);
+    } else {
+        w.rlist = nullptr;
+        w.rcnt = nullptr;
+        w.rgroups = nullptr;
+        w.rtiles = nullptr;
+    }
     w.bytes = c.off + 256;
     return w;
 }
@@ -336,7 +358,7 @@ void add_pair(Plan& P, const void* X, const void* Y, int64_t n, int64_t m, uint3
 }
 
 hbt_status check_enums(const hbt_perm_params* prm) {
-    if (prm->precision < HBT_F64 || prm->precision > HBT_BF16_E4M3)
+    if (prm->precision < HBT_F64 || prm->precision > HBT_BF16_LAZY)
         return fail(HBT_ERR_ARG, "unknown precision %d", prm->precision);
     if (prm->input_dtype != HBT_IN_F32 && prm->input_dtype != HBT_IN_F64)
         return fail(HBT_ERR_DTYPE, "unknown input dtype %d", prm->input_dtype);
@@ -347,8 +369,10 @@ hbt_status check_enums(const hbt_perm_params* prm) {
     if (prm->align != 0 && prm->align != 1) return fail(HBT_ERR_ARG, "align must be 0 or 1");
     if (prm->stat_route != 0 && prm->stat_route != 1)
         return fail(HBT_ERR_ARG, "unknown stat_route %d", prm->stat_route);
-    if (prm->stat_route == 1 && (prm->precision == HBT_I8X3 || prm->precision == HBT_BF16_E4M3))
-        return fail(HBT_ERR_UNSUPPORTED, "the int8 and BF16 + e4m3 planes compute the statistic by route 0 only");
+    if (prm->stat_route == 1 &&
+        (prm->precision == HBT_I8X3 || prm->precision == HBT_BF16_E4M3 || prm->precision == HBT_BF16_LAZY))
+        return fail(HBT_ERR_UNSUPPORTED,
+                    "the int8, BF16 + e4m3 and lazy split-BF16 products compute the statistic by route 0 only");
     if (prm->flags & ~(HBT_FLAG_NO_RECHECK | HBT_FLAG_T_OUT_F64 | HBT_FLAG_T_OUT_NORMS))
         return fail(HBT_ERR_ARG, "unknown flags 0x%x", prm->flags);
     return HBT_OK;
@@ -370,9 +394,12 @@ void finish_plan(Plan& P, int64_t d, int precision, int input_dtype) {
     P.d = (int)d;
     P.d_pad = (int)round_up(d, kDPad);
     P.nslot = P.d_pad / kDSlot;
-    P.precision = precision;
+    // the lazy precision stores and tunes as split BF16; only its product
+    // and statistic stages differ
+    P.lazy = precision == HBT_BF16_LAZY;
+    P.precision = P.lazy ? HBT_BF16X2 : precision;
     P.input_dtype = input_dtype;
-    P.tune = tile_cost(P.d_pad, precision);
+    P.tune = tile_cost(P.d_pad, P.precision);
 }
 
 // ---------------------------------------------------------------------------
@@ -652,7 +679,23 @@ hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_pa
                             hbt_result* results, hipStream_t s) {
     const int np = P.npairs;
     const int no_recheck = common->flags & HBT_FLAG_NO_RECHECK;
-    { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st,
+    if (P.lazy) {
+        // first pass: decide from the hi-plane sums what they can decide,
+        // list the rest; second pass: split-BF16 sums of the listed splits
+        { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat_lazy(false, w.pairs, w.bp, np, P.block_rows, w.st,
+                          w.partial, P.nslot, P.block_rows, P.d, common->gd, common->alternative,
+                          precision_band(HBT_BF16_LAZY, P.d, false), no_recheck, w.tw, w.cnt, w.flags, w.nflag,
+                          w.rlist, w.rcnt, s)); }
+        { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_refine_tiles(w.groups, (int)P.groups.size(), w.rcnt,
+                          P.d_pad, w.rgroups, w.rtiles, s)); }
+        { StageTimer t_(HBT_STAGE_GROUPSUM, s); HIP_TRY(launch_groupsum_refine(w.pairs, w.bp, w.rgroups,
+                          (int)P.groups.size(), w.rtiles, P.d_pad, w.zstore, P.zrows * P.d_pad, w.mask, w.t32,
+                          w.partial, P.block_rows, w.rlist, w.rcnt, P.tune.grid_narrow, s)); }
+        { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat_lazy(true, w.pairs, w.bp, np, P.block_rows, w.st,
+                          w.partial, P.nslot, P.block_rows, P.d, common->gd, common->alternative,
+                          precision_band(HBT_BF16X2, P.d, false), no_recheck, w.tw, w.cnt, w.flags, w.nflag,
+                          w.rlist, w.rcnt, s)); }
+    } else { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, np, P.block_rows, w.st,
                         P.route2 ? w.partial2 : w.partial, P.route2 ? 0 : P.nslot,
                         P.block_rows, P.d, common->gd,
                         common->alternative, precision_band(P.precision, P.d, P.route2), no_recheck, nullptr,
@@ -700,6 +743,7 @@ hbt_status batched_pipelined(const Plan& P, const Workspace& w, const hbt_perm_p
         HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
         HIP_TRY(zero(w.nflag, 8, s));
+        if (P.lazy) HIP_TRY(zero(w.rcnt, (size_t)(np + 1) / 2 * 8, s));
     }
     HIP_TRY(ev.record(s, &e0));
     HIP_TRY(hipStreamWaitEvent(qg, e0, 0));
@@ -733,7 +777,7 @@ hbt_status batched_pipelined(const Plan& P, const Workspace& w, const hbt_perm_p
             HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, 0, w.groups + c.g0, c.ngw,
                                     (int)c.ntw, c.ng256, (int)c.nt256, P.d_pad, w.zstore,
                                     P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
-                                    nullptr, qg, P.tune.grid_wide, P.tune.grid_narrow));
+                                    nullptr, qg, P.tune.grid_wide, P.tune.grid_narrow, nullptr, nullptr, P.lazy));
         }
     }
     hipEvent_t ej;
@@ -851,7 +895,7 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm) {
     if (!prm || check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset) ||
         prm->precision < HBT_F64 || prm->precision > HBT_BF16_E4M3) {
-        return 0;
+        return 0;  // (the lazy precision is for the batched call only)
     }
     int64_t B0;
     Plan P = plan_single(prm, nullptr, nullptr, &B0);
@@ -867,6 +911,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     hbt_status st = check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset);
     if (st) return st;
     if ((st = check_enums(prm))) return st;
+    if (prm->precision == HBT_BF16_LAZY)
+        return fail(HBT_ERR_UNSUPPORTED, "the lazy split-BF16 precision is for the batched call only");
     if (prm->block_perms < 0) return fail(HBT_ERR_ARG, "block_perms must be >= 0");
     int64_t B0;
     Plan P = plan_single(prm, X, Y, &B0);
@@ -1134,7 +1180,7 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
         return order;
     };
     const std::vector<int> order = by_size(0, (int)npairs);
-    const int tb = groupsum_tile_splits(common->precision);
+    const int tb = groupsum_tile_splits(P.precision);
     for (int p : order)
         for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
     // Pipeline chunks: consecutive pair ranges of about equal product work
@@ -1172,7 +1218,7 @@ size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, co
                                             const int64_t* B, int64_t d,
                                             const hbt_perm_params* common) {
     if (npairs < 1 || !n || !m || !B || !common) return 0;
-    if (common->precision < HBT_F64 || common->precision > HBT_BF16_E4M3) return 0;
+    if (common->precision < HBT_F64 || common->precision > HBT_BF16_LAZY) return 0;
     for (int64_t p = 0; p < npairs; ++p)
         if (check_sizes(n[p], m[p], d, B[p], common->perm_offset)) return 0;
     std::vector<int64_t> off((size_t)npairs + 1, 0);
@@ -1245,6 +1291,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
             HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), qt));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), qt));
         HIP_TRY(zero(w.nflag, 8, qt));
+        if (P.lazy) HIP_TRY(zero(w.rcnt, (size_t)(np + 1) / 2 * 8, qt));
         if (P.route2) HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(CTile), qt));
     }
     {
@@ -1266,7 +1313,8 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, (int)P.tiles.size(), w.groups,
                                 P.ngw, (int)P.ntw, P.ng256, (int)P.nt256, P.d_pad, w.zstore,
                                 P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial, P.block_rows,
-                                P.route2 ? w.sig : nullptr, s, P.tune.grid_wide, P.tune.grid_narrow));
+                                P.route2 ? w.sig : nullptr, s, P.tune.grid_wide, P.tune.grid_narrow, nullptr,
+                                nullptr, P.lazy));
     }
     if (P.route2) {
         StageTimer t_(HBT_STAGE_CENTROID, s);
@@ -1527,7 +1575,7 @@ hbt_status hbt_recheck_band(int32_t precision, int32_t stat_route, int32_t gd, i
                             int64_t d, double r1, double r2, double* eps) {
     g_err.clear();
     if (!eps) return fail(HBT_ERR_ARG, "NULL pointer");
-    if (precision < HBT_F64 || precision > HBT_BF16_E4M3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
+    if (precision < HBT_F64 || precision > HBT_BF16_LAZY) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
     if (stat_route != 0 && stat_route != 1) return fail(HBT_ERR_ARG, "unknown stat_route %d", stat_route);
     if (gd != HBT_GD_BANERJEE && gd != HBT_GD_IDENTITY) return fail(HBT_ERR_ARG, "unknown g_d %d", gd);
     if (n < 1 || m < 1 || d < 1 || d > HBT_MAX_D)

@@ -17,6 +17,7 @@
 // Tile = kDSlot columns x (1024 splits for split BF16 with eight waves, or
 // 256 with four; 256 for FP32 / FP64 and the int8 digit planes).
 #include <atomic>
+#include <type_traits>
 
 #include "hbt_launch.h"
 
@@ -136,24 +137,37 @@ constexpr int wait_vmcnt(int loads) { return (loads & 0xf) | ((loads >> 4) << 14
 // sum_i m_i lo_i exactly as stored, into the same FP32 accumulators.  The
 // fp8 MFMA forms each 64-term dot product to about 2^-13 of the sum of the
 // terms' magnitudes (measured), far below the e4m3 rounding of lo itself.
-template <int JB, int NW, bool FOLD, bool LO8>
+//
+// HI (the lazy precision's first pass): the hi plane alone; a chunk holds its
+// 16 octets.  REFINE (its second pass): both planes as split BF16, for the
+// splits listed per pair in rlist (pair p's rcnt[p] split rows from
+// rlist[mrow0 of p]), with the tile table and its length (ntile_dev) built on
+// the device; each listed split's sums are those the split-BF16 kernel gives
+// it (same instructions, same order), written to its own partial row.
+enum GroupsumMode { kModeSplit = 0, kModeLo8 = 1, kModeHi = 2, kModeRefine = 3 };
+template <int JB, int NW, bool FOLD, int MODE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_groupsum_bf16x2(
     const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp,
-    const GemmGroup* __restrict__ groups, int ngroups, int ntile_total, int nslot, int d_pad,
+    const GemmGroup* __restrict__ groups, int ngroups, int ntile_arg, int nslot, int d_pad,
     const uint4* __restrict__ zhi, const uint4* __restrict__ zlo,
     const uint32_t* __restrict__ mask, const float* __restrict__ t32,
     double* __restrict__ partial, int64_t prow, float* __restrict__ sig,
-    const float* __restrict__ v32, double* __restrict__ pv, int scale_lo, int scale_mask) {
+    const float* __restrict__ v32, double* __restrict__ pv, int scale_lo, int scale_mask,
+    const uint32_t* __restrict__ rlist, const uint32_t* __restrict__ rcnt,
+    const int64_t* __restrict__ ntile_dev) {
+    constexpr bool LO8 = MODE == kModeLo8, HI = MODE == kModeHi, IND = MODE == kModeRefine;
     constexpr int kWS = 32 * JB;
     constexpr int kTile = NW * kWS;
     constexpr int kMaskVec = kTile;
     constexpr int kMaskLoads = kWS / 64;
     // LDS rows (64 uint4 each) of a chunk: 16 octets of each bf16 plane, or
     // 16 hi octets and 8 lo units; each wave loads an equal share
-    constexpr int kChunkRows = LO8 ? kOct + kOct / 2 : 2 * kOct;
+    constexpr int kChunkRows = LO8 ? kOct + kOct / 2 : HI ? kOct : 2 * kOct;
     constexpr int kRowsW = kChunkRows / NW;
     static_assert(kRowsW * NW == kChunkRows, "waves split a chunk evenly");
-    static_assert(!(FOLD && LO8), "the fold runs on split BF16 only");
+    static_assert(!FOLD || MODE == kModeSplit, "the fold runs on split BF16 only");
+    static_assert(!IND || JB == 2, "the refinement skips blocks of 32 splits: 0, 1 or 2 per wave");
+    const int ntile_total = IND ? (int)*ntile_dev : ntile_arg;
     __shared__ uint4 zbuf[2][kChunkVec];
     __shared__ uint4 mbuf[2][kMaskVec];
     const int tid = threadIdx.x;
@@ -202,7 +216,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
         for (int k = 0; k < kMaskLoads; ++k) {
             const int r = t.b0 + wave * kWS + 64 * k + lane;
-            l_mload[k] = (const uint4*)mask_row(mask, bq, bq.mrow0 + (r < bq.nb ? r : 0), pd.Wp);
+            int64_t mrow;
+            if constexpr (IND) mrow = rlist[bq.mrow0 + (r < (int)rcnt[t.pair] ? r : 0)];
+            else mrow = bq.mrow0 + (r < bq.nb ? r : 0);
+            l_mload[k] = (const uint4*)mask_row(mask, bq, mrow, pd.Wp);
         }
     };
     l_setup();
@@ -256,7 +273,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
             brow[j] = t.b0 + wave * kWS + j * 32 + c;
-            keep[j] = brow[j] < bq.nb ? 0xffffffffu : 0u;
+            if constexpr (IND) {  // the listed split's row in the block (relative to the pair's first)
+                const bool in = brow[j] < (int)rcnt[t.pair];
+                keep[j] = in ? 0xffffffffu : 0u;
+                brow[j] = in ? (int)((int64_t)rlist[bq.mrow0 + brow[j]] - bq.mrow0) : 0;
+            } else {
+                keep[j] = brow[j] < bq.nb ? 0xffffffffu : 0u;
+            }
+        }
+        // REFINE: the wave's leading blocks of 32 splits that hold listed
+        // splits (wave-uniform, 0 to JB)
+        int jlive = JB;
+        if constexpr (IND) {
+            const int rem = (int)rcnt[t.pair] - (t.b0 + wave * kWS);
+            jlive = __builtin_amdgcn_readfirstlane(rem <= 0 ? 0 : rem >= kWS ? JB : (rem + 31) / 32);
         }
         f32x16 acc[2][JB];
 #pragma unroll
@@ -281,33 +311,44 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
                 };
                 mw[j] = make_uint4(prep(x.x), prep(x.y), prep(x.z), prep(x.w));
             }
-            auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[JB]) {
-                const int o = 2 * s + h;
+            // the bf16 products of the wave's first NJ blocks of 32 splits
+            auto products = [&](auto nj_) {
+                constexpr int NJ = decltype(nj_)::value;
+                auto fetch = [&](int s, bf16x8 (&a)[2][2], bf16x8 (&bm)[JB]) {
+                    const int o = 2 * s + h;
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
-                    if (!LO8) a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
-                }
-                const uint32_t kBit = 0x00800080u << (4 * (s & 1));
+                    for (int i = 0; i < 2; ++i) {
+                        a[0][i] = as_bf16x8(cur[o * kDSlot + 32 * i + c]);
+                        if (!LO8 && !HI) a[1][i] = as_bf16x8(cur[(kOct + o) * kDSlot + 32 * i + c]);
+                    }
+                    const uint32_t kBit = 0x00800080u << (4 * (s & 1));
 #pragma unroll
-                for (int j = 0; j < JB; ++j) {
-                    const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
-                    bm[j] = as_bf16x8(make_uint4(word & kBit, word & (kBit << 1), word & (kBit << 2), word & (kBit << 3)));
+                    for (int j = 0; j < NJ; ++j) {
+                        const uint32_t word = s < 2 ? mw[j].x : s < 4 ? mw[j].y : s < 6 ? mw[j].z : mw[j].w;
+                        bm[j] = as_bf16x8(make_uint4(word & kBit, word & (kBit << 1), word & (kBit << 2),
+                                                     word & (kBit << 3)));
+                    }
+                };
+                bf16x8 a[2][2][2], bm[2][JB];
+                fetch(0, a[0], bm[0]);
+#pragma unroll
+                for (int s = 0; s < kChunk / 16; ++s) {
+                    if (s + 1 < kChunk / 16) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
+#pragma unroll
+                    for (int pl = 0; pl < (LO8 || HI ? 1 : 2); ++pl)
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+#pragma unroll
+                            for (int j = 0; j < NJ; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s & 1][pl][i], bm[s & 1][j],
+                                                                                    acc[i][j], 0, 0, 0);
                 }
             };
-            bf16x8 a[2][2][2], bm[2][JB];
-            fetch(0, a[0], bm[0]);
-#pragma unroll
-            for (int s = 0; s < kChunk / 16; ++s) {
-                if (s + 1 < kChunk / 16) fetch(s + 1, a[(s + 1) & 1], bm[(s + 1) & 1]);
-#pragma unroll
-                for (int pl = 0; pl < (LO8 ? 1 : 2); ++pl)
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-#pragma unroll
-                        for (int j = 0; j < JB; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s & 1][pl][i], bm[s & 1][j],
-                                                                                acc[i][j], 0, 0, 0);
+            if constexpr (IND) {  // blocks past the pair's list have no split to multiply
+                if (jlive == JB) products(std::integral_constant<int, JB>{});
+                else if (jlive > 0) products(std::integral_constant<int, 1>{});
+            } else {
+                products(std::integral_constant<int, JB>{});
             }
             if constexpr (LO8) {
                 // the lo plane: two 64-row K-steps; group g = 2 s2 + h of the
@@ -763,35 +804,47 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            int ntw, int ng256, int nt256, int d_pad, const void* zstore,
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig, hipStream_t s,
-                           int grid_wide, int grid_narrow, const float* v32, double* pv) {
+                           int grid_wide, int grid_narrow, const float* v32, double* pv, bool hi_only) {
     const int nslot = d_pad / kDSlot;
     if (grid_wide <= 0) grid_wide = 16;
     if (grid_narrow <= 0) grid_narrow = precision == HBT_I8X3 ? 16 : 32;
     dim3 block(256);
+    if (hi_only && (precision != HBT_BF16X2 || pv)) return hipErrorInvalidValue;
     switch (precision) {
         case HBT_BF16X2: {
             const uint4* zhi = (const uint4*)zstore;
             const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
             static_assert(32 * 4 * 8 == kTileWide && 32 * 2 * 4 == kTileNarrow, "tile widths");
+            if (hi_only) {
+                if (ntw > 0)
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, kModeHi>), dim3(persistent_grid(ntw, grid_wide)),
+                                       dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
+                                       t32, partial, prow, sig, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr);
+                if (nt256 > 0)
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, kModeHi>), dim3(persistent_grid(nt256, grid_narrow)),
+                                       block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
+                                       mask, t32, partial, prow, sig, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr);
+                break;
+            }
             if (ntw > 0) {
                 if (pv)
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, true, false>), dim3(persistent_grid(ntw, grid_wide)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, true, kModeSplit>), dim3(persistent_grid(ntw, grid_wide)),
                                        dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
-                                       t32, partial, prow, sig, v32, pv, 0, 0);
+                                       t32, partial, prow, sig, v32, pv, 0, 0, nullptr, nullptr, nullptr);
                 else
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, false>), dim3(persistent_grid(ntw, grid_wide)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, kModeSplit>), dim3(persistent_grid(ntw, grid_wide)),
                                        dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
-                                       t32, partial, prow, sig, nullptr, nullptr, 0, 0);
+                                       t32, partial, prow, sig, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr);
             }
             if (nt256 > 0) {
                 if (pv)
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, true, false>), dim3(persistent_grid(nt256, grid_narrow)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, true, kModeSplit>), dim3(persistent_grid(nt256, grid_narrow)),
                                        block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                       mask, t32, partial, prow, sig, v32, pv, 0, 0);
+                                       mask, t32, partial, prow, sig, v32, pv, 0, 0, nullptr, nullptr, nullptr);
                 else
-                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, false>), dim3(persistent_grid(nt256, grid_narrow)),
+                    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, kModeSplit>), dim3(persistent_grid(nt256, grid_narrow)),
                                        block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                       mask, t32, partial, prow, sig, nullptr, nullptr, 0, 0);
+                                       mask, t32, partial, prow, sig, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr);
             }
             break;
         }
@@ -802,13 +855,13 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
             const uint4* zlo = (const uint4*)((const char*)zstore + 2 * zplane_elems);
             const int sa = 127 - kE4m3LoShift, sb = 127 + 9;  // E8M0: 2^-17 on lo, 2^9 on the 0x01 mask bytes
             if (ntw > 0)
-                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, true>), dim3(persistent_grid(ntw, grid_wide)),
+                hipLaunchKernelGGL((k_groupsum_bf16x2<4, 8, false, kModeLo8>), dim3(persistent_grid(ntw, grid_wide)),
                                    dim3(512), 0, s, pairs, bp, groups, ngw, ntw, nslot, d_pad, zhi, zlo, mask,
-                                   t32, partial, prow, sig, nullptr, nullptr, sa, sb);
+                                   t32, partial, prow, sig, nullptr, nullptr, sa, sb, nullptr, nullptr, nullptr);
             if (nt256 > 0)
-                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, true>), dim3(persistent_grid(nt256, grid_narrow)),
+                hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, kModeLo8>), dim3(persistent_grid(nt256, grid_narrow)),
                                    block, 0, s, pairs, bp, groups + ngw, ng256, nt256, nslot, d_pad, zhi, zlo,
-                                   mask, t32, partial, prow, sig, nullptr, nullptr, sa, sb);
+                                   mask, t32, partial, prow, sig, nullptr, nullptr, sa, sb, nullptr, nullptr, nullptr);
             break;
         }
         case HBT_I8X3:
@@ -830,6 +883,70 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                                partial, prow, sig);
             break;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The lazy precision's second pass.  Tile table: group g of the product's
+// table (one per pair, longest pair first) gets ceil(rcnt / 256) b-tiles of
+// the listed splits per column slot, tile0 the running sum; one work-group
+// scans the groups 256 at a time and writes the total to ntile.  (Tiles of
+// kTileWide splits for pairs with long lists were measured slower: each
+// refinement tile is a chain of chunk loads with few products per chunk, so
+// the number of tiles in flight matters more than the Z reads they save.)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_refine_tiles(const GemmGroup* __restrict__ groups, int ngroups,
+                                                      const uint32_t* __restrict__ rcnt, int nslot,
+                                                      GemmGroup* __restrict__ out, int64_t* __restrict__ ntile) {
+    __shared__ int64_t sh[256];
+    const int t = threadIdx.x;
+    int64_t base = 0;
+    for (int g0 = 0; g0 < ngroups; g0 += 256) {
+        const int g = g0 + t;
+        int pair = 0, nbt = 0;
+        if (g < ngroups) {
+            pair = groups[g].pair;
+            nbt = (int)((rcnt[pair] + kTileNarrow - 1) / kTileNarrow);
+        }
+        const int64_t tiles = (int64_t)nbt * nslot;
+        sh[t] = tiles;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
+            const int64_t v = t >= o ? sh[t - o] : 0;
+            __syncthreads();
+            sh[t] += v;
+            __syncthreads();
+        }
+        if (g < ngroups) out[g] = GemmGroup{pair, nbt, base + sh[t] - tiles};
+        base += sh[255];
+        __syncthreads();  // every thread has read sh[255] before the next chunk writes sh
+    }
+    if (t == 0) *ntile = base;
+}
+
+hipError_t launch_refine_tiles(const GemmGroup* groups, int ngroups, const uint32_t* rcnt, int d_pad,
+                               GemmGroup* out, int64_t* ntile, hipStream_t s) {
+    if (ngroups <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_refine_tiles, dim3(1), dim3(256), 0, s, groups, ngroups, rcnt, d_pad / kDSlot, out,
+                       ntile);
+    return hipGetLastError();
+}
+
+hipError_t launch_groupsum_refine(const PairDesc* pairs, const BlockPair* bp, const GemmGroup* rgroups,
+                                  int ngroups, const int64_t* ntile, int d_pad, const void* zstore,
+                                  int64_t zplane_elems, const uint32_t* mask, const float* t32, double* partial,
+                                  int64_t prow, const uint32_t* rlist, const uint32_t* rcnt, int grid_narrow,
+                                  hipStream_t s) {
+    if (ngroups <= 0) return hipErrorInvalidValue;
+    if (grid_narrow <= 0) grid_narrow = 32;
+    const uint4* zhi = (const uint4*)zstore;
+    const uint4* zlo = (const uint4*)zstore + zplane_elems / 8;
+    // the tile count is known on the device only: a full persistent grid,
+    // whose work-groups without a tile return at once
+    const unsigned grid = (unsigned)((device_cus() * grid_narrow + 31) / 32 * 32);
+    hipLaunchKernelGGL((k_groupsum_bf16x2<2, 4, false, kModeRefine>), dim3(grid), dim3(256), 0, s, pairs, bp,
+                       rgroups, ngroups, 0, d_pad / kDSlot, d_pad, zhi, zlo, mask, t32, partial, prow, nullptr,
+                       nullptr, nullptr, 0, 0, rlist, rcnt, ntile);
     return hipGetLastError();
 }
 

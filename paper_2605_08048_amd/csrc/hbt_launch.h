@@ -109,12 +109,32 @@ hipError_t launch_groupsum(int precision, const PairDesc* pairs, const BlockPair
                            int64_t zplane_elems, const uint32_t* mask, const float* t32,
                            const double* t64, double* partial, int64_t prow, float* sig,
                            hipStream_t s, int grid_wide = 16, int grid_narrow = 0,
-                           const float* v32 = nullptr, double* pv = nullptr);
+                           const float* v32 = nullptr, double* pv = nullptr, bool hi_only = false);
 // grid_wide / grid_narrow: persistent work-groups per CU of the 1024-split
 // launch and of the 256-split (or int8) launch (0: 32 for the 256-split
 // split-BF16 kernel, 16 for int8).  pv (split BF16 only, nullable): also
 // v . sigma per split and slot (v32 the pairs' FP32 Householder vectors),
-// for pairs whose rows are stored unreflected.
+// for pairs whose rows are stored unreflected.  hi_only (split BF16, no pv):
+// the products of the hi plane alone (the lazy precision's first pass).
+
+// The lazy precision's second pass: rlist holds, for each pair p, rcnt[p]
+// split rows from rlist[mrow0 of p] (the splits its first pass could not
+// decide).  launch_refine_tiles builds their 256-split tile table (one group
+// per entry of `groups`, the first pass's table, in its order) and the tile
+// count on the device; launch_groupsum_refine runs the split-BF16 product on
+// those splits and writes their partial rows in place.
+hipError_t launch_refine_tiles(const GemmGroup* groups, int ngroups, const uint32_t* rcnt, int d_pad,
+                               GemmGroup* out, int64_t* ntile, hipStream_t s);
+hipError_t launch_groupsum_refine(const PairDesc* pairs, const BlockPair* bp, const GemmGroup* rgroups,
+                                  int ngroups, const int64_t* ntile, int d_pad, const void* zstore,
+                                  int64_t zplane_elems, const uint32_t* mask, const float* t32, double* partial,
+                                  int64_t prow, const uint32_t* rlist, const uint32_t* rcnt, int grid_narrow,
+                                  hipStream_t s);
+hipError_t launch_groupsum_refine(const PairDesc* pairs, const BlockPair* bp, const GemmGroup* rgroups,
+                                  int ngroups, const int64_t* ntile, int d_pad, const void* zstore,
+                                  int64_t zplane_elems, const uint32_t* mask, const float* t32, double* partial,
+                                  int64_t prow, const uint32_t* rlist, const uint32_t* rcnt, int grid_wide,
+                                  int grid_narrow, hipStream_t s);
 
 // --- point-to-centroid route (statistic route 2) -------------------------
 // z_i . t per pooled row; then Q = Z S^T with the masked column sums
@@ -145,6 +165,17 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
 // a first kernel writes each split's fold sums per segment into fpart
 // (fold_segs x rows doubles, segment-major; fold_segs = the largest pair's
 // fold_segments(n)), which the statistic kernel adds in segment order.
+// The lazy precision's statistic.  First pass (refined = false), on the hi
+// plane's sums: splits within `band` of the threshold, NaN, or of a pair with
+// min(n, m) < kLazyMinGroup go to their pair's list (rlist / rcnt, zeroed
+// counts) and are not counted; the others are decided.  Second pass (refined
+// = true), on the listed splits' split-BF16 sums: decided, or flagged for the
+// FP64 recheck.  Tw holds each split's latest T_b.
+constexpr int kLazyMinGroup = 16;
+hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
+                            const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
+                            int alternative, const RecheckBand& band, int no_recheck, double* Tw, PairCount* cnt,
+                            uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s);
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
 // doubles of per-wave segment sums (nullptr: every flag done whole by one
 // work-group); the value of each flag's sums does not depend on it.

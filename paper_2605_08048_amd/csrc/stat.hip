@@ -91,6 +91,15 @@ void k_fold_c(const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ 
     if (active) fpart[(int64_t)seg * rows + row] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// MODE kStatLazyFirst (the lazy precision's first pass, hi-plane sums): a
+// split whose T_b lies within the band, is NaN, or belongs to a pair with
+// min(n, m) < kLazyMinGroup joins its pair's refinement list (rlist from the
+// pair's first row, rcnt the length) instead of being decided.  MODE
+// kStatRefined: thread i takes list entry i (entry k of pair p is thread
+// mrow0 of p + k, for k < rcnt[p]) and decides that split from its
+// split-BF16 sums, with the usual FP64-recheck flags.
+enum StatMode { kStatPlain = 0, kStatLazyFirst = 1, kStatRefined = 2 };
+template <int MODE>
 __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs,
                                               const BlockPair* __restrict__ bp, int npairs,
                                               int64_t rows, const PairState* __restrict__ st,
@@ -101,15 +110,23 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
                                               int T_mode, double* __restrict__ Tw,
                                               PairCount* cnt, uint32_t* flags, uint32_t* nflag,
                                               const double* __restrict__ pv,
-                                              const double* __restrict__ fpart) {
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool active = row < rows;
+                                              const double* __restrict__ fpart,
+                                              uint32_t* __restrict__ rlist, uint32_t* __restrict__ rcnt) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool in_range = i < rows;
     int p = 0;
     bool exceed = false;
-    if (active) p = upper_index(npairs, row, [&](int k) { return bp[k].mrow0; });
-    // a wave's first lane is active whenever any of its lanes is
+    if (in_range) p = upper_index(npairs, i, [&](int k) { return bp[k].mrow0; });
+    // a wave's first lane is in range whenever any of its lanes is
     const int p0 = __shfl(p, 0, 64);
-    const bool one_pair = __ballot(!active || p == p0) == ~0ull;
+    bool active = in_range;
+    bool refine = false;  // kStatLazyFirst: the split goes to its pair's list
+    int64_t row = i;
+    if (MODE == kStatRefined && in_range) {
+        active = i - bp[p].mrow0 < (int64_t)rcnt[p];
+        if (active) row = rlist[i];
+    }
+    const bool one_pair = __ballot(!in_range || p == p0) == ~0ull;
     if (active) {
         const PairDesc pd = pairs[p];
         const PairState q = st[p];
@@ -162,12 +179,30 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
         const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
         const double eps = recheck_eps(band, n, m, dd, r1, r2, gd);
         const bool nan = T != T;
-        const bool border = !no_recheck && !nan && fabs(val - thr) <= eps;
-        if (border) {
-            const uint32_t k = atomicAdd(nflag, 1u);
-            flags[k] = (uint32_t)row;
+        if (MODE == kStatLazyFirst) {
+            refine = nan || fabs(val - thr) <= eps || (pd.n < pd.m ? pd.n : pd.m) < kLazyMinGroup;
+            if (!refine) exceed = val >= thr;
         } else {
-            exceed = nan || val >= thr;
+            const bool border = !no_recheck && !nan && fabs(val - thr) <= eps;
+            if (border) {
+                const uint32_t k = atomicAdd(nflag, 1u);
+                flags[k] = (uint32_t)row;
+            } else {
+                exceed = nan || val >= thr;
+            }
+        }
+    }
+    if (MODE == kStatLazyFirst) {
+        // list appends: one atomic per wave when all its rows belong to one pair
+        const uint64_t rm = __ballot(refine);
+        if (one_pair) {
+            uint32_t base = 0;
+            if (lane_id() == 0 && rm) base = atomicAdd(&rcnt[p0], (uint32_t)__popcll(rm));
+            base = (uint32_t)__shfl((int)base, 0, 64);
+            if (refine) rlist[bp[p0].mrow0 + base + mbcnt64(rm)] = (uint32_t)row;
+        } else if (refine) {
+            const uint32_t k = atomicAdd(&rcnt[p], 1u);
+            rlist[bp[p].mrow0 + k] = (uint32_t)row;
         }
     }
     // count: one atomic per wave when all its rows belong to one pair
@@ -192,8 +227,27 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
         hipLaunchKernelGGL(k_fold_c, dim3(grid.x, (unsigned)fold_segs), dim3(256), 0, s, pairs, bp, npairs,
                            rows, mask, coef, fpart);
     }
-    hipLaunchKernelGGL(k_stat, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial, nslot, prow, d,
-                       gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag, pv, fpart);
+    hipLaunchKernelGGL(k_stat<kStatPlain>, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial, nslot,
+                       prow, d, gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag, pv, fpart,
+                       nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
+                            const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
+                            int alternative, const RecheckBand& band, int no_recheck, double* Tw, PairCount* cnt,
+                            uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    if (!rlist || !rcnt) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((rows + 255) / 256));
+    if (refined)
+        hipLaunchKernelGGL(k_stat<kStatRefined>, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial,
+                           nslot, prow, d, gd, alternative, band, no_recheck, nullptr, 0, Tw, cnt, flags, nflag,
+                           nullptr, nullptr, rlist, rcnt);
+    else
+        hipLaunchKernelGGL(k_stat<kStatLazyFirst>, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial,
+                           nslot, prow, d, gd, alternative, band, no_recheck, nullptr, 0, Tw, cnt, flags, nflag,
+                           nullptr, nullptr, rlist, rcnt);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = Path(os.environ.get("HBT_LIBRARY") or Path(__file__).resolve().parent
 
 OK, ERR_ARG, ERR_SIZE, ERR_DTYPE, ERR_WORKSPACE, ERR_DEGENERATE, ERR_MASK, ERR_DEVICE, \
     ERR_UNSUPPORTED, ERR_INTERNAL, ERR_NOT_UNIT = range(11)
-PRECISION = {"f64": 0, "f32": 1, "bf16x2": 2, "i8x3": 3, "bf16e4m3": 4}
+PRECISION = {"f64": 0, "f32": 1, "bf16x2": 2, "i8x3": 3, "bf16e4m3": 4, "bf16lazy": 5}
 DTYPE = {"f32": 0, "f64": 1}
 GD = {"banerjee": 0, "identity": 1}
 ALT = {"greater": 0, "two-sided": 1}

@@ -185,11 +185,29 @@ def test_batched_validation():
     st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                  FAKE, need, None)
     assert st == hbt.ERR_WORKSPACE
-    for prec in ("i8x3", "bf16e4m3"):  # route 0 only
+    for prec in ("i8x3", "bf16e4m3", "bf16lazy"):  # route 0 only
         prm.precision = hbt.PRECISION[prec]
         st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
                                      FAKE, need2, None)
         assert st == hbt.ERR_UNSUPPORTED, prec
+    # the lazy precision stores as split BF16 and adds its refinement lists
+    prm.stat_route = 0
+    prm.precision = hbt.PRECISION["bf16lazy"]
+    need_lazy = L.hbt_perm_test_batched_workspace_size(P, ptr(n), ptr(m), ptr(B), 8, C.byref(prm))
+    assert need_lazy > need
+    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8, C.byref(prm), FAKE,
+                                 FAKE, need, None)
+    assert st == hbt.ERR_WORKSPACE
+
+
+def test_lazy_precision_is_batched_only():
+    """The lazy split-BF16 precision runs in the batched call only: the
+    single-pair call refuses it before anything is enqueued, and reports no
+    workspace size for it."""
+    prm = hbt.make_params(10, 12, 8, 10, precision="bf16lazy")
+    assert hbt.lib().hbt_perm_test_workspace_size(C.byref(prm)) == 0
+    assert _call(prm) == hbt.ERR_UNSUPPORTED
+    assert b"batched" in hbt.lib().hbt_last_error()
 
 
 def test_clouds_validation():
@@ -213,7 +231,7 @@ def test_clouds_validation():
     assert call(prm, px=np.array([0, 3], dtype=np.int64)) == hbt.ERR_ARG
     assert call(prm, rows=np.array([40, 1, 33], dtype=np.int64)) == hbt.ERR_SIZE
     assert call(prm, d=66) == hbt.ERR_UNSUPPORTED
-    for prec in ("f32", "i8x3", "bf16e4m3"):
+    for prec in ("f32", "i8x3", "bf16e4m3", "bf16lazy"):
         assert call(hbt.make_params(0, 0, 64, 0, precision=prec)) == hbt.ERR_UNSUPPORTED
     assert call(hbt.make_params(0, 0, 64, 0, precision="bf16x2", stat_route=1)) == hbt.ERR_UNSUPPORTED
 

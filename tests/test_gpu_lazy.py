@@ -1,0 +1,125 @@
+"""GPU: the lazy split-BF16 precision (HBT_BF16_LAZY) of the batched call.
+
+Its first product multiplies the hi plane alone; the splits whose T_b it
+cannot decide (within the hi plane's error band of the threshold, NaN, or in
+a pair with a group under 16 items) get the split-BF16 product, then the FP64
+recheck.  So:
+  * counts and p equal the FP64 oracle's (as for every precision) and the
+    split-BF16 call's, and so does n_recheck (the splits inside the
+    split-BF16 band lie far inside the hi band);
+  * in a pair with a group under 16 items every split is refined, so even
+    t_mean and t_sd equal the split-BF16 call's bit for bit;
+  * elsewhere the null moments carry the hi plane's error, held here to
+    5e-4 of |f(r1)| + |f(r2)| (the emulated hi-plane error of T_b stays
+    under 1e-4 of it on such clouds);
+  * results do not depend on the order in which the refinement lists fill,
+    nor on the pipeline chunks.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_08048_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from paper_2605_08048_amd import hbt  # noqa: E402
+
+DEV = "cuda:0"
+TOL_MOMENTS = 5e-4
+
+
+def _pair(n, m, d, kx, ky, seed):
+    g = np.random.default_rng([17, seed])
+    mu = synth.random_unit(g, d)
+    mv = synth.direction_at_angle(g, mu, 40.0)
+    X = synth.unit_rows(kx * mu + g.standard_normal((n, d)) / math.sqrt(d)).astype(np.float32)
+    Y = synth.unit_rows(ky * mv + g.standard_normal((m, d)) / math.sqrt(d)).astype(np.float32)
+    return X, Y
+
+
+def _run(bt, prec, **kw):
+    return hbt.perm_test_batched(torch.from_numpy(bt.Z).to(DEV), bt.row_offset, bt.n, bt.m, bt.B,
+                                 pair_index=bt.pair_index, precision=prec, **kw)
+
+
+def _equal(a, b, fields):
+    for f in fields:
+        assert np.array_equal(a[f], b[f]), f
+
+
+# n, m, kappa_x, kappa_y: null pairs (equal kappa) put many splits near T_obs
+SIZES = [(5, 300, 2.0, 2.0), (300, 9, 2.0, 2.4), (15, 15, 2.0, 2.0), (16, 400, 2.0, 2.0), (40, 60, 2.0, 2.4),
+         (700, 650, 2.0, 2.0), (1000, 1048, 2.0, 2.1), (2000, 1500, 2.0, 2.0), (130, 3000, 1.6, 1.6)]
+
+
+@pytest.mark.parametrize("alternative,gd", [("greater", "banerjee"), ("two-sided", "identity")])
+def test_lazy_counts_equal_oracle_and_split_bf16(alternative, gd):
+    d, B, seed = 192, 700, 31
+    pairs = [synth.Pair(*_pair(n, m, d, kx, ky, 40 + k), B=B, pair_index=k) for k, (n, m, kx, ky) in enumerate(SIZES)]
+    bt = synth.pack_batch(pairs, d)
+    print(f"lazy vs split BF16 and the oracle: {len(pairs)} pairs, d={d}, B={B}, {alternative}, {gd}", flush=True)
+    lz = _run(bt, "bf16lazy", seed=seed, alternative=alternative, gd=gd)
+    sb = _run(bt, "bf16x2", seed=seed, alternative=alternative, gd=gd)
+    assert np.all(lz["status"] == 0)
+    _equal(lz, sb, ["count", "p", "n_recheck", "B", "t_obs", "r_x", "r_y"])
+    two = alternative == "two-sided"
+    for p, pr in enumerate(pairs):
+        n, m = pr.X.shape[0], pr.Y.shape[0]
+        o = O.perm_test(pr.X, pr.Y, B, seed=seed, pair=pr.pair_index, want_T=True,
+                        alternative=O.ALT_TWO_SIDED if two else O.ALT_GREATER,
+                        gd=O.GD_IDENTITY if gd == "identity" else O.GD_BANERJEE)
+        tie = int(np.sum(np.abs(np.abs(o["T"]) - abs(o["t_obs"]) if two else o["T"] - o["t_obs"])
+                         <= 1e-6 * abs(o["t_obs"])))
+        assert abs(lz[p]["count"] - o["count"]) <= tie, (p, lz[p]["count"], o["count"])
+        if min(n, m) < 16:  # every split refined: the split-BF16 values throughout
+            assert lz[p]["t_mean"] == sb[p]["t_mean"] and lz[p]["t_sd"] == sb[p]["t_sd"], p
+        else:
+            at = O.perm_stats_at(pr.X, pr.Y, np.arange(B), seed=seed, pair=pr.pair_index,
+                                 gd=O.GD_IDENTITY if gd == "identity" else O.GD_BANERJEE)
+            f = (lambda r: np.log(r * (d - r * r) / (1 - r * r))) if gd == "banerjee" else np.log
+            scale = np.max(np.abs(f(at["r1"])) + np.abs(f(at["r2"])))
+            assert abs(lz[p]["t_mean"] - o["T"].mean()) <= TOL_MOMENTS * scale, p
+            assert abs(lz[p]["t_sd"] - o["T"].std()) <= 2 * TOL_MOMENTS * scale, p
+
+
+def test_lazy_on_benchmark_pairs():
+    """96 pairs of the 512-pair workload (d = 768, B = 2000): counts, p and
+    n_recheck equal to the split-BF16 call's on every pair, and to the
+    oracle's on four of them."""
+    b = synth.batch_512_d768(limit=range(96))
+    print(f"lazy on {b.npairs} pairs of the 512-pair workload", flush=True)
+    Z = torch.from_numpy(b.Z).to(DEV)
+    lz = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16lazy")
+    sb = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
+    assert np.all(lz["status"] == 0)
+    _equal(lz, sb, ["count", "p", "n_recheck", "B"])
+    for p in (0, 1, 2, 3):
+        pr = b.pair(p)
+        o = O.perm_test(pr.X, pr.Y, pr.B, seed=b.seed, pair=pr.pair_index, want_T=True)
+        tie = int(np.sum(np.abs(o["T"] - o["t_obs"]) <= 1e-6 * abs(o["t_obs"])))
+        assert abs(lz[p]["count"] - o["count"]) <= tie, p
+
+
+def test_lazy_results_do_not_depend_on_list_order_or_pipeline():
+    """The refinement lists fill in whatever order the statistic's atomics
+    take; each listed split's sums come from the same instructions wherever
+    it sits in a tile, so repeated calls agree bit for bit, and so does the
+    call pipelined over chunks of pairs."""
+    b = synth.batch_512_d768(limit=range(60))
+    print("lazy: repeat and pipeline chunks on 60 pairs", flush=True)
+    Z = torch.from_numpy(b.Z).to(DEV)
+    fields = ["t_obs", "r_x", "r_y", "p", "t_mean", "t_sd", "count", "B", "n_recheck", "status"]
+    ref = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16lazy")
+    again = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16lazy")
+    _equal(again, ref, fields)
+    prev = hbt.pipeline_chunks(3)
+    try:
+        piped = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16lazy")
+    finally:
+        hbt.pipeline_chunks(prev)
+    _equal(piped, ref, fields)

@@ -6,7 +6,8 @@ library's band (hbt_recheck_band) of the threshold, so the band must cover
 side without a recheck.  Here the rows are stored as the kernels store them
 (FP32; split BF16 hi = bf16(z), lo = bf16(z - hi), both round-to-nearest-even
 from the FP32 row; BF16 + e4m3 the same hi and lo = e4m3(2^17 (z - hi)) 2^-17,
-nearest-even; int8 digits of round(z 2^20) from the FP64 row) and the
+nearest-even; int8 digits of round(z 2^20) from the FP64 row; the lazy
+precision's first pass the hi plane alone) and the
 group sums are formed exactly in FP64, which isolates the storage error
 (the accumulation error is the band's e_acc, checked on the GPU).
 
@@ -48,6 +49,8 @@ def _stored(Z, prec):
     if prec == "f32":
         return zf.astype(np.float64)
     hi = _bf16(zf)
+    if prec == "bf16lazy":  # the lazy precision's first pass: the hi plane alone
+        return hi.astype(np.float64)
     if prec == "bf16e4m3":
         lo = (zf - hi).astype(np.float64)            # exact in FP32
         return hi.astype(np.float64) + _e4m3(lo * 2.0 ** 17) / 2.0 ** 17
@@ -100,7 +103,10 @@ def _worst_ratio(n, m, d, kx, ky, rep, B, seed=0):
 
     r1, r2, T64 = stat(Z)
     out = {}
-    for prec in ("f32", "bf16x2", "i8x3", "bf16e4m3"):
+    # the lazy precision's first pass decides nothing for pairs with a group
+    # under 16 items (every split goes to the split-BF16 product)
+    lazy = ("bf16lazy",) if min(n, m) >= 16 else ()
+    for prec in ("f32", "bf16x2", "i8x3", "bf16e4m3") + lazy:
         T = stat(_stored(Z, prec))[2]
         eps = hbt.recheck_band(prec, n, m, d, r1, r2)
         out[prec] = float((np.abs(T - T64) / eps).max())
@@ -125,6 +131,9 @@ CASES = [
     (900, 1100, 768, 30.0, 30.0, 300, 200),    # r ~ 0.9995, repeated rows
     (2, 2000, 768, 0.05, 0.05, 1, 300),        # a group of 2 in a diffuse cloud
     (100, 100, 64, 8.0, 8.0, 50, 100),
+    (16, 300, 64, 8.0, 8.0, 1, 300),           # the smallest groups the lazy first pass decides
+    (300, 16, 64, 0.05, 0.05, 1, 300),
+    (16, 16, 64, 8.0, 8.0, 1, 300),
 ]
 SEEDS = {1: [0], 10: [0]}  # repeated rows: the worst case depends on which rows repeat
 
