@@ -523,33 +523,37 @@ def test_batch_512_d768_full_size_sampled_pairs():
 
 # --------------------------------------------------------------------- graph capture
 
-def test_batched_call_replays_from_a_hip_graph():
+@pytest.mark.parametrize("prec", ["bf16x2", "bf16lazy"])
+def test_batched_call_replays_from_a_hip_graph(prec):
     """The batched call enqueues only kernels on the caller's stream (tables go
     in as kernel arguments, no memset, no allocation, no synchronisation), so
     it can be captured once and replayed.  Every replay, with eager calls that
-    reuse the same workspace in between, must reproduce the eager results."""
-    print("graph capture: 12 pairs of the 512-pair workload", flush=True)
+    reuse the same workspace in between, must reproduce the eager results.
+    (The lazy precision's refinement lists and tile table are built on the
+    device each call, its counters cleared by a fill kernel.)"""
+    print(f"graph capture {prec}: 12 pairs of the 512-pair workload", flush=True)
     b = synth.batch_512_d768(limit=range(12))
     Z = _dev(b.Z)
     args = (Z, b.row_offset, b.n, b.m, b.B)
-    ref = hbt.perm_test_batched(*args, seed=b.seed, precision="bf16x2")
-    need = hbt.batched_workspace_size(b.row_offset, b.n, b.m, b.B, b.d, precision="bf16x2")
+    ref = hbt.perm_test_batched(*args, seed=b.seed, precision=prec)
+    need = hbt.batched_workspace_size(b.row_offset, b.n, b.m, b.B, b.d, precision=prec)
     ws = torch.empty(need, dtype=torch.uint8, device=DEV)
     res = torch.zeros(hbt.RESULT_BYTES * b.npairs, dtype=torch.uint8, device=DEV)
-    hbt.perm_test_batched(*args, seed=b.seed, precision="bf16x2", sync=False, results=res, workspace=ws)
+    hbt.perm_test_batched(*args, seed=b.seed, precision=prec, sync=False, results=res, workspace=ws)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        hbt.perm_test_batched(*args, seed=b.seed, precision="bf16x2", sync=False, results=res, workspace=ws)
+        hbt.perm_test_batched(*args, seed=b.seed, precision=prec, sync=False, results=res, workspace=ws)
+    fields = ["t_obs", "r_x", "r_y", "p", "t_mean", "t_sd", "count", "B", "n_recheck", "status"]
     for rep in range(3):
         res.zero_()
         g.replay()
         torch.cuda.synchronize()
         got = hbt.results_to_numpy(res)
-        for f in ["t_obs", "r_x", "r_y", "p", "count", "B", "n_recheck", "status"]:
+        for f in fields:
             assert np.array_equal(got[f], ref[f]), (rep, f)
         # eager work on the same workspace between replays (another seed)
-        other = hbt.perm_test_batched(*args, seed=b.seed + 1, precision="bf16x2", workspace=ws)
+        other = hbt.perm_test_batched(*args, seed=b.seed + 1, precision=prec, workspace=ws)
         assert np.all(other["status"] == 0)
 
 
