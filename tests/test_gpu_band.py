@@ -113,3 +113,32 @@ def test_repeated_rows_counts_match_oracle(prec):
         assert abs(res[j]["count"] - o["count"]) <= tie, (prec, k, res[j]["count"], o["count"])
         print(f"  pair {k}: count {res[j]['count']} (oracle {o['count']}), rechecked {res[j]['n_recheck']}",
               flush=True)
+
+
+def test_repeated_rows_counts_match_oracle_lazy():
+    """The lazy precision (batched call only) on the same clouds: its first
+    pass decides from the hi plane alone, whose rounding errors add up
+    coherently over repeated rows; counts must equal the oracle's and the
+    split-BF16 call's, pair by pair."""
+    B = 2000
+    for d in (768, 1024):
+        sel = [k for k, c in enumerate(REPEAT_CASES) if c[2] == d]
+        pairs = []
+        for k in sel:
+            n, m, _, kappa, rep = REPEAT_CASES[k]
+            X, Y = _pair(n, m, d, kappa, kappa, rep, seed=50 + k, angle=30.0)
+            pairs.append(synth.Pair(X, Y, B=B, pair_index=k))
+        bt = synth.pack_batch(pairs, d)
+        print(f"repeated rows lazy batched d={d}, {len(sel)} pairs", flush=True)
+        Z = _dev(bt.Z)
+        ids = np.array(sel, dtype=np.uint32)
+        lz = hbt.perm_test_batched(Z, bt.row_offset, bt.n, bt.m, bt.B, seed=3, pair_index=ids, precision="bf16lazy")
+        sb = hbt.perm_test_batched(Z, bt.row_offset, bt.n, bt.m, bt.B, seed=3, pair_index=ids, precision="bf16x2")
+        for j, pr in enumerate(pairs):
+            o = O.perm_test(pr.X, pr.Y, B, seed=3, pair=pr.pair_index, want_T=True)
+            tie = int(np.sum(np.abs(o["T"] - o["t_obs"]) <= 1e-6 * abs(o["t_obs"])))
+            assert lz[j]["status"] == 0
+            assert abs(lz[j]["count"] - o["count"]) <= tie, (d, j, lz[j]["count"], o["count"])
+            assert lz[j]["count"] == sb[j]["count"] and lz[j]["n_recheck"] == sb[j]["n_recheck"], (d, j)
+            print(f"  pair {pr.pair_index}: count {lz[j]['count']} (oracle {o['count']}), "
+                  f"rechecked {lz[j]['n_recheck']}", flush=True)

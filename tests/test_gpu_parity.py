@@ -24,7 +24,10 @@ pytestmark = [pytest.mark.gpu,
 from paper_2605_08048_amd import hbt  # noqa: E402
 
 DEV = "cuda:0"
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "i8x3": 1e-4, "bf16e4m3": 1e-4}
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "i8x3": 1e-4, "bf16e4m3": 1e-4,
+       # the lazy precision (batched call only): its T_b outside the hi plane's
+       # band carry the hi plane's error; its null moments are held to this
+       "bf16lazy": 5e-4}
 
 
 def _dev(a, dtype=None):
@@ -383,7 +386,7 @@ def test_batched_matches_oracle_per_pair():
         pairs.append(synth.Pair(X, Y, B=int(rng.integers(1, 700)), pair_index=p))
     pairs[3] = synth.Pair(pairs[3].X, pairs[3].X.copy(), B=300, pair_index=3)  # identical groups
     bt = synth.pack_batch(pairs, 96)
-    for prec in ["f32", "bf16x2", "f64", "i8x3", "bf16e4m3"]:
+    for prec in ["f32", "bf16x2", "f64", "i8x3", "bf16e4m3", "bf16lazy"]:
         res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=9, precision=prec)
         for p, pr in enumerate(pairs):
             o = O.perm_test(pr.X, pr.Y, pr.B, seed=9, pair=p, want_T=True)
@@ -412,7 +415,7 @@ def test_batched_storage_group_boundaries(d):
         X, Y = _pair(n, m, d, kx=2.0, ky=2.6, angle=50.0, seed=300 + p)
         pairs.append(synth.Pair(X, Y, B=257, pair_index=p))
     bt = synth.pack_batch(pairs, d)
-    for prec in ["bf16x2", "i8x3", "f32", "bf16e4m3"]:
+    for prec in ["bf16x2", "i8x3", "f32", "bf16e4m3", "bf16lazy"]:
         res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=4, precision=prec)
         for p, pr in enumerate(pairs):
             o = O.perm_test(pr.X, pr.Y, pr.B, seed=4, pair=p, want_T=True)
@@ -501,7 +504,7 @@ def test_batch_512_d768_full_size_sampled_pairs():
     Z = _dev(b.Z)
     hbt.tune_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed)
     res = {prec: hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision=prec)
-           for prec in ["bf16x2", "i8x3", "bf16e4m3"]}
+           for prec in ["bf16x2", "i8x3", "bf16e4m3", "bf16lazy"]}
     del Z
     order = np.argsort(b.n + b.m, kind="stable")
     P = b.npairs
@@ -597,7 +600,7 @@ def test_pairs_with_equal_sizes_and_index_share_their_splits():
         X, Y = _pair(n, m, d, kx=2.0, ky=2.3, angle=30.0, seed=500 + p)
         pairs.append(synth.Pair(X, Y, B=400, pair_index=k))
     bt = synth.pack_batch(pairs, d)
-    for prec in ["bf16x2", "f32", "i8x3"]:
+    for prec in ["bf16x2", "f32", "i8x3", "bf16lazy"]:
         res = hbt.perm_test_batched(_dev(bt.Z), bt.row_offset, bt.n, bt.m, bt.B, seed=11,
                                     pair_index=bt.pair_index, precision=prec)
         for p, pr in enumerate(pairs):
