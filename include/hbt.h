@@ -341,8 +341,9 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
  *   chunks      pipeline chunks of the batched call (default 1; see
  *               hbt_pipeline_chunks).
  * No result depends on any of them.
- *   hbt_tune_batched: measures them on the caller's workload (split BF16 or
- *     int8 planes, common->precision) with HIP events, every candidate
+ *   hbt_tune_batched: measures them on the caller's workload (split BF16,
+ *     BF16 + e4m3 or int8 planes, common->precision; the lazy split-BF16
+ *     precision uses the split-BF16 entry) with HIP events, every candidate
  *     twice keeping the faster: the widths (every pair forced to each;
  *     cost_w = product time / sum_p round_up(B_p, w) round_up(n_p + m_p,
  *     128)), then the grids of the launches the workload uses (wide 4, 8,
