@@ -440,7 +440,7 @@ def main():
             Y = torch.from_numpy(pair.Y).to(dev)
             row = {"n": pair.n, "m": pair.m, "d": pair.d, "B": pair.B}
             counts = {}
-            for prec in ("f32", "bf16x2", "i8x3", "bf16e4m3"):
+            for prec in ("f32", "bf16x2", "i8x3", "bf16e4m3", "bf16lazy"):
                 call = lambda: hbt.perm_test(X, Y, pair.B, seed=pair.seed, precision=prec, sync=False)
                 call()
                 torch.cuda.synchronize()

@@ -94,8 +94,8 @@ typedef enum hbt_precision {
                          planes, then the FP64 recheck as usual.  Counts and p
                          are those of the FP64 statistic, as for the other
                          precisions; T_b (and t_mean, t_sd) carry the hi plane's
-                         error outside the band.  hbt_perm_test_batched only
-                         (HBT_ERR_UNSUPPORTED elsewhere), route 0 */
+                         error outside the band.  hbt_perm_test,
+                         hbt_perm_test_static and hbt_perm_test_batched; route 0 */
 } hbt_precision;
 
 typedef enum hbt_dtype { HBT_IN_F32 = 0, HBT_IN_F64 = 1 } hbt_dtype;
@@ -185,7 +185,9 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
  *   result: one device hbt_result.
  *   T_out (nullable, device, B floats; B doubles with HBT_FLAG_T_OUT_F64;
  *     B x 3 doubles (T_b, |sigma_1|^2, |sigma_2|^2) with HBT_FLAG_T_OUT_NORMS):
- *     T_b as computed by the chosen precision (before any FP64 recheck).
+ *     T_b as computed by the chosen precision (before any FP64 recheck;
+ *     HBT_BF16_LAZY: by the hi plane, or by split BF16 for the splits its
+ *     first pass could not decide).
  *   mask_out (nullable, device, B x ceil((n+m)/32) words): the splits used.
  * Errors: as hbt_align, plus HBT_ERR_DTYPE and HBT_ERR_UNSUPPORTED. */
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm);

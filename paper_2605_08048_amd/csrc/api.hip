@@ -894,8 +894,8 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
 // ---------------------------------------------------------------------------
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm) {
     if (!prm || check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset) ||
-        prm->precision < HBT_F64 || prm->precision > HBT_BF16_E4M3) {
-        return 0;  // (the lazy precision is for the batched call only)
+        prm->precision < HBT_F64 || prm->precision > HBT_BF16_LAZY) {
+        return 0;
     }
     int64_t B0;
     Plan P = plan_single(prm, nullptr, nullptr, &B0);
@@ -911,8 +911,6 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     hbt_status st = check_sizes(prm->n, prm->m, prm->d, prm->B, prm->perm_offset);
     if (st) return st;
     if ((st = check_enums(prm))) return st;
-    if (prm->precision == HBT_BF16_LAZY)
-        return fail(HBT_ERR_UNSUPPORTED, "the lazy split-BF16 precision is for the batched call only");
     if (prm->block_perms < 0) return fail(HBT_ERR_ARG, "block_perms must be >= 0");
     int64_t B0;
     Plan P = plan_single(prm, X, Y, &B0);
@@ -1016,11 +1014,13 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         {
             StageTimer t_(HBT_STAGE_GROUPSUM, s);
             const int nt = grp.nbt * P.nslot;
+            if (P.lazy) HIP_TRY(zero(w.rcnt, 8, s));  // the block's refinement list
             // the wide segment, or the other one (the narrow split-BF16 width, int8 planes)
             HIP_TRY(launch_groupsum(P.precision, w.pairs, w.bp, w.tiles, ntiles, w.groups, wdt == kTileWide,
                                     wdt == kTileWide ? nt : 0, wdt != kTileWide, wdt != kTileWide ? nt : 0, P.d_pad,
                                     w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.t64, w.partial,
-                                    P.block_rows, w.sig, s, P.tune.grid_wide, P.tune.grid_narrow));
+                                    P.block_rows, w.sig, s, P.tune.grid_wide, P.tune.grid_narrow, nullptr, nullptr,
+                                    P.lazy));
         }
         if (P.route2) {
             StageTimer t_(HBT_STAGE_CENTROID, s);
@@ -1029,11 +1029,26 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
                                     z32, w.sig,
                                     w.mask, w.zt, w.partial2, P.block_rows, s));
         }
-        { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
+        void* T_blk = T_out ? (char*)T_out + b0 * t_size : nullptr;
+        if (P.lazy) {
+            // decide what the hi plane can, refine the rest with both planes
+            { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat_lazy(false, w.pairs, w.bp, 1, nb, w.st,
+                              w.partial, P.nslot, P.block_rows, P.d, prm->gd, prm->alternative,
+                              precision_band(HBT_BF16_LAZY, P.d, false), no_recheck, w.tw, w.cnt, w.flags,
+                              w.nflag, w.rlist, w.rcnt, s, T_blk, t_mode)); }
+            { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_refine_tiles(w.groups, 1, w.rcnt, P.d_pad,
+                              w.rgroups, w.rtiles, s)); }
+            { StageTimer t_(HBT_STAGE_GROUPSUM, s); HIP_TRY(launch_groupsum_refine(w.pairs, w.bp, w.rgroups, 1,
+                              w.rtiles, P.d_pad, w.zstore, P.zrows * P.d_pad, w.mask, w.t32, w.partial,
+                              P.block_rows, w.rlist, w.rcnt, P.tune.grid_narrow, s)); }
+            { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat_lazy(true, w.pairs, w.bp, 1, nb, w.st,
+                              w.partial, P.nslot, P.block_rows, P.d, prm->gd, prm->alternative,
+                              precision_band(HBT_BF16X2, P.d, false), no_recheck, w.tw, w.cnt, w.flags,
+                              w.nflag, w.rlist, w.rcnt, s, T_blk, t_mode)); }
+        } else { StageTimer t_(HBT_STAGE_STAT, s); HIP_TRY(launch_stat(w.pairs, w.bp, 1, nb, w.st,
                             P.route2 ? w.partial2 : w.partial, P.route2 ? 0 : P.nslot,
                             P.block_rows, P.d, prm->gd,
-                            prm->alternative, band, no_recheck,
-                            T_out ? (char*)T_out + b0 * t_size : nullptr, t_mode, w.tw,
+                            prm->alternative, band, no_recheck, T_blk, t_mode, w.tw,
                             w.cnt, w.flags, w.nflag, s)); }
         if (!no_recheck) {
             StageTimer t_(HBT_STAGE_RECHECK, s);

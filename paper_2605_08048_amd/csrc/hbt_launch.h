@@ -170,12 +170,14 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
 // min(n, m) < kLazyMinGroup go to their pair's list (rlist / rcnt, zeroed
 // counts) and are not counted; the others are decided.  Second pass (refined
 // = true), on the listed splits' split-BF16 sums: decided, or flagged for the
-// FP64 recheck.  Tw holds each split's latest T_b.
+// FP64 recheck.  Tw (and T_out, nullable, as in launch_stat) holds each
+// split's latest T_b.
 constexpr int kLazyMinGroup = 16;
 hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                             const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                             int alternative, const RecheckBand& band, int no_recheck, double* Tw, PairCount* cnt,
-                            uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s);
+                            uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s,
+                            void* T_out = nullptr, int T_mode = 0);
 // FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
 // doubles of per-wave segment sums (nullptr: every flag done whole by one
 // work-group); the value of each flag's sums does not depend on it.

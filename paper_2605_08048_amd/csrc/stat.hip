@@ -236,17 +236,18 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
 hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair* bp, int npairs, int64_t rows,
                             const PairState* st, const double* partial, int nslot, int64_t prow, int d, int gd,
                             int alternative, const RecheckBand& band, int no_recheck, double* Tw, PairCount* cnt,
-                            uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s) {
+                            uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s,
+                            void* T_out, int T_mode) {
     if (rows <= 0) return hipSuccess;
     if (!rlist || !rcnt) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((rows + 255) / 256));
     if (refined)
         hipLaunchKernelGGL(k_stat<kStatRefined>, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial,
-                           nslot, prow, d, gd, alternative, band, no_recheck, nullptr, 0, Tw, cnt, flags, nflag,
+                           nslot, prow, d, gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag,
                            nullptr, nullptr, rlist, rcnt);
     else
         hipLaunchKernelGGL(k_stat<kStatLazyFirst>, grid, dim3(256), 0, s, pairs, bp, npairs, rows, st, partial,
-                           nslot, prow, d, gd, alternative, band, no_recheck, nullptr, 0, Tw, cnt, flags, nflag,
+                           nslot, prow, d, gd, alternative, band, no_recheck, T_out, T_mode, Tw, cnt, flags, nflag,
                            nullptr, nullptr, rlist, rcnt);
     return hipGetLastError();
 }

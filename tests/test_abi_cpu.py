@@ -200,14 +200,15 @@ def test_batched_validation():
     assert st == hbt.ERR_WORKSPACE
 
 
-def test_lazy_precision_is_batched_only():
-    """The lazy split-BF16 precision runs in the batched call only: the
-    single-pair call refuses it before anything is enqueued, and reports no
-    workspace size for it."""
-    prm = hbt.make_params(10, 12, 8, 10, precision="bf16lazy")
-    assert hbt.lib().hbt_perm_test_workspace_size(C.byref(prm)) == 0
-    assert _call(prm) == hbt.ERR_UNSUPPORTED
-    assert b"batched" in hbt.lib().hbt_last_error()
+def test_lazy_precision_workspace_and_route():
+    """The lazy split-BF16 precision stores as split BF16 and adds its
+    refinement list, so the single-pair call needs a little more workspace;
+    the point-to-centroid route refuses it before anything is enqueued."""
+    L = hbt.lib()
+    lazy = hbt.make_params(300, 400, 64, 5000, precision="bf16lazy")
+    split = hbt.make_params(300, 400, 64, 5000, precision="bf16x2")
+    assert L.hbt_perm_test_workspace_size(C.byref(lazy)) > L.hbt_perm_test_workspace_size(C.byref(split)) > 0
+    assert _call(hbt.make_params(10, 12, 8, 10, precision="bf16lazy", stat_route=1)) == hbt.ERR_UNSUPPORTED
 
 
 def test_clouds_validation():

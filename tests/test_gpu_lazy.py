@@ -1,4 +1,4 @@
-"""GPU: the lazy split-BF16 precision (HBT_BF16_LAZY) of the batched call.
+"""GPU: the lazy split-BF16 precision (HBT_BF16_LAZY), batched and single-pair calls.
 
 Its first product multiplies the hi plane alone; the splits whose T_b it
 cannot decide (within the hi plane's error band of the threshold, NaN, or in
@@ -13,7 +13,10 @@ recheck.  So:
     5e-4 of |f(r1)| + |f(r2)| (the emulated hi-plane error of T_b stays
     under 1e-4 of it on such clouds);
   * results do not depend on the order in which the refinement lists fill,
-    nor on the pipeline chunks.
+    nor on the pipeline chunks, nor (single pair) on the split blocks;
+  * single pair: each T_b is either the split-BF16 call's, bit for bit (a
+    refined split), or the hi plane's, within 5e-4 of |f(r1)| + |f(r2)| of
+    the oracle's FP64 value.
 """
 import math
 
@@ -123,3 +126,40 @@ def test_lazy_results_do_not_depend_on_list_order_or_pipeline():
     finally:
         hbt.pipeline_chunks(prev)
     _equal(piped, ref, fields)
+
+
+def _scale(at, d):
+    f = lambda r: np.log(r * (d - r * r) / (1 - r * r))
+    return np.abs(f(at["r1"])) + np.abs(f(at["r2"]))
+
+
+@pytest.mark.parametrize("n,m,d,B,kx,ky", [(1500, 1200, 768, 6000, 2.0, 2.0), (9, 500, 256, 3000, 2.0, 2.0),
+                                            (700, 2100, 1024, 4000, 1.8, 2.2)])
+def test_lazy_single_pair(n, m, d, B, kx, ky):
+    print(f"lazy single pair n={n} m={m} d={d} B={B}", flush=True)
+    X, Y = _pair(n, m, d, kx, ky, seed=n + m)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    lz = hbt.perm_test(Xd, Yd, B, seed=13, precision="bf16lazy", want_T="f64")
+    sb = hbt.perm_test(Xd, Yd, B, seed=13, precision="bf16x2", want_T="f64")
+    assert lz["status"] == 0
+    for k in ["count", "p", "n_recheck", "t_obs", "B"]:
+        assert lz[k] == sb[k], (k, lz[k], sb[k])
+    refined = lz["T"] == sb["T"]
+    if min(n, m) < 16:
+        assert refined.all()  # every split of such a pair goes to the split-BF16 product
+    elif kx == ky:
+        assert 0 < refined.sum() < B  # a null pair: some splits lie near T_obs, most do not
+    else:
+        assert refined.sum() < B  # T_obs in the tail: few or none near it
+    o = O.perm_test(X, Y, B, seed=13, want_T=True)
+    tie = int(np.sum(np.abs(o["T"] - o["t_obs"]) <= 1e-6 * abs(o["t_obs"])))
+    assert abs(lz["count"] - o["count"]) <= tie
+    sample = np.unique(np.concatenate([np.arange(0, B, 53), [B - 1]]))
+    at = O.perm_stats_at(X, Y, sample, seed=13)
+    err = np.abs(lz["T"][sample] - at["T"]) / _scale(at, d)
+    assert err.max() <= TOL_MOMENTS, err.max()
+    # the same test in blocks of 1000 splits (a refinement list per block)
+    blk = hbt.perm_test(Xd, Yd, B, seed=13, precision="bf16lazy", want_T="f64", block_perms=1000)
+    assert np.array_equal(blk["T"], lz["T"])
+    for k in ["count", "n_recheck", "t_mean", "t_sd"]:
+        assert blk[k] == lz[k], k

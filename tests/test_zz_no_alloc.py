@@ -30,7 +30,7 @@ def _pair(n, m, d, seed):
     return X, Y
 
 
-@pytest.mark.parametrize("prec", ["bf16x2", "f32", "i8x3"])
+@pytest.mark.parametrize("prec", ["bf16x2", "f32", "i8x3", "bf16lazy"])
 def test_static_scratch_matches_workspace_call(prec):
     # the second call is smaller: it must not see anything the first left behind
     for n, m, d, B in [(3000, 2000, 1024, 6000), (300, 170, 96, 900)]:
