@@ -116,7 +116,7 @@ def test_repeated_rows_counts_match_oracle(prec):
 
 
 def test_repeated_rows_counts_match_oracle_lazy():
-    """The lazy precision (batched call only) on the same clouds: its first
+    """The lazy precision (batched call) on the same clouds: its first
     pass decides from the hi plane alone, whose rounding errors add up
     coherently over repeated rows; counts must equal the oracle's and the
     split-BF16 call's, pair by pair."""

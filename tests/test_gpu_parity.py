@@ -25,7 +25,7 @@ from paper_2605_08048_amd import hbt  # noqa: E402
 
 DEV = "cuda:0"
 TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x2": 1e-4, "i8x3": 1e-4, "bf16e4m3": 1e-4,
-       # the lazy precision (batched call only): its T_b outside the hi plane's
+       # the lazy precision: its T_b outside the hi plane's
        # band carry the hi plane's error; its null moments are held to this
        "bf16lazy": 5e-4}
 
