@@ -189,6 +189,13 @@ CASES = [
     (101, 157, 8192, 200, "bf16e4m3", False),
     (9000, 8000, 64, 100, "bf16e4m3", False),  # many 32-row groups and lo units per pair
     (9000, 8000, 64, 100, "bf16x2", False),
+    (50, 60, 64, 999, "bf16lazy", True),       # lazy split BF16: FP64 input
+    (150, 37, 100, 700, "bf16lazy", False),
+    (300, 450, 768, 600, "bf16lazy", False),
+    (70, 40, 37, 300, "bf16lazy", False),
+    (101, 157, 1030, 300, "bf16lazy", False),
+    (101, 157, 8192, 200, "bf16lazy", False),
+    (9000, 8000, 64, 100, "bf16lazy", False),
 ]
 
 
