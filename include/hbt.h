@@ -189,7 +189,10 @@ hbt_status hbt_align(int32_t input_dtype, const void* X, int64_t n, const void* 
  *     HBT_BF16_LAZY: by the hi plane, or by split BF16 for the splits its
  *     first pass could not decide).
  *   mask_out (nullable, device, B x ceil((n+m)/32) words): the splits used.
- * Errors: as hbt_align, plus HBT_ERR_DTYPE and HBT_ERR_UNSUPPORTED. */
+ * Errors: as hbt_align, plus HBT_ERR_DTYPE and HBT_ERR_UNSUPPORTED;
+ * HBT_ERR_SIZE when one block of splits (block_perms) would need more
+ * group-sum tiles than 32-bit tile numbers hold (blocks of billions of
+ * splits at a large d). */
 size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm);
 hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* prm,
                          hbt_result* result, float* T_out, uint32_t* mask_out, void* ws,
@@ -213,7 +216,10 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
  *   common: precision, input_dtype, gd, alternative, align, seed,
  *     perm_offset, flags (n, m, d, B, masks and block_perms are ignored).
  *   results: DEVICE array of npairs hbt_result.
- * Errors: as hbt_perm_test; a pair with bad sizes fails the whole call. */
+ * Errors: as hbt_perm_test; a pair with bad sizes fails the whole call;
+ * HBT_ERR_SIZE also when the call's group-sum tiles would not fit 32-bit
+ * tile numbers (only near the size limits, e.g. thousands of pairs of 2^20
+ * splits at d = 8192; split the batch). */
 size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, const int64_t* m,
                                             const int64_t* B, int64_t d,
                                             const hbt_perm_params* common);

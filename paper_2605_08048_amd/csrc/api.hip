@@ -237,6 +237,26 @@ struct Plan {
     std::vector<PairDesc> cdesc;   // their clouds
 };
 
+// The product kernels number their tiles with 32-bit integers.  A plan whose
+// tile list would not fit (possible only near the size limits: many pairs at
+// a large d, or very large split blocks) is refused before anything is
+// enqueued; the lazy precision is checked for the refinement tiles it would
+// need if every split went to its second product.
+hbt_status check_tiles(const Plan& P) {
+    constexpr int64_t kMaxTiles = INT32_MAX - 64;
+    int64_t worst = std::max<int64_t>(P.ntile_total, (int64_t)P.tiles.size() * P.nslot);
+    worst = std::max<int64_t>(worst, (int64_t)P.ctiles.size());
+    if (P.lazy) {
+        int64_t t = 0;
+        for (const BlockPair& b : P.bp) t += (b.nb + kTileNarrow - 1) / kTileNarrow;
+        worst = std::max<int64_t>(worst, t * P.nslot);
+    }
+    if (worst > kMaxTiles)
+        return fail(HBT_ERR_SIZE, "%lld product tiles in one call, at most %lld: split the batch or the block",
+                    (long long)worst, (long long)kMaxTiles);
+    return HBT_OK;
+}
+
 Workspace carve(const Plan& P, void* ws) {
     Carve c(ws);
     Workspace w;
@@ -899,6 +919,7 @@ size_t hbt_perm_test_workspace_size(const hbt_perm_params* prm) {
     }
     int64_t B0;
     Plan P = plan_single(prm, nullptr, nullptr, &B0);
+    if (check_tiles(P)) return 0;
     return carve(P, nullptr).bytes;
 }
 
@@ -914,6 +935,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
     if (prm->block_perms < 0) return fail(HBT_ERR_ARG, "block_perms must be >= 0");
     int64_t B0;
     Plan P = plan_single(prm, X, Y, &B0);
+    if ((st = check_tiles(P))) return st;
     const size_t need = carve(P, nullptr).bytes;
     if (!ws || ws_bytes < need)
         return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
@@ -1195,9 +1217,11 @@ static bool plan_batched(Plan& P, int64_t npairs, const void* Z_all, const int64
         return order;
     };
     const std::vector<int> order = by_size(0, (int)npairs);
+    // the tile list of the FP32 / FP64 products (the others use the groups)
     const int tb = groupsum_tile_splits(P.precision);
-    for (int p : order)
-        for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
+    if (P.precision == HBT_F32 || P.precision == HBT_F64)
+        for (int p : order)
+            for (int64_t b = 0; b < B[p]; b += tb) P.tiles.push_back(GemmTile{p, (int32_t)b});
     // Pipeline chunks: consecutive pair ranges of about equal product work
     // (B N), so that the product of one chunk runs while the next chunk is
     // aligned and split.  Only for the persistent product kernels on the
@@ -1239,6 +1263,7 @@ size_t hbt_perm_test_batched_workspace_size(int64_t npairs, const int64_t* n, co
     std::vector<int64_t> off((size_t)npairs + 1, 0);
     Plan P;
     plan_batched(P, npairs, nullptr, off.data(), n, m, B, nullptr, d, common);
+    if (check_tiles(P)) return 0;
     return carve(P, nullptr).bytes;
 }
 
@@ -1263,6 +1288,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
     if (total_rows >= (int64_t)1 << 32) return fail(HBT_ERR_SIZE, "too many splits in one call");
     Plan P;
     plan_batched(P, npairs, Z_all, row_offset, n, m, B, pair_index, d, common);
+    if ((st = check_tiles(P))) return st;
     const size_t need = carve(P, nullptr).bytes;
     if (!ws || ws_bytes < need)
         return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
@@ -1501,6 +1527,7 @@ size_t hbt_perm_test_clouds_workspace_size(int64_t nclouds, const int64_t* cloud
     std::vector<int64_t> off((size_t)nclouds, 0);
     Plan P;
     plan_clouds(P, nclouds, nullptr, off.data(), cloud_rows, npairs, pair_x, pair_y, B, nullptr, d, common);
+    if (check_tiles(P)) return 0;
     return carve(P, nullptr).bytes;
 }
 
@@ -1518,6 +1545,7 @@ hbt_status hbt_perm_test_clouds(int64_t nclouds, const void* Z_all, const int64_
     Plan P;
     plan_clouds(P, nclouds, Z_all, cloud_offset, cloud_rows, npairs, pair_x, pair_y, B, pair_index, d, common);
     if (!vector_rows(P)) return fail(HBT_ERR_UNSUPPORTED, "shared clouds: every cloud must start on 16 bytes");
+    if ((st = check_tiles(P))) return st;
     const size_t need = carve(P, nullptr).bytes;
     if (!ws || ws_bytes < need)
         return fail(HBT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);

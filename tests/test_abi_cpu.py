@@ -301,3 +301,32 @@ def test_tuning_cache_is_read_on_first_use(tmp_path):
     env = dict(os.environ, HBT_TUNE_CACHE=str(f))
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
+
+
+def test_plans_whose_tile_lists_overflow_are_refused():
+    """The product kernels number tiles with 32-bit integers: a plan that
+    would need more (4096 pairs of about 2^20 splits at d = 8192 in the lazy
+    precision, whose refinement could list every split; one pair in a single
+    block of 2^32 - 1 splits at d = 8192) is refused with HBT_ERR_SIZE before
+    anything is enqueued, and its workspace size is reported as 0."""
+    import numpy as np
+    L = hbt.lib()
+    P = 4096
+    n = np.full(P, 2, dtype=np.int64)
+    m = np.full(P, 2, dtype=np.int64)
+    B = np.full(P, (1 << 20) - 1, dtype=np.int64)
+    off = np.arange(P + 1, dtype=np.int64) * 4
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    lazy = hbt.make_params(0, 0, 8192, 0, precision="bf16lazy")
+    assert L.hbt_perm_test_batched_workspace_size(P, ptr(n), ptr(m), ptr(B), 8192, C.byref(lazy)) == 0
+    st = L.hbt_perm_test_batched(P, FAKE, ptr(off), ptr(n), ptr(m), ptr(B), None, 8192, C.byref(lazy), FAKE,
+                                 FAKE, 1 << 60, None)
+    assert st == hbt.ERR_SIZE and b"product tiles" in L.hbt_last_error()
+    # the same batch in split BF16 takes 1024-split tiles and fits
+    split = hbt.make_params(0, 0, 8192, 0, precision="bf16x2")
+    assert L.hbt_perm_test_batched_workspace_size(P, ptr(n), ptr(m), ptr(B), 8192, C.byref(split)) > 0
+    one = hbt.make_params(300, 200, 8192, (1 << 32) - 1, precision="bf16x2", block_perms=(1 << 32) - 1)
+    assert L.hbt_perm_test_workspace_size(C.byref(one)) == 0
+    assert _call(one) == hbt.ERR_SIZE and b"product tiles" in L.hbt_last_error()
+    one.block_perms = 0  # blocks of 32768 splits
+    assert L.hbt_perm_test_workspace_size(C.byref(one)) > 0
