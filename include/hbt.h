@@ -364,7 +364,8 @@ hbt_status hbt_stage_times(double* ms, int64_t* launches);
  *     entries are written to it (JSON), and the library reads it on first
  *     use in every process.
  *   hbt_tune_entry_get / hbt_tune_entry_set: one entry (tuned = 1 once
- *     measured, set or loaded).
+ *     measured, set or loaded).  HBT_BF16_LAZY has no entry of its own (it
+ *     runs on the HBT_BF16X2 one) and is refused with HBT_ERR_ARG.
  *   hbt_tune_get / hbt_tune_set: only the split-BF16 costs of dimension d
  *     (costs[0] for width 1024, costs[1] for 256).
  *   hbt_tune_save / hbt_tune_load: every tuned entry to / from a JSON file

@@ -1659,6 +1659,8 @@ hbt_status hbt_tune_set(int64_t d, const double* costs) {
 hbt_status hbt_tune_entry_get(int32_t precision, int64_t d, hbt_tune_entry* e) {
     g_err.clear();
     if (!e) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (precision == HBT_BF16_LAZY)
+        return fail(HBT_ERR_ARG, "the lazy split-BF16 precision uses the split-BF16 entry (HBT_BF16X2)");
     if (precision < HBT_F64 || precision > HBT_BF16_E4M3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
     const TileCost t = tile_cost((int)round_up(d, kDPad), precision);
@@ -1676,6 +1678,8 @@ hbt_status hbt_tune_entry_get(int32_t precision, int64_t d, hbt_tune_entry* e) {
 hbt_status hbt_tune_entry_set(int32_t precision, int64_t d, const hbt_tune_entry* e) {
     g_err.clear();
     if (!e) return fail(HBT_ERR_ARG, "NULL pointer");
+    if (precision == HBT_BF16_LAZY)
+        return fail(HBT_ERR_ARG, "the lazy split-BF16 precision uses the split-BF16 entry (HBT_BF16X2)");
     if (precision < HBT_F64 || precision > HBT_BF16_E4M3) return fail(HBT_ERR_ARG, "unknown precision %d", precision);
     if (d < 1 || d > HBT_MAX_D) return fail(HBT_ERR_SIZE, "d = %lld", (long long)d);
     const TileCost t{{e->cost[0], e->cost[1]}, e->grid_wide, e->grid_narrow, e->split_cap, e->chunks, true};

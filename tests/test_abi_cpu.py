@@ -209,6 +209,11 @@ def test_lazy_precision_workspace_and_route():
     split = hbt.make_params(300, 400, 64, 5000, precision="bf16x2")
     assert L.hbt_perm_test_workspace_size(C.byref(lazy)) > L.hbt_perm_test_workspace_size(C.byref(split)) > 0
     assert _call(hbt.make_params(10, 12, 8, 10, precision="bf16lazy", stat_route=1)) == hbt.ERR_UNSUPPORTED
+    # its tuning entry is the split-BF16 one
+    e = hbt.HbtTuneEntry()
+    for f in (L.hbt_tune_entry_get, L.hbt_tune_entry_set):
+        assert f(hbt.PRECISION["bf16lazy"], 768, C.byref(e)) == hbt.ERR_ARG
+        assert b"split-BF16 entry" in L.hbt_last_error()
 
 
 def test_clouds_validation():
