@@ -166,7 +166,8 @@ struct Workspace {
     uint32_t* flags;
     double* tw;         // final T_b of the current block (moments)
     double* rseg;       // recheck segment sums (nullptr when no pair has more than one segment)
-    uint32_t* nflag;
+    int64_t* rplan;     // recheck work plan
+    uint32_t* nflag;    // per pair: its recheck flags
     int32_t* sstat;     // per pair: problems of the split stage (merged into the result status)
     // point-to-centroid route
     float* sig;         // group sums of the smaller group, block rows x d_pad
@@ -283,8 +284,9 @@ Workspace carve(const Plan& P, void* ws) {
         w.flags = c.take<uint32_t>(std::max<int64_t>(P.block_rows, 1));
         w.tw = c.take<double>(std::max<int64_t>(P.block_rows, 1));
         w.rseg = recheck_segments(P.max_np) > 1
-                     ? c.take<double>((size_t)kRecheckSegSlots * kRecheckSegRows * P.d_pad) : nullptr;
-        w.nflag = c.take<uint32_t>(2);
+                     ? c.take<double>((size_t)recheck_slots(P.npairs, P.d_pad) * P.d_pad) : nullptr;
+        w.rplan = c.take<int64_t>(recheck_plan_words(np));
+        w.nflag = c.take<uint32_t>((size_t)(np + 1) / 2 * 2);
         w.sstat = c.take<int32_t>((size_t)(np + 1) / 2 * 2);
         if (P.route2) {
             w.sig = c.take<float>((size_t)std::max<int64_t>(P.block_rows, 1) * P.d_pad);
@@ -312,6 +314,7 @@ Workspace carve(const Plan& P, void* ws) {
         w.flags = nullptr;
         w.tw = nullptr;
         w.rseg = nullptr;
+        w.rplan = nullptr;
         w.nflag = nullptr;
         w.sstat = nullptr;
     }
@@ -723,7 +726,8 @@ hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_pa
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
-                               w.nflag, P.block_rows, P.max_np, w.rseg, P.d, common->gd, common->alternative,
+                               w.nflag, w.rplan, P.block_rows, P.max_np, w.rseg, recheck_slots(np, P.d_pad),
+                               P.d, common->gd, common->alternative,
                                w.cnt, w.tw, s));
     }
     { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(np, w.bp, w.st, w.tw, w.cnt, s)); }
@@ -762,7 +766,7 @@ hbt_status batched_pipelined(const Plan& P, const Workspace& w, const hbt_perm_p
         HIP_TRY(upload(w.pairs, P.pairs.data(), P.pairs.size() * sizeof(PairDesc), s));
         HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), s));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), s));
-        HIP_TRY(zero(w.nflag, 8, s));
+        HIP_TRY(zero(w.nflag, (size_t)(np + 1) / 2 * 8, s));
         if (P.lazy) HIP_TRY(zero(w.rcnt, (size_t)(np + 1) / 2 * 8, s));
     }
     HIP_TRY(ev.record(s, &e0));
@@ -1075,8 +1079,8 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         if (!no_recheck) {
             StageTimer t_(HBT_STAGE_RECHECK, s);
             HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.t64, w.coef, w.mask,
-                                   w.flags, w.nflag, nb, P.max_np, w.rseg, P.d, prm->gd, prm->alternative,
-                                   w.cnt, w.tw, s));
+                                   w.flags, w.nflag, w.rplan, nb, P.max_np, w.rseg, recheck_slots(1, P.d_pad),
+                                   P.d, prm->gd, prm->alternative, w.cnt, w.tw, s));
         }
         { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(1, w.bp, w.st, w.tw, w.cnt, s)); }
         if (mask_out)
@@ -1331,7 +1335,7 @@ hbt_status hbt_perm_test_batched(int64_t npairs, const void* Z_all, const int64_
         else
             HIP_TRY(upload(w.tiles, P.tiles.data(), P.tiles.size() * sizeof(GemmTile), qt));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), qt));
-        HIP_TRY(zero(w.nflag, 8, qt));
+        HIP_TRY(zero(w.nflag, (size_t)(np + 1) / 2 * 8, qt));
         if (P.lazy) HIP_TRY(zero(w.rcnt, (size_t)(np + 1) / 2 * 8, qt));
         if (P.route2) HIP_TRY(upload(w.ctiles, P.ctiles.data(), P.ctiles.size() * sizeof(CTile), qt));
     }
@@ -1573,7 +1577,7 @@ hbt_status hbt_perm_test_clouds(int64_t nclouds, const void* Z_all, const int64_
         StageTimer t_(HBT_STAGE_OTHER, qt);
         HIP_TRY(upload(w.groups, P.groups.data(), P.groups.size() * sizeof(GemmGroup), qt));
         HIP_TRY(upload(w.Btot, P.Btot.data(), P.Btot.size() * sizeof(int64_t), qt));
-        HIP_TRY(zero(w.nflag, 8, qt));
+        HIP_TRY(zero(w.nflag, (size_t)(np + 1) / 2 * 8, qt));
     }
     {
         StageTimer t_(HBT_STAGE_OTHER, s);

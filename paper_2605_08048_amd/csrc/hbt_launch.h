@@ -160,6 +160,9 @@ hipError_t launch_stat(const PairDesc* pairs, const BlockPair* bp, int npairs, i
                        PairCount* cnt, uint32_t* flags, uint32_t* nflag, hipStream_t s, const double* pv = nullptr,
                        const uint32_t* mask = nullptr, const double* coef = nullptr,
                        double* fpart = nullptr, int fold_segs = 0);
+// A split whose T_b is within `band` of the threshold is flagged: it joins
+// its pair's recheck list (flags from the pair's first block row, nflag[pair]
+// counting them; the counts are zeroed by the caller) and is not counted.
 // launch_stat with pv (v . sigma per slot), mask, coef and fpart non-null
 // reflects the group sums of pairs stored unreflected (the Householder fold):
 // a first kernel writes each split's fold sums per segment into fpart
@@ -178,17 +181,20 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
                             int alternative, const RecheckBand& band, int no_recheck, double* Tw, PairCount* cnt,
                             uint32_t* flags, uint32_t* nflag, uint32_t* rlist, uint32_t* rcnt, hipStream_t s,
                             void* T_out = nullptr, int T_mode = 0);
-// FP64 recheck of the flagged splits.  rseg: kRecheckSegSlots x 8 x d_pad
-// doubles of per-wave segment sums (nullptr: every flag done whole by one
-// work-group); the value of each flag's sums does not depend on it.
-constexpr int kRecheckSegSlots = 256;
-constexpr int kRecheckSegRows = 8;  // per-wave rows of a slot
+// FP64 recheck of the flagged splits.  flags: per pair, from the pair's
+// first block row, the split rows k_stat flagged; nflag: their number per
+// pair.  plan: 4 (npairs + 1) + 1 int64 of work plan (written here).  rseg:
+// `slots` vectors of d_pad doubles (per flag and segment sums; nullptr when
+// no pair has more than one segment); the value of each flag's sums does not
+// depend on it.
+constexpr int kRecheckSlotsSingle = 2048;
+inline int64_t recheck_plan_words(int npairs) { return 4 * ((int64_t)npairs + 1) + 1; }
 int recheck_segments(int max_np);
-hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
-                          int npairs, const PairState* st, const double* v, const double* t64,
-                          const double* coef,
-                          const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag,
-                          int64_t max_flags, int max_np, double* rseg, int d, int gd,
+int64_t recheck_slots(int npairs, int d_pad);
+hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp, int npairs,
+                          const PairState* st, const double* v, const double* t64, const double* coef,
+                          const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag, int64_t* plan,
+                          int64_t max_flags, int max_np, double* rseg, int64_t slots, int d, int gd,
                           int alternative, PairCount* cnt, double* Tw, hipStream_t s);
 // Sums of T_b - T_obs and its square per pair over the current block (Tw
 // holds the block's final T_b, recheck applied).

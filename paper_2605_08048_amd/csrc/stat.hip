@@ -98,6 +98,25 @@ void k_fold_c(const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ 
 // kStatRefined: thread i takes list entry i (entry k of pair p is thread
 // mrow0 of p + k, for k < rcnt[p]) and decides that split from its
 // split-BF16 sums, with the usual FP64-recheck flags.
+//
+// A split row joins a list of its pair (the recheck flags, or the lazy
+// precision's refinement list) at list[first block row of the pair + k], k
+// from the pair's counter: one atomic per wave when all its rows belong to
+// one pair.
+__device__ __forceinline__ void list_append(bool want, bool one_pair, int p0, int p, int64_t row,
+                                            const BlockPair* bp, uint32_t* list, uint32_t* count) {
+    const uint64_t wm = __ballot(want);
+    if (one_pair) {
+        uint32_t base = 0;
+        if (lane_id() == 0 && wm) base = atomicAdd(&count[p0], (uint32_t)__popcll(wm));
+        base = (uint32_t)__shfl((int)base, 0, 64);
+        if (want) list[bp[p0].mrow0 + base + mbcnt64(wm)] = (uint32_t)row;
+    } else if (want) {
+        const uint32_t k = atomicAdd(&count[p], 1u);
+        list[bp[p].mrow0 + k] = (uint32_t)row;
+    }
+}
+
 enum StatMode { kStatPlain = 0, kStatLazyFirst = 1, kStatRefined = 2 };
 template <int MODE>
 __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs,
@@ -121,6 +140,7 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
     const int p0 = __shfl(p, 0, 64);
     bool active = in_range;
     bool refine = false;  // kStatLazyFirst: the split goes to its pair's list
+    bool flag = false;    // the split goes to its pair's FP64-recheck list
     int64_t row = i;
     if (MODE == kStatRefined && in_range) {
         active = i - bp[p].mrow0 < (int64_t)rcnt[p];
@@ -183,28 +203,14 @@ __global__ __launch_bounds__(256) void k_stat(const PairDesc* __restrict__ pairs
             refine = nan || fabs(val - thr) <= eps || (pd.n < pd.m ? pd.n : pd.m) < kLazyMinGroup;
             if (!refine) exceed = val >= thr;
         } else {
-            const bool border = !no_recheck && !nan && fabs(val - thr) <= eps;
-            if (border) {
-                const uint32_t k = atomicAdd(nflag, 1u);
-                flags[k] = (uint32_t)row;
-            } else {
-                exceed = nan || val >= thr;
-            }
+            flag = !no_recheck && !nan && fabs(val - thr) <= eps;
+            if (!flag) exceed = nan || val >= thr;
         }
     }
-    if (MODE == kStatLazyFirst) {
-        // list appends: one atomic per wave when all its rows belong to one pair
-        const uint64_t rm = __ballot(refine);
-        if (one_pair) {
-            uint32_t base = 0;
-            if (lane_id() == 0 && rm) base = atomicAdd(&rcnt[p0], (uint32_t)__popcll(rm));
-            base = (uint32_t)__shfl((int)base, 0, 64);
-            if (refine) rlist[bp[p0].mrow0 + base + mbcnt64(rm)] = (uint32_t)row;
-        } else if (refine) {
-            const uint32_t k = atomicAdd(&rcnt[p], 1u);
-            rlist[bp[p].mrow0 + k] = (uint32_t)row;
-        }
-    }
+    if (MODE == kStatLazyFirst)
+        list_append(refine, one_pair, p0, p, row, bp, rlist, rcnt);
+    else
+        list_append(flag, one_pair, p0, p, row, bp, flags, nflag);
     // count: one atomic per wave when all its rows belong to one pair
     const uint64_t ex = __ballot(exceed);
     if (one_pair) {
@@ -255,286 +261,424 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
 // ---------------------------------------------------------------------------
 // FP64 recheck of the flagged splits.  The smaller group's sum is gathered
 // from the input rows, each rebuilt in FP64 as the aligned row
-// x_i - coef_i v (X) or y_j (Y); the other group's sum is t - sigma_small
-// with the FP64 pooled total t.
+// x_i - coef_i v (X, one rounding: fma(-coef_i, v, x_i)) or y_j (Y); the
+// other group's sum is t - sigma_small with the FP64 pooled total t.
 //
-// The gather over a split's mask words is cut into segments of kSegWords
-// words (512 pooled rows); wave w of a work-group walks words w, w + 8, ...
-// of a segment.  sigma_small is always formed in one order: per wave, its
-// segment sums added in segment order; then the 8 waves' totals added in
-// wave order.  The first f_seg flags of the list (when segments are enabled)
-// are split into one work item per segment, whose per-wave sums go to
-// workspace slots that k_recheck_finish adds in that order; this puts many
-// work-groups on a call with few flags.  Every other flag is done whole by
-// one work-group whose waves keep their running totals in registers.  The
-// value of a flag's sums therefore does not depend on how the work is
-// spread.  512 threads, columns in passes of 768.
+// k_stat lists the flags of each pair from the pair's first block row.  The
+// rows of a pair are cut into segments of kSegWords mask words (512 pooled
+// rows); wave w of a work-group takes words w and w + 8 of a segment, and
+// each lane columns c0 + 64 u + lane (u < 12) of each pass of kRecheckPass
+// columns.  For each flag and column, sigma_small is formed in one order: per
+// wave, its rows of the segment in ascending order; the segment's sum is the
+// 8 wave sums added in wave order; then the segment sums are added in
+// segment order.  For the squares, thread t of the work-group holds columns
+// c0 + t and c0 + t + 512 of each pass (passes in order, c0 + t first); the
+// work-group adds its threads' squares in a fixed tree.  How the work is
+// spread never changes a bit:
+//   * a work item takes a group of up to kRecheckGroup flags of one pair and
+//     reads each row of a segment once for all of them (a row is read when
+//     any of them holds it): a pair with F flags reads its rows about
+//     F / 4 times rather than F times;
+//   * a pair whose flag segments fit the workspace slots has one item per
+//     group and segment, whose sums go to the slots and are added by
+//     k_recheck_finish; every other pair has one item per flag that walks
+//     all segments with running totals;
+//   * the group size is 4 when the call has many flag segments and smaller
+//     when it has few, so that a call with a handful of flags still spreads
+//     over many work-groups (k_recheck_plan decides it on the device).
 // ---------------------------------------------------------------------------
-constexpr int kRecheckWaves = kRecheckSegRows;  // 8
+constexpr int kRecheckWaves = 8;
 constexpr int kRecheckThreads = 64 * kRecheckWaves;
-constexpr int kRecheckPass = 768;        // columns per pass (12 per lane)
+constexpr int kRecheckPass = 768;  // columns per pass (12 per lane)
 constexpr int kSegWords = 16;
+constexpr int kRecheckGroup = 2;   // flags per work item at most
+constexpr int kRecheckRows = 4;    // rows in flight per wave
 
-struct FlagCtx {
-    int64_t row;
-    int p, N, W, G;
-    PairDesc pd;
-    PairState q;
-    const uint32_t* mk;
-};
+// Segments of a pair's pooled mask positions.
+__device__ __forceinline__ int pair_words(const PairDesc& pd) { return (pd.n + pd.m + pd.ygap + 31) >> 5; }
+__device__ __forceinline__ int pair_segs(const PairDesc& pd) { return (pair_words(pd) + kSegWords - 1) / kSegWords; }
 
-__device__ __forceinline__ FlagCtx flag_ctx(const PairDesc* pairs, const BlockPair* bp, int npairs,
-                                            const PairState* st, const uint32_t* mask,
-                                            const uint32_t* flags, uint32_t f) {
-    FlagCtx c;
-    c.row = flags[f];
-    c.p = upper_index(npairs, c.row, [&](int k) { return bp[k].mrow0; });
-    c.pd = pairs[c.p];
-    c.q = st[c.p];
-    c.mk = mask_row(mask, bp[c.p], c.row, c.pd.Wp);
-    c.N = c.pd.n + c.pd.m;
-    c.W = (c.N + c.pd.ygap + 31) >> 5;  // mask words that hold items (Y's start ygap further on)
-    c.G = (c.W + kSegWords - 1) / kSegWords;
-    return c;
+// Sum over the 512 threads of a work-group in a fixed order (a butterfly in
+// each wave, then the 8 waves in order); every thread gets the sum.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    __syncthreads();  // the previous sum's readers are done with red
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRecheckWaves; ++q) s += red[q];
+    return s;
 }
 
-// The flag's statistic from the per-thread sums of squares (thread t holds
-// the columns c0 + t + 512 k of every pass, in that order), its decision and
-// its FP64 T_b.
-__device__ void recheck_finish_flag(const FlagCtx& c, double ss_small, double ss_large, int d,
-                                    int gd, int alternative, PairCount* cnt, double* Tw,
-                                    double* red1, double* red2) {
-    red1[threadIdx.x] = ss_small;
-    red2[threadIdx.x] = ss_large;
+// The squares of one column's sums (thread-local, in the order above).
+__device__ __forceinline__ void add_squares(double sm, double tcol, double& ss_small, double& ss_large) {
+    const double l = tcol - sm;
+    ss_small = fma(sm, sm, ss_small);
+    ss_large = fma(l, l, ss_large);
+}
+
+// The flag's FP64 statistic, decision and T_b (one thread).
+__device__ void recheck_decide(const PairDesc& pd, const PairState& q, int p, int64_t row, double ss_small,
+                               double ss_large, int d, int gd, int alternative, PairCount* cnt, double* Tw) {
+    const double dd = (double)d;
+    const double ss1 = pd.flip ? ss_large : ss_small;
+    const double ss2 = pd.flip ? ss_small : ss_large;
+    const double r1 = sqrt(ss1) / (double)pd.n, r2 = sqrt(ss2) / (double)pd.m;
+    const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);
+    const bool two = alternative == HBT_ALT_TWO_SIDED;
+    const double val = two ? fabs(T) : T;
+    const double thr = (two ? fabs(q.t_obs) : q.t_obs) - q.tau;
+    if (T != T || val >= thr) atomicAdd(&cnt[p].count, 1ull);
+    atomicAdd(&cnt[p].n_recheck, 1ull);
+    Tw[row] = T;
+}
+
+// The work plan (one work-group), five arrays of npairs + 1 int64 in `plan`:
+//   [0] whole items, [1] segmented items, [2] slots, [3] segmented flags:
+//       exclusive prefixes over the pairs, totals at index npairs;
+//   [4][0] the group size.
+// A pair is segmented when it has more than one segment and its flag
+// segments, added to those of the pairs before it, fit `slots`.
+__device__ __forceinline__ int64_t block_scan1024(int64_t x, int64_t* sh, int64_t* total) {
+    const int t = threadIdx.x;
+    sh[t] = x;
     __syncthreads();
-    for (int o = kRecheckThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            red1[threadIdx.x] += red1[threadIdx.x + o];
-            red2[threadIdx.x] += red2[threadIdx.x + o];
-        }
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t y = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += y;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double dd = (double)d;
-        const double ss1 = c.pd.flip ? red2[0] : red1[0];
-        const double ss2 = c.pd.flip ? red1[0] : red2[0];
-        const double r1 = sqrt(ss1) / (double)c.pd.n, r2 = sqrt(ss2) / (double)c.pd.m;
-        const double T = log_g(r2, dd, gd) - log_g(r1, dd, gd);
-        const bool two = alternative == HBT_ALT_TWO_SIDED;
-        const double val = two ? fabs(T) : T;
-        const double thr = (two ? fabs(c.q.t_obs) : c.q.t_obs) - c.q.tau;
-        if (T != T || val >= thr) atomicAdd(&cnt[c.p].count, 1ull);
-        atomicAdd(&cnt[c.p].n_recheck, 1ull);
-        Tw[c.row] = T;
-    }
+    const int64_t r = sh[t];
+    *total = sh[1023];
     __syncthreads();
+    return r;
 }
 
-template <typename Tin>
-__global__ __launch_bounds__(kRecheckThreads) void k_recheck(
-    const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
-    const PairState* __restrict__ st, const double* __restrict__ v,
-    const double* __restrict__ t64, const double* __restrict__ coef,
-    const uint32_t* __restrict__ mask, const uint32_t* __restrict__ flags,
-    const uint32_t* __restrict__ nflag, int d, int d_pad, int gd, int alternative,
-    double* __restrict__ rseg, int f_seg, int g_max, PairCount* cnt, double* __restrict__ Tw) {
+__global__ __launch_bounds__(1024) void k_recheck_plan(const PairDesc* __restrict__ pairs, int npairs,
+                                                       const uint32_t* __restrict__ nflag, int64_t slots,
+                                                       int64_t target, int gmax, int64_t* __restrict__ plan) {
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const int np1 = npairs + 1;
+    int64_t x = 0;
+    for (int p = t; p < npairs; p += 1024) x += (int64_t)nflag[p] * pair_segs(pairs[p]);
+    int64_t all;
+    (void)block_scan1024(x, sh, &all);
+    // flags alone while there are few flag segments; up to gmax per item when
+    // there are enough for `target` work-groups anyway
+    const int64_t gq = all / (target > 0 ? target : 1);
+    const int g = gq < 1 ? 1 : gq > gmax ? gmax : (int)gq;
+    int64_t bw = 0, bs = 0, bc = 0, bf = 0;
+    for (int p0 = 0; p0 < npairs; p0 += 1024) {
+        const int p = p0 + t;
+        int64_t F = 0, G = 0;
+        if (p < npairs) {
+            F = nflag[p];
+            G = pair_segs(pairs[p]);
+        }
+        const int64_t J = (F + g - 1) / g;
+        const int64_t cand = (G > 1 && F > 0) ? F * G : 0;
+        int64_t tc, tw, ts, tf;
+        const int64_t ic = block_scan1024(cand, sh, &tc);
+        const bool seg = cand > 0 && bc + ic <= slots;
+        const int64_t wi = seg ? 0 : F, si = seg ? J * G : 0, fi = seg ? F : 0;
+        const int64_t iw = block_scan1024(wi, sh, &tw);
+        const int64_t is = block_scan1024(si, sh, &ts);
+        const int64_t jf = block_scan1024(fi, sh, &tf);
+        if (p < npairs) {
+            plan[p] = bw + iw - wi;
+            plan[np1 + p] = bs + is - si;
+            plan[2 * np1 + p] = bc + ic - cand;
+            plan[3 * np1 + p] = bf + jf - fi;
+        }
+        bw += tw;
+        bs += ts;
+        bc += tc;
+        bf += tf;
+    }
+    if (t == 0) {
+        plan[npairs] = bw;
+        plan[np1 + npairs] = bs;
+        plan[2 * np1 + npairs] = bc;
+        plan[3 * np1 + npairs] = bf;
+        plan[4 * np1] = g;
+    }
+}
+
+struct RecheckArgs {
+    const PairDesc* pairs;
+    const BlockPair* bp;
+    int npairs;
+    const PairState* st;
+    const double* v;
+    const double* t64;
+    const double* coef;
+    const uint32_t* mask;
+    const uint32_t* flags;
+    const uint32_t* nflag;
+    const int64_t* plan;
+    int d, d_pad, gd, alternative;
+    double* rseg;
+    PairCount* cnt;
+    double* Tw;
+};
+
+// One work item: flags [f0, f0 + nf) of pair p (nf <= FG), segments
+// [sg0, sg1).  Segmented items write each flag's segment sums to its slots;
+// whole items (FG = 1) keep running totals over every segment and decide the
+// flag.
+template <typename Tin, int FG>
+__device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg0, int sg1, bool whole,
+                             double (*part)[kRecheckPass], double* red) {
     constexpr int kU = kRecheckPass / 64;  // columns per lane per pass
-    constexpr int kRows = 4;               // rows in flight per wave
-    __shared__ double part[kRecheckWaves][kRecheckPass];  // per-wave partial group sums
-    __shared__ double red1[kRecheckThreads], red2[kRecheckThreads];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const uint32_t total = *nflag;
-    const int64_t nseg = total < (uint32_t)f_seg ? (int64_t)total : (int64_t)f_seg;
-    const int64_t nitems = nseg * g_max + ((int64_t)total - nseg);
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const bool whole = it >= nseg * g_max;
-        const uint32_t f = whole ? (uint32_t)(nseg + (it - nseg * g_max)) : (uint32_t)(it / g_max);
-        const int sg = whole ? 0 : (int)(it % g_max);
-        const FlagCtx c = flag_ctx(pairs, bp, npairs, st, mask, flags, f);
-        if (!whole && sg >= c.G) continue;  // work-group-uniform
-        const int s0 = sg, s1 = whole ? c.G : sg + 1;
-        const PairDesc& pd = c.pd;
-        const double* vp = v + (int64_t)c.p * d_pad;
-        const double* tp = t64 + (int64_t)c.p * d_pad;
-        const double* cf = coef + pd.coef0;
-        const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
-        const Tin* X = (const Tin*)pd.X;
-        const Tin* Y = (const Tin*)pd.Y;
-        const int W = c.W;
-        // members of the smaller group in mask word w
-        auto word_bits = [&](int w, int wend) -> uint32_t {
-            if (w >= wend) return 0u;
-            return (c.mk[w] ^ flip) & item_bits(w, pd.n, pd.m, pd.ygap);
-        };
-        double ss_small = 0.0, ss_large = 0.0;
-        for (int c0 = 0; c0 < d; c0 += kRecheckPass) {
-            double vc[kU], tot[kU];
+    const int t = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63;
+    const PairDesc pd = A.pairs[p];
+    const BlockPair bq = A.bp[p];
+    const int d = A.d;
+    const int W = pair_words(pd), G = pair_segs(pd);
+    const uint32_t flip = pd.flip ? 0xffffffffu : 0u;
+    const Tin* X = (const Tin*)pd.X;
+    const Tin* Y = (const Tin*)pd.Y;
+    const double* vp = A.v + (int64_t)p * A.d_pad;
+    const double* tp = A.t64 + (int64_t)p * A.d_pad;
+    const double* cf = A.coef + pd.coef0;
+    const int64_t slot = whole ? 0 : A.plan[2 * (A.npairs + 1) + p] + (int64_t)f0 * G;
+    const uint32_t* mk[FG];
+    int64_t row0 = 0;
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int col = c0 + 64 * u + lane;
-                vc[u] = col < d ? vp[col] : 0.0;
-                tot[u] = 0.0;
-            }
-            for (int sgi = s0; sgi < s1; ++sgi) {
-                const int wend = min(W, (sgi + 1) * kSegWords);
-                double acc[kU];
+    for (int f = 0; f < FG; ++f) {
+        const int64_t row = A.flags[bq.mrow0 + f0 + (f < nf ? f : 0)];
+        if (f == 0) row0 = row;
+        mk[f] = mask_row(A.mask, bq, row, pd.Wp);
+    }
+    double ssS = 0.0, ssL = 0.0;
+    for (int c0 = 0; c0 < d; c0 += kRecheckPass) {
+        double vc[kU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-                // kRows rows at a time, all loads issued before the adds
-                int w = sgi * kSegWords + wave;
-                uint32_t bits = word_bits(w, wend);
-                for (;;) {
-                    int rows[kRows];
+        for (int u = 0; u < kU; ++u) {
+            const int col = c0 + 64 * u + lane;
+            vc[u] = col < d ? vp[col] : 0.0;
+        }
+        double tot[2] = {0.0, 0.0};
+        for (int sg = sg0; sg < sg1; ++sg) {
+            double acc[FG][kU];
 #pragma unroll
-                    for (int t = 0; t < kRows; ++t) {
-                        while (!bits && w < wend) {
-                            w += kRecheckWaves;
-                            bits = word_bits(w, wend);
-                        }
-                        if (bits) {
-                            rows[t] = 32 * w + __builtin_ctz(bits);
-                            bits &= bits - 1u;
-                        } else {
-                            rows[t] = -1;
-                        }
-                    }
-                    if (rows[0] < 0) break;
-                    // columns are clamped to the row (no branch around a load);
-                    // absent rows and clamped columns are weighted by 0
-                    Tin z[kRows][kU];
-                    double kc[kRows], wt[kRows];
+            for (int f = 0; f < FG; ++f)
 #pragma unroll
-                    for (int t = 0; t < kRows; ++t) {
-                        int i = rows[t] < 0 ? 0 : rows[t];
-                        if (i >= pd.n) i -= pd.ygap;  // Y's mask positions to pooled items
-                        const bool isx = i < pd.n;
-                        kc[t] = (rows[t] >= 0 && isx) ? cf[i] : 0.0;
-                        wt[t] = rows[t] >= 0 ? 1.0 : 0.0;
-                        const Tin* src = isx ? X + (int64_t)i * d : Y + (int64_t)(i - pd.n) * d;
+                for (int u = 0; u < kU; ++u) acc[f][u] = 0.0;
+            // this wave's words of the segment: w0 and w0 + 8
+            const int w0 = sg * kSegWords + wave, we = min(W, (sg + 1) * kSegWords);
+            int w = w0;
+            uint32_t bits[FG], U = 0;
+            auto load_word = [&](int ww) {
+                U = 0;
+                if (ww >= we) {
 #pragma unroll
-                        for (int u = 0; u < kU; ++u) {
-                            const int col = c0 + 64 * u + lane;
-                            z[t][u] = src[col < d ? col : d - 1];
-                        }
-                    }
-#pragma unroll
-                    for (int t = 0; t < kRows; ++t)
-#pragma unroll
-                        for (int u = 0; u < kU; ++u) {
-                            const double cm = (c0 + 64 * u + lane) < d ? wt[t] : 0.0;
-                            acc[u] += cm * ((double)z[t][u] - kc[t] * vc[u]);
-                        }
+                    for (int f = 0; f < FG; ++f) bits[f] = 0u;
+                    return;
                 }
-                if (whole) {
+                const uint32_t ib = item_bits(ww, pd.n, pd.m, pd.ygap);
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) tot[u] += acc[u];
-                } else {
-                    double* dst = rseg + (((int64_t)f * g_max + sgi) * kRecheckWaves + wave) * d_pad + c0;
+                for (int f = 0; f < FG; ++f) {
+                    bits[f] = f < nf ? (mk[f][ww] ^ flip) & ib : 0u;
+                    U |= bits[f];
+                }
+            };
+            load_word(w);
+            for (;;) {
+                int rows[kRecheckRows];
+                uint32_t mem[kRecheckRows];
 #pragma unroll
-                    for (int u = 0; u < kU; ++u)
-                        if (c0 + 64 * u + lane < d) dst[64 * u + lane] = acc[u];
+                for (int k = 0; k < kRecheckRows; ++k) {
+                    if (!U && w == w0) load_word(w += kRecheckWaves);
+                    if (U) {
+                        const int b = __builtin_ctz(U);
+                        U &= U - 1u;
+                        rows[k] = 32 * w + b;
+                        uint32_t mm = 0;
+#pragma unroll
+                        for (int f = 0; f < FG; ++f) mm |= ((bits[f] >> b) & 1u) << f;
+                        mem[k] = mm;
+                    } else {
+                        rows[k] = -1;
+                        mem[k] = 0;
+                    }
+                }
+                if (rows[0] < 0) break;
+                // columns are clamped to the row (no branch around a load)
+                Tin z[kRecheckRows][kU];
+                double kc[kRecheckRows];
+#pragma unroll
+                for (int k = 0; k < kRecheckRows; ++k) {
+                    int i = rows[k] < 0 ? 0 : rows[k];
+                    if (i >= pd.n) i -= pd.ygap;  // Y's mask positions to pooled items
+                    const bool isx = i < pd.n;
+                    kc[k] = isx ? cf[i] : 0.0;
+                    const Tin* src = isx ? X + (int64_t)i * d : Y + (int64_t)(i - pd.n) * d;
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const int col = c0 + 64 * u + lane;
+                        z[k][u] = src[col < d ? col : d - 1];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kRecheckRows; ++k) {
+                    if (!mem[k]) continue;
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const double x = fma(-kc[k], vc[u], (double)z[k][u]);
+#pragma unroll
+                        for (int f = 0; f < FG; ++f)
+                            if ((mem[k] >> f) & 1u) acc[f][u] += x;
+                    }
                 }
             }
-            if (whole) {
+            // the segment's sums: the 8 wave sums in wave order, per flag
 #pragma unroll
-                for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = tot[u];
+            for (int f = 0; f < FG; ++f) {
+                if (f >= nf) break;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = acc[f][u];
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const int cc = threadIdx.x + kRecheckThreads * k;
-                    if (cc < kRecheckPass && c0 + cc < d) {
+                    const int cc = t + kRecheckThreads * k;
+                    if (cc < kRecheckPass) {
                         double sm = 0.0;
 #pragma unroll
                         for (int q = 0; q < kRecheckWaves; ++q) sm += part[q][cc];
-                        const double l = tp[c0 + cc] - sm;
-                        ss_small += sm * sm;
-                        ss_large += l * l;
+                        if (whole)
+                            tot[k] += sm;
+                        else if (c0 + cc < d)
+                            A.rseg[(slot + (int64_t)f * G + sg) * A.d_pad + c0 + cc] = sm;
                     }
                 }
                 __syncthreads();
             }
         }
-        if (whole) recheck_finish_flag(c, ss_small, ss_large, d, gd, alternative, cnt, Tw, red1, red2);
+        if (whole) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int cc = t + kRecheckThreads * k;
+                if (cc < kRecheckPass && c0 + cc < d) add_squares(tot[k], tp[c0 + cc], ssS, ssL);
+            }
+        }
+    }
+    if (whole) {
+        const double s1 = block_sum(ssS, red), s2 = block_sum(ssL, red);
+        if (t == 0) recheck_decide(pd, A.st[p], p, row0, s1, s2, d, A.gd, A.alternative, A.cnt, A.Tw);
     }
 }
 
-// The segmented flags: sigma_small from the per-wave segment sums in the
-// order above, then the same statistic and decision as a whole flag.
-__global__ __launch_bounds__(kRecheckThreads) void k_recheck_finish(
-    const PairDesc* __restrict__ pairs, const BlockPair* __restrict__ bp, int npairs,
-    const PairState* __restrict__ st, const double* __restrict__ t64,
-    const uint32_t* __restrict__ mask, const uint32_t* __restrict__ flags,
-    const uint32_t* __restrict__ nflag, int d, int d_pad, int gd, int alternative,
-    const double* __restrict__ rseg, int f_seg, int g_max, PairCount* cnt, double* __restrict__ Tw) {
-    __shared__ double red1[kRecheckThreads], red2[kRecheckThreads];
-    const uint32_t total = *nflag;
-    const uint32_t f = blockIdx.x;
-    if (f >= total || f >= (uint32_t)f_seg) return;
-    const FlagCtx c = flag_ctx(pairs, bp, npairs, st, mask, flags, f);
-    const double* tp = t64 + (int64_t)c.p * d_pad;
-    double ss_small = 0.0, ss_large = 0.0;
-    for (int c0 = 0; c0 < d; c0 += kRecheckPass)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int cc = threadIdx.x + kRecheckThreads * k;
-            if (cc < kRecheckPass && c0 + cc < d) {
-                // the 8 wave totals are independent chains: each segment's 8
-                // loads are issued together
-                double t[kRecheckWaves];
-#pragma unroll
-                for (int q = 0; q < kRecheckWaves; ++q) t[q] = 0.0;
-                const double* src = rseg + (int64_t)f * g_max * kRecheckWaves * d_pad + c0 + cc;
-                for (int sgi = 0; sgi < c.G; ++sgi) {
-                    double x[kRecheckWaves];
-#pragma unroll
-                    for (int q = 0; q < kRecheckWaves; ++q) x[q] = src[((int64_t)sgi * kRecheckWaves + q) * d_pad];
-#pragma unroll
-                    for (int q = 0; q < kRecheckWaves; ++q) t[q] += x[q];
+template <typename Tin>
+__global__ __launch_bounds__(kRecheckThreads) void k_recheck(RecheckArgs A) {
+    __shared__ double part[kRecheckWaves][kRecheckPass];  // per-wave sums of a segment
+    __shared__ double red[kRecheckWaves];
+    const int np1 = A.npairs + 1;
+    const int64_t* wpre = A.plan;
+    const int64_t* spre = A.plan + np1;
+    const int g = (int)A.plan[4 * np1];
+    const int64_t NW = wpre[A.npairs], NS = spre[A.npairs];
+    for (int64_t it = blockIdx.x; it < NW + NS; it += gridDim.x) {
+        if (it < NW) {  // one flag, every segment
+            const int p = upper_index(A.npairs, it, [&](int k) { return wpre[k]; });
+            recheck_item<Tin, 1>(A, p, (int)(it - wpre[p]), 1, 0, pair_segs(A.pairs[p]), true, part, red);
+        } else {  // a group of g flags, one segment
+            const int64_t x = it - NW;
+            const int p = upper_index(A.npairs, x, [&](int k) { return spre[k]; });
+            const int64_t r = x - spre[p];
+            const int G = pair_segs(A.pairs[p]);
+            const int F = (int)A.nflag[p];
+            const int f0 = (int)(r / G) * g, sg = (int)(r % G);
+            if constexpr (sizeof(Tin) == 4) {
+                if (g > 1) {
+                    recheck_item<Tin, kRecheckGroup>(A, p, f0, min(g, F - f0), sg, sg + 1, false, part, red);
+                    continue;
                 }
-                double sm = 0.0;
-#pragma unroll
-                for (int q = 0; q < kRecheckWaves; ++q) sm += t[q];
-                const double l = tp[c0 + cc] - sm;
-                ss_small += sm * sm;
-                ss_large += l * l;
             }
+            recheck_item<Tin, 1>(A, p, f0, 1, sg, sg + 1, false, part, red);
         }
-    recheck_finish_flag(c, ss_small, ss_large, d, gd, alternative, cnt, Tw, red1, red2);
+    }
+}
+
+// The segmented flags: sigma_small from the segment sums in segment order,
+// then the same squares, statistic and decision as a whole item.
+__global__ __launch_bounds__(kRecheckThreads) void k_recheck_finish(RecheckArgs A) {
+    __shared__ double red[kRecheckWaves];
+    const int np1 = A.npairs + 1;
+    const int64_t* spl = A.plan + 2 * np1;
+    const int64_t* fpre = A.plan + 3 * np1;
+    const int64_t NF = fpre[A.npairs];
+    const int t = threadIdx.x, d = A.d;
+    for (int64_t qf = blockIdx.x; qf < NF; qf += gridDim.x) {
+        const int p = upper_index(A.npairs, qf, [&](int k) { return fpre[k]; });
+        const int64_t j = qf - fpre[p];
+        const PairDesc pd = A.pairs[p];
+        const int G = pair_segs(pd);
+        const int64_t row = A.flags[A.bp[p].mrow0 + j];
+        const double* src = A.rseg + (spl[p] + j * G) * A.d_pad;
+        const double* tp = A.t64 + (int64_t)p * A.d_pad;
+        double ssS = 0.0, ssL = 0.0;
+        for (int c0 = 0; c0 < d; c0 += kRecheckPass)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int cc = t + kRecheckThreads * k;
+                const int col = c0 + cc;
+                if (cc < kRecheckPass && col < d) {
+                    double sm = 0.0;
+                    for (int sg = 0; sg < G; ++sg) sm += src[(int64_t)sg * A.d_pad + col];
+                    add_squares(sm, tp[col], ssS, ssL);
+                }
+            }
+        const double s1 = block_sum(ssS, red), s2 = block_sum(ssL, red);
+        if (t == 0) recheck_decide(pd, A.st[p], p, row, s1, s2, d, A.gd, A.alternative, A.cnt, A.Tw);
+    }
 }
 
 int recheck_segments(int max_np) { return ((max_np + 31) / 32 + kSegWords - 1) / kSegWords; }
 
-int recheck_seg_flags(int max_np) {
-    const int g = recheck_segments(max_np);
-    return g > 1 ? kRecheckSegSlots / g : 0;
+int64_t recheck_slots(int npairs, int d_pad) {
+    // a single pair has few flags; a batch gets up to 8192 slots within 128 MiB
+    if (npairs <= 1) return kRecheckSlotsSingle;
+    const int64_t fit = ((int64_t)128 << 20) / ((int64_t)8 * d_pad);
+    return fit < kRecheckSlotsSingle ? kRecheckSlotsSingle : fit > 8192 ? 8192 : fit;
 }
 
-hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp,
-                          int npairs, const PairState* st, const double* v, const double* t64,
-                          const double* coef, const uint32_t* mask, const uint32_t* flags,
-                          const uint32_t* nflag, int64_t max_flags, int max_np, double* rseg, int d,
-                          int gd, int alternative, PairCount* cnt, double* Tw, hipStream_t s) {
+hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp, int npairs,
+                          const PairState* st, const double* v, const double* t64, const double* coef,
+                          const uint32_t* mask, const uint32_t* flags, const uint32_t* nflag, int64_t* plan,
+                          int64_t max_flags, int max_np, double* rseg, int64_t slots, int d, int gd,
+                          int alternative, PairCount* cnt, double* Tw, hipStream_t s) {
     if (max_flags <= 0) return hipSuccess;
+    if (!plan || npairs < 1) return hipErrorInvalidValue;
     const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
-    const int g_max = recheck_segments(max_np);
-    int f_seg = rseg ? recheck_seg_flags(max_np) : 0;
-    if (f_seg > max_flags) f_seg = (int)max_flags;
-    // enough work-groups for every segment of the segmented flags
-    const int64_t want = max_flags + (int64_t)f_seg * (g_max - 1);
+    const int64_t target = 2 * (int64_t)device_cus();
+    // FP64 rows take one flag per item (a group's accumulators would not fit
+    // the registers)
+    const int gmax = input_dtype == HBT_IN_F64 ? 1 : kRecheckGroup;
+    hipLaunchKernelGGL(k_recheck_plan, dim3(1), dim3(1024), 0, s, pairs, npairs, nflag, rseg ? slots : (int64_t)0,
+                       target, gmax, plan);
+    const RecheckArgs A{pairs, bp, npairs, st, v, t64, coef, mask, flags, nflag, plan,
+                        d, d_pad, gd, alternative, rseg, cnt, Tw};
+    // the item count is known on the device only: a grid for the largest
+    // count, whose work-groups without an item return at once
+    const int64_t want = max_flags * (int64_t)recheck_segments(max_np);
     const unsigned g = (unsigned)(want < 4096 ? want : 4096);
     if (input_dtype == HBT_IN_F64)
-        hipLaunchKernelGGL(k_recheck<double>, dim3(g), dim3(kRecheckThreads), 0, s, pairs, bp, npairs,
-                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, rseg, f_seg,
-                           g_max, cnt, Tw);
+        hipLaunchKernelGGL(k_recheck<double>, dim3(g), dim3(kRecheckThreads), 0, s, A);
     else
-        hipLaunchKernelGGL(k_recheck<float>, dim3(g), dim3(kRecheckThreads), 0, s, pairs, bp, npairs,
-                           st, v, t64, coef, mask, flags, nflag, d, d_pad, gd, alternative, rseg, f_seg,
-                           g_max, cnt, Tw);
-    if (f_seg > 0)
-        hipLaunchKernelGGL(k_recheck_finish, dim3((unsigned)f_seg), dim3(kRecheckThreads), 0, s, pairs, bp,
-                           npairs, st, t64, mask, flags, nflag, d, d_pad, gd, alternative, rseg, f_seg,
-                           g_max, cnt, Tw);
+        hipLaunchKernelGGL(k_recheck<float>, dim3(g), dim3(kRecheckThreads), 0, s, A);
+    if (rseg) {
+        // a segmented flag takes at least two slots
+        int64_t fw = slots / 2 < max_flags ? slots / 2 : max_flags;
+        if (fw > 4096) fw = 4096;
+        if (fw > 0)
+            hipLaunchKernelGGL(k_recheck_finish, dim3((unsigned)fw), dim3(kRecheckThreads), 0, s, A);
+    }
     return hipGetLastError();
 }
 
