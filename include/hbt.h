@@ -276,6 +276,14 @@ hbt_status hbt_perm_test_clouds(int64_t nclouds, const void* Z_all, const int64_
  * Errors: HBT_ERR_ARG (chunks outside [0, 64]). */
 hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous);
 
+/* The FP64 recheck spreads its work in one of two ways, with the same bits:
+ * the flags of a pair whose segment sums fit the workspace's slots become
+ * one work item per group of flags and 512-row segment, the others one work
+ * item per flag over all segments.  The environment variable
+ * HBT_RECHECK_SLOTS (a count, read by every call) caps the slots a call
+ * uses, 0 sending every flag down the second way; results do not depend on
+ * it. */
+
 /* hbt_recheck_band: the half-width *eps (host double) of the band around the
  * decision threshold inside which a split's T_b, computed by `precision` and
  * `stat_route`, is re-evaluated in FP64 (the count follows the FP64 statistic

@@ -2,6 +2,7 @@
 // plan tables and the launch sequence of a test.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -696,6 +697,20 @@ struct Fork {
     }
 };
 
+// Segment slots of the recheck: what the workspace holds, or fewer when the
+// environment variable HBT_RECHECK_SLOTS asks for fewer (0: every flag is
+// done whole by one work-group).  The results do not depend on it; it exists
+// to exercise both ways of spreading the work.
+int64_t recheck_slot_budget(int npairs, int d_pad) {
+    const int64_t held = recheck_slots(npairs, d_pad);
+    const char* e = getenv("HBT_RECHECK_SLOTS");
+    if (!e || !*e) return held;
+    char* end = nullptr;
+    const long long v = strtoll(e, &end, 10);
+    if (end == e || v < 0) return held;
+    return v < held ? (int64_t)v : held;
+}
+
 // The stages after the group sums: statistic and counts, recheck, null
 // moments, p-values.
 hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_params* common,
@@ -726,7 +741,7 @@ hbt_status batched_epilogue(const Plan& P, const Workspace& w, const hbt_perm_pa
     if (!no_recheck) {
         StageTimer t_(HBT_STAGE_RECHECK, s);
         HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, np, w.st, w.v, w.t64, w.coef, w.mask, w.flags,
-                               w.nflag, w.rplan, P.block_rows, P.max_np, w.rseg, recheck_slots(np, P.d_pad),
+                               w.nflag, w.rplan, P.block_rows, P.max_np, w.rseg, recheck_slot_budget(np, P.d_pad),
                                P.d, common->gd, common->alternative,
                                w.cnt, w.tw, s));
     }
@@ -1079,7 +1094,7 @@ hbt_status hbt_perm_test(const void* X, const void* Y, const hbt_perm_params* pr
         if (!no_recheck) {
             StageTimer t_(HBT_STAGE_RECHECK, s);
             HIP_TRY(launch_recheck(P.input_dtype, w.pairs, w.bp, 1, w.st, w.v, w.t64, w.coef, w.mask,
-                                   w.flags, w.nflag, w.rplan, nb, P.max_np, w.rseg, recheck_slots(1, P.d_pad),
+                                   w.flags, w.nflag, w.rplan, nb, P.max_np, w.rseg, recheck_slot_budget(1, P.d_pad),
                                    P.d, prm->gd, prm->alternative, w.cnt, w.tw, s));
         }
         { StageTimer t_(HBT_STAGE_OTHER, s); HIP_TRY(launch_moments(1, w.bp, w.st, w.tw, w.cnt, s)); }

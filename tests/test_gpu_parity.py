@@ -619,21 +619,28 @@ def test_pairs_with_equal_sizes_and_index_share_their_splits():
             _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
 
 
-def test_recheck_value_does_not_depend_on_how_it_is_spread():
-    """A flagged split's FP64 group sum is the sum of 512-row segment sums in
-    segment order, whether one work-group walks every segment (flags past the
-    segmented quota of a call) or each segment is a work item of its own (the
-    first flags of a call).  In the batched call below more flags are raised
-    than the quota, so some are done whole there, while a single-pair call
-    segments all of its few flags: their results must agree bit for bit."""
-    b = synth.batch_512_d768(limit=range(96))
+def test_recheck_value_does_not_depend_on_how_it_is_spread(monkeypatch):
+    """A flagged split's FP64 group sum is formed in one order: per wave its
+    rows of a 512-row segment in ascending order, the segment's wave sums in
+    wave order, the segments in order.  The benchmark batch raises enough
+    flags for the recheck to take them in groups of two, segment by segment;
+    with HBT_RECHECK_SLOTS=0 every flag is one work item over all its
+    segments; a single-pair call takes its few flags one by one, segment by
+    segment.  Counts, n_recheck and the null moments (which hold the
+    rechecked T_b) must agree bit for bit."""
+    b = synth.batch_512_d768()
     print(f"recheck spread: {b.npairs} pairs of the 512-pair workload", flush=True)
-    res = hbt.perm_test_batched(_dev(b.Z), b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
-    # the segmented quota: 256 workspace slots over the segments of the largest pair
-    quota = 256 // (((int(max(b.n + b.m)) + 127) // 128 * 128 // 32 + 15) // 16)
-    assert int(res["n_recheck"].sum()) > quota
+    Z = _dev(b.Z)
+    res = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
+    assert int(res["n_recheck"].sum()) >= 1000  # flag segments enough for groups of two
+    monkeypatch.setenv("HBT_RECHECK_SLOTS", "0")
+    whole = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
+    monkeypatch.delenv("HBT_RECHECK_SLOTS")
+    del Z
+    for f in ["count", "n_recheck", "t_mean", "t_sd", "status"]:
+        assert np.array_equal(whole[f], res[f]), f
     checked = 0
-    for p in np.nonzero(res["n_recheck"] > 0)[0][:12]:
+    for p in np.nonzero(res["n_recheck"] > 1)[0][:8]:
         pr = b.pair(int(p))
         one = hbt.perm_test(_dev(pr.X), _dev(pr.Y), pr.B, seed=b.seed, pair_index=pr.pair_index,
                             precision="bf16x2")
