@@ -340,38 +340,41 @@ __device__ void recheck_decide(const PairDesc& pd, const PairState& q, int p, in
 //   [4][0] the group size.
 // A pair is segmented when it has more than one segment and its flag
 // segments, added to those of the pairs before it, fit `slots`.
-__device__ __forceinline__ int64_t block_scan1024(int64_t x, int64_t* sh, int64_t* total) {
+template <int NT>
+__device__ __forceinline__ int64_t block_scan(int64_t x, int64_t* sh, int64_t* total) {
     const int t = threadIdx.x;
     sh[t] = x;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
+    for (int o = 1; o < NT; o <<= 1) {
         const int64_t y = t >= o ? sh[t - o] : 0;
         __syncthreads();
         sh[t] += y;
         __syncthreads();
     }
     const int64_t r = sh[t];
-    *total = sh[1023];
+    *total = sh[NT - 1];
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(1024) void k_recheck_plan(const PairDesc* __restrict__ pairs, int npairs,
-                                                       const uint32_t* __restrict__ nflag, int64_t slots,
-                                                       int64_t target, int gmax, int64_t* __restrict__ plan) {
-    __shared__ int64_t sh[1024];
+// NT threads: 64 for calls of at most 64 pairs (a single pair), else 1024
+template <int NT>
+__global__ __launch_bounds__(NT) void k_recheck_plan(const PairDesc* __restrict__ pairs, int npairs,
+                                                     const uint32_t* __restrict__ nflag, int64_t slots,
+                                                     int64_t target, int gmax, int64_t* __restrict__ plan) {
+    __shared__ int64_t sh[NT];
     const int t = threadIdx.x;
     const int np1 = npairs + 1;
     int64_t x = 0;
-    for (int p = t; p < npairs; p += 1024) x += (int64_t)nflag[p] * pair_segs(pairs[p]);
+    for (int p = t; p < npairs; p += NT) x += (int64_t)nflag[p] * pair_segs(pairs[p]);
     int64_t all;
-    (void)block_scan1024(x, sh, &all);
+    (void)block_scan<NT>(x, sh, &all);
     // flags alone while there are few flag segments; up to gmax per item when
     // there are enough for `target` work-groups anyway
     const int64_t gq = all / (target > 0 ? target : 1);
     const int g = gq < 1 ? 1 : gq > gmax ? gmax : (int)gq;
     int64_t bw = 0, bs = 0, bc = 0, bf = 0;
-    for (int p0 = 0; p0 < npairs; p0 += 1024) {
+    for (int p0 = 0; p0 < npairs; p0 += NT) {
         const int p = p0 + t;
         int64_t F = 0, G = 0;
         if (p < npairs) {
@@ -381,12 +384,12 @@ __global__ __launch_bounds__(1024) void k_recheck_plan(const PairDesc* __restric
         const int64_t J = (F + g - 1) / g;
         const int64_t cand = (G > 1 && F > 0) ? F * G : 0;
         int64_t tc, tw, ts, tf;
-        const int64_t ic = block_scan1024(cand, sh, &tc);
+        const int64_t ic = block_scan<NT>(cand, sh, &tc);
         const bool seg = cand > 0 && bc + ic <= slots;
         const int64_t wi = seg ? 0 : F, si = seg ? J * G : 0, fi = seg ? F : 0;
-        const int64_t iw = block_scan1024(wi, sh, &tw);
-        const int64_t is = block_scan1024(si, sh, &ts);
-        const int64_t jf = block_scan1024(fi, sh, &tf);
+        const int64_t iw = block_scan<NT>(wi, sh, &tw);
+        const int64_t is = block_scan<NT>(si, sh, &ts);
+        const int64_t jf = block_scan<NT>(fi, sh, &tf);
         if (p < npairs) {
             plan[p] = bw + iw - wi;
             plan[np1 + p] = bs + is - si;
@@ -660,14 +663,21 @@ hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPai
     // FP64 rows take one flag per item (a group's accumulators would not fit
     // the registers)
     const int gmax = input_dtype == HBT_IN_F64 ? 1 : kRecheckGroup;
-    hipLaunchKernelGGL(k_recheck_plan, dim3(1), dim3(1024), 0, s, pairs, npairs, nflag, rseg ? slots : (int64_t)0,
-                       target, gmax, plan);
+    if (npairs <= 64)
+        hipLaunchKernelGGL(k_recheck_plan<64>, dim3(1), dim3(64), 0, s, pairs, npairs, nflag,
+                           rseg ? slots : (int64_t)0, target, gmax, plan);
+    else
+        hipLaunchKernelGGL(k_recheck_plan<1024>, dim3(1), dim3(1024), 0, s, pairs, npairs, nflag,
+                           rseg ? slots : (int64_t)0, target, gmax, plan);
     const RecheckArgs A{pairs, bp, npairs, st, v, t64, coef, mask, flags, nflag, plan,
                         d, d_pad, gd, alternative, rseg, cnt, Tw};
     // the item count is known on the device only: a grid for the largest
-    // count, whose work-groups without an item return at once
+    // count, whose work-groups without an item return at once (a single
+    // pair, whose flags are few, gets at most 1024; the work-groups loop over
+    // the items when there are more)
+    const int64_t gmax_grid = npairs == 1 ? 1024 : 4096;
     const int64_t want = max_flags * (int64_t)recheck_segments(max_np);
-    const unsigned g = (unsigned)(want < 4096 ? want : 4096);
+    const unsigned g = (unsigned)(want < gmax_grid ? want : gmax_grid);
     if (input_dtype == HBT_IN_F64)
         hipLaunchKernelGGL(k_recheck<double>, dim3(g), dim3(kRecheckThreads), 0, s, A);
     else
@@ -675,7 +685,7 @@ hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPai
     if (rseg) {
         // a segmented flag takes at least two slots
         int64_t fw = slots / 2 < max_flags ? slots / 2 : max_flags;
-        if (fw > 4096) fw = 4096;
+        if (fw > gmax_grid) fw = gmax_grid;
         if (fw > 0)
             hipLaunchKernelGGL(k_recheck_finish, dim3((unsigned)fw), dim3(kRecheckThreads), 0, s, A);
     }
