@@ -277,15 +277,17 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
 // spread never changes a bit:
 //   * a work item takes a group of up to kRecheckGroup flags of one pair and
 //     reads each row of a segment once for all of them (a row is read when
-//     any of them holds it): a pair with F flags reads its rows about
-//     F / 4 times rather than F times;
+//     any of them holds it), so a pair with F flags reads its rows about
+//     F / 2 times rather than F times (FP32 rows; FP64 rows take one flag
+//     per item);
 //   * a pair whose flag segments fit the workspace slots has one item per
 //     group and segment, whose sums go to the slots and are added by
 //     k_recheck_finish; every other pair has one item per flag that walks
 //     all segments with running totals;
-//   * the group size is 4 when the call has many flag segments and smaller
-//     when it has few, so that a call with a handful of flags still spreads
-//     over many work-groups (k_recheck_plan decides it on the device).
+//   * the group size is 2 when the call has enough flag segments to fill the
+//     GPU without grouping, 1 otherwise, so that a call with a handful of
+//     flags still spreads over many work-groups (k_recheck_plan decides it
+//     on the device).
 // ---------------------------------------------------------------------------
 constexpr int kRecheckWaves = 8;
 constexpr int kRecheckThreads = 64 * kRecheckWaves;
