@@ -633,12 +633,15 @@ def test_recheck_value_does_not_depend_on_how_it_is_spread(monkeypatch):
     Z = _dev(b.Z)
     res = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
     assert int(res["n_recheck"].sum()) >= 1000  # flag segments enough for groups of two
-    monkeypatch.setenv("HBT_RECHECK_SLOTS", "0")
-    whole = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
+    # 0 slots: every flag whole; 2000 slots: the first pairs' flags by
+    # segment, the others whole, in the same call
+    for slots in ["0", "2000"]:
+        monkeypatch.setenv("HBT_RECHECK_SLOTS", slots)
+        other = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
+        for f in ["count", "n_recheck", "t_mean", "t_sd", "status"]:
+            assert np.array_equal(other[f], res[f]), (slots, f)
     monkeypatch.delenv("HBT_RECHECK_SLOTS")
     del Z
-    for f in ["count", "n_recheck", "t_mean", "t_sd", "status"]:
-        assert np.array_equal(whole[f], res[f]), f
     checked = 0
     for p in np.nonzero(res["n_recheck"] > 1)[0][:8]:
         pr = b.pair(int(p))
@@ -648,6 +651,16 @@ def test_recheck_value_does_not_depend_on_how_it_is_spread(monkeypatch):
             assert one[f] == res[p][f], (int(p), f, one[f], res[p][f])
         checked += 1
     assert checked > 0
+    # a single pair of ten segments: its flags by segment, or each whole
+    pr = synth.null_pair_d1024()
+    X, Y = _dev(pr.X), _dev(pr.Y)
+    seg = hbt.perm_test(X, Y, pr.B, seed=pr.seed, precision="bf16x2", want_T="f64")
+    monkeypatch.setenv("HBT_RECHECK_SLOTS", "0")
+    whole = hbt.perm_test(X, Y, pr.B, seed=pr.seed, precision="bf16x2", want_T="f64")
+    monkeypatch.delenv("HBT_RECHECK_SLOTS")
+    assert seg["n_recheck"] > 0
+    for f in ["count", "n_recheck", "t_mean", "t_sd", "status"]:
+        assert whole[f] == seg[f], f
 
 
 def test_single_pair_wide_and_narrow_tiles_agree():
