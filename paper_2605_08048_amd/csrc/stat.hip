@@ -266,14 +266,15 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
 //
 // k_stat lists the flags of each pair from the pair's first block row.  The
 // rows of a pair are cut into segments of kSegWords mask words (512 pooled
-// rows); wave w of a work-group takes words w and w + 8 of a segment, and
-// each lane columns c0 + 64 u + lane (u < 12) of each pass of kRecheckPass
-// columns.  For each flag and column, sigma_small is formed in one order: per
-// wave, its rows of the segment in ascending order; the segment's sum is the
-// 8 wave sums added in wave order; then the segment sums are added in
-// segment order.  For the squares, thread t of the work-group holds columns
-// c0 + t and c0 + t + 512 of each pass (passes in order, c0 + t first); the
-// work-group adds its threads' squares in a fixed tree.  How the work is
+// rows); wave w of a work-group takes words w, w + 4, w + 8 and w + 12 of a
+// segment, and each lane columns c0 + 64 u + lane (u < 12) of each pass of
+// kRecheckPass columns.  For each flag and column, sigma_small is formed in
+// one order: per wave, its rows of the segment in ascending order; the
+// segment's sum is the 4 wave sums added in wave order; then the segment
+// sums are added in segment order.  For the squares, thread t of the
+// work-group holds columns c0 + t, c0 + t + 256 and c0 + t + 512 of each
+// pass (passes in order, then in that order); the work-group adds its
+// threads' squares in a fixed tree.  How the work is
 // spread never changes a bit:
 //   * a work item takes a group of up to kRecheckGroup flags of one pair and
 //     reads each row of a segment once for all of them (a row is read when
@@ -289,9 +290,11 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
 //     flags still spreads over many work-groups (k_recheck_plan decides it
 //     on the device).
 // ---------------------------------------------------------------------------
-constexpr int kRecheckWaves = 8;
+constexpr int kRecheckWaves = 4;
 constexpr int kRecheckThreads = 64 * kRecheckWaves;
 constexpr int kRecheckPass = 768;  // columns per pass (12 per lane)
+constexpr int kRecheckCols = kRecheckPass / kRecheckThreads;  // columns per thread in the sums
+static_assert(kRecheckPass % kRecheckThreads == 0, "a pass is whole columns per thread");
 constexpr int kSegWords = 16;
 constexpr int kRecheckGroup = 2;   // flags per work item at most
 constexpr int kRecheckRows = 4;    // rows in flight per wave
@@ -300,8 +303,8 @@ constexpr int kRecheckRows = 4;    // rows in flight per wave
 __device__ __forceinline__ int pair_words(const PairDesc& pd) { return (pd.n + pd.m + pd.ygap + 31) >> 5; }
 __device__ __forceinline__ int pair_segs(const PairDesc& pd) { return (pair_words(pd) + kSegWords - 1) / kSegWords; }
 
-// Sum over the 512 threads of a work-group in a fixed order (a butterfly in
-// each wave, then the 8 waves in order); every thread gets the sum.
+// Sum over the threads of a work-group in a fixed order (a butterfly in each
+// wave, then the waves in order); every thread gets the sum.
 __device__ __forceinline__ double block_sum(double x, double* red) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     __syncthreads();  // the previous sum's readers are done with red
@@ -468,14 +471,16 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
             const int col = c0 + 64 * u + lane;
             vc[u] = col < d ? vp[col] : 0.0;
         }
-        double tot[2] = {0.0, 0.0};
+        double tot[kRecheckCols];
+#pragma unroll
+        for (int k = 0; k < kRecheckCols; ++k) tot[k] = 0.0;
         for (int sg = sg0; sg < sg1; ++sg) {
             double acc[FG][kU];
 #pragma unroll
             for (int f = 0; f < FG; ++f)
 #pragma unroll
                 for (int u = 0; u < kU; ++u) acc[f][u] = 0.0;
-            // this wave's words of the segment: w0 and w0 + 8
+            // this wave's words of the segment: w0, w0 + 4, w0 + 8, w0 + 12
             const int w0 = sg * kSegWords + wave, we = min(W, (sg + 1) * kSegWords);
             int w = w0;
             uint32_t bits[FG], U = 0;
@@ -499,7 +504,7 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
                 uint32_t mem[kRecheckRows];
 #pragma unroll
                 for (int k = 0; k < kRecheckRows; ++k) {
-                    if (!U && w == w0) load_word(w += kRecheckWaves);
+                    while (!U && w + kRecheckWaves < we) load_word(w += kRecheckWaves);
                     if (U) {
                         const int b = __builtin_ctz(U);
                         U &= U - 1u;
@@ -542,7 +547,7 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
                     }
                 }
             }
-            // the segment's sums: the 8 wave sums in wave order, per flag
+            // the segment's sums: the wave sums in wave order, per flag
 #pragma unroll
             for (int f = 0; f < FG; ++f) {
                 if (f >= nf) break;
@@ -550,9 +555,9 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
                 for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = acc[f][u];
                 __syncthreads();
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
+                for (int k = 0; k < kRecheckCols; ++k) {
                     const int cc = t + kRecheckThreads * k;
-                    if (cc < kRecheckPass) {
+                    {
                         double sm = 0.0;
 #pragma unroll
                         for (int q = 0; q < kRecheckWaves; ++q) sm += part[q][cc];
@@ -567,9 +572,9 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
         }
         if (whole) {
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < kRecheckCols; ++k) {
                 const int cc = t + kRecheckThreads * k;
-                if (cc < kRecheckPass && c0 + cc < d) add_squares(tot[k], tp[c0 + cc], ssS, ssL);
+                if (c0 + cc < d) add_squares(tot[k], tp[c0 + cc], ssS, ssL);
             }
         }
     }
@@ -630,10 +635,10 @@ __global__ __launch_bounds__(kRecheckThreads) void k_recheck_finish(RecheckArgs 
         double ssS = 0.0, ssL = 0.0;
         for (int c0 = 0; c0 < d; c0 += kRecheckPass)
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < kRecheckCols; ++k) {
                 const int cc = t + kRecheckThreads * k;
                 const int col = c0 + cc;
-                if (cc < kRecheckPass && col < d) {
+                if (col < d) {
                     double sm = 0.0;
                     for (int sg = 0; sg < G; ++sg) sm += src[(int64_t)sg * A.d_pad + col];
                     add_squares(sm, tp[col], ssS, ssL);
