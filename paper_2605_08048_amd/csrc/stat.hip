@@ -297,7 +297,7 @@ constexpr int kRecheckCols = kRecheckPass / kRecheckThreads;  // columns per thr
 static_assert(kRecheckPass % kRecheckThreads == 0, "a pass is whole columns per thread");
 constexpr int kSegWords = 16;
 constexpr int kRecheckGroup = 2;   // flags per work item at most
-constexpr int kRecheckRows = 4;    // rows in flight per wave
+constexpr int kRecheckRows = 4;    // rows in flight per wave (8 for one FP32 flag per item)
 
 // Segments of a pair's pooled mask positions.
 __device__ __forceinline__ int pair_words(const PairDesc& pd) { return (pd.n + pd.m + pd.ygap + 31) >> 5; }
@@ -441,6 +441,9 @@ template <typename Tin, int FG>
 __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg0, int sg1, bool whole,
                              double (*part)[kRecheckPass], double* red) {
     constexpr int kU = kRecheckPass / 64;  // columns per lane per pass
+    // rows in flight per wave: a lone flag's item has the registers for twice
+    // as many (the order in which rows are added does not change)
+    constexpr int kRows = (FG == 1 && sizeof(Tin) == 4) ? 2 * kRecheckRows : kRecheckRows;
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
@@ -500,10 +503,10 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
             };
             load_word(w);
             for (;;) {
-                int rows[kRecheckRows];
-                uint32_t mem[kRecheckRows];
+                int rows[kRows];
+                uint32_t mem[kRows];
 #pragma unroll
-                for (int k = 0; k < kRecheckRows; ++k) {
+                for (int k = 0; k < kRows; ++k) {
                     while (!U && w + kRecheckWaves < we) load_word(w += kRecheckWaves);
                     if (U) {
                         const int b = __builtin_ctz(U);
@@ -520,10 +523,10 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
                 }
                 if (rows[0] < 0) break;
                 // columns are clamped to the row (no branch around a load)
-                Tin z[kRecheckRows][kU];
-                double kc[kRecheckRows];
+                Tin z[kRows][kU];
+                double kc[kRows];
 #pragma unroll
-                for (int k = 0; k < kRecheckRows; ++k) {
+                for (int k = 0; k < kRows; ++k) {
                     int i = rows[k] < 0 ? 0 : rows[k];
                     if (i >= pd.n) i -= pd.ygap;  // Y's mask positions to pooled items
                     const bool isx = i < pd.n;
@@ -536,7 +539,7 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
                     }
                 }
 #pragma unroll
-                for (int k = 0; k < kRecheckRows; ++k) {
+                for (int k = 0; k < kRows; ++k) {
                     if (!mem[k]) continue;
 #pragma unroll
                     for (int u = 0; u < kU; ++u) {
