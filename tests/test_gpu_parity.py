@@ -406,6 +406,33 @@ def test_batched_matches_oracle_per_pair():
                 _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
 
 
+@pytest.mark.parametrize("prec", ["f64", "bf16x2"])
+def test_batched_fp64_rows_match_oracle_per_pair(prec):
+    """FP64 input rows in a batch (the recheck gathers them as doubles, one
+    flag per work item; the FP64 product's band is too narrow to flag any):
+    counts, T_obs and moments against the oracle on the same values."""
+    rng = np.random.default_rng(18)
+    pairs = []
+    for p in range(6):
+        n = int(rng.integers(2, 700))
+        m = int(rng.integers(2, 700))
+        X, Y = _pair(n, m, 80, kx=rng.uniform(1.5, 3), ky=rng.uniform(1.5, 3), seed=200 + p)
+        pairs.append(synth.Pair(X, Y, B=int(rng.integers(1000, 2500)), pair_index=p))
+    bt = synth.pack_batch(pairs, 80)
+    print(f"batched FP64 rows {prec}: {len(pairs)} pairs", flush=True)
+    res = hbt.perm_test_batched(torch.from_numpy(bt.Z.astype(np.float64)).to(DEV), bt.row_offset, bt.n, bt.m,
+                                bt.B, seed=4, precision=prec)
+    if prec == "bf16x2":
+        assert int(res["n_recheck"].sum()) > 0
+    for p, pr in enumerate(pairs):
+        o = O.perm_test(pr.X, pr.Y, pr.B, seed=4, pair=p, want_T=True)
+        assert res[p]["status"] == 0
+        assert abs(res[p]["t_obs"] - o["t_obs"]) <= 1e-12 * max(1, abs(o["t_obs"]))
+        assert abs(res[p]["count"] - o["count"]) <= _tie_band(o["T"], o["t_obs"]), (prec, p)
+        at = O.perm_stats_at(pr.X, pr.Y, np.arange(pr.B), seed=4, pair=p)
+        _check_extras(res[p], o, pr.X.shape[0], pr.Y.shape[0], _scale(pr.X, pr.Y, at), prec)
+
+
 @pytest.mark.parametrize("d", [64, 200, 1030, 8192])
 def test_batched_storage_group_boundaries(d):
     """The Z storage is written in 32-row groups: the column-sum pass stores the
