@@ -183,12 +183,12 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
                             void* T_out = nullptr, int T_mode = 0);
 // FP64 recheck of the flagged splits.  flags: per pair, from the pair's
 // first block row, the split rows k_stat flagged; nflag: their number per
-// pair.  plan: 4 (npairs + 1) + 1 int64 of work plan (written here).  rseg:
+// pair.  plan: 4 (npairs + 1) int64 of work plan (written here).  rseg:
 // `slots` vectors of d_pad doubles (per flag and segment sums; nullptr when
 // no pair has more than one segment); the value of each flag's sums does not
 // depend on it.
 constexpr int kRecheckSlotsSingle = 2048;
-inline int64_t recheck_plan_words(int npairs) { return 4 * ((int64_t)npairs + 1) + 1; }
+inline int64_t recheck_plan_words(int npairs) { return 4 * ((int64_t)npairs + 1); }
 int recheck_segments(int max_np);
 int64_t recheck_slots(int npairs, int d_pad);
 hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPair* bp, int npairs,

@@ -276,19 +276,11 @@ hipError_t launch_stat_lazy(bool refined, const PairDesc* pairs, const BlockPair
 // pass (passes in order, then in that order); the work-group adds its
 // threads' squares in a fixed tree.  How the work is
 // spread never changes a bit:
-//   * a work item takes a group of up to kRecheckGroup flags of one pair and
-//     reads each row of a segment once for all of them (a row is read when
-//     any of them holds it), so a pair with F flags reads its rows about
-//     F / 2 times rather than F times (FP32 rows; FP64 rows take one flag
-//     per item);
-//   * a pair whose flag segments fit the workspace slots has one item per
-//     group and segment, whose sums go to the slots and are added by
+//   * a pair whose flag segments fit the workspace slots has one work item
+//     per flag and segment, whose sums go to the slots and are added by
 //     k_recheck_finish; every other pair has one item per flag that walks
-//     all segments with running totals;
-//   * the group size is 2 when the call has enough flag segments to fill the
-//     GPU without grouping, 1 otherwise, so that a call with a handful of
-//     flags still spreads over many work-groups (k_recheck_plan decides it
-//     on the device).
+//     all segments with running totals (k_recheck_plan lays the items out on
+//     the device, from the per-pair flag counts).
 // ---------------------------------------------------------------------------
 constexpr int kRecheckWaves = 4;
 constexpr int kRecheckThreads = 64 * kRecheckWaves;
@@ -296,8 +288,7 @@ constexpr int kRecheckPass = 768;  // columns per pass (12 per lane)
 constexpr int kRecheckCols = kRecheckPass / kRecheckThreads;  // columns per thread in the sums
 static_assert(kRecheckPass % kRecheckThreads == 0, "a pass is whole columns per thread");
 constexpr int kSegWords = 16;
-constexpr int kRecheckGroup = 2;   // flags per work item at most
-constexpr int kRecheckRows = 4;    // rows in flight per wave (8 for one FP32 flag per item)
+constexpr int kRecheckRows = 8;    // rows in flight per wave (4 for FP64 rows)
 
 // Segments of a pair's pooled mask positions.
 __device__ __forceinline__ int pair_words(const PairDesc& pd) { return (pd.n + pd.m + pd.ygap + 31) >> 5; }
@@ -339,10 +330,9 @@ __device__ void recheck_decide(const PairDesc& pd, const PairState& q, int p, in
     Tw[row] = T;
 }
 
-// The work plan (one work-group), five arrays of npairs + 1 int64 in `plan`:
+// The work plan (one work-group), four arrays of npairs + 1 int64 in `plan`:
 //   [0] whole items, [1] segmented items, [2] slots, [3] segmented flags:
-//       exclusive prefixes over the pairs, totals at index npairs;
-//   [4][0] the group size.
+//       exclusive prefixes over the pairs, totals at index npairs.
 // A pair is segmented when it has more than one segment and its flag
 // segments, added to those of the pairs before it, fit `slots`.
 template <int NT>
@@ -366,18 +356,10 @@ __device__ __forceinline__ int64_t block_scan(int64_t x, int64_t* sh, int64_t* t
 template <int NT>
 __global__ __launch_bounds__(NT) void k_recheck_plan(const PairDesc* __restrict__ pairs, int npairs,
                                                      const uint32_t* __restrict__ nflag, int64_t slots,
-                                                     int64_t target, int gmax, int64_t* __restrict__ plan) {
+                                                     int64_t* __restrict__ plan) {
     __shared__ int64_t sh[NT];
     const int t = threadIdx.x;
     const int np1 = npairs + 1;
-    int64_t x = 0;
-    for (int p = t; p < npairs; p += NT) x += (int64_t)nflag[p] * pair_segs(pairs[p]);
-    int64_t all;
-    (void)block_scan<NT>(x, sh, &all);
-    // flags alone while there are few flag segments; up to gmax per item when
-    // there are enough for `target` work-groups anyway
-    const int64_t gq = all / (target > 0 ? target : 1);
-    const int g = gq < 1 ? 1 : gq > gmax ? gmax : (int)gq;
     int64_t bw = 0, bs = 0, bc = 0, bf = 0;
     for (int p0 = 0; p0 < npairs; p0 += NT) {
         const int p = p0 + t;
@@ -386,12 +368,11 @@ __global__ __launch_bounds__(NT) void k_recheck_plan(const PairDesc* __restrict_
             F = nflag[p];
             G = pair_segs(pairs[p]);
         }
-        const int64_t J = (F + g - 1) / g;
         const int64_t cand = (G > 1 && F > 0) ? F * G : 0;
         int64_t tc, tw, ts, tf;
         const int64_t ic = block_scan<NT>(cand, sh, &tc);
         const bool seg = cand > 0 && bc + ic <= slots;
-        const int64_t wi = seg ? 0 : F, si = seg ? J * G : 0, fi = seg ? F : 0;
+        const int64_t wi = seg ? 0 : F, si = seg ? F * G : 0, fi = seg ? F : 0;
         const int64_t iw = block_scan<NT>(wi, sh, &tw);
         const int64_t is = block_scan<NT>(si, sh, &ts);
         const int64_t jf = block_scan<NT>(fi, sh, &tf);
@@ -411,7 +392,6 @@ __global__ __launch_bounds__(NT) void k_recheck_plan(const PairDesc* __restrict_
         plan[np1 + npairs] = bs;
         plan[2 * np1 + npairs] = bc;
         plan[3 * np1 + npairs] = bf;
-        plan[4 * np1] = g;
     }
 }
 
@@ -433,17 +413,16 @@ struct RecheckArgs {
     double* Tw;
 };
 
-// One work item: flags [f0, f0 + nf) of pair p (nf <= FG), segments
-// [sg0, sg1).  Segmented items write each flag's segment sums to its slots;
-// whole items (FG = 1) keep running totals over every segment and decide the
-// flag.
-template <typename Tin, int FG>
-__device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg0, int sg1, bool whole,
+// One work item: flag j of pair p over segments [sg0, sg1).  Segmented items
+// write the flag's segment sums to its slots; whole items keep running
+// totals over every segment and decide the flag.
+template <typename Tin>
+__device__ void recheck_item(const RecheckArgs& A, int p, int64_t j, int sg0, int sg1, bool whole,
                              double (*part)[kRecheckPass], double* red) {
     constexpr int kU = kRecheckPass / 64;  // columns per lane per pass
-    // rows in flight per wave: a lone flag's item has the registers for twice
-    // as many (the order in which rows are added does not change)
-    constexpr int kRows = (FG == 1 && sizeof(Tin) == 4) ? 2 * kRecheckRows : kRecheckRows;
+    // rows in flight per wave (FP64 rows: half as many, for the registers;
+    // the order in which rows are added does not depend on it)
+    constexpr int kRows = sizeof(Tin) == 4 ? kRecheckRows : kRecheckRows / 2;
     const int t = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int lane = t & 63;
@@ -457,15 +436,9 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
     const double* vp = A.v + (int64_t)p * A.d_pad;
     const double* tp = A.t64 + (int64_t)p * A.d_pad;
     const double* cf = A.coef + pd.coef0;
-    const int64_t slot = whole ? 0 : A.plan[2 * (A.npairs + 1) + p] + (int64_t)f0 * G;
-    const uint32_t* mk[FG];
-    int64_t row0 = 0;
-#pragma unroll
-    for (int f = 0; f < FG; ++f) {
-        const int64_t row = A.flags[bq.mrow0 + f0 + (f < nf ? f : 0)];
-        if (f == 0) row0 = row;
-        mk[f] = mask_row(A.mask, bq, row, pd.Wp);
-    }
+    const int64_t slot = whole ? 0 : A.plan[2 * (A.npairs + 1) + p] + j * G;
+    const int64_t row = A.flags[bq.mrow0 + j];
+    const uint32_t* mk = mask_row(A.mask, bq, row, pd.Wp);
     double ssS = 0.0, ssL = 0.0;
     for (int c0 = 0; c0 < d; c0 += kRecheckPass) {
         double vc[kU];
@@ -478,47 +451,26 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
 #pragma unroll
         for (int k = 0; k < kRecheckCols; ++k) tot[k] = 0.0;
         for (int sg = sg0; sg < sg1; ++sg) {
-            double acc[FG][kU];
+            double acc[kU];
 #pragma unroll
-            for (int f = 0; f < FG; ++f)
-#pragma unroll
-                for (int u = 0; u < kU; ++u) acc[f][u] = 0.0;
+            for (int u = 0; u < kU; ++u) acc[u] = 0.0;
             // this wave's words of the segment: w0, w0 + 4, w0 + 8, w0 + 12
             const int w0 = sg * kSegWords + wave, we = min(W, (sg + 1) * kSegWords);
             int w = w0;
-            uint32_t bits[FG], U = 0;
-            auto load_word = [&](int ww) {
-                U = 0;
-                if (ww >= we) {
-#pragma unroll
-                    for (int f = 0; f < FG; ++f) bits[f] = 0u;
-                    return;
-                }
-                const uint32_t ib = item_bits(ww, pd.n, pd.m, pd.ygap);
-#pragma unroll
-                for (int f = 0; f < FG; ++f) {
-                    bits[f] = f < nf ? (mk[f][ww] ^ flip) & ib : 0u;
-                    U |= bits[f];
-                }
+            auto word_bits = [&](int ww) -> uint32_t {
+                return ww < we ? (mk[ww] ^ flip) & item_bits(ww, pd.n, pd.m, pd.ygap) : 0u;
             };
-            load_word(w);
+            uint32_t U = word_bits(w);
             for (;;) {
                 int rows[kRows];
-                uint32_t mem[kRows];
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
-                    while (!U && w + kRecheckWaves < we) load_word(w += kRecheckWaves);
+                    while (!U && w + kRecheckWaves < we) U = word_bits(w += kRecheckWaves);
                     if (U) {
-                        const int b = __builtin_ctz(U);
+                        rows[k] = 32 * w + __builtin_ctz(U);
                         U &= U - 1u;
-                        rows[k] = 32 * w + b;
-                        uint32_t mm = 0;
-#pragma unroll
-                        for (int f = 0; f < FG; ++f) mm |= ((bits[f] >> b) & 1u) << f;
-                        mem[k] = mm;
                     } else {
                         rows[k] = -1;
-                        mem[k] = 0;
                     }
                 }
                 if (rows[0] < 0) break;
@@ -540,38 +492,27 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
                 }
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
-                    if (!mem[k]) continue;
+                    if (rows[k] < 0) continue;
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const double x = fma(-kc[k], vc[u], (double)z[k][u]);
-#pragma unroll
-                        for (int f = 0; f < FG; ++f)
-                            if ((mem[k] >> f) & 1u) acc[f][u] += x;
-                    }
+                    for (int u = 0; u < kU; ++u) acc[u] += fma(-kc[k], vc[u], (double)z[k][u]);
                 }
             }
-            // the segment's sums: the wave sums in wave order, per flag
+            // the segment's sum: the wave sums in wave order
 #pragma unroll
-            for (int f = 0; f < FG; ++f) {
-                if (f >= nf) break;
+            for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = acc[u];
+            __syncthreads();
 #pragma unroll
-                for (int u = 0; u < kU; ++u) part[wave][64 * u + lane] = acc[f][u];
-                __syncthreads();
+            for (int k = 0; k < kRecheckCols; ++k) {
+                const int cc = t + kRecheckThreads * k;
+                double sm = 0.0;
 #pragma unroll
-                for (int k = 0; k < kRecheckCols; ++k) {
-                    const int cc = t + kRecheckThreads * k;
-                    {
-                        double sm = 0.0;
-#pragma unroll
-                        for (int q = 0; q < kRecheckWaves; ++q) sm += part[q][cc];
-                        if (whole)
-                            tot[k] += sm;
-                        else if (c0 + cc < d)
-                            A.rseg[(slot + (int64_t)f * G + sg) * A.d_pad + c0 + cc] = sm;
-                    }
-                }
-                __syncthreads();
+                for (int q = 0; q < kRecheckWaves; ++q) sm += part[q][cc];
+                if (whole)
+                    tot[k] += sm;
+                else if (c0 + cc < d)
+                    A.rseg[(slot + sg) * A.d_pad + c0 + cc] = sm;
             }
+            __syncthreads();
         }
         if (whole) {
 #pragma unroll
@@ -583,7 +524,7 @@ __device__ void recheck_item(const RecheckArgs& A, int p, int f0, int nf, int sg
     }
     if (whole) {
         const double s1 = block_sum(ssS, red), s2 = block_sum(ssL, red);
-        if (t == 0) recheck_decide(pd, A.st[p], p, row0, s1, s2, d, A.gd, A.alternative, A.cnt, A.Tw);
+        if (t == 0) recheck_decide(pd, A.st[p], p, row, s1, s2, d, A.gd, A.alternative, A.cnt, A.Tw);
     }
 }
 
@@ -594,26 +535,18 @@ __global__ __launch_bounds__(kRecheckThreads) void k_recheck(RecheckArgs A) {
     const int np1 = A.npairs + 1;
     const int64_t* wpre = A.plan;
     const int64_t* spre = A.plan + np1;
-    const int g = (int)A.plan[4 * np1];
     const int64_t NW = wpre[A.npairs], NS = spre[A.npairs];
     for (int64_t it = blockIdx.x; it < NW + NS; it += gridDim.x) {
         if (it < NW) {  // one flag, every segment
             const int p = upper_index(A.npairs, it, [&](int k) { return wpre[k]; });
-            recheck_item<Tin, 1>(A, p, (int)(it - wpre[p]), 1, 0, pair_segs(A.pairs[p]), true, part, red);
-        } else {  // a group of g flags, one segment
+            recheck_item<Tin>(A, p, it - wpre[p], 0, pair_segs(A.pairs[p]), true, part, red);
+        } else {  // one flag, one segment
             const int64_t x = it - NW;
             const int p = upper_index(A.npairs, x, [&](int k) { return spre[k]; });
             const int64_t r = x - spre[p];
             const int G = pair_segs(A.pairs[p]);
-            const int F = (int)A.nflag[p];
-            const int f0 = (int)(r / G) * g, sg = (int)(r % G);
-            if constexpr (sizeof(Tin) == 4) {
-                if (g > 1) {
-                    recheck_item<Tin, kRecheckGroup>(A, p, f0, min(g, F - f0), sg, sg + 1, false, part, red);
-                    continue;
-                }
-            }
-            recheck_item<Tin, 1>(A, p, f0, 1, sg, sg + 1, false, part, red);
+            const int sg = (int)(r % G);
+            recheck_item<Tin>(A, p, r / G, sg, sg + 1, false, part, red);
         }
     }
 }
@@ -669,16 +602,12 @@ hipError_t launch_recheck(int input_dtype, const PairDesc* pairs, const BlockPai
     if (max_flags <= 0) return hipSuccess;
     if (!plan || npairs < 1) return hipErrorInvalidValue;
     const int d_pad = (d + kDPad - 1) / kDPad * kDPad;
-    const int64_t target = 2 * (int64_t)device_cus();
-    // FP64 rows take one flag per item (a group's accumulators would not fit
-    // the registers)
-    const int gmax = input_dtype == HBT_IN_F64 ? 1 : kRecheckGroup;
     if (npairs <= 64)
         hipLaunchKernelGGL(k_recheck_plan<64>, dim3(1), dim3(64), 0, s, pairs, npairs, nflag,
-                           rseg ? slots : (int64_t)0, target, gmax, plan);
+                           rseg ? slots : (int64_t)0, plan);
     else
         hipLaunchKernelGGL(k_recheck_plan<1024>, dim3(1), dim3(1024), 0, s, pairs, npairs, nflag,
-                           rseg ? slots : (int64_t)0, target, gmax, plan);
+                           rseg ? slots : (int64_t)0, plan);
     const RecheckArgs A{pairs, bp, npairs, st, v, t64, coef, mask, flags, nflag, plan,
                         d, d_pad, gd, alternative, rseg, cnt, Tw};
     // the item count is known on the device only: a grid for the largest

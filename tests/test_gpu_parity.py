@@ -408,8 +408,8 @@ def test_batched_matches_oracle_per_pair():
 
 @pytest.mark.parametrize("prec", ["f64", "bf16x2"])
 def test_batched_fp64_rows_match_oracle_per_pair(prec):
-    """FP64 input rows in a batch (the recheck gathers them as doubles, one
-    flag per work item; the FP64 product's band is too narrow to flag any):
+    """FP64 input rows in a batch (the recheck gathers them as doubles; the
+    FP64 product's band is too narrow to flag any):
     counts, T_obs and moments against the oracle on the same values."""
     rng = np.random.default_rng(18)
     pairs = []
@@ -649,17 +649,18 @@ def test_pairs_with_equal_sizes_and_index_share_their_splits():
 def test_recheck_value_does_not_depend_on_how_it_is_spread(monkeypatch):
     """A flagged split's FP64 group sum is formed in one order: per wave its
     rows of a 512-row segment in ascending order, the segment's wave sums in
-    wave order, the segments in order.  The benchmark batch raises enough
-    flags for the recheck to take them in groups of two, segment by segment;
-    with HBT_RECHECK_SLOTS=0 every flag is one work item over all its
-    segments; a single-pair call takes its few flags one by one, segment by
-    segment.  Counts, n_recheck and the null moments (which hold the
-    rechecked T_b) must agree bit for bit."""
+    wave order, the segments in order.  The benchmark batch takes its flags
+    segment by segment (one work item per flag and segment, the segment sums
+    added by a second kernel); with HBT_RECHECK_SLOTS=0 every flag is one
+    work item over all its segments, and with 2000 slots the first pairs are
+    done one way and the rest the other; a single-pair call takes its few
+    flags segment by segment.  Counts, n_recheck and the null moments (which
+    hold the rechecked T_b) must agree bit for bit."""
     b = synth.batch_512_d768()
     print(f"recheck spread: {b.npairs} pairs of the 512-pair workload", flush=True)
     Z = _dev(b.Z)
     res = hbt.perm_test_batched(Z, b.row_offset, b.n, b.m, b.B, seed=b.seed, precision="bf16x2")
-    assert int(res["n_recheck"].sum()) >= 1000  # flag segments enough for groups of two
+    assert int(res["n_recheck"].sum()) >= 1000  # more flag segments than 2000 slots
     # 0 slots: every flag whole; 2000 slots: the first pairs' flags by
     # segment, the others whole, in the same call
     for slots in ["0", "2000"]:
