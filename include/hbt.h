@@ -278,8 +278,8 @@ hbt_status hbt_pipeline_chunks(int32_t chunks, int32_t* previous);
 
 /* The FP64 recheck spreads its work in one of two ways, with the same bits:
  * the flags of a pair whose segment sums fit the workspace's slots become
- * one work item per group of flags and 512-row segment, the others one work
- * item per flag over all segments.  The environment variable
+ * one work item per flag and 512-row segment, the others one work item per
+ * flag over all segments.  The environment variable
  * HBT_RECHECK_SLOTS (a count, read by every call) caps the slots a call
  * uses, 0 sending every flag down the second way; results do not depend on
  * it. */
